@@ -1,0 +1,246 @@
+"""Restarted GMRES(m) variants of the oracle, plain FP64 (test infrastructure only).
+
+* ``gmres(..., ortho='mgs')``  -- standard GMRES(m), Arnoldi with modified
+  Gram-Schmidt, one new vector per iteration (Sec. I); the backward-stable
+  reference.
+* ``gmres(..., ortho='cgs2')`` -- the same with classical Gram-Schmidt applied
+  twice, the paper's "standard GMRES" baseline (Tables 2-4).
+* ``sstep_gmres``              -- s-step GMRES(m) (Sec. III, Fig. 1): each panel is
+  s SpMVs of the matrix-powers kernel followed by a block orthogonalization;
+  ortho = 'two_stage' (Sec. V, Fig. 5 with s_hat = m), 'bcgs_pip2' (Fig. 4b) or
+  'bcgs2_cholqr2' (Fig. 2b).
+
+One restart cycle of every variant computes, in exact arithmetic, the same
+iterate: x + argmin_{z in K_k(A, r)} ||b - A(x + z)||, with k the number of
+basis vectors generated in that cycle.
+
+Outer loop (all variants): r = b - A x, stop if ||r|| <= tol ||b|| (explicit
+residual), else run one cycle.  Inside a cycle the implicit residual estimate
+is checked after every new vector (standard), after every panel (one-stage
+s-step) or once at the end of the cycle (two-stage with s_hat = m).  The
+iteration count is the number of Krylov vectors generated.
+
+s-step Hessenberg recovery (the small-matrix algebra implied by Fig. 1 and
+Sec. VI; the paper's listing is not reproduced): with the basis
+w_i = (A w_{i-1} - theta_i w_{i-1}) / sigma_i, w_0 = qhat_k,
+  A [w_0 .. w_{s-1}] = [w_0 .. w_s] B,   B(i,i) = theta_i, B(i+1,i) = sigma_i,
+and the panel factorization W = Qhat_{1:k} P + Qhat_{k+1:k+s} R gives
+[w_0, W] = Qhat_{1:k+s} S with S(:,1) = e_k, S(:,2:s+1) = [P; R].  Splitting the
+first k-1 rows off S(1:k+s-1,1:s) and using A Qhat_{1:k-1} = Qhat_{1:k} Hhat
+yields, with T = S(k:k+s-1, 1:s) (upper triangular, T(1,1) = 1),
+  Hhat(1:k+s, k:k+s-1) = (S B - [Hhat(1:k,1:k-1) S(1:k-1,1:s); 0]) T^{-1}.
+Two-stage: Qhat = Q R2 with R2 = Chol(Qhat^T Qhat) (stage 2 = CholQR of the
+m+1 columns), so A Q_{1:m} = Q_{1:m+1} H with H = R2 Hhat R2(1:m,1:m)^{-1}; the
+projected problem is min || beta R2(1,1) e_1 - H y || and x += Qhat_{1:m} z with
+z = R2(1:m,1:m)^{-1} y.
+
+Breakdown (our reading; the paper does not treat it): if a panel's Cholesky
+fails (a pivot at or below the relative threshold of ``dense.PIVOT_TOL``), the
+panel lies numerically in the span of the basis -- the Krylov space is
+(numerically) invariant.  The cycle then ends with the k columns built before
+that panel; if the stage-2 Cholesky fails at pivot p, with the first p columns.
+A cycle that can keep no column makes no progress and the solve stops.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .dense import (PIVOT_TOL, CholeskyBreakdown, GivensState, chol_upper, givens_lsq,
+                    right_solve_upper, solve_upper)
+from .sparse import Operator, basis_params, spmv
+from . import blockortho
+
+
+def _outer(A, b, x0, tol, max_iters, cycle_fn, record):
+    op = A if isinstance(A, Operator) else Operator(A)
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros(op.n) if x0 is None else np.array(x0, dtype=np.float64)
+    bnorm = float(np.linalg.norm(b))
+    iters = 0
+    cycles = 0
+    history = []
+    estimates = []
+    records = []
+    converged = False
+    while True:
+        r = b - spmv(op, x)
+        beta = float(np.linalg.norm(r))
+        history.append(beta / bnorm)
+        if beta <= tol * bnorm:
+            converged = True
+            break
+        if iters >= max_iters:
+            break
+        dx, k_used, est, rec = cycle_fn(op, r, beta, tol * bnorm)
+        x = x + dx
+        iters += k_used
+        cycles += 1
+        estimates.append(est / bnorm)
+        if record:
+            records.append(rec)
+        if k_used == 0:
+            break
+    return {
+        "x": x, "iters": iters, "cycles": cycles, "converged": converged,
+        "relres": history[-1], "history": history, "estimates": estimates,
+        "records": records,
+    }
+
+
+def gmres(A, b, x0=None, m: int = 60, tol: float = 1e-10, max_iters: int = 10**9,
+          ortho: str = "mgs", record: bool = False):
+    """Standard restarted GMRES(m) with MGS or CGS2 Arnoldi."""
+
+    def cycle(op, r, beta, tol_abs):
+        n = op.n
+        Q = np.zeros((n, m + 1))
+        H = np.zeros((m + 1, m))
+        Q[:, 0] = r / beta
+        giv = GivensState(beta, m)
+        k_used = m
+        for j in range(m):
+            w = spmv(op, Q[:, j])
+            h = np.zeros(j + 2)
+            if ortho == "mgs":
+                for i in range(j + 1):
+                    h[i] = Q[:, i] @ w
+                    w = w - h[i] * Q[:, i]
+            elif ortho == "cgs2":
+                Qj = Q[:, : j + 1]
+                h1 = Qj.T @ w
+                w = w - Qj @ h1
+                h2 = Qj.T @ w
+                w = w - Qj @ h2
+                h[: j + 1] = h1 + h2
+            else:
+                raise ValueError(ortho)
+            h[j + 1] = np.sqrt(w @ w)
+            H[: j + 2, j] = h
+            giv.add_column(h)
+            if h[j + 1] == 0.0:  # happy breakdown: K_{j+1} is invariant
+                k_used = j + 1
+                break
+            Q[:, j + 1] = w / h[j + 1]
+            if giv.residual() <= tol_abs:
+                k_used = j + 1
+                break
+        y = giv.solve(k_used)
+        rec = {"Q": Q[:, : k_used + 1], "H": H[: k_used + 1, :k_used]} if record else None
+        return Q[:, :k_used] @ y, k_used, giv.residual(), rec
+
+    return _outer(A, b, x0, tol, max_iters, cycle, record)
+
+
+def mpk(op, w0: np.ndarray, theta: np.ndarray, sigma: np.ndarray):
+    """Matrix-powers kernel: s SpMVs in sequence (Sec. III).  Returns (W, B)."""
+    s = len(theta)
+    W = np.zeros((op.n, s))
+    B = np.zeros((s + 1, s))
+    w = w0
+    for i in range(s):
+        w = (spmv(op, w) - theta[i] * w) / sigma[i]
+        W[:, i] = w
+        B[i, i] = theta[i]
+        B[i + 1, i] = sigma[i]
+    return W, B
+
+
+def hessenberg_block(Hh: np.ndarray, P: np.ndarray, R: np.ndarray, B: np.ndarray, k: int):
+    """Columns k-1 .. k+s-2 (0-based) of the Hessenberg matrix of the basis, rows 0..k+s-1."""
+    s = R.shape[0]
+    S = np.zeros((k + s, s + 1))
+    S[k - 1, 0] = 1.0
+    S[:k, 1:] = P
+    S[k:, 1:] = R
+    T = S[k - 1: k - 1 + s, :s]
+    M = S @ B
+    if k > 1:
+        M[:k, :] -= Hh[:k, : k - 1] @ S[: k - 1, :s]
+    return right_solve_upper(M, T)
+
+
+def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
+                max_iters: int = 10**9, ortho: str = "two_stage",
+                basis: str = "monomial", shifts=None, record: bool = False):
+    """s-step GMRES(m) with one-stage or two-stage (s_hat = m) block orthogonalization."""
+    if m % s != 0:
+        raise ValueError("s must divide m")
+    op = A if isinstance(A, Operator) else Operator(A)
+    theta, sigma = basis_params(op, s, basis, shifts)
+    J = m // s
+    one_stage = None if ortho == "two_stage" else blockortho.ONE_STAGE[ortho]
+
+    def cycle(op, r, beta, tol_abs):
+        n = op.n
+        Qh = np.zeros((n, m + 1))
+        Hh = np.zeros((m + 1, m))
+        Qh[:, 0] = r / beta
+        giv = GivensState(beta, m)
+        panels = []
+        k_used = m
+        breakdown = None
+        for j in range(J):
+            k = j * s + 1
+            W, B = mpk(op, Qh[:, k - 1], theta, sigma)
+            try:
+                if one_stage is None:
+                    Qn, P, R = blockortho.bcgs_pip(Qh[:, :k], W, PIVOT_TOL)  # stage 1
+                else:
+                    Qn, P, R = one_stage(Qh[:, :k], W, PIVOT_TOL)
+            except CholeskyBreakdown:
+                # the panel is numerically in the span of the basis: keep the k columns
+                # built so far (k-1 Hessenberg columns) and end the cycle there
+                k_used = k - 1
+                breakdown = ("panel", j)
+                break
+            Qh[:, k: k + s] = Qn
+            Hh[: k + s, k - 1: k - 1 + s] = hessenberg_block(Hh, P, R, B, k)
+            if record:
+                panels.append({"k": k, "P": P, "R": R, "B": B})
+            if one_stage is not None:
+                for c in range(k - 1, k - 1 + s):
+                    giv.add_column(Hh[: c + 2, c])
+                if giv.residual() <= tol_abs:
+                    k_used = k - 1 + s
+                    break
+        rec = None
+        if k_used == 0:
+            return np.zeros(n), 0, beta, {"breakdown": breakdown} if record else None
+        if one_stage is None:
+            kb = k_used + 1
+            G2 = Qh[:, :kb].T @ Qh[:, :kb]
+            try:
+                R2 = chol_upper(G2, tol=PIVOT_TOL)  # stage 2: CholQR of the big panel
+            except CholeskyBreakdown as e:
+                kb = e.index  # leading kb columns factor cleanly
+                k_used = kb - 1
+                breakdown = ("stage2", kb)
+                if k_used <= 0:
+                    return np.zeros(n), 0, beta, {"breakdown": breakdown} if record else None
+                R2 = chol_upper(G2[:kb, :kb], tol=PIVOT_TOL)
+            H = right_solve_upper(R2 @ Hh[:kb, :k_used], R2[:k_used, :k_used])
+            y, est = givens_lsq(H, beta * R2[0, 0])
+            z = solve_upper(R2[:k_used, :k_used], y)
+            dx = Qh[:, :k_used] @ z
+            if record:
+                rec = {"Qhat": Qh[:, :kb], "Hhat": Hh[:kb, :k_used], "R2": R2, "H": H, "y": y,
+                       "z": z, "panels": panels, "beta": beta, "breakdown": breakdown}
+            return dx, k_used, est, rec
+        y = giv.solve(k_used)
+        if record:
+            rec = {"Q": Qh[:, : k_used + 1], "H": Hh[: k_used + 1, :k_used], "y": y,
+                   "panels": panels, "beta": beta, "breakdown": breakdown}
+        return Qh[:, :k_used] @ y, k_used, abs(giv.g[k_used]), rec
+
+    out = _outer(op, b, x0, tol, max_iters, cycle, record)
+    out["theta"], out["sigma"] = theta, sigma
+    return out
+
+
+def dense_solve(A, b):
+    """Direct solve of a tiny system with LAPACK LU (numpy), for pins only."""
+    M = np.zeros((A.n, A.n))
+    for i in range(A.n):
+        for p in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            M[i, A.col[p]] += A.val[p]
+    return np.linalg.solve(M, b), M
