@@ -1,0 +1,157 @@
+/*
+ * tsgmres.h -- C ABI of the MI355X (gfx950) library for s-step GMRES with
+ * two-stage block orthogonalization.
+ *
+ * Method: I. Yamazaki, A. J. Higgins, E. G. Boman, D. B. Szyld, "Two-Stage Block
+ * Orthogonalization to Improve Performance of s-step GMRES", arXiv:2402.15033.
+ *
+ * Conventions for every entry point
+ *   - Pointers are DEVICE pointers (hipMalloc'd or torch CUDA/HIP tensors) unless
+ *     the comment says "host".
+ *   - Dense blocks are column-major with an explicit leading dimension.
+ *   - Sparse matrices are CSR with int32 row pointers / column indices and float64
+ *     values; row r holds entries row_ptr[r] .. row_ptr[r+1]-1.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default stream).
+ *     All device work is enqueued on it, in order.
+ *   - The caller owns every buffer it passes.  The library never frees caller
+ *     memory; all O(n) scratch lives in a caller-provided workspace whose size is
+ *     returned by the matching *_workspace_bytes() query.
+ *   - Errors: no exception or abort crosses this ABI.  A negative status is a
+ *     caller or runtime error detected before (or instead of) numerical work; a
+ *     positive status is a numerical outcome.  tsg_last_error() returns a
+ *     thread-local message describing the last non-OK status.
+ */
+#ifndef TSGMRES_H
+#define TSGMRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TSG_OK = 0,
+  TSG_NOT_CONVERGED = 1,    /* max_iters reached; x holds the last iterate            */
+  TSG_BREAKDOWN = 2,        /* a restart cycle could keep no basis vector              */
+  TSG_ERR_INVALID_ARG = -1, /* bad sizes / NULL pointers / unsupported combination    */
+  TSG_ERR_HIP = -2,         /* a HIP runtime call failed (message in tsg_last_error)  */
+  TSG_ERR_WORKSPACE = -3,   /* workspace too small or misaligned (256-byte alignment) */
+  TSG_ERR_UNSUPPORTED = -4  /* valid request outside what this build implements       */
+} tsg_status;
+
+/* Block orthogonalization scheme used inside a restart cycle.
+ *   TWO_STAGE      Sec. V, Fig. 5 with s_hat = m: one BCGS-PIP per s-column panel
+ *                  (stage 1), one CholQR of the m+1 columns at the end of the cycle
+ *                  (stage 2).  One global reduction per panel plus one per cycle.
+ *   BCGS_PIP2      Sec. IV-C, Fig. 4b (two reductions per panel).
+ *   BCGS2_CHOLQR2  Sec. IV-B, Fig. 2b with CholQR2 then CholQR (five per panel).
+ *   CGS2           standard GMRES(m), classical Gram-Schmidt twice, one vector per
+ *                  iteration (the paper's "standard GMRES" baseline, Tables 2-4). */
+typedef enum {
+  TSG_ORTHO_TWO_STAGE = 0,
+  TSG_ORTHO_BCGS_PIP2 = 1,
+  TSG_ORTHO_BCGS2_CHOLQR2 = 2,
+  TSG_ORTHO_CGS2 = 3
+} tsg_ortho;
+
+/* s-step basis w_i = (A w_{i-1} - theta_i w_{i-1}) / sigma_i (matrix-powers kernel,
+ * Sec. III).  [lo, hi] is the Gershgorin interval computed at tsg_csr_create.
+ *   MONOMIAL  theta = 0, sigma = max(|lo|, |hi|)          (the paper's choice, Sec. VI)
+ *   SHIFTED   theta = (lo+hi)/2, sigma = (hi-lo)/2
+ *   NEWTON    theta_i = newton_shifts[i] (host), sigma = (hi-lo)/2              */
+typedef enum { TSG_BASIS_MONOMIAL = 0, TSG_BASIS_SHIFTED = 1, TSG_BASIS_NEWTON = 2 } tsg_basis;
+
+/* FP64: every step in float64.
+ * FP32_IR: basis, SpMV and tall-skinny products in float32 with float32
+ * accumulation; Gram Cholesky, Hessenberg/Givens least squares, solution update
+ * and the outer residual r = b - A x in float64.  Each restart cycle is one step of
+ * iterative refinement (not in the paper). */
+typedef enum { TSG_PREC_FP64 = 0, TSG_PREC_FP32_IR = 1 } tsg_prec;
+
+typedef struct {
+  int32_t m;            /* restart length (Krylov vectors per cycle), 1 <= m <= 63      */
+  int32_t s;            /* step size; s divides m; 1 <= s <= 16 (CGS2 ignores s)        */
+  int32_t s_hat;        /* second step size; 0 or m (s_hat < m is not built: UNSUPPORTED)*/
+  int32_t ortho;        /* tsg_ortho                                                    */
+  int32_t basis;        /* tsg_basis                                                    */
+  int32_t precision;    /* tsg_prec                                                     */
+  double tol;           /* stop when ||b - A x||_2 <= tol ||b||_2 (explicit, FP64)      */
+  int64_t max_iters;    /* stop (TSG_NOT_CONVERGED) once this many vectors were built   */
+  const double* newton_shifts; /* host, length s, only for TSG_BASIS_NEWTON             */
+  int32_t timing;       /* nonzero: time each kernel class with HIP events (adds one
+                           host synchronization per restart cycle)                      */
+  int32_t reserved;
+} tsg_solve_params;
+
+typedef struct {
+  int64_t iters;        /* Krylov vectors generated (the paper's iteration count)       */
+  int64_t cycles;       /* restart cycles run                                           */
+  double relres;        /* explicit ||b - A x|| / ||b|| of the returned x (FP64)         */
+  double relres_est;    /* implicit estimate at the end of the last cycle               */
+  int32_t status;       /* tsg_status of the solve                                      */
+  int32_t truncated_cycles; /* cycles shortened by a Cholesky breakdown                 */
+  /* filled only when params.timing != 0 (milliseconds of GPU time, HIP events) */
+  double ms_total, ms_spmv, ms_ortho_reduce, ms_ortho_update, ms_small, ms_xupdate, ms_residual;
+  int64_t n_ortho_reduce, n_ortho_update, n_spmv;  /* launches of each class           */
+  double bytes_ortho_reduce, bytes_ortho_update, bytes_spmv; /* algorithmic bytes moved */
+} tsg_solve_info;
+
+typedef struct tsg_csr_s* tsg_csr;
+
+/* Create a handle for the n x n CSR matrix (Sec. VII: the operator).  The handle
+ * BORROWS row_ptr[n+1], col[nnz], val[nnz] (device): they must stay valid and
+ * unchanged until tsg_csr_destroy.  Computes the Gershgorin interval on the device
+ * (one small kernel, synchronizes `stream`).  The handle owns one 4 KiB device block.
+ * Errors: INVALID_ARG for n < 1, nnz < 0, nnz >= 2^31, NULL pointers; HIP. */
+tsg_status tsg_csr_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                          const double* val, void* stream, tsg_csr* out /* host */);
+tsg_status tsg_csr_destroy(tsg_csr A);
+/* Gershgorin interval [lo, hi] (host outputs). */
+tsg_status tsg_csr_gershgorin(tsg_csr A, double* lo, double* hi);
+
+/* y = A x in float64 (the SpMV of the matrix-powers kernel with theta = 0, sigma = 1).
+ * x and y must not overlap.  Asynchronous on `stream`. */
+tsg_status tsg_spmv(tsg_csr A, const double* x, double* y, void* stream);
+
+/* Workspace (device, 256-byte aligned) needed by tsg_solve for this matrix and params. */
+size_t tsg_solve_workspace_bytes(int64_t n, int64_t nnz, const tsg_solve_params* p);
+
+/* Solve A x = b by restarted s-step GMRES(m) (Sec. III, Fig. 1) with the block
+ * orthogonalization p->ortho.  b[n] (device, float64) is read; x[n] (device, float64)
+ * holds x0 on entry and the result on exit.  Every step of a restart cycle runs in
+ * the library's HIP kernels on `stream`; the host only reads back an 64-byte status
+ * block once per cycle.  Returns after the solve has finished on the device.
+ * Status: OK (converged), NOT_CONVERGED, BREAKDOWN, or a negative error (then x is
+ * untouched).  `info` (host) is filled for every non-negative status. */
+tsg_status tsg_solve(tsg_csr A, const double* b, double* x, const tsg_solve_params* p,
+                     void* workspace, size_t ws_bytes, void* stream,
+                     tsg_solve_info* info /* host, may be NULL */);
+
+/* Workspace (device) needed by tsg_orthogonalize for an n x k block with step s. */
+size_t tsg_orthogonalize_workspace_bytes(int64_t n, int32_t k, int32_t s);
+
+/* Orthonormalize the tall-skinny block X (n x k, column-major, leading dimension
+ * ldx >= n, device float64) in place:  on exit X holds Q with X_in = Q R, Q^T Q = I,
+ * R upper triangular with positive diagonal (the contract of Fig. 1's caption).
+ * Column 1 is normalized alone; then panels of s columns (the last may be short).
+ * algo: TWO_STAGE (stage 1 = BCGS-PIP per panel, stage 2 = one CholQR over all k
+ * columns, then Q = Qhat R2^{-1}), BCGS_PIP2 or BCGS2_CHOLQR2.  s_hat must be 0 or
+ * k-1.  R (device, k x k, column-major, leading dimension ldr >= k) receives R; its
+ * strictly lower part is set to 0.  Requires 1 <= k <= 64, 1 <= s <= 16, k <= n.
+ * Asynchronous unless orth_err (host) is non-NULL, in which case ||I - Q^T Q||_F is
+ * computed on the device and returned (one extra pass, synchronizes `stream`).
+ * Status BREAKDOWN: a Gram matrix was not numerically positive definite (X is then
+ * partially overwritten). */
+tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr,
+                             int32_t s, int32_t s_hat, int32_t algo, void* workspace,
+                             size_t ws_bytes, void* stream, double* orth_err /* host, opt */);
+
+const char* tsg_status_string(tsg_status st);
+const char* tsg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSGMRES_H */

@@ -1,0 +1,283 @@
+"""ctypes binding of libtsgmres.so (the C ABI in include/tsgmres.h).
+
+Argument marshalling only: tensors are checked (device, dtype, contiguity) and
+passed as raw device pointers together with the current HIP stream.  Every step
+of the computation runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libtsgmres.so"
+
+ORTHO = {"two_stage": 0, "bcgs_pip2": 1, "bcgs2_cholqr2": 2, "cgs2": 3}
+BASIS = {"monomial": 0, "shifted": 1, "newton": 2}
+PRECISION = {"fp64": 0, "fp32_ir": 1}
+STATUS = {0: "ok", 1: "not converged", 2: "breakdown", -1: "invalid argument",
+          -2: "HIP runtime error", -3: "workspace", -4: "unsupported"}
+
+
+class TSGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"tsgmres status {status} ({STATUS.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class _Params(C.Structure):
+    _fields_ = [("m", C.c_int32), ("s", C.c_int32), ("s_hat", C.c_int32), ("ortho", C.c_int32),
+                ("basis", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double),
+                ("max_iters", C.c_int64), ("newton_shifts", C.POINTER(C.c_double)),
+                ("timing", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("cycles", C.c_int64), ("relres", C.c_double),
+                ("relres_est", C.c_double), ("status", C.c_int32), ("truncated_cycles", C.c_int32),
+                ("ms_total", C.c_double), ("ms_spmv", C.c_double), ("ms_ortho_reduce", C.c_double),
+                ("ms_ortho_update", C.c_double), ("ms_small", C.c_double), ("ms_xupdate", C.c_double),
+                ("ms_residual", C.c_double), ("n_ortho_reduce", C.c_int64),
+                ("n_ortho_update", C.c_int64), ("n_spmv", C.c_int64),
+                ("bytes_ortho_reduce", C.c_double), ("bytes_ortho_update", C.c_double),
+                ("bytes_spmv", C.c_double)]
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iters: int
+    cycles: int
+    relres: float
+    relres_est: float
+    truncated_cycles: int
+    ms_total: float = 0.0
+    ms_spmv: float = 0.0
+    ms_ortho_reduce: float = 0.0
+    ms_ortho_update: float = 0.0
+    ms_small: float = 0.0
+    ms_xupdate: float = 0.0
+    ms_residual: float = 0.0
+    n_ortho_reduce: int = 0
+    n_ortho_update: int = 0
+    n_spmv: int = 0
+    bytes_ortho_reduce: float = 0.0
+    bytes_ortho_update: float = 0.0
+    bytes_spmv: float = 0.0
+
+    @property
+    def converged(self) -> bool:
+        return self.status == 0
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return os.environ.get("TSGMRES_LIB", os.path.join(HERE, _LIB_NAME))
+
+
+def load_library():
+    """Load libtsgmres.so (raises if it has not been built; there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_2402_15033_amd.build` "
+                           "(or __graft_entry__.build()); no CPU fallback exists")
+    lib = C.CDLL(path)
+    vp, i32, i64, f64p = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    lib.tsg_csr_create.argtypes = [i64, i64, vp, vp, vp, vp, C.POINTER(vp)]
+    lib.tsg_csr_create.restype = C.c_int
+    lib.tsg_csr_destroy.argtypes = [vp]
+    lib.tsg_csr_destroy.restype = C.c_int
+    lib.tsg_csr_gershgorin.argtypes = [vp, f64p, f64p]
+    lib.tsg_csr_gershgorin.restype = C.c_int
+    lib.tsg_spmv.argtypes = [vp, vp, vp, vp]
+    lib.tsg_spmv.restype = C.c_int
+    lib.tsg_solve_workspace_bytes.argtypes = [i64, i64, C.POINTER(_Params)]
+    lib.tsg_solve_workspace_bytes.restype = C.c_size_t
+    lib.tsg_solve.argtypes = [vp, vp, vp, C.POINTER(_Params), vp, C.c_size_t, vp, C.POINTER(_Info)]
+    lib.tsg_solve.restype = C.c_int
+    lib.tsg_orthogonalize_workspace_bytes.argtypes = [i64, i32, i32]
+    lib.tsg_orthogonalize_workspace_bytes.restype = C.c_size_t
+    lib.tsg_orthogonalize.argtypes = [i64, i32, vp, i64, vp, i32, i32, i32, i32, vp, C.c_size_t, vp, f64p]
+    lib.tsg_orthogonalize.restype = C.c_int
+    lib.tsg_status_string.argtypes = [C.c_int]
+    lib.tsg_status_string.restype = C.c_char_p
+    lib.tsg_last_error.argtypes = []
+    lib.tsg_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow_positive: bool = False) -> int:
+    if status == 0 or (allow_positive and status > 0):
+        return status
+    msg = load_library().tsg_last_error().decode(errors="replace")
+    raise TSGError(status, msg)
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_tensor(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _workspace(nbytes: int, device, ws: torch.Tensor | None):
+    """Device buffer of at least nbytes whose address is 256-byte aligned."""
+    if ws is not None:
+        p = ws.data_ptr()
+        if p % 256 or ws.numel() * ws.element_size() < nbytes:
+            raise ValueError("workspace too small or not 256-byte aligned")
+        return ws, p
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    p = buf.data_ptr()
+    return buf, (p + 255) // 256 * 256
+
+
+class CSRMatrix:
+    """Handle on a device CSR matrix (borrows the three tensors; keeps references)."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor):
+        lib = load_library()
+        self.row_ptr = _dev_tensor(row_ptr, torch.int32, "row_ptr")
+        self.col = _dev_tensor(col, torch.int32, "col")
+        self.val = _dev_tensor(val, torch.float64, "val")
+        self.n = row_ptr.numel() - 1
+        self.nnz = col.numel()
+        self.device = val.device
+        h = C.c_void_p()
+        _check(lib.tsg_csr_create(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                                  self.val.data_ptr(), _stream(self.device), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_host(cls, A, device="cuda"):
+        """From any object with numpy row_ptr/col/val (e.g. workloads.CSR)."""
+        return cls(torch.as_tensor(A.row_ptr, device=device), torch.as_tensor(A.col, device=device),
+                   torch.as_tensor(A.val, device=device))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def gershgorin(self):
+        lo, hi = C.c_double(), C.c_double()
+        _check(load_library().tsg_csr_gershgorin(self._h, C.byref(lo), C.byref(hi)))
+        return lo.value, hi.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().tsg_csr_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spmv(A: CSRMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    _dev_tensor(x, torch.float64, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _check(load_library().tsg_spmv(A.handle, x.data_ptr(), y.data_ptr(), _stream(x.device)))
+    return y
+
+
+def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing):
+    p = _Params()
+    p.m, p.s, p.s_hat = int(m), int(s), 0
+    p.ortho = ORTHO[ortho] if isinstance(ortho, str) else int(ortho)
+    p.basis = BASIS[basis] if isinstance(basis, str) else int(basis)
+    p.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    p.tol = float(tol)
+    p.max_iters = int(max_iters)
+    keep = None
+    if shifts is not None:
+        keep = (C.c_double * len(shifts))(*[float(v) for v in shifts])
+        p.newton_shifts = C.cast(keep, C.POINTER(C.c_double))
+    p.timing = 1 if timing else 0
+    return p, keep
+
+
+def solve_workspace_bytes(A: CSRMatrix, m=60, s=5, ortho="two_stage", basis="monomial",
+                          precision="fp64") -> int:
+    p, _ = _params(m, s, ortho, basis, precision, 1e-10, 1 << 40, None, False)
+    return int(load_library().tsg_solve_workspace_bytes(A.n, A.nnz, C.byref(p)))
+
+
+def solve(A: CSRMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, m: int = 60, s: int = 5,
+          tol: float = 1e-10, max_iters: int = 1 << 40, ortho: str = "two_stage",
+          basis: str = "monomial", precision: str = "fp64", shifts=None, timing: bool = False,
+          workspace: torch.Tensor | None = None):
+    """Solve A x = b (x updated in place; zeros if None).  Returns (x, SolveInfo)."""
+    lib = load_library()
+    _dev_tensor(b, torch.float64, "b")
+    if x is None:
+        x = torch.zeros_like(b)
+    _dev_tensor(x, torch.float64, "x")
+    p, keep = _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing)
+    need = int(lib.tsg_solve_workspace_bytes(A.n, A.nnz, C.byref(p)))
+    if need == 0:
+        _check(-1)
+    ws, wp = _workspace(need, b.device, workspace)
+    info = _Info()
+    st = lib.tsg_solve(A.handle, b.data_ptr(), x.data_ptr(), C.byref(p), wp, need,
+                       _stream(b.device), C.byref(info))
+    _check(st, allow_positive=True)
+    del keep, ws
+    out = SolveInfo(**{f: getattr(info, f) for f, _ in _Info._fields_})
+    return x, out
+
+
+def orthogonalize(X: torch.Tensor, s: int = 5, algo: str = "two_stage", *, ldx: int | None = None,
+                  orth_err: bool = False, workspace: torch.Tensor | None = None):
+    """Orthonormalize the n x k block in place.
+
+    X is a float64 device tensor viewed as column-major: either a (k, ldx) contiguous tensor
+    whose row c is column c of the block, or an (n, k) tensor with stride (1, ldx) (e.g. the
+    transpose of a contiguous (k, n) tensor).  Returns (X, R[, ||I - Q^T Q||_F]).
+    """
+    lib = load_library()
+    if X.dim() != 2 or X.dtype != torch.float64 or X.device.type != "cuda":
+        raise ValueError("X must be a 2-D float64 device tensor")
+    if X.stride(0) == 1:  # (n, k) column-major view
+        n, k = X.shape
+        ld = X.stride(1) if k > 1 else n
+    elif X.stride(1) == 1:  # (k, ld) rows are columns
+        k = X.shape[0]
+        n = X.shape[1] if ldx is None else int(ldx)
+        ld = X.stride(0) if k > 1 else X.shape[1]
+        n = min(n, X.shape[1])
+    else:
+        raise ValueError("X must be column-major")
+    R = torch.zeros((k, k), dtype=torch.float64, device=X.device)  # column-major: R_t[j, i] = R[i, j]
+    need = int(lib.tsg_orthogonalize_workspace_bytes(n, k, s))
+    if need == 0:
+        _check(-1)
+    ws, wp = _workspace(need, X.device, workspace)
+    err = C.c_double(0.0)
+    st = lib.tsg_orthogonalize(n, k, X.data_ptr(), ld, R.data_ptr(), k, int(s), 0,
+                               ORTHO[algo] if isinstance(algo, str) else int(algo), wp, need,
+                               _stream(X.device), C.byref(err) if orth_err else None)
+    _check(st)
+    del ws
+    Rt = R.t()  # R was written column-major
+    if orth_err:
+        return X, Rt, err.value
+    return X, Rt

@@ -1,0 +1,404 @@
+// Sparse, vector and end-of-cycle kernels of the tsgmres library.
+#pragma once
+
+#include "panel.hpp"
+
+namespace tsg {
+
+constexpr int kRowBlock = 256;  // threads (rows) per block of the row-parallel kernels
+
+// ------------------------------------------------------------------ matrix powers
+// One step of the matrix-powers kernel (Sec. III): y = (A x - theta x) / sigma.
+// Scalar CSR, one row per thread; values of type V (float64, or the float32 copy in
+// the mixed-precision form), vectors of type T.  Blocks are mapped XCD-contiguously
+// so the x gathers of neighbouring rows hit the same L2.
+template <typename T, typename VT>
+__global__ __launch_bounds__(kRowBlock) void mpk_step_kernel(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const VT* __restrict__ val, const T* __restrict__ x, T* __restrict__ y, int64_t n,
+    double theta, double sigma, const SmallState* __restrict__ st, int panel) {
+  if (st->h.done || panel > st->h.stop_panel) return;
+  const int64_t r = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
+  if (r >= n) return;
+  const int p0 = row_ptr[r], p1 = row_ptr[r + 1];
+  T acc = (T)0;
+  for (int p = p0; p < p1; ++p) acc += (T)val[p] * x[col[p]];
+  y[r] = (acc - (T)theta * x[r]) / (T)sigma;
+}
+
+// y = A x in float64 (stand-alone SpMV entry point).
+__global__ __launch_bounds__(kRowBlock) void spmv_f64_kernel(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const double* __restrict__ x, double* __restrict__ y,
+    int64_t n) {
+  const int64_t r = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
+  if (r >= n) return;
+  const int p0 = row_ptr[r], p1 = row_ptr[r + 1];
+  double acc = 0.0;
+  for (int p = p0; p < p1; ++p) acc += val[p] * x[col[p]];
+  y[r] = acc;
+}
+
+// ------------------------------------------------------------------ restart residual
+// r = b - A x (float64), stored into basis column 0 (type T); ||r||^2 reduced in
+// deterministic order; the last block decides convergence (explicit residual test)
+// and initializes the cycle: beta, T = 1/beta for the scaling pass, Givens rhs,
+// cleared Hessenberg and stage-2 Gram.
+template <typename T>
+__global__ __launch_bounds__(kRowBlock) void residual_kernel(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, const double* __restrict__ x, const double* __restrict__ b,
+    T* __restrict__ r_out, int64_t n, SmallState* st, double* part1, double* part2,
+    unsigned* cnt) {
+  if (st->h.done) return;
+  const int64_t r = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
+  double rr = 0.0;
+  if (r < n) {
+    const int p0 = row_ptr[r], p1 = row_ptr[r + 1];
+    double acc = 0.0;
+    for (int p = p0; p < p1; ++p) acc += val[p] * x[col[p]];
+    double v = b[r] - acc;
+    r_out[r] = (T)v;
+    rr = v * v;
+  }
+  __shared__ double wsum[kRowBlock / kWave];
+  rr = wave_sum(rr);
+  if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = rr;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kRowBlock / kWave; ++w) s += wsum[w];
+    part1[blockIdx.x] = s;
+  }
+  __shared__ double s_tot;
+  bool last = last_block_reduce(part1, part2, cnt, 1, gridDim.x, [&](int, double v) { s_tot = v; });
+  if (!last) return;
+  __syncthreads();
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ int s_go;
+  if (tid == 0) {
+    double beta = sqrt(s_tot);
+    st->h.relres = beta / st->bnorm;
+    s_go = 0;
+    if (st->h.relres <= st->tol) {
+      st->h.done = 1;
+      st->h.status = 0;
+    } else if (st->h.iters >= st->max_iters) {
+      st->h.done = 1;
+      st->h.status = 1;
+    } else if (st->h.cycles > 0 && st->h.k_used == 0) {
+      st->h.done = 1;  // the previous cycle could keep no vector: no progress possible
+      st->h.status = 2;
+    } else {
+      s_go = 1;
+      st->beta = beta;
+      st->inv_beta = 1.0 / beta;
+      st->Tcur[0] = 1.0 / beta;
+      st->identity_t = 0;
+      st->h.stop_panel = 1 << 30;
+      st->h.k_used = st->m;
+    }
+  }
+  __syncthreads();
+  if (!s_go) return;
+  for (int i = tid; i < kLd * kLd; i += nt) {
+    st->Hh[i] = 0.0;
+    st->G2[i] = 0.0;
+  }
+  for (int i = tid; i <= kLd; i += nt) st->gg[i] = (i == 0) ? st->beta : 0.0;
+}
+
+// ||b||^2 -> st->bnorm (float64, deterministic).
+__global__ __launch_bounds__(kRowBlock) void norm_kernel(const double* __restrict__ b, int64_t n,
+                                                         SmallState* st, double* part1,
+                                                         double* part2, unsigned* cnt) {
+  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  double v = (r < n) ? b[r] * b[r] : 0.0;
+  __shared__ double wsum[kRowBlock / kWave];
+  v = wave_sum(v);
+  if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kRowBlock / kWave; ++w) s += wsum[w];
+    part1[blockIdx.x] = s;
+  }
+  __shared__ double s_tot;
+  bool last = last_block_reduce(part1, part2, cnt, 1, gridDim.x, [&](int, double x) { s_tot = x; });
+  if (!last) return;
+  if (threadIdx.x == 0) st->bnorm = sqrt(s_tot);
+}
+
+// ------------------------------------------------------------------ Gershgorin interval
+// Per-block min(a_ii - r_i) and max(a_ii + r_i), r_i = sum_{j != i} |a_ij|.
+__global__ __launch_bounds__(kRowBlock) void gershgorin_kernel(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+    const double* __restrict__ val, int64_t n, double* out /* [2 * gridDim] */) {
+  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  double lo = INFINITY, hi = -INFINITY;
+  if (r < n) {
+    double d = 0.0, rad = 0.0;
+    for (int p = row_ptr[r]; p < row_ptr[r + 1]; ++p) {
+      if (col[p] == r) d += val[p];
+      else rad += fabs(val[p]);
+    }
+    lo = d - rad;
+    hi = d + rad;
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, kWave));
+    hi = fmax(hi, __shfl_xor(hi, o, kWave));
+  }
+  __shared__ double slo[kRowBlock / kWave], shi[kRowBlock / kWave];
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    slo[threadIdx.x / kWave] = lo;
+    shi[threadIdx.x / kWave] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kRowBlock / kWave; ++w) {
+      lo = fmin(lo, slo[w]);
+      hi = fmax(hi, shi[w]);
+    }
+    out[2 * blockIdx.x] = lo;
+    out[2 * blockIdx.x + 1] = hi;
+  }
+}
+
+__global__ __launch_bounds__(kRowBlock) void minmax_final_kernel(const double* in, int nb, double* out) {
+  double lo = INFINITY, hi = -INFINITY;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    lo = fmin(lo, in[2 * i]);
+    hi = fmax(hi, in[2 * i + 1]);
+  }
+  __shared__ double slo[kRowBlock], shi[kRowBlock];
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)blockDim.x; ++i) {
+      lo = fmin(lo, slo[i]);
+      hi = fmax(hi, shi[i]);
+    }
+    out[0] = lo;
+    out[1] = hi;
+  }
+}
+
+// float64 -> float32 copy (CSR values of the mixed-precision form).
+__global__ __launch_bounds__(kRowBlock) void to_f32_kernel(const double* __restrict__ a,
+                                                           float* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// ------------------------------------------------------------------ solution update
+// x += V(:, 0:ku) coef (x float64, basis type T).  coef is uniform across the block.
+template <typename T>
+__global__ __launch_bounds__(kRowBlock) void xupdate_kernel(double* __restrict__ x,
+                                                            const T* __restrict__ V, int64_t ld,
+                                                            int64_t n, const SmallState* __restrict__ st) {
+  if (st->h.done) return;
+  const int ku = st->h.k_used;
+  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  if (r >= n) return;
+  double acc = 0.0;
+  for (int c = 0; c < ku; ++c) acc += (double)V[(int64_t)c * ld + r] * st->coef[c];
+  x[r] += acc;
+}
+
+// ------------------------------------------------------------------ end of cycle
+// One block.  Two-stage: stage 2 = CholQR of the kept columns (R2 = Chol(G2)),
+// H = R2 Hhat R2^{-1} (Fig. 5 with s_hat = m), Givens least squares with rhs
+// beta R2(1,1) e_1, coef = R2^{-1} y.  Other variants: coef from the incremental
+// Givens factorization.  Then the iteration counters advance.
+__global__ __launch_bounds__(256) void cycle_end_kernel(SmallState* st, int two_stage) {
+  if (st->h.done) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double sG[kLd * kLd];
+  __shared__ double sR[kLd * kLd];
+  __shared__ double sH[kLd * kLd];
+  __shared__ double sc[kLd], ss[kLd], sg[kLd + 1], sy[kLd];
+  __shared__ int s_ku, s_kb;
+  if (tid == 0) s_ku = st->h.k_used;
+  __syncthreads();
+  int ku = s_ku;
+  double est = 0.0;
+  if (two_stage && ku > 0) {
+    int kb = ku + 1;
+    for (int i = tid; i < kb * kb; i += nt) sG[(i % kb) + (i / kb) * kLd] = st->G2[(i % kb) + (i / kb) * kLd];
+    __syncthreads();
+    int f = block_chol_upper(sG, kLd, sR, kLd, kb, nullptr, st->pivot_tol);
+    if (tid == 0) {
+      s_kb = kb;
+      if (f >= 0) {  // keep the leading f columns (rows 0..f-1 of R are complete)
+        s_kb = f;
+        st->h.truncated += 1;
+      }
+    }
+    __syncthreads();
+    kb = s_kb;
+    ku = kb - 1;
+    if (ku > 0) {
+      // sH = R2(0:kb,0:kb) * Hhat(0:kb,0:ku)   (R2 upper, Hhat upper Hessenberg)
+      for (int idx = tid; idx < kb * ku; idx += nt) {
+        int i = idx % kb, j = idx / kb;
+        double v = 0.0;
+        int lmax = min(kb - 1, j + 1);
+        for (int l = i; l <= lmax; ++l) v += sR[i + l * kLd] * st->Hh[l + j * kLd];
+        sH[i + j * kLd] = v;
+      }
+      __syncthreads();
+      // sG <- R2(0:ku,0:ku)^{-1}
+      block_tri_inv_upper(sR, kLd, sG, kLd, ku);
+      // H = sH * R2^{-1}, computed in place column by column from the right
+      for (int idx = tid; idx < kb; idx += nt) {
+        double row[kLd];
+        for (int j = 0; j < ku; ++j) row[j] = sH[idx + j * kLd];
+        for (int j = ku - 1; j >= 0; --j) {
+          double v = 0.0;
+          for (int l = 0; l <= j; ++l) v += row[l] * sG[l + j * kLd];
+          row[j] = v;
+        }
+        for (int j = 0; j < ku; ++j) sH[idx + j * kLd] = row[j];
+      }
+      __syncthreads();
+      // Givens least squares on the Hessenberg part of H, rhs beta R2(0,0) e_1
+      for (int i = tid; i <= kLd; i += nt) sg[i] = 0.0;
+      __syncthreads();
+      if (tid == 0) sg[0] = st->beta * sR[0];
+      __syncthreads();
+      for (int i = 0; i < ku; ++i) {
+        if (tid == 0) {
+          double a = sH[i + i * kLd], b = sH[(i + 1) + i * kLd];
+          double rho = hypot(a, b);
+          double c = 1.0, s = 0.0;
+          if (rho != 0.0) { c = a / rho; s = b / rho; }
+          sc[i] = c;
+          ss[i] = s;
+          sH[i + i * kLd] = rho;
+          double gi = sg[i];
+          sg[i] = c * gi;
+          sg[i + 1] = -s * gi;
+        }
+        __syncthreads();
+        for (int t = i + 1 + tid; t < ku; t += nt) {
+          double a = sH[i + t * kLd], b = sH[(i + 1) + t * kLd];
+          sH[i + t * kLd] = sc[i] * a + ss[i] * b;
+          sH[(i + 1) + t * kLd] = -ss[i] * a + sc[i] * b;
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        for (int i = ku - 1; i >= 0; --i) {
+          double v = sg[i];
+          for (int l = i + 1; l < ku; ++l) v -= sH[i + l * kLd] * sy[l];
+          sy[i] = v / sH[i + i * kLd];
+        }
+      }
+      __syncthreads();
+      // coef = R2^{-1} y
+      for (int i = tid; i < ku; i += nt) {
+        double v = 0.0;
+        for (int l = i; l < ku; ++l) v += sG[i + l * kLd] * sy[l];
+        st->coef[i] = v;
+      }
+      est = fabs(sg[ku]);
+    }
+  } else if (!two_stage && ku > 0) {
+    givens_solve(st, ku);
+    est = fabs(st->gg[ku]);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    st->h.k_used = ku > 0 ? ku : 0;
+    st->h.iters += ku > 0 ? ku : 0;
+    st->h.cycles += 1;
+    st->h.est = est / st->bnorm;
+  }
+}
+
+// ------------------------------------------------------------------ stand-alone ortho
+// Q = Qhat R2^{-1} in place, one row per thread (K = max columns held in registers).
+template <int K>
+__global__ __launch_bounds__(kRowBlock) void apply_rinv_kernel(double* __restrict__ V, int64_t ld,
+                                                               int64_t n, int k,
+                                                               const double* __restrict__ Rinv) {
+  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  if (r >= n) return;
+  double q[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) q[c] = (c < k) ? V[(int64_t)c * ld + r] : 0.0;
+#pragma unroll
+  for (int j = K - 1; j >= 0; --j) {
+    if (j < k) {
+      double v = 0.0;
+#pragma unroll
+      for (int i = 0; i <= j; ++i) v += q[i] * Rinv[i + j * kLd];
+      q[j] = v;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < K; ++c)
+    if (c < k) V[(int64_t)c * ld + r] = q[c];
+}
+
+// Stage 2 of the stand-alone two-stage scheme: R2 = Chol(G2), Rinv = R2^{-1} (st->Wk),
+// R = R2 R1 with R1 the stage-1 factor in st->Hh.  One block.
+__global__ __launch_bounds__(256) void sa_stage2_kernel(SmallState* st, int k) {
+  if (st->h.done) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double sG[kLd * kLd];
+  __shared__ double sR[kLd * kLd];
+  for (int i = tid; i < k * k; i += nt) sG[(i % k) + (i / k) * kLd] = st->G2[(i % k) + (i / k) * kLd];
+  __syncthreads();
+  int f = block_chol_upper(sG, kLd, sR, kLd, k, nullptr, 0.0);
+  if (f >= 0) {
+    if (tid == 0) {
+      st->h.status = 2;
+      st->h.done = 1;
+    }
+    return;
+  }
+  block_tri_inv_upper(sR, kLd, st->Wk, kLd, k);
+  // R = R2 * R1 (both upper); write into G2 as output staging
+  for (int idx = tid; idx < k * k; idx += nt) {
+    int i = idx % k, j = idx / k;
+    double v = 0.0;
+    if (i <= j)
+      for (int l = i; l <= j; ++l) v += sR[i + l * kLd] * st->Hh[l + j * kLd];
+    st->G2[i + j * kLd] = v;
+  }
+}
+
+// Copy a k x k upper-triangular factor (ld kLd, from src) to the caller's R (ldr).
+__global__ __launch_bounds__(256) void copy_r_kernel(const SmallState* st, int which, int k,
+                                                     double* R, int ldr) {
+  const double* src = which == 0 ? st->Hh : st->G2;
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+    int i = idx % k, j = idx / k;
+    R[i + (int64_t)j * ldr] = (i <= j) ? src[i + j * kLd] : 0.0;
+  }
+}
+
+// ||I - G||_F for the k x k Gram in st->Wk (upper triangle valid) -> st->Wk[kLd*kLd-1].
+__global__ __launch_bounds__(256) void orth_err_kernel(SmallState* st, int k) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+    int i = idx % k, j = idx / k;
+    double g = (i <= j) ? st->Wk[i + j * kLd] : st->Wk[j + i * kLd];
+    double e = ((i == j) ? 1.0 : 0.0) - g;
+    acc += e * e;
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)blockDim.x; ++i) t += s[i];
+    st->beta = sqrt(t);
+  }
+}
+
+}  // namespace tsg

@@ -1,0 +1,514 @@
+// Streaming panel kernel: the tall-skinny products of every block orthogonalization
+// scheme (Sec. IV-V), with an FP64 "tail" executed by the last block.
+//
+// One launch streams the rows of the column-major basis V once and, per row r, forms
+//     y  = W(r,:) - Q(r,:) P          (PF_HAS_P; else y = W(r,:))
+//     q  = y T                        (PF_HAS_T, T upper triangular; else q = y)
+//     W(r,:) <- q                     (PF_STORE, in place)
+//     G += [Q(r,:), q]^T q            (PF_GRAM_Q: Q rows, PF_GRAM_W: q rows)
+// where Q = V(:, 0:k) and W = V(:, wcol:wcol+sw).  The Gram G ((k+sw) x sw) is
+// reduced across lanes, waves and blocks (deterministic order), and the last block
+// runs the tail (Cholesky of the Pythagorean Gram, Hessenberg block, Givens, ...).
+//
+// Mapping (wave64, 8 waves = 512 threads per block): a block owns a contiguous range
+// of rows; each lane owns one row per batch of 64*RPL rows.  The k+sw columns are
+// dealt to the 8 waves round-robin (column c -> wave c % 8), so every column is read
+// from HBM exactly once per launch with fully coalesced 512-byte wave accesses, and
+// each wave keeps the Gram rows of its own columns in registers for the whole launch.
+// Partial projections y_g = Q_g(r,:) P_g and the panel values W(r,:) are exchanged
+// through LDS so that every wave can form q for its Gram rows.
+#pragma once
+
+#include "small.hpp"
+
+namespace tsg {
+
+enum PanelFlags : int {
+  PF_HAS_P = 1,
+  PF_HAS_T = 2,
+  PF_STORE = 4,
+  PF_GRAM_Q = 8,
+  PF_GRAM_W = 16,
+};
+
+enum TailOp : int {
+  TAIL_NONE = 0,
+  TAIL_NORM0,      // two-stage: G2(0,0) <- q0^T q0
+  TAIL_SA_NORM,    // stand-alone: r00 = ||x0||, T = 1/r00
+  TAIL_PIP,        // BCGS-PIP Cholesky; two-stage stage 1 (+ Hessenberg block)
+  TAIL_G2COL,      // two-stage: block column of the stage-2 Gram
+  TAIL_PIP2_A,     // BCGS-PIP2 first pass
+  TAIL_PIP2_B,     // BCGS-PIP2 second pass (+ Hessenberg block, Givens)
+  TAIL_BC_P1,      // BCGS2 + CholQR2: P1 = Q^T W
+  TAIL_BC_A1,      // ... Ra1 = Chol(Vhat^T Vhat)
+  TAIL_BC_A2,      // ... Ra2 = Chol(Qt1^T Qt1), Ra = Ra2 Ra1
+  TAIL_BC_P2,      // ... P2 = Q^T Qt
+  TAIL_BC_C,       // ... Rc = Chol(Y^T Y) (+ Hessenberg block, Givens)
+  TAIL_CGS_H1,     // standard GMRES, CGS2 first pass
+  TAIL_CGS_H2,     // standard GMRES, CGS2 second pass (+ Hessenberg column, Givens)
+  TAIL_GRAM_OUT,   // copy the reduced Gram into st->Wk (orthogonality check)
+};
+
+struct PanelArgs {
+  void* V;
+  int64_t ld;
+  int64_t n;
+  int64_t rows_per_block;
+  int32_t k;         // Q = V(:, 0:k)
+  int32_t wcol;      // W = V(:, wcol : wcol+sw)
+  int32_t sw;        // panel width (<= template S)
+  int32_t flags;
+  int32_t tail;
+  int32_t nblocks;
+  int32_t gate;      // return at entry when the solve is done or panel > stop_panel
+  int32_t standalone;// tails assemble an R factor (st->Hh) instead of Hessenberg/Givens
+  int32_t kkeep;     // Krylov vectors kept if this panel breaks down (solver mode)
+  int32_t panel;     // index of the panel within the cycle (-1: cycle set-up)
+  SmallState* st;
+  double* part1;
+  double* part2;
+  unsigned* cnt;
+};
+
+// ----------------------------------------------------------------------------- tails
+// Called by every thread of the last block with the reduced Gram sred ((k+sw) x sw,
+// entry (c, j) at sred[c * sw + j]).
+
+__device__ void tail_breakdown(const PanelArgs& a, int kkeep) {
+  SmallState* st = a.st;
+  if (threadIdx.x == 0) {
+    if (a.standalone) {
+      st->h.status = 2;
+      st->h.done = 1;
+    } else {  // this panel is discarded: stop after the previous one
+      st->h.stop_panel = a.panel - 1;
+      st->h.k_used = kkeep;
+      st->h.truncated += 1;
+    }
+  }
+  __syncthreads();
+}
+
+// Convergence check of the one-stage variants after Hessenberg columns 0..ncols-1:
+// the current panel still completes, later panels of the cycle are skipped.
+__device__ void tail_check(SmallState* st, int ncols, int panel) {
+  if (threadIdx.x == 0) {
+    double est = fabs(st->gg[ncols]);
+    if (est <= st->tol * st->bnorm && ncols < st->m) {
+      st->h.stop_panel = panel;
+      st->h.k_used = ncols;
+    }
+  }
+  __syncthreads();
+}
+
+// Pythagorean Gram G = Gw - P^T P (P = sred rows 0..k-1, Gw = rows k..k+s-1) and its
+// Cholesky factor into R (ld kMaxS).  Returns the failing pivot or -1.
+__device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, double* R) {
+  const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double sG[kMaxS * kMaxS], sRef[kMaxS];
+  for (int idx = tid; idx < k * s; idx += nt) {
+    int c = idx % k, j = idx / k;
+    P[c + j * kLd] = sred[c * s + j];
+  }
+  for (int idx = tid; idx < s * s; idx += nt) {
+    int i = idx % s, j = idx / s;
+    double v = sred[(k + i) * s + j];
+    for (int c = 0; c < k; ++c) v -= sred[c * s + i] * sred[c * s + j];
+    sG[i + j * kMaxS] = v;
+    if (i == j) sRef[i] = sred[(k + i) * s + j];
+  }
+  __syncthreads();
+  return block_chol_upper(sG, kMaxS, R, kMaxS, s, sRef, a.st->pivot_tol);
+}
+
+// Plain Cholesky of rows r0..r0+s-1 of sred (a q^T q Gram) into R (ld kMaxS).
+__device__ int tail_chol_rows(const PanelArgs& a, const double* sred, int r0, double* R, double tol) {
+  const int s = a.sw, tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double sG[kMaxS * kMaxS];
+  for (int idx = tid; idx < s * s; idx += nt) {
+    int i = idx % s, j = idx / s;
+    sG[i + j * kMaxS] = sred[(r0 + i) * s + j];
+  }
+  __syncthreads();
+  return block_chol_upper(sG, kMaxS, R, kMaxS, s, nullptr, tol);
+}
+
+// Write T = R^{-1} (s x s) for the next update kernel.
+__device__ void tail_set_tinv(SmallState* st, const double* R, int s) {
+  block_tri_inv_upper(R, kMaxS, st->Tcur, kMaxS, s);
+  if (threadIdx.x == 0) st->identity_t = 0;
+  __syncthreads();
+}
+
+// The panel's final factors (P, R): V_panel = Q P + Q_new R.  Solver mode: Hessenberg
+// block, and (one-stage) Givens + convergence check.  Stand-alone: R factor assembly.
+__device__ void tail_emit_panel(const PanelArgs& a, const double* P, const double* R, bool givens) {
+  SmallState* st = a.st;
+  const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
+  const int c0 = a.wcol;
+  if (a.standalone) {
+    for (int idx = tid; idx < (k + s) * s; idx += nt) {
+      int i = idx % (k + s), j = idx / (k + s);
+      double v = (i < k) ? P[i + j * kLd] : ((i - k) <= j ? R[(i - k) + j * kMaxS] : 0.0);
+      st->Hh[(i < k ? i : c0 + i - k) + (c0 + j) * kLd] = v;
+    }
+    __syncthreads();
+    return;
+  }
+  block_hessenberg_panel(st->Hh, P, R, st->theta, st->sigma, k, s, st->Wk);
+  if (givens) {
+    givens_append(st, st->Hh, k - 1, k - 1 + s);
+    tail_check(st, k - 1 + s, a.panel);
+  }
+}
+
+__device__ void panel_tail(const PanelArgs& a, const double* sred) {
+  SmallState* st = a.st;
+  const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double sR[kMaxS * kMaxS], sR2[kMaxS * kMaxS], sP[kLd * kMaxS];
+  switch (a.tail) {
+    case TAIL_NORM0: {
+      if (tid == 0) st->G2[0] = sred[0];
+      __syncthreads();
+    } break;
+    case TAIL_SA_NORM: {
+      if (tid == 0) {
+        double r = sqrt(sred[0]);
+        if (!(r > 0.0)) {
+          st->h.status = 2;
+          st->h.done = 1;
+        } else {
+          st->Tcur[0] = 1.0 / r;
+          st->identity_t = 0;
+          st->Hh[0] = r;
+        }
+      }
+      __syncthreads();
+    } break;
+    case TAIL_PIP: {
+      int f = tail_pip_chol(a, sred, st->Pcur, sR);
+      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      tail_set_tinv(st, sR, s);
+      tail_emit_panel(a, st->Pcur, sR, false);
+    } break;
+    case TAIL_G2COL: {
+      for (int idx = tid; idx < (k + s) * s; idx += nt) {
+        int c = idx % (k + s), j = idx / (k + s);
+        int row = (c < k) ? c : a.wcol + (c - k);
+        int col = a.wcol + j;
+        if (row <= col) st->G2[row + col * kLd] = sred[c * s + j];
+      }
+      __syncthreads();
+    } break;
+    case TAIL_PIP2_A: {
+      int f = tail_pip_chol(a, sred, st->Pcur, st->R1);
+      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      for (int idx = tid; idx < k * s; idx += nt) {
+        int c = idx % k, j = idx / k;
+        st->P1[c + j * kLd] = st->Pcur[c + j * kLd];
+      }
+      __syncthreads();
+      tail_set_tinv(st, st->R1, s);
+    } break;
+    case TAIL_PIP2_B: {
+      int f = tail_pip_chol(a, sred, st->Pcur, sR2);
+      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      tail_set_tinv(st, sR2, s);
+      // P = P1 + P2 R1,  R = R2 R1
+      for (int idx = tid; idx < k * s; idx += nt) {
+        int c = idx % k, j = idx / k;
+        double v = st->P1[c + j * kLd];
+        for (int l = 0; l <= j; ++l) v += st->Pcur[c + l * kLd] * st->R1[l + j * kMaxS];
+        sP[c + j * kLd] = v;
+      }
+      for (int idx = tid; idx < s * s; idx += nt) {
+        int i = idx % s, j = idx / s;
+        double v = 0.0;
+        for (int l = i; l <= j; ++l) v += sR2[i + l * kMaxS] * st->R1[l + j * kMaxS];
+        sR[i + j * kMaxS] = (i <= j) ? v : 0.0;
+      }
+      __syncthreads();
+      tail_emit_panel(a, sP, sR, true);
+    } break;
+    case TAIL_BC_P1: {
+      for (int idx = tid; idx < k * s; idx += nt) {
+        int c = idx % k, j = idx / k;
+        st->Pcur[c + j * kLd] = sred[c * s + j];
+        st->P1[c + j * kLd] = sred[c * s + j];
+      }
+      if (tid == 0) st->identity_t = 1;
+      __syncthreads();
+    } break;
+    case TAIL_BC_A1: {
+      int f = tail_chol_rows(a, sred, k, st->Ra, st->pivot_tol);
+      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      tail_set_tinv(st, st->Ra, s);
+    } break;
+    case TAIL_BC_A2: {
+      // this launch has k = 0 (the panel alone)
+      int f = tail_chol_rows(a, sred, 0, sR, st->pivot_tol);
+      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      tail_set_tinv(st, sR, s);
+      for (int idx = tid; idx < s * s; idx += nt) {
+        int i = idx % s, j = idx / s;
+        double v = 0.0;
+        for (int l = i; l <= j; ++l) v += sR[i + l * kMaxS] * st->Ra[l + j * kMaxS];
+        sR2[i + j * kMaxS] = (i <= j) ? v : 0.0;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < s * s; idx += nt) st->Ra[idx % s + (idx / s) * kMaxS] = sR2[idx % s + (idx / s) * kMaxS];
+      __syncthreads();
+    } break;
+    case TAIL_BC_P2: {
+      for (int idx = tid; idx < k * s; idx += nt) {
+        int c = idx % k, j = idx / k;
+        st->Pcur[c + j * kLd] = sred[c * s + j];
+        st->P2[c + j * kLd] = sred[c * s + j];
+      }
+      if (tid == 0) st->identity_t = 1;
+      __syncthreads();
+    } break;
+    case TAIL_BC_C: {
+      int f = tail_chol_rows(a, sred, k, sR2, st->pivot_tol);
+      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      tail_set_tinv(st, sR2, s);
+      // P = P1 + P2 Ra,  R = Rc Ra
+      for (int idx = tid; idx < k * s; idx += nt) {
+        int c = idx % k, j = idx / k;
+        double v = st->P1[c + j * kLd];
+        for (int l = 0; l <= j; ++l) v += st->P2[c + l * kLd] * st->Ra[l + j * kMaxS];
+        sP[c + j * kLd] = v;
+      }
+      for (int idx = tid; idx < s * s; idx += nt) {
+        int i = idx % s, j = idx / s;
+        double v = 0.0;
+        for (int l = i; l <= j; ++l) v += sR2[i + l * kMaxS] * st->Ra[l + j * kMaxS];
+        sR[i + j * kMaxS] = (i <= j) ? v : 0.0;
+      }
+      __syncthreads();
+      tail_emit_panel(a, sP, sR, true);
+    } break;
+    case TAIL_CGS_H1: {
+      for (int c = tid; c < k; c += nt) {
+        st->Pcur[c] = sred[c];
+        st->P1[c] = sred[c];
+      }
+      if (tid == 0) st->identity_t = 1;
+      __syncthreads();
+    } break;
+    case TAIL_CGS_H2: {
+      // h2 = sred(0:k), ||w1||^2 = sred(k); beta^2 = ||w1||^2 - ||h2||^2 (Pythagorean)
+      const int j = k - 1;  // Hessenberg column of this iteration
+      for (int c = tid; c < k; c += nt) {
+        st->Pcur[c] = sred[c];
+        st->Hh[c + j * kLd] = st->P1[c] + sred[c];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double nw = sred[k], h2 = 0.0;
+        for (int c = 0; c < k; ++c) h2 += sred[c] * sred[c];
+        double b2 = nw - h2;
+        double beta = (b2 > st->pivot_tol * nw) ? sqrt(b2) : 0.0;
+        st->Hh[k + j * kLd] = beta;
+        st->Wk[0] = beta;
+        if (beta > 0.0) {
+          st->Tcur[0] = 1.0 / beta;
+          st->identity_t = 0;
+        }
+      }
+      __syncthreads();
+      givens_append(st, st->Hh, j, j + 1);
+      if (tid == 0) {
+        double est = fabs(st->gg[k]);
+        bool stop = (st->Wk[0] == 0.0) || (est <= st->tol * st->bnorm);
+        if (stop && k < st->m) {
+          st->h.stop_panel = a.panel;
+          st->h.k_used = k;
+        }
+      }
+      __syncthreads();
+    } break;
+    case TAIL_GRAM_OUT: {
+      for (int idx = tid; idx < (k + s) * s; idx += nt) {
+        int c = idx % (k + s), j = idx / (k + s);
+        int row = (c < k) ? c : a.wcol + (c - k);
+        st->Wk[row + (a.wcol + j) * kLd] = sred[c * s + j];
+      }
+      __syncthreads();
+    } break;
+    default:
+      break;
+  }
+}
+
+// ----------------------------------------------------------------------------- kernel
+template <typename T, int S, int RPL>
+__global__ __launch_bounds__(512) void panel_kernel(PanelArgs a) {
+  SmallState* st = a.st;
+  if (a.gate && (st->h.done || a.panel > st->h.stop_panel)) return;
+  constexpr int NW = 8;
+  constexpr int BR = kWave * RPL;  // rows per batch
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int k = a.k, sw = a.sw, ncol = k + sw;
+  const int flags = a.flags;
+  const bool hasP = flags & PF_HAS_P;
+  const bool hasT = (flags & PF_HAS_T) && !st->identity_t;
+  const bool store = flags & PF_STORE;
+  const bool gramQ = flags & PF_GRAM_Q;
+  const bool gramW = flags & PF_GRAM_W;
+  const bool loadQ = hasP || gramQ;
+  T* __restrict__ V = reinterpret_cast<T*>(a.V);
+  const int64_t ld = a.ld;
+
+  __shared__ T ly[NW][S][BR];
+  __shared__ T lw[S][BR];
+  __shared__ T lP[kMaxCols][S];
+  __shared__ T lT[S][S];
+  __shared__ double sred[kMaxCols * kMaxS];
+
+  for (int idx = threadIdx.x; idx < kMaxCols * S; idx += blockDim.x) {
+    int c = idx / S, j = idx % S;
+    lP[c][j] = (hasP && c < k && j < sw) ? (T)st->Pcur[c + j * kLd] : (T)0;
+  }
+  for (int idx = threadIdx.x; idx < S * S; idx += blockDim.x) {
+    int i = idx / S, j = idx % S;
+    lT[i][j] = (i < sw && j < sw && i <= j) ? (T)st->Tcur[i + j * kMaxS] : (T)0;
+  }
+  __syncthreads();
+
+  T acc[8][S];
+#pragma unroll
+  for (int sl = 0; sl < 8; ++sl)
+#pragma unroll
+    for (int j = 0; j < S; ++j) acc[sl][j] = (T)0;
+
+  const int64_t rb = (int64_t)blockIdx.x * a.rows_per_block;
+  const int64_t re = min(a.n, rb + a.rows_per_block);
+  for (int64_t r0 = rb; r0 < re; r0 += BR) {
+    T v[8][RPL];
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) {
+      const int c = wv + NW * sl;
+      const bool ok = (c < ncol) && (c >= k || loadQ);
+      const int64_t col = (c < k) ? c : (int64_t)a.wcol + (c - k);
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        const int64_t row = r0 + lane + kWave * t;
+        v[sl][t] = (ok && row < re) ? V[col * ld + row] : (T)0;
+      }
+    }
+    if (hasP) {
+      T yp[S][RPL];
+#pragma unroll
+      for (int j = 0; j < S; ++j)
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) yp[j][t] = (T)0;
+#pragma unroll
+      for (int sl = 0; sl < 8; ++sl) {
+        const int c = wv + NW * sl;
+        if (c < k) {
+#pragma unroll
+          for (int j = 0; j < S; ++j) {
+            const T p = lP[c][j];
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) yp[j][t] += v[sl][t] * p;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < S; ++j)
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) ly[wv][j][lane + kWave * t] = yp[j][t];
+    }
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) {
+      const int c = wv + NW * sl;
+      if (c >= k && c < ncol) {
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) lw[c - k][lane + kWave * t] = v[sl][t];
+      }
+    }
+    __syncthreads();
+    T q[S][RPL];
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        T y = (j < sw) ? lw[j][lane + kWave * t] : (T)0;
+        if (hasP) {
+#pragma unroll
+          for (int g = 0; g < NW; ++g) y -= ly[g][j][lane + kWave * t];
+        }
+        q[j][t] = y;
+      }
+    if (hasT) {
+#pragma unroll
+      for (int j = S - 1; j >= 0; --j)
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          T acc2 = (T)0;
+#pragma unroll
+          for (int i = 0; i <= j; ++i) acc2 += q[i][t] * lT[i][j];
+          q[j][t] = acc2;
+        }
+    }
+    // q of this wave's own panel columns (static register indexing via selects)
+#pragma unroll
+    for (int sl = 0; sl < 8; ++sl) {
+      const int c = wv + NW * sl;
+      if (c >= k && c < ncol) {
+        const int jj = c - k;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          T qv = (T)0;
+#pragma unroll
+          for (int j = 0; j < S; ++j) qv = (j == jj) ? q[j][t] : qv;
+          v[sl][t] = qv;  // reuse: v now holds q for panel columns
+          const int64_t row = r0 + lane + kWave * t;
+          if (store && row < re) V[((int64_t)a.wcol + jj) * ld + row] = qv;
+        }
+      }
+    }
+    if (gramQ || gramW) {
+#pragma unroll
+      for (int sl = 0; sl < 8; ++sl) {
+        const int c = wv + NW * sl;
+        const bool use = (c < k) ? gramQ : (c < ncol && gramW);
+        if (use) {
+#pragma unroll
+          for (int j = 0; j < S; ++j)
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) acc[sl][j] += v[sl][t] * q[j][t];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (!(gramQ || gramW)) return;
+  const int E = ncol * sw;
+  double* part = a.part1 + (size_t)blockIdx.x * E;
+#pragma unroll
+  for (int sl = 0; sl < 8; ++sl) {
+    const int c = wv + NW * sl;
+    if (c < ncol) {
+      const bool use = (c < k) ? gramQ : gramW;
+#pragma unroll
+      for (int j = 0; j < S; ++j) {
+        if (j < sw) {
+          T sum = wave_sum(acc[sl][j]);
+          if (lane == 0) part[c * sw + j] = use ? (double)sum : 0.0;
+        }
+      }
+    }
+  }
+  bool last = last_block_reduce(a.part1, a.part2, a.cnt, E, a.nblocks,
+                                [&](int e, double val) { sred[e] = val; });
+  if (!last) return;
+  __syncthreads();
+  panel_tail(a, sred);
+}
+
+}  // namespace tsg

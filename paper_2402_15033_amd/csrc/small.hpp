@@ -1,0 +1,167 @@
+// Small dense float64 routines executed by one thread block (the tails of the
+// reduction kernels and the end-of-cycle kernel).  Matrices are column-major; every
+// routine must be called by all threads of the block and ends with a barrier.
+#pragma once
+
+#include "state.hpp"
+
+namespace tsg {
+
+// Upper Cholesky factor R of the k x k symmetric matrix G (upper triangle read):
+// R^T R = G, R_jj > 0 (Fig. 3's Chol).  Row-oriented: pivot d_j = G_jj - sum_{i<j} R_ij^2;
+// the pivot fails when it is not > tol * ref_j (ref = ref_diag, or diag(G) if NULL),
+// which with tol = 0 is the usual "not positive definite" test.  Returns -1 on success
+// or the first failing pivot index.  The strictly lower part of R is zeroed.
+__device__ int block_chol_upper(const double* G, int ldg, double* R, int ldr, int k,
+                                const double* ref_diag, double tol) {
+  __shared__ double s_piv;
+  __shared__ int s_fail;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int idx = tid; idx < k * k; idx += nt) {
+    int i = idx % k, c = idx / k;
+    if (i > c) R[i + c * ldr] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      double d = G[j + j * ldg];
+      for (int i = 0; i < j; ++i) {
+        double r = R[i + j * ldr];
+        d -= r * r;
+      }
+      double ref = ref_diag ? ref_diag[j] : G[j + j * ldg];
+      int fail = !(d > tol * ref);
+      s_fail = fail;
+      s_piv = fail ? 0.0 : sqrt(d);
+      if (!fail) R[j + j * ldr] = s_piv;
+    }
+    __syncthreads();
+    if (s_fail) return j;
+    const double rjj = s_piv;
+    for (int c = j + 1 + tid; c < k; c += nt) {
+      double v = G[j + c * ldg];
+      for (int i = 0; i < j; ++i) v -= R[i + j * ldr] * R[i + c * ldr];
+      R[j + c * ldr] = v / rjj;
+    }
+    __syncthreads();
+  }
+  return -1;
+}
+
+// X = R^{-1} for upper-triangular k x k R (one thread per column of X).
+__device__ void block_tri_inv_upper(const double* R, int ldr, double* X, int ldx, int k) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int c = tid; c < k; c += nt) {
+    for (int i = k - 1; i >= 0; --i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      if (i <= c) {
+        for (int l = i + 1; l <= c; ++l) v -= R[i + l * ldr] * X[l + c * ldx];
+        v /= R[i + i * ldr];
+      }
+      X[i + c * ldx] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// C (a x b) = A (a x l) * B (l x b), general, parallel over entries.
+__device__ void block_gemm(const double* A, int lda, const double* B, int ldb, double* C, int ldc,
+                           int a, int l, int b) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int idx = tid; idx < a * b; idx += nt) {
+    int i = idx % a, j = idx / a;
+    double v = 0.0;
+    for (int t = 0; t < l; ++t) v += A[i + t * lda] * B[t + j * ldb];
+    C[i + j * ldc] = v;
+  }
+  __syncthreads();
+}
+
+// Hessenberg block of one s-step panel (the small-matrix algebra of Fig. 1):
+//   [w_0, W] = Qb_{1:k+s} S,  S(:,1) = e_k,  S(:,2:s+1) = [P; R]
+//   A [w_0..w_{s-1}] = [w_0..w_s] B,  B(i,i) = theta_i, B(i+1,i) = sigma_i
+//   H(1:k+s, k:k+s-1) = (S B - [H(1:k,1:k-1) S(1:k-1,1:s); 0]) T^{-1},
+//   T = S(k:k+s-1, 1:s).
+// P (k x s, ld kLd) and R (s x s, ld kMaxS) are the panel factors, H (ld kLd) holds
+// columns 0..k-2 on entry.  M is a kLd x kMaxS scratch.  0-based: the new columns are
+// k-1 .. k+s-2 and rows 0 .. k+s-1.
+__device__ void block_hessenberg_panel(double* H, const double* P, const double* R,
+                                       const double* theta, const double* sigma, int k, int s,
+                                       double* M) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int rows = k + s;
+  auto Sv = [&](int i, int l) -> double {  // S(i, l), 0-based, l in [0, s]
+    if (l == 0) return (i == k - 1) ? 1.0 : 0.0;
+    return (i < k) ? P[i + (l - 1) * kLd] : R[(i - k) + (l - 1) * kMaxS];
+  };
+  for (int idx = tid; idx < rows * s; idx += nt) {
+    int i = idx % rows, c = idx / rows;
+    double v = Sv(i, c) * theta[c] + Sv(i, c + 1) * sigma[c];
+    if (c >= 1 && i < k) {
+      for (int l = 0; l < k - 1; ++l) v -= H[i + l * kLd] * P[l + (c - 1) * kLd];
+    }
+    M[i + c * kLd] = v;
+  }
+  __syncthreads();
+  // right solve with T (upper triangular): X(:,c) = (M(:,c) - sum_{a<c} X(:,a) T(a,c)) / T(c,c)
+  auto Tv = [&](int a, int c) -> double {
+    if (c == 0) return (a == 0) ? 1.0 : 0.0;
+    if (a == 0) return P[(k - 1) + (c - 1) * kLd];
+    return R[(a - 1) + (c - 1) * kMaxS];
+  };
+  for (int c = 0; c < s; ++c) {
+    for (int i = tid; i < rows; i += nt) {
+      double v = M[i + c * kLd];
+      for (int a = 0; a < c; ++a) v -= H[i + (k - 1 + a) * kLd] * Tv(a, c);
+      H[i + (k - 1 + c) * kLd] = v / Tv(c, c);
+    }
+    __syncthreads();
+  }
+}
+
+// Append Hessenberg columns c0..c1-1 (0-based) to the incremental Givens QR held in
+// st (rotations gc/gs, rhs gg, triangular Rg).  One thread; columns are copied to
+// a local buffer so the rotation chain runs in registers / LDS.
+__device__ void givens_append(SmallState* st, const double* H, int c0, int c1) {
+  __shared__ double col[kLd + 1];
+  if (threadIdx.x == 0) {
+    for (int c = c0; c < c1; ++c) {
+      for (int i = 0; i <= c + 1; ++i) col[i] = H[i + c * kLd];
+      for (int i = 0; i < c; ++i) {
+        double cs = st->gc[i], sn = st->gs[i];
+        double a = col[i], b = col[i + 1];
+        col[i] = cs * a + sn * b;
+        col[i + 1] = -sn * a + cs * b;
+      }
+      double a = col[c], b = col[c + 1];
+      double rho = hypot(a, b);
+      double cs = 1.0, sn = 0.0;
+      if (rho != 0.0) {
+        cs = a / rho;
+        sn = b / rho;
+      }
+      st->gc[c] = cs;
+      st->gs[c] = sn;
+      col[c] = rho;
+      for (int i = 0; i <= c; ++i) st->Rg[i + c * kLd] = col[i];
+      double gk = st->gg[c];
+      st->gg[c] = cs * gk;
+      st->gg[c + 1] = -sn * gk;
+    }
+  }
+  __syncthreads();
+}
+
+// coef(0:k) = Rg(0:k,0:k)^{-1} gg(0:k) (back substitution, one thread).
+__device__ void givens_solve(SmallState* st, int k) {
+  if (threadIdx.x == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      double v = st->gg[i];
+      for (int l = i + 1; l < k; ++l) v -= st->Rg[i + l * kLd] * st->coef[l];
+      st->coef[i] = v / st->Rg[i + i * kLd];
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace tsg

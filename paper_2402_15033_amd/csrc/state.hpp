@@ -1,0 +1,51 @@
+// Device-resident state of one solve: parameters, cycle control flags and every
+// small dense matrix of the method, in one block of device memory (float64).
+// Small matrices are column-major with leading dimension kLd = 64.
+#pragma once
+
+#include "common.hpp"
+
+namespace tsg {
+
+// Head: read back by the host once per restart cycle (keep it first and small).
+struct StateHead {
+  int32_t done;          // solve finished: every later kernel returns at entry
+  int32_t status;        // 0 converged, 1 max_iters reached, 2 breakdown
+  int32_t stop_panel;    // panels with a larger index are skipped in this cycle
+  int32_t k_used;        // Krylov vectors kept in the current cycle
+  int64_t iters;         // Krylov vectors generated so far (all cycles)
+  int64_t cycles;        // restart cycles completed
+  double relres;         // explicit relative residual at the last check
+  double est;            // implicit relative residual estimate at the end of the last cycle
+  int32_t truncated;     // cycles truncated by a Cholesky breakdown
+  int32_t pad;
+};
+
+struct SmallState {
+  StateHead h;
+  // parameters (written by the host at solve start)
+  int32_t m, s, ortho, prec;
+  int64_t max_iters;
+  double tol, bnorm, pivot_tol;
+  double theta[kMaxS], sigma[kMaxS];
+  // cycle scalars
+  double beta, inv_beta;
+  int32_t identity_t;    // the next update kernel uses T = I (no scaling)
+  int32_t pad2;
+  // small matrices
+  double Hh[kLd * kLd];    // Hessenberg of the basis, (m+1) x m
+  double G2[kLd * kLd];    // stage-2 Gram of the pre-processed basis (upper triangle)
+  double Wk[kLd * kLd];    // scratch matrix
+  double Pcur[kLd * kMaxS];   // P read by the next update kernel (k x s)
+  double Tcur[kMaxS * kMaxS]; // upper-triangular T read by the next update kernel
+  double P1[kLd * kMaxS];     // first-pass projection coefficients
+  double R1[kMaxS * kMaxS];   // first-pass triangular factor
+  double Ra[kMaxS * kMaxS];   // accumulated CholQR factor (BCGS2 + CholQR2)
+  double P2[kLd * kMaxS];     // second-pass projection coefficients
+  // Givens state of the one-stage variants and of standard GMRES
+  double gc[kLd], gs[kLd], gg[kLd + 1];
+  double Rg[kLd * kLd];       // Givens-triangularized Hessenberg
+  double coef[kLd];           // x-update coefficients of the current cycle
+};
+
+}  // namespace tsg

@@ -1,0 +1,708 @@
+// C ABI and host driver of the tsgmres library (s-step GMRES with two-stage block
+// orthogonalization, arXiv:2402.15033) for AMD MI355X (gfx950).
+//
+// The host only enqueues kernels on the caller's stream and, once per restart cycle,
+// reads back the 64-byte StateHead; every numerical decision (convergence, breakdown,
+// truncation) is taken on the device by the tails of the reduction kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tsgmres.h"
+#include "kernels.hpp"
+
+using namespace tsg;
+
+struct tsg_csr_s {
+  int64_t n, nnz;
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const double* val;
+  double lo, hi;
+  double* dev;  // 4 KiB: Gershgorin partials scratch of the final reduce
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+tsg_status fail(tsg_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(TSG_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define HIP_LAUNCH_CHECK()                                                              \
+  do {                                                                                  \
+    hipError_t e_ = hipGetLastError();                                                  \
+    if (e_ != hipSuccess) return fail(TSG_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Leading dimension of a basis with n rows: a multiple of 64 elements; a column
+// stride that is a multiple of 64 KiB elements gets 64 more so that the 8 columns
+// read side by side by one block do not all start on the same HBM channel.
+int64_t basis_ld(int64_t n) {
+  int64_t ld = (n + 63) / 64 * 64;
+  if (ld % 65536 == 0) ld += 64;
+  return ld;
+}
+
+constexpr int kPanelThreads = 512;
+constexpr int kMaxPanelBlocks = 512;
+constexpr int kCounters = 1 + 4096;  // level-2 + level-1 counters (n / 256 / 16 groups max)
+
+// Workspace carving shared by solve and orthogonalize.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+struct Common {
+  SmallState* st;
+  unsigned* cnt;
+  double* part1;
+  double* part2;
+  size_t part1_n, part2_n;
+};
+
+size_t common_bytes(int64_t n) {
+  int64_t nb_rows = cdiv(n, kRowBlock);
+  size_t p1 = std::max<size_t>((size_t)kMaxPanelBlocks * kMaxCols * kMaxS, (size_t)nb_rows);
+  size_t p2 = std::max<size_t>((size_t)cdiv(kMaxPanelBlocks, kGroup) * kMaxCols * kMaxS,
+                               (size_t)cdiv(nb_rows, kGroup));
+  if (cdiv(nb_rows, kGroup) + 1 > kCounters) return (size_t)-1;
+  return align_up(sizeof(SmallState)) + align_up(kCounters * sizeof(unsigned)) +
+         align_up(p1 * sizeof(double)) + align_up(p2 * sizeof(double));
+}
+
+Common carve_common(Carve& cv, int64_t n) {
+  Common c;
+  int64_t nb_rows = cdiv(n, kRowBlock);
+  c.part1_n = std::max<size_t>((size_t)kMaxPanelBlocks * kMaxCols * kMaxS, (size_t)nb_rows);
+  c.part2_n = std::max<size_t>((size_t)cdiv(kMaxPanelBlocks, kGroup) * kMaxCols * kMaxS,
+                               (size_t)cdiv(nb_rows, kGroup));
+  c.st = cv.take<SmallState>(1);
+  c.cnt = cv.take<unsigned>(kCounters);
+  c.part1 = cv.take<double>(c.part1_n);
+  c.part2 = cv.take<double>(c.part2_n);
+  return c;
+}
+
+__global__ void zero_u32_kernel(unsigned* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+__global__ void zero_f64_kernel(double* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// ------------------------------------------------------------------ kernel classes
+enum KClass { KC_SPMV = 0, KC_REDUCE, KC_UPDATE, KC_SMALL, KC_XUPD, KC_RESID, KC_N };
+
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<int> cls;
+  size_t used = 0;
+  double ms[KC_N] = {0};
+  int64_t count[KC_N] = {0};
+  double bytes[KC_N] = {0};
+  ~Timer() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(hipStream_t s, int c) {
+    if (!on) return;
+    hipEvent_t e = next();
+    if (e) (void)hipEventRecord(e, s);
+    cls.push_back(c);
+  }
+  void end(hipStream_t s) {
+    if (!on) return;
+    hipEvent_t e = next();
+    if (e) (void)hipEventRecord(e, s);
+  }
+  // after a stream synchronization: fold the recorded pairs into the totals
+  void harvest() {
+    if (!on) return;
+    for (size_t i = 0; i < cls.size(); ++i) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, pool[2 * i], pool[2 * i + 1]) == hipSuccess) ms[cls[i]] += t;
+    }
+    cls.clear();
+    used = 0;
+  }
+};
+
+// ------------------------------------------------------------------ panel launcher
+struct PanelCtx {
+  void* V;
+  int64_t ld, n;
+  int elem;  // sizeof(T)
+  bool f32;
+  Common c;
+  hipStream_t stream;
+  Timer* timer;
+  int standalone;
+};
+
+template <typename T, int S>
+void launch_panel_t(const PanelArgs& a, int nb, hipStream_t s) {
+  constexpr int RPL = (S <= 6) ? 2 : 1;
+  hipLaunchKernelGGL((panel_kernel<T, S, RPL>), dim3(nb), dim3(kPanelThreads), 0, s, a);
+}
+
+template <typename T>
+void launch_panel_dispatch(const PanelArgs& a, int nb, hipStream_t s) {
+  switch (a.sw) {
+    case 1: launch_panel_t<T, 1>(a, nb, s); break;
+    case 2: launch_panel_t<T, 2>(a, nb, s); break;
+    case 3: launch_panel_t<T, 3>(a, nb, s); break;
+    case 4: launch_panel_t<T, 4>(a, nb, s); break;
+    case 5: launch_panel_t<T, 5>(a, nb, s); break;
+    case 6: launch_panel_t<T, 6>(a, nb, s); break;
+    case 7: case 8: launch_panel_t<T, 8>(a, nb, s); break;
+    case 9: case 10: launch_panel_t<T, 10>(a, nb, s); break;
+    case 11: case 12: launch_panel_t<T, 12>(a, nb, s); break;
+    default: launch_panel_t<T, 16>(a, nb, s); break;
+  }
+}
+
+int panel_rpl(int sw) {
+  int S = sw <= 6 ? sw : (sw <= 8 ? 8 : (sw <= 10 ? 10 : (sw <= 12 ? 12 : 16)));
+  return S <= 6 ? 2 : 1;
+}
+
+tsg_status panel(const PanelCtx& p, int k, int wcol, int sw, int flags, int tail, int panel_idx,
+                 int kkeep, int gate = 1) {
+  PanelArgs a{};
+  a.V = p.V;
+  a.ld = p.ld;
+  a.n = p.n;
+  a.k = k;
+  a.wcol = wcol;
+  a.sw = sw;
+  a.flags = flags;
+  a.tail = tail;
+  a.gate = gate;
+  a.standalone = p.standalone;
+  a.kkeep = kkeep;
+  a.panel = panel_idx;
+  a.st = p.c.st;
+  a.part1 = p.c.part1;
+  a.part2 = p.c.part2;
+  a.cnt = p.c.cnt;
+  const int br = kWave * panel_rpl(sw);
+  int64_t tiles = cdiv(p.n, br);
+  int nb = (int)std::min<int64_t>(tiles, kMaxPanelBlocks);
+  a.rows_per_block = cdiv(cdiv(p.n, nb), br) * br;
+  nb = (int)cdiv(p.n, a.rows_per_block);
+  a.nblocks = nb;
+  const bool upd = flags & PF_STORE;
+  const bool loadQ = (flags & (PF_HAS_P | PF_GRAM_Q)) != 0;
+  double cols = (loadQ ? k : 0) + sw + (upd ? sw : 0);
+  if (p.timer) {
+    int kc = upd ? KC_UPDATE : KC_REDUCE;
+    p.timer->count[kc] += 1;
+    p.timer->bytes[kc] += cols * (double)p.n * p.elem;
+    p.timer->begin(p.stream, kc);
+  }
+  if (p.f32) launch_panel_dispatch<float>(a, nb, p.stream);
+  else launch_panel_dispatch<double>(a, nb, p.stream);
+  if (p.timer) p.timer->end(p.stream);
+  HIP_LAUNCH_CHECK();
+  return TSG_OK;
+}
+
+#define TRY(x)                  \
+  do {                          \
+    tsg_status s_ = (x);        \
+    if (s_ != TSG_OK) return s_; \
+  } while (0)
+
+}  // namespace
+
+// =================================================================== C ABI
+// (the entry points keep the C linkage of their declarations in tsgmres.h)
+
+const char* tsg_status_string(tsg_status st) {
+  switch (st) {
+    case TSG_OK: return "ok";
+    case TSG_NOT_CONVERGED: return "not converged";
+    case TSG_BREAKDOWN: return "breakdown";
+    case TSG_ERR_INVALID_ARG: return "invalid argument";
+    case TSG_ERR_HIP: return "HIP runtime error";
+    case TSG_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case TSG_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* tsg_last_error(void) { return g_err.c_str(); }
+
+tsg_status tsg_csr_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
+                          const double* val, void* stream, tsg_csr* out) {
+  if (!out) return fail(TSG_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || nnz < 0 || nnz >= (int64_t(1) << 31) || n >= (int64_t(1) << 31))
+    return fail(TSG_ERR_INVALID_ARG, "bad sizes n=%lld nnz=%lld", (long long)n, (long long)nnz);
+  if (!row_ptr || (nnz > 0 && (!col || !val)))
+    return fail(TSG_ERR_INVALID_ARG, "NULL CSR array");
+  hipStream_t s = (hipStream_t)stream;
+  tsg_csr A = new (std::nothrow) tsg_csr_s();
+  if (!A) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
+  A->n = n;
+  A->nnz = nnz;
+  A->row_ptr = row_ptr;
+  A->col = col;
+  A->val = val;
+  int nb = (int)cdiv(n, kRowBlock);
+  double* part = nullptr;
+  hipError_t e = hipMalloc(&A->dev, 4096);
+  if (e == hipSuccess) e = hipMallocAsync(&part, sizeof(double) * 2 * nb, s);
+  if (e != hipSuccess) {
+    if (A->dev) (void)hipFree(A->dev);
+    delete A;
+    return fail(TSG_ERR_HIP, "allocation failed: %s", hipGetErrorString(e));
+  }
+  hipLaunchKernelGGL(gershgorin_kernel, dim3(nb), dim3(kRowBlock), 0, s, row_ptr, col, val, n, part);
+  hipLaunchKernelGGL(minmax_final_kernel, dim3(1), dim3(kRowBlock), 0, s, part, nb, A->dev);
+  double lohi[2] = {0, 0};
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(lohi, A->dev, sizeof(lohi), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipFreeAsync(part, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(A->dev);
+    delete A;
+    return fail(TSG_ERR_HIP, "Gershgorin pass failed: %s", hipGetErrorString(e));
+  }
+  A->lo = lohi[0];
+  A->hi = lohi[1];
+  *out = A;
+  return TSG_OK;
+}
+
+tsg_status tsg_csr_destroy(tsg_csr A) {
+  if (!A) return TSG_OK;
+  hipError_t e = hipFree(A->dev);
+  delete A;
+  if (e != hipSuccess) return fail(TSG_ERR_HIP, "hipFree: %s", hipGetErrorString(e));
+  return TSG_OK;
+}
+
+tsg_status tsg_csr_gershgorin(tsg_csr A, double* lo, double* hi) {
+  if (!A || !lo || !hi) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  *lo = A->lo;
+  *hi = A->hi;
+  return TSG_OK;
+}
+
+tsg_status tsg_spmv(tsg_csr A, const double* x, double* y, void* stream) {
+  if (!A || !x || !y) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  int nb = (int)cdiv(A->n, kRowBlock);
+  hipLaunchKernelGGL(spmv_f64_kernel, dim3(nb), dim3(kRowBlock), 0, (hipStream_t)stream,
+                     A->row_ptr, A->col, A->val, x, y, A->n);
+  HIP_LAUNCH_CHECK();
+  return TSG_OK;
+}
+
+static tsg_status validate_params(int64_t n, const tsg_solve_params* p) {
+  if (!p) return fail(TSG_ERR_INVALID_ARG, "params is NULL");
+  if (p->m < 1 || p->m + 1 > kMaxCols) return fail(TSG_ERR_INVALID_ARG, "m=%d outside [1, 63]", p->m);
+  if (p->m + 1 > n) return fail(TSG_ERR_INVALID_ARG, "m+1=%d exceeds n=%lld", p->m + 1, (long long)n);
+  if (p->ortho < 0 || p->ortho > 3) return fail(TSG_ERR_INVALID_ARG, "bad ortho %d", p->ortho);
+  if (p->ortho != TSG_ORTHO_CGS2) {
+    if (p->s < 1 || p->s > kMaxS) return fail(TSG_ERR_INVALID_ARG, "s=%d outside [1, 16]", p->s);
+    if (p->m % p->s != 0) return fail(TSG_ERR_INVALID_ARG, "s=%d does not divide m=%d", p->s, p->m);
+  }
+  if (p->s_hat != 0 && p->s_hat != p->m)
+    return fail(TSG_ERR_UNSUPPORTED, "s_hat=%d: only s_hat = m is built", p->s_hat);
+  if (p->basis < 0 || p->basis > 2) return fail(TSG_ERR_INVALID_ARG, "bad basis %d", p->basis);
+  if (p->basis == TSG_BASIS_NEWTON && !p->newton_shifts)
+    return fail(TSG_ERR_INVALID_ARG, "newton basis needs newton_shifts");
+  if (p->precision < 0 || p->precision > 1) return fail(TSG_ERR_INVALID_ARG, "bad precision");
+  if (!(p->tol >= 0.0)) return fail(TSG_ERR_INVALID_ARG, "bad tol");
+  if (p->max_iters < 0) return fail(TSG_ERR_INVALID_ARG, "bad max_iters");
+  return TSG_OK;
+}
+
+size_t tsg_solve_workspace_bytes(int64_t n, int64_t nnz, const tsg_solve_params* p) {
+  if (n < 1 || !p || validate_params(n, p) != TSG_OK) return 0;
+  size_t cb = common_bytes(n);
+  if (cb == (size_t)-1) return 0;
+  size_t elem = p->precision == TSG_PREC_FP32_IR ? 4 : 8;
+  size_t basis = align_up((size_t)basis_ld(n) * (p->m + 1) * elem);
+  size_t v32 = p->precision == TSG_PREC_FP32_IR ? align_up((size_t)nnz * 4) : 0;
+  return cb + basis + v32 + kAlign;
+}
+
+namespace {
+
+template <typename T, typename VT>
+tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_params* p,
+                     const Common& c, T* V, int64_t ld, const VT* val, hipStream_t s,
+                     tsg_solve_info* info) {
+  const int64_t n = A->n;
+  const int m = p->m;
+  const int ortho = p->ortho;
+  const int sstep = (ortho == TSG_ORTHO_CGS2) ? 1 : p->s;
+  const int J = m / sstep;
+  const bool two = ortho == TSG_ORTHO_TWO_STAGE;
+  const bool f32 = sizeof(T) == 4;
+  Timer timer;
+  timer.on = p->timing != 0;
+  PanelCtx pc{V, ld, n, (int)sizeof(T), f32, c, s, &timer, 0};
+
+  // basis parameters from the Gershgorin interval (Sec. VI uses the monomial basis)
+  std::vector<double> theta(sstep), sigma(sstep);
+  const double lo = A->lo, hi = A->hi;
+  for (int i = 0; i < sstep; ++i) {
+    if (ortho == TSG_ORTHO_CGS2) {
+      theta[i] = 0.0;
+      sigma[i] = 1.0;
+    } else if (p->basis == TSG_BASIS_MONOMIAL) {
+      theta[i] = 0.0;
+      sigma[i] = std::max(std::fabs(lo), std::fabs(hi));
+    } else if (p->basis == TSG_BASIS_SHIFTED) {
+      theta[i] = 0.5 * (lo + hi);
+      sigma[i] = 0.5 * (hi - lo);
+    } else {
+      theta[i] = p->newton_shifts[i];
+      sigma[i] = 0.5 * (hi - lo);
+    }
+    if (!(sigma[i] > 0.0)) sigma[i] = 1.0;
+  }
+
+  // parameters -> device state (head + parameter block only)
+  SmallState* hs = new (std::nothrow) SmallState();
+  if (!hs) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
+  std::memset(hs, 0, sizeof(SmallState));
+  hs->h.stop_panel = 1 << 30;
+  hs->m = m;
+  hs->s = sstep;
+  hs->ortho = ortho;
+  hs->prec = p->precision;
+  hs->max_iters = p->max_iters;
+  hs->tol = p->tol;
+  hs->pivot_tol = f32 ? kPivotTolF32 : kPivotTolF64;
+  for (int i = 0; i < sstep; ++i) {
+    hs->theta[i] = theta[i];
+    hs->sigma[i] = sigma[i];
+  }
+  const size_t head_bytes = offsetof(SmallState, Hh);
+  hipError_t e = hipMemcpyAsync(c.st, hs, head_bytes, hipMemcpyHostToDevice, s);
+  delete hs;
+  HIP_TRY(e);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(cdiv(kCounters, 256)), dim3(256), 0, s, c.cnt, kCounters);
+  const int nbr = (int)cdiv(n, kRowBlock);
+  hipLaunchKernelGGL(norm_kernel, dim3(nbr), dim3(kRowBlock), 0, s, b, n, c.st, c.part1, c.part2, c.cnt);
+  HIP_LAUNCH_CHECK();
+  double bnorm = 0.0;
+  HIP_TRY(hipMemcpyAsync(&bnorm, &c.st->bnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (bnorm == 0.0) {  // b = 0: x = 0 is the solution
+    hipLaunchKernelGGL(zero_f64_kernel, dim3(nbr), dim3(kRowBlock), 0, s, x, n);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->status = TSG_OK;
+    }
+    return TSG_OK;
+  }
+
+  StateHead* head = nullptr;
+  HIP_TRY(hipHostMalloc((void**)&head, sizeof(StateHead), hipHostMallocDefault));
+  const double spmv_bytes = (double)(n + 1) * 4 + (double)A->nnz * (4 + sizeof(VT)) + 2.0 * n * sizeof(T);
+  const double resid_bytes = (double)(n + 1) * 4 + (double)A->nnz * 12 + 2.0 * n * 8 + n * sizeof(T);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (timer.on) {
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+    HIP_TRY(hipEventRecord(t0, s));
+  }
+
+  auto mpk = [&](int col_in, int col_out, int i, int panel_idx) -> tsg_status {
+    timer.begin(s, KC_SPMV);
+    timer.count[KC_SPMV] += 1;
+    timer.bytes[KC_SPMV] += spmv_bytes;
+    hipLaunchKernelGGL((mpk_step_kernel<T, VT>), dim3(nbr), dim3(kRowBlock), 0, s, A->row_ptr, A->col,
+                       val, V + (int64_t)col_in * ld, V + (int64_t)col_out * ld, n, theta[i], sigma[i],
+                       c.st, panel_idx);
+    timer.end(s);
+    HIP_LAUNCH_CHECK();
+    return TSG_OK;
+  };
+
+  tsg_status result = TSG_OK;
+  for (;;) {
+    // ---- restart residual r = b - A x, beta, convergence test (explicit, FP64)
+    timer.begin(s, KC_RESID);
+    timer.count[KC_RESID] += 1;
+    timer.bytes[KC_RESID] += resid_bytes;
+    hipLaunchKernelGGL((residual_kernel<T>), dim3(nbr), dim3(kRowBlock), 0, s, A->row_ptr, A->col,
+                       A->val, x, b, V, n, c.st, c.part1, c.part2, c.cnt);
+    timer.end(s);
+    HIP_LAUNCH_CHECK();
+    // ---- qhat_1 = r / beta (two-stage: also G2(0,0) of the stored column)
+    TRY(panel(pc, 0, 0, 1, PF_HAS_T | PF_STORE | (two ? PF_GRAM_W : 0), two ? TAIL_NORM0 : TAIL_NONE,
+              -1, 0));
+    for (int j = 0; j < J; ++j) {
+      const int k = j * sstep + 1;
+      const int kkeep = k - 1;
+      for (int i = 0; i < sstep; ++i) TRY(mpk(k - 1 + i, k + i, i, j));
+      switch (ortho) {
+        case TSG_ORTHO_TWO_STAGE:
+          // stage 1: BCGS-PIP of the panel against all previous columns (one reduction)
+          TRY(panel(pc, k, k, sstep, PF_GRAM_Q | PF_GRAM_W, TAIL_PIP, j, kkeep));
+          // update in place; the same pass accumulates the stage-2 Gram block column
+          TRY(panel(pc, k, k, sstep, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_G2COL, j,
+                    kkeep));
+          break;
+        case TSG_ORTHO_BCGS_PIP2:
+          TRY(panel(pc, k, k, sstep, PF_GRAM_Q | PF_GRAM_W, TAIL_PIP2_A, j, kkeep));
+          TRY(panel(pc, k, k, sstep, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_PIP2_B, j,
+                    kkeep));
+          TRY(panel(pc, k, k, sstep, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep));
+          break;
+        case TSG_ORTHO_BCGS2_CHOLQR2:
+          TRY(panel(pc, k, k, sstep, PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P1, j, kkeep));
+          TRY(panel(pc, k, k, sstep, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_A1, j, kkeep));
+          TRY(panel(pc, 0, k, sstep, PF_HAS_T | PF_STORE | PF_GRAM_W, TAIL_BC_A2, j, kkeep));
+          TRY(panel(pc, k, k, sstep, PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P2, j, kkeep));
+          TRY(panel(pc, k, k, sstep, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_C, j, kkeep));
+          TRY(panel(pc, 0, k, sstep, PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep));
+          break;
+        case TSG_ORTHO_CGS2:
+          TRY(panel(pc, k, k, 1, PF_GRAM_Q | PF_GRAM_W, TAIL_CGS_H1, j, kkeep));
+          TRY(panel(pc, k, k, 1, PF_HAS_P | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_CGS_H2, j, kkeep));
+          TRY(panel(pc, k, k, 1, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep));
+          break;
+      }
+    }
+    // ---- stage 2 (two-stage) / projected least squares; counters
+    timer.begin(s, KC_SMALL);
+    timer.count[KC_SMALL] += 1;
+    hipLaunchKernelGGL(cycle_end_kernel, dim3(1), dim3(256), 0, s, c.st, two ? 1 : 0);
+    timer.end(s);
+    HIP_LAUNCH_CHECK();
+    // ---- x += V(:, 0:k_used) coef
+    timer.begin(s, KC_XUPD);
+    timer.count[KC_XUPD] += 1;
+    timer.bytes[KC_XUPD] += (double)m * n * sizeof(T) + 16.0 * n;
+    hipLaunchKernelGGL((xupdate_kernel<T>), dim3(nbr), dim3(kRowBlock), 0, s, x, V, ld, n, c.st);
+    timer.end(s);
+    HIP_LAUNCH_CHECK();
+    e = hipMemcpyAsync(head, &c.st->h, sizeof(StateHead), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      result = fail(TSG_ERR_HIP, "cycle sync failed: %s", hipGetErrorString(e));
+      break;
+    }
+    timer.harvest();
+    if (head->done) break;
+  }
+  if (timer.on && result == TSG_OK) {
+    (void)hipEventRecord(t1, s);
+    (void)hipEventSynchronize(t1);
+    float tot = 0.f;
+    (void)hipEventElapsedTime(&tot, t0, t1);
+    if (info) info->ms_total = tot;
+  }
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  StateHead h = *head;
+  (void)hipHostFree(head);
+  if (result != TSG_OK) return result;
+  tsg_status st = h.status == 0 ? TSG_OK : (h.status == 1 ? TSG_NOT_CONVERGED : TSG_BREAKDOWN);
+  if (info) {
+    double ms_total = info->ms_total;
+    std::memset(info, 0, sizeof(*info));
+    info->iters = h.iters;
+    info->cycles = h.cycles;
+    info->relres = h.relres;
+    info->relres_est = h.est;
+    info->status = st;
+    info->truncated_cycles = h.truncated;
+    if (timer.on) {
+      info->ms_total = ms_total;
+      info->ms_spmv = timer.ms[KC_SPMV];
+      info->ms_ortho_reduce = timer.ms[KC_REDUCE];
+      info->ms_ortho_update = timer.ms[KC_UPDATE];
+      info->ms_small = timer.ms[KC_SMALL];
+      info->ms_xupdate = timer.ms[KC_XUPD];
+      info->ms_residual = timer.ms[KC_RESID];
+      info->n_ortho_reduce = timer.count[KC_REDUCE];
+      info->n_ortho_update = timer.count[KC_UPDATE];
+      info->n_spmv = timer.count[KC_SPMV];
+      info->bytes_ortho_reduce = timer.bytes[KC_REDUCE];
+      info->bytes_ortho_update = timer.bytes[KC_UPDATE];
+      info->bytes_spmv = timer.bytes[KC_SPMV];
+    }
+  }
+  return st;
+}
+
+}  // namespace
+
+tsg_status tsg_solve(tsg_csr A, const double* b, double* x, const tsg_solve_params* p, void* workspace,
+                     size_t ws_bytes, void* stream, tsg_solve_info* info) {
+  if (!A || !b || !x) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  TRY(validate_params(A->n, p));
+  if (!workspace) return fail(TSG_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(TSG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  size_t need = tsg_solve_workspace_bytes(A->n, A->nnz, p);
+  if (need == 0) return fail(TSG_ERR_INVALID_ARG, "problem too large for the reduction buffers");
+  if (ws_bytes < need) return fail(TSG_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  Carve cv{(char*)workspace};
+  Common c = carve_common(cv, A->n);
+  const int64_t ld = basis_ld(A->n);
+  if (p->precision == TSG_PREC_FP32_IR) {
+    float* V = cv.take<float>((size_t)ld * (p->m + 1));
+    float* v32 = cv.take<float>((size_t)std::max<int64_t>(A->nnz, 1));
+    if (A->nnz > 0) {
+      hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(A->nnz, kRowBlock)), dim3(kRowBlock), 0, s, A->val, v32,
+                         A->nnz);
+      HIP_LAUNCH_CHECK();
+    }
+    return run_solve<float, float>(A, b, x, p, c, V, ld, v32, s, info);
+  }
+  double* V = cv.take<double>((size_t)ld * (p->m + 1));
+  return run_solve<double, double>(A, b, x, p, c, V, ld, A->val, s, info);
+}
+
+size_t tsg_orthogonalize_workspace_bytes(int64_t n, int32_t k, int32_t s) {
+  if (n < 1 || k < 1 || k > kMaxCols || s < 1 || s > kMaxS) return 0;
+  size_t cb = common_bytes(n);
+  if (cb == (size_t)-1) return 0;
+  return cb + kAlign;
+}
+
+tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr,
+                             int32_t s, int32_t s_hat, int32_t algo, void* workspace, size_t ws_bytes,
+                             void* stream, double* orth_err) {
+  if (!X || !R || !workspace) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  if (n < 1 || k < 1 || k > kMaxCols || k > n)
+    return fail(TSG_ERR_INVALID_ARG, "need 1 <= k <= min(n, 64): n=%lld k=%d", (long long)n, k);
+  if (ldx < n || ldr < k) return fail(TSG_ERR_INVALID_ARG, "leading dimension too small");
+  if (s < 1 || s > kMaxS) return fail(TSG_ERR_INVALID_ARG, "s=%d outside [1, 16]", s);
+  if (algo != TSG_ORTHO_TWO_STAGE && algo != TSG_ORTHO_BCGS_PIP2 && algo != TSG_ORTHO_BCGS2_CHOLQR2)
+    return fail(TSG_ERR_INVALID_ARG, "bad algo %d", algo);
+  if (algo == TSG_ORTHO_TWO_STAGE && s_hat != 0 && s_hat != k - 1)
+    return fail(TSG_ERR_UNSUPPORTED, "s_hat=%d: only one big panel (s_hat = k-1) is built", s_hat);
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(TSG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  size_t need = tsg_orthogonalize_workspace_bytes(n, k, s);
+  if (need == 0) return fail(TSG_ERR_INVALID_ARG, "problem too large for the reduction buffers");
+  if (ws_bytes < need) return fail(TSG_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  Carve cv{(char*)workspace};
+  Common c = carve_common(cv, n);
+  const bool two = algo == TSG_ORTHO_TWO_STAGE;
+
+  SmallState* hs = new (std::nothrow) SmallState();
+  if (!hs) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
+  std::memset(hs, 0, sizeof(SmallState));
+  hs->h.stop_panel = 1 << 30;
+  hs->pivot_tol = 0.0;  // stand-alone: fail only when a Gram is not positive definite
+  hipError_t e = hipMemcpyAsync(c.st, hs, offsetof(SmallState, Hh), hipMemcpyHostToDevice, st);
+  delete hs;
+  HIP_TRY(e);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(cdiv(kCounters, 256)), dim3(256), 0, st, c.cnt, kCounters);
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(kLd * kLd, 256)), dim3(256), 0, st, c.st->Hh,
+                     (int64_t)kLd * kLd);
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(kLd * kLd, 256)), dim3(256), 0, st, c.st->G2,
+                     (int64_t)kLd * kLd);
+  HIP_LAUNCH_CHECK();
+  PanelCtx pc{X, ldx, n, 8, false, c, st, nullptr, 1};
+  // column 1 alone
+  TRY(panel(pc, 0, 0, 1, PF_GRAM_W, TAIL_SA_NORM, -1, 0));
+  TRY(panel(pc, 0, 0, 1, PF_HAS_T | PF_STORE | (two ? PF_GRAM_W : 0), two ? TAIL_NORM0 : TAIL_NONE, -1, 0));
+  for (int c0 = 1; c0 < k; c0 += s) {
+    const int sw = std::min(s, k - c0);
+    const int kq = c0;
+    switch (algo) {
+      case TSG_ORTHO_TWO_STAGE:
+        TRY(panel(pc, kq, c0, sw, PF_GRAM_Q | PF_GRAM_W, TAIL_PIP, 0, 0));
+        TRY(panel(pc, kq, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_G2COL, 0, 0));
+        break;
+      case TSG_ORTHO_BCGS_PIP2:
+        TRY(panel(pc, kq, c0, sw, PF_GRAM_Q | PF_GRAM_W, TAIL_PIP2_A, 0, 0));
+        TRY(panel(pc, kq, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_PIP2_B, 0, 0));
+        TRY(panel(pc, kq, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, 0, 0));
+        break;
+      default:
+        TRY(panel(pc, kq, c0, sw, PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P1, 0, 0));
+        TRY(panel(pc, kq, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_A1, 0, 0));
+        TRY(panel(pc, 0, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_W, TAIL_BC_A2, 0, 0));
+        TRY(panel(pc, kq, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P2, 0, 0));
+        TRY(panel(pc, kq, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_C, 0, 0));
+        TRY(panel(pc, 0, c0, sw, PF_HAS_T | PF_STORE, TAIL_NONE, 0, 0));
+        break;
+    }
+  }
+  if (two) {
+    // stage 2: one CholQR over all k columns, then Q = Qhat R2^{-1}
+    hipLaunchKernelGGL(sa_stage2_kernel, dim3(1), dim3(256), 0, st, c.st, k);
+    HIP_LAUNCH_CHECK();
+    const int nb = (int)cdiv(n, kRowBlock);
+    // rows are independent; the kernel returns early when the solve is done (breakdown)
+    hipLaunchKernelGGL((apply_rinv_kernel<kMaxCols>), dim3(nb), dim3(kRowBlock), 0, st, X, ldx, n, k,
+                       (const double*)c.st->Wk);
+    HIP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(copy_r_kernel, dim3(1), dim3(256), 0, st, c.st, 1, k, R, ldr);
+  } else {
+    hipLaunchKernelGGL(copy_r_kernel, dim3(1), dim3(256), 0, st, c.st, 0, k, R, ldr);
+  }
+  HIP_LAUNCH_CHECK();
+  if (orth_err) {
+    for (int c0 = 0; c0 < k; c0 += kMaxS) {
+      const int sw = std::min(kMaxS, k - c0);
+      TRY(panel(pc, c0, c0, sw, PF_GRAM_Q | PF_GRAM_W, TAIL_GRAM_OUT, 0, 0, 0));
+    }
+    hipLaunchKernelGGL(orth_err_kernel, dim3(1), dim3(256), 0, st, c.st, k);
+    HIP_LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(orth_err, &c.st->beta, sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  StateHead h{};
+  HIP_TRY(hipMemcpyAsync(&h, &c.st->h, sizeof(StateHead), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h.status == 2) return fail(TSG_BREAKDOWN, "a Gram matrix was not positive definite");
+  return TSG_OK;
+}

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances (FP64):
+* SpMV: per-entry relative 4 eps (CSR order on both sides; the GPU contracts to FMA).
+* Block orthogonalization with the same scheme: ||R_gpu - R_oracle|| / ||R|| <= 1e-12 and
+  ||Q_gpu - Q_oracle|| <= 1e-12 sqrt(k) on well-conditioned blocks (rounding of the reductions
+  differs: per-lane, per-wave and per-block partial sums against BLAS); O(eps) orthogonality.
+* Solves (A-19 gates): explicit relative residual <= tol recomputed by the oracle's SpMV;
+  the same iteration count as the oracle's run of the same variant; relative difference of the
+  iterates <= 1e-10 where both ran the same cycles; error against x_true <= 2 tol kappa_2(A).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import blockortho as BO
+from oracle import dense as D
+from oracle import gmres as G
+from oracle import sparse as S
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def tsg():
+    import paper_2402_15033_amd as m
+
+    m.load_library()
+    return m
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+# ------------------------------------------------------------------------- SpMV
+@pytest.mark.parametrize("kind,N", [("laplace2d", 37), ("laplace3d", 11), ("convdiff2d", 45)])
+def test_spmv_and_gershgorin(tsg, kind, N):
+    _say("case spmv", kind, N)
+    pr = W.make_problem(kind, N, seed=3)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x = W.uniform_vector(pr["A"].n, 9)
+    y = tsg.spmv(A, _dev(x)).cpu().numpy()
+    yr = S.spmv(pr["A"], x)
+    scale = np.abs(pr["A"].to_scipy()) @ np.abs(x)
+    assert np.all(np.abs(y - yr) <= 4 * EPS * scale + 1e-300)
+    lo, hi = A.gershgorin()
+    lo_o, hi_o = S.gershgorin(pr["A"])
+    assert abs(lo - lo_o) <= 1e-14 * max(1, abs(lo_o)) and abs(hi - hi_o) <= 1e-14 * abs(hi_o)
+
+
+# ------------------------------------------------------------------------- ortho
+def _ortho_case(tsg, X, s, algo):
+    n, k = X.shape
+    Xt = _dev(X.T)  # (k, n) contiguous = column-major n x k
+    _, R, oerr = tsg.orthogonalize(Xt, s=s, algo=algo, orth_err=True)
+    Q = Xt.cpu().numpy().T
+    Rg = R.cpu().numpy()
+    Qo, Ro = BO.orthogonalize(X, s, algo)
+    return Q, Rg, Qo, Ro, oerr
+
+
+@pytest.mark.parametrize("algo", ["two_stage", "bcgs_pip2", "bcgs2_cholqr2"])
+@pytest.mark.parametrize("n,k,s", [(100003, 61, 5), (20000, 61, 10), (7777, 14, 5), (4096, 1, 5),
+                                   (129, 64, 16), (300, 9, 3)])
+def test_orthogonalize_matches_oracle(tsg, algo, n, k, s):
+    _say("case ortho", algo, n, k, s)
+    X = W.gaussian_block(n, k, seed=n + k)
+    Q, R, Qo, Ro, oerr = _ortho_case(tsg, X, s, algo)
+    assert np.allclose(np.tril(R, -1), 0)
+    assert np.linalg.norm(R - Ro) / np.linalg.norm(Ro) <= 1e-12
+    assert np.linalg.norm(Q - Qo) / np.sqrt(k) <= 1e-12
+    assert D.orth_error(Q) <= 1e-13
+    assert abs(oerr - D.orth_error(Q)) <= 1e-14
+    assert D.repr_error(X, Q, R) <= 1e-14
+
+
+def test_orthogonalize_glued_matrix(tsg):
+    _say("case ortho glued")
+    V = W.glued_block(20000, 12, 5, 1e7, seed=1)  # 61 columns, panel condition 1e7
+    for algo in ("two_stage", "bcgs_pip2", "bcgs2_cholqr2"):
+        Q, R, Qo, Ro, _ = _ortho_case(tsg, V, 5, algo)
+        assert D.orth_error(Q) <= 1e-13, algo
+        assert D.repr_error(V, Q, R) <= 1e-15, algo
+        # both are the unique QR up to kappa * eps
+        assert np.linalg.norm(R - Ro) / np.linalg.norm(Ro) <= 1e-8, algo
+
+
+def test_orthogonalize_breakdown_is_reported(tsg):
+    _say("case ortho breakdown")
+    X = W.gaussian_block(5000, 11, seed=2)
+    X[:, 7] = X[:, 3]  # exactly dependent column
+    with pytest.raises(tsg.TSGError) as ei:
+        _ortho_case(tsg, X, 5, "two_stage")
+    assert ei.value.status == 2
+
+
+# ------------------------------------------------------------------------- solves
+VARIANTS = [("two_stage", "two_stage"), ("bcgs_pip2", "bcgs_pip2"),
+            ("bcgs2_cholqr2", "bcgs2_cholqr2"), ("cgs2", "cgs2")]
+
+
+def _oracle_run(pr, variant, **kw):
+    if variant == "cgs2":
+        return G.gmres(pr["A"], pr["b"], ortho="cgs2", m=kw["m"], tol=kw["tol"])
+    return G.sstep_gmres(pr["A"], pr["b"], ortho=variant, m=kw["m"], s=kw["s"], tol=kw["tol"],
+                         basis=kw.get("basis", "monomial"))
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+@pytest.mark.parametrize("variant,_o", VARIANTS)
+def test_solve_laplace64_matches_oracle(tsg, seed, variant, _o):
+    """The 64 x 64 2D Laplace configuration: m = 60, s = 5, tol 1e-10, x0 = 0."""
+    _say("case solve laplace64", variant, seed)
+    pr = W.make_problem("laplace2d", 64, seed=seed)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=60, s=5, tol=1e-10, ortho=variant)
+    xg = x.cpu().numpy()
+    ref = _oracle_run(pr, variant, m=60, s=5, tol=1e-10)
+    bn = np.linalg.norm(pr["b"])
+    relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], xg)) / bn
+    assert info.converged and relres <= 1e-10, (info, relres)
+    assert abs(info.relres - relres) <= 1e-3 * relres + 1e-16
+    assert info.iters == ref["iters"] and info.cycles == ref["cycles"], (info.iters, ref["iters"])
+    assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
+    lmin, lmax = W.laplace_extreme_eigs(64, 2)
+    xt = pr["x_true"]
+    assert np.linalg.norm(xg - xt) / np.linalg.norm(xt) <= 2 * 1e-10 * lmax / lmin
+
+
+@pytest.mark.parametrize("variant,_o", VARIANTS)
+def test_solve_convdiff_ragged(tsg, variant, _o):
+    """Nonsymmetric operator, n = 93^2 (not a multiple of any tile), s = 5 / m = 30."""
+    _say("case solve convdiff93", variant)
+    pr = W.make_problem("convdiff2d", 93, seed=4)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=30, s=5, tol=1e-10, ortho=variant)
+    xg = x.cpu().numpy()
+    ref = _oracle_run(pr, variant, m=30, s=5, tol=1e-10)
+    relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], xg)) / np.linalg.norm(pr["b"])
+    assert info.converged and relres <= 1e-10
+    assert info.iters == ref["iters"], (info.iters, ref["iters"])
+    assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
+
+
+def test_solve_shifted_basis_s10(tsg):
+    _say("case solve shifted s10")
+    pr = W.make_problem("laplace2d", 48, seed=5)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=60, s=10, tol=1e-10, basis="shifted")
+    ref = G.sstep_gmres(pr["A"], pr["b"], m=60, s=10, tol=1e-10, basis="shifted")
+    xg = x.cpu().numpy()
+    assert info.converged and info.iters == ref["iters"]
+    assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
+
+
+def test_solve_tiny_system_with_breakdown(tsg):
+    """n = 144 converges inside a cycle; the two-stage cycle truncates at the Cholesky
+    breakdown (numerically invariant Krylov space) on both sides."""
+    _say("case solve tiny breakdown")
+    pr = W.make_problem("convdiff2d", 12, seed=0)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=30, s=5, tol=1e-10)
+    xg = x.cpu().numpy()
+    x_lu, M = G.dense_solve(pr["A"], pr["b"])
+    assert info.converged
+    assert np.linalg.norm(xg - x_lu) / np.linalg.norm(x_lu) <= 2e-10 * np.linalg.cond(M)
+
+
+def test_solve_max_iters_and_x0(tsg):
+    _say("case solve max_iters")
+    pr = W.make_problem("laplace2d", 64, seed=0)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=60, s=5, tol=1e-10, max_iters=120)
+    assert info.status == 1 and info.iters == 120 and info.cycles == 2
+    ref = G.sstep_gmres(pr["A"], pr["b"], m=60, s=5, tol=1e-10, max_iters=120)
+    assert np.linalg.norm(x.cpu().numpy() - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
+    # restart from the returned x (resume): finishes like an uninterrupted solve
+    x2, info2 = tsg.solve(A, _dev(pr["b"]), x=x.clone(), m=60, s=5, tol=1e-10)
+    assert info2.converged and info2.iters == 360 - 120
+
+
+def test_zero_rhs(tsg):
+    pr = W.make_problem("laplace2d", 16, seed=0)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x0 = torch.ones(A.n, dtype=torch.float64, device="cuda")
+    x, info = tsg.solve(A, torch.zeros_like(x0), x=x0, m=60, s=5)
+    assert info.converged and float(x.abs().max()) == 0.0
+
+
+def test_determinism(tsg):
+    _say("case determinism")
+    pr = W.make_problem("convdiff2d", 64, seed=1)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    b = _dev(pr["b"])
+    x1, _ = tsg.solve(A, b, m=60, s=5, tol=1e-10)
+    x2, _ = tsg.solve(A, b, m=60, s=5, tol=1e-10)
+    assert torch.equal(x1, x2)
