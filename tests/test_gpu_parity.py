@@ -94,11 +94,16 @@ def test_orthogonalize_glued_matrix(tsg):
 
 def test_orthogonalize_breakdown_is_reported(tsg):
     _say("case ortho breakdown")
+    # a zero column gives an exactly zero Cholesky pivot (an exactly duplicated column only
+    # gives a rounding-noise pivot of either sign, so it is not a reliable breakdown)
     X = W.gaussian_block(5000, 11, seed=2)
-    X[:, 7] = X[:, 3]  # exactly dependent column
-    with pytest.raises(tsg.TSGError) as ei:
-        _ortho_case(tsg, X, 5, "two_stage")
-    assert ei.value.status == 2
+    X[:, 7] = 0.0
+    with pytest.raises(D.CholeskyBreakdown):
+        BO.orthogonalize(X, 5, "two_stage")
+    for algo in ("two_stage", "bcgs_pip2", "bcgs2_cholqr2"):
+        with pytest.raises(tsg.TSGError) as ei:
+            _ortho_case(tsg, X, 5, algo)
+        assert ei.value.status == 2
 
 
 # ------------------------------------------------------------------------- solves
