@@ -70,10 +70,9 @@ def bcgs_pip(Q: np.ndarray, V: np.ndarray, tol: float = 0.0):
     [P; G_V] = [Q, V]^T V;  G = G_V - P^T P;  R = Chol(G);  Qnew = (V - Q P) R^{-1}.
     ``tol``: relative pivot threshold against diag(G_V) (0 = fail only if not SPD).
     """
-    k = Q.shape[1]
-    Z = np.hstack([Q, V]).T @ V  # the single fused reduction
-    P = Z[:k, :]
-    GV = Z[k:, :]
+    # the single fused reduction [Q, V]^T V, written as its two blocks
+    P = Q.T @ V
+    GV = V.T @ V
     G = GV - P.T @ P
     R = chol_upper(G, ref_diag=np.diag(GV), tol=tol)
     Qnew = right_solve_upper(V - Q @ P, R)
@@ -135,7 +134,7 @@ def orthogonalize(X: np.ndarray, s: int, algo: str = "two_stage", s_hat: int | N
     if algo == "two_stage":
         return two_stage(X, s, s_hat if s_hat is not None else k - 1)
     step = ONE_STAGE[algo]
-    Q = np.zeros((n, k))
+    Q = np.zeros((n, k), order="F")
     R = np.zeros((k, k))
     Q[:, 0], R[0, 0] = _normalize_first(X)
     for c0, c1 in panel_bounds(k, s):
@@ -180,7 +179,7 @@ def two_stage(X: np.ndarray, s: int, s_hat: int, return_stage1: bool = False):
     """
     X = np.asarray(X, dtype=np.float64)
     n, k = X.shape
-    Y = np.zeros((n, k))
+    Y = np.zeros((n, k), order="F")
     Rh = np.zeros((k, k))
     Y[:, 0], Rh[0, 0] = _normalize_first(X)
     panels = panel_bounds(k, s)

@@ -93,7 +93,7 @@ def gmres(A, b, x0=None, m: int = 60, tol: float = 1e-10, max_iters: int = 10**9
 
     def cycle(op, r, beta, tol_abs):
         n = op.n
-        Q = np.zeros((n, m + 1))
+        Q = np.zeros((n, m + 1), order="F")
         H = np.zeros((m + 1, m))
         Q[:, 0] = r / beta
         giv = GivensState(beta, m)
@@ -134,7 +134,7 @@ def gmres(A, b, x0=None, m: int = 60, tol: float = 1e-10, max_iters: int = 10**9
 def mpk(op, w0: np.ndarray, theta: np.ndarray, sigma: np.ndarray):
     """Matrix-powers kernel: s SpMVs in sequence (Sec. III).  Returns (W, B)."""
     s = len(theta)
-    W = np.zeros((op.n, s))
+    W = np.zeros((op.n, s), order="F")
     B = np.zeros((s + 1, s))
     w = w0
     for i in range(s):
@@ -172,7 +172,7 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
 
     def cycle(op, r, beta, tol_abs):
         n = op.n
-        Qh = np.zeros((n, m + 1))
+        Qh = np.zeros((n, m + 1), order="F")
         Hh = np.zeros((m + 1, m))
         Qh[:, 0] = r / beta
         giv = GivensState(beta, m)
