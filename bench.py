@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark: two-stage s-step GMRES on one MI355X.
+
+One step = one full solve of the 2D Laplace 5-point system on a 2048 x 2048 grid
+(n = 4,194,304, CSR float64), b = A x_true with x_true ~ U(-1,1) (seed 0), x0 = 0,
+restart m = 60, step s = 5, two-stage block orthogonalization (s_hat = m),
+relative residual 1e-10.  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line.  value = solves per second (whole job, one GPU).  Extra fields:
+time to solution, per-kernel-class times from HIP events recorded by the library on
+the solve's stream, the roofline of the dominant kernel, the isolated block
+orthogonalization of a 4,194,304 x 61 float64 Gaussian block, and the FP64 CPU
+oracle timed on a bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ortho time & time-to-solution (2D Laplace n=4M) + HBM GB/s; solves/s, p99"
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "panel_kernel_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2402_15033_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hpp", ".hip")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
+    current kernel sources (else None)."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=2048, help="grid side of the 2D Laplace problem")
+    ap.add_argument("--s", type=int, default=5)
+    ap.add_argument("--m", type=int, default=60)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--ortho", default="two_stage",
+                    choices=["two_stage", "bcgs_pip2", "bcgs2_cholqr2", "cgs2"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_ir"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ortho-bench", action="store_true")
+    ap.add_argument("--ortho-reps", type=int, default=20)
+    ap.add_argument("--cpu-cycles", type=int, default=1)
+    ap.add_argument("--compare", action="store_true",
+                    help="also time one solve of each other orthogonalization scheme")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on exactly one GPU (the whole problem fits one MI355X); "
+              "multi-GPU runs are not part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2402_15033_amd as tsg
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    tsg.load_library()
+    N = args.N
+    log(f"[bench] building 2D Laplace {N}x{N}")
+    pr = W.make_problem("laplace2d", N, seed=0)
+    Ah = pr["A"]
+    A = tsg.CSRMatrix.from_host(Ah, device=dev)
+    b = torch.as_tensor(pr["b"], device=dev)
+    x = torch.zeros_like(b)
+    kw = dict(m=args.m, s=args.s, tol=args.tol, ortho=args.ortho, precision=args.precision)
+    need = tsg.binding.solve_workspace_bytes(A, m=args.m, s=args.s, ortho=args.ortho,
+                                             precision=args.precision)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off:]
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        x.zero_()
+        _, info = tsg.solve(A, b, x, workspace=ws, **kw)
+        log(f"[bench] warmup {i}: iters={info.iters} cycles={info.cycles} relres={info.relres:.3e}")
+    torch.cuda.synchronize()
+
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        x.zero_()
+        _, info = tsg.solve(A, b, x, workspace=ws, timing=True, **kw)
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[bench] timed {args.steps} solves in {elapsed:.3f}s")
+    info = infos[-1]
+    # independent residual check of the final iterate (scipy on the host)
+    xh = x.cpu().numpy()
+    relres_host = float(np.linalg.norm(pr["b"] - Ah.to_scipy() @ xh) / np.linalg.norm(pr["b"]))
+
+    def tot(f):
+        return sum(getattr(i, f) for i in infos)
+
+    cls = {
+        "panel": (tot("ms_ortho_reduce") + tot("ms_ortho_update"),
+                  tot("bytes_ortho_reduce") + tot("bytes_ortho_update"),
+                  tot("n_ortho_reduce") + tot("n_ortho_update")),
+        "spmv": (tot("ms_spmv"), tot("bytes_spmv"), tot("n_spmv")),
+    }
+    dom = max(cls, key=lambda c: cls[c][0])
+    ms, by, cnt = cls[dom]
+    elem = "double" if args.precision == "fp64" else "float"
+    kname = {"panel": f"panel_kernel<{elem}, {args.s}, {2 if args.s <= 6 else 1}>",
+             "spmv": f"mpk_step_kernel<{elem}, {elem}>"}[dom]
+    achieved = by / (ms * 1e-3) / 1e9
+    traffic = measured_traffic(kname)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": traffic, "kernel": kname,
+                "avg_launch_us": round(ms / cnt * 1e3, 2), "launches": int(cnt),
+                "algorithmic_bytes_per_launch": round(by / cnt)}
+    per_class = {}
+    for c, (cms, cby, ccnt) in cls.items():
+        per_class[c] = {"ms_per_solve": round(cms / len(infos), 2),
+                        "GBps": round(cby / (cms * 1e-3) / 1e9, 1) if cms > 0 else None,
+                        "launches_per_solve": int(ccnt / len(infos))}
+    per_class["small_ms_per_solve"] = round(tot("ms_small") / len(infos), 2)
+    per_class["xupdate_ms_per_solve"] = round(tot("ms_xupdate") / len(infos), 2)
+    per_class["residual_ms_per_solve"] = round(tot("ms_residual") / len(infos), 2)
+    ortho_ms_cycle = (tot("ms_ortho_reduce") + tot("ms_ortho_update") + tot("ms_small")) / tot("cycles")
+
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / elapsed, 5),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D Laplace 5-point {N}x{N} (n={Ah.n}, nnz={Ah.nnz}) CSR, "
+                               f"x_true~U(-1,1) seed 0, x0=0; s-step GMRES m={args.m} s={args.s} "
+                               f"{args.ortho} (s_hat=m), tol={args.tol:g}, {args.precision}",
+                   "n": Ah.n, "nnz": Ah.nnz, "m": args.m, "s": args.s, "ortho": args.ortho,
+                   "precision": args.precision, "tol": args.tol},
+        "time_to_solution_s": round(elapsed / args.steps, 4),
+        "iters": int(info.iters), "cycles": int(info.cycles),
+        "relres_device": info.relres, "relres_host_check": relres_host,
+        "ortho_ms_per_cycle": round(ortho_ms_cycle, 3),
+        "kernel_classes": per_class,
+        "roofline": roofline,
+    }
+
+    if args.compare:
+        cmp = {}
+        for o in ("two_stage", "bcgs_pip2", "bcgs2_cholqr2", "cgs2"):
+            if o == args.ortho:
+                cmp[o] = {"time_to_solution_s": out["time_to_solution_s"], "iters": out["iters"],
+                          "ortho_ms_per_cycle": out["ortho_ms_per_cycle"]}
+                continue
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, ci = tsg.solve(A, b, x, workspace=None, timing=True, m=args.m, s=args.s, tol=args.tol,
+                              ortho=o, precision=args.precision)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t
+            cmp[o] = {"time_to_solution_s": round(t, 4), "iters": int(ci.iters), "relres": ci.relres,
+                      "ortho_ms_per_cycle": round((ci.ms_ortho_reduce + ci.ms_ortho_update + ci.ms_small)
+                                                  / max(ci.cycles, 1), 3)}
+            log(f"[bench] compare {o}: {cmp[o]}")
+        out["compare"] = cmp
+
+    if not args.no_ortho_bench:
+        n, k, s = Ah.n, 61, args.s
+        log("[bench] isolated block orthogonalization 4194304 x 61")
+        X0 = torch.as_tensor(W.gaussian_block(n, k, seed=7).T.copy(), device=dev)
+        Xw = torch.empty_like(X0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        oerr = None
+        for r in range(args.ortho_reps + 2):
+            Xw.copy_(X0)
+            e0.record()
+            _, R = tsg.orthogonalize(Xw, s=s, algo="two_stage")
+            e1.record()
+            torch.cuda.synchronize()
+            if r >= 2:
+                times.append(e0.elapsed_time(e1))
+        _, _, oerr = tsg.orthogonalize(Xw.copy_(X0), s=s, algo="two_stage", orth_err=True)
+        med = float(np.median(times))
+        panels = [(c0, min(s, k - c0)) for c0 in range(1, k, s)]
+        passes = 3 + sum(2 * (c0 + sw) + sw for c0, sw in panels) + 2 * k
+        moved = passes * n * 8
+        method_bytes = 1047 * n * 8  # stage-2 Gram pass counted as a separate read
+        out["ortho_bench"] = {"shape": [n, k], "s": s, "algo": "two_stage", "median_ms": round(med, 3),
+                              "column_passes": passes, "GBps": round(moved / med / 1e6, 1),
+                              "GBps_method_equiv": round(method_bytes / med / 1e6, 1),
+                              "orth_err": oerr, "reps": args.ortho_reps}
+        del X0, Xw
+
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle: {args.cpu_cycles} restart cycle(s) of the same solve")
+        from oracle import gmres as G
+        from oracle import sparse as S
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        op = S.Operator(Ah)
+        t = time.perf_counter()
+        ref = G.sstep_gmres(op, pr["b"], m=args.m, s=args.s, tol=args.tol, ortho=args.ortho
+                            if args.ortho != "cgs2" else "two_stage", max_iters=args.cpu_cycles * args.m)
+        t = time.perf_counter() - t
+        t_cycle = t / max(ref["cycles"], 1)
+        cpu_solves_per_s = 1.0 / (t_cycle * max(info.cycles, 1))
+        out["cpu_baseline"] = {"value": cpu_solves_per_s, "unit": "solves/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{ref['cycles']} restart cycle(s) of the same {N}x{N} solve "
+                                         f"({t:.1f} s, {t_cycle:.2f} s/cycle), scaled by the "
+                                         f"{info.cycles} cycles the GPU solve needed; numpy BLAS on "
+                                         f"{cores} threads, scipy SpMV single-threaded"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -208,7 +208,7 @@ int panel_rpl(int sw) {
 }
 
 tsg_status panel(const PanelCtx& p, int k, int wcol, int sw, int flags, int tail, int panel_idx,
-                 int kkeep, int gate = 1) {
+                 int kkeep, int gate = 1, int kclass = -1) {
   PanelArgs a{};
   a.V = p.V;
   a.ld = p.ld;
@@ -236,7 +236,7 @@ tsg_status panel(const PanelCtx& p, int k, int wcol, int sw, int flags, int tail
   const bool loadQ = (flags & (PF_HAS_P | PF_GRAM_Q)) != 0;
   double cols = (loadQ ? k : 0) + sw + (upd ? sw : 0);
   if (p.timer) {
-    int kc = upd ? KC_UPDATE : KC_REDUCE;
+    int kc = kclass >= 0 ? kclass : (upd ? KC_UPDATE : KC_REDUCE);
     p.timer->count[kc] += 1;
     p.timer->bytes[kc] += cols * (double)p.n * p.elem;
     p.timer->begin(p.stream, kc);
@@ -480,7 +480,7 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
     HIP_LAUNCH_CHECK();
     // ---- qhat_1 = r / beta (two-stage: also G2(0,0) of the stored column)
     TRY(panel(pc, 0, 0, 1, PF_HAS_T | PF_STORE | (two ? PF_GRAM_W : 0), two ? TAIL_NORM0 : TAIL_NONE,
-              -1, 0));
+              -1, 0, 1, KC_RESID));
     for (int j = 0; j < J; ++j) {
       const int k = j * sstep + 1;
       const int kkeep = k - 1;

@@ -207,3 +207,30 @@ def test_determinism(tsg):
     x1, _ = tsg.solve(A, b, m=60, s=5, tol=1e-10)
     x2, _ = tsg.solve(A, b, m=60, s=5, tol=1e-10)
     assert torch.equal(x1, x2)
+
+
+# ------------------------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("kind,N,basis", [("laplace2d", 128, "shifted"), ("convdiff2d", 160, "shifted")])
+def test_mixed_precision_refinement(tsg, kind, N, basis):
+    """FP32 basis / SpMV / tall-skinny products, FP64 Cholesky, least squares and outer residual:
+    every restart cycle is one refinement step, so the FP64 gates still hold at tol 1e-10.
+    The FP32 iterates have no oracle of their own (parity unpinned); the final x is compared
+    with the FP64 oracle's x and with x_true."""
+    _say("case mixed", kind, N, basis)
+    pr = W.make_problem(kind, N, seed=6)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=60, s=5, tol=1e-10, basis=basis, precision="fp32_ir")
+    xg = x.cpu().numpy()
+    relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], xg)) / np.linalg.norm(pr["b"])
+    assert info.converged and relres <= 1e-10, (info, relres)
+    ref = G.sstep_gmres(pr["A"], pr["b"], m=60, s=5, tol=1e-10, basis=basis)
+    err = np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"])
+    if kind == "laplace2d":
+        lmin, lmax = W.laplace_extreme_eigs(N, 2)
+        kap = lmax / lmin
+        assert err <= 2 * 1e-10 * kap
+        xt = pr["x_true"]
+        assert np.linalg.norm(xg - xt) / np.linalg.norm(xt) <= 2 * 1e-10 * kap
+    else:
+        assert err <= 1e-6
+    _say(f"  mixed {kind}: iters {info.iters} (fp64 oracle {ref['iters']}), |x - x_fp64| = {err:.2e}")
