@@ -126,17 +126,31 @@ def main():
     def tot(f):
         return sum(getattr(i, f) for i in infos)
 
-    cls = {
-        "panel": (tot("ms_ortho_reduce") + tot("ms_ortho_update"),
-                  tot("bytes_ortho_reduce") + tot("bytes_ortho_update"),
-                  tot("n_ortho_reduce") + tot("n_ortho_update")),
-        "spmv": (tot("ms_spmv"), tot("bytes_spmv"), tot("n_spmv")),
-    }
-    dom = max(cls, key=lambda c: cls[c][0])
-    ms, by, cnt = cls[dom]
+    # per kernel class (one kernel instantiation each), from HIP events on the solve stream
+    classes = {}
+    for inf in infos:
+        for name, (cms, cn, cby) in inf.kernel_classes().items():
+            a = classes.setdefault(name, [0.0, 0, 0.0])
+            a[0] += cms
+            a[1] += cn
+            a[2] += cby
     elem = "double" if args.precision == "fp64" else "float"
-    kname = {"panel": f"panel_kernel<{elem}, {args.s}, {2 if args.s <= 6 else 1}>",
-             "spmv": f"mpk_step_kernel<{elem}, {elem}>"}[dom]
+    st_ = lambda w: w if w <= 6 else (8 if w <= 8 else (10 if w <= 10 else (12 if w <= 12 else 16)))
+    nzt = lambda w: w if w <= 6 else (8 if w <= 8 else 10)
+    s_ = args.s
+    names = {
+        "mpk": f"mpk_step_kernel<{elem}, {elem}>",
+        "gram": ("gram_mfma_kernel<1..4>" if elem == "double"
+                 else f"gram_kernel<{elem}, {nzt(2 * s_)}, 8, {2 if nzt(2 * s_) <= 6 else 1}>"),
+        "gram_first": ("gram_mfma_kernel<1>" if elem == "double"
+                       else f"gram_kernel<{elem}, {nzt(s_)}, 8, {2 if nzt(s_) <= 6 else 1}>"),
+        "update": f"update_kernel<{elem}, {st_(s_)}>",
+        "fused": f"panel_kernel<{elem}, {st_(s_)}, {2 if st_(s_) <= 6 else 1}>",
+    }
+    streaming = {c: v for c, v in classes.items() if c in names and v[0] > 0}
+    dom = max(streaming, key=lambda c: streaming[c][0])
+    ms, cnt, by = streaming[dom]
+    kname = names[dom]
     achieved = by / (ms * 1e-3) / 1e9
     traffic = measured_traffic(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -145,13 +159,10 @@ def main():
                 "avg_launch_us": round(ms / cnt * 1e3, 2), "launches": int(cnt),
                 "algorithmic_bytes_per_launch": round(by / cnt)}
     per_class = {}
-    for c, (cms, cby, ccnt) in cls.items():
-        per_class[c] = {"ms_per_solve": round(cms / len(infos), 2),
-                        "GBps": round(cby / (cms * 1e-3) / 1e9, 1) if cms > 0 else None,
-                        "launches_per_solve": int(ccnt / len(infos))}
-    per_class["small_ms_per_solve"] = round(tot("ms_small") / len(infos), 2)
-    per_class["xupdate_ms_per_solve"] = round(tot("ms_xupdate") / len(infos), 2)
-    per_class["residual_ms_per_solve"] = round(tot("ms_residual") / len(infos), 2)
+    for c, (cms, ccnt, cby) in classes.items():
+        per_class[c] = {"kernel": names.get(c), "ms_per_solve": round(cms / len(infos), 2),
+                        "launches_per_solve": int(ccnt / len(infos)),
+                        "GBps": round(cby / (cms * 1e-3) / 1e9, 1) if cms > 0 and cby > 0 else None}
     ortho_ms_cycle = (tot("ms_ortho_reduce") + tot("ms_ortho_update") + tot("ms_small")) / tot("cycles")
 
     out = {

@@ -85,6 +85,22 @@ typedef struct {
   int32_t reserved;
 } tsg_solve_params;
 
+/* Kernel classes reported by tsg_solve_info (timing mode).  Each class is one kernel
+ * instantiation for a given precision and step size s. */
+enum {
+  TSG_KC_MPK = 0,        /* one step of the matrix-powers kernel (SpMV)                  */
+  TSG_KC_GRAM = 1,       /* panel reduction (two-stage: with the previous panel's Gram)   */
+  TSG_KC_GRAM_FIRST = 2, /* panel reduction of the first panel of a cycle                 */
+  TSG_KC_UPDATE = 3,     /* panel update W <- (W - Q P) T                                 */
+  TSG_KC_FUSED = 4,      /* panel update that also reduces the Gram of its output         */
+  TSG_KC_TAIL = 5,       /* one-block FP64 tail of a reduction                            */
+  TSG_KC_CYCLE_END = 6,  /* stage 2 / projected least squares                             */
+  TSG_KC_XUPDATE = 7,    /* x += V coef                                                   */
+  TSG_KC_RESIDUAL = 8,   /* r = b - A x and its tail                                      */
+  TSG_KC_SCALE = 9,      /* first basis vector r / beta                                   */
+  TSG_KC_COUNT = 10
+};
+
 typedef struct {
   int64_t iters;        /* Krylov vectors generated (the paper's iteration count)       */
   int64_t cycles;       /* restart cycles run                                           */
@@ -96,6 +112,9 @@ typedef struct {
   double ms_total, ms_spmv, ms_ortho_reduce, ms_ortho_update, ms_small, ms_xupdate, ms_residual;
   int64_t n_ortho_reduce, n_ortho_update, n_spmv;  /* launches of each class           */
   double bytes_ortho_reduce, bytes_ortho_update, bytes_spmv; /* algorithmic bytes moved */
+  double kc_ms[16];        /* per kernel class (TSG_KC_*): GPU milliseconds               */
+  int64_t kc_launches[16]; /* launches that did work                                      */
+  double kc_bytes[16];     /* algorithmic bytes (sum over launches)                       */
 } tsg_solve_info;
 
 typedef struct tsg_csr_s* tsg_csr;

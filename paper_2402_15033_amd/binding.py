@@ -43,7 +43,12 @@ class _Info(C.Structure):
                 ("ms_residual", C.c_double), ("n_ortho_reduce", C.c_int64),
                 ("n_ortho_update", C.c_int64), ("n_spmv", C.c_int64),
                 ("bytes_ortho_reduce", C.c_double), ("bytes_ortho_update", C.c_double),
-                ("bytes_spmv", C.c_double)]
+                ("bytes_spmv", C.c_double), ("kc_ms", C.c_double * 16),
+                ("kc_launches", C.c_int64 * 16), ("kc_bytes", C.c_double * 16)]
+
+
+KERNEL_CLASSES = ["mpk", "gram", "gram_first", "update", "fused", "tail", "cycle_end", "xupdate",
+                  "residual", "scale"]
 
 
 @dataclass
@@ -67,6 +72,14 @@ class SolveInfo:
     bytes_ortho_reduce: float = 0.0
     bytes_ortho_update: float = 0.0
     bytes_spmv: float = 0.0
+    kc_ms: tuple = ()
+    kc_launches: tuple = ()
+    kc_bytes: tuple = ()
+
+    def kernel_classes(self) -> dict:
+        """{class: (ms, launches, algorithmic bytes)} for the classes that ran (timing mode)."""
+        return {n: (self.kc_ms[i], self.kc_launches[i], self.kc_bytes[i])
+                for i, n in enumerate(KERNEL_CLASSES) if i < len(self.kc_launches) and self.kc_launches[i]}
 
     @property
     def converged(self) -> bool:
@@ -241,7 +254,11 @@ def solve(A: CSRMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, m: in
                        _stream(b.device), C.byref(info))
     _check(st, allow_positive=True)
     del keep, ws
-    out = SolveInfo(**{f: getattr(info, f) for f, _ in _Info._fields_})
+    vals = {}
+    for f, _ in _Info._fields_:
+        v = getattr(info, f)
+        vals[f] = tuple(v) if f.startswith("kc_") else v
+    out = SolveInfo(**vals)
     return x, out
 
 

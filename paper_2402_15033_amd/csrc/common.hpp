@@ -10,7 +10,7 @@ constexpr int kWave = 64;
 constexpr int kLd = 64;      // leading dimension of every small matrix in SmallState
 constexpr int kMaxCols = 64; // max basis columns (m + 1) and max tall-skinny block width
 constexpr int kMaxS = 16;    // max step size
-constexpr int kGroup = 16;   // blocks per first-level group of the two-level reduction
+constexpr int kTailThreads = 1024;  // threads of the one-block tail kernels
 
 // Relative pivot threshold of the Cholesky factorizations inside a restart cycle:
 // a pivot d_j <= tol * ref_j (ref = diagonal of the raw Gram matrix) is treated as a
@@ -29,15 +29,6 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-
-__device__ __forceinline__ unsigned atomic_ticket(unsigned* p) {
-  return __hip_atomic_fetch_add(p, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void atomic_reset(unsigned* p) {
-  __hip_atomic_store(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).
 // Map the hardware block index to a logical tile so that each XCD walks one
@@ -50,50 +41,44 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return x * per + (x < rem ? x : rem) + j;
 }
 
-// Deterministic two-level "last block" reduction.
-//   Every block has written its E partial sums to part1[blockIdx.x * E + e] (all
-//   threads of the block may have written some).  Blocks are grouped by kGroup
-//   consecutive indices.  The last block of each group to arrive sums its group's
-//   partials in block order into part2[group * E + e]; the last group reducer sums
-//   part2 in group order into out[e] (any address space) and returns true.  Every
-//   other block returns false.  Counters: cnt[0] for level 2, cnt[1 + group] for
-//   level 1; each is reset to zero by the block that consumed it, so the same counter
-//   array serves every launch on one stream.  Must be called by all threads.
-template <typename OutFn>
-__device__ bool last_block_reduce(const double* part1, double* part2, unsigned* cnt, int E,
-                                  int nblocks, OutFn out) {
-  __shared__ int s_flag;
+// Deterministic cross-block reduction, run by ONE block of a separate "tail" kernel
+// (the kernel boundary makes the partials of the streaming kernel visible; no
+// device-scope fence is executed -- on gfx950 such a fence writes back the L2 of
+// the XCD, which per block of a streaming kernel costs far more than a launch).
+//   out[e] = sum_{b < nblocks} part1[b * E + e]   for e < E,
+// with G = min(nt / E, nblocks) threads per entry each summing a contiguous range of
+// blocks, then the G partial sums combined in group order: the summation order
+// depends only on (E, nblocks, blockDim), never on timing.  scratch: >= blockDim
+// doubles of LDS.  Must be called by all threads; ends with a barrier.
+__device__ void block_sum_partials(const double* __restrict__ part1, int E, int nblocks,
+                                   double* out, double* scratch) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int group = blockIdx.x / kGroup;
-  const int g0 = group * kGroup;
-  const int gsz = min(kGroup, nblocks - g0);
-  const int ngroups = (nblocks + kGroup - 1) / kGroup;
-  fence_release();
+  if (E >= nt || nblocks == 1) {
+    for (int e = tid; e < E; e += nt) {
+      double acc = 0.0;
+      for (int b = 0; b < nblocks; ++b) acc += part1[(size_t)b * E + e];
+      out[e] = acc;
+    }
+    __syncthreads();
+    return;
+  }
+  const int G = min(nt / E, nblocks);
+  const int chunk = (nblocks + G - 1) / G;
+  if (tid < G * E) {
+    const int e = tid % E, g = tid / E;
+    const int b0 = g * chunk, b1 = min(nblocks, b0 + chunk);
+    double acc = 0.0;
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) acc += part1[(size_t)b * E + e];
+    scratch[g * E + e] = acc;
+  }
   __syncthreads();
-  if (tid == 0) s_flag = (atomic_ticket(&cnt[1 + group]) == (unsigned)(gsz - 1));
-  __syncthreads();
-  if (!s_flag) return false;
-  fence_acquire();
   for (int e = tid; e < E; e += nt) {
     double acc = 0.0;
-    for (int b = 0; b < gsz; ++b) acc += part1[(size_t)(g0 + b) * E + e];
-    part2[(size_t)group * E + e] = acc;
+    for (int g = 0; g < G; ++g) acc += scratch[g * E + e];
+    out[e] = acc;
   }
-  if (tid == 0) atomic_reset(&cnt[1 + group]);
-  fence_release();
   __syncthreads();
-  if (tid == 0) s_flag = (atomic_ticket(&cnt[0]) == (unsigned)(ngroups - 1));
-  __syncthreads();
-  if (!s_flag) return false;
-  fence_acquire();
-  for (int e = tid; e < E; e += nt) {
-    double acc = 0.0;
-    for (int g = 0; g < ngroups; ++g) acc += part2[(size_t)g * E + e];
-    out(e, acc);
-  }
-  if (tid == 0) atomic_reset(&cnt[0]);
-  __syncthreads();
-  return true;
 }
 
 }  // namespace tsg

@@ -8,22 +8,65 @@ namespace tsg {
 constexpr int kRowBlock = 256;  // threads (rows) per block of the row-parallel kernels
 
 // ------------------------------------------------------------------ matrix powers
+// Wave-level synchronization of LDS traffic (workgroup-scope fences only: no cache
+// write-back, just ordering of this wave's LDS accesses).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+constexpr int kSegCap = 8 * kWave;  // products staged per wave (rows of <= 8 nonzeros on average)
+
+// acc(r) = sum_p val[p] x[col[p]] for the 64 rows r0 .. r0+63 of one wave.  The wave's
+// nonzeros form one contiguous CSR segment: it is loaded with fully coalesced accesses,
+// multiplied by the gathered x, staged in LDS, and every lane then sums its own row's
+// slice.  Segments longer than kSegCap fall back to the per-row loop.
+template <typename T, typename VT>
+__device__ __forceinline__ T csr_row_dot(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                         const VT* __restrict__ val, const T* __restrict__ x, int64_t n,
+                                         int64_t r0, int lane, T* prod) {
+  const int64_t r = r0 + lane;
+  const int nrows = (int)min((int64_t)kWave, n - r0);
+  const int rp = (r < n) ? row_ptr[r] : 0;
+  const int rp1 = (r < n) ? row_ptr[r + 1] : 0;
+  const int base = __shfl(rp, 0, kWave);
+  const int end = __shfl(rp1, nrows - 1, kWave);
+  const int cnt = end - base;
+  T acc = (T)0;
+  if (cnt <= kSegCap) {
+#pragma unroll 4
+    for (int e = lane; e < cnt; e += kWave) prod[e] = (T)val[base + e] * x[col[base + e]];
+    wave_lds_sync();
+    for (int e = rp - base; e < rp1 - base; ++e) acc += prod[e];
+    wave_lds_sync();
+  } else {
+    for (int p = rp; p < rp1; ++p) acc += (T)val[p] * x[col[p]];
+  }
+  return acc;
+}
+
 // One step of the matrix-powers kernel (Sec. III): y = (A x - theta x) / sigma.
-// Scalar CSR, one row per thread; values of type V (float64, or the float32 copy in
-// the mixed-precision form), vectors of type T.  Blocks are mapped XCD-contiguously
-// so the x gathers of neighbouring rows hit the same L2.
+// 4 waves x 64 rows per block; blocks are mapped XCD-contiguously so the x gathers of
+// neighbouring rows hit the same L2.  Values of type VT (float64, or the float32 copy of
+// the mixed-precision form), vectors of type T.
 template <typename T, typename VT>
 __global__ __launch_bounds__(kRowBlock) void mpk_step_kernel(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const VT* __restrict__ val, const T* __restrict__ x, T* __restrict__ y, int64_t n,
     double theta, double sigma, const SmallState* __restrict__ st, int panel) {
   if (st->h.done || panel > st->h.stop_panel) return;
-  const int64_t r = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
-  if (r >= n) return;
-  const int p0 = row_ptr[r], p1 = row_ptr[r + 1];
-  T acc = (T)0;
-  for (int p = p0; p < p1; ++p) acc += (T)val[p] * x[col[p]];
-  y[r] = (acc - (T)theta * x[r]) / (T)sigma;
+  __shared__ T prod[kRowBlock / kWave][kSegCap];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int64_t r0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kRowBlock + wv * kWave;
+  if (r0 >= n) return;
+  const T acc = csr_row_dot<T, VT>(row_ptr, col, val, x, n, r0, lane, prod[wv]);
+  const int64_t r = r0 + lane;
+  if (r < n) {
+    T v = acc;
+    if (theta != 0.0) v -= (T)theta * x[r];
+    y[r] = v / (T)sigma;
+  }
 }
 
 // y = A x in float64 (stand-alone SpMV entry point).
@@ -40,44 +83,50 @@ __global__ __launch_bounds__(kRowBlock) void spmv_f64_kernel(
 }
 
 // ------------------------------------------------------------------ restart residual
-// r = b - A x (float64), stored into basis column 0 (type T); ||r||^2 reduced in
-// deterministic order; the last block decides convergence (explicit residual test)
-// and initializes the cycle: beta, T = 1/beta for the scaling pass, Givens rhs,
-// cleared Hessenberg and stage-2 Gram.
+// r = b - A x (float64), stored into basis column 0 (type T); per-block ||r||^2
+// partials.  residual_tail_kernel sums them in a fixed order and decides convergence
+// (explicit residual test), then initializes the cycle: beta, T = 1/beta for the
+// scaling pass, Givens rhs, cleared Hessenberg and stage-2 Gram.
 template <typename T>
 __global__ __launch_bounds__(kRowBlock) void residual_kernel(
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
     const double* __restrict__ val, const double* __restrict__ x, const double* __restrict__ b,
-    T* __restrict__ r_out, int64_t n, SmallState* st, double* part1, double* part2,
-    unsigned* cnt) {
+    T* __restrict__ r_out, int64_t n, const SmallState* __restrict__ st, double* part1) {
   if (st->h.done) return;
-  const int64_t r = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kRowBlock + threadIdx.x;
+  __shared__ double prod[kRowBlock / kWave][kSegCap];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int64_t r0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kRowBlock + wv * kWave;
   double rr = 0.0;
-  if (r < n) {
-    const int p0 = row_ptr[r], p1 = row_ptr[r + 1];
-    double acc = 0.0;
-    for (int p = p0; p < p1; ++p) acc += val[p] * x[col[p]];
-    double v = b[r] - acc;
-    r_out[r] = (T)v;
-    rr = v * v;
+  if (r0 < n) {
+    const double acc = csr_row_dot<double, double>(row_ptr, col, val, x, n, r0, lane, prod[wv]);
+    const int64_t r = r0 + lane;
+    if (r < n) {
+      double v = b[r] - acc;
+      r_out[r] = (T)v;
+      rr = v * v;
+    }
   }
   __shared__ double wsum[kRowBlock / kWave];
   rr = wave_sum(rr);
   if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = rr;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < kRowBlock / kWave; ++w) s += wsum[w];
-    part1[blockIdx.x] = s;
+    double sum = 0.0;
+    for (int w = 0; w < kRowBlock / kWave; ++w) sum += wsum[w];
+    part1[blockIdx.x] = sum;
   }
-  __shared__ double s_tot;
-  bool last = last_block_reduce(part1, part2, cnt, 1, gridDim.x, [&](int, double v) { s_tot = v; });
-  if (!last) return;
-  __syncthreads();
-  const int tid = threadIdx.x, nt = blockDim.x;
+}
+
+__global__ __launch_bounds__(kTailThreads) void residual_tail_kernel(SmallState* st, const double* part1,
+                                                                     int nblocks) {
+  if (st->h.done) return;
+  __shared__ double s_tot[1];
+  __shared__ double scratch[kTailThreads];
   __shared__ int s_go;
+  block_sum_partials(part1, 1, nblocks, s_tot, scratch);
+  const int tid = threadIdx.x, nt = blockDim.x;
   if (tid == 0) {
-    double beta = sqrt(s_tot);
+    double beta = sqrt(s_tot[0]);
     st->h.relres = beta / st->bnorm;
     s_go = 0;
     if (st->h.relres <= st->tol) {
@@ -108,10 +157,9 @@ __global__ __launch_bounds__(kRowBlock) void residual_kernel(
   for (int i = tid; i <= kLd; i += nt) st->gg[i] = (i == 0) ? st->beta : 0.0;
 }
 
-// ||b||^2 -> st->bnorm (float64, deterministic).
+// per-block partials of ||b||^2; norm_tail_kernel -> st->bnorm (float64, deterministic).
 __global__ __launch_bounds__(kRowBlock) void norm_kernel(const double* __restrict__ b, int64_t n,
-                                                         SmallState* st, double* part1,
-                                                         double* part2, unsigned* cnt) {
+                                                         double* part1) {
   const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
   double v = (r < n) ? b[r] * b[r] : 0.0;
   __shared__ double wsum[kRowBlock / kWave];
@@ -119,14 +167,18 @@ __global__ __launch_bounds__(kRowBlock) void norm_kernel(const double* __restric
   if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int w = 0; w < kRowBlock / kWave; ++w) s += wsum[w];
-    part1[blockIdx.x] = s;
+    double sum = 0.0;
+    for (int w = 0; w < kRowBlock / kWave; ++w) sum += wsum[w];
+    part1[blockIdx.x] = sum;
   }
-  __shared__ double s_tot;
-  bool last = last_block_reduce(part1, part2, cnt, 1, gridDim.x, [&](int, double x) { s_tot = x; });
-  if (!last) return;
-  if (threadIdx.x == 0) st->bnorm = sqrt(s_tot);
+}
+
+__global__ __launch_bounds__(kTailThreads) void norm_tail_kernel(SmallState* st, const double* part1,
+                                                                 int nblocks) {
+  __shared__ double s_tot[1];
+  __shared__ double scratch[kTailThreads];
+  block_sum_partials(part1, 1, nblocks, s_tot, scratch);
+  if (threadIdx.x == 0) st->bnorm = sqrt(s_tot[0]);
 }
 
 // ------------------------------------------------------------------ Gershgorin interval

@@ -1,5 +1,5 @@
 // Streaming panel kernel: the tall-skinny products of every block orthogonalization
-// scheme (Sec. IV-V), with an FP64 "tail" executed by the last block.
+// scheme (Sec. IV-V), followed by a one-block FP64 "tail" kernel.
 //
 // One launch streams the rows of the column-major basis V once and, per row r, forms
 //     y  = W(r,:) - Q(r,:) P          (PF_HAS_P; else y = W(r,:))
@@ -7,8 +7,9 @@
 //     W(r,:) <- q                     (PF_STORE, in place)
 //     G += [Q(r,:), q]^T q            (PF_GRAM_Q: Q rows, PF_GRAM_W: q rows)
 // where Q = V(:, 0:k) and W = V(:, wcol:wcol+sw).  The Gram G ((k+sw) x sw) is
-// reduced across lanes, waves and blocks (deterministic order), and the last block
-// runs the tail (Cholesky of the Pythagorean Gram, Hessenberg block, Givens, ...).
+// reduced across lanes and waves in registers; each block writes its partial, and
+// panel_tail_kernel sums the partials in a fixed order and runs the tail (Cholesky of
+// the Pythagorean Gram, Hessenberg block, Givens, ...).
 //
 // Mapping (wave64, 8 waves = 512 threads per block): a block owns a contiguous range
 // of rows; each lane owns one row per batch of 64*RPL rows.  The k+sw columns are
@@ -64,15 +65,19 @@ struct PanelArgs {
   int32_t standalone;// tails assemble an R factor (st->Hh) instead of Hessenberg/Givens
   int32_t kkeep;     // Krylov vectors kept if this panel breaks down (solver mode)
   int32_t panel;     // index of the panel within the cycle (-1: cycle set-up)
+  int32_t nz;        // reduced Gram has nz columns: nz - sw previous-panel columns, then W
+  int32_t pad;
   SmallState* st;
-  double* part1;
-  double* part2;
-  unsigned* cnt;
+  double* part1;     // per-block partial Grams, nblocks x (k+sw)*sw
 };
 
 // ----------------------------------------------------------------------------- tails
-// Called by every thread of the last block with the reduced Gram sred ((k+sw) x sw,
-// entry (c, j) at sred[c * sw + j]).
+// Called by every thread of the tail block with the reduced Gram sred ((k+sw) x nz, entry
+// (c, z) at sred[c * nz + z]); its last sw columns belong to the panel W:
+// red(c, j) = sred[c * nz + (nz - sw) + j].
+__device__ __forceinline__ double red(const PanelArgs& a, const double* sred, int c, int j) {
+  return sred[c * a.nz + (a.nz - a.sw) + j];
+}
 
 __device__ void tail_breakdown(const PanelArgs& a, int kkeep) {
   SmallState* st = a.st;
@@ -109,14 +114,14 @@ __device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, 
   __shared__ double sG[kMaxS * kMaxS], sRef[kMaxS];
   for (int idx = tid; idx < k * s; idx += nt) {
     int c = idx % k, j = idx / k;
-    P[c + j * kLd] = sred[c * s + j];
+    P[c + j * kLd] = red(a, sred, c, j);
   }
   for (int idx = tid; idx < s * s; idx += nt) {
     int i = idx % s, j = idx / s;
-    double v = sred[(k + i) * s + j];
-    for (int c = 0; c < k; ++c) v -= sred[c * s + i] * sred[c * s + j];
+    double v = red(a, sred, k + i, j);
+    for (int c = 0; c < k; ++c) v -= red(a, sred, c, i) * red(a, sred, c, j);
     sG[i + j * kMaxS] = v;
-    if (i == j) sRef[i] = sred[(k + i) * s + j];
+    if (i == j) sRef[i] = red(a, sred, k + i, j);
   }
   __syncthreads();
   return block_chol_upper(sG, kMaxS, R, kMaxS, s, sRef, a.st->pivot_tol);
@@ -128,7 +133,7 @@ __device__ int tail_chol_rows(const PanelArgs& a, const double* sred, int r0, do
   __shared__ double sG[kMaxS * kMaxS];
   for (int idx = tid; idx < s * s; idx += nt) {
     int i = idx % s, j = idx / s;
-    sG[i + j * kMaxS] = sred[(r0 + i) * s + j];
+    sG[i + j * kMaxS] = red(a, sred, r0 + i, j);
   }
   __syncthreads();
   return block_chol_upper(sG, kMaxS, R, kMaxS, s, nullptr, tol);
@@ -169,12 +174,12 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
   __shared__ double sR[kMaxS * kMaxS], sR2[kMaxS * kMaxS], sP[kLd * kMaxS];
   switch (a.tail) {
     case TAIL_NORM0: {
-      if (tid == 0) st->G2[0] = sred[0];
+      if (tid == 0) st->G2[0] = red(a, sred, 0, 0);
       __syncthreads();
     } break;
     case TAIL_SA_NORM: {
       if (tid == 0) {
-        double r = sqrt(sred[0]);
+        double r = sqrt(red(a, sred, 0, 0));
         if (!(r > 0.0)) {
           st->h.status = 2;
           st->h.done = 1;
@@ -187,6 +192,16 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
       __syncthreads();
     } break;
     case TAIL_PIP: {
+      // the previous panel's block column of the stage-2 Gram (nz - s leading columns of
+      // the reduction: [Qhat(:, 0:k)]^T Qhat(:, k-np:k)), written before this panel's
+      // Cholesky so that it survives a breakdown of this panel
+      const int np = a.nz - s;
+      for (int idx = tid; idx < k * np; idx += nt) {
+        int c = idx % k, z = idx / k;
+        int col = k - np + z;
+        if (c <= col) st->G2[c + col * kLd] = sred[c * a.nz + z];
+      }
+      __syncthreads();
       int f = tail_pip_chol(a, sred, st->Pcur, sR);
       if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
       tail_set_tinv(st, sR, s);
@@ -197,7 +212,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
         int c = idx % (k + s), j = idx / (k + s);
         int row = (c < k) ? c : a.wcol + (c - k);
         int col = a.wcol + j;
-        if (row <= col) st->G2[row + col * kLd] = sred[c * s + j];
+        if (row <= col) st->G2[row + col * kLd] = red(a, sred, c, j);
       }
       __syncthreads();
     } break;
@@ -234,8 +249,8 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
     case TAIL_BC_P1: {
       for (int idx = tid; idx < k * s; idx += nt) {
         int c = idx % k, j = idx / k;
-        st->Pcur[c + j * kLd] = sred[c * s + j];
-        st->P1[c + j * kLd] = sred[c * s + j];
+        st->Pcur[c + j * kLd] = red(a, sred, c, j);
+        st->P1[c + j * kLd] = red(a, sred, c, j);
       }
       if (tid == 0) st->identity_t = 1;
       __syncthreads();
@@ -263,8 +278,8 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
     case TAIL_BC_P2: {
       for (int idx = tid; idx < k * s; idx += nt) {
         int c = idx % k, j = idx / k;
-        st->Pcur[c + j * kLd] = sred[c * s + j];
-        st->P2[c + j * kLd] = sred[c * s + j];
+        st->Pcur[c + j * kLd] = red(a, sred, c, j);
+        st->P2[c + j * kLd] = red(a, sred, c, j);
       }
       if (tid == 0) st->identity_t = 1;
       __syncthreads();
@@ -291,8 +306,8 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
     } break;
     case TAIL_CGS_H1: {
       for (int c = tid; c < k; c += nt) {
-        st->Pcur[c] = sred[c];
-        st->P1[c] = sred[c];
+        st->Pcur[c] = red(a, sred, c, 0);
+        st->P1[c] = red(a, sred, c, 0);
       }
       if (tid == 0) st->identity_t = 1;
       __syncthreads();
@@ -301,13 +316,13 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
       // h2 = sred(0:k), ||w1||^2 = sred(k); beta^2 = ||w1||^2 - ||h2||^2 (Pythagorean)
       const int j = k - 1;  // Hessenberg column of this iteration
       for (int c = tid; c < k; c += nt) {
-        st->Pcur[c] = sred[c];
-        st->Hh[c + j * kLd] = st->P1[c] + sred[c];
+        st->Pcur[c] = red(a, sred, c, 0);
+        st->Hh[c + j * kLd] = st->P1[c] + red(a, sred, c, 0);
       }
       __syncthreads();
       if (tid == 0) {
-        double nw = sred[k], h2 = 0.0;
-        for (int c = 0; c < k; ++c) h2 += sred[c] * sred[c];
+        double nw = red(a, sred, k, 0), h2 = 0.0;
+        for (int c = 0; c < k; ++c) h2 += red(a, sred, c, 0) * red(a, sred, c, 0);
         double b2 = nw - h2;
         double beta = (b2 > st->pivot_tol * nw) ? sqrt(b2) : 0.0;
         st->Hh[k + j * kLd] = beta;
@@ -333,7 +348,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
       for (int idx = tid; idx < (k + s) * s; idx += nt) {
         int c = idx % (k + s), j = idx / (k + s);
         int row = (c < k) ? c : a.wcol + (c - k);
-        st->Wk[row + (a.wcol + j) * kLd] = sred[c * s + j];
+        st->Wk[row + (a.wcol + j) * kLd] = red(a, sred, c, j);
       }
       __syncthreads();
     } break;
@@ -366,7 +381,6 @@ __global__ __launch_bounds__(512) void panel_kernel(PanelArgs a) {
   __shared__ T lw[S][BR];
   __shared__ T lP[kMaxCols][S];
   __shared__ T lT[S][S];
-  __shared__ double sred[kMaxCols * kMaxS];
 
   for (int idx = threadIdx.x; idx < kMaxCols * S; idx += blockDim.x) {
     int c = idx / S, j = idx % S;
@@ -504,10 +518,17 @@ __global__ __launch_bounds__(512) void panel_kernel(PanelArgs a) {
       }
     }
   }
-  bool last = last_block_reduce(a.part1, a.part2, a.cnt, E, a.nblocks,
-                                [&](int e, double val) { sred[e] = val; });
-  if (!last) return;
-  __syncthreads();
+}
+
+// The reduction of a panel launch: one block sums the per-block partial Grams in a fixed
+// order and runs the FP64 tail (Cholesky, Hessenberg block, Givens, ...).
+__global__ __launch_bounds__(kTailThreads) void panel_tail_kernel(PanelArgs a) {
+  SmallState* st = a.st;
+  if (a.gate && (st->h.done || a.panel > st->h.stop_panel)) return;
+  __shared__ double sred[kMaxCols * kMaxS];
+  __shared__ double scratch[kTailThreads];
+  const int E = (a.k + a.sw) * a.nz;
+  block_sum_partials(a.part1, E, a.nblocks, sred, scratch);
   panel_tail(a, sred);
 }
 

@@ -16,6 +16,7 @@
 
 #include "../../include/tsgmres.h"
 #include "kernels.hpp"
+#include "stream.hpp"
 
 using namespace tsg;
 
@@ -68,8 +69,8 @@ int64_t basis_ld(int64_t n) {
 }
 
 constexpr int kPanelThreads = 512;
-constexpr int kMaxPanelBlocks = 512;
-constexpr int kCounters = 1 + 4096;  // level-2 + level-1 counters (n / 256 / 16 groups max)
+constexpr int kMaxPanelBlocks = 256;  // one 8-wave block per CU
+constexpr int kMaxReduceBlocks = 512;  // largest grid of any reduction kernel (MFMA Gram)
 
 // Workspace carving shared by solve and orthogonalize.
 struct Carve {
@@ -85,55 +86,47 @@ struct Carve {
 
 struct Common {
   SmallState* st;
-  unsigned* cnt;
-  double* part1;
-  double* part2;
-  size_t part1_n, part2_n;
+  double* part1;  // per-block partial sums of the streaming kernels
+  size_t part1_n;
 };
 
+size_t part1_count(int64_t n) {
+  return std::max<size_t>((size_t)kMaxReduceBlocks * kMaxCols * kMaxS, (size_t)cdiv(n, kRowBlock));
+}
+
 size_t common_bytes(int64_t n) {
-  int64_t nb_rows = cdiv(n, kRowBlock);
-  size_t p1 = std::max<size_t>((size_t)kMaxPanelBlocks * kMaxCols * kMaxS, (size_t)nb_rows);
-  size_t p2 = std::max<size_t>((size_t)cdiv(kMaxPanelBlocks, kGroup) * kMaxCols * kMaxS,
-                               (size_t)cdiv(nb_rows, kGroup));
-  if (cdiv(nb_rows, kGroup) + 1 > kCounters) return (size_t)-1;
-  return align_up(sizeof(SmallState)) + align_up(kCounters * sizeof(unsigned)) +
-         align_up(p1 * sizeof(double)) + align_up(p2 * sizeof(double));
+  return align_up(sizeof(SmallState)) + align_up(part1_count(n) * sizeof(double));
 }
 
 Common carve_common(Carve& cv, int64_t n) {
   Common c;
-  int64_t nb_rows = cdiv(n, kRowBlock);
-  c.part1_n = std::max<size_t>((size_t)kMaxPanelBlocks * kMaxCols * kMaxS, (size_t)nb_rows);
-  c.part2_n = std::max<size_t>((size_t)cdiv(kMaxPanelBlocks, kGroup) * kMaxCols * kMaxS,
-                               (size_t)cdiv(nb_rows, kGroup));
+  c.part1_n = part1_count(n);
   c.st = cv.take<SmallState>(1);
-  c.cnt = cv.take<unsigned>(kCounters);
   c.part1 = cv.take<double>(c.part1_n);
-  c.part2 = cv.take<double>(c.part2_n);
   return c;
-}
-
-__global__ void zero_u32_kernel(unsigned* p, int n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
 }
 __global__ void zero_f64_kernel(double* p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
 }
 
-// ------------------------------------------------------------------ kernel classes
-enum KClass { KC_SPMV = 0, KC_REDUCE, KC_UPDATE, KC_SMALL, KC_XUPD, KC_RESID, KC_N };
+#define TRY(x)                  \
+  do {                          \
+    tsg_status s_ = (x);        \
+    if (s_ != TSG_OK) return s_; \
+  } while (0)
 
+// ------------------------------------------------------------------ timing
+// Per kernel class (TSG_KC_*): HIP events around every launch on the solve's stream,
+// folded into totals after each per-cycle synchronization.
 struct Timer {
   bool on = false;
   std::vector<hipEvent_t> pool;
   std::vector<int> cls;
   size_t used = 0;
-  double ms[KC_N] = {0};
-  int64_t count[KC_N] = {0};
-  double bytes[KC_N] = {0};
+  double ms[16] = {0};
+  int64_t count[16] = {0};
+  double bytes[16] = {0};
   ~Timer() {
     for (auto e : pool) (void)hipEventDestroy(e);
   }
@@ -145,7 +138,9 @@ struct Timer {
     }
     return pool[used++];
   }
-  void begin(hipStream_t s, int c) {
+  void begin(hipStream_t s, int c, double nbytes) {
+    count[c] += 1;
+    bytes[c] += nbytes;
     if (!on) return;
     hipEvent_t e = next();
     if (e) (void)hipEventRecord(e, s);
@@ -156,7 +151,6 @@ struct Timer {
     hipEvent_t e = next();
     if (e) (void)hipEventRecord(e, s);
   }
-  // after a stream synchronization: fold the recorded pairs into the totals
   void harvest() {
     if (!on) return;
     for (size_t i = 0; i < cls.size(); ++i) {
@@ -168,7 +162,7 @@ struct Timer {
   }
 };
 
-// ------------------------------------------------------------------ panel launcher
+// ------------------------------------------------------------------ panel launchers
 struct PanelCtx {
   void* V;
   int64_t ld, n;
@@ -180,79 +174,247 @@ struct PanelCtx {
   int standalone;
 };
 
+// Round a panel width up to an instantiated template width.
+int s_template(int sw) { return sw <= 6 ? sw : (sw <= 8 ? 8 : (sw <= 10 ? 10 : (sw <= 12 ? 12 : 16))); }
+int fused_rpl(int sw) { return s_template(sw) <= 6 ? 2 : 1; }
+int nz_template(int nz) { return nz <= 6 ? nz : (nz <= 8 ? 8 : 10); }
+int gram_rpl(int nz) { return nz_template(nz) <= 6 ? 2 : 1; }
+constexpr int kMaxGramNzF32 = 10;  // widest lean FP32 reduction (VALU: 8 slots x 10 accumulators)
+constexpr int kMaxGramNzF64 = 16;  // widest FP64 reduction on the matrix cores (one 16-wide tile)
+inline int max_gram_nz(bool f32) { return f32 ? kMaxGramNzF32 : kMaxGramNzF64; }
+constexpr int kMaxMfmaBlocks = 512;  // two 8-wave blocks per CU
+static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks && kMaxPanelBlocks <= kMaxReduceBlocks,
+              "reduction partial buffer too small");
+
 template <typename T, int S>
-void launch_panel_t(const PanelArgs& a, int nb, hipStream_t s) {
+void launch_fused_t(const PanelArgs& a, int nb, hipStream_t s) {
   constexpr int RPL = (S <= 6) ? 2 : 1;
   hipLaunchKernelGGL((panel_kernel<T, S, RPL>), dim3(nb), dim3(kPanelThreads), 0, s, a);
 }
-
 template <typename T>
-void launch_panel_dispatch(const PanelArgs& a, int nb, hipStream_t s) {
-  switch (a.sw) {
-    case 1: launch_panel_t<T, 1>(a, nb, s); break;
-    case 2: launch_panel_t<T, 2>(a, nb, s); break;
-    case 3: launch_panel_t<T, 3>(a, nb, s); break;
-    case 4: launch_panel_t<T, 4>(a, nb, s); break;
-    case 5: launch_panel_t<T, 5>(a, nb, s); break;
-    case 6: launch_panel_t<T, 6>(a, nb, s); break;
-    case 7: case 8: launch_panel_t<T, 8>(a, nb, s); break;
-    case 9: case 10: launch_panel_t<T, 10>(a, nb, s); break;
-    case 11: case 12: launch_panel_t<T, 12>(a, nb, s); break;
-    default: launch_panel_t<T, 16>(a, nb, s); break;
+void launch_fused(const PanelArgs& a, int nb, hipStream_t s) {
+  switch (s_template(a.sw)) {
+    case 1: launch_fused_t<T, 1>(a, nb, s); break;
+    case 2: launch_fused_t<T, 2>(a, nb, s); break;
+    case 3: launch_fused_t<T, 3>(a, nb, s); break;
+    case 4: launch_fused_t<T, 4>(a, nb, s); break;
+    case 5: launch_fused_t<T, 5>(a, nb, s); break;
+    case 6: launch_fused_t<T, 6>(a, nb, s); break;
+    case 8: launch_fused_t<T, 8>(a, nb, s); break;
+    case 10: launch_fused_t<T, 10>(a, nb, s); break;
+    case 12: launch_fused_t<T, 12>(a, nb, s); break;
+    default: launch_fused_t<T, 16>(a, nb, s); break;
+  }
+}
+template <typename T, int NZ>
+void launch_gram_t(const PanelArgs& a, int nb, hipStream_t s) {
+  constexpr int RPL = (NZ <= 6) ? 2 : 1;
+  hipLaunchKernelGGL((gram_kernel<T, NZ, 8, RPL>), dim3(nb), dim3(8 * kWave), 0, s, a);
+}
+template <typename T>
+void launch_gram(const PanelArgs& a, int nb, hipStream_t s) {
+  switch (nz_template(a.nz)) {
+    case 1: launch_gram_t<T, 1>(a, nb, s); break;
+    case 2: launch_gram_t<T, 2>(a, nb, s); break;
+    case 3: launch_gram_t<T, 3>(a, nb, s); break;
+    case 4: launch_gram_t<T, 4>(a, nb, s); break;
+    case 5: launch_gram_t<T, 5>(a, nb, s); break;
+    case 6: launch_gram_t<T, 6>(a, nb, s); break;
+    case 8: launch_gram_t<T, 8>(a, nb, s); break;
+    default: launch_gram_t<T, 10>(a, nb, s); break;
+  }
+}
+template <typename T>
+void launch_update(const PanelArgs& a, int nb, hipStream_t s) {
+  switch (s_template(a.sw)) {
+    case 1: hipLaunchKernelGGL((update_kernel<T, 1>), dim3(nb), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((update_kernel<T, 2>), dim3(nb), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((update_kernel<T, 3>), dim3(nb), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((update_kernel<T, 4>), dim3(nb), dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((update_kernel<T, 5>), dim3(nb), dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((update_kernel<T, 6>), dim3(nb), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((update_kernel<T, 8>), dim3(nb), dim3(256), 0, s, a); break;
+    case 10: hipLaunchKernelGGL((update_kernel<T, 10>), dim3(nb), dim3(256), 0, s, a); break;
+    case 12: hipLaunchKernelGGL((update_kernel<T, 12>), dim3(nb), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((update_kernel<T, 16>), dim3(nb), dim3(256), 0, s, a); break;
   }
 }
 
-int panel_rpl(int sw) {
-  int S = sw <= 6 ? sw : (sw <= 8 ? 8 : (sw <= 10 ? 10 : (sw <= 12 ? 12 : 16)));
-  return S <= 6 ? 2 : 1;
-}
+enum PanelKind { PK_GRAM, PK_UPDATE, PK_FUSED };
 
-tsg_status panel(const PanelCtx& p, int k, int wcol, int sw, int flags, int tail, int panel_idx,
-                 int kkeep, int gate = 1, int kclass = -1) {
+struct Step {
+  PanelKind kind;
+  int k, wcol, sw;
+  int nprev = 0;      // PK_GRAM: previous-panel columns reduced along (stage-2 Gram block)
+  int flags = 0;
+  int tail = TAIL_NONE;
+  int panel = 0, kkeep = 0, gate = 1;
+  int kclass = -1;
+};
+
+// One panel step: the streaming kernel and, when it reduces, the one-block tail kernel.
+tsg_status run_step(const PanelCtx& p, const Step& st) {
   PanelArgs a{};
   a.V = p.V;
   a.ld = p.ld;
   a.n = p.n;
-  a.k = k;
-  a.wcol = wcol;
-  a.sw = sw;
-  a.flags = flags;
-  a.tail = tail;
-  a.gate = gate;
+  a.k = st.k;
+  a.wcol = st.wcol;
+  a.sw = st.sw;
+  a.flags = st.flags;
+  a.tail = st.tail;
+  a.gate = st.gate;
   a.standalone = p.standalone;
-  a.kkeep = kkeep;
-  a.panel = panel_idx;
+  a.kkeep = st.kkeep;
+  a.panel = st.panel;
   a.st = p.c.st;
   a.part1 = p.c.part1;
-  a.part2 = p.c.part2;
-  a.cnt = p.c.cnt;
-  const int br = kWave * panel_rpl(sw);
-  int64_t tiles = cdiv(p.n, br);
-  int nb = (int)std::min<int64_t>(tiles, kMaxPanelBlocks);
-  a.rows_per_block = cdiv(cdiv(p.n, nb), br) * br;
-  nb = (int)cdiv(p.n, a.rows_per_block);
-  a.nblocks = nb;
-  const bool upd = flags & PF_STORE;
-  const bool loadQ = (flags & (PF_HAS_P | PF_GRAM_Q)) != 0;
-  double cols = (loadQ ? k : 0) + sw + (upd ? sw : 0);
-  if (p.timer) {
-    int kc = kclass >= 0 ? kclass : (upd ? KC_UPDATE : KC_REDUCE);
-    p.timer->count[kc] += 1;
-    p.timer->bytes[kc] += cols * (double)p.n * p.elem;
-    p.timer->begin(p.stream, kc);
+  bool reduces = false;
+  int nb = 0;
+  double cols = 0;
+  int kc = st.kclass;
+  if (st.kind == PK_UPDATE) {
+    a.nz = st.sw;
+    nb = (int)cdiv(p.n, 256);
+    a.rows_per_block = 256;
+    a.nblocks = nb;
+    cols = ((st.flags & PF_HAS_P) ? st.k : 0) + 2.0 * st.sw;
+    if (kc < 0) kc = TSG_KC_UPDATE;
+  } else {
+    const bool gram = st.kind == PK_GRAM;
+    a.nz = gram ? st.nprev + st.sw : st.sw;
+    const bool mfma = gram && !p.f32;
+    const int br = mfma ? 64 : kWave * (gram ? gram_rpl(a.nz) : fused_rpl(st.sw));
+    int64_t tiles = cdiv(p.n, br);
+    nb = (int)std::min<int64_t>(tiles, mfma ? kMaxMfmaBlocks : kMaxPanelBlocks);
+    a.rows_per_block = cdiv(cdiv(p.n, nb), br) * br;
+    nb = (int)cdiv(p.n, a.rows_per_block);
+    a.nblocks = nb;
+    if (gram) {
+      reduces = true;
+      cols = st.k + st.sw;
+      if (kc < 0) kc = st.nprev > 0 ? TSG_KC_GRAM : TSG_KC_GRAM_FIRST;
+    } else {
+      reduces = (st.flags & (PF_GRAM_Q | PF_GRAM_W)) != 0;
+      const bool loadQ = (st.flags & (PF_HAS_P | PF_GRAM_Q)) != 0;
+      cols = (loadQ ? st.k : 0) + st.sw + ((st.flags & PF_STORE) ? st.sw : 0);
+      if (kc < 0) kc = TSG_KC_FUSED;
+    }
   }
-  if (p.f32) launch_panel_dispatch<float>(a, nb, p.stream);
-  else launch_panel_dispatch<double>(a, nb, p.stream);
+  if (reduces && (size_t)nb * (size_t)((st.k + st.sw) * a.nz) > p.c.part1_n)
+    return fail(TSG_ERR_WORKSPACE, "internal: reduction partials (%d blocks x %d) exceed the buffer", nb,
+                (st.k + st.sw) * a.nz);
+  if (p.timer) p.timer->begin(p.stream, kc, cols * (double)p.n * p.elem);
+  switch (st.kind) {
+    case PK_GRAM:
+      if (p.f32) {
+        launch_gram<float>(a, nb, p.stream);
+      } else {
+        switch ((st.k + st.sw + 15) / 16) {
+          case 1: hipLaunchKernelGGL((gram_mfma_kernel<1>), dim3(nb), dim3(512), 0, p.stream, a); break;
+          case 2: hipLaunchKernelGGL((gram_mfma_kernel<2>), dim3(nb), dim3(512), 0, p.stream, a); break;
+          case 3: hipLaunchKernelGGL((gram_mfma_kernel<3>), dim3(nb), dim3(512), 0, p.stream, a); break;
+          default: hipLaunchKernelGGL((gram_mfma_kernel<4>), dim3(nb), dim3(512), 0, p.stream, a); break;
+        }
+      }
+      break;
+    case PK_UPDATE:
+      if (p.f32) launch_update<float>(a, nb, p.stream);
+      else launch_update<double>(a, nb, p.stream);
+      break;
+    case PK_FUSED:
+      if (p.f32) launch_fused<float>(a, nb, p.stream);
+      else launch_fused<double>(a, nb, p.stream);
+      break;
+  }
   if (p.timer) p.timer->end(p.stream);
   HIP_LAUNCH_CHECK();
+  if (reduces) {
+    if (p.timer) p.timer->begin(p.stream, TSG_KC_TAIL, 0.0);
+    hipLaunchKernelGGL(panel_tail_kernel, dim3(1), dim3(kTailThreads), 0, p.stream, a);
+    if (p.timer) p.timer->end(p.stream);
+    HIP_LAUNCH_CHECK();
+  }
   return TSG_OK;
 }
 
-#define TRY(x)                  \
-  do {                          \
-    tsg_status s_ = (x);        \
-    if (s_ != TSG_OK) return s_; \
-  } while (0)
+// A reduction over the k + sw columns (lean kernel when it fits, else the fused kernel in
+// reduce-only mode).
+Step gram_step(bool f32, int k, int wcol, int sw, int nprev, int tail, int panel, int kkeep, int gate = 1) {
+  Step st{};
+  if (nprev + sw <= max_gram_nz(f32)) {
+    st.kind = PK_GRAM;
+    st.nprev = nprev;
+  } else {
+    st.kind = PK_FUSED;
+    st.flags = PF_GRAM_Q | PF_GRAM_W;
+  }
+  st.k = k;
+  st.wcol = wcol;
+  st.sw = sw;
+  st.tail = tail;
+  st.panel = panel;
+  st.kkeep = kkeep;
+  st.gate = gate;
+  return st;
+}
+Step upd_step(PanelKind kind, int k, int wcol, int sw, int flags, int tail, int panel, int kkeep) {
+  Step st{};
+  st.kind = kind;
+  st.k = k;
+  st.wcol = wcol;
+  st.sw = sw;
+  st.flags = flags;
+  st.tail = tail;
+  st.panel = panel;
+  st.kkeep = kkeep;
+  return st;
+}
+
+// The kernel sequence of one panel (columns wcol .. wcol+sw-1 against the k before them).
+//   two_stage: stage-1 BCGS-PIP; the reduction also covers the previous panel's stage-2
+//              Gram block column when nprev > 0; the last panel's update is fused with
+//              its own stage-2 Gram block column.
+//   others:    as in the paper's figures, with fused passes where the next reduction
+//              reads exactly the columns just written.
+tsg_status panel_sequence(const PanelCtx& p, int ortho, int k, int sw, int nprev, bool fuse_update, int j,
+                          int kkeep) {
+  const int c0 = k;
+  switch (ortho) {
+    case TSG_ORTHO_TWO_STAGE: {
+      TRY(run_step(p, gram_step(p.f32, k, c0, sw, nprev, TAIL_PIP, j, kkeep)));
+      if (fuse_update) {
+        TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W,
+                                 TAIL_G2COL, j, kkeep)));
+      } else {
+        TRY(run_step(p, upd_step(PK_UPDATE, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
+      }
+    } break;
+    case TSG_ORTHO_BCGS_PIP2:
+      TRY(run_step(p, gram_step(p.f32, k, c0, sw, 0, TAIL_PIP2_A, j, kkeep)));
+      TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W,
+                               TAIL_PIP2_B, j, kkeep)));
+      TRY(run_step(p, upd_step(PK_UPDATE, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
+      break;
+    case TSG_ORTHO_BCGS2_CHOLQR2:
+      TRY(run_step(p, gram_step(p.f32, k, c0, sw, 0, TAIL_BC_P1, j, kkeep)));
+      TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_A1, j, kkeep)));
+      TRY(run_step(p, upd_step(PK_FUSED, 0, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_W, TAIL_BC_A2, j, kkeep)));
+      TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P2, j,
+                               kkeep)));
+      TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_C, j, kkeep)));
+      TRY(run_step(p, upd_step(PK_UPDATE, 0, c0, sw, PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
+      break;
+    case TSG_ORTHO_CGS2:
+      TRY(run_step(p, gram_step(p.f32, k, c0, 1, 0, TAIL_CGS_H1, j, kkeep)));
+      TRY(run_step(p, upd_step(PK_FUSED, k, c0, 1, PF_HAS_P | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_CGS_H2, j,
+                               kkeep)));
+      TRY(run_step(p, upd_step(PK_UPDATE, k, c0, 1, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
+      break;
+  }
+  return TSG_OK;
+}
+
 
 }  // namespace
 
@@ -428,9 +590,9 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   hipError_t e = hipMemcpyAsync(c.st, hs, head_bytes, hipMemcpyHostToDevice, s);
   delete hs;
   HIP_TRY(e);
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(cdiv(kCounters, 256)), dim3(256), 0, s, c.cnt, kCounters);
   const int nbr = (int)cdiv(n, kRowBlock);
-  hipLaunchKernelGGL(norm_kernel, dim3(nbr), dim3(kRowBlock), 0, s, b, n, c.st, c.part1, c.part2, c.cnt);
+  hipLaunchKernelGGL(norm_kernel, dim3(nbr), dim3(kRowBlock), 0, s, b, n, c.part1);
+  hipLaunchKernelGGL(norm_tail_kernel, dim3(1), dim3(kTailThreads), 0, s, c.st, (const double*)c.part1, nbr);
   HIP_LAUNCH_CHECK();
   double bnorm = 0.0;
   HIP_TRY(hipMemcpyAsync(&bnorm, &c.st->bnorm, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -457,9 +619,7 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   }
 
   auto mpk = [&](int col_in, int col_out, int i, int panel_idx) -> tsg_status {
-    timer.begin(s, KC_SPMV);
-    timer.count[KC_SPMV] += 1;
-    timer.bytes[KC_SPMV] += spmv_bytes;
+    timer.begin(s, TSG_KC_MPK, spmv_bytes);
     hipLaunchKernelGGL((mpk_step_kernel<T, VT>), dim3(nbr), dim3(kRowBlock), 0, s, A->row_ptr, A->col,
                        val, V + (int64_t)col_in * ld, V + (int64_t)col_out * ld, n, theta[i], sigma[i],
                        c.st, panel_idx);
@@ -471,59 +631,37 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   tsg_status result = TSG_OK;
   for (;;) {
     // ---- restart residual r = b - A x, beta, convergence test (explicit, FP64)
-    timer.begin(s, KC_RESID);
-    timer.count[KC_RESID] += 1;
-    timer.bytes[KC_RESID] += resid_bytes;
+    timer.begin(s, TSG_KC_RESIDUAL, resid_bytes);
     hipLaunchKernelGGL((residual_kernel<T>), dim3(nbr), dim3(kRowBlock), 0, s, A->row_ptr, A->col,
-                       A->val, x, b, V, n, c.st, c.part1, c.part2, c.cnt);
+                       A->val, x, b, V, n, c.st, c.part1);
+    hipLaunchKernelGGL(residual_tail_kernel, dim3(1), dim3(kTailThreads), 0, s, c.st,
+                       (const double*)c.part1, nbr);
     timer.end(s);
     HIP_LAUNCH_CHECK();
-    // ---- qhat_1 = r / beta (two-stage: also G2(0,0) of the stored column)
-    TRY(panel(pc, 0, 0, 1, PF_HAS_T | PF_STORE | (two ? PF_GRAM_W : 0), two ? TAIL_NORM0 : TAIL_NONE,
-              -1, 0, 1, KC_RESID));
+    // ---- qhat_1 = r / beta (two-stage: the same pass gives G2(0,0) of the stored column)
+    {
+      Step sc = upd_step(two ? PK_FUSED : PK_UPDATE, 0, 0, 1,
+                         PF_HAS_T | PF_STORE | (two ? PF_GRAM_W : 0), two ? TAIL_NORM0 : TAIL_NONE, -1, 0);
+      sc.kclass = TSG_KC_SCALE;
+      TRY(run_step(pc, sc));
+    }
     for (int j = 0; j < J; ++j) {
       const int k = j * sstep + 1;
-      const int kkeep = k - 1;
       for (int i = 0; i < sstep; ++i) TRY(mpk(k - 1 + i, k + i, i, j));
-      switch (ortho) {
-        case TSG_ORTHO_TWO_STAGE:
-          // stage 1: BCGS-PIP of the panel against all previous columns (one reduction)
-          TRY(panel(pc, k, k, sstep, PF_GRAM_Q | PF_GRAM_W, TAIL_PIP, j, kkeep));
-          // update in place; the same pass accumulates the stage-2 Gram block column
-          TRY(panel(pc, k, k, sstep, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_G2COL, j,
-                    kkeep));
-          break;
-        case TSG_ORTHO_BCGS_PIP2:
-          TRY(panel(pc, k, k, sstep, PF_GRAM_Q | PF_GRAM_W, TAIL_PIP2_A, j, kkeep));
-          TRY(panel(pc, k, k, sstep, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_PIP2_B, j,
-                    kkeep));
-          TRY(panel(pc, k, k, sstep, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep));
-          break;
-        case TSG_ORTHO_BCGS2_CHOLQR2:
-          TRY(panel(pc, k, k, sstep, PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P1, j, kkeep));
-          TRY(panel(pc, k, k, sstep, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_A1, j, kkeep));
-          TRY(panel(pc, 0, k, sstep, PF_HAS_T | PF_STORE | PF_GRAM_W, TAIL_BC_A2, j, kkeep));
-          TRY(panel(pc, k, k, sstep, PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P2, j, kkeep));
-          TRY(panel(pc, k, k, sstep, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_C, j, kkeep));
-          TRY(panel(pc, 0, k, sstep, PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep));
-          break;
-        case TSG_ORTHO_CGS2:
-          TRY(panel(pc, k, k, 1, PF_GRAM_Q | PF_GRAM_W, TAIL_CGS_H1, j, kkeep));
-          TRY(panel(pc, k, k, 1, PF_HAS_P | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_CGS_H2, j, kkeep));
-          TRY(panel(pc, k, k, 1, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep));
-          break;
-      }
+      // two-stage: the next panel's reduction covers this panel's stage-2 Gram block column
+      // when both panels fit one lean reduction; otherwise the update is fused with it
+      const bool lean2 = 2 * sstep <= max_gram_nz(f32);
+      const bool covered = j < J - 1 && lean2;
+      const int nprev = (two && j > 0 && lean2) ? sstep : 0;
+      TRY(panel_sequence(pc, ortho, k, sstep, nprev, !covered, j, k - 1));
     }
     // ---- stage 2 (two-stage) / projected least squares; counters
-    timer.begin(s, KC_SMALL);
-    timer.count[KC_SMALL] += 1;
+    timer.begin(s, TSG_KC_CYCLE_END, 0.0);
     hipLaunchKernelGGL(cycle_end_kernel, dim3(1), dim3(256), 0, s, c.st, two ? 1 : 0);
     timer.end(s);
     HIP_LAUNCH_CHECK();
     // ---- x += V(:, 0:k_used) coef
-    timer.begin(s, KC_XUPD);
-    timer.count[KC_XUPD] += 1;
-    timer.bytes[KC_XUPD] += (double)m * n * sizeof(T) + 16.0 * n;
+    timer.begin(s, TSG_KC_XUPDATE, (double)m * n * sizeof(T) + 16.0 * n);
     hipLaunchKernelGGL((xupdate_kernel<T>), dim3(nbr), dim3(kRowBlock), 0, s, x, V, ld, n, c.st);
     timer.end(s);
     HIP_LAUNCH_CHECK();
@@ -560,18 +698,24 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
     info->truncated_cycles = h.truncated;
     if (timer.on) {
       info->ms_total = ms_total;
-      info->ms_spmv = timer.ms[KC_SPMV];
-      info->ms_ortho_reduce = timer.ms[KC_REDUCE];
-      info->ms_ortho_update = timer.ms[KC_UPDATE];
-      info->ms_small = timer.ms[KC_SMALL];
-      info->ms_xupdate = timer.ms[KC_XUPD];
-      info->ms_residual = timer.ms[KC_RESID];
-      info->n_ortho_reduce = timer.count[KC_REDUCE];
-      info->n_ortho_update = timer.count[KC_UPDATE];
-      info->n_spmv = timer.count[KC_SPMV];
-      info->bytes_ortho_reduce = timer.bytes[KC_REDUCE];
-      info->bytes_ortho_update = timer.bytes[KC_UPDATE];
-      info->bytes_spmv = timer.bytes[KC_SPMV];
+      auto& T_ = timer;
+      info->ms_spmv = T_.ms[TSG_KC_MPK];
+      info->ms_ortho_reduce = T_.ms[TSG_KC_GRAM] + T_.ms[TSG_KC_GRAM_FIRST];
+      info->ms_ortho_update = T_.ms[TSG_KC_UPDATE] + T_.ms[TSG_KC_FUSED];
+      info->ms_small = T_.ms[TSG_KC_TAIL] + T_.ms[TSG_KC_CYCLE_END];
+      info->ms_xupdate = T_.ms[TSG_KC_XUPDATE];
+      info->ms_residual = T_.ms[TSG_KC_RESIDUAL] + T_.ms[TSG_KC_SCALE];
+      info->n_ortho_reduce = T_.count[TSG_KC_GRAM] + T_.count[TSG_KC_GRAM_FIRST];
+      info->n_ortho_update = T_.count[TSG_KC_UPDATE] + T_.count[TSG_KC_FUSED];
+      info->n_spmv = T_.count[TSG_KC_MPK];
+      info->bytes_ortho_reduce = T_.bytes[TSG_KC_GRAM] + T_.bytes[TSG_KC_GRAM_FIRST];
+      info->bytes_ortho_update = T_.bytes[TSG_KC_UPDATE] + T_.bytes[TSG_KC_FUSED];
+      info->bytes_spmv = T_.bytes[TSG_KC_MPK];
+      for (int i = 0; i < TSG_KC_COUNT; ++i) {
+        info->kc_ms[i] = T_.ms[i];
+        info->kc_launches[i] = T_.count[i];
+        info->kc_bytes[i] = T_.bytes[i];
+      }
     }
   }
   return st;
@@ -644,7 +788,6 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   hipError_t e = hipMemcpyAsync(c.st, hs, offsetof(SmallState, Hh), hipMemcpyHostToDevice, st);
   delete hs;
   HIP_TRY(e);
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(cdiv(kCounters, 256)), dim3(256), 0, st, c.cnt, kCounters);
   hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(kLd * kLd, 256)), dim3(256), 0, st, c.st->Hh,
                      (int64_t)kLd * kLd);
   hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(kLd * kLd, 256)), dim3(256), 0, st, c.st->G2,
@@ -652,30 +795,15 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   HIP_LAUNCH_CHECK();
   PanelCtx pc{X, ldx, n, 8, false, c, st, nullptr, 1};
   // column 1 alone
-  TRY(panel(pc, 0, 0, 1, PF_GRAM_W, TAIL_SA_NORM, -1, 0));
-  TRY(panel(pc, 0, 0, 1, PF_HAS_T | PF_STORE | (two ? PF_GRAM_W : 0), two ? TAIL_NORM0 : TAIL_NONE, -1, 0));
+  TRY(run_step(pc, gram_step(false, 0, 0, 1, 0, TAIL_SA_NORM, -1, 0)));
+  TRY(run_step(pc, upd_step(two ? PK_FUSED : PK_UPDATE, 0, 0, 1, PF_HAS_T | PF_STORE | (two ? PF_GRAM_W : 0),
+                            two ? TAIL_NORM0 : TAIL_NONE, -1, 0)));
+  const bool lean2 = 2 * s <= max_gram_nz(false);
   for (int c0 = 1; c0 < k; c0 += s) {
     const int sw = std::min(s, k - c0);
-    const int kq = c0;
-    switch (algo) {
-      case TSG_ORTHO_TWO_STAGE:
-        TRY(panel(pc, kq, c0, sw, PF_GRAM_Q | PF_GRAM_W, TAIL_PIP, 0, 0));
-        TRY(panel(pc, kq, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_G2COL, 0, 0));
-        break;
-      case TSG_ORTHO_BCGS_PIP2:
-        TRY(panel(pc, kq, c0, sw, PF_GRAM_Q | PF_GRAM_W, TAIL_PIP2_A, 0, 0));
-        TRY(panel(pc, kq, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_PIP2_B, 0, 0));
-        TRY(panel(pc, kq, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, 0, 0));
-        break;
-      default:
-        TRY(panel(pc, kq, c0, sw, PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P1, 0, 0));
-        TRY(panel(pc, kq, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_A1, 0, 0));
-        TRY(panel(pc, 0, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_W, TAIL_BC_A2, 0, 0));
-        TRY(panel(pc, kq, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P2, 0, 0));
-        TRY(panel(pc, kq, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_C, 0, 0));
-        TRY(panel(pc, 0, c0, sw, PF_HAS_T | PF_STORE, TAIL_NONE, 0, 0));
-        break;
-    }
+    const bool last = c0 + sw >= k;
+    const int nprev = (two && c0 > 1 && lean2) ? s : 0;  // panels before the last have width s
+    TRY(panel_sequence(pc, algo, c0, sw, nprev, last || !lean2, 0, 0));
   }
   if (two) {
     // stage 2: one CholQR over all k columns, then Q = Qhat R2^{-1}
@@ -694,7 +822,7 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   if (orth_err) {
     for (int c0 = 0; c0 < k; c0 += kMaxS) {
       const int sw = std::min(kMaxS, k - c0);
-      TRY(panel(pc, c0, c0, sw, PF_GRAM_Q | PF_GRAM_W, TAIL_GRAM_OUT, 0, 0, 0));
+      TRY(run_step(pc, gram_step(false, c0, c0, sw, 0, TAIL_GRAM_OUT, 0, 0, 0)));
     }
     hipLaunchKernelGGL(orth_err_kernel, dim3(1), dim3(256), 0, st, c.st, k);
     HIP_LAUNCH_CHECK();
