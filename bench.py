@@ -71,6 +71,13 @@ def main():
     ap.add_argument("--no-ortho-bench", action="store_true")
     ap.add_argument("--ortho-reps", type=int, default=20)
     ap.add_argument("--cpu-cycles", type=int, default=1)
+    ap.add_argument("--time-stride", type=int, default=8,
+                    help="HIP-event timing of every launch in every n-th restart cycle of the timed "
+                         "solves (1 = every cycle; events between launches slow a cycle by ~7%%)")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch every kernel directly instead of replaying one captured cycle")
+    ap.add_argument("--modes", action="store_true",
+                    help="also time one solve in each launch mode (graph/eager x events on/off)")
     ap.add_argument("--compare", action="store_true",
                     help="also time one solve of each other orthogonalization scheme")
     args = ap.parse_args()
@@ -95,7 +102,8 @@ def main():
     A = tsg.CSRMatrix.from_host(Ah, device=dev)
     b = torch.as_tensor(pr["b"], device=dev)
     x = torch.zeros_like(b)
-    kw = dict(m=args.m, s=args.s, tol=args.tol, ortho=args.ortho, precision=args.precision)
+    kw = dict(m=args.m, s=args.s, tol=args.tol, ortho=args.ortho, precision=args.precision,
+              graph=not args.eager)
     need = tsg.binding.solve_workspace_bytes(A, m=args.m, s=args.s, ortho=args.ortho,
                                              precision=args.precision)
     ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
@@ -113,7 +121,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         x.zero_()
-        _, info = tsg.solve(A, b, x, workspace=ws, timing=True, **kw)
+        _, info = tsg.solve(A, b, x, workspace=ws, timing=args.time_stride, **kw)
         infos.append(info)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -125,6 +133,8 @@ def main():
 
     def tot(f):
         return sum(getattr(i, f) for i in infos)
+
+    tcyc = tot("timed_cycles")
 
     # per kernel class (one kernel instantiation each), from HIP events on the solve stream
     classes = {}
@@ -157,13 +167,14 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": traffic, "kernel": kname,
                 "avg_launch_us": round(ms / cnt * 1e3, 2), "launches": int(cnt),
-                "algorithmic_bytes_per_launch": round(by / cnt)}
+                "algorithmic_bytes_per_launch": round(by / cnt),
+                "timed_cycles": int(tcyc), "time_stride": args.time_stride}
     per_class = {}
     for c, (cms, ccnt, cby) in classes.items():
-        per_class[c] = {"kernel": names.get(c), "ms_per_solve": round(cms / len(infos), 2),
-                        "launches_per_solve": int(ccnt / len(infos)),
+        per_class[c] = {"kernel": names.get(c), "ms_per_cycle": round(cms / tcyc, 4),
+                        "launches_per_cycle": round(ccnt / tcyc, 2),
                         "GBps": round(cby / (cms * 1e-3) / 1e9, 1) if cms > 0 and cby > 0 else None}
-    ortho_ms_cycle = (tot("ms_ortho_reduce") + tot("ms_ortho_update") + tot("ms_small")) / tot("cycles")
+    ortho_ms_cycle = (tot("ms_ortho_reduce") + tot("ms_ortho_update") + tot("ms_small")) / tcyc
 
     out = {
         "metric": METRIC,
@@ -191,6 +202,25 @@ def main():
         "roofline": roofline,
     }
 
+    if args.modes:
+        modes = {}
+        for graph in (True, False):
+            for timing in (False, True):
+                x.zero_()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                key = ("graph" if graph else "eager") + ("+events" if timing else "")
+                try:
+                    tsg.solve(A, b, x, workspace=ws, timing=int(timing), **dict(kw, graph=graph))
+                except tsg.TSGError as exc:
+                    modes[key] = str(exc)
+                    log(f"[bench] mode {key}: {exc}")
+                    continue
+                torch.cuda.synchronize()
+                modes[key] = round(time.perf_counter() - t, 4)
+                log(f"[bench] mode {key}: {modes[key]} s")
+        out["launch_modes_s"] = modes
+
     if args.compare:
         cmp = {}
         for o in ("two_stage", "bcgs_pip2", "bcgs2_cholqr2", "cgs2"):
@@ -202,12 +232,12 @@ def main():
             torch.cuda.synchronize()
             t = time.perf_counter()
             _, ci = tsg.solve(A, b, x, workspace=None, timing=True, m=args.m, s=args.s, tol=args.tol,
-                              ortho=o, precision=args.precision)
+                              ortho=o, precision=args.precision, graph=not args.eager)
             torch.cuda.synchronize()
             t = time.perf_counter() - t
             cmp[o] = {"time_to_solution_s": round(t, 4), "iters": int(ci.iters), "relres": ci.relres,
                       "ortho_ms_per_cycle": round((ci.ms_ortho_reduce + ci.ms_ortho_update + ci.ms_small)
-                                                  / max(ci.cycles, 1), 3)}
+                                                  / max(ci.timed_cycles, 1), 3)}
             log(f"[bench] compare {o}: {cmp[o]}")
         out["compare"] = cmp
 

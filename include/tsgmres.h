@@ -80,10 +80,20 @@ typedef struct {
   double tol;           /* stop when ||b - A x||_2 <= tol ||b||_2 (explicit, FP64)      */
   int64_t max_iters;    /* stop (TSG_NOT_CONVERGED) once this many vectors were built   */
   const double* newton_shifts; /* host, length s, only for TSG_BASIS_NEWTON             */
-  int32_t timing;       /* nonzero: time each kernel class with HIP events (adds one
-                           host synchronization per restart cycle)                      */
-  int32_t reserved;
+  int32_t timing;       /* 0: off.  t >= 1: time each launch of every t-th restart cycle
+                           (cycles 0, t, 2t, ...) with HIP events; timed cycles are
+                           launched directly even in graph mode                         */
+  int32_t flags;        /* TSG_FLAG_* bits, 0 by default                                */
 } tsg_solve_params;
+
+/* tsg_solve_params.flags.  By default the launches of one restart cycle (they are the
+ * same in every cycle) are captured once per solve into a HIP graph on a private
+ * stream and the graph is replayed on `stream` once per cycle (HIP events cannot be
+ * captured as timing nodes here, so cycles timed by params.timing are enqueued
+ * directly).
+ *   EAGER  launch every kernel of every cycle directly on `stream` instead (same
+ *          kernels and arguments, bitwise-identical results). */
+enum { TSG_FLAG_EAGER = 1 };
 
 /* Kernel classes reported by tsg_solve_info (timing mode).  Each class is one kernel
  * instantiation for a given precision and step size s. */
@@ -108,13 +118,15 @@ typedef struct {
   double relres_est;    /* implicit estimate at the end of the last cycle               */
   int32_t status;       /* tsg_status of the solve                                      */
   int32_t truncated_cycles; /* cycles shortened by a Cholesky breakdown                 */
-  /* filled only when params.timing != 0 (milliseconds of GPU time, HIP events) */
+  /* filled only when params.timing != 0 (milliseconds of GPU time, HIP events); every
+   * per-class figure is a total over the timed cycles only; ms_total spans the solve */
   double ms_total, ms_spmv, ms_ortho_reduce, ms_ortho_update, ms_small, ms_xupdate, ms_residual;
   int64_t n_ortho_reduce, n_ortho_update, n_spmv;  /* launches of each class           */
   double bytes_ortho_reduce, bytes_ortho_update, bytes_spmv; /* algorithmic bytes moved */
   double kc_ms[16];        /* per kernel class (TSG_KC_*): GPU milliseconds               */
   int64_t kc_launches[16]; /* launches that did work                                      */
   double kc_bytes[16];     /* algorithmic bytes (sum over launches)                       */
+  int64_t timed_cycles;    /* restart cycles whose launches were timed                    */
 } tsg_solve_info;
 
 typedef struct tsg_csr_s* tsg_csr;
@@ -140,8 +152,9 @@ size_t tsg_solve_workspace_bytes(int64_t n, int64_t nnz, const tsg_solve_params*
 /* Solve A x = b by restarted s-step GMRES(m) (Sec. III, Fig. 1) with the block
  * orthogonalization p->ortho.  b[n] (device, float64) is read; x[n] (device, float64)
  * holds x0 on entry and the result on exit.  Every step of a restart cycle runs in
- * the library's HIP kernels on `stream`; the host only reads back an 64-byte status
- * block once per cycle.  Returns after the solve has finished on the device.
+ * the library's HIP kernels on `stream`; the host only reads back a 64-byte status
+ * block once per cycle (the host synchronizes `stream` once per cycle).  Returns after
+ * the solve has finished on the device.
  * Status: OK (converged), NOT_CONVERGED, BREAKDOWN, or a negative error (then x is
  * untouched).  `info` (host) is filled for every non-negative status. */
 tsg_status tsg_solve(tsg_csr A, const double* b, double* x, const tsg_solve_params* p,
@@ -159,8 +172,9 @@ size_t tsg_orthogonalize_workspace_bytes(int64_t n, int32_t k, int32_t s);
  * columns, then Q = Qhat R2^{-1}), BCGS_PIP2 or BCGS2_CHOLQR2.  s_hat must be 0 or
  * k-1.  R (device, k x k, column-major, leading dimension ldr >= k) receives R; its
  * strictly lower part is set to 0.  Requires 1 <= k <= 64, 1 <= s <= 16, k <= n.
- * Asynchronous unless orth_err (host) is non-NULL, in which case ||I - Q^T Q||_F is
- * computed on the device and returned (one extra pass, synchronizes `stream`).
+ * Synchronizes `stream` before returning (the breakdown status is read back).  If
+ * orth_err (host) is non-NULL, ||I - Q^T Q||_F is also computed on the device (one
+ * extra pass) and returned.
  * Status BREAKDOWN: a Gram matrix was not numerically positive definite (X is then
  * partially overwritten). */
 tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr,

@@ -18,6 +18,7 @@ _LIB_NAME = "libtsgmres.so"
 ORTHO = {"two_stage": 0, "bcgs_pip2": 1, "bcgs2_cholqr2": 2, "cgs2": 3}
 BASIS = {"monomial": 0, "shifted": 1, "newton": 2}
 PRECISION = {"fp64": 0, "fp32_ir": 1}
+FLAG_EAGER = 1
 STATUS = {0: "ok", 1: "not converged", 2: "breakdown", -1: "invalid argument",
           -2: "HIP runtime error", -3: "workspace", -4: "unsupported"}
 
@@ -32,7 +33,7 @@ class _Params(C.Structure):
     _fields_ = [("m", C.c_int32), ("s", C.c_int32), ("s_hat", C.c_int32), ("ortho", C.c_int32),
                 ("basis", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double),
                 ("max_iters", C.c_int64), ("newton_shifts", C.POINTER(C.c_double)),
-                ("timing", C.c_int32), ("reserved", C.c_int32)]
+                ("timing", C.c_int32), ("flags", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -44,7 +45,8 @@ class _Info(C.Structure):
                 ("n_ortho_update", C.c_int64), ("n_spmv", C.c_int64),
                 ("bytes_ortho_reduce", C.c_double), ("bytes_ortho_update", C.c_double),
                 ("bytes_spmv", C.c_double), ("kc_ms", C.c_double * 16),
-                ("kc_launches", C.c_int64 * 16), ("kc_bytes", C.c_double * 16)]
+                ("kc_launches", C.c_int64 * 16), ("kc_bytes", C.c_double * 16),
+                ("timed_cycles", C.c_int64)]
 
 
 KERNEL_CLASSES = ["mpk", "gram", "gram_first", "update", "fused", "tail", "cycle_end", "xupdate",
@@ -75,6 +77,7 @@ class SolveInfo:
     kc_ms: tuple = ()
     kc_launches: tuple = ()
     kc_bytes: tuple = ()
+    timed_cycles: int = 0
 
     def kernel_classes(self) -> dict:
         """{class: (ms, launches, algorithmic bytes)} for the classes that ran (timing mode)."""
@@ -212,7 +215,7 @@ def spmv(A: CSRMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.
     return y
 
 
-def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing):
+def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph=True):
     p = _Params()
     p.m, p.s, p.s_hat = int(m), int(s), 0
     p.ortho = ORTHO[ortho] if isinstance(ortho, str) else int(ortho)
@@ -224,7 +227,8 @@ def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing):
     if shifts is not None:
         keep = (C.c_double * len(shifts))(*[float(v) for v in shifts])
         p.newton_shifts = C.cast(keep, C.POINTER(C.c_double))
-    p.timing = 1 if timing else 0
+    p.timing = int(timing)  # False/True -> 0/1; an int t > 1 times every t-th cycle
+    p.flags = 0 if graph else FLAG_EAGER
     return p, keep
 
 
@@ -237,14 +241,17 @@ def solve_workspace_bytes(A: CSRMatrix, m=60, s=5, ortho="two_stage", basis="mon
 def solve(A: CSRMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, m: int = 60, s: int = 5,
           tol: float = 1e-10, max_iters: int = 1 << 40, ortho: str = "two_stage",
           basis: str = "monomial", precision: str = "fp64", shifts=None, timing: bool = False,
-          workspace: torch.Tensor | None = None):
-    """Solve A x = b (x updated in place; zeros if None).  Returns (x, SolveInfo)."""
+          graph: bool = True, workspace: torch.Tensor | None = None):
+    """Solve A x = b (x updated in place; zeros if None).  Returns (x, SolveInfo).
+
+    graph=False launches every kernel directly instead of replaying one captured restart
+    cycle per cycle (same results, bit for bit)."""
     lib = load_library()
     _dev_tensor(b, torch.float64, "b")
     if x is None:
         x = torch.zeros_like(b)
     _dev_tensor(x, torch.float64, "x")
-    p, keep = _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing)
+    p, keep = _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph)
     need = int(lib.tsg_solve_workspace_bytes(A.n, A.nnz, C.byref(p)))
     if need == 0:
         _check(-1)

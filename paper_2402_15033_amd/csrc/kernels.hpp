@@ -36,7 +36,12 @@ __device__ __forceinline__ T csr_row_dot(const int32_t* __restrict__ row_ptr, co
   T acc = (T)0;
   if (cnt <= kSegCap) {
 #pragma unroll 4
-    for (int e = lane; e < cnt; e += kWave) prod[e] = (T)val[base + e] * x[col[base + e]];
+    for (int e = lane; e < cnt; e += kWave) {
+      // the CSR arrays stream through once per product: non-temporal, so x stays cached
+      const VT a = __builtin_nontemporal_load(&val[base + e]);
+      const int32_t cidx = __builtin_nontemporal_load(&col[base + e]);
+      prod[e] = (T)a * x[cidx];
+    }
     wave_lds_sync();
     for (int e = rp - base; e < rp1 - base; ++e) acc += prod[e];
     wave_lds_sync();
@@ -261,106 +266,139 @@ __global__ __launch_bounds__(kRowBlock) void xupdate_kernel(double* __restrict__
 }
 
 // ------------------------------------------------------------------ end of cycle
-// One block.  Two-stage: stage 2 = CholQR of the kept columns (R2 = Chol(G2)),
-// H = R2 Hhat R2^{-1} (Fig. 5 with s_hat = m), Givens least squares with rhs
-// beta R2(1,1) e_1, coef = R2^{-1} y.  Other variants: coef from the incremental
-// Givens factorization.  Then the iteration counters advance.
+// Back substitution z = U(0:k,0:k)^{-1} g(0:k) for upper-triangular U in LDS (ld kLd),
+// column-oriented, by wave 0 with wave-level synchronization; g is overwritten.
+__device__ void wave_back_subst(const double* U, double* g, double* z, int k) {
+  const int lane = threadIdx.x;
+  for (int i = k - 1; i >= 0; --i) {
+    if (lane == 0) z[i] = g[i] / U[i + i * kLd];
+    wave_lds_sync();
+    const double zi = z[i];
+    if (lane < i) g[lane] -= U[lane + i * kLd] * zi;
+    wave_lds_sync();
+  }
+}
+
+// One block.  Two-stage: stage 2 = CholQR of the kept columns, R2 = Chol(G2) (Fig. 5 with
+// s_hat = m); then the projected least-squares problem in its Qhat form:
+//   z = argmin || beta R2(1,1) e_1 - (R2 Hhat) z ||,
+// which equals R2(1:m,1:m)^{-1} y for y = argmin || beta R2(1,1) e_1 - H y ||, H = R2 Hhat R2^{-1}
+// (substitute y = R2 z), so neither R2^{-1} nor H is formed; x += Qhat z follows.  Other
+// variants: z from the incremental Givens factorization of their Hessenberg matrix.  Then
+// the iteration counters advance.
 __global__ __launch_bounds__(256) void cycle_end_kernel(SmallState* st, int two_stage) {
   if (st->h.done) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ double sG[kLd * kLd];
   __shared__ double sR[kLd * kLd];
-  __shared__ double sH[kLd * kLd];
-  __shared__ double sc[kLd], ss[kLd], sg[kLd + 1], sy[kLd];
-  __shared__ int s_ku, s_kb;
+  __shared__ double sM[kLd * kLd];
+  __shared__ double sc[kLd], ss[kLd], sg[kLd + 1], sz[kLd];
+  __shared__ int s_ku, s_kb, s_fail;
+  __shared__ double s_piv;
   if (tid == 0) s_ku = st->h.k_used;
   __syncthreads();
   int ku = s_ku;
   double est = 0.0;
   if (two_stage && ku > 0) {
     int kb = ku + 1;
-    for (int i = tid; i < kb * kb; i += nt) sG[(i % kb) + (i / kb) * kLd] = st->G2[(i % kb) + (i / kb) * kLd];
-    __syncthreads();
-    int f = block_chol_upper(sG, kLd, sR, kLd, kb, nullptr, st->pivot_tol);
-    if (tid == 0) {
-      s_kb = kb;
-      if (f >= 0) {  // keep the leading f columns (rows 0..f-1 of R are complete)
-        s_kb = f;
-        st->h.truncated += 1;
-      }
+    for (int i = tid; i < kb * kb; i += nt) {
+      const int r = i % kb, c = i / kb;
+      const double g = st->G2[r + c * kLd];
+      sG[r + c * kLd] = g;
+      sR[r + c * kLd] = (r <= c) ? g : 0.0;
     }
     __syncthreads();
-    kb = s_kb;
+    // right-looking Cholesky of the upper triangle; a pivot d_j <= tol * G_jj truncates
+    int fail = -1;
+    for (int j = 0; j < kb; ++j) {
+      if (tid == 0) {
+        const double d = sR[j + j * kLd];
+        s_fail = !(d > st->pivot_tol * sG[j + j * kLd]);
+        s_piv = s_fail ? 0.0 : sqrt(d);
+        if (!s_fail) sR[j + j * kLd] = s_piv;
+      }
+      __syncthreads();
+      if (s_fail) {
+        fail = j;
+        break;
+      }
+      const double rjj = s_piv;
+      for (int c = j + 1 + tid; c < kb; c += nt) sR[j + c * kLd] /= rjj;
+      __syncthreads();
+      const int t = kb - j - 1;
+      for (int idx = tid; idx < t * t; idx += nt) {
+        const int i = j + 1 + idx / t, c = j + 1 + idx % t;
+        if (i <= c) sR[i + c * kLd] -= sR[j + i * kLd] * sR[j + c * kLd];
+      }
+      __syncthreads();
+    }
+    if (fail >= 0) {  // keep the leading `fail` columns (rows 0..fail-1 of R are final)
+      kb = fail;
+      if (tid == 0) st->h.truncated += 1;
+    }
     ku = kb - 1;
     if (ku > 0) {
-      // sH = R2(0:kb,0:kb) * Hhat(0:kb,0:ku)   (R2 upper, Hhat upper Hessenberg)
+      // stage Hhat in LDS (sG is free now), then sM = R2(0:kb,0:kb) Hhat(0:kb,0:ku)
       for (int idx = tid; idx < kb * ku; idx += nt) {
-        int i = idx % kb, j = idx / kb;
+        const int i = idx % kb, j = idx / kb;
+        sG[i + j * kLd] = st->Hh[i + j * kLd];
+      }
+      __syncthreads();
+      for (int idx = tid; idx < kb * ku; idx += nt) {
+        const int i = idx % kb, j = idx / kb;
         double v = 0.0;
-        int lmax = min(kb - 1, j + 1);
-        for (int l = i; l <= lmax; ++l) v += sR[i + l * kLd] * st->Hh[l + j * kLd];
-        sH[i + j * kLd] = v;
+        const int lmax = min(kb - 1, j + 1);
+        for (int l = i; l <= lmax; ++l) v += sR[i + l * kLd] * sG[l + j * kLd];
+        sM[i + j * kLd] = v;
       }
-      __syncthreads();
-      // sG <- R2(0:ku,0:ku)^{-1}
-      block_tri_inv_upper(sR, kLd, sG, kLd, ku);
-      // H = sH * R2^{-1}, computed in place column by column from the right
-      for (int idx = tid; idx < kb; idx += nt) {
-        double row[kLd];
-        for (int j = 0; j < ku; ++j) row[j] = sH[idx + j * kLd];
-        for (int j = ku - 1; j >= 0; --j) {
-          double v = 0.0;
-          for (int l = 0; l <= j; ++l) v += row[l] * sG[l + j * kLd];
-          row[j] = v;
-        }
-        for (int j = 0; j < ku; ++j) sH[idx + j * kLd] = row[j];
-      }
-      __syncthreads();
-      // Givens least squares on the Hessenberg part of H, rhs beta R2(0,0) e_1
       for (int i = tid; i <= kLd; i += nt) sg[i] = 0.0;
       __syncthreads();
-      if (tid == 0) sg[0] = st->beta * sR[0];
-      __syncthreads();
-      for (int i = 0; i < ku; ++i) {
-        if (tid == 0) {
-          double a = sH[i + i * kLd], b = sH[(i + 1) + i * kLd];
-          double rho = hypot(a, b);
-          double c = 1.0, s = 0.0;
-          if (rho != 0.0) { c = a / rho; s = b / rho; }
-          sc[i] = c;
-          ss[i] = s;
-          sH[i + i * kLd] = rho;
-          double gi = sg[i];
-          sg[i] = c * gi;
-          sg[i + 1] = -s * gi;
+      if (tid < kWave) {  // wave 0: Givens QR of sM and back substitution
+        const int lane = tid;
+        if (lane == 0) sg[0] = st->beta * sR[0];
+        wave_lds_sync();
+        for (int i = 0; i < ku; ++i) {
+          if (lane == 0) {
+            const double a = sM[i + i * kLd], b = sM[(i + 1) + i * kLd];
+            const double rho = hypot(a, b);
+            double c = 1.0, s = 0.0;
+            if (rho != 0.0) {
+              c = a / rho;
+              s = b / rho;
+            }
+            sc[i] = c;
+            ss[i] = s;
+            sM[i + i * kLd] = rho;
+            const double gi = sg[i];
+            sg[i] = c * gi;
+            sg[i + 1] = -s * gi;
+          }
+          wave_lds_sync();
+          const int t = lane;
+          if (t > i && t < ku) {
+            const double a = sM[i + t * kLd], b = sM[(i + 1) + t * kLd];
+            sM[i + t * kLd] = sc[i] * a + ss[i] * b;
+            sM[(i + 1) + t * kLd] = -ss[i] * a + sc[i] * b;
+          }
+          wave_lds_sync();
         }
-        __syncthreads();
-        for (int t = i + 1 + tid; t < ku; t += nt) {
-          double a = sH[i + t * kLd], b = sH[(i + 1) + t * kLd];
-          sH[i + t * kLd] = sc[i] * a + ss[i] * b;
-          sH[(i + 1) + t * kLd] = -ss[i] * a + sc[i] * b;
-        }
-        __syncthreads();
+        est = fabs(sg[ku]);
+        wave_back_subst(sM, sg, sz, ku);
+        for (int i = lane; i < ku; i += kWave) st->coef[i] = sz[i];
       }
-      if (tid == 0) {
-        for (int i = ku - 1; i >= 0; --i) {
-          double v = sg[i];
-          for (int l = i + 1; l < ku; ++l) v -= sH[i + l * kLd] * sy[l];
-          sy[i] = v / sH[i + i * kLd];
-        }
-      }
-      __syncthreads();
-      // coef = R2^{-1} y
-      for (int i = tid; i < ku; i += nt) {
-        double v = 0.0;
-        for (int l = i; l < ku; ++l) v += sG[i + l * kLd] * sy[l];
-        st->coef[i] = v;
-      }
-      est = fabs(sg[ku]);
     }
   } else if (!two_stage && ku > 0) {
-    givens_solve(st, ku);
-    est = fabs(st->gg[ku]);
+    for (int i = tid; i < ku * ku; i += nt) {
+      const int r = i % ku, c = i / ku;
+      sM[r + c * kLd] = st->Rg[r + c * kLd];
+    }
+    for (int i = tid; i <= ku; i += nt) sg[i] = st->gg[i];
+    __syncthreads();
+    if (tid < kWave) {
+      est = fabs(sg[ku]);
+      wave_back_subst(sM, sg, sz, ku);
+      for (int i = tid; i < ku; i += kWave) st->coef[i] = sz[i];
+    }
   }
   __syncthreads();
   if (tid == 0) {

@@ -520,6 +520,21 @@ __global__ __launch_bounds__(512) void panel_kernel(PanelArgs a) {
   }
 }
 
+// First level of a cross-block reduction with many blocks: block g sums the partials of
+// blocks [g*chunk, min(nblocks, (g+1)*chunk)) in block order, for every entry, into
+// part2[g * E + e].  The tail then sums the few group partials in group order.
+__global__ __launch_bounds__(256) void partial_reduce_kernel(PanelArgs a, double* part2, int chunk) {
+  const SmallState* st = a.st;
+  if (a.gate && (st->h.done || a.panel > st->h.stop_panel)) return;
+  const int E = (a.k + a.sw) * a.nz;
+  const int b0 = blockIdx.x * chunk, b1 = min(a.nblocks, b0 + chunk);
+  for (int e = threadIdx.x; e < E; e += blockDim.x) {
+    double acc = 0.0;
+    for (int b = b0; b < b1; ++b) acc += a.part1[(size_t)b * E + e];
+    part2[(size_t)blockIdx.x * E + e] = acc;
+  }
+}
+
 // The reduction of a panel launch: one block sums the per-block partial Grams in a fixed
 // order and runs the FP64 tail (Cholesky, Hessenberg block, Givens, ...).
 __global__ __launch_bounds__(kTailThreads) void panel_tail_kernel(PanelArgs a) {

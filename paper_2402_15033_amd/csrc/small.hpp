@@ -90,15 +90,27 @@ __device__ void block_hessenberg_panel(double* H, const double* P, const double*
                                        double* M) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int rows = k + s;
+  // LDS copies of the operands of the inner products (H(0:k, 0:k-1) is upper Hessenberg)
+  __shared__ double lH[kLd * kLd];
+  __shared__ double lP[kLd * kMaxS];
+  for (int idx = tid; idx < k * (k - 1); idx += nt) {
+    const int i = idx % k, l = idx / k;
+    lH[i + l * kLd] = H[i + l * kLd];
+  }
+  for (int idx = tid; idx < k * s; idx += nt) {
+    const int i = idx % k, c = idx / k;
+    lP[i + c * kLd] = P[i + c * kLd];
+  }
+  __syncthreads();
   auto Sv = [&](int i, int l) -> double {  // S(i, l), 0-based, l in [0, s]
     if (l == 0) return (i == k - 1) ? 1.0 : 0.0;
-    return (i < k) ? P[i + (l - 1) * kLd] : R[(i - k) + (l - 1) * kMaxS];
+    return (i < k) ? lP[i + (l - 1) * kLd] : R[(i - k) + (l - 1) * kMaxS];
   };
   for (int idx = tid; idx < rows * s; idx += nt) {
     int i = idx % rows, c = idx / rows;
     double v = Sv(i, c) * theta[c] + Sv(i, c + 1) * sigma[c];
     if (c >= 1 && i < k) {
-      for (int l = 0; l < k - 1; ++l) v -= H[i + l * kLd] * P[l + (c - 1) * kLd];
+      for (int l = (i > 0 ? i - 1 : 0); l < k - 1; ++l) v -= lH[i + l * kLd] * lP[l + (c - 1) * kLd];
     }
     M[i + c * kLd] = v;
   }
@@ -124,11 +136,17 @@ __device__ void block_hessenberg_panel(double* H, const double* P, const double*
 // a local buffer so the rotation chain runs in registers / LDS.
 __device__ void givens_append(SmallState* st, const double* H, int c0, int c1) {
   __shared__ double col[kLd + 1];
+  __shared__ double lc[kLd], ls[kLd];
+  for (int i = threadIdx.x; i < c0; i += blockDim.x) {
+    lc[i] = st->gc[i];
+    ls[i] = st->gs[i];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     for (int c = c0; c < c1; ++c) {
       for (int i = 0; i <= c + 1; ++i) col[i] = H[i + c * kLd];
       for (int i = 0; i < c; ++i) {
-        double cs = st->gc[i], sn = st->gs[i];
+        double cs = lc[i], sn = ls[i];
         double a = col[i], b = col[i + 1];
         col[i] = cs * a + sn * b;
         col[i + 1] = -sn * a + cs * b;
@@ -142,6 +160,8 @@ __device__ void givens_append(SmallState* st, const double* H, int c0, int c1) {
       }
       st->gc[c] = cs;
       st->gs[c] = sn;
+      lc[c] = cs;
+      ls[c] = sn;
       col[c] = rho;
       for (int i = 0; i <= c; ++i) st->Rg[i + c * kLd] = col[i];
       double gk = st->gg[c];

@@ -108,43 +108,54 @@ __global__ __launch_bounds__(NW * kWave) void gram_kernel(PanelArgs a) {
 // B(l/16, l%16) and D(l/16 + 4r, l%16) in accumulator register r -- the layout was
 // measured on gfx950 with a one-wave probe).
 //   A = V(rows, tile columns)^T, B = V(rows, Z columns): the K dimension is the rows.
-// A block of 8 waves stages 64-row batches of all ncol <= 64 columns in LDS
-// (column-major, rows padded to 65 doubles; double-buffered, one barrier per batch),
-// loading the next batch into registers while the matrix cores consume the current one.
-// Each wave owns two K-steps (8 rows) of every batch and accumulates all MT 16-column
-// tiles: 4 MT doubles of accumulators per lane instead of one copy of every Gram entry
-// per lane, so occupancy stays at 2 blocks per CU.  The 8 waves' tiles are summed in LDS
-// in wave order at the end.  Requires nz <= 16.
+// A block of 8 waves stages batches of BR = 64 * floor(64 / ncol) rows of all ncol <= 64
+// columns in LDS (column-major, row stride BR + 1; double-buffered, one barrier per batch),
+// loading the next two batches into registers while the matrix cores consume the current
+// one.  The K-steps (4 rows each) of a batch are dealt to the waves round-robin; every
+// wave accumulates all MT 16-column tiles: 4 MT doubles of accumulators per lane instead
+// of one copy of every Gram entry per lane, so occupancy stays at 2 blocks per CU.  The 8
+// waves' tiles are summed in LDS in wave order at the end.  Requires nz <= 16.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaTile = kMaxCols * (kWave + 1);  // doubles per LDS tile buffer
 
 template <int MT>
 __global__ __launch_bounds__(512) void gram_mfma_kernel(PanelArgs a) {
   SmallState* st = a.st;
   if (a.gate && (st->h.done || a.panel > st->h.stop_panel)) return;
-  constexpr int NW = 8, BR = 64, LDT = BR + 1;
-  constexpr int SL = kMaxCols / NW;
+  constexpr int NW = 8, SL = 8;
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const int k = a.k, ncol = a.k + a.sw, nz = a.nz, z0 = ncol - nz;
+  // a batch is RB chunks of 64 rows of all ncol columns (ncol * RB <= 64 load items, so
+  // narrow reductions still keep 64 wave loads in flight); LDS row stride BR + 1
+  const int RB = kMaxCols / ncol;
+  const int BR = kWave * RB, LDT = BR + 1;
+  const int items = ncol * RB;
   const double* __restrict__ V = reinterpret_cast<const double*>(a.V);
   const int64_t ld = a.ld;
-  __shared__ double lt[2][kMaxCols][LDT];
+  __shared__ double lt[2][kMfmaTile];
 
   const int64_t rb = (int64_t)blockIdx.x * a.rows_per_block;
   const int64_t re = min(a.n, rb + a.rows_per_block);
-  int64_t colof[SL];
+  // load item t = wv + 8 sl: column c = t % ncol, 64-row chunk t / ncol of the batch
+  int64_t colbase[SL];
+  int rowoff[SL], ldsof[SL];
 #pragma unroll
   for (int sl = 0; sl < SL; ++sl) {
-    const int c = wv + NW * sl;
-    colof[sl] = ((c < k) ? (int64_t)c : (int64_t)a.wcol + (c - k)) * ld;
+    const int t = wv + NW * sl;
+    const int c = t % ncol, chunk = t / ncol;
+    colbase[sl] = ((c < k) ? (int64_t)c : (int64_t)a.wcol + (c - k)) * ld;
+    rowoff[sl] = chunk * kWave;
+    ldsof[sl] = c * LDT + chunk * kWave;
   }
-  double v[SL], vn[SL];
+  double v[SL], vn[SL], vnn[SL];
   auto load = [&](double (&dst)[SL], int64_t r0) {
-    const int64_t row = r0 + lane;
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
-      const int c = wv + NW * sl;
-      dst[sl] = (c < ncol && row < re) ? V[colof[sl] + row] : 0.0;
+      const int t = wv + NW * sl;
+      const int64_t row = r0 + rowoff[sl] + lane;
+      dst[sl] = (t < items && row < re) ? V[colbase[sl] + row] : 0.0;
     }
   };
   dbl4 acc[MT];
@@ -152,34 +163,40 @@ __global__ __launch_bounds__(512) void gram_mfma_kernel(PanelArgs a) {
   for (int mt = 0; mt < MT; ++mt) acc[mt] = dbl4{0.0, 0.0, 0.0, 0.0};
   const int li = lane & 15, lk = lane >> 4;
   const bool zok = li < nz;
+  const int ksteps = BR / 4;  // K-steps of 4 rows per batch, dealt to the waves round-robin
+  // prefetch depth 2: batches r0+BR and r0+2BR are in flight while r0 is consumed
   load(v, rb);
+  if (rb + BR < re) load(vn, rb + BR);
   int buf = 0;
   for (int64_t r0 = rb; r0 < re; r0 += BR) {
-    if (r0 + BR < re) load(vn, r0 + BR);
+    if (r0 + 2 * BR < re) load(vnn, r0 + 2 * BR);
+    double* T = lt[buf];
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
-      const int c = wv + NW * sl;
-      if (c < ncol) lt[buf][c][lane] = v[sl];
+      const int t = wv + NW * sl;
+      if (t < items) T[ldsof[sl] + lane] = v[sl];
     }
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const int row = (2 * wv + ks) * 4 + lk;
-      const double bv = zok ? lt[buf][z0 + li][row] : 0.0;
+    for (int ks = wv; ks < ksteps; ks += NW) {
+      const int row = ks * 4 + lk;
+      const double bv = zok ? T[(z0 + li) * LDT + row] : 0.0;
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
         const int c = mt * 16 + li;
-        const double av = (c < ncol) ? lt[buf][c][row] : 0.0;
+        const double av = (c < ncol) ? T[c * LDT + row] : 0.0;
         acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[mt], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int sl = 0; sl < SL; ++sl) v[sl] = vn[sl];
+    for (int sl = 0; sl < SL; ++sl) {
+      v[sl] = vn[sl];
+      vn[sl] = vnn[sl];
+    }
     buf ^= 1;
   }
   __syncthreads();
   // sum the 8 waves' partial tiles in wave order: red[w][c][z], c < 16 MT, z < 16
-  double* red = &lt[0][0][0];  // 8 x 64 x 16 doubles = 64 KiB fits in the two tiles
+  double* red = &lt[0][0];  // 8 x 64 x 16 doubles = 64 KiB fits in the two tiles
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll

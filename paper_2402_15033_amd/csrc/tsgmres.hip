@@ -84,9 +84,12 @@ struct Carve {
   }
 };
 
+constexpr int kReduceGroups = 32;  // first-level groups of the two-level cross-block reduction
+
 struct Common {
   SmallState* st;
   double* part1;  // per-block partial sums of the streaming kernels
+  double* part2;  // per-group partial sums (two-level reduction)
   size_t part1_n;
 };
 
@@ -95,7 +98,8 @@ size_t part1_count(int64_t n) {
 }
 
 size_t common_bytes(int64_t n) {
-  return align_up(sizeof(SmallState)) + align_up(part1_count(n) * sizeof(double));
+  return align_up(sizeof(SmallState)) + align_up(part1_count(n) * sizeof(double)) +
+         align_up((size_t)kReduceGroups * kMaxCols * kMaxS * sizeof(double));
 }
 
 Common carve_common(Carve& cv, int64_t n) {
@@ -103,6 +107,7 @@ Common carve_common(Carve& cv, int64_t n) {
   c.part1_n = part1_count(n);
   c.st = cv.take<SmallState>(1);
   c.part1 = cv.take<double>(c.part1_n);
+  c.part2 = cv.take<double>((size_t)kReduceGroups * kMaxCols * kMaxS);
   return c;
 }
 __global__ void zero_f64_kernel(double* p, int64_t n) {
@@ -120,45 +125,66 @@ __global__ void zero_f64_kernel(double* p, int64_t n) {
 // Per kernel class (TSG_KC_*): HIP events around every launch on the solve's stream,
 // folded into totals after each per-cycle synchronization.
 struct Timer {
-  bool on = false;
-  std::vector<hipEvent_t> pool;
-  std::vector<int> cls;
-  size_t used = 0;
+  bool on = false;  // time the launches enqueued now
+  struct Pair {
+    int cls;
+    double bytes;
+    hipEvent_t b, e;
+  };
+  std::vector<Pair> pairs;  // launches of the current enqueue (one cycle, or the captured graph)
+  std::vector<hipEvent_t> spare;
   double ms[16] = {0};
   int64_t count[16] = {0};
   double bytes[16] = {0};
+  hipError_t err = hipSuccess;  // first failed event call (reported by the caller)
   ~Timer() {
-    for (auto e : pool) (void)hipEventDestroy(e);
-  }
-  hipEvent_t next() {
-    if (used == pool.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      pool.push_back(e);
+    for (auto& p : pairs) {
+      (void)hipEventDestroy(p.b);
+      (void)hipEventDestroy(p.e);
     }
-    return pool[used++];
+    for (auto e : spare) (void)hipEventDestroy(e);
+  }
+  hipEvent_t make() {
+    if (!spare.empty()) {
+      hipEvent_t e = spare.back();
+      spare.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
   }
   void begin(hipStream_t s, int c, double nbytes) {
-    count[c] += 1;
-    bytes[c] += nbytes;
     if (!on) return;
-    hipEvent_t e = next();
-    if (e) (void)hipEventRecord(e, s);
-    cls.push_back(c);
+    Pair p{c, nbytes, make(), make()};
+    if (!p.b || !p.e) {
+      if (err == hipSuccess) err = hipErrorOutOfMemory;
+      (void)hipGetLastError();
+    } else {
+      note(hipEventRecord(p.b, s));
+    }
+    pairs.push_back(p);
   }
   void end(hipStream_t s) {
-    if (!on) return;
-    hipEvent_t e = next();
-    if (e) (void)hipEventRecord(e, s);
+    if (!on || pairs.empty()) return;
+    if (pairs.back().e) note(hipEventRecord(pairs.back().e, s));
   }
+  void note(hipError_t e) {
+    if (e == hipSuccess) return;
+    if (err == hipSuccess) err = e;
+    (void)hipGetLastError();  // keep the launch checks about launches
+  }
+  // after a stream synchronization: fold the pairs' elapsed times into the totals
   void harvest() {
-    if (!on) return;
-    for (size_t i = 0; i < cls.size(); ++i) {
+    for (auto& p : pairs) {
       float t = 0.f;
-      if (hipEventElapsedTime(&t, pool[2 * i], pool[2 * i + 1]) == hipSuccess) ms[cls[i]] += t;
+      if (p.b && p.e && hipEventElapsedTime(&t, p.b, p.e) == hipSuccess) ms[p.cls] += t;
+      count[p.cls] += 1;
+      bytes[p.cls] += p.bytes;
+      if (p.b) spare.push_back(p.b);
+      if (p.e) spare.push_back(p.e);
     }
-    cls.clear();
-    used = 0;
+    pairs.clear();
   }
 };
 
@@ -284,7 +310,8 @@ tsg_status run_step(const PanelCtx& p, const Step& st) {
     const bool gram = st.kind == PK_GRAM;
     a.nz = gram ? st.nprev + st.sw : st.sw;
     const bool mfma = gram && !p.f32;
-    const int br = mfma ? 64 : kWave * (gram ? gram_rpl(a.nz) : fused_rpl(st.sw));
+    const int br = mfma ? kWave * (kMaxCols / (st.k + st.sw))  // the MFMA kernel's batch height
+                        : kWave * (gram ? gram_rpl(a.nz) : fused_rpl(st.sw));
     int64_t tiles = cdiv(p.n, br);
     nb = (int)std::min<int64_t>(tiles, mfma ? kMaxMfmaBlocks : kMaxPanelBlocks);
     a.rows_per_block = cdiv(cdiv(p.n, nb), br) * br;
@@ -331,7 +358,15 @@ tsg_status run_step(const PanelCtx& p, const Step& st) {
   HIP_LAUNCH_CHECK();
   if (reduces) {
     if (p.timer) p.timer->begin(p.stream, TSG_KC_TAIL, 0.0);
-    hipLaunchKernelGGL(panel_tail_kernel, dim3(1), dim3(kTailThreads), 0, p.stream, a);
+    PanelArgs at = a;
+    if (nb > 2 * kReduceGroups) {  // two-level: many blocks sum the partials first
+      const int chunk = (int)cdiv(nb, kReduceGroups);
+      const int ng = (int)cdiv(nb, chunk);
+      hipLaunchKernelGGL(partial_reduce_kernel, dim3(ng), dim3(256), 0, p.stream, a, p.c.part2, chunk);
+      at.part1 = p.c.part2;
+      at.nblocks = ng;
+    }
+    hipLaunchKernelGGL(panel_tail_kernel, dim3(1), dim3(kTailThreads), 0, p.stream, at);
     if (p.timer) p.timer->end(p.stream);
     HIP_LAUNCH_CHECK();
   }
@@ -520,6 +555,8 @@ static tsg_status validate_params(int64_t n, const tsg_solve_params* p) {
   if (p->precision < 0 || p->precision > 1) return fail(TSG_ERR_INVALID_ARG, "bad precision");
   if (!(p->tol >= 0.0)) return fail(TSG_ERR_INVALID_ARG, "bad tol");
   if (p->max_iters < 0) return fail(TSG_ERR_INVALID_ARG, "bad max_iters");
+  if (p->timing < 0) return fail(TSG_ERR_INVALID_ARG, "bad timing %d", p->timing);
+  if (p->flags & ~TSG_FLAG_EAGER) return fail(TSG_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
   return TSG_OK;
 }
 
@@ -547,7 +584,8 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   const bool two = ortho == TSG_ORTHO_TWO_STAGE;
   const bool f32 = sizeof(T) == 4;
   Timer timer;
-  timer.on = p->timing != 0;
+  const bool timing = p->timing != 0;
+  const int64_t stride = p->timing > 1 ? p->timing : 1;  // time every stride-th cycle
   PanelCtx pc{V, ld, n, (int)sizeof(T), f32, c, s, &timer, 0};
 
   // basis parameters from the Gershgorin interval (Sec. VI uses the monomial basis)
@@ -612,69 +650,118 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   const double spmv_bytes = (double)(n + 1) * 4 + (double)A->nnz * (4 + sizeof(VT)) + 2.0 * n * sizeof(T);
   const double resid_bytes = (double)(n + 1) * 4 + (double)A->nnz * 12 + 2.0 * n * 8 + n * sizeof(T);
   hipEvent_t t0 = nullptr, t1 = nullptr;
-  if (timer.on) {
+  if (timing) {
     HIP_TRY(hipEventCreate(&t0));
     HIP_TRY(hipEventCreate(&t1));
     HIP_TRY(hipEventRecord(t0, s));
   }
 
-  auto mpk = [&](int col_in, int col_out, int i, int panel_idx) -> tsg_status {
-    timer.begin(s, TSG_KC_MPK, spmv_bytes);
-    hipLaunchKernelGGL((mpk_step_kernel<T, VT>), dim3(nbr), dim3(kRowBlock), 0, s, A->row_ptr, A->col,
-                       val, V + (int64_t)col_in * ld, V + (int64_t)col_out * ld, n, theta[i], sigma[i],
-                       c.st, panel_idx);
-    timer.end(s);
-    HIP_LAUNCH_CHECK();
-    return TSG_OK;
-  };
 
-  tsg_status result = TSG_OK;
-  for (;;) {
+  const bool g00_here = two && 1 + sstep > max_gram_nz(f32);
+  // Every launch of a restart cycle has the same arguments in every cycle (what changes --
+  // convergence, truncation after a breakdown, the iteration count -- lives in the device
+  // state), so one cycle is enqueued on stream q either directly or into a graph.
+  auto enqueue_cycle = [&](hipStream_t q) -> tsg_status {
+    pc.stream = q;
     // ---- restart residual r = b - A x, beta, convergence test (explicit, FP64)
-    timer.begin(s, TSG_KC_RESIDUAL, resid_bytes);
-    hipLaunchKernelGGL((residual_kernel<T>), dim3(nbr), dim3(kRowBlock), 0, s, A->row_ptr, A->col,
+    timer.begin(q, TSG_KC_RESIDUAL, resid_bytes);
+    hipLaunchKernelGGL((residual_kernel<T>), dim3(nbr), dim3(kRowBlock), 0, q, A->row_ptr, A->col,
                        A->val, x, b, V, n, c.st, c.part1);
-    hipLaunchKernelGGL(residual_tail_kernel, dim3(1), dim3(kTailThreads), 0, s, c.st,
+    hipLaunchKernelGGL(residual_tail_kernel, dim3(1), dim3(kTailThreads), 0, q, c.st,
                        (const double*)c.part1, nbr);
-    timer.end(s);
+    timer.end(q);
     HIP_LAUNCH_CHECK();
-    // ---- qhat_1 = r / beta (two-stage: the same pass gives G2(0,0) of the stored column)
+    // ---- qhat_1 = r / beta (two-stage: its G2(0,0) comes with the first panel's reduction
+    //      when column 0 and the panel fit one lean reduction, else from this pass)
     {
-      Step sc = upd_step(two ? PK_FUSED : PK_UPDATE, 0, 0, 1,
-                         PF_HAS_T | PF_STORE | (two ? PF_GRAM_W : 0), two ? TAIL_NORM0 : TAIL_NONE, -1, 0);
+      Step sc = upd_step(g00_here ? PK_FUSED : PK_UPDATE, 0, 0, 1,
+                         PF_HAS_T | PF_STORE | (g00_here ? PF_GRAM_W : 0), g00_here ? TAIL_NORM0 : TAIL_NONE,
+                         -1, 0);
       sc.kclass = TSG_KC_SCALE;
       TRY(run_step(pc, sc));
     }
     for (int j = 0; j < J; ++j) {
       const int k = j * sstep + 1;
-      for (int i = 0; i < sstep; ++i) TRY(mpk(k - 1 + i, k + i, i, j));
+      for (int i = 0; i < sstep; ++i) {
+        timer.begin(q, TSG_KC_MPK, spmv_bytes);
+        hipLaunchKernelGGL((mpk_step_kernel<T, VT>), dim3(nbr), dim3(kRowBlock), 0, q, A->row_ptr, A->col,
+                           val, V + (int64_t)(k - 1 + i) * ld, V + (int64_t)(k + i) * ld, n, theta[i],
+                           sigma[i], c.st, j);
+        timer.end(q);
+        HIP_LAUNCH_CHECK();
+      }
       // two-stage: the next panel's reduction covers this panel's stage-2 Gram block column
       // when both panels fit one lean reduction; otherwise the update is fused with it
       const bool lean2 = 2 * sstep <= max_gram_nz(f32);
       const bool covered = j < J - 1 && lean2;
-      const int nprev = (two && j > 0 && lean2) ? sstep : 0;
+      // previous panel's columns reduced along: column 0 for the first panel, else s
+      const int nprev = !two ? 0 : (j == 0 ? (g00_here ? 0 : 1) : (lean2 ? sstep : 0));
       TRY(panel_sequence(pc, ortho, k, sstep, nprev, !covered, j, k - 1));
     }
     // ---- stage 2 (two-stage) / projected least squares; counters
-    timer.begin(s, TSG_KC_CYCLE_END, 0.0);
-    hipLaunchKernelGGL(cycle_end_kernel, dim3(1), dim3(256), 0, s, c.st, two ? 1 : 0);
-    timer.end(s);
+    timer.begin(q, TSG_KC_CYCLE_END, 0.0);
+    hipLaunchKernelGGL(cycle_end_kernel, dim3(1), dim3(256), 0, q, c.st, two ? 1 : 0);
+    timer.end(q);
     HIP_LAUNCH_CHECK();
     // ---- x += V(:, 0:k_used) coef
-    timer.begin(s, TSG_KC_XUPDATE, (double)m * n * sizeof(T) + 16.0 * n);
-    hipLaunchKernelGGL((xupdate_kernel<T>), dim3(nbr), dim3(kRowBlock), 0, s, x, V, ld, n, c.st);
-    timer.end(s);
+    timer.begin(q, TSG_KC_XUPDATE, (double)m * n * sizeof(T) + 16.0 * n);
+    hipLaunchKernelGGL((xupdate_kernel<T>), dim3(nbr), dim3(kRowBlock), 0, q, x, V, ld, n, c.st);
+    timer.end(q);
     HIP_LAUNCH_CHECK();
+    return TSG_OK;
+  };
+
+  // graph mode: capture one cycle on a private stream, replay it on s.  A timed cycle is
+  // enqueued directly (its events bracket each launch; same kernels and arguments).
+  const bool use_graph = (p->flags & TSG_FLAG_EAGER) == 0;
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  tsg_status result = TSG_OK;
+  if (use_graph) {
+    hipError_t ge = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (ge == hipSuccess) ge = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (ge == hipSuccess) {
+      timer.on = false;
+      tsg_status cst = enqueue_cycle(cs);
+      ge = hipStreamEndCapture(cs, &graph);
+      if (cst != TSG_OK) result = cst;
+    }
+    if (ge == hipSuccess && result == TSG_OK) ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ge != hipSuccess && result == TSG_OK)
+      result = fail(TSG_ERR_HIP, "capture of a restart cycle failed: %s", hipGetErrorString(ge));
+  }
+  int64_t timed_cycles = 0;
+  for (int64_t cyc = 0; result == TSG_OK; ++cyc) {
+    timer.on = timing && cyc % stride == 0;
+    if (use_graph && !timer.on) {
+      e = hipGraphLaunch(exec, s);
+      if (e != hipSuccess) {
+        result = fail(TSG_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+        break;
+      }
+    } else {
+      result = enqueue_cycle(s);
+      if (result != TSG_OK) break;
+      timed_cycles += timer.on ? 1 : 0;
+    }
     e = hipMemcpyAsync(head, &c.st->h, sizeof(StateHead), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       result = fail(TSG_ERR_HIP, "cycle sync failed: %s", hipGetErrorString(e));
       break;
     }
+    if (timer.err != hipSuccess) {
+      result = fail(TSG_ERR_HIP, "timing event: %s", hipGetErrorString(timer.err));
+      break;
+    }
     timer.harvest();
     if (head->done) break;
   }
-  if (timer.on && result == TSG_OK) {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (timing && result == TSG_OK) {
     (void)hipEventRecord(t1, s);
     (void)hipEventSynchronize(t1);
     float tot = 0.f;
@@ -696,8 +783,9 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
     info->relres_est = h.est;
     info->status = st;
     info->truncated_cycles = h.truncated;
-    if (timer.on) {
+    if (timing) {
       info->ms_total = ms_total;
+      info->timed_cycles = timed_cycles;
       auto& T_ = timer;
       info->ms_spmv = T_.ms[TSG_KC_MPK];
       info->ms_ortho_reduce = T_.ms[TSG_KC_GRAM] + T_.ms[TSG_KC_GRAM_FIRST];
@@ -796,13 +884,18 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   PanelCtx pc{X, ldx, n, 8, false, c, st, nullptr, 1};
   // column 1 alone
   TRY(run_step(pc, gram_step(false, 0, 0, 1, 0, TAIL_SA_NORM, -1, 0)));
-  TRY(run_step(pc, upd_step(two ? PK_FUSED : PK_UPDATE, 0, 0, 1, PF_HAS_T | PF_STORE | (two ? PF_GRAM_W : 0),
-                            two ? TAIL_NORM0 : TAIL_NONE, -1, 0)));
+  // two-stage with panels: G2(0,0) comes with the first panel's reduction when column 0 and
+  // the first panel fit one lean reduction
+  const bool g00 = two && (k == 1 || 1 + std::min(s, k - 1) > max_gram_nz(false));
+  TRY(run_step(pc, upd_step(g00 ? PK_FUSED : PK_UPDATE, 0, 0, 1, PF_HAS_T | PF_STORE | (g00 ? PF_GRAM_W : 0),
+                            g00 ? TAIL_NORM0 : TAIL_NONE, -1, 0)));
   const bool lean2 = 2 * s <= max_gram_nz(false);
   for (int c0 = 1; c0 < k; c0 += s) {
     const int sw = std::min(s, k - c0);
     const bool last = c0 + sw >= k;
-    const int nprev = (two && c0 > 1 && lean2) ? s : 0;  // panels before the last have width s
+    // previous columns reduced along: column 0 for the first panel, else the previous panel
+    // (panels before the last have width s)
+    const int nprev = !two ? 0 : (c0 == 1 ? (g00 ? 0 : 1) : (lean2 ? s : 0));
     TRY(panel_sequence(pc, algo, c0, sw, nprev, last || !lean2, 0, 0));
   }
   if (two) {

@@ -209,6 +209,39 @@ def test_determinism(tsg):
     assert torch.equal(x1, x2)
 
 
+@pytest.mark.parametrize("ortho,prec", [("two_stage", "fp64"), ("bcgs_pip2", "fp64"),
+                                        ("bcgs2_cholqr2", "fp64"), ("cgs2", "fp64"),
+                                        ("two_stage", "fp32_ir")])
+def test_graph_replay_matches_eager(tsg, ortho, prec):
+    """One captured restart cycle replayed once per cycle (many replays, with the host's
+    read-back and synchronization between them, and directly launched timed cycles mixed
+    in) gives the eager launches' iterate bit for bit."""
+    _say("case graph vs eager", ortho, prec)
+    pr = W.make_problem("convdiff2d", 64, seed=3)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    b = _dev(pr["b"])
+    kw = dict(m=30, s=5, tol=1e-10, ortho=ortho, precision=prec, basis="shifted")
+    xe, ie = tsg.solve(A, b, graph=False, **kw)
+    assert ie.cycles >= 4
+    for timing in (0, 3):
+        _say("  graph, timing", timing)
+        xg, ig = tsg.solve(A, b, graph=True, timing=timing, **kw)
+        assert torch.equal(xe, xg)
+        assert (ig.iters, ig.cycles, ig.status) == (ie.iters, ie.cycles, ie.status)
+        assert ig.relres == ie.relres
+    # sampled timing: passes 0, 3, 6, ... are timed, with the same launches per pass as
+    # timing every pass of an eager solve.  A converged solve enqueues cycles + 1 passes:
+    # the last one computes the final residual, which stops it (the rest is gated off).
+    assert ig.timed_cycles == -(-(ie.cycles + 1) // 3)
+    _, it = tsg.solve(A, b, graph=False, timing=1, **kw)
+    assert it.timed_cycles == ie.cycles + 1
+    assert it.kernel_classes().keys() == ig.kernel_classes().keys()
+    for name, (_, cnt, by) in it.kernel_classes().items():  # every cycle has the same launches
+        _, cg, bg = ig.kernel_classes()[name]
+        assert cnt * ig.timed_cycles == cg * it.timed_cycles, name
+        assert by * ig.timed_cycles == bg * it.timed_cycles, name
+
+
 # ------------------------------------------------------------------------- mixed precision
 @pytest.mark.parametrize("kind,N,basis", [("laplace2d", 128, "shifted"), ("convdiff2d", 160, "shifted")])
 def test_mixed_precision_refinement(tsg, kind, N, basis):
