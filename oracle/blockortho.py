@@ -79,6 +79,35 @@ def bcgs_pip(Q: np.ndarray, V: np.ndarray, tol: float = 0.0):
     return Qnew, P, R
 
 
+def bcgs_pip_explicit(Q: np.ndarray, V: np.ndarray, tol: float = 0.0):
+    """BCGS-PIP, with an explicit-Gram second pass where the Pythagorean Gram fails.
+
+    The Pythagorean Gram G_V - P^T P loses all accuracy once [Q, V] is too ill-conditioned
+    for the working precision (the stability condition of BCGS-PIP, Sec. IV-C).  When its
+    Cholesky fails the pivot test, the projection is applied explicitly first,
+    Y = V - Q P1, and Y is orthogonalized by a second BCGS-PIP pass whose Gram has no
+    cancellation: P2 = Q^T Y, G = Y^T Y - P2^T P2, R = Chol(G), Qnew = (Y - Q P2) R^{-1},
+    so V = Q (P1 + P2) + Qnew R.  A pivot of the second pass fails when it is at most
+    tol * (Y^T Y)_jj (Y itself too ill-conditioned) or at most tol^2 * (V^T V)_jj (the
+    column is numerically in span(Q): the pivot is at the rounding level of V).
+    Returns (Qnew, P, R, used_second_pass).
+    """
+    try:
+        Qn, P, R = bcgs_pip(Q, V, tol)
+        return Qn, P, R, False
+    except CholeskyBreakdown:
+        pass
+    P1 = Q.T @ V
+    Y = V - Q @ P1
+    P2 = Q.T @ Y
+    GY = Y.T @ Y
+    G = GY - P2.T @ P2
+    thr = np.maximum(tol * np.diag(GY), tol * tol * np.diag(V.T @ V))
+    R = chol_upper(G, ref_diag=thr, tol=1.0 if tol > 0.0 else 0.0)
+    Qnew = right_solve_upper(Y - Q @ P2, R)
+    return Qnew, P1 + P2, R, True
+
+
 def bcgs_pip2(Q: np.ndarray, V: np.ndarray, tol: float = 0.0):
     """BCGS-PIP twice (two reductions).  Fig. 4b.
 

@@ -169,6 +169,7 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
     theta, sigma = basis_params(op, s, basis, shifts)
     J = m // s
     one_stage = None if ortho == "two_stage" else blockortho.ONE_STAGE[ortho]
+    stats = {"fallbacks": 0}  # stage-1 panels that needed the explicit second pass
 
     def cycle(op, r, beta, tol_abs):
         n = op.n
@@ -183,8 +184,9 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
             k = j * s + 1
             W, B = mpk(op, Qh[:, k - 1], theta, sigma)
             try:
-                if one_stage is None:
-                    Qn, P, R = blockortho.bcgs_pip(Qh[:, :k], W, PIVOT_TOL)  # stage 1
+                if one_stage is None:  # stage 1 (second pass only where PIP fails)
+                    Qn, P, R, fb = blockortho.bcgs_pip_explicit(Qh[:, :k], W, PIVOT_TOL)
+                    stats["fallbacks"] += int(fb)
                 else:
                     Qn, P, R = one_stage(Qh[:, :k], W, PIVOT_TOL)
             except CholeskyBreakdown:
@@ -234,6 +236,7 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
 
     out = _outer(op, b, x0, tol, max_iters, cycle, record)
     out["theta"], out["sigma"] = theta, sigma
+    out["fallbacks"] = stats["fallbacks"]
     return out
 
 

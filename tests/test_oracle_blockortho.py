@@ -159,3 +159,53 @@ def test_two_stage_on_glued_matrix(glued):
 def test_bcgs_pip2_on_glued_matrix(glued):
     Q, R = BO.orthogonalize(glued, 5, "bcgs_pip2")
     assert D.orth_error(Q) <= 1e-13 and D.repr_error(glued, Q, R) <= 1e-15
+
+
+def _nearly_dependent_panel(n, k, s, delta, seed):
+    """Q (n x k orthonormal) and V = Q C + delta Z with Z orthonormal and orthogonal to Q:
+    [Q, V] has condition number ~ 1/delta while V - Q Q^T V = delta Z is perfectly
+    conditioned."""
+    rng = np.random.default_rng(seed)
+    X, _ = np.linalg.qr(rng.standard_normal((n, k + s)))
+    Q, Z = X[:, :k], X[:, k:]
+    C = rng.standard_normal((k, s))
+    return Q, Q @ C + delta * Z
+
+
+def test_pip_explicit_second_pass_where_pip_fails():
+    """PIP's Gram G_V - P^T P cancels to rounding once kappa([Q, V]) ~ eps^-1/2 (Sec. IV-C);
+    the explicit second pass still yields the thin QR of [Q, V]: orthogonal to O(eps),
+    V = Q P + Qnew R to O(eps), R equal to the Householder factor's trailing block."""
+    n, k, s = 4000, 9, 5
+    Q, V = _nearly_dependent_panel(n, k, s, 1e-7, seed=11)
+    with pytest.raises(D.CholeskyBreakdown):
+        BO.bcgs_pip(Q, V, 1e-12)
+    Qn, P, R, used = BO.bcgs_pip_explicit(Q, V, 1e-12)
+    assert used
+    Qf = np.hstack([Q, Qn])
+    assert D.orth_error(Qf) <= 1e-13
+    assert np.linalg.norm(V - Q @ P - Qn @ R) / np.linalg.norm(V) <= 1e-15
+    _, Rh = D.householder_qr(np.hstack([Q, V]))
+    Rb = Rh[k:, k:]
+    assert np.linalg.norm(R - Rb) / np.linalg.norm(Rb) <= 1e-8  # O(eps kappa), kappa ~ 1e7
+    # a well-conditioned panel takes the one-pass path and gives PIP's result
+    Q2, V2 = _nearly_dependent_panel(n, k, s, 1.0, seed=12)
+    Qa, Pa, Ra = BO.bcgs_pip(Q2, V2, 1e-12)
+    Qb, Pb, Rb2, used2 = BO.bcgs_pip_explicit(Q2, V2, 1e-12)
+    assert not used2 and np.array_equal(Qa, Qb) and np.array_equal(Ra, Rb2)
+
+
+def test_pip_explicit_second_pass_rejects_dependent_columns():
+    """A column that is in span(Q) up to rounding fails the second pass's tol^2 test
+    (its pivot is at the rounding level of V) instead of being normalized noise."""
+    n, k, s = 4000, 9, 5
+    Q, V = _nearly_dependent_panel(n, k, s, 0.0, seed=13)
+    with pytest.raises(D.CholeskyBreakdown) as e:
+        BO.bcgs_pip_explicit(Q, V, 1e-12)
+    assert e.value.index == 0
+    # one dependent column in the middle of an otherwise healthy panel
+    Q, V = _nearly_dependent_panel(n, k, s, 1e-3, seed=14)
+    V[:, 2] = Q @ np.arange(1.0, k + 1.0)
+    with pytest.raises(D.CholeskyBreakdown) as e:
+        BO.bcgs_pip_explicit(Q, V, 1e-12)
+    assert e.value.index == 2

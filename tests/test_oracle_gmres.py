@@ -192,3 +192,21 @@ def test_shifted_basis_and_s10_converge():
     for basis in ("monomial", "shifted"):
         out = G.sstep_gmres(pr["A"], pr["b"], m=60, s=10, tol=1e-10, basis=basis)
         assert out["converged"] and out["relres"] <= 1e-10
+
+
+def test_monomial_s10_takes_the_explicit_second_pass():
+    """With the monomial basis at s = 10 the panels [Q, W] exceed PIP's stability limit
+    (kappa ~ 1e7, Sec. IV-C): stage 1 takes the explicit second pass on some panels and the
+    solve still meets the explicit residual and error gates."""
+    pr = W.make_problem("laplace2d", 64, seed=0)
+    out = G.sstep_gmres(pr["A"], pr["b"], m=60, s=10, tol=1e-10, basis="monomial")
+    assert out["fallbacks"] >= 1
+    assert out["converged"] and out["relres"] <= 1e-10
+    relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], out["x"])) / np.linalg.norm(pr["b"])
+    assert relres <= 1e-10
+    lmin, lmax = W.laplace_extreme_eigs(64, 2)
+    xt = pr["x_true"]
+    assert np.linalg.norm(out["x"] - xt) / np.linalg.norm(xt) <= 2e-10 * lmax / lmin
+    # the shifted basis keeps every panel inside the limit: no second pass
+    out2 = G.sstep_gmres(pr["A"], pr["b"], m=60, s=10, tol=1e-10, basis="shifted")
+    assert out2["fallbacks"] == 0
