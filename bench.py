@@ -60,7 +60,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--N", type=int, default=2048, help="grid side of the 2D Laplace problem")
+    ap.add_argument("--problem", default="laplace2d", choices=["laplace2d", "laplace3d", "convdiff2d"])
+    ap.add_argument("--N", type=int, default=None,
+                    help="grid side (default 2048 in 2D, 160 in 3D)")
+    ap.add_argument("--basis", default="monomial", choices=["monomial", "shifted"])
     ap.add_argument("--s", type=int, default=5)
     ap.add_argument("--m", type=int, default=60)
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -95,15 +98,19 @@ def main():
 
     dev = torch.device("cuda:0")
     tsg.load_library()
-    N = args.N
-    log(f"[bench] building 2D Laplace {N}x{N}")
-    pr = W.make_problem("laplace2d", N, seed=0)
+    N = args.N or (160 if args.problem == "laplace3d" else 2048)
+    desc = {"laplace2d": f"2D Laplace 5-point {N}x{N}", "laplace3d": f"3D Laplace 7-point {N}^3",
+            "convdiff2d": f"2D convection-diffusion upwind {N}x{N}"}[args.problem]
+    log(f"[bench] building {desc}")
+    pr = W.make_problem(args.problem, N, seed=0)
+    if args.problem == "convdiff2d":
+        desc += f" (Pe={pr['meta']['pe']:.2f}, theta={pr['meta']['theta']:.3f})"
     Ah = pr["A"]
     A = tsg.CSRMatrix.from_host(Ah, device=dev)
     b = torch.as_tensor(pr["b"], device=dev)
     x = torch.zeros_like(b)
     kw = dict(m=args.m, s=args.s, tol=args.tol, ortho=args.ortho, precision=args.precision,
-              graph=not args.eager)
+              basis=args.basis, graph=not args.eager)
     need = tsg.binding.solve_workspace_bytes(A, m=args.m, s=args.s, ortho=args.ortho,
                                              precision=args.precision)
     ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
@@ -189,11 +196,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"2D Laplace 5-point {N}x{N} (n={Ah.n}, nnz={Ah.nnz}) CSR, "
+        "config": {"workload": f"{desc} (n={Ah.n}, nnz={Ah.nnz}) CSR, "
                                f"x_true~U(-1,1) seed 0, x0=0; s-step GMRES m={args.m} s={args.s} "
-                               f"{args.ortho} (s_hat=m), tol={args.tol:g}, {args.precision}",
+                               f"{args.ortho} (s_hat=m), {args.basis} basis, tol={args.tol:g}, "
+                               f"{args.precision}",
+                   "problem": args.problem, "N": N,
                    "n": Ah.n, "nnz": Ah.nnz, "m": args.m, "s": args.s, "ortho": args.ortho,
-                   "precision": args.precision, "tol": args.tol},
+                   "basis": args.basis, "precision": args.precision, "tol": args.tol},
         "time_to_solution_s": round(elapsed / args.steps, 4),
         "iters": int(info.iters), "cycles": int(info.cycles),
         "relres_device": info.relres, "relres_host_check": relres_host,
@@ -232,7 +241,7 @@ def main():
             torch.cuda.synchronize()
             t = time.perf_counter()
             _, ci = tsg.solve(A, b, x, workspace=None, timing=True, m=args.m, s=args.s, tol=args.tol,
-                              ortho=o, precision=args.precision, graph=not args.eager)
+                              ortho=o, precision=args.precision, basis=args.basis, graph=not args.eager)
             torch.cuda.synchronize()
             t = time.perf_counter() - t
             cmp[o] = {"time_to_solution_s": round(t, 4), "iters": int(ci.iters), "relres": ci.relres,
@@ -281,13 +290,14 @@ def main():
         op = S.Operator(Ah)
         t = time.perf_counter()
         ref = G.sstep_gmres(op, pr["b"], m=args.m, s=args.s, tol=args.tol, ortho=args.ortho
-                            if args.ortho != "cgs2" else "two_stage", max_iters=args.cpu_cycles * args.m)
+                            if args.ortho != "cgs2" else "two_stage", basis=args.basis,
+                            max_iters=args.cpu_cycles * args.m)
         t = time.perf_counter() - t
         t_cycle = t / max(ref["cycles"], 1)
         cpu_solves_per_s = 1.0 / (t_cycle * max(info.cycles, 1))
         out["cpu_baseline"] = {"value": cpu_solves_per_s, "unit": "solves/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": f"{ref['cycles']} restart cycle(s) of the same {N}x{N} solve "
+                               "sample": f"{ref['cycles']} restart cycle(s) of the same {desc} solve "
                                          f"({t:.1f} s, {t_cycle:.2f} s/cycle), scaled by the "
                                          f"{info.cycles} cycles the GPU solve needed; numpy BLAS on "
                                          f"{cores} threads, scipy SpMV single-threaded"}

@@ -45,6 +45,9 @@ typedef enum {
  *   TWO_STAGE      Sec. V, Fig. 5 with s_hat = m: one BCGS-PIP per s-column panel
  *                  (stage 1), one CholQR of the m+1 columns at the end of the cycle
  *                  (stage 2).  One global reduction per panel plus one per cycle.
+ *                  A panel whose Pythagorean Gram fails the pivot test (beyond the
+ *                  PIP stability limit of Sec. IV-C) is projected explicitly and
+ *                  orthogonalized by a second PIP pass (one more reduction).
  *   BCGS_PIP2      Sec. IV-C, Fig. 4b (two reductions per panel).
  *   BCGS2_CHOLQR2  Sec. IV-B, Fig. 2b with CholQR2 then CholQR (five per panel).
  *   CGS2           standard GMRES(m), classical Gram-Schmidt twice, one vector per
@@ -108,7 +111,9 @@ enum {
   TSG_KC_XUPDATE = 7,    /* x += V coef                                                   */
   TSG_KC_RESIDUAL = 8,   /* r = b - A x and its tail                                      */
   TSG_KC_SCALE = 9,      /* first basis vector r / beta                                   */
-  TSG_KC_COUNT = 10
+  TSG_KC_FALLBACK = 10,  /* two-stage explicit second pass (its launches return at entry
+                            unless a panel needs it; no bytes are attributed)            */
+  TSG_KC_COUNT = 11
 };
 
 typedef struct {
@@ -127,6 +132,8 @@ typedef struct {
   int64_t kc_launches[16]; /* launches that did work                                      */
   double kc_bytes[16];     /* algorithmic bytes (sum over launches)                       */
   int64_t timed_cycles;    /* restart cycles whose launches were timed                    */
+  int64_t pip_fallbacks;   /* two-stage: stage-1 panels whose Pythagorean Gram failed the
+                              pivot test and took the explicit second pass              */
 } tsg_solve_info;
 
 typedef struct tsg_csr_s* tsg_csr;

@@ -46,11 +46,11 @@ class _Info(C.Structure):
                 ("bytes_ortho_reduce", C.c_double), ("bytes_ortho_update", C.c_double),
                 ("bytes_spmv", C.c_double), ("kc_ms", C.c_double * 16),
                 ("kc_launches", C.c_int64 * 16), ("kc_bytes", C.c_double * 16),
-                ("timed_cycles", C.c_int64)]
+                ("timed_cycles", C.c_int64), ("pip_fallbacks", C.c_int64)]
 
 
 KERNEL_CLASSES = ["mpk", "gram", "gram_first", "update", "fused", "tail", "cycle_end", "xupdate",
-                  "residual", "scale"]
+                  "residual", "scale", "fallback"]
 
 
 @dataclass
@@ -78,6 +78,7 @@ class SolveInfo:
     kc_launches: tuple = ()
     kc_bytes: tuple = ()
     timed_cycles: int = 0
+    pip_fallbacks: int = 0
 
     def kernel_classes(self) -> dict:
         """{class: (ms, launches, algorithmic bytes)} for the classes that ran (timing mode)."""

@@ -151,6 +151,7 @@ __global__ __launch_bounds__(kTailThreads) void residual_tail_kernel(SmallState*
       st->identity_t = 0;
       st->h.stop_panel = 1 << 30;
       st->h.k_used = st->m;
+      st->h.refine = 0;
     }
   }
   __syncthreads();

@@ -37,6 +37,7 @@ enum TailOp : int {
   TAIL_NORM0,      // two-stage: G2(0,0) <- q0^T q0
   TAIL_SA_NORM,    // stand-alone: r00 = ||x0||, T = 1/r00
   TAIL_PIP,        // BCGS-PIP Cholesky; two-stage stage 1 (+ Hessenberg block)
+  TAIL_PIP_FB,     // two-stage stage 1: explicit second pass after a failed PIP pivot
   TAIL_G2COL,      // two-stage: block column of the stage-2 Gram
   TAIL_PIP2_A,     // BCGS-PIP2 first pass
   TAIL_PIP2_B,     // BCGS-PIP2 second pass (+ Hessenberg block, Givens)
@@ -61,7 +62,8 @@ struct PanelArgs {
   int32_t flags;
   int32_t tail;
   int32_t nblocks;
-  int32_t gate;      // return at entry when the solve is done or panel > stop_panel
+  int32_t gate;      // 1: return at entry when the solve is done or panel > stop_panel;
+                     // 2: also unless this panel asked for the explicit second pass
   int32_t standalone;// tails assemble an R factor (st->Hh) instead of Hessenberg/Givens
   int32_t kkeep;     // Krylov vectors kept if this panel breaks down (solver mode)
   int32_t panel;     // index of the panel within the cycle (-1: cycle set-up)
@@ -70,6 +72,12 @@ struct PanelArgs {
   SmallState* st;
   double* part1;     // per-block partial Grams, nblocks x (k+sw)*sw
 };
+
+__device__ __forceinline__ bool gated_off(const PanelArgs& a, const SmallState* st) {
+  if (!a.gate) return false;
+  if (st->h.done || a.panel > st->h.stop_panel) return true;
+  return a.gate == 2 && st->h.refine != a.panel + 1;
+}
 
 // ----------------------------------------------------------------------------- tails
 // Called by every thread of the tail block with the reduced Gram sred ((k+sw) x nz, entry
@@ -108,9 +116,14 @@ __device__ void tail_check(SmallState* st, int ncols, int panel) {
 }
 
 // Pythagorean Gram G = Gw - P^T P (P = sred rows 0..k-1, Gw = rows k..k+s-1) and its
-// Cholesky factor into R (ld kMaxS).  Returns the failing pivot or -1.
-__device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, double* R) {
+// Cholesky factor into R (ld kMaxS).  A pivot fails when it is at most pivot_tol * Gw_jj,
+// or, for the explicit second pass (second = true, the panel holds Y = W - Q P1), at most
+// max(pivot_tol * Gw_jj, pivot_tol^2 * refW_j) with refW the raw Gram diagonal of W.
+// Returns the failing pivot or -1.
+__device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, double* R,
+                             bool second = false) {
   const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
+  const double tol = a.st->pivot_tol;
   __shared__ double sG[kMaxS * kMaxS], sRef[kMaxS];
   for (int idx = tid; idx < k * s; idx += nt) {
     int c = idx % k, j = idx / k;
@@ -121,10 +134,13 @@ __device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, 
     double v = red(a, sred, k + i, j);
     for (int c = 0; c < k; ++c) v -= red(a, sred, c, i) * red(a, sred, c, j);
     sG[i + j * kMaxS] = v;
-    if (i == j) sRef[i] = red(a, sred, k + i, j);
+    if (i == j) {
+      const double d = red(a, sred, k + i, j);
+      sRef[i] = second ? fmax(tol * d, tol * tol * a.st->refW[i]) : tol * d;
+    }
   }
   __syncthreads();
-  return block_chol_upper(sG, kMaxS, R, kMaxS, s, sRef, a.st->pivot_tol);
+  return block_chol_upper(sG, kMaxS, R, kMaxS, s, sRef, 1.0);
 }
 
 // Plain Cholesky of rows r0..r0+s-1 of sred (a q^T q Gram) into R (ld kMaxS).
@@ -203,9 +219,39 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
       }
       __syncthreads();
       int f = tail_pip_chol(a, sred, st->Pcur, sR);
-      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      if (f >= 0) {
+        if (a.standalone) { tail_breakdown(a, a.kkeep); break; }
+        // The Pythagorean Gram has cancelled to rounding: apply the projection
+        // explicitly (the next update computes Y = W - Q P1 with T = I) and let the
+        // gated second pass orthogonalize Y.
+        for (int idx = tid; idx < k * s; idx += nt) {
+          int c = idx % k, j = idx / k;
+          st->P1[c + j * kLd] = st->Pcur[c + j * kLd];
+        }
+        for (int j = tid; j < s; j += nt) st->refW[j] = red(a, sred, k + j, j);
+        if (tid == 0) {
+          st->identity_t = 1;
+          st->h.refine = a.panel + 1;
+          st->h.fallbacks += 1;
+        }
+        __syncthreads();
+        break;
+      }
       tail_set_tinv(st, sR, s);
       tail_emit_panel(a, st->Pcur, sR, false);
+    } break;
+    case TAIL_PIP_FB: {
+      // second pass on the panel Y = W - Q P1: P2 = Q^T Y, R = Chol(Y^T Y - P2^T P2);
+      // V_panel = Q (P1 + P2) + Q_new R
+      int f = tail_pip_chol(a, sred, st->Pcur, sR, true);
+      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      tail_set_tinv(st, sR, s);
+      for (int idx = tid; idx < k * s; idx += nt) {
+        int c = idx % k, j = idx / k;
+        sP[c + j * kLd] = st->P1[c + j * kLd] + st->Pcur[c + j * kLd];
+      }
+      __syncthreads();
+      tail_emit_panel(a, sP, sR, false);
     } break;
     case TAIL_G2COL: {
       for (int idx = tid; idx < (k + s) * s; idx += nt) {
@@ -361,7 +407,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
 template <typename T, int S, int RPL>
 __global__ __launch_bounds__(512) void panel_kernel(PanelArgs a) {
   SmallState* st = a.st;
-  if (a.gate && (st->h.done || a.panel > st->h.stop_panel)) return;
+  if (gated_off(a, st)) return;
   constexpr int NW = 8;
   constexpr int BR = kWave * RPL;  // rows per batch
   const int lane = threadIdx.x & (kWave - 1);
@@ -525,7 +571,7 @@ __global__ __launch_bounds__(512) void panel_kernel(PanelArgs a) {
 // part2[g * E + e].  The tail then sums the few group partials in group order.
 __global__ __launch_bounds__(256) void partial_reduce_kernel(PanelArgs a, double* part2, int chunk) {
   const SmallState* st = a.st;
-  if (a.gate && (st->h.done || a.panel > st->h.stop_panel)) return;
+  if (gated_off(a, st)) return;
   const int E = (a.k + a.sw) * a.nz;
   const int b0 = blockIdx.x * chunk, b1 = min(a.nblocks, b0 + chunk);
   for (int e = threadIdx.x; e < E; e += blockDim.x) {
@@ -539,7 +585,7 @@ __global__ __launch_bounds__(256) void partial_reduce_kernel(PanelArgs a, double
 // order and runs the FP64 tail (Cholesky, Hessenberg block, Givens, ...).
 __global__ __launch_bounds__(kTailThreads) void panel_tail_kernel(PanelArgs a) {
   SmallState* st = a.st;
-  if (a.gate && (st->h.done || a.panel > st->h.stop_panel)) return;
+  if (gated_off(a, st)) return;
   __shared__ double sred[kMaxCols * kMaxS];
   __shared__ double scratch[kTailThreads];
   const int E = (a.k + a.sw) * a.nz;

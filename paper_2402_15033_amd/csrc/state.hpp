@@ -18,6 +18,8 @@ struct StateHead {
   double relres;         // explicit relative residual at the last check
   double est;            // implicit relative residual estimate at the end of the last cycle
   int32_t truncated;     // cycles truncated by a Cholesky breakdown
+  int32_t refine;        // panel + 1 of the panel whose stage-1 PIP needs the explicit pass
+  int32_t fallbacks;     // stage-1 panels that took the explicit second pass (all cycles)
   int32_t pad;
 };
 
@@ -42,6 +44,7 @@ struct SmallState {
   double R1[kMaxS * kMaxS];   // first-pass triangular factor
   double Ra[kMaxS * kMaxS];   // accumulated CholQR factor (BCGS2 + CholQR2)
   double P2[kLd * kMaxS];     // second-pass projection coefficients
+  double refW[kMaxS];         // raw Gram diagonal of the panel whose PIP pass failed
   // Givens state of the one-stage variants and of standard GMRES
   double gc[kLd], gs[kLd], gg[kLd + 1];
   double Rg[kLd * kLd];       // Givens-triangularized Hessenberg

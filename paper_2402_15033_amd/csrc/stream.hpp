@@ -18,7 +18,7 @@ namespace tsg {
 template <typename T, int NZ, int NW, int RPL>
 __global__ __launch_bounds__(NW * kWave) void gram_kernel(PanelArgs a) {
   SmallState* st = a.st;
-  if (a.gate && (st->h.done || a.panel > st->h.stop_panel)) return;
+  if (gated_off(a, st)) return;
   constexpr int SL = kMaxCols / NW;  // column slots per wave
   constexpr int BR = kWave * RPL;
   const int lane = threadIdx.x & (kWave - 1);
@@ -122,7 +122,7 @@ constexpr int kMfmaTile = kMaxCols * (kWave + 1);  // doubles per LDS tile buffe
 template <int MT>
 __global__ __launch_bounds__(512) void gram_mfma_kernel(PanelArgs a) {
   SmallState* st = a.st;
-  if (a.gate && (st->h.done || a.panel > st->h.stop_panel)) return;
+  if (gated_off(a, st)) return;
   constexpr int NW = 8, SL = 8;
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(512) void gram_mfma_kernel(PanelArgs a) {
 template <typename T, int S>
 __global__ __launch_bounds__(256) void update_kernel(PanelArgs a) {
   const SmallState* st = a.st;
-  if (a.gate && (st->h.done || a.panel > st->h.stop_panel)) return;
+  if (gated_off(a, st)) return;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.n) return;
   const int k = a.k, sw = a.sw;

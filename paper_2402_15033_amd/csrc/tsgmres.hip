@@ -331,7 +331,8 @@ tsg_status run_step(const PanelCtx& p, const Step& st) {
   if (reduces && (size_t)nb * (size_t)((st.k + st.sw) * a.nz) > p.c.part1_n)
     return fail(TSG_ERR_WORKSPACE, "internal: reduction partials (%d blocks x %d) exceed the buffer", nb,
                 (st.k + st.sw) * a.nz);
-  if (p.timer) p.timer->begin(p.stream, kc, cols * (double)p.n * p.elem);
+  const bool fb = kc == TSG_KC_FALLBACK;
+  if (p.timer) p.timer->begin(p.stream, kc, fb ? 0.0 : cols * (double)p.n * p.elem);
   switch (st.kind) {
     case PK_GRAM:
       if (p.f32) {
@@ -357,7 +358,7 @@ tsg_status run_step(const PanelCtx& p, const Step& st) {
   if (p.timer) p.timer->end(p.stream);
   HIP_LAUNCH_CHECK();
   if (reduces) {
-    if (p.timer) p.timer->begin(p.stream, TSG_KC_TAIL, 0.0);
+    if (p.timer) p.timer->begin(p.stream, fb ? TSG_KC_FALLBACK : TSG_KC_TAIL, 0.0);
     PanelArgs at = a;
     if (nb > 2 * kReduceGroups) {  // two-level: many blocks sum the partials first
       const int chunk = (int)cdiv(nb, kReduceGroups);
@@ -417,12 +418,21 @@ tsg_status panel_sequence(const PanelCtx& p, int ortho, int k, int sw, int nprev
   const int c0 = k;
   switch (ortho) {
     case TSG_ORTHO_TWO_STAGE: {
-      TRY(run_step(p, gram_step(p.f32, k, c0, sw, nprev, TAIL_PIP, j, kkeep)));
-      if (fuse_update) {
-        TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W,
-                                 TAIL_G2COL, j, kkeep)));
-      } else {
-        TRY(run_step(p, upd_step(PK_UPDATE, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
+      // stage-1 BCGS-PIP; in solver mode followed by the explicit second pass, whose
+      // launches return at entry unless this panel's PIP pivot failed (gate 2)
+      const int passes = p.standalone ? 1 : 2;
+      for (int pass = 0; pass < passes; ++pass) {
+        const int gate = pass == 0 ? 1 : 2;
+        Step g = gram_step(p.f32, k, c0, sw, pass == 0 ? nprev : 0, pass == 0 ? TAIL_PIP : TAIL_PIP_FB, j,
+                           kkeep, gate);
+        if (pass == 1) g.kclass = TSG_KC_FALLBACK;
+        TRY(run_step(p, g));
+        Step u = fuse_update ? upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W,
+                                        TAIL_G2COL, j, kkeep)
+                             : upd_step(PK_UPDATE, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep);
+        u.gate = gate;
+        if (pass == 1) u.kclass = TSG_KC_FALLBACK;
+        TRY(run_step(p, u));
       }
     } break;
     case TSG_ORTHO_BCGS_PIP2:
@@ -783,6 +793,7 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
     info->relres_est = h.est;
     info->status = st;
     info->truncated_cycles = h.truncated;
+    info->pip_fallbacks = h.fallbacks;
     if (timing) {
       info->ms_total = ms_total;
       info->timed_cycles = timed_cycles;

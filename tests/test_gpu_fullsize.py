@@ -91,3 +91,21 @@ def test_ortho_bench_block(tsg):
     assert orth <= 2e-12
     assert rep <= 1e-14
     assert rerr <= 1e-12
+
+
+def test_mixed_precision_convdiff2048(tsg):
+    """The mixed-precision form on 2D convection-diffusion 2048^2: FP32 basis, SpMV and
+    tall-skinny products, FP64 Cholesky / least squares / outer residual.  Late in the solve
+    the residual is smooth, the FP32 Pythagorean Gram of the first panels cancels past its
+    pivot test, and those panels take the explicit second pass; the final residual gate is
+    the FP64 one."""
+    _say("case fullsize mixed convdiff")
+    pr = W.make_problem("convdiff2d", 2048, seed=0)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    b = torch.as_tensor(pr["b"], device="cuda")
+    x, info = tsg.solve(A, b, m=60, s=5, tol=1e-10, basis="shifted", precision="fp32_ir")
+    xg = x.cpu().numpy()
+    relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], xg)) / np.linalg.norm(pr["b"])
+    _say(f"  iters {info.iters} cycles {info.cycles} fallbacks {info.pip_fallbacks} "
+         f"truncated {info.truncated_cycles} relres {relres:.3e}")
+    assert info.converged and relres <= 1e-10

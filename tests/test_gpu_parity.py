@@ -165,6 +165,22 @@ def test_solve_shifted_basis_s10(tsg):
     assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
 
 
+def test_solve_monomial_s10_explicit_second_pass(tsg):
+    """Panels beyond PIP's stability limit take the explicit second pass on both sides:
+    same panels, same iteration count, same iterate."""
+    _say("case solve monomial s10 second pass")
+    pr = W.make_problem("laplace2d", 64, seed=0)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=60, s=10, tol=1e-10, basis="monomial")
+    ref = G.sstep_gmres(pr["A"], pr["b"], m=60, s=10, tol=1e-10, basis="monomial")
+    xg = x.cpu().numpy()
+    _say(f"  fallbacks gpu {info.pip_fallbacks} oracle {ref['fallbacks']}; iters {info.iters} {ref['iters']}")
+    assert ref["fallbacks"] >= 1
+    assert info.converged and info.iters == ref["iters"] and info.cycles == ref["cycles"]
+    assert info.pip_fallbacks == ref["fallbacks"]
+    assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
+
+
 def test_solve_tiny_system_with_breakdown(tsg):
     """n = 144 converges inside a cycle; the two-stage cycle truncates at the Cholesky
     breakdown (numerically invariant Krylov space) on both sides."""
