@@ -153,16 +153,14 @@ def main():
             a[2] += cby
     elem = "double" if args.precision == "fp64" else "float"
     st_ = lambda w: w if w <= 6 else (8 if w <= 8 else (10 if w <= 10 else (12 if w <= 12 else 16)))
-    nzt = lambda w: w if w <= 6 else (8 if w <= 8 else 10)
     s_ = args.s
+    nt2 = 1 if 2 * args.s <= 16 else 2
     names = {
         "mpk": f"mpk_step_kernel<{elem}, {elem}>",
-        "gram": ("gram_mfma_kernel<1..4>" if elem == "double"
-                 else f"gram_kernel<{elem}, {nzt(2 * s_)}, 8, {2 if nzt(2 * s_) <= 6 else 1}>"),
-        "gram_first": ("gram_mfma_kernel<1>" if elem == "double"
-                       else f"gram_kernel<{elem}, {nzt(s_)}, 8, {2 if nzt(s_) <= 6 else 1}>"),
+        "gram": f"gram_mfma_kernel<{elem}, 1..4, {nt2}>",
+        "gram_first": f"gram_mfma_kernel<{elem}, {(args.s + 16) // 16}, {(args.s + 16) // 16}>",
         "update": f"update_kernel<{elem}, {st_(s_)}>",
-        "fused": f"panel_kernel<{elem}, {st_(s_)}, {2 if st_(s_) <= 6 else 1}>",
+        "fused": f"panel_mfma_kernel<{elem}, 4, {s_ if s_ in (1, 2, 4, 5, 8, 10, 16) else 16}>",
     }
     streaming = {c: v for c, v in classes.items() if c in names and v[0] > 0}
     dom = max(streaming, key=lambda c: streaming[c][0])

@@ -10,6 +10,7 @@ constexpr int kWave = 64;
 constexpr int kLd = 64;      // leading dimension of every small matrix in SmallState
 constexpr int kMaxCols = 64; // max basis columns (m + 1) and max tall-skinny block width
 constexpr int kMaxS = 16;    // max step size
+constexpr int kMaxNz = 32;   // max right-hand columns of a lean Gram reduction (2 kMaxS)
 constexpr int kTailThreads = 1024;  // threads of the one-block tail kernels
 
 // Relative pivot threshold of the Cholesky factorizations inside a restart cycle:

@@ -1,23 +1,16 @@
-// Streaming panel kernel: the tall-skinny products of every block orthogonalization
-// scheme (Sec. IV-V), followed by a one-block FP64 "tail" kernel.
+// Panel steps of every block orthogonalization scheme (Sec. IV-V): the arguments shared
+// by the streaming kernels (gram_mfma_kernel, panel_mfma_kernel, update_kernel), and the
+// one-block FP64 "tail" that follows a reduction.
 //
-// One launch streams the rows of the column-major basis V once and, per row r, forms
+// A streaming launch passes once over the rows of the column-major basis V and, per row r,
+// forms some of
 //     y  = W(r,:) - Q(r,:) P          (PF_HAS_P; else y = W(r,:))
 //     q  = y T                        (PF_HAS_T, T upper triangular; else q = y)
 //     W(r,:) <- q                     (PF_STORE, in place)
 //     G += [Q(r,:), q]^T q            (PF_GRAM_Q: Q rows, PF_GRAM_W: q rows)
-// where Q = V(:, 0:k) and W = V(:, wcol:wcol+sw).  The Gram G ((k+sw) x sw) is
-// reduced across lanes and waves in registers; each block writes its partial, and
-// panel_tail_kernel sums the partials in a fixed order and runs the tail (Cholesky of
-// the Pythagorean Gram, Hessenberg block, Givens, ...).
-//
-// Mapping (wave64, 8 waves = 512 threads per block): a block owns a contiguous range
-// of rows; each lane owns one row per batch of 64*RPL rows.  The k+sw columns are
-// dealt to the 8 waves round-robin (column c -> wave c % 8), so every column is read
-// from HBM exactly once per launch with fully coalesced 512-byte wave accesses, and
-// each wave keeps the Gram rows of its own columns in registers for the whole launch.
-// Partial projections y_g = Q_g(r,:) P_g and the panel values W(r,:) are exchanged
-// through LDS so that every wave can form q for its Gram rows.
+// where Q = V(:, 0:k) and W = V(:, wcol:wcol+sw).  Each block writes its partial Gram;
+// panel_tail_kernel sums the partials in a fixed order and runs the tail (Cholesky of the
+// Pythagorean Gram, Hessenberg block, Givens, ...).
 #pragma once
 
 #include "small.hpp"
@@ -403,169 +396,6 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
   }
 }
 
-// ----------------------------------------------------------------------------- kernel
-template <typename T, int S, int RPL>
-__global__ __launch_bounds__(512) void panel_kernel(PanelArgs a) {
-  SmallState* st = a.st;
-  if (gated_off(a, st)) return;
-  constexpr int NW = 8;
-  constexpr int BR = kWave * RPL;  // rows per batch
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
-  const int k = a.k, sw = a.sw, ncol = k + sw;
-  const int flags = a.flags;
-  const bool hasP = flags & PF_HAS_P;
-  const bool hasT = (flags & PF_HAS_T) && !st->identity_t;
-  const bool store = flags & PF_STORE;
-  const bool gramQ = flags & PF_GRAM_Q;
-  const bool gramW = flags & PF_GRAM_W;
-  const bool loadQ = hasP || gramQ;
-  T* __restrict__ V = reinterpret_cast<T*>(a.V);
-  const int64_t ld = a.ld;
-
-  __shared__ T ly[NW][S][BR];
-  __shared__ T lw[S][BR];
-  __shared__ T lP[kMaxCols][S];
-  __shared__ T lT[S][S];
-
-  for (int idx = threadIdx.x; idx < kMaxCols * S; idx += blockDim.x) {
-    int c = idx / S, j = idx % S;
-    lP[c][j] = (hasP && c < k && j < sw) ? (T)st->Pcur[c + j * kLd] : (T)0;
-  }
-  for (int idx = threadIdx.x; idx < S * S; idx += blockDim.x) {
-    int i = idx / S, j = idx % S;
-    lT[i][j] = (i < sw && j < sw && i <= j) ? (T)st->Tcur[i + j * kMaxS] : (T)0;
-  }
-  __syncthreads();
-
-  T acc[8][S];
-#pragma unroll
-  for (int sl = 0; sl < 8; ++sl)
-#pragma unroll
-    for (int j = 0; j < S; ++j) acc[sl][j] = (T)0;
-
-  const int64_t rb = (int64_t)blockIdx.x * a.rows_per_block;
-  const int64_t re = min(a.n, rb + a.rows_per_block);
-  for (int64_t r0 = rb; r0 < re; r0 += BR) {
-    T v[8][RPL];
-#pragma unroll
-    for (int sl = 0; sl < 8; ++sl) {
-      const int c = wv + NW * sl;
-      const bool ok = (c < ncol) && (c >= k || loadQ);
-      const int64_t col = (c < k) ? c : (int64_t)a.wcol + (c - k);
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const int64_t row = r0 + lane + kWave * t;
-        v[sl][t] = (ok && row < re) ? V[col * ld + row] : (T)0;
-      }
-    }
-    if (hasP) {
-      T yp[S][RPL];
-#pragma unroll
-      for (int j = 0; j < S; ++j)
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) yp[j][t] = (T)0;
-#pragma unroll
-      for (int sl = 0; sl < 8; ++sl) {
-        const int c = wv + NW * sl;
-        if (c < k) {
-#pragma unroll
-          for (int j = 0; j < S; ++j) {
-            const T p = lP[c][j];
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) yp[j][t] += v[sl][t] * p;
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < S; ++j)
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) ly[wv][j][lane + kWave * t] = yp[j][t];
-    }
-#pragma unroll
-    for (int sl = 0; sl < 8; ++sl) {
-      const int c = wv + NW * sl;
-      if (c >= k && c < ncol) {
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) lw[c - k][lane + kWave * t] = v[sl][t];
-      }
-    }
-    __syncthreads();
-    T q[S][RPL];
-#pragma unroll
-    for (int j = 0; j < S; ++j)
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        T y = (j < sw) ? lw[j][lane + kWave * t] : (T)0;
-        if (hasP) {
-#pragma unroll
-          for (int g = 0; g < NW; ++g) y -= ly[g][j][lane + kWave * t];
-        }
-        q[j][t] = y;
-      }
-    if (hasT) {
-#pragma unroll
-      for (int j = S - 1; j >= 0; --j)
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          T acc2 = (T)0;
-#pragma unroll
-          for (int i = 0; i <= j; ++i) acc2 += q[i][t] * lT[i][j];
-          q[j][t] = acc2;
-        }
-    }
-    // q of this wave's own panel columns (static register indexing via selects)
-#pragma unroll
-    for (int sl = 0; sl < 8; ++sl) {
-      const int c = wv + NW * sl;
-      if (c >= k && c < ncol) {
-        const int jj = c - k;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-          T qv = (T)0;
-#pragma unroll
-          for (int j = 0; j < S; ++j) qv = (j == jj) ? q[j][t] : qv;
-          v[sl][t] = qv;  // reuse: v now holds q for panel columns
-          const int64_t row = r0 + lane + kWave * t;
-          if (store && row < re) V[((int64_t)a.wcol + jj) * ld + row] = qv;
-        }
-      }
-    }
-    if (gramQ || gramW) {
-#pragma unroll
-      for (int sl = 0; sl < 8; ++sl) {
-        const int c = wv + NW * sl;
-        const bool use = (c < k) ? gramQ : (c < ncol && gramW);
-        if (use) {
-#pragma unroll
-          for (int j = 0; j < S; ++j)
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) acc[sl][j] += v[sl][t] * q[j][t];
-        }
-      }
-    }
-    __syncthreads();
-  }
-
-  if (!(gramQ || gramW)) return;
-  const int E = ncol * sw;
-  double* part = a.part1 + (size_t)blockIdx.x * E;
-#pragma unroll
-  for (int sl = 0; sl < 8; ++sl) {
-    const int c = wv + NW * sl;
-    if (c < ncol) {
-      const bool use = (c < k) ? gramQ : gramW;
-#pragma unroll
-      for (int j = 0; j < S; ++j) {
-        if (j < sw) {
-          T sum = wave_sum(acc[sl][j]);
-          if (lane == 0) part[c * sw + j] = use ? (double)sum : 0.0;
-        }
-      }
-    }
-  }
-}
-
 // First level of a cross-block reduction with many blocks: block g sums the partials of
 // blocks [g*chunk, min(nblocks, (g+1)*chunk)) in block order, for every entry, into
 // part2[g * E + e].  The tail then sums the few group partials in group order.
@@ -586,7 +416,7 @@ __global__ __launch_bounds__(256) void partial_reduce_kernel(PanelArgs a, double
 __global__ __launch_bounds__(kTailThreads) void panel_tail_kernel(PanelArgs a) {
   SmallState* st = a.st;
   if (gated_off(a, st)) return;
-  __shared__ double sred[kMaxCols * kMaxS];
+  __shared__ double sred[kMaxCols * kMaxNz];
   __shared__ double scratch[kTailThreads];
   const int E = (a.k + a.sw) * a.nz;
   block_sum_partials(a.part1, E, a.nblocks, sred, scratch);

@@ -1,218 +1,198 @@
 // Lean streaming kernels of the panel steps:
-//   gram_kernel   -- the reduction  G = V(:, 0:ncol)^T V(:, ncol-nz : ncol)  (no update)
-//   update_kernel -- the update     W <- (W - Q P) T  in place            (no reduction)
-// The fused kernel in panel.hpp (update + Gram of its own output in one pass) is kept
-// for the steps whose next reduction needs exactly the columns just written.
+//   gram_mfma_kernel  -- the reduction  G = V(:, 0:ncol)^T V(:, ncol-nz : ncol)  (no update)
+//   update_kernel     -- the update     W <- (W - Q P) T  in place            (no reduction)
+//   panel_mfma_kernel -- the update and the Gram of its output in one pass, for the steps
+//                        whose next reduction needs exactly the columns just written
 #pragma once
 
 #include "panel.hpp"
 
 namespace tsg {
 
-// Reduction over the first ncol = k + sw basis columns (Q = V(:,0:k), W = V(:,wcol:wcol+sw)),
-// against the last nz of them (nz = nprev + sw: the previous panel's nprev columns -- their
-// block column of the stage-2 Gram -- and the panel W).  Block = NW waves, column c of the
-// loaded set is owned by wave c % NW for the whole launch; the nz right-hand columns are
-// exchanged through a double-buffered LDS tile (one barrier per batch); the next batch's
-// loads are issued before the current batch is processed.  Partials: ncol x nz per block.
-template <typename T, int NZ, int NW, int RPL>
-__global__ __launch_bounds__(NW * kWave) void gram_kernel(PanelArgs a) {
+// Matrix-core products of the panel steps.  The Gram of a row batch is a sum over rows,
+// so the rows are the K dimension of the MFMA: A = V(rows, 16-column tile)^T,
+// B = V(rows, 16 right-hand columns).
+//   FP64: v_mfma_f64_16x16x4f64; FP32 (FP32 products, FP32 accumulation):
+//   v_mfma_f32_16x16x4f32.  D(16x16) += A(16x4) B(4x16); lane l holds A(l%16, l/16) and
+//   B(l/16, l%16) for both; accumulator register r of lane l holds D(l/16 + 4r, l%16)
+//   for FP64 and D(4(l/16) + r, l%16) for FP32 (both measured on gfx950 with a one-wave
+//   probe).
+template <typename T>
+struct MfmaOp;
+template <>
+struct MfmaOp<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct MfmaOp<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lk, int r) { return 4 * lk + r; }
+};
+
+// Batch staging shared by the MFMA kernels.  A block of 8 waves moves batches of BR rows of
+// ncol <= 64 basis columns into an LDS tile (column-major, row stride BR + 1, two buffers).
+// A batch is 64 load items of 64 R rows of one column (R = 8 / sizeof(T): each lane loads
+// one double or two adjacent floats, 8 bytes either way); item t = wave + 8 sl, sl < 8,
+// holds column t % ncol, row chunk t / ncol.  So BR = 64 R floor(64 / ncol): every lane
+// keeps 8 loads of 8 bytes in flight whatever ncol is.
+constexpr int kTileItems = 64;
+template <typename T>
+constexpr int tile_rows_per_lane() { return 8 / (int)sizeof(T); }
+template <typename T>
+constexpr int mfma_tile() { return kWave * kTileItems * tile_rows_per_lane<T>() + kMaxCols; }
+
+template <typename T>
+struct TileLoad {
+  static constexpr int R = tile_rows_per_lane<T>(), SL = 8, NW = 8;
+  int64_t colbase[SL];
+  int rowoff[SL], ldsof[SL];
+  int items, BR, LDT;
+  // staged column c is V(:, c) for c < kq, else V(:, wcol + c - kq)
+  __device__ void init(int wv, int ncol, int kq, int64_t wcol, int64_t ld) {
+    const int RB = kTileItems / ncol;
+    BR = kWave * R * RB;
+    LDT = BR + 1;
+    items = ncol * RB;
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+      const int t = wv + NW * sl;
+      const int c = t % ncol, chunk = t / ncol;
+      colbase[sl] = ((c < kq) ? (int64_t)c : wcol + (c - kq)) * ld;
+      rowoff[sl] = chunk * kWave * R;
+      ldsof[sl] = c * LDT + chunk * kWave * R;
+    }
+  }
+  __device__ void load(const T* __restrict__ V, int wv, int lane, int64_t r0, int64_t re,
+                       T (&dst)[SL][R]) const {
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+      const int t = wv + NW * sl;
+      const int64_t row = r0 + rowoff[sl] + (int64_t)R * lane;
+      if (t < items && row + R <= re) {
+        if constexpr (R == 2) {
+          const float2 x = *reinterpret_cast<const float2*>(V + colbase[sl] + row);
+          dst[sl][0] = x.x;
+          dst[sl][1] = x.y;
+        } else {
+          dst[sl][0] = V[colbase[sl] + row];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < R; ++e) dst[sl][e] = (t < items && row + e < re) ? V[colbase[sl] + row + e] : (T)0;
+      }
+    }
+  }
+  __device__ void to_lds(T* L, int wv, int lane, const T (&src)[SL][R]) const {
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+      const int t = wv + NW * sl;
+      if (t < items) {
+#pragma unroll
+        for (int e = 0; e < R; ++e) L[ldsof[sl] + R * lane + e] = src[sl][e];
+      }
+    }
+  }
+};
+
+// The reduction G = V(:, 0:ncol)^T V(:, ncol-nz : ncol) of a panel step on the matrix
+// cores, where ncol = k + sw (Q = V(:,0:k), W = V(:,wcol:wcol+sw)) and the nz right-hand
+// columns are the previous panel's nprev columns (their block column of the stage-2 Gram)
+// followed by W.  Batches are staged as in TileLoad (one barrier per batch), the next two
+// batches loading into registers while the matrix cores consume the current one.  The
+// K-steps (4 rows each) of a batch are dealt to the waves round-robin; every wave
+// accumulates all MT x NT tiles (4 MT NT values per lane).  The 8 waves' tiles are summed
+// in LDS in wave order (in float64) at the end.  Partials: ncol x nz float64 per block.
+// Requires ncol <= 16 MT, nz <= 16 NT.
+template <typename T, int MT, int NT>
+__global__ __launch_bounds__(512) void gram_mfma_kernel(PanelArgs a) {
   SmallState* st = a.st;
   if (gated_off(a, st)) return;
-  constexpr int SL = kMaxCols / NW;  // column slots per wave
-  constexpr int BR = kWave * RPL;
+  typedef typename MfmaOp<T>::v4 v4;
+  typedef TileLoad<T> TL;
+  constexpr int NW = 8, SL = TL::SL, R = TL::R;
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int k = a.k, ncol = a.k + a.sw, nz = a.nz, z0 = ncol - nz;
   const T* __restrict__ V = reinterpret_cast<const T*>(a.V);
-  const int64_t ld = a.ld;
-  __shared__ T lz[2][NZ][BR];
-
-  T acc[SL][NZ];
-#pragma unroll
-  for (int sl = 0; sl < SL; ++sl)
-#pragma unroll
-    for (int z = 0; z < NZ; ++z) acc[sl][z] = (T)0;
+  __shared__ T lt[2][mfma_tile<T>()];
+  TL tl;
+  tl.init(wv, ncol, k, a.wcol, a.ld);
+  const int BR = tl.BR, LDT = tl.LDT;
 
   const int64_t rb = (int64_t)blockIdx.x * a.rows_per_block;
   const int64_t re = min(a.n, rb + a.rows_per_block);
-  int64_t colof[SL];
+  T v[SL][R], vn[SL][R], vnn[SL][R];
+  v4 acc[MT][NT];
 #pragma unroll
-  for (int sl = 0; sl < SL; ++sl) {
-    const int c = wv + NW * sl;
-    colof[sl] = ((c < k) ? (int64_t)c : (int64_t)a.wcol + (c - k)) * ld;
-  }
-  T v[SL][RPL], vn[SL][RPL];
-  auto load = [&](T (&dst)[SL][RPL], int64_t r0) {
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int sl = 0; sl < SL; ++sl) {
-      const int c = wv + NW * sl;
-#pragma unroll
-      for (int t = 0; t < RPL; ++t) {
-        const int64_t row = r0 + lane + kWave * t;
-        dst[sl][t] = (c < ncol && row < re) ? V[colof[sl] + row] : (T)0;
-      }
-    }
-  };
-  load(v, rb);
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4{0, 0, 0, 0};
+  const int li = lane & 15, lk = lane >> 4;
+  const int ksteps = BR / 4;  // K-steps of 4 rows per batch, dealt to the waves round-robin
+  // prefetch depth 2: batches r0+BR and r0+2BR are in flight while r0 is consumed
+  tl.load(V, wv, lane, rb, re, v);
+  if (rb + BR < re) tl.load(V, wv, lane, rb + BR, re, vn);
   int buf = 0;
   for (int64_t r0 = rb; r0 < re; r0 += BR) {
-    if (r0 + BR < re) load(vn, r0 + BR);
-#pragma unroll
-    for (int sl = 0; sl < SL; ++sl) {
-      const int c = wv + NW * sl;
-      if (c >= z0 && c < ncol) {
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) lz[buf][c - z0][lane + kWave * t] = v[sl][t];
-      }
-    }
+    if (r0 + 2 * BR < re) tl.load(V, wv, lane, r0 + 2 * BR, re, vnn);
+    T* L = lt[buf];
+    tl.to_lds(L, wv, lane, v);
     __syncthreads();
+    for (int ks = wv; ks < ksteps; ks += NW) {
+      const int row = ks * 4 + lk;
+      T bv[NT];
 #pragma unroll
-    for (int z = 0; z < NZ; ++z) {
-      if (z < nz) {
-        T zv[RPL];
+      for (int nt = 0; nt < NT; ++nt) {
+        const int z = nt * 16 + li;
+        bv[nt] = (z < nz) ? L[(z0 + z) * LDT + row] : (T)0;
+      }
 #pragma unroll
-        for (int t = 0; t < RPL; ++t) zv[t] = lz[buf][z][lane + kWave * t];
+      for (int mt = 0; mt < MT; ++mt) {
+        const int c = mt * 16 + li;
+        const T av = (c < ncol) ? L[c * LDT + row] : (T)0;
 #pragma unroll
-        for (int sl = 0; sl < SL; ++sl) {
-#pragma unroll
-          for (int t = 0; t < RPL; ++t) acc[sl][z] += v[sl][t] * zv[t];
-        }
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = MfmaOp<T>::mac(av, bv[nt], acc[mt][nt]);
       }
     }
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl)
 #pragma unroll
-      for (int t = 0; t < RPL; ++t) v[sl][t] = vn[sl][t];
+      for (int e = 0; e < R; ++e) {
+        v[sl][e] = vn[sl][e];
+        vn[sl][e] = vnn[sl][e];
+      }
     buf ^= 1;
   }
+  // sum the 8 waves' partial tiles in wave order, one 16-wide Z tile at a time:
+  // red[w][c][z], c < 64, z < 16 (8 x 64 x 16 values fit in the two LDS buffers)
+  T* red = &lt[0][0];
   double* part = a.part1 + (size_t)blockIdx.x * ncol * nz;
 #pragma unroll
-  for (int sl = 0; sl < SL; ++sl) {
-    const int c = wv + NW * sl;
-    if (c < ncol) {
-#pragma unroll
-      for (int z = 0; z < NZ; ++z) {
-        if (z < nz) {
-          T sum = wave_sum(acc[sl][z]);
-          if (lane == 0) part[c * nz + z] = (double)sum;
-        }
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------------------
-// The same reduction G = V(:, 0:ncol)^T V(:, ncol-nz:ncol) on the FP64 matrix cores
-// (v_mfma_f64_16x16x4f64: D(16x16) += A(16x4) B(4x16); lane l holds A(l%16, l/16),
-// B(l/16, l%16) and D(l/16 + 4r, l%16) in accumulator register r -- the layout was
-// measured on gfx950 with a one-wave probe).
-//   A = V(rows, tile columns)^T, B = V(rows, Z columns): the K dimension is the rows.
-// A block of 8 waves stages batches of BR = 64 * floor(64 / ncol) rows of all ncol <= 64
-// columns in LDS (column-major, row stride BR + 1; double-buffered, one barrier per batch),
-// loading the next two batches into registers while the matrix cores consume the current
-// one.  The K-steps (4 rows each) of a batch are dealt to the waves round-robin; every
-// wave accumulates all MT 16-column tiles: 4 MT doubles of accumulators per lane instead
-// of one copy of every Gram entry per lane, so occupancy stays at 2 blocks per CU.  The 8
-// waves' tiles are summed in LDS in wave order at the end.  Requires nz <= 16.
-typedef double dbl4 __attribute__((ext_vector_type(4)));
-
-constexpr int kMfmaTile = kMaxCols * (kWave + 1);  // doubles per LDS tile buffer
-
-template <int MT>
-__global__ __launch_bounds__(512) void gram_mfma_kernel(PanelArgs a) {
-  SmallState* st = a.st;
-  if (gated_off(a, st)) return;
-  constexpr int NW = 8, SL = 8;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
-  const int k = a.k, ncol = a.k + a.sw, nz = a.nz, z0 = ncol - nz;
-  // a batch is RB chunks of 64 rows of all ncol columns (ncol * RB <= 64 load items, so
-  // narrow reductions still keep 64 wave loads in flight); LDS row stride BR + 1
-  const int RB = kMaxCols / ncol;
-  const int BR = kWave * RB, LDT = BR + 1;
-  const int items = ncol * RB;
-  const double* __restrict__ V = reinterpret_cast<const double*>(a.V);
-  const int64_t ld = a.ld;
-  __shared__ double lt[2][kMfmaTile];
-
-  const int64_t rb = (int64_t)blockIdx.x * a.rows_per_block;
-  const int64_t re = min(a.n, rb + a.rows_per_block);
-  // load item t = wv + 8 sl: column c = t % ncol, 64-row chunk t / ncol of the batch
-  int64_t colbase[SL];
-  int rowoff[SL], ldsof[SL];
-#pragma unroll
-  for (int sl = 0; sl < SL; ++sl) {
-    const int t = wv + NW * sl;
-    const int c = t % ncol, chunk = t / ncol;
-    colbase[sl] = ((c < k) ? (int64_t)c : (int64_t)a.wcol + (c - k)) * ld;
-    rowoff[sl] = chunk * kWave;
-    ldsof[sl] = c * LDT + chunk * kWave;
-  }
-  double v[SL], vn[SL], vnn[SL];
-  auto load = [&](double (&dst)[SL], int64_t r0) {
-#pragma unroll
-    for (int sl = 0; sl < SL; ++sl) {
-      const int t = wv + NW * sl;
-      const int64_t row = r0 + rowoff[sl] + lane;
-      dst[sl] = (t < items && row < re) ? V[colbase[sl] + row] : 0.0;
-    }
-  };
-  dbl4 acc[MT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) acc[mt] = dbl4{0.0, 0.0, 0.0, 0.0};
-  const int li = lane & 15, lk = lane >> 4;
-  const bool zok = li < nz;
-  const int ksteps = BR / 4;  // K-steps of 4 rows per batch, dealt to the waves round-robin
-  // prefetch depth 2: batches r0+BR and r0+2BR are in flight while r0 is consumed
-  load(v, rb);
-  if (rb + BR < re) load(vn, rb + BR);
-  int buf = 0;
-  for (int64_t r0 = rb; r0 < re; r0 += BR) {
-    if (r0 + 2 * BR < re) load(vnn, r0 + 2 * BR);
-    double* T = lt[buf];
-#pragma unroll
-    for (int sl = 0; sl < SL; ++sl) {
-      const int t = wv + NW * sl;
-      if (t < items) T[ldsof[sl] + lane] = v[sl];
-    }
+  for (int nt = 0; nt < NT; ++nt) {
     __syncthreads();
-    for (int ks = wv; ks < ksteps; ks += NW) {
-      const int row = ks * 4 + lk;
-      const double bv = zok ? T[(z0 + li) * LDT + row] : 0.0;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int c = mt * 16 + li;
-        const double av = (c < ncol) ? T[c * LDT + row] : 0.0;
-        acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[mt], 0, 0, 0);
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = mt * 16 + MfmaOp<T>::row(lk, r);
+        red[(wv * kMaxCols + c) * 16 + li] = acc[mt][nt][r];
       }
-    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ncol * 16; e += blockDim.x) {
+      const int c = e / 16, z = nt * 16 + e % 16;
+      if (z < nz) {
+        double sum = 0.0;
 #pragma unroll
-    for (int sl = 0; sl < SL; ++sl) {
-      v[sl] = vn[sl];
-      vn[sl] = vnn[sl];
-    }
-    buf ^= 1;
-  }
-  __syncthreads();
-  // sum the 8 waves' partial tiles in wave order: red[w][c][z], c < 16 MT, z < 16
-  double* red = &lt[0][0];  // 8 x 64 x 16 doubles = 64 KiB fits in the two tiles
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int c = mt * 16 + lk + 4 * r;
-      red[(wv * kMaxCols + c) * 16 + li] = acc[mt][r];
-    }
-  __syncthreads();
-  double* part = a.part1 + (size_t)blockIdx.x * ncol * nz;
-  for (int e = threadIdx.x; e < ncol * 16; e += blockDim.x) {
-    const int c = e / 16, z = e % 16;
-    if (z < nz) {
-      double sum = 0.0;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) sum += red[(w * kMaxCols + c) * 16 + z];
-      part[c * nz + z] = sum;
+        for (int w = 0; w < NW; ++w) sum += (double)red[(w * kMaxCols + c) * 16 + e % 16];
+        part[c * nz + z] = sum;
+      }
     }
   }
 }
@@ -257,6 +237,171 @@ __global__ __launch_bounds__(256) void update_kernel(PanelArgs a) {
 #pragma unroll
   for (int j = 0; j < S; ++j)
     if (j < sw) W[(int64_t)j * ld] = y[j];
+}
+
+
+
+// The fused panel step on the matrix cores: per row, the update
+//     q = (W(r,:) - Q(r,:) P) T          (PF_HAS_P / PF_HAS_T; Q = V(:,0:k), W = V(:,wcol:+sw))
+// stored in place (PF_STORE), and the Gram of its output  G = [Q, q]^T q  (PF_GRAM_Q: Q rows;
+// the q rows always), in one pass over the rows.  Batches of the staged columns (Q when
+// it is needed, then W) go through LDS as in TileLoad; between the two barriers of a batch
+// every row's q is formed in the tile (the next two batches load meanwhile): `parts` consecutive lanes share a row, each summing
+// Q(r,c) P(c,:) over every parts-th column, the partial sums are combined by lane exchange
+// (xor shuffles), and each lane applies T for its own columns and writes q over W.  The
+// matrix cores then reduce the tile, and the waves store q from LDS in whole row segments.
+// Partials: (k + sw) x sw float64 per block (rows of Q zero unless PF_GRAM_Q).
+template <typename T, int MT, int S>
+__global__ __launch_bounds__(512) void panel_mfma_kernel(PanelArgs a) {
+  SmallState* st = a.st;
+  if (gated_off(a, st)) return;
+  typedef typename MfmaOp<T>::v4 v4;
+  typedef TileLoad<T> TL;
+  constexpr int NW = 8, SL = TL::SL, R = TL::R;
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
+  const int k = a.k, sw = a.sw, flags = a.flags;
+  const bool hasP = flags & PF_HAS_P;
+  const bool hasT = (flags & PF_HAS_T) && !st->identity_t;
+  const bool store = flags & PF_STORE;
+  const bool gramQ = flags & PF_GRAM_Q;
+  const int kq = (hasP || gramQ) ? k : 0;  // staged Q columns
+  const int ncol = kq + sw;                // staged columns: Q then W
+  const int a0 = gramQ ? 0 : kq;           // first staged column on the A side of the Gram
+  const int ncolA = ncol - a0;
+  T* __restrict__ V = reinterpret_cast<T*>(a.V);
+  const int64_t ld = a.ld;
+  __shared__ T lt[2][mfma_tile<T>()];
+  __shared__ T lP[kMaxCols * S];
+  __shared__ T lT[S * S];
+  for (int idx = tid; idx < kMaxCols * S; idx += blockDim.x) {
+    const int c = idx / S, j = idx % S;
+    lP[idx] = (hasP && c < k && j < sw) ? (T)st->Pcur[c + j * kLd] : (T)0;
+  }
+  for (int idx = tid; idx < S * S; idx += blockDim.x) {
+    const int i = idx / S, j = idx % S;
+    lT[idx] = (i < sw && j < sw && i <= j) ? (T)st->Tcur[i + j * kMaxS] : (T)0;
+  }
+  TL tl;
+  tl.init(wv, ncol, kq, a.wcol, ld);
+  const int BR = tl.BR, LDT = tl.LDT;
+  const int parts = BR <= 64 ? 8 : (BR <= 128 ? 4 : (BR <= 256 ? 2 : 1));  // lanes per row
+  const int rows_pass = 512 / parts;
+  const int part = tid % parts;
+
+  const int64_t rb = (int64_t)blockIdx.x * a.rows_per_block;
+  const int64_t re = min(a.n, rb + a.rows_per_block);
+  T v[SL][R], vn[SL][R], vnn[SL][R];
+  v4 acc[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) acc[mt] = v4{0, 0, 0, 0};
+  const int li = lane & 15, lk = lane >> 4;
+  tl.load(V, wv, lane, rb, re, v);
+  if (rb + BR < re) tl.load(V, wv, lane, rb + BR, re, vn);
+  int buf = 0;
+  for (int64_t r0 = rb; r0 < re; r0 += BR) {
+    if (r0 + 2 * BR < re) tl.load(V, wv, lane, r0 + 2 * BR, re, vnn);
+    T* L = lt[buf];
+    tl.to_lds(L, wv, lane, v);
+    __syncthreads();
+    // ---- q = (W - Q P) T for the rows of the batch, in the tile.  The compiler barrier
+    //      keeps P and T in LDS (held in registers across batches they would take
+    //      k s + s^2 of them)
+    asm volatile("" ::: "memory");
+    for (int rbase = 0; rbase < BR; rbase += rows_pass) {
+      const int rl = rbase + tid / parts;
+      const bool rok = rl < BR;
+      T y[S];
+#pragma unroll
+      for (int j = 0; j < S; ++j) y[j] = (T)0;
+      if (hasP) {
+        for (int c = part; c < k; c += parts) {
+          const T qv = rok ? L[c * LDT + rl] : (T)0;
+#pragma unroll
+          for (int j = 0; j < S; ++j) y[j] += qv * lP[c * S + j];
+        }
+        for (int o = 1; o < parts; o <<= 1) {
+#pragma unroll
+          for (int j = 0; j < S; ++j) y[j] += __shfl_xor(y[j], o, kWave);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < S; ++j) y[j] = (rok && j < sw) ? L[(kq + j) * LDT + rl] - y[j] : (T)0;
+      // every lane of the row now holds y; each forms q(r, j) = sum_{i <= j} y_i T(i, j) for
+      // its own columns j = part, part + parts, ... and writes it over W(r, j)
+      for (int j = part; j < sw; j += parts) {
+        T q = (T)0;
+        if (hasT) {
+#pragma unroll
+          for (int i = 0; i < S; ++i)
+            if (i <= j) q += y[i] * lT[i * S + j];
+        } else {
+#pragma unroll
+          for (int i = 0; i < S; ++i)
+            if (i == j) q = y[i];
+        }
+        if (rok) L[(kq + j) * LDT + rl] = q;
+      }
+    }
+    __syncthreads();
+    // ---- Gram of the tile on the matrix cores; q back to HBM in whole row segments
+    for (int ks = wv; ks < BR / 4; ks += NW) {
+      const int row = ks * 4 + lk;
+      const T bv = (li < sw) ? L[(kq + li) * LDT + row] : (T)0;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int c = a0 + mt * 16 + li;
+        const T av = (c < ncol) ? L[c * LDT + row] : (T)0;
+        acc[mt] = MfmaOp<T>::mac(av, bv, acc[mt]);
+      }
+    }
+    if (store) {
+      const int nchunk = BR / (kWave * R);
+      for (int t = wv; t < sw * nchunk; t += NW) {
+        const int j = t % sw, chunk = t / sw;
+        const int rl = chunk * kWave * R + R * lane;
+#pragma unroll
+        for (int e = 0; e < R; ++e) {
+          const int64_t row = r0 + rl + e;
+          if (row < re) V[((int64_t)a.wcol + j) * ld + row] = L[(kq + j) * LDT + rl + e];
+        }
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl)
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        v[sl][e] = vn[sl][e];
+        vn[sl][e] = vnn[sl][e];
+      }
+    buf ^= 1;
+  }
+  __syncthreads();
+  T* red = &lt[0][0];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = mt * 16 + MfmaOp<T>::row(lk, r);
+      red[(wv * kMaxCols + c) * 16 + li] = acc[mt][r];
+    }
+  __syncthreads();
+  double* part1 = a.part1 + (size_t)blockIdx.x * (k + sw) * sw;
+  if (!gramQ) {
+    for (int e = tid; e < k * sw; e += blockDim.x) part1[e] = 0.0;
+  }
+  for (int e = tid; e < ncolA * 16; e += blockDim.x) {
+    const int c = e / 16, z = e % 16;
+    if (z < sw) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sum += (double)red[(w * kMaxCols + c) * 16 + z];
+      const int sc = a0 + c;  // staged column
+      const int prow = sc < kq ? sc : k + (sc - kq);
+      part1[prow * sw + z] = sum;
+    }
+  }
 }
 
 }  // namespace tsg

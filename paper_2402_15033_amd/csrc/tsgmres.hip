@@ -68,8 +68,6 @@ int64_t basis_ld(int64_t n) {
   return ld;
 }
 
-constexpr int kPanelThreads = 512;
-constexpr int kMaxPanelBlocks = 256;  // one 8-wave block per CU
 constexpr int kMaxReduceBlocks = 512;  // largest grid of any reduction kernel (MFMA Gram)
 
 // Workspace carving shared by solve and orthogonalize.
@@ -94,12 +92,12 @@ struct Common {
 };
 
 size_t part1_count(int64_t n) {
-  return std::max<size_t>((size_t)kMaxReduceBlocks * kMaxCols * kMaxS, (size_t)cdiv(n, kRowBlock));
+  return std::max<size_t>((size_t)kMaxReduceBlocks * kMaxCols * kMaxNz, (size_t)cdiv(n, kRowBlock));
 }
 
 size_t common_bytes(int64_t n) {
   return align_up(sizeof(SmallState)) + align_up(part1_count(n) * sizeof(double)) +
-         align_up((size_t)kReduceGroups * kMaxCols * kMaxS * sizeof(double));
+         align_up((size_t)kReduceGroups * kMaxCols * kMaxNz * sizeof(double));
 }
 
 Common carve_common(Carve& cv, int64_t n) {
@@ -107,7 +105,7 @@ Common carve_common(Carve& cv, int64_t n) {
   c.part1_n = part1_count(n);
   c.st = cv.take<SmallState>(1);
   c.part1 = cv.take<double>(c.part1_n);
-  c.part2 = cv.take<double>((size_t)kReduceGroups * kMaxCols * kMaxS);
+  c.part2 = cv.take<double>((size_t)kReduceGroups * kMaxCols * kMaxNz);
   return c;
 }
 __global__ void zero_f64_kernel(double* p, int64_t n) {
@@ -202,52 +200,48 @@ struct PanelCtx {
 
 // Round a panel width up to an instantiated template width.
 int s_template(int sw) { return sw <= 6 ? sw : (sw <= 8 ? 8 : (sw <= 10 ? 10 : (sw <= 12 ? 12 : 16))); }
-int fused_rpl(int sw) { return s_template(sw) <= 6 ? 2 : 1; }
-int nz_template(int nz) { return nz <= 6 ? nz : (nz <= 8 ? 8 : 10); }
-int gram_rpl(int nz) { return nz_template(nz) <= 6 ? 2 : 1; }
-constexpr int kMaxGramNzF32 = 10;  // widest lean FP32 reduction (VALU: 8 slots x 10 accumulators)
-constexpr int kMaxGramNzF64 = 16;  // widest FP64 reduction on the matrix cores (one 16-wide tile)
-inline int max_gram_nz(bool f32) { return f32 ? kMaxGramNzF32 : kMaxGramNzF64; }
+constexpr int kMaxGramNz = kMaxNz;  // widest lean reduction (two 16-wide MFMA tiles)
 constexpr int kMaxMfmaBlocks = 512;  // two 8-wave blocks per CU
-static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks && kMaxPanelBlocks <= kMaxReduceBlocks,
+static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks,
               "reduction partial buffer too small");
 
-template <typename T, int S>
-void launch_fused_t(const PanelArgs& a, int nb, hipStream_t s) {
-  constexpr int RPL = (S <= 6) ? 2 : 1;
-  hipLaunchKernelGGL((panel_kernel<T, S, RPL>), dim3(nb), dim3(kPanelThreads), 0, s, a);
-}
-template <typename T>
-void launch_fused(const PanelArgs& a, int nb, hipStream_t s) {
-  switch (s_template(a.sw)) {
-    case 1: launch_fused_t<T, 1>(a, nb, s); break;
-    case 2: launch_fused_t<T, 2>(a, nb, s); break;
-    case 3: launch_fused_t<T, 3>(a, nb, s); break;
-    case 4: launch_fused_t<T, 4>(a, nb, s); break;
-    case 5: launch_fused_t<T, 5>(a, nb, s); break;
-    case 6: launch_fused_t<T, 6>(a, nb, s); break;
-    case 8: launch_fused_t<T, 8>(a, nb, s); break;
-    case 10: launch_fused_t<T, 10>(a, nb, s); break;
-    case 12: launch_fused_t<T, 12>(a, nb, s); break;
-    default: launch_fused_t<T, 16>(a, nb, s); break;
+// Panel widths with a fused-kernel instantiation (a panel runs in the smallest one >= sw).
+int fused_s(int sw) { return sw <= 1 ? 1 : sw <= 2 ? 2 : sw <= 4 ? 4 : sw <= 5 ? 5 : sw <= 8 ? 8 : sw <= 10 ? 10 : 16; }
+// Columns staged by the fused kernel (Q only when the step projects or reduces against it).
+template <typename T, int MT>
+void launch_fused_mt(const PanelArgs& a, int nb, hipStream_t s) {
+  switch (fused_s(a.sw)) {
+    case 1: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 1>), dim3(nb), dim3(512), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 2>), dim3(nb), dim3(512), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 4>), dim3(nb), dim3(512), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 5>), dim3(nb), dim3(512), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 8>), dim3(nb), dim3(512), 0, s, a); break;
+    case 10: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 10>), dim3(nb), dim3(512), 0, s, a); break;
+    default: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 16>), dim3(nb), dim3(512), 0, s, a); break;
   }
 }
-template <typename T, int NZ>
-void launch_gram_t(const PanelArgs& a, int nb, hipStream_t s) {
-  constexpr int RPL = (NZ <= 6) ? 2 : 1;
-  hipLaunchKernelGGL((gram_kernel<T, NZ, 8, RPL>), dim3(nb), dim3(8 * kWave), 0, s, a);
+// ncolA: columns on the A side of the fused kernel's Gram ([Q, q] or q alone)
+template <typename T>
+void launch_fused(const PanelArgs& a, int ncolA, int nb, hipStream_t s) {
+  switch ((ncolA + 15) / 16) {
+    case 1: launch_fused_mt<T, 1>(a, nb, s); break;
+    case 2: launch_fused_mt<T, 2>(a, nb, s); break;
+    case 3: launch_fused_mt<T, 3>(a, nb, s); break;
+    default: launch_fused_mt<T, 4>(a, nb, s); break;
+  }
+}
+template <typename T, int MT>
+void launch_gram_mt(const PanelArgs& a, int nb, hipStream_t s) {
+  if (a.nz <= 16) hipLaunchKernelGGL((gram_mfma_kernel<T, MT, 1>), dim3(nb), dim3(512), 0, s, a);
+  else hipLaunchKernelGGL((gram_mfma_kernel<T, MT, 2>), dim3(nb), dim3(512), 0, s, a);
 }
 template <typename T>
 void launch_gram(const PanelArgs& a, int nb, hipStream_t s) {
-  switch (nz_template(a.nz)) {
-    case 1: launch_gram_t<T, 1>(a, nb, s); break;
-    case 2: launch_gram_t<T, 2>(a, nb, s); break;
-    case 3: launch_gram_t<T, 3>(a, nb, s); break;
-    case 4: launch_gram_t<T, 4>(a, nb, s); break;
-    case 5: launch_gram_t<T, 5>(a, nb, s); break;
-    case 6: launch_gram_t<T, 6>(a, nb, s); break;
-    case 8: launch_gram_t<T, 8>(a, nb, s); break;
-    default: launch_gram_t<T, 10>(a, nb, s); break;
+  switch ((a.k + a.sw + 15) / 16) {
+    case 1: launch_gram_mt<T, 1>(a, nb, s); break;
+    case 2: launch_gram_mt<T, 2>(a, nb, s); break;
+    case 3: launch_gram_mt<T, 3>(a, nb, s); break;
+    default: launch_gram_mt<T, 4>(a, nb, s); break;
   }
 }
 template <typename T>
@@ -309,11 +303,12 @@ tsg_status run_step(const PanelCtx& p, const Step& st) {
   } else {
     const bool gram = st.kind == PK_GRAM;
     a.nz = gram ? st.nprev + st.sw : st.sw;
-    const bool mfma = gram && !p.f32;
-    const int br = mfma ? kWave * (kMaxCols / (st.k + st.sw))  // the MFMA kernel's batch height
-                        : kWave * (gram ? gram_rpl(a.nz) : fused_rpl(st.sw));
+    const int rpl = p.f32 ? tile_rows_per_lane<float>() : tile_rows_per_lane<double>();
+    const bool loadQ = (st.flags & (PF_HAS_P | PF_GRAM_Q)) != 0;
+    const int staged = gram ? st.k + st.sw : (loadQ ? st.k : 0) + st.sw;
+    const int br = kWave * rpl * (kTileItems / staged);  // the MFMA kernels' batch height
     int64_t tiles = cdiv(p.n, br);
-    nb = (int)std::min<int64_t>(tiles, mfma ? kMaxMfmaBlocks : kMaxPanelBlocks);
+    nb = (int)std::min<int64_t>(tiles, kMaxMfmaBlocks);
     a.rows_per_block = cdiv(cdiv(p.n, nb), br) * br;
     nb = (int)cdiv(p.n, a.rows_per_block);
     a.nblocks = nb;
@@ -322,12 +317,13 @@ tsg_status run_step(const PanelCtx& p, const Step& st) {
       cols = st.k + st.sw;
       if (kc < 0) kc = st.nprev > 0 ? TSG_KC_GRAM : TSG_KC_GRAM_FIRST;
     } else {
-      reduces = (st.flags & (PF_GRAM_Q | PF_GRAM_W)) != 0;
-      const bool loadQ = (st.flags & (PF_HAS_P | PF_GRAM_Q)) != 0;
-      cols = (loadQ ? st.k : 0) + st.sw + ((st.flags & PF_STORE) ? st.sw : 0);
+      reduces = true;
+      cols = staged + ((st.flags & PF_STORE) ? st.sw : 0);
       if (kc < 0) kc = TSG_KC_FUSED;
     }
   }
+  if (a.nz > kMaxGramNz || st.k + st.sw > kMaxCols)
+    return fail(TSG_ERR_UNSUPPORTED, "internal: reduction of %d x %d columns", st.k + st.sw, a.nz);
   if (reduces && (size_t)nb * (size_t)((st.k + st.sw) * a.nz) > p.c.part1_n)
     return fail(TSG_ERR_WORKSPACE, "internal: reduction partials (%d blocks x %d) exceed the buffer", nb,
                 (st.k + st.sw) * a.nz);
@@ -335,25 +331,18 @@ tsg_status run_step(const PanelCtx& p, const Step& st) {
   if (p.timer) p.timer->begin(p.stream, kc, fb ? 0.0 : cols * (double)p.n * p.elem);
   switch (st.kind) {
     case PK_GRAM:
-      if (p.f32) {
-        launch_gram<float>(a, nb, p.stream);
-      } else {
-        switch ((st.k + st.sw + 15) / 16) {
-          case 1: hipLaunchKernelGGL((gram_mfma_kernel<1>), dim3(nb), dim3(512), 0, p.stream, a); break;
-          case 2: hipLaunchKernelGGL((gram_mfma_kernel<2>), dim3(nb), dim3(512), 0, p.stream, a); break;
-          case 3: hipLaunchKernelGGL((gram_mfma_kernel<3>), dim3(nb), dim3(512), 0, p.stream, a); break;
-          default: hipLaunchKernelGGL((gram_mfma_kernel<4>), dim3(nb), dim3(512), 0, p.stream, a); break;
-        }
-      }
+      if (p.f32) launch_gram<float>(a, nb, p.stream);
+      else launch_gram<double>(a, nb, p.stream);
       break;
     case PK_UPDATE:
       if (p.f32) launch_update<float>(a, nb, p.stream);
       else launch_update<double>(a, nb, p.stream);
       break;
-    case PK_FUSED:
-      if (p.f32) launch_fused<float>(a, nb, p.stream);
-      else launch_fused<double>(a, nb, p.stream);
-      break;
+    case PK_FUSED: {
+      const int ncolA = (st.flags & PF_GRAM_Q) ? st.k + st.sw : st.sw;
+      if (p.f32) launch_fused<float>(a, ncolA, nb, p.stream);
+      else launch_fused<double>(a, ncolA, nb, p.stream);
+    } break;
   }
   if (p.timer) p.timer->end(p.stream);
   HIP_LAUNCH_CHECK();
@@ -376,15 +365,10 @@ tsg_status run_step(const PanelCtx& p, const Step& st) {
 
 // A reduction over the k + sw columns (lean kernel when it fits, else the fused kernel in
 // reduce-only mode).
-Step gram_step(bool f32, int k, int wcol, int sw, int nprev, int tail, int panel, int kkeep, int gate = 1) {
+Step gram_step(int k, int wcol, int sw, int nprev, int tail, int panel, int kkeep, int gate = 1) {
   Step st{};
-  if (nprev + sw <= max_gram_nz(f32)) {
-    st.kind = PK_GRAM;
-    st.nprev = nprev;
-  } else {
-    st.kind = PK_FUSED;
-    st.flags = PF_GRAM_Q | PF_GRAM_W;
-  }
+  st.kind = PK_GRAM;
+  st.nprev = nprev;
   st.k = k;
   st.wcol = wcol;
   st.sw = sw;
@@ -423,7 +407,7 @@ tsg_status panel_sequence(const PanelCtx& p, int ortho, int k, int sw, int nprev
       const int passes = p.standalone ? 1 : 2;
       for (int pass = 0; pass < passes; ++pass) {
         const int gate = pass == 0 ? 1 : 2;
-        Step g = gram_step(p.f32, k, c0, sw, pass == 0 ? nprev : 0, pass == 0 ? TAIL_PIP : TAIL_PIP_FB, j,
+        Step g = gram_step(k, c0, sw, pass == 0 ? nprev : 0, pass == 0 ? TAIL_PIP : TAIL_PIP_FB, j,
                            kkeep, gate);
         if (pass == 1) g.kclass = TSG_KC_FALLBACK;
         TRY(run_step(p, g));
@@ -436,13 +420,13 @@ tsg_status panel_sequence(const PanelCtx& p, int ortho, int k, int sw, int nprev
       }
     } break;
     case TSG_ORTHO_BCGS_PIP2:
-      TRY(run_step(p, gram_step(p.f32, k, c0, sw, 0, TAIL_PIP2_A, j, kkeep)));
+      TRY(run_step(p, gram_step(k, c0, sw, 0, TAIL_PIP2_A, j, kkeep)));
       TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W,
                                TAIL_PIP2_B, j, kkeep)));
       TRY(run_step(p, upd_step(PK_UPDATE, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
       break;
     case TSG_ORTHO_BCGS2_CHOLQR2:
-      TRY(run_step(p, gram_step(p.f32, k, c0, sw, 0, TAIL_BC_P1, j, kkeep)));
+      TRY(run_step(p, gram_step(k, c0, sw, 0, TAIL_BC_P1, j, kkeep)));
       TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_A1, j, kkeep)));
       TRY(run_step(p, upd_step(PK_FUSED, 0, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_W, TAIL_BC_A2, j, kkeep)));
       TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P2, j,
@@ -451,7 +435,7 @@ tsg_status panel_sequence(const PanelCtx& p, int ortho, int k, int sw, int nprev
       TRY(run_step(p, upd_step(PK_UPDATE, 0, c0, sw, PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
       break;
     case TSG_ORTHO_CGS2:
-      TRY(run_step(p, gram_step(p.f32, k, c0, 1, 0, TAIL_CGS_H1, j, kkeep)));
+      TRY(run_step(p, gram_step(k, c0, 1, 0, TAIL_CGS_H1, j, kkeep)));
       TRY(run_step(p, upd_step(PK_FUSED, k, c0, 1, PF_HAS_P | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_CGS_H2, j,
                                kkeep)));
       TRY(run_step(p, upd_step(PK_UPDATE, k, c0, 1, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
@@ -667,7 +651,7 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   }
 
 
-  const bool g00_here = two && 1 + sstep > max_gram_nz(f32);
+  const bool g00_here = two && 1 + sstep > kMaxGramNz;
   // Every launch of a restart cycle has the same arguments in every cycle (what changes --
   // convergence, truncation after a breakdown, the iteration count -- lives in the device
   // state), so one cycle is enqueued on stream q either directly or into a graph.
@@ -702,7 +686,7 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
       }
       // two-stage: the next panel's reduction covers this panel's stage-2 Gram block column
       // when both panels fit one lean reduction; otherwise the update is fused with it
-      const bool lean2 = 2 * sstep <= max_gram_nz(f32);
+      const bool lean2 = 2 * sstep <= kMaxGramNz;
       const bool covered = j < J - 1 && lean2;
       // previous panel's columns reduced along: column 0 for the first panel, else s
       const int nprev = !two ? 0 : (j == 0 ? (g00_here ? 0 : 1) : (lean2 ? sstep : 0));
@@ -894,13 +878,13 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   HIP_LAUNCH_CHECK();
   PanelCtx pc{X, ldx, n, 8, false, c, st, nullptr, 1};
   // column 1 alone
-  TRY(run_step(pc, gram_step(false, 0, 0, 1, 0, TAIL_SA_NORM, -1, 0)));
+  TRY(run_step(pc, gram_step(0, 0, 1, 0, TAIL_SA_NORM, -1, 0)));
   // two-stage with panels: G2(0,0) comes with the first panel's reduction when column 0 and
   // the first panel fit one lean reduction
-  const bool g00 = two && (k == 1 || 1 + std::min(s, k - 1) > max_gram_nz(false));
+  const bool g00 = two && (k == 1 || 1 + std::min(s, k - 1) > kMaxGramNz);
   TRY(run_step(pc, upd_step(g00 ? PK_FUSED : PK_UPDATE, 0, 0, 1, PF_HAS_T | PF_STORE | (g00 ? PF_GRAM_W : 0),
                             g00 ? TAIL_NORM0 : TAIL_NONE, -1, 0)));
-  const bool lean2 = 2 * s <= max_gram_nz(false);
+  const bool lean2 = 2 * s <= kMaxGramNz;
   for (int c0 = 1; c0 < k; c0 += s) {
     const int sw = std::min(s, k - c0);
     const bool last = c0 + sw >= k;
@@ -926,7 +910,7 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   if (orth_err) {
     for (int c0 = 0; c0 < k; c0 += kMaxS) {
       const int sw = std::min(kMaxS, k - c0);
-      TRY(run_step(pc, gram_step(false, c0, c0, sw, 0, TAIL_GRAM_OUT, 0, 0, 0)));
+      TRY(run_step(pc, gram_step(c0, c0, sw, 0, TAIL_GRAM_OUT, 0, 0, 0)));
     }
     hipLaunchKernelGGL(orth_err_kernel, dim3(1), dim3(256), 0, st, c.st, k);
     HIP_LAUNCH_CHECK();
