@@ -188,6 +188,49 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
                              int32_t s, int32_t s_hat, int32_t algo, void* workspace,
                              size_t ws_bytes, void* stream, double* orth_err /* host, opt */);
 
+/* ---------------------------------------------------------------- solve server
+ * Continuous batching of many solves (different operators and sizes) that share one
+ * tsg_solve_params (m, s, ortho, basis monomial or shifted, precision, tol, max_iters;
+ * timing must be 0).  Requests wait in a FIFO queue; at every restart-cycle boundary
+ * tsg_server_step admits queued requests in arrival order while their buffers fit the
+ * arena and a slot is free (a request that does not fit blocks the ones behind it), runs
+ * ONE restart cycle of every active request -- each kernel of the cycle is one launch over
+ * all of them -- and retires the finished ones, whose memory serves the queue next.  A
+ * request computes bit for bit what tsg_solve computes for it (its launches use its own
+ * buffers and block decomposition whatever else is batched).  Not thread-safe: one host
+ * thread drives a server. */
+typedef struct tsg_server_s* tsg_server;
+
+/* Arena bytes one request occupies while active (its admission footprint): reduction
+ * buffers and state, the (m+1)-column basis, and the FP32 copy of the values in the mixed
+ * form.  0 for invalid arguments. */
+size_t tsg_server_request_bytes(int64_t n, int64_t nnz, const tsg_solve_params* p);
+
+/* Create a server.  arena (device, 256-byte aligned, arena_bytes) is caller-owned and must
+ * outlive the server: it holds the launch image of up to max_active requests (512 KiB
+ * each), their status heads, and every admitted request's buffers (the HBM budget).  The
+ * server makes no device allocation; it owns one pinned host buffer of max_active x 64
+ * bytes.  All device work goes to `stream`.  Errors: INVALID_ARG (bad params, max_active
+ * outside [1, 4096]), UNSUPPORTED (timing or a Newton basis), WORKSPACE (arena misaligned
+ * or smaller than the launch images plus 1 MiB). */
+tsg_status tsg_server_create(const tsg_solve_params* p, void* arena, size_t arena_bytes, int32_t max_active,
+                             void* stream, tsg_server* out /* host */);
+tsg_status tsg_server_destroy(tsg_server S);
+
+/* Queue the solve of A x = b.  b[n] and x[n] are device float64 (x holds x0); they and the
+ * CSR handle must stay valid until the request is returned by tsg_server_poll.  tag is the
+ * caller's identifier.  INVALID_ARG if the request could never fit the arena. */
+tsg_status tsg_server_submit(tsg_server S, tsg_csr A, const double* b, double* x, int64_t tag);
+
+/* One restart-cycle boundary: admission, one cycle of every active request, retirement.
+ * Synchronizes the stream (one read-back of all status heads).  n_active / n_queued
+ * (host, optional) receive the counts afterwards. */
+tsg_status tsg_server_step(tsg_server S, int32_t* n_active, int32_t* n_queued);
+
+/* Remove up to max finished requests: tags[i] (host) and infos[i] (host, may be NULL;
+ * iteration counts, residuals and status as from tsg_solve).  Returns how many. */
+int32_t tsg_server_poll(tsg_server S, int64_t* tags, tsg_solve_info* infos, int32_t max);
+
 const char* tsg_status_string(tsg_status st);
 const char* tsg_last_error(void);
 

@@ -9,6 +9,7 @@ PyTorch supplies device memory and streams only.
     A = tsg.CSRMatrix(row_ptr, col, val)              # device tensors (int32, int32, float64)
     x, info = tsg.solve(A, b, m=60, s=5, tol=1e-10)   # two-stage s-step GMRES
     Q, R = tsg.orthogonalize(X, s=5)                  # two-stage block orthogonalization
+    srv = tsg.Server(arena_bytes)                      # continuous batching of many solves
 
 There is no CPU fallback: if the library is missing, every call raises.
 """
@@ -24,4 +25,5 @@ from .binding import (  # noqa: F401
     solve,
     orthogonalize,
     spmv,
+    Server,
 )

@@ -124,6 +124,18 @@ def load_library():
     lib.tsg_orthogonalize_workspace_bytes.restype = C.c_size_t
     lib.tsg_orthogonalize.argtypes = [i64, i32, vp, i64, vp, i32, i32, i32, i32, vp, C.c_size_t, vp, f64p]
     lib.tsg_orthogonalize.restype = C.c_int
+    lib.tsg_server_request_bytes.argtypes = [i64, i64, C.POINTER(_Params)]
+    lib.tsg_server_request_bytes.restype = C.c_size_t
+    lib.tsg_server_create.argtypes = [C.POINTER(_Params), vp, C.c_size_t, i32, vp, C.POINTER(vp)]
+    lib.tsg_server_create.restype = C.c_int
+    lib.tsg_server_destroy.argtypes = [vp]
+    lib.tsg_server_destroy.restype = C.c_int
+    lib.tsg_server_submit.argtypes = [vp, vp, vp, vp, i64]
+    lib.tsg_server_submit.restype = C.c_int
+    lib.tsg_server_step.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    lib.tsg_server_step.restype = C.c_int
+    lib.tsg_server_poll.argtypes = [vp, C.POINTER(i64), C.POINTER(_Info), i32]
+    lib.tsg_server_poll.restype = i32
     lib.tsg_status_string.argtypes = [C.c_int]
     lib.tsg_status_string.restype = C.c_char_p
     lib.tsg_last_error.argtypes = []
@@ -306,3 +318,76 @@ def orthogonalize(X: torch.Tensor, s: int = 5, algo: str = "two_stage", *, ldx: 
     if orth_err:
         return X, Rt, err.value
     return X, Rt
+
+
+def _info_to_py(info: _Info) -> SolveInfo:
+    vals = {}
+    for f, _ in _Info._fields_:
+        v = getattr(info, f)
+        vals[f] = tuple(v) if f.startswith("kc_") else v
+    return SolveInfo(**vals)
+
+
+class Server:
+    """Continuous-batching solve server (tsg_server_* in the C ABI).
+
+    Requests share the solver parameters; each brings its own CSR operator, right-hand side
+    and solution vector (device tensors, kept referenced here until the request is polled).
+    ``arena_bytes`` of device memory is allocated once (torch) and is the HBM budget that
+    admission checks against; the library allocates nothing.
+    """
+
+    def __init__(self, arena_bytes: int, *, m: int = 60, s: int = 5, tol: float = 1e-8,
+                 max_iters: int = 1 << 40, ortho: str = "two_stage", basis: str = "shifted",
+                 precision: str = "fp32_ir", max_active: int = 256, device="cuda"):
+        lib = load_library()
+        self._p, _ = _params(m, s, ortho, basis, precision, tol, max_iters, None, False)
+        self.device = torch.device(device)
+        self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
+        base = (self._arena.data_ptr() + 255) // 256 * 256
+        self.arena_bytes = int(arena_bytes)
+        h = C.c_void_p()
+        _check(lib.tsg_server_create(C.byref(self._p), base, self.arena_bytes, int(max_active),
+                                     _stream(self.device), C.byref(h)))
+        self._h = h
+        self._live = {}  # tag -> (A, b, x) kept alive while the request is in the server
+
+    def request_bytes(self, A: CSRMatrix) -> int:
+        return int(load_library().tsg_server_request_bytes(A.n, A.nnz, C.byref(self._p)))
+
+    def submit(self, tag: int, A: CSRMatrix, b: torch.Tensor, x: torch.Tensor | None = None) -> torch.Tensor:
+        _dev_tensor(b, torch.float64, "b")
+        if x is None:
+            x = torch.zeros_like(b)
+        _dev_tensor(x, torch.float64, "x")
+        _check(load_library().tsg_server_submit(self._h, A.handle, b.data_ptr(), x.data_ptr(), int(tag)))
+        self._live[int(tag)] = (A, b, x)
+        return x
+
+    def step(self):
+        """One restart-cycle boundary.  Returns (active, queued)."""
+        na, nq = C.c_int32(), C.c_int32()
+        _check(load_library().tsg_server_step(self._h, C.byref(na), C.byref(nq)))
+        return na.value, nq.value
+
+    def poll(self, max_n: int = 1024):
+        """Finished requests: list of (tag, x, SolveInfo)."""
+        tags = (C.c_int64 * max_n)()
+        infos = (_Info * max_n)()
+        k = load_library().tsg_server_poll(self._h, tags, infos, max_n)
+        out = []
+        for i in range(k):
+            A, b, x = self._live.pop(int(tags[i]))
+            out.append((int(tags[i]), x, _info_to_py(infos[i])))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().tsg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

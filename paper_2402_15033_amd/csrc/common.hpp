@@ -19,6 +19,20 @@ constexpr int kTailThreads = 1024;  // threads of the one-block tail kernels
 constexpr double kPivotTolF64 = 1e-12;
 constexpr double kPivotTolF32 = 1e-5;
 
+// Device (global) memory as the compiler's address space 1.  The kernels take their
+// pointers from a per-launch argument table in memory, so to the compiler they are
+// generic pointers and their accesses would be flat instructions (which also count
+// against the LDS wait counter, and never become scalar loads).  Every pointer of the
+// table points to device memory; the hot loops access it through gbl<T>* pointers,
+// which compile to global loads and stores, and to scalar loads for wave-uniform
+// addresses.
+template <typename T>
+using gbl = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gbl<T>* G(T* p) {
+  return (gbl<T>*)p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

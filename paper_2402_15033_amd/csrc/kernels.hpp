@@ -23,9 +23,9 @@ constexpr int kSegCap = 8 * kWave;  // products staged per wave (rows of <= 8 no
 // multiplied by the gathered x, staged in LDS, and every lane then sums its own row's
 // slice.  Segments longer than kSegCap fall back to the per-row loop.
 template <typename T, typename VT>
-__device__ __forceinline__ T csr_row_dot(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                                         const VT* __restrict__ val, const T* __restrict__ x, int64_t n,
-                                         int64_t r0, int lane, T* prod) {
+__device__ __forceinline__ T csr_row_dot(gbl<const int32_t>* __restrict__ row_ptr,
+                                         gbl<const int32_t>* __restrict__ col, gbl<const VT>* __restrict__ val,
+                                         gbl<const T>* __restrict__ x, int64_t n, int64_t r0, int lane, T* prod) {
   const int64_t r = r0 + lane;
   const int nrows = (int)min((int64_t)kWave, n - r0);
   const int rp = (r < n) ? row_ptr[r] : 0;
@@ -55,24 +55,45 @@ __device__ __forceinline__ T csr_row_dot(const int32_t* __restrict__ row_ptr, co
 // 4 waves x 64 rows per block; blocks are mapped XCD-contiguously so the x gathers of
 // neighbouring rows hit the same L2.  Values of type VT (float64, or the float32 copy of
 // the mixed-precision form), vectors of type T.
+struct MpkArgs {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const void* val;  // VT[nnz]
+  const void* x;    // T[n]
+  void* y;          // T[n]
+  int64_t n;
+  double theta, sigma;
+  const SmallState* st;
+  int32_t panel;
+  int32_t pad;
+};
 template <typename T, typename VT>
-__global__ __launch_bounds__(kRowBlock) void mpk_step_kernel(
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-    const VT* __restrict__ val, const T* __restrict__ x, T* __restrict__ y, int64_t n,
-    double theta, double sigma, const SmallState* __restrict__ st, int panel) {
-  if (st->h.done || panel > st->h.stop_panel) return;
-  __shared__ T prod[kRowBlock / kWave][kSegCap];
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int64_t r0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kRowBlock + wv * kWave;
-  if (r0 >= n) return;
-  const T acc = csr_row_dot<T, VT>(row_ptr, col, val, x, n, r0, lane, prod[wv]);
-  const int64_t r = r0 + lane;
-  if (r < n) {
-    T v = acc;
-    if (theta != 0.0) v -= (T)theta * x[r];
-    y[r] = v / (T)sigma;
+struct MpkBody {
+  typedef MpkArgs Args;
+  static constexpr int kThreads = kRowBlock;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const MpkArgs& a, int bid, int nb) {
+    gbl<const SmallState>* st = G(a.st);
+    if (st->h.done || a.panel > st->h.stop_panel) return;
+    gbl<const int32_t>* __restrict__ row_ptr = G(a.row_ptr);
+    gbl<const int32_t>* __restrict__ col = G(a.col);
+    gbl<const VT>* __restrict__ val = G(reinterpret_cast<const VT*>(a.val));
+    gbl<const T>* __restrict__ x = G(reinterpret_cast<const T*>(a.x));
+    gbl<T>* __restrict__ y = G(reinterpret_cast<T*>(a.y));
+    const int64_t n = a.n;
+    __shared__ T prod[kRowBlock / kWave][kSegCap];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t r0 = (int64_t)xcd_tile(bid, nb) * kRowBlock + wv * kWave;
+    if (r0 >= n) return;
+    const T acc = csr_row_dot<T, VT>(row_ptr, col, val, x, n, r0, lane, prod[wv]);
+    const int64_t r = r0 + lane;
+    if (r < n) {
+      T v = acc;
+      if (a.theta != 0.0) v -= (T)a.theta * x[r];
+      y[r] = v / (T)a.sigma;
+    }
   }
-}
+};
 
 // y = A x in float64 (stand-alone SpMV entry point).
 __global__ __launch_bounds__(kRowBlock) void spmv_f64_kernel(
@@ -92,15 +113,39 @@ __global__ __launch_bounds__(kRowBlock) void spmv_f64_kernel(
 // partials.  residual_tail_kernel sums them in a fixed order and decides convergence
 // (explicit residual test), then initializes the cycle: beta, T = 1/beta for the
 // scaling pass, Givens rhs, cleared Hessenberg and stage-2 Gram.
+struct ResidArgs {
+  const int32_t* row_ptr;
+  const int32_t* col;
+  const double* val;
+  const double* x;
+  const double* b;
+  void* r_out;  // T[n]: basis column 0
+  int64_t n;
+  const SmallState* st;
+  double* part1;
+};
 template <typename T>
-__global__ __launch_bounds__(kRowBlock) void residual_kernel(
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-    const double* __restrict__ val, const double* __restrict__ x, const double* __restrict__ b,
-    T* __restrict__ r_out, int64_t n, const SmallState* __restrict__ st, double* part1) {
+struct ResidBody {
+  typedef ResidArgs Args;
+  static constexpr int kThreads = kRowBlock;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const ResidArgs& a, int bid, int nb);
+};
+template <typename T>
+__device__ void ResidBody<T>::run(const ResidArgs& a, int bid, int nb) {
+  gbl<const SmallState>* __restrict__ st = G(a.st);
   if (st->h.done) return;
+  gbl<const int32_t>* __restrict__ row_ptr = G(a.row_ptr);
+  gbl<const int32_t>* __restrict__ col = G(a.col);
+  gbl<const double>* __restrict__ val = G(a.val);
+  gbl<const double>* __restrict__ x = G(a.x);
+  gbl<const double>* __restrict__ b = G(a.b);
+  gbl<T>* __restrict__ r_out = G(reinterpret_cast<T*>(a.r_out));
+  const int64_t n = a.n;
+  gbl<double>* part1 = G(a.part1);
   __shared__ double prod[kRowBlock / kWave][kSegCap];
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int64_t r0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kRowBlock + wv * kWave;
+  const int64_t r0 = (int64_t)xcd_tile(bid, nb) * kRowBlock + wv * kWave;
   double rr = 0.0;
   if (r0 < n) {
     const double acc = csr_row_dot<double, double>(row_ptr, col, val, x, n, r0, lane, prod[wv]);
@@ -118,12 +163,27 @@ __global__ __launch_bounds__(kRowBlock) void residual_kernel(
   if (threadIdx.x == 0) {
     double sum = 0.0;
     for (int w = 0; w < kRowBlock / kWave; ++w) sum += wsum[w];
-    part1[blockIdx.x] = sum;
+    part1[bid] = sum;
   }
 }
 
-__global__ __launch_bounds__(kTailThreads) void residual_tail_kernel(SmallState* st, const double* part1,
-                                                                     int nblocks) {
+// Arguments of the one-block kernels that act on one request's small state.
+struct TailArgs {
+  SmallState* st;
+  const double* part1;
+  int32_t nblocks;
+  int32_t two_stage;
+};
+struct RTailBody {
+  typedef TailArgs Args;
+  static constexpr int kThreads = kTailThreads;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const TailArgs& a, int bid, int nb);
+};
+__device__ void RTailBody::run(const TailArgs& a, int, int) {
+  SmallState* st = a.st;
+  const double* part1 = a.part1;
+  const int nblocks = a.nblocks;
   if (st->h.done) return;
   __shared__ double s_tot[1];
   __shared__ double scratch[kTailThreads];
@@ -253,18 +313,30 @@ __global__ __launch_bounds__(kRowBlock) void to_f32_kernel(const double* __restr
 
 // ------------------------------------------------------------------ solution update
 // x += V(:, 0:ku) coef (x float64, basis type T).  coef is uniform across the block.
+struct XupdArgs {
+  double* x;
+  const void* V;  // T basis
+  int64_t ld, n;
+  const SmallState* st;
+};
 template <typename T>
-__global__ __launch_bounds__(kRowBlock) void xupdate_kernel(double* __restrict__ x,
-                                                            const T* __restrict__ V, int64_t ld,
-                                                            int64_t n, const SmallState* __restrict__ st) {
-  if (st->h.done) return;
-  const int ku = st->h.k_used;
-  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
-  if (r >= n) return;
-  double acc = 0.0;
-  for (int c = 0; c < ku; ++c) acc += (double)V[(int64_t)c * ld + r] * st->coef[c];
-  x[r] += acc;
-}
+struct XupdBody {
+  typedef XupdArgs Args;
+  static constexpr int kThreads = kRowBlock;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const XupdArgs& a, int bid, int) {
+    gbl<const SmallState>* __restrict__ st = G(a.st);
+    if (st->h.done) return;
+    gbl<const T>* __restrict__ V = G(reinterpret_cast<const T*>(a.V));
+    gbl<double>* __restrict__ x = G(a.x);
+    const int ku = st->h.k_used;
+    const int64_t r = (int64_t)bid * kRowBlock + threadIdx.x;
+    if (r >= a.n) return;
+    double acc = 0.0;
+    for (int c = 0; c < ku; ++c) acc += (double)V[(int64_t)c * a.ld + r] * st->coef[c];
+    x[r] += acc;
+  }
+};
 
 // ------------------------------------------------------------------ end of cycle
 // Back substitution z = U(0:k,0:k)^{-1} g(0:k) for upper-triangular U in LDS (ld kLd),
@@ -287,7 +359,15 @@ __device__ void wave_back_subst(const double* U, double* g, double* z, int k) {
 // (substitute y = R2 z), so neither R2^{-1} nor H is formed; x += Qhat z follows.  Other
 // variants: z from the incremental Givens factorization of their Hessenberg matrix.  Then
 // the iteration counters advance.
-__global__ __launch_bounds__(256) void cycle_end_kernel(SmallState* st, int two_stage) {
+struct CycleEndBody {
+  typedef TailArgs Args;
+  static constexpr int kThreads = 256;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const TailArgs& a, int bid, int nb);
+};
+__device__ void CycleEndBody::run(const TailArgs& a, int, int) {
+  SmallState* st = a.st;
+  const int two_stage = a.two_stage;
   if (st->h.done) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ double sG[kLd * kLd];

@@ -66,8 +66,10 @@ struct PanelArgs {
   double* part1;     // per-block partial Grams, nblocks x (k+sw)*sw
 };
 
-__device__ __forceinline__ bool gated_off(const PanelArgs& a, const SmallState* st) {
+
+__device__ __forceinline__ bool gated_off(const PanelArgs& a, const SmallState* st_) {
   if (!a.gate) return false;
+  gbl<const SmallState>* st = G(st_);
   if (st->h.done || a.panel > st->h.stop_panel) return true;
   return a.gate == 2 && st->h.refine != a.panel + 1;
 }
@@ -399,21 +401,39 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
 // First level of a cross-block reduction with many blocks: block g sums the partials of
 // blocks [g*chunk, min(nblocks, (g+1)*chunk)) in block order, for every entry, into
 // part2[g * E + e].  The tail then sums the few group partials in group order.
-__global__ __launch_bounds__(256) void partial_reduce_kernel(PanelArgs a, double* part2, int chunk) {
-  const SmallState* st = a.st;
-  if (gated_off(a, st)) return;
-  const int E = (a.k + a.sw) * a.nz;
-  const int b0 = blockIdx.x * chunk, b1 = min(a.nblocks, b0 + chunk);
-  for (int e = threadIdx.x; e < E; e += blockDim.x) {
-    double acc = 0.0;
-    for (int b = b0; b < b1; ++b) acc += a.part1[(size_t)b * E + e];
-    part2[(size_t)blockIdx.x * E + e] = acc;
+struct RedArgs {
+  PanelArgs a;
+  double* part2;
+  int32_t chunk;
+  int32_t pad;
+};
+struct PReduceBody {
+  typedef RedArgs Args;
+  static constexpr int kThreads = 256;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const RedArgs& ra, int bid, int) {
+    const PanelArgs& a = ra.a;
+    const SmallState* st = a.st;
+    if (gated_off(a, st)) return;
+    const int E = (a.k + a.sw) * a.nz;
+    const int b0 = bid * ra.chunk, b1 = min(a.nblocks, b0 + ra.chunk);
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+      double acc = 0.0;
+      for (int b = b0; b < b1; ++b) acc += a.part1[(size_t)b * E + e];
+      ra.part2[(size_t)bid * E + e] = acc;
+    }
   }
-}
+};
 
 // The reduction of a panel launch: one block sums the per-block partial Grams in a fixed
 // order and runs the FP64 tail (Cholesky, Hessenberg block, Givens, ...).
-__global__ __launch_bounds__(kTailThreads) void panel_tail_kernel(PanelArgs a) {
+struct PTailBody {
+  typedef PanelArgs Args;
+  static constexpr int kThreads = kTailThreads;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const PanelArgs& a, int bid, int nb);
+};
+__device__ void PTailBody::run(const PanelArgs& a, int, int) {
   SmallState* st = a.st;
   if (gated_off(a, st)) return;
   __shared__ double sred[kMaxCols * kMaxNz];

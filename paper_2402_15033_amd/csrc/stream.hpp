@@ -69,7 +69,7 @@ struct TileLoad {
       ldsof[sl] = c * LDT + chunk * kWave * R;
     }
   }
-  __device__ void load(const T* __restrict__ V, int wv, int lane, int64_t r0, int64_t re,
+  __device__ void load(gbl<const T>* __restrict__ V, int wv, int lane, int64_t r0, int64_t re,
                        T (&dst)[SL][R]) const {
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
@@ -77,7 +77,8 @@ struct TileLoad {
       const int64_t row = r0 + rowoff[sl] + (int64_t)R * lane;
       if (t < items && row + R <= re) {
         if constexpr (R == 2) {
-          const float2 x = *reinterpret_cast<const float2*>(V + colbase[sl] + row);
+          typedef float f2 __attribute__((ext_vector_type(2)));
+          const f2 x = *reinterpret_cast<gbl<const f2>*>(V + colbase[sl] + row);
           dst[sl][0] = x.x;
           dst[sl][1] = x.y;
         } else {
@@ -111,22 +112,28 @@ struct TileLoad {
 // in LDS in wave order (in float64) at the end.  Partials: ncol x nz float64 per block.
 // Requires ncol <= 16 MT, nz <= 16 NT.
 template <typename T, int MT, int NT>
-__global__ __launch_bounds__(512) void gram_mfma_kernel(PanelArgs a) {
-  SmallState* st = a.st;
-  if (gated_off(a, st)) return;
+struct GramBody {
+  typedef PanelArgs Args;
+  static constexpr int kThreads = 512;
+  static constexpr int kMinWaves = 4;  // two 8-wave blocks per CU: at most 128 VGPRs
+  static __device__ void run(const PanelArgs& a, int bid, int nb);
+};
+template <typename T, int MT, int NT>
+__device__ void GramBody<T, MT, NT>::run(const PanelArgs& a, int bid, int) {
+  if (gated_off(a, a.st)) return;
   typedef typename MfmaOp<T>::v4 v4;
   typedef TileLoad<T> TL;
   constexpr int NW = 8, SL = TL::SL, R = TL::R;
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
   const int k = a.k, ncol = a.k + a.sw, nz = a.nz, z0 = ncol - nz;
-  const T* __restrict__ V = reinterpret_cast<const T*>(a.V);
+  gbl<const T>* __restrict__ V = G(reinterpret_cast<const T*>(a.V));
   __shared__ T lt[2][mfma_tile<T>()];
   TL tl;
   tl.init(wv, ncol, k, a.wcol, a.ld);
   const int BR = tl.BR, LDT = tl.LDT;
 
-  const int64_t rb = (int64_t)blockIdx.x * a.rows_per_block;
+  const int64_t rb = (int64_t)bid * a.rows_per_block;
   const int64_t re = min(a.n, rb + a.rows_per_block);
   T v[SL][R], vn[SL][R], vnn[SL][R];
   v4 acc[MT][NT];
@@ -173,7 +180,7 @@ __global__ __launch_bounds__(512) void gram_mfma_kernel(PanelArgs a) {
   // sum the 8 waves' partial tiles in wave order, one 16-wide Z tile at a time:
   // red[w][c][z], c < 64, z < 16 (8 x 64 x 16 values fit in the two LDS buffers)
   T* red = &lt[0][0];
-  double* part = a.part1 + (size_t)blockIdx.x * ncol * nz;
+  gbl<double>* part = G(a.part1) + (size_t)bid * ncol * nz;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     __syncthreads();
@@ -201,22 +208,29 @@ __global__ __launch_bounds__(512) void gram_mfma_kernel(PanelArgs a) {
 // its row of the k + sw columns (each wave access is a coalesced 64-row segment of one
 // column), P and T are uniform (scalar loads).  No LDS, no barrier, high occupancy.
 template <typename T, int S>
-__global__ __launch_bounds__(256) void update_kernel(PanelArgs a) {
-  const SmallState* st = a.st;
-  if (gated_off(a, st)) return;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+struct UpdateBody {
+  typedef PanelArgs Args;
+  static constexpr int kThreads = 256;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const PanelArgs& a, int bid, int nb);
+};
+template <typename T, int S>
+__device__ void UpdateBody<T, S>::run(const PanelArgs& a, int bid, int) {
+  if (gated_off(a, a.st)) return;
+  gbl<const SmallState>* st = G(a.st);
+  const int64_t r = (int64_t)bid * blockDim.x + threadIdx.x;
   if (r >= a.n) return;
   const int k = a.k, sw = a.sw;
   const bool hasP = a.flags & PF_HAS_P;
   const bool hasT = (a.flags & PF_HAS_T) && !st->identity_t;
-  T* __restrict__ V = reinterpret_cast<T*>(a.V);
+  gbl<T>* __restrict__ V = G(reinterpret_cast<T*>(a.V));
   const int64_t ld = a.ld;
-  T* W = V + (int64_t)a.wcol * ld + r;
+  gbl<T>* W = V + (int64_t)a.wcol * ld + r;
   T y[S];
 #pragma unroll
   for (int j = 0; j < S; ++j) y[j] = (j < sw) ? W[(int64_t)j * ld] : (T)0;
   if (hasP) {
-    const double* P = st->Pcur;
+    gbl<const double>* P = st->Pcur;
 #pragma unroll 8
     for (int c = 0; c < k; ++c) {
       const T qc = V[(int64_t)c * ld + r];
@@ -225,7 +239,7 @@ __global__ __launch_bounds__(256) void update_kernel(PanelArgs a) {
     }
   }
   if (hasT) {
-    const double* Tm = st->Tcur;
+    gbl<const double>* Tm = st->Tcur;
 #pragma unroll
     for (int j = S - 1; j >= 0; --j) {
       T v = (T)0;
@@ -252,9 +266,16 @@ __global__ __launch_bounds__(256) void update_kernel(PanelArgs a) {
 // matrix cores then reduce the tile, and the waves store q from LDS in whole row segments.
 // Partials: (k + sw) x sw float64 per block (rows of Q zero unless PF_GRAM_Q).
 template <typename T, int MT, int S>
-__global__ __launch_bounds__(512) void panel_mfma_kernel(PanelArgs a) {
-  SmallState* st = a.st;
-  if (gated_off(a, st)) return;
+struct FusedBody {
+  typedef PanelArgs Args;
+  static constexpr int kThreads = 512;
+  static constexpr int kMinWaves = S <= 10 ? 4 : 1;  // two 8-wave blocks per CU up to s = 10
+  static __device__ void run(const PanelArgs& a, int bid, int nb);
+};
+template <typename T, int MT, int S>
+__device__ void FusedBody<T, MT, S>::run(const PanelArgs& a, int bid, int) {
+  if (gated_off(a, a.st)) return;
+  gbl<const SmallState>* st = G(a.st);
   typedef typename MfmaOp<T>::v4 v4;
   typedef TileLoad<T> TL;
   constexpr int NW = 8, SL = TL::SL, R = TL::R;
@@ -270,7 +291,7 @@ __global__ __launch_bounds__(512) void panel_mfma_kernel(PanelArgs a) {
   const int ncol = kq + sw;                // staged columns: Q then W
   const int a0 = gramQ ? 0 : kq;           // first staged column on the A side of the Gram
   const int ncolA = ncol - a0;
-  T* __restrict__ V = reinterpret_cast<T*>(a.V);
+  gbl<T>* __restrict__ V = G(reinterpret_cast<T*>(a.V));
   const int64_t ld = a.ld;
   __shared__ T lt[2][mfma_tile<T>()];
   __shared__ T lP[kMaxCols * S];
@@ -290,7 +311,7 @@ __global__ __launch_bounds__(512) void panel_mfma_kernel(PanelArgs a) {
   const int rows_pass = 512 / parts;
   const int part = tid % parts;
 
-  const int64_t rb = (int64_t)blockIdx.x * a.rows_per_block;
+  const int64_t rb = (int64_t)bid * a.rows_per_block;
   const int64_t re = min(a.n, rb + a.rows_per_block);
   T v[SL][R], vn[SL][R], vnn[SL][R];
   v4 acc[MT];
@@ -387,7 +408,7 @@ __global__ __launch_bounds__(512) void panel_mfma_kernel(PanelArgs a) {
       red[(wv * kMaxCols + c) * 16 + li] = acc[mt][r];
     }
   __syncthreads();
-  double* part1 = a.part1 + (size_t)blockIdx.x * (k + sw) * sw;
+  gbl<double>* part1 = G(a.part1) + (size_t)bid * (k + sw) * sw;
   if (!gramQ) {
     for (int e = tid; e < k * sw; e += blockDim.x) part1[e] = 0.0;
   }
@@ -402,6 +423,27 @@ __global__ __launch_bounds__(512) void panel_mfma_kernel(PanelArgs a) {
       part1[prow * sw + z] = sum;
     }
   }
+}
+
+// ----------------------------------------------------------------------------- launcher
+// Every per-request kernel of a restart cycle runs through this launcher: one launch
+// serves a batch of requests (one, for a plain solve).  Request r owns blocks
+// bstart[r] .. bstart[r+1]-1 of the grid and reads its arguments from args[r]; its body
+// sees its own block index and block count, so a request computes exactly the same
+// thing whatever else shares the launch.
+template <typename Body>
+__global__ __launch_bounds__(Body::kThreads, Body::kMinWaves) void batched_kernel(const typename Body::Args* __restrict__ args,
+                                                                 const int* __restrict__ bstart, int nreq) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nreq - 1;  // last r with bstart[r] <= b (requests with no block are skipped)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bstart[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const typename Body::Args a = args[lo];  // into registers: the bodies' memory clobbers
+                                           // would otherwise reload the fields
+  Body::run(a, b - bstart[lo], bstart[lo + 1] - bstart[lo]);
 }
 
 }  // namespace tsg

@@ -186,79 +186,165 @@ struct Timer {
   }
 };
 
-// ------------------------------------------------------------------ panel launchers
-struct PanelCtx {
-  void* V;
-  int64_t ld, n;
-  int elem;  // sizeof(T)
-  bool f32;
-  Common c;
-  hipStream_t stream;
-  Timer* timer;
-  int standalone;
-};
+// ------------------------------------------------------------------ launch programs
+// A restart cycle (or a stand-alone orthogonalization) is a fixed sequence of phases; every
+// phase is one launch of batched_kernel<Body> over a batch of requests (one request for
+// tsg_solve / tsg_orthogonalize, many for the server).  A Program holds the phases and a
+// host image of every launch's per-request arguments and block starts; the image is
+// copied to the device once, and executing the program only launches kernels, so it can
+// be replayed cycle after cycle (or captured into a graph).
 
 // Round a panel width up to an instantiated template width.
 int s_template(int sw) { return sw <= 6 ? sw : (sw <= 8 ? 8 : (sw <= 10 ? 10 : (sw <= 12 ? 12 : 16))); }
-constexpr int kMaxGramNz = kMaxNz;  // widest lean reduction (two 16-wide MFMA tiles)
-constexpr int kMaxMfmaBlocks = 512;  // two 8-wave blocks per CU
-static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks,
-              "reduction partial buffer too small");
-
 // Panel widths with a fused-kernel instantiation (a panel runs in the smallest one >= sw).
 int fused_s(int sw) { return sw <= 1 ? 1 : sw <= 2 ? 2 : sw <= 4 ? 4 : sw <= 5 ? 5 : sw <= 8 ? 8 : sw <= 10 ? 10 : 16; }
-// Columns staged by the fused kernel (Q only when the step projects or reduces against it).
+constexpr int kMaxGramNz = kMaxNz;   // widest lean reduction (two 16-wide MFMA tiles)
+constexpr int kMaxMfmaBlocks = 512;  // two 8-wave blocks per CU
+static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks, "reduction partial buffer too small");
+// Device bytes reserved for the launch image of one request's program.
+constexpr size_t kProgramBytesPerRequest = 512 * 1024;
+
+enum Family : int { F_RESID, F_RTAIL, F_UPDATE, F_MPK, F_GRAM, F_PREDUCE, F_PTAIL, F_FUSED, F_CYCLE_END, F_XUPD };
+
+struct Phase {
+  Family f;
+  int t1 = 0, t2 = 0;  // template selectors: S (update), MT/NT (gram), MT/S (fused)
+  size_t aoff = 0, boff = 0;
+  int blocks = 0;
+  int tclass = -1;     // >= 0: a timing span of this kernel class starts at this phase
+  double bytes = 0.0;  // algorithmic bytes of that span, all requests
+};
+
+struct Program {
+  bool f32 = false;
+  int nreq = 0;
+  std::vector<char> blob;
+  std::vector<Phase> phases;
+  size_t put(const void* p, size_t bytes) {
+    size_t off = align_up(blob.size(), 16);
+    blob.resize(off + bytes);
+    std::memcpy(blob.data() + off, p, bytes);
+    return off;
+  }
+  template <typename A>
+  void add(Family f, int t1, int t2, const std::vector<A>& args, const std::vector<int>& blocks, int tclass,
+           double bytes) {
+    std::vector<int> bs(args.size() + 1, 0);
+    for (size_t r = 0; r < args.size(); ++r) bs[r + 1] = bs[r] + blocks[r];
+    if (bs.back() == 0) return;  // no request has work in this phase
+    Phase ph;
+    ph.f = f;
+    ph.t1 = t1;
+    ph.t2 = t2;
+    ph.aoff = put(args.data(), sizeof(A) * args.size());
+    ph.boff = put(bs.data(), sizeof(int) * bs.size());
+    ph.blocks = bs.back();
+    ph.tclass = tclass;
+    ph.bytes = bytes;
+    phases.push_back(ph);
+  }
+};
+
+template <typename Body>
+void launch_b(const Phase& ph, const char* d, int nreq, hipStream_t s) {
+  hipLaunchKernelGGL((batched_kernel<Body>), dim3(ph.blocks), dim3(Body::kThreads), 0, s,
+                     reinterpret_cast<const typename Body::Args*>(d + ph.aoff),
+                     reinterpret_cast<const int*>(d + ph.boff), nreq);
+}
 template <typename T, int MT>
-void launch_fused_mt(const PanelArgs& a, int nb, hipStream_t s) {
-  switch (fused_s(a.sw)) {
-    case 1: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 1>), dim3(nb), dim3(512), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 2>), dim3(nb), dim3(512), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 4>), dim3(nb), dim3(512), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 5>), dim3(nb), dim3(512), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 8>), dim3(nb), dim3(512), 0, s, a); break;
-    case 10: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 10>), dim3(nb), dim3(512), 0, s, a); break;
-    default: hipLaunchKernelGGL((panel_mfma_kernel<T, MT, 16>), dim3(nb), dim3(512), 0, s, a); break;
-  }
-}
-// ncolA: columns on the A side of the fused kernel's Gram ([Q, q] or q alone)
-template <typename T>
-void launch_fused(const PanelArgs& a, int ncolA, int nb, hipStream_t s) {
-  switch ((ncolA + 15) / 16) {
-    case 1: launch_fused_mt<T, 1>(a, nb, s); break;
-    case 2: launch_fused_mt<T, 2>(a, nb, s); break;
-    case 3: launch_fused_mt<T, 3>(a, nb, s); break;
-    default: launch_fused_mt<T, 4>(a, nb, s); break;
+void launch_fused_mt(const Phase& ph, const char* d, int nreq, hipStream_t s) {
+  switch (ph.t2) {
+    case 1: launch_b<FusedBody<T, MT, 1>>(ph, d, nreq, s); break;
+    case 2: launch_b<FusedBody<T, MT, 2>>(ph, d, nreq, s); break;
+    case 4: launch_b<FusedBody<T, MT, 4>>(ph, d, nreq, s); break;
+    case 5: launch_b<FusedBody<T, MT, 5>>(ph, d, nreq, s); break;
+    case 8: launch_b<FusedBody<T, MT, 8>>(ph, d, nreq, s); break;
+    case 10: launch_b<FusedBody<T, MT, 10>>(ph, d, nreq, s); break;
+    default: launch_b<FusedBody<T, MT, 16>>(ph, d, nreq, s); break;
   }
 }
 template <typename T, int MT>
-void launch_gram_mt(const PanelArgs& a, int nb, hipStream_t s) {
-  if (a.nz <= 16) hipLaunchKernelGGL((gram_mfma_kernel<T, MT, 1>), dim3(nb), dim3(512), 0, s, a);
-  else hipLaunchKernelGGL((gram_mfma_kernel<T, MT, 2>), dim3(nb), dim3(512), 0, s, a);
+void launch_gram_mt(const Phase& ph, const char* d, int nreq, hipStream_t s) {
+  if (ph.t2 == 1) launch_b<GramBody<T, MT, 1>>(ph, d, nreq, s);
+  else launch_b<GramBody<T, MT, 2>>(ph, d, nreq, s);
 }
 template <typename T>
-void launch_gram(const PanelArgs& a, int nb, hipStream_t s) {
-  switch ((a.k + a.sw + 15) / 16) {
-    case 1: launch_gram_mt<T, 1>(a, nb, s); break;
-    case 2: launch_gram_mt<T, 2>(a, nb, s); break;
-    case 3: launch_gram_mt<T, 3>(a, nb, s); break;
-    default: launch_gram_mt<T, 4>(a, nb, s); break;
+void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
+  switch (ph.f) {
+    case F_RESID: launch_b<ResidBody<T>>(ph, d, nreq, s); break;
+    case F_RTAIL: launch_b<RTailBody>(ph, d, nreq, s); break;
+    case F_MPK: launch_b<MpkBody<T, T>>(ph, d, nreq, s); break;
+    case F_PREDUCE: launch_b<PReduceBody>(ph, d, nreq, s); break;
+    case F_PTAIL: launch_b<PTailBody>(ph, d, nreq, s); break;
+    case F_CYCLE_END: launch_b<CycleEndBody>(ph, d, nreq, s); break;
+    case F_XUPD: launch_b<XupdBody<T>>(ph, d, nreq, s); break;
+    case F_UPDATE:
+      switch (ph.t1) {
+        case 1: launch_b<UpdateBody<T, 1>>(ph, d, nreq, s); break;
+        case 2: launch_b<UpdateBody<T, 2>>(ph, d, nreq, s); break;
+        case 3: launch_b<UpdateBody<T, 3>>(ph, d, nreq, s); break;
+        case 4: launch_b<UpdateBody<T, 4>>(ph, d, nreq, s); break;
+        case 5: launch_b<UpdateBody<T, 5>>(ph, d, nreq, s); break;
+        case 6: launch_b<UpdateBody<T, 6>>(ph, d, nreq, s); break;
+        case 8: launch_b<UpdateBody<T, 8>>(ph, d, nreq, s); break;
+        case 10: launch_b<UpdateBody<T, 10>>(ph, d, nreq, s); break;
+        case 12: launch_b<UpdateBody<T, 12>>(ph, d, nreq, s); break;
+        default: launch_b<UpdateBody<T, 16>>(ph, d, nreq, s); break;
+      }
+      break;
+    case F_GRAM:
+      switch (ph.t1) {
+        case 1: launch_gram_mt<T, 1>(ph, d, nreq, s); break;
+        case 2: launch_gram_mt<T, 2>(ph, d, nreq, s); break;
+        case 3: launch_gram_mt<T, 3>(ph, d, nreq, s); break;
+        default: launch_gram_mt<T, 4>(ph, d, nreq, s); break;
+      }
+      break;
+    case F_FUSED:
+      switch (ph.t1) {
+        case 1: launch_fused_mt<T, 1>(ph, d, nreq, s); break;
+        case 2: launch_fused_mt<T, 2>(ph, d, nreq, s); break;
+        case 3: launch_fused_mt<T, 3>(ph, d, nreq, s); break;
+        default: launch_fused_mt<T, 4>(ph, d, nreq, s); break;
+      }
+      break;
   }
 }
-template <typename T>
-void launch_update(const PanelArgs& a, int nb, hipStream_t s) {
-  switch (s_template(a.sw)) {
-    case 1: hipLaunchKernelGGL((update_kernel<T, 1>), dim3(nb), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((update_kernel<T, 2>), dim3(nb), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((update_kernel<T, 3>), dim3(nb), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((update_kernel<T, 4>), dim3(nb), dim3(256), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((update_kernel<T, 5>), dim3(nb), dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((update_kernel<T, 6>), dim3(nb), dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((update_kernel<T, 8>), dim3(nb), dim3(256), 0, s, a); break;
-    case 10: hipLaunchKernelGGL((update_kernel<T, 10>), dim3(nb), dim3(256), 0, s, a); break;
-    case 12: hipLaunchKernelGGL((update_kernel<T, 12>), dim3(nb), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((update_kernel<T, 16>), dim3(nb), dim3(256), 0, s, a); break;
+
+// Launch phases [first, last) of a program whose image is at d (device).
+tsg_status exec_program(const Program& P, const char* d, hipStream_t s, Timer* timer, size_t first = 0,
+                        size_t last = (size_t)-1) {
+  last = std::min(last, P.phases.size());
+  bool open = false;
+  for (size_t i = first; i < last; ++i) {
+    const Phase& ph = P.phases[i];
+    if (timer && ph.tclass >= 0) {
+      if (open) timer->end(s);
+      timer->begin(s, ph.tclass, ph.bytes);
+      open = true;
+    }
+    if (P.f32) launch_phase_t<float>(ph, d, P.nreq, s);
+    else launch_phase_t<double>(ph, d, P.nreq, s);
+    HIP_LAUNCH_CHECK();
   }
+  if (timer && open) timer->end(s);
+  return TSG_OK;
 }
+
+// One request of a program: its operator, vectors, basis and reduction buffers.
+struct ReqCtx {
+  const int32_t* row_ptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;   // FP64 values (restart residual)
+  const void* valT = nullptr;    // values of the basis type (MPK)
+  int64_t nnz = 0;
+  const double* b = nullptr;
+  double* x = nullptr;
+  void* V = nullptr;
+  int64_t ld = 0, n = 0;
+  Common c{};
+  double theta[kMaxS] = {0}, sigma[kMaxS] = {0};
+};
 
 enum PanelKind { PK_GRAM, PK_UPDATE, PK_FUSED };
 
@@ -272,99 +358,151 @@ struct Step {
   int kclass = -1;
 };
 
-// One panel step: the streaming kernel and, when it reduces, the one-block tail kernel.
-tsg_status run_step(const PanelCtx& p, const Step& st) {
-  PanelArgs a{};
-  a.V = p.V;
-  a.ld = p.ld;
-  a.n = p.n;
-  a.k = st.k;
-  a.wcol = st.wcol;
-  a.sw = st.sw;
-  a.flags = st.flags;
-  a.tail = st.tail;
-  a.gate = st.gate;
-  a.standalone = p.standalone;
-  a.kkeep = st.kkeep;
-  a.panel = st.panel;
-  a.st = p.c.st;
-  a.part1 = p.c.part1;
-  bool reduces = false;
-  int nb = 0;
-  double cols = 0;
-  int kc = st.kclass;
-  if (st.kind == PK_UPDATE) {
-    a.nz = st.sw;
-    nb = (int)cdiv(p.n, 256);
-    a.rows_per_block = 256;
-    a.nblocks = nb;
-    cols = ((st.flags & PF_HAS_P) ? st.k : 0) + 2.0 * st.sw;
-    if (kc < 0) kc = TSG_KC_UPDATE;
-  } else {
-    const bool gram = st.kind == PK_GRAM;
-    a.nz = gram ? st.nprev + st.sw : st.sw;
-    const int rpl = p.f32 ? tile_rows_per_lane<float>() : tile_rows_per_lane<double>();
-    const bool loadQ = (st.flags & (PF_HAS_P | PF_GRAM_Q)) != 0;
-    const int staged = gram ? st.k + st.sw : (loadQ ? st.k : 0) + st.sw;
-    const int br = kWave * rpl * (kTileItems / staged);  // the MFMA kernels' batch height
-    int64_t tiles = cdiv(p.n, br);
-    nb = (int)std::min<int64_t>(tiles, kMaxMfmaBlocks);
-    a.rows_per_block = cdiv(cdiv(p.n, nb), br) * br;
-    nb = (int)cdiv(p.n, a.rows_per_block);
-    a.nblocks = nb;
-    if (gram) {
-      reduces = true;
-      cols = st.k + st.sw;
-      if (kc < 0) kc = st.nprev > 0 ? TSG_KC_GRAM : TSG_KC_GRAM_FIRST;
-    } else {
-      reduces = true;
-      cols = staged + ((st.flags & PF_STORE) ? st.sw : 0);
-      if (kc < 0) kc = TSG_KC_FUSED;
-    }
-  }
-  if (a.nz > kMaxGramNz || st.k + st.sw > kMaxCols)
-    return fail(TSG_ERR_UNSUPPORTED, "internal: reduction of %d x %d columns", st.k + st.sw, a.nz);
-  if (reduces && (size_t)nb * (size_t)((st.k + st.sw) * a.nz) > p.c.part1_n)
-    return fail(TSG_ERR_WORKSPACE, "internal: reduction partials (%d blocks x %d) exceed the buffer", nb,
-                (st.k + st.sw) * a.nz);
-  const bool fb = kc == TSG_KC_FALLBACK;
-  if (p.timer) p.timer->begin(p.stream, kc, fb ? 0.0 : cols * (double)p.n * p.elem);
-  switch (st.kind) {
-    case PK_GRAM:
-      if (p.f32) launch_gram<float>(a, nb, p.stream);
-      else launch_gram<double>(a, nb, p.stream);
-      break;
-    case PK_UPDATE:
-      if (p.f32) launch_update<float>(a, nb, p.stream);
-      else launch_update<double>(a, nb, p.stream);
-      break;
-    case PK_FUSED: {
-      const int ncolA = (st.flags & PF_GRAM_Q) ? st.k + st.sw : st.sw;
-      if (p.f32) launch_fused<float>(a, ncolA, nb, p.stream);
-      else launch_fused<double>(a, ncolA, nb, p.stream);
-    } break;
-  }
-  if (p.timer) p.timer->end(p.stream);
-  HIP_LAUNCH_CHECK();
-  if (reduces) {
-    if (p.timer) p.timer->begin(p.stream, fb ? TSG_KC_FALLBACK : TSG_KC_TAIL, 0.0);
-    PanelArgs at = a;
-    if (nb > 2 * kReduceGroups) {  // two-level: many blocks sum the partials first
-      const int chunk = (int)cdiv(nb, kReduceGroups);
-      const int ng = (int)cdiv(nb, chunk);
-      hipLaunchKernelGGL(partial_reduce_kernel, dim3(ng), dim3(256), 0, p.stream, a, p.c.part2, chunk);
-      at.part1 = p.c.part2;
-      at.nblocks = ng;
-    }
-    hipLaunchKernelGGL(panel_tail_kernel, dim3(1), dim3(kTailThreads), 0, p.stream, at);
-    if (p.timer) p.timer->end(p.stream);
-    HIP_LAUNCH_CHECK();
-  }
-  return TSG_OK;
-}
+// Builds the phases of a batch of requests that share the basis type and every step
+// parameter; each request keeps its own sizes, buffers and block decomposition.
+struct Builder {
+  Program& P;
+  std::vector<ReqCtx*> R;
+  int standalone = 0;
+  int elem() const { return P.f32 ? 4 : 8; }
 
-// A reduction over the k + sw columns (lean kernel when it fits, else the fused kernel in
-// reduce-only mode).
+  // One panel step: the streaming kernel and, when it reduces, the tail (after a
+  // first-level reduction for requests with more than 64 blocks).
+  tsg_status step(const Step& st) {
+    const size_t nr = R.size();
+    std::vector<PanelArgs> a(nr);
+    std::vector<int> nb(nr);
+    double bytes = 0.0;
+    bool reduces = false;
+    int kc = st.kclass;
+    const bool gram = st.kind == PK_GRAM;
+    const bool loadQ = (st.flags & (PF_HAS_P | PF_GRAM_Q)) != 0;
+    const int nz = gram ? st.nprev + st.sw : st.sw;
+    if (nz > kMaxGramNz || st.k + st.sw > kMaxCols)
+      return fail(TSG_ERR_UNSUPPORTED, "internal: reduction of %d x %d columns", st.k + st.sw, nz);
+    for (size_t r = 0; r < nr; ++r) {
+      const ReqCtx& q = *R[r];
+      PanelArgs& x = a[r];
+      x = PanelArgs{};
+      x.V = q.V;
+      x.ld = q.ld;
+      x.n = q.n;
+      x.k = st.k;
+      x.wcol = st.wcol;
+      x.sw = st.sw;
+      x.flags = st.flags;
+      x.tail = st.tail;
+      x.gate = st.gate;
+      x.standalone = standalone;
+      x.kkeep = st.kkeep;
+      x.panel = st.panel;
+      x.st = q.c.st;
+      x.part1 = q.c.part1;
+      x.nz = nz;
+      double cols;
+      if (st.kind == PK_UPDATE) {
+        nb[r] = (int)cdiv(q.n, 256);
+        x.rows_per_block = 256;
+        cols = ((st.flags & PF_HAS_P) ? st.k : 0) + 2.0 * st.sw;
+      } else {
+        const int rpl = P.f32 ? tile_rows_per_lane<float>() : tile_rows_per_lane<double>();
+        const int staged = gram ? st.k + st.sw : (loadQ ? st.k : 0) + st.sw;
+        const int br = kWave * rpl * (kTileItems / staged);  // the MFMA kernels' batch height
+        int64_t tiles = cdiv(q.n, br);
+        int b0 = (int)std::min<int64_t>(tiles, kMaxMfmaBlocks);
+        x.rows_per_block = cdiv(cdiv(q.n, b0), br) * br;
+        nb[r] = (int)cdiv(q.n, x.rows_per_block);
+        cols = gram ? st.k + st.sw : staged + ((st.flags & PF_STORE) ? st.sw : 0);
+        reduces = true;
+        if ((size_t)nb[r] * (size_t)((st.k + st.sw) * nz) > q.c.part1_n)
+          return fail(TSG_ERR_WORKSPACE, "internal: reduction partials (%d blocks x %d) exceed the buffer", nb[r],
+                      (st.k + st.sw) * nz);
+      }
+      x.nblocks = nb[r];
+      bytes += cols * (double)q.n * elem();
+    }
+    if (kc < 0) kc = st.kind == PK_UPDATE ? TSG_KC_UPDATE : (gram ? (st.nprev > 0 ? TSG_KC_GRAM : TSG_KC_GRAM_FIRST) : TSG_KC_FUSED);
+    const bool fb = kc == TSG_KC_FALLBACK;
+    if (st.kind == PK_UPDATE) {
+      P.add(F_UPDATE, s_template(st.sw), 0, a, nb, kc, fb ? 0.0 : bytes);
+    } else if (gram) {
+      P.add(F_GRAM, (st.k + st.sw + 15) / 16, nz <= 16 ? 1 : 2, a, nb, kc, fb ? 0.0 : bytes);
+    } else {
+      const int ncolA = (st.flags & PF_GRAM_Q) ? st.k + st.sw : st.sw;
+      P.add(F_FUSED, (ncolA + 15) / 16, fused_s(st.sw), a, nb, kc, fb ? 0.0 : bytes);
+    }
+    if (!reduces) return TSG_OK;
+    // first level for requests with many blocks, then the tail
+    std::vector<RedArgs> ra(nr);
+    std::vector<int> rb(nr, 0), one(nr, 1);
+    std::vector<PanelArgs> at(a);
+    for (size_t r = 0; r < nr; ++r) {
+      ra[r] = RedArgs{a[r], R[r]->c.part2, 0, 0};
+      if (nb[r] > 2 * kReduceGroups) {
+        const int chunk = (int)cdiv(nb[r], kReduceGroups);
+        rb[r] = (int)cdiv(nb[r], chunk);
+        ra[r].chunk = chunk;
+        at[r].part1 = R[r]->c.part2;
+        at[r].nblocks = rb[r];
+      }
+    }
+    const int tc = fb ? TSG_KC_FALLBACK : TSG_KC_TAIL;
+    size_t before = P.phases.size();
+    P.add(F_PREDUCE, 0, 0, ra, rb, tc, 0.0);
+    P.add(F_PTAIL, 0, 0, at, one, P.phases.size() > before ? -1 : tc, 0.0);
+    return TSG_OK;
+  }
+
+  // restart residual r = b - A x into column 0, beta, convergence test, cycle set-up
+  void resid() {
+    std::vector<ResidArgs> a;
+    std::vector<TailArgs> t;
+    std::vector<int> nb, one(R.size(), 1);
+    double bytes = 0.0;
+    for (ReqCtx* q : R) {
+      const int nbr = (int)cdiv(q->n, kRowBlock);
+      a.push_back(ResidArgs{q->row_ptr, q->col, q->val, q->x, q->b, q->V, q->n, q->c.st, q->c.part1});
+      t.push_back(TailArgs{q->c.st, q->c.part1, nbr, 0});
+      nb.push_back(nbr);
+      bytes += (double)(q->n + 1) * 4 + (double)q->nnz * 12 + 2.0 * q->n * 8 + (double)q->n * elem();
+    }
+    P.add(F_RESID, 0, 0, a, nb, TSG_KC_RESIDUAL, bytes);
+    P.add(F_RTAIL, 0, 0, t, one, -1, 0.0);
+  }
+  // w_i = (A w_{i-1} - theta_i w_{i-1}) / sigma_i into column col_out
+  void mpk(int col_in, int col_out, int i, int panel) {
+    std::vector<MpkArgs> a;
+    std::vector<int> nb;
+    double bytes = 0.0;
+    for (ReqCtx* q : R) {
+      char* V = static_cast<char*>(q->V);
+      a.push_back(MpkArgs{q->row_ptr, q->col, q->valT, V + (size_t)col_in * q->ld * elem(),
+                          V + (size_t)col_out * q->ld * elem(), q->n, q->theta[i], q->sigma[i], q->c.st, panel, 0});
+      nb.push_back((int)cdiv(q->n, kRowBlock));
+      bytes += (double)(q->n + 1) * 4 + (double)q->nnz * (4 + elem()) + 2.0 * q->n * elem();
+    }
+    P.add(F_MPK, 0, 0, a, nb, TSG_KC_MPK, bytes);
+  }
+  void cycle_end(int two) {
+    std::vector<TailArgs> t;
+    std::vector<int> one(R.size(), 1);
+    for (ReqCtx* q : R) t.push_back(TailArgs{q->c.st, nullptr, 0, two});
+    P.add(F_CYCLE_END, 0, 0, t, one, TSG_KC_CYCLE_END, 0.0);
+  }
+  void xupdate(int m) {
+    std::vector<XupdArgs> a;
+    std::vector<int> nb;
+    double bytes = 0.0;
+    for (ReqCtx* q : R) {
+      a.push_back(XupdArgs{q->x, q->V, q->ld, q->n, q->c.st});
+      nb.push_back((int)cdiv(q->n, kRowBlock));
+      bytes += (double)m * q->n * elem() + 16.0 * q->n;
+    }
+    P.add(F_XUPD, 0, 0, a, nb, TSG_KC_XUPDATE, bytes);
+  }
+};
+
+// A reduction over the k + sw columns against the nprev previous-panel columns and W.
 Step gram_step(int k, int wcol, int sw, int nprev, int tail, int panel, int kkeep, int gate = 1) {
   Step st{};
   st.kind = PK_GRAM;
@@ -397,53 +535,78 @@ Step upd_step(PanelKind kind, int k, int wcol, int sw, int flags, int tail, int 
 //              its own stage-2 Gram block column.
 //   others:    as in the paper's figures, with fused passes where the next reduction
 //              reads exactly the columns just written.
-tsg_status panel_sequence(const PanelCtx& p, int ortho, int k, int sw, int nprev, bool fuse_update, int j,
-                          int kkeep) {
+tsg_status panel_sequence(Builder& B, int ortho, int k, int sw, int nprev, bool fuse_update, int j, int kkeep) {
   const int c0 = k;
   switch (ortho) {
     case TSG_ORTHO_TWO_STAGE: {
       // stage-1 BCGS-PIP; in solver mode followed by the explicit second pass, whose
       // launches return at entry unless this panel's PIP pivot failed (gate 2)
-      const int passes = p.standalone ? 1 : 2;
+      const int passes = B.standalone ? 1 : 2;
       for (int pass = 0; pass < passes; ++pass) {
         const int gate = pass == 0 ? 1 : 2;
-        Step g = gram_step(k, c0, sw, pass == 0 ? nprev : 0, pass == 0 ? TAIL_PIP : TAIL_PIP_FB, j,
-                           kkeep, gate);
+        Step g = gram_step(k, c0, sw, pass == 0 ? nprev : 0, pass == 0 ? TAIL_PIP : TAIL_PIP_FB, j, kkeep, gate);
         if (pass == 1) g.kclass = TSG_KC_FALLBACK;
-        TRY(run_step(p, g));
+        TRY(B.step(g));
         Step u = fuse_update ? upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W,
                                         TAIL_G2COL, j, kkeep)
                              : upd_step(PK_UPDATE, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep);
         u.gate = gate;
         if (pass == 1) u.kclass = TSG_KC_FALLBACK;
-        TRY(run_step(p, u));
+        TRY(B.step(u));
       }
     } break;
     case TSG_ORTHO_BCGS_PIP2:
-      TRY(run_step(p, gram_step(k, c0, sw, 0, TAIL_PIP2_A, j, kkeep)));
-      TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W,
-                               TAIL_PIP2_B, j, kkeep)));
-      TRY(run_step(p, upd_step(PK_UPDATE, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
+      TRY(B.step(gram_step(k, c0, sw, 0, TAIL_PIP2_A, j, kkeep)));
+      TRY(B.step(upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_PIP2_B, j,
+                          kkeep)));
+      TRY(B.step(upd_step(PK_UPDATE, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
       break;
     case TSG_ORTHO_BCGS2_CHOLQR2:
-      TRY(run_step(p, gram_step(k, c0, sw, 0, TAIL_BC_P1, j, kkeep)));
-      TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_A1, j, kkeep)));
-      TRY(run_step(p, upd_step(PK_FUSED, 0, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_W, TAIL_BC_A2, j, kkeep)));
-      TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P2, j,
-                               kkeep)));
-      TRY(run_step(p, upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_C, j, kkeep)));
-      TRY(run_step(p, upd_step(PK_UPDATE, 0, c0, sw, PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
+      TRY(B.step(gram_step(k, c0, sw, 0, TAIL_BC_P1, j, kkeep)));
+      TRY(B.step(upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_A1, j, kkeep)));
+      TRY(B.step(upd_step(PK_FUSED, 0, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_W, TAIL_BC_A2, j, kkeep)));
+      TRY(B.step(upd_step(PK_FUSED, k, c0, sw, PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_BC_P2, j, kkeep)));
+      TRY(B.step(upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_STORE | PF_GRAM_W, TAIL_BC_C, j, kkeep)));
+      TRY(B.step(upd_step(PK_UPDATE, 0, c0, sw, PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
       break;
     case TSG_ORTHO_CGS2:
-      TRY(run_step(p, gram_step(k, c0, 1, 0, TAIL_CGS_H1, j, kkeep)));
-      TRY(run_step(p, upd_step(PK_FUSED, k, c0, 1, PF_HAS_P | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_CGS_H2, j,
-                               kkeep)));
-      TRY(run_step(p, upd_step(PK_UPDATE, k, c0, 1, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
+      TRY(B.step(gram_step(k, c0, 1, 0, TAIL_CGS_H1, j, kkeep)));
+      TRY(B.step(upd_step(PK_FUSED, k, c0, 1, PF_HAS_P | PF_STORE | PF_GRAM_Q | PF_GRAM_W, TAIL_CGS_H2, j, kkeep)));
+      TRY(B.step(upd_step(PK_UPDATE, k, c0, 1, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep)));
       break;
   }
   return TSG_OK;
 }
 
+// The phases of one restart cycle of s-step GMRES(m) with the given orthogonalization.
+tsg_status build_cycle(Builder& B, int m, int sstep, int ortho) {
+  const bool two = ortho == TSG_ORTHO_TWO_STAGE;
+  const int J = m / sstep;
+  B.resid();
+  // qhat_1 = r / beta; two-stage: its G2(0,0) comes with the first panel's reduction when
+  // column 0 and the panel fit one lean reduction, else from this pass
+  const bool g00_here = two && 1 + sstep > kMaxGramNz;
+  {
+    Step sc = upd_step(g00_here ? PK_FUSED : PK_UPDATE, 0, 0, 1, PF_HAS_T | PF_STORE | (g00_here ? PF_GRAM_W : 0),
+                       g00_here ? TAIL_NORM0 : TAIL_NONE, -1, 0);
+    sc.kclass = TSG_KC_SCALE;
+    TRY(B.step(sc));
+  }
+  const bool lean2 = 2 * sstep <= kMaxGramNz;
+  for (int j = 0; j < J; ++j) {
+    const int k = j * sstep + 1;
+    for (int i = 0; i < sstep; ++i) B.mpk(k - 1 + i, k + i, i, j);
+    // two-stage: the next panel's reduction covers this panel's stage-2 Gram block column
+    // when both panels fit one lean reduction; otherwise the update is fused with it
+    const bool covered = j < J - 1 && lean2;
+    // previous panel's columns reduced along: column 0 for the first panel, else s
+    const int nprev = !two ? 0 : (j == 0 ? (g00_here ? 0 : 1) : (lean2 ? sstep : 0));
+    TRY(panel_sequence(B, ortho, k, sstep, nprev, !covered, j, k - 1));
+  }
+  B.cycle_end(two ? 1 : 0);
+  B.xupdate(m);
+  return TSG_OK;
+}
 
 }  // namespace
 
@@ -554,39 +717,27 @@ static tsg_status validate_params(int64_t n, const tsg_solve_params* p) {
   return TSG_OK;
 }
 
-size_t tsg_solve_workspace_bytes(int64_t n, int64_t nnz, const tsg_solve_params* p) {
-  if (n < 1 || !p || validate_params(n, p) != TSG_OK) return 0;
+// One request's device bytes: reduction buffers and state, basis, FP32 values (mixed form).
+static size_t request_bytes(int64_t n, int64_t nnz, const tsg_solve_params* p) {
   size_t cb = common_bytes(n);
-  if (cb == (size_t)-1) return 0;
   size_t elem = p->precision == TSG_PREC_FP32_IR ? 4 : 8;
   size_t basis = align_up((size_t)basis_ld(n) * (p->m + 1) * elem);
-  size_t v32 = p->precision == TSG_PREC_FP32_IR ? align_up((size_t)nnz * 4) : 0;
-  return cb + basis + v32 + kAlign;
+  size_t v32 = p->precision == TSG_PREC_FP32_IR ? align_up((size_t)std::max<int64_t>(nnz, 1) * 4) : 0;
+  return cb + basis + v32;
+}
+
+size_t tsg_solve_workspace_bytes(int64_t n, int64_t nnz, const tsg_solve_params* p) {
+  if (n < 1 || nnz < 0 || !p || validate_params(n, p) != TSG_OK) return 0;
+  return request_bytes(n, nnz, p) + kProgramBytesPerRequest + kAlign;
 }
 
 namespace {
 
-template <typename T, typename VT>
-tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_params* p,
-                     const Common& c, T* V, int64_t ld, const VT* val, hipStream_t s,
-                     tsg_solve_info* info) {
-  const int64_t n = A->n;
-  const int m = p->m;
-  const int ortho = p->ortho;
-  const int sstep = (ortho == TSG_ORTHO_CGS2) ? 1 : p->s;
-  const int J = m / sstep;
-  const bool two = ortho == TSG_ORTHO_TWO_STAGE;
-  const bool f32 = sizeof(T) == 4;
-  Timer timer;
-  const bool timing = p->timing != 0;
-  const int64_t stride = p->timing > 1 ? p->timing : 1;  // time every stride-th cycle
-  PanelCtx pc{V, ld, n, (int)sizeof(T), f32, c, s, &timer, 0};
-
-  // basis parameters from the Gershgorin interval (Sec. VI uses the monomial basis)
-  std::vector<double> theta(sstep), sigma(sstep);
+// Basis parameters from the Gershgorin interval (Sec. VI uses the monomial basis).
+void basis_params(const tsg_csr_s* A, const tsg_solve_params* p, int sstep, double* theta, double* sigma) {
   const double lo = A->lo, hi = A->hi;
   for (int i = 0; i < sstep; ++i) {
-    if (ortho == TSG_ORTHO_CGS2) {
+    if (p->ortho == TSG_ORTHO_CGS2) {
       theta[i] = 0.0;
       sigma[i] = 1.0;
     } else if (p->basis == TSG_BASIS_MONOMIAL) {
@@ -601,36 +752,98 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
     }
     if (!(sigma[i] > 0.0)) sigma[i] = 1.0;
   }
+}
 
-  // parameters -> device state (head + parameter block only)
+int step_size(const tsg_solve_params* p) { return p->ortho == TSG_ORTHO_CGS2 ? 1 : p->s; }
+
+// Carve one request's buffers from its workspace region: reduction buffers and state,
+// the basis, and (mixed form) the FP32 copy of the values.
+void carve_request(char* base, const tsg_csr_s* A, const tsg_solve_params* p, ReqCtx& q) {
+  Carve cv{base};
+  q.c = carve_common(cv, A->n);
+  q.ld = basis_ld(A->n);
+  q.n = A->n;
+  q.nnz = A->nnz;
+  q.row_ptr = A->row_ptr;
+  q.col = A->col;
+  q.val = A->val;
+  const bool f32 = p->precision == TSG_PREC_FP32_IR;
+  if (f32) {
+    q.V = cv.take<float>((size_t)q.ld * (p->m + 1));
+    q.valT = cv.take<float>((size_t)std::max<int64_t>(A->nnz, 1));
+  } else {
+    q.V = cv.take<double>((size_t)q.ld * (p->m + 1));
+    q.valT = A->val;
+  }
+}
+
+
+// Enqueue a request's set-up: device parameters, FP32 values (mixed form), ||b||.
+tsg_status init_request(const tsg_csr_s* A, const tsg_solve_params* p, ReqCtx& q, hipStream_t s) {
+  const int sstep = step_size(p);
+  const bool f32 = p->precision == TSG_PREC_FP32_IR;
+  basis_params(A, p, sstep, q.theta, q.sigma);
   SmallState* hs = new (std::nothrow) SmallState();
   if (!hs) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
   std::memset(hs, 0, sizeof(SmallState));
   hs->h.stop_panel = 1 << 30;
-  hs->m = m;
+  hs->m = p->m;
   hs->s = sstep;
-  hs->ortho = ortho;
+  hs->ortho = p->ortho;
   hs->prec = p->precision;
   hs->max_iters = p->max_iters;
   hs->tol = p->tol;
   hs->pivot_tol = f32 ? kPivotTolF32 : kPivotTolF64;
   for (int i = 0; i < sstep; ++i) {
-    hs->theta[i] = theta[i];
-    hs->sigma[i] = sigma[i];
+    hs->theta[i] = q.theta[i];
+    hs->sigma[i] = q.sigma[i];
   }
-  const size_t head_bytes = offsetof(SmallState, Hh);
-  hipError_t e = hipMemcpyAsync(c.st, hs, head_bytes, hipMemcpyHostToDevice, s);
+  // pageable source: the copy is staged before the call returns
+  hipError_t e = hipMemcpyAsync(q.c.st, hs, offsetof(SmallState, Hh), hipMemcpyHostToDevice, s);
   delete hs;
   HIP_TRY(e);
-  const int nbr = (int)cdiv(n, kRowBlock);
-  hipLaunchKernelGGL(norm_kernel, dim3(nbr), dim3(kRowBlock), 0, s, b, n, c.part1);
-  hipLaunchKernelGGL(norm_tail_kernel, dim3(1), dim3(kTailThreads), 0, s, c.st, (const double*)c.part1, nbr);
+  if (f32 && A->nnz > 0) {
+    hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(A->nnz, kRowBlock)), dim3(kRowBlock), 0, s, A->val,
+                       (float*)q.valT, A->nnz);
+  }
+  const int nbr = (int)cdiv(q.n, kRowBlock);
+  hipLaunchKernelGGL(norm_kernel, dim3(nbr), dim3(kRowBlock), 0, s, q.b, q.n, q.c.part1);
+  hipLaunchKernelGGL(norm_tail_kernel, dim3(1), dim3(kTailThreads), 0, s, q.c.st, (const double*)q.c.part1, nbr);
   HIP_LAUNCH_CHECK();
+  return TSG_OK;
+}
+
+void fill_info(tsg_solve_info* info, const StateHead& h, tsg_status st) {
+  std::memset(info, 0, sizeof(*info));
+  info->iters = h.iters;
+  info->cycles = h.cycles;
+  info->relres = h.relres;
+  info->relres_est = h.est;
+  info->status = st;
+  info->truncated_cycles = h.truncated;
+  info->pip_fallbacks = h.fallbacks;
+}
+
+tsg_status head_status(const StateHead& h) {
+  return h.status == 0 ? TSG_OK : (h.status == 1 ? TSG_NOT_CONVERGED : TSG_BREAKDOWN);
+}
+
+tsg_status run_solve(tsg_csr A, const tsg_solve_params* p, ReqCtx& q, char* dprog, hipStream_t s,
+                     tsg_solve_info* info) {
+  const int m = p->m;
+  const int ortho = p->ortho;
+  const int sstep = step_size(p);
+  const bool f32 = p->precision == TSG_PREC_FP32_IR;
+  Timer timer;
+  const bool timing = p->timing != 0;
+  const int64_t stride = p->timing > 1 ? p->timing : 1;  // time every stride-th cycle
+
+  TRY(init_request(A, p, q, s));
   double bnorm = 0.0;
-  HIP_TRY(hipMemcpyAsync(&bnorm, &c.st->bnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&bnorm, &q.c.st->bnorm, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (bnorm == 0.0) {  // b = 0: x = 0 is the solution
-    hipLaunchKernelGGL(zero_f64_kernel, dim3(nbr), dim3(kRowBlock), 0, s, x, n);
+    hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(q.n, kRowBlock)), dim3(kRowBlock), 0, s, q.x, q.n);
     HIP_TRY(hipStreamSynchronize(s));
     if (info) {
       std::memset(info, 0, sizeof(*info));
@@ -639,10 +852,18 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
     return TSG_OK;
   }
 
+  // the launches of one restart cycle (identical in every cycle: what changes --
+  // convergence, truncation, the fallback flag, the counters -- lives in the device state)
+  Program P;
+  P.f32 = f32;
+  P.nreq = 1;
+  Builder B{P, {&q}, 0};
+  TRY(build_cycle(B, m, sstep, ortho));
+  if (P.blob.size() > kProgramBytesPerRequest) return fail(TSG_ERR_UNSUPPORTED, "internal: launch image too large");
+  HIP_TRY(hipMemcpyAsync(dprog, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, s));
+
   StateHead* head = nullptr;
   HIP_TRY(hipHostMalloc((void**)&head, sizeof(StateHead), hipHostMallocDefault));
-  const double spmv_bytes = (double)(n + 1) * 4 + (double)A->nnz * (4 + sizeof(VT)) + 2.0 * n * sizeof(T);
-  const double resid_bytes = (double)(n + 1) * 4 + (double)A->nnz * 12 + 2.0 * n * 8 + n * sizeof(T);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (timing) {
     HIP_TRY(hipEventCreate(&t0));
@@ -650,74 +871,19 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
     HIP_TRY(hipEventRecord(t0, s));
   }
 
-
-  const bool g00_here = two && 1 + sstep > kMaxGramNz;
-  // Every launch of a restart cycle has the same arguments in every cycle (what changes --
-  // convergence, truncation after a breakdown, the iteration count -- lives in the device
-  // state), so one cycle is enqueued on stream q either directly or into a graph.
-  auto enqueue_cycle = [&](hipStream_t q) -> tsg_status {
-    pc.stream = q;
-    // ---- restart residual r = b - A x, beta, convergence test (explicit, FP64)
-    timer.begin(q, TSG_KC_RESIDUAL, resid_bytes);
-    hipLaunchKernelGGL((residual_kernel<T>), dim3(nbr), dim3(kRowBlock), 0, q, A->row_ptr, A->col,
-                       A->val, x, b, V, n, c.st, c.part1);
-    hipLaunchKernelGGL(residual_tail_kernel, dim3(1), dim3(kTailThreads), 0, q, c.st,
-                       (const double*)c.part1, nbr);
-    timer.end(q);
-    HIP_LAUNCH_CHECK();
-    // ---- qhat_1 = r / beta (two-stage: its G2(0,0) comes with the first panel's reduction
-    //      when column 0 and the panel fit one lean reduction, else from this pass)
-    {
-      Step sc = upd_step(g00_here ? PK_FUSED : PK_UPDATE, 0, 0, 1,
-                         PF_HAS_T | PF_STORE | (g00_here ? PF_GRAM_W : 0), g00_here ? TAIL_NORM0 : TAIL_NONE,
-                         -1, 0);
-      sc.kclass = TSG_KC_SCALE;
-      TRY(run_step(pc, sc));
-    }
-    for (int j = 0; j < J; ++j) {
-      const int k = j * sstep + 1;
-      for (int i = 0; i < sstep; ++i) {
-        timer.begin(q, TSG_KC_MPK, spmv_bytes);
-        hipLaunchKernelGGL((mpk_step_kernel<T, VT>), dim3(nbr), dim3(kRowBlock), 0, q, A->row_ptr, A->col,
-                           val, V + (int64_t)(k - 1 + i) * ld, V + (int64_t)(k + i) * ld, n, theta[i],
-                           sigma[i], c.st, j);
-        timer.end(q);
-        HIP_LAUNCH_CHECK();
-      }
-      // two-stage: the next panel's reduction covers this panel's stage-2 Gram block column
-      // when both panels fit one lean reduction; otherwise the update is fused with it
-      const bool lean2 = 2 * sstep <= kMaxGramNz;
-      const bool covered = j < J - 1 && lean2;
-      // previous panel's columns reduced along: column 0 for the first panel, else s
-      const int nprev = !two ? 0 : (j == 0 ? (g00_here ? 0 : 1) : (lean2 ? sstep : 0));
-      TRY(panel_sequence(pc, ortho, k, sstep, nprev, !covered, j, k - 1));
-    }
-    // ---- stage 2 (two-stage) / projected least squares; counters
-    timer.begin(q, TSG_KC_CYCLE_END, 0.0);
-    hipLaunchKernelGGL(cycle_end_kernel, dim3(1), dim3(256), 0, q, c.st, two ? 1 : 0);
-    timer.end(q);
-    HIP_LAUNCH_CHECK();
-    // ---- x += V(:, 0:k_used) coef
-    timer.begin(q, TSG_KC_XUPDATE, (double)m * n * sizeof(T) + 16.0 * n);
-    hipLaunchKernelGGL((xupdate_kernel<T>), dim3(nbr), dim3(kRowBlock), 0, q, x, V, ld, n, c.st);
-    timer.end(q);
-    HIP_LAUNCH_CHECK();
-    return TSG_OK;
-  };
-
   // graph mode: capture one cycle on a private stream, replay it on s.  A timed cycle is
-  // enqueued directly (its events bracket each launch; same kernels and arguments).
+  // launched directly (HIP events around each launch; same kernels and arguments).
   const bool use_graph = (p->flags & TSG_FLAG_EAGER) == 0;
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   tsg_status result = TSG_OK;
+  hipError_t e = hipSuccess;
   if (use_graph) {
     hipError_t ge = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (ge == hipSuccess) ge = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
     if (ge == hipSuccess) {
-      timer.on = false;
-      tsg_status cst = enqueue_cycle(cs);
+      tsg_status cst = exec_program(P, dprog, cs, nullptr);
       ge = hipStreamEndCapture(cs, &graph);
       if (cst != TSG_OK) result = cst;
     }
@@ -735,11 +901,11 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
         break;
       }
     } else {
-      result = enqueue_cycle(s);
+      result = exec_program(P, dprog, s, &timer);
       if (result != TSG_OK) break;
       timed_cycles += timer.on ? 1 : 0;
     }
-    e = hipMemcpyAsync(head, &c.st->h, sizeof(StateHead), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(head, &q.c.st->h, sizeof(StateHead), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       result = fail(TSG_ERR_HIP, "cycle sync failed: %s", hipGetErrorString(e));
@@ -755,29 +921,22 @@ tsg_status run_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cs) (void)hipStreamDestroy(cs);
+  double ms_total = 0.0;
   if (timing && result == TSG_OK) {
     (void)hipEventRecord(t1, s);
     (void)hipEventSynchronize(t1);
     float tot = 0.f;
     (void)hipEventElapsedTime(&tot, t0, t1);
-    if (info) info->ms_total = tot;
+    ms_total = tot;
   }
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
   StateHead h = *head;
   (void)hipHostFree(head);
   if (result != TSG_OK) return result;
-  tsg_status st = h.status == 0 ? TSG_OK : (h.status == 1 ? TSG_NOT_CONVERGED : TSG_BREAKDOWN);
+  tsg_status st = head_status(h);
   if (info) {
-    double ms_total = info->ms_total;
-    std::memset(info, 0, sizeof(*info));
-    info->iters = h.iters;
-    info->cycles = h.cycles;
-    info->relres = h.relres;
-    info->relres_est = h.est;
-    info->status = st;
-    info->truncated_cycles = h.truncated;
-    info->pip_fallbacks = h.fallbacks;
+    fill_info(info, h, st);
     if (timing) {
       info->ms_total = ms_total;
       info->timed_cycles = timed_cycles;
@@ -816,29 +975,19 @@ tsg_status tsg_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   size_t need = tsg_solve_workspace_bytes(A->n, A->nnz, p);
   if (need == 0) return fail(TSG_ERR_INVALID_ARG, "problem too large for the reduction buffers");
   if (ws_bytes < need) return fail(TSG_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, need);
-  hipStream_t s = (hipStream_t)stream;
-  Carve cv{(char*)workspace};
-  Common c = carve_common(cv, A->n);
-  const int64_t ld = basis_ld(A->n);
-  if (p->precision == TSG_PREC_FP32_IR) {
-    float* V = cv.take<float>((size_t)ld * (p->m + 1));
-    float* v32 = cv.take<float>((size_t)std::max<int64_t>(A->nnz, 1));
-    if (A->nnz > 0) {
-      hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(A->nnz, kRowBlock)), dim3(kRowBlock), 0, s, A->val, v32,
-                         A->nnz);
-      HIP_LAUNCH_CHECK();
-    }
-    return run_solve<float, float>(A, b, x, p, c, V, ld, v32, s, info);
-  }
-  double* V = cv.take<double>((size_t)ld * (p->m + 1));
-  return run_solve<double, double>(A, b, x, p, c, V, ld, A->val, s, info);
+  ReqCtx q;
+  q.b = b;
+  q.x = x;
+  carve_request((char*)workspace, A, p, q);
+  char* dprog = (char*)workspace + request_bytes(A->n, A->nnz, p);
+  return run_solve(A, p, q, dprog, (hipStream_t)stream, info);
 }
 
 size_t tsg_orthogonalize_workspace_bytes(int64_t n, int32_t k, int32_t s) {
   if (n < 1 || k < 1 || k > kMaxCols || s < 1 || s > kMaxS) return 0;
   size_t cb = common_bytes(n);
   if (cb == (size_t)-1) return 0;
-  return cb + kAlign;
+  return cb + kProgramBytesPerRequest + kAlign;
 }
 
 tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr,
@@ -861,6 +1010,7 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   hipStream_t st = (hipStream_t)stream;
   Carve cv{(char*)workspace};
   Common c = carve_common(cv, n);
+  char* dprog = cv.take<char>(kProgramBytesPerRequest);
   const bool two = algo == TSG_ORTHO_TWO_STAGE;
 
   SmallState* hs = new (std::nothrow) SmallState();
@@ -876,14 +1026,21 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(kLd * kLd, 256)), dim3(256), 0, st, c.st->G2,
                      (int64_t)kLd * kLd);
   HIP_LAUNCH_CHECK();
-  PanelCtx pc{X, ldx, n, 8, false, c, st, nullptr, 1};
+  ReqCtx q;
+  q.V = X;
+  q.ld = ldx;
+  q.n = n;
+  q.c = c;
+  Program P;
+  P.nreq = 1;
+  Builder B{P, {&q}, 1};
   // column 1 alone
-  TRY(run_step(pc, gram_step(0, 0, 1, 0, TAIL_SA_NORM, -1, 0)));
+  TRY(B.step(gram_step(0, 0, 1, 0, TAIL_SA_NORM, -1, 0)));
   // two-stage with panels: G2(0,0) comes with the first panel's reduction when column 0 and
   // the first panel fit one lean reduction
   const bool g00 = two && (k == 1 || 1 + std::min(s, k - 1) > kMaxGramNz);
-  TRY(run_step(pc, upd_step(g00 ? PK_FUSED : PK_UPDATE, 0, 0, 1, PF_HAS_T | PF_STORE | (g00 ? PF_GRAM_W : 0),
-                            g00 ? TAIL_NORM0 : TAIL_NONE, -1, 0)));
+  TRY(B.step(upd_step(g00 ? PK_FUSED : PK_UPDATE, 0, 0, 1, PF_HAS_T | PF_STORE | (g00 ? PF_GRAM_W : 0),
+                      g00 ? TAIL_NORM0 : TAIL_NONE, -1, 0)));
   const bool lean2 = 2 * s <= kMaxGramNz;
   for (int c0 = 1; c0 < k; c0 += s) {
     const int sw = std::min(s, k - c0);
@@ -891,8 +1048,18 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
     // previous columns reduced along: column 0 for the first panel, else the previous panel
     // (panels before the last have width s)
     const int nprev = !two ? 0 : (c0 == 1 ? (g00 ? 0 : 1) : (lean2 ? s : 0));
-    TRY(panel_sequence(pc, algo, c0, sw, nprev, last || !lean2, 0, 0));
+    TRY(panel_sequence(B, algo, c0, sw, nprev, last || !lean2, 0, 0));
   }
+  const size_t n_main = P.phases.size();
+  if (orth_err) {  // the Gram of the result, 16 columns at a time, into st->Wk
+    for (int c0 = 0; c0 < k; c0 += kMaxS) {
+      const int sw = std::min(kMaxS, k - c0);
+      TRY(B.step(gram_step(c0, c0, sw, 0, TAIL_GRAM_OUT, 0, 0, 0)));
+    }
+  }
+  if (P.blob.size() > kProgramBytesPerRequest) return fail(TSG_ERR_UNSUPPORTED, "internal: launch image too large");
+  HIP_TRY(hipMemcpyAsync(dprog, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, st));
+  TRY(exec_program(P, dprog, st, nullptr, 0, n_main));
   if (two) {
     // stage 2: one CholQR over all k columns, then Q = Qhat R2^{-1}
     hipLaunchKernelGGL(sa_stage2_kernel, dim3(1), dim3(256), 0, st, c.st, k);
@@ -908,10 +1075,7 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   }
   HIP_LAUNCH_CHECK();
   if (orth_err) {
-    for (int c0 = 0; c0 < k; c0 += kMaxS) {
-      const int sw = std::min(kMaxS, k - c0);
-      TRY(run_step(pc, gram_step(c0, c0, sw, 0, TAIL_GRAM_OUT, 0, 0, 0)));
-    }
+    TRY(exec_program(P, dprog, st, nullptr, n_main));
     hipLaunchKernelGGL(orth_err_kernel, dim3(1), dim3(256), 0, st, c.st, k);
     HIP_LAUNCH_CHECK();
     HIP_TRY(hipMemcpyAsync(orth_err, &c.st->beta, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -921,4 +1085,253 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   HIP_TRY(hipStreamSynchronize(st));
   if (h.status == 2) return fail(TSG_BREAKDOWN, "a Gram matrix was not positive definite");
   return TSG_OK;
+}
+
+// =================================================================== solve server
+// Continuous batching of many solves that share the solver parameters.  Requests queue
+// on the host; at every restart-cycle boundary the server admits queued requests in
+// arrival order while their buffers fit its arena (and a slot is free), then runs ONE
+// restart cycle of every active request: each phase of the cycle is one batched launch
+// over all active requests, so small and large solves share every kernel.  Finished
+// requests (converged, out of iterations, or broken down) leave at the cycle boundary and
+// free their memory for the queue.  A request computes exactly what tsg_solve computes for
+// it: its launches see their own block indices and buffers whatever else is batched.
+
+namespace {
+
+__global__ void gather_heads_kernel(SmallState* const* sts, StateHead* out, int nreq) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nreq) out[r] = sts[r]->h;
+}
+
+// First-fit allocator of arena offsets (host bookkeeping only).
+struct Arena {
+  std::vector<std::pair<size_t, size_t>> free_;  // (offset, size), sorted by offset
+  void init(size_t off, size_t bytes) { free_.assign(1, {off, bytes}); }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align_up(bytes);
+    for (size_t i = 0; i < free_.size(); ++i) {
+      if (free_[i].second >= bytes) {
+        *off = free_[i].first;
+        free_[i].first += bytes;
+        free_[i].second -= bytes;
+        if (free_[i].second == 0) free_.erase(free_.begin() + i);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align_up(bytes);
+    auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (size_t)0));
+    it = free_.insert(it, {off, bytes});
+    // merge with the next and the previous block
+    if (it + 1 != free_.end() && it->first + it->second == (it + 1)->first) {
+      it->second += (it + 1)->second;
+      free_.erase(it + 1);
+    }
+    if (it != free_.begin() && (it - 1)->first + (it - 1)->second == it->first) {
+      (it - 1)->second += it->second;
+      free_.erase(it);
+    }
+  }
+};
+
+struct ServeReq {
+  int64_t tag;
+  tsg_csr A;
+  ReqCtx q;
+  size_t off = 0, bytes = 0;
+};
+
+}  // namespace
+
+struct tsg_server_s {
+  tsg_solve_params p;
+  char* arena;
+  size_t arena_bytes;
+  int max_active;
+  hipStream_t s;
+  char* dimage;              // launch image of the current batch
+  size_t image_bytes;
+  StateHead* dheads;         // gathered heads (device)
+  StateHead* hheads;         // pinned copy
+  Arena mem;
+  std::vector<ServeReq*> queue;   // FIFO
+  std::vector<ServeReq*> active;
+  std::vector<std::pair<int64_t, tsg_solve_info>> done;
+  Program prog;
+  size_t sts_off = 0;        // offset of the SmallState* table in the image
+  bool dirty = true;         // membership changed: rebuild the launch image
+};
+
+size_t tsg_server_request_bytes(int64_t n, int64_t nnz, const tsg_solve_params* p) {
+  if (n < 1 || nnz < 0 || !p || validate_params(n, p) != TSG_OK) return 0;
+  return align_up(request_bytes(n, nnz, p));
+}
+
+tsg_status tsg_server_create(const tsg_solve_params* p, void* arena, size_t arena_bytes, int32_t max_active,
+                             void* stream, tsg_server* out) {
+  if (!p || !arena || !out) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  TRY(validate_params(1 << 30, p));
+  if (max_active < 1 || max_active > 4096) return fail(TSG_ERR_INVALID_ARG, "max_active=%d outside [1, 4096]", max_active);
+  if (p->timing != 0) return fail(TSG_ERR_UNSUPPORTED, "per-kernel timing is not available in the server");
+  if (reinterpret_cast<uintptr_t>(arena) % kAlign != 0) return fail(TSG_ERR_WORKSPACE, "arena must be 256-byte aligned");
+  const size_t image = align_up((size_t)max_active * kProgramBytesPerRequest);
+  const size_t heads = align_up((size_t)max_active * sizeof(StateHead));
+  if (arena_bytes < image + heads + (1 << 20))
+    return fail(TSG_ERR_WORKSPACE, "arena %zu too small for %d slots", arena_bytes, max_active);
+  tsg_server_s* S = new (std::nothrow) tsg_server_s();
+  if (!S) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
+  S->p = *p;
+  S->p.newton_shifts = nullptr;
+  if (p->basis == TSG_BASIS_NEWTON) {
+    delete S;
+    return fail(TSG_ERR_UNSUPPORTED, "the server takes monomial or shifted bases");
+  }
+  S->arena = (char*)arena;
+  S->arena_bytes = arena_bytes;
+  S->max_active = max_active;
+  S->s = (hipStream_t)stream;
+  S->dimage = S->arena;
+  S->image_bytes = image;
+  S->dheads = reinterpret_cast<StateHead*>(S->arena + image);
+  S->mem.init(image + heads, arena_bytes - image - heads);
+  if (hipHostMalloc((void**)&S->hheads, heads, hipHostMallocDefault) != hipSuccess) {
+    delete S;
+    return fail(TSG_ERR_HIP, "hipHostMalloc of the status buffer failed");
+  }
+  *out = S;
+  return TSG_OK;
+}
+
+tsg_status tsg_server_destroy(tsg_server S) {
+  if (!S) return TSG_OK;
+  (void)hipStreamSynchronize(S->s);
+  (void)hipHostFree(S->hheads);
+  for (auto* r : S->queue) delete r;
+  for (auto* r : S->active) delete r;
+  delete S;
+  return TSG_OK;
+}
+
+tsg_status tsg_server_submit(tsg_server S, tsg_csr A, const double* b, double* x, int64_t tag) {
+  if (!S || !A || !b || !x) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  TRY(validate_params(A->n, &S->p));
+  const size_t bytes = align_up(request_bytes(A->n, A->nnz, &S->p));
+  if (bytes > S->arena_bytes - S->image_bytes)
+    return fail(TSG_ERR_INVALID_ARG, "request of %zu bytes can never fit the arena", bytes);
+  ServeReq* r = new (std::nothrow) ServeReq();
+  if (!r) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
+  r->tag = tag;
+  r->A = A;
+  r->bytes = bytes;
+  r->q.b = b;
+  r->q.x = x;
+  S->queue.push_back(r);
+  return TSG_OK;
+}
+
+namespace {
+
+void retire(tsg_server S, ServeReq* r, const StateHead& h) {
+  tsg_solve_info info;
+  fill_info(&info, h, head_status(h));
+  S->done.push_back({r->tag, info});
+  S->mem.release(r->off, r->bytes);
+  delete r;
+}
+
+}  // namespace
+
+tsg_status tsg_server_step(tsg_server S, int32_t* n_active, int32_t* n_queued) {
+  if (!S) return fail(TSG_ERR_INVALID_ARG, "NULL server");
+  hipStream_t s = S->s;
+  // ---- admission at the cycle boundary: arrival order, while memory and slots allow
+  std::vector<ServeReq*> joining;
+  size_t qi = 0;
+  while (qi < S->queue.size() && (int)(S->active.size() + joining.size()) < S->max_active) {
+    ServeReq* r = S->queue[qi];
+    size_t off = 0;
+    if (!S->mem.alloc(r->bytes, &off)) break;  // head of the line waits for memory
+    r->off = off;
+    carve_request(S->arena + off, r->A, &S->p, r->q);
+    tsg_status st = init_request(r->A, &S->p, r->q, s);
+    if (st != TSG_OK) {
+      S->mem.release(off, r->bytes);
+      return st;
+    }
+    joining.push_back(r);
+    ++qi;
+  }
+  S->queue.erase(S->queue.begin(), S->queue.begin() + qi);
+  if (!joining.empty()) {
+    // b = 0 solves finish at once (x = 0); read every new ||b|| with one synchronization
+    std::vector<double> bn(joining.size());
+    for (size_t i = 0; i < joining.size(); ++i)
+      HIP_TRY(hipMemcpyAsync(&bn[i], &joining[i]->q.c.st->bnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (size_t i = 0; i < joining.size(); ++i) {
+      ServeReq* r = joining[i];
+      if (bn[i] == 0.0) {
+        hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(r->q.n, kRowBlock)), dim3(kRowBlock), 0, s, r->q.x, r->q.n);
+        HIP_LAUNCH_CHECK();
+        StateHead h{};
+        h.done = 1;
+        retire(S, r, h);
+      } else {
+        S->active.push_back(r);
+        S->dirty = true;
+      }
+    }
+  }
+  if (!S->active.empty()) {
+    // ---- the launch image of the current batch
+    if (S->dirty) {
+      S->prog = Program();
+      S->prog.f32 = S->p.precision == TSG_PREC_FP32_IR;
+      S->prog.nreq = (int)S->active.size();
+      Builder B{S->prog, {}, 0};
+      for (auto* r : S->active) B.R.push_back(&r->q);
+      TRY(build_cycle(B, S->p.m, step_size(&S->p), S->p.ortho));
+      std::vector<SmallState*> sts;
+      for (auto* r : S->active) sts.push_back(r->q.c.st);
+      S->sts_off = S->prog.put(sts.data(), sizeof(SmallState*) * sts.size());
+      if (S->prog.blob.size() > S->image_bytes) return fail(TSG_ERR_UNSUPPORTED, "internal: launch image too large");
+      HIP_TRY(hipMemcpyAsync(S->dimage, S->prog.blob.data(), S->prog.blob.size(), hipMemcpyHostToDevice, s));
+      S->dirty = false;
+    }
+    // ---- one restart cycle of every active request, then their status heads
+    TRY(exec_program(S->prog, S->dimage, s, nullptr));
+    const int na = (int)S->active.size();
+    hipLaunchKernelGGL(gather_heads_kernel, dim3(cdiv(na, 256)), dim3(256), 0, s,
+                       reinterpret_cast<SmallState* const*>(S->dimage + S->sts_off), S->dheads, na);
+    HIP_LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(S->hheads, S->dheads, sizeof(StateHead) * na, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<ServeReq*> keep;
+    for (int i = 0; i < na; ++i) {
+      if (S->hheads[i].done) {
+        retire(S, S->active[i], S->hheads[i]);
+        S->dirty = true;
+      } else {
+        keep.push_back(S->active[i]);
+      }
+    }
+    S->active.swap(keep);
+  }
+  if (n_active) *n_active = (int32_t)S->active.size();
+  if (n_queued) *n_queued = (int32_t)S->queue.size();
+  return TSG_OK;
+}
+
+int32_t tsg_server_poll(tsg_server S, int64_t* tags, tsg_solve_info* infos, int32_t max) {
+  if (!S || max <= 0) return 0;
+  const int32_t k = (int32_t)std::min<size_t>((size_t)max, S->done.size());
+  for (int32_t i = 0; i < k; ++i) {
+    if (tags) tags[i] = S->done[i].first;
+    if (infos) infos[i] = S->done[i].second;
+  }
+  S->done.erase(S->done.begin(), S->done.begin() + k);
+  return k;
 }

@@ -1,0 +1,145 @@
+"""The solve server (continuous batching, tsg_server_* through the C ABI).
+
+A request computes bit for bit what tsg_solve computes for it, whatever else shares the
+batched launches: checked with requests of different sizes and operators submitted
+together, arriving while others run, and admitted one by one through an arena too small
+to hold them all.  tsg_solve itself is checked against the oracle in test_gpu_parity.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import sparse as S
+
+pytestmark = pytest.mark.gpu
+
+KW = dict(m=60, s=5, tol=1e-8, basis="shifted", precision="fp32_ir")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def tsg():
+    import paper_2402_15033_amd as m
+
+    m.load_library()
+    return m
+
+
+def _requests(tsg, specs):
+    out = []
+    for i, (kind, N) in enumerate(specs):
+        pr = W.make_problem(kind, N, seed=100 + i, rhs="uniform", pe_range=(1.0, 100.0))
+        A = tsg.CSRMatrix.from_host(pr["A"])
+        b = torch.as_tensor(pr["b"], device="cuda")
+        out.append((pr, A, b))
+    return out
+
+
+SPECS = [("laplace2d", 32), ("convdiff2d", 40), ("laplace2d", 48), ("convdiff2d", 24), ("laplace2d", 20)]
+
+
+def _alone(tsg, reqs, **kw):
+    res = []
+    for pr, A, b in reqs:
+        x, info = tsg.solve(A, b, **dict(KW, **kw))
+        res.append((x, info))
+    return res
+
+
+def _drain(srv, n):
+    got = {}
+    steps = 0
+    while len(got) < n:
+        srv.step()
+        for tag, x, info in srv.poll():
+            got[tag] = (x, info)
+        steps += 1
+        assert steps < 100000
+    return got
+
+
+def test_mix_equals_alone(tsg):
+    _say("case server mix == alone")
+    reqs = _requests(tsg, SPECS)
+    alone = _alone(tsg, reqs)
+    srv = tsg.Server(1 << 30, **KW)
+    for i, (pr, A, b) in enumerate(reqs):
+        srv.submit(i, A, b)
+    got = _drain(srv, len(reqs))
+    for i, (pr, A, b) in enumerate(reqs):
+        xa, ia = alone[i]
+        xm, im = got[i]
+        assert torch.equal(xa, xm), i
+        assert (ia.iters, ia.cycles, ia.status) == (im.iters, im.cycles, im.status)
+        relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], xm.cpu().numpy())) / np.linalg.norm(pr["b"])
+        assert im.converged and relres <= 1e-8
+    srv.close()
+
+
+def test_continuous_admission_and_budget(tsg):
+    """Requests arrive while others are active, and an arena that holds two requests at a
+    time admits the rest as memory frees up; every result is still the solo result."""
+    _say("case server admission")
+    reqs = _requests(tsg, SPECS)
+    alone = _alone(tsg, reqs)
+    probe = tsg.Server(1 << 30, **KW)
+    sizes = [probe.request_bytes(A) for _, A, _ in reqs]
+    probe.close()
+    top2 = sum(sorted(sizes)[-2:])
+    # launch images (256 slots x 512 KiB) + heads + room for the two largest requests
+    arena = 8 * 512 * 1024 + (1 << 20) + top2 + 4096
+    srv = tsg.Server(arena, max_active=8, **KW)
+    srv.submit(0, *reqs[0][1:])
+    srv.submit(1, *reqs[1][1:])
+    got = {}
+    max_active = 0
+    for step in range(3):
+        na, nq = srv.step()
+        max_active = max(max_active, na)
+        for tag, x, info in srv.poll():
+            got[tag] = (x, info)
+    for i in range(2, len(reqs)):
+        srv.submit(i, *reqs[i][1:])
+    while len(got) < len(reqs):
+        na, nq = srv.step()
+        max_active = max(max_active, na)
+        assert na <= 2
+        for tag, x, info in srv.poll():
+            got[tag] = (x, info)
+    for i in range(len(reqs)):
+        assert torch.equal(alone[i][0], got[i][0]), i
+        assert alone[i][1].iters == got[i][1].iters
+    assert max_active == 2
+    srv.close()
+
+
+def test_fp64_requests_and_zero_rhs(tsg):
+    _say("case server fp64 + b=0")
+    reqs = _requests(tsg, SPECS[:3])
+    kw = dict(precision="fp64", basis="monomial", tol=1e-10)
+    alone = _alone(tsg, reqs, **kw)
+    srv = tsg.Server(1 << 30, **dict(KW, **kw))
+    for i, (pr, A, b) in enumerate(reqs):
+        srv.submit(i, A, b)
+    zb = torch.zeros_like(reqs[0][2])
+    x0 = torch.ones_like(zb)
+    srv.submit(99, reqs[0][1], zb, x0)
+    got = _drain(srv, len(reqs) + 1)
+    for i in range(len(reqs)):
+        assert torch.equal(alone[i][0], got[i][0])
+    x, info = got[99]
+    assert info.converged and info.iters == 0 and float(x.abs().max()) == 0.0
+    srv.close()
+
+
+def test_request_larger_than_arena_is_rejected(tsg):
+    _say("case server reject")
+    reqs = _requests(tsg, [("laplace2d", 128)])
+    srv = tsg.Server(256 * 512 * 1024 + (1 << 20) + (1 << 16), **KW)
+    with pytest.raises(tsg.TSGError):
+        srv.submit(0, *reqs[0][1:])
+    srv.close()
