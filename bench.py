@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ortho time & time-to-solution (2D Laplace n=4M) + HBM GB/s; solves/s, p99"
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "panel_kernel_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kernel_traffic.json")
 
 
 def log(*a):
@@ -81,6 +81,9 @@ def main():
                     help="launch every kernel directly instead of replaying one captured cycle")
     ap.add_argument("--modes", action="store_true",
                     help="also time one solve in each launch mode (graph/eager x events on/off)")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="short run for hardware-counter passes: three 1 GiB device copies (the "
+                         "calibration kernel) and the first two restart cycles of the solve")
     ap.add_argument("--serve", action="store_true",
                     help="run the served form instead: Poisson arrivals of mixed solves through the "
                          "continuous-batching server")
@@ -107,6 +110,23 @@ def main():
     tsg.load_library()
     if args.serve:
         serve_bench(args, tsg, W, np, torch, dev)
+        return
+    if args.pmc_probe:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        N = args.N or 2048
+        pr = W.make_problem(args.problem, N, seed=0)
+        A = tsg.CSRMatrix.from_host(pr["A"], device=dev)
+        b = torch.as_tensor(pr["b"], device=dev)
+        _, info = tsg.solve(A, b, m=args.m, s=args.s, tol=args.tol, ortho=args.ortho,
+                            precision=args.precision, basis=args.basis, max_iters=2 * args.m, graph=False)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": True, "copy_bytes": 1 << 30, "iters": int(info.iters)}), flush=True)
         return
     N = args.N or (160 if args.problem == "laplace3d" else 2048)
     desc = {"laplace2d": f"2D Laplace 5-point {N}x{N}", "laplace3d": f"3D Laplace 7-point {N}^3",
