@@ -140,14 +140,28 @@ typedef struct tsg_csr_s* tsg_csr;
 
 /* Create a handle for the n x n CSR matrix (Sec. VII: the operator).  The handle
  * BORROWS row_ptr[n+1], col[nnz], val[nnz] (device): they must stay valid and
- * unchanged until tsg_csr_destroy.  Computes the Gershgorin interval on the device
- * (one small kernel, synchronizes `stream`).  The handle owns one 4 KiB device block.
+ * unchanged until tsg_csr_destroy.  Computes the Gershgorin interval and the plan of the
+ * packed layout on the device (small kernels, synchronizes `stream`).  The handle owns one
+ * 4 KiB device block and (n/64 + 1) x 8 bytes of host memory.
  * Errors: INVALID_ARG for n < 1, nnz < 0, nnz >= 2^31, NULL pointers; HIP. */
 tsg_status tsg_csr_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
                           const double* val, void* stream, tsg_csr* out /* host */);
 tsg_status tsg_csr_destroy(tsg_csr A);
 /* Gershgorin interval [lo, hi] (host outputs). */
 tsg_status tsg_csr_gershgorin(tsg_csr A, double* lo, double* hi);
+
+/* Packed layout of the operator for the solver's SpMVs (optional, recommended): SELL-64 --
+ * slices of 64 rows stored entry by entry, so one wave reads its slice's values and
+ * columns as contiguous 64-entry runs and no row pointers; columns as int16 deltas
+ * col - row when all fit, else int32; FP64 values and their FP32 copy (mixed form).
+ * tsg_csr_pack_bytes: device bytes needed (the layout plan is computed at create).
+ * tsg_csr_pack: fill buf (device, 256-byte aligned, caller-owned, must stay valid while
+ * the handle uses it) from the CSR arrays, asynchronously on `stream`; from then on every
+ * solve with A uses the packed copy (the CSR arrays must still stay valid).  buf = NULL
+ * returns to the CSR arrays (synchronizes `stream`).  The packed SpMV sums each row's
+ * products in CSR order, rounded as the CSR kernel rounds them: results are identical. */
+size_t tsg_csr_pack_bytes(tsg_csr A);
+tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream);
 
 /* y = A x in float64 (the SpMV of the matrix-powers kernel with theta = 0, sigma = 1).
  * x and y must not overlap.  Asynchronous on `stream`. */

@@ -114,6 +114,10 @@ def load_library():
     lib.tsg_csr_destroy.restype = C.c_int
     lib.tsg_csr_gershgorin.argtypes = [vp, f64p, f64p]
     lib.tsg_csr_gershgorin.restype = C.c_int
+    lib.tsg_csr_pack_bytes.argtypes = [vp]
+    lib.tsg_csr_pack_bytes.restype = C.c_size_t
+    lib.tsg_csr_pack.argtypes = [vp, vp, C.c_size_t, vp]
+    lib.tsg_csr_pack.restype = C.c_int
     lib.tsg_spmv.argtypes = [vp, vp, vp, vp]
     lib.tsg_spmv.restype = C.c_int
     lib.tsg_solve_workspace_bytes.argtypes = [i64, i64, C.POINTER(_Params)]
@@ -178,9 +182,13 @@ def _workspace(nbytes: int, device, ws: torch.Tensor | None):
 
 
 class CSRMatrix:
-    """Handle on a device CSR matrix (borrows the three tensors; keeps references)."""
+    """Handle on a device CSR matrix (borrows the three tensors; keeps references).
 
-    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor):
+    pack=True (default) also builds the library's packed SELL-64 copy of the operator
+    (tsg_csr_pack, device memory owned by this object), which every solve then uses; the
+    results are identical to the CSR kernels'."""
+
+    def __init__(self, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, pack: bool = True):
         lib = load_library()
         self.row_ptr = _dev_tensor(row_ptr, torch.int32, "row_ptr")
         self.col = _dev_tensor(col, torch.int32, "col")
@@ -192,12 +200,30 @@ class CSRMatrix:
         _check(lib.tsg_csr_create(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
                                   self.val.data_ptr(), _stream(self.device), C.byref(h)))
         self._h = h
+        self._pack = None
+        if pack:
+            self.pack()
+
+    def pack(self):
+        """Build the packed copy (SELL-64) used by the solver's SpMVs."""
+        lib = load_library()
+        nbytes = int(lib.tsg_csr_pack_bytes(self._h))
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        p = (buf.data_ptr() + 255) // 256 * 256
+        _check(lib.tsg_csr_pack(self._h, p, nbytes, _stream(self.device)))
+        self._pack = buf
+        return self
+
+    def unpack(self):
+        _check(load_library().tsg_csr_pack(self._h, None, 0, _stream(self.device)))
+        self._pack = None
+        return self
 
     @classmethod
-    def from_host(cls, A, device="cuda"):
+    def from_host(cls, A, device="cuda", pack: bool = True):
         """From any object with numpy row_ptr/col/val (e.g. workloads.CSR)."""
         return cls(torch.as_tensor(A.row_ptr, device=device), torch.as_tensor(A.col, device=device),
-                   torch.as_tensor(A.val, device=device))
+                   torch.as_tensor(A.val, device=device), pack=pack)
 
     @property
     def handle(self):

@@ -26,6 +26,7 @@ template <typename T, typename VT>
 __device__ __forceinline__ T csr_row_dot(gbl<const int32_t>* __restrict__ row_ptr,
                                          gbl<const int32_t>* __restrict__ col, gbl<const VT>* __restrict__ val,
                                          gbl<const T>* __restrict__ x, int64_t n, int64_t r0, int lane, T* prod) {
+#pragma clang fp contract(off)
   const int64_t r = r0 + lane;
   const int nrows = (int)min((int64_t)kWave, n - r0);
   const int rp = (r < n) ? row_ptr[r] : 0;
@@ -51,23 +52,123 @@ __device__ __forceinline__ T csr_row_dot(gbl<const int32_t>* __restrict__ row_pt
   return acc;
 }
 
+// ------------------------------------------------------------------ packed operator
+// SELL-64 layout of the operator (built once per CSR handle by tsg_csr_pack): slices of 64
+// consecutive rows, one wave each; slice s holds width w_s = its longest row, stored entry
+// by entry -- element e of row 64 s + l at off_s + 64 e + l -- so that the wave's loads of
+// values and columns are fully coalesced 64-entry runs and no row pointer is read.  Short
+// rows are padded with value 0 and column delta 0.  Columns are stored as int16 deltas
+// col - row when every delta fits (FMT_SELL16: 2 bytes instead of 4 per nonzero), else as
+// int32 columns (FMT_SELL32).
+enum OpFormat : int { FMT_CSR = 0, FMT_SELL16 = 1, FMT_SELL32 = 2 };
+
+// acc(r) = sum_e val * x[col] for row r = 64 slice + lane of a packed operator; the
+// products are rounded before they are summed, in the rows' CSR order (as csr_row_dot).
+template <typename T, typename VT, int FMT>
+__device__ __forceinline__ T sell_row_dot(gbl<const int64_t>* __restrict__ soff, gbl<const VT>* __restrict__ sval,
+                                          const void* scol_, gbl<const T>* __restrict__ x, int64_t n, int64_t slice,
+                                          int lane) {
+#pragma clang fp contract(off)
+  const int64_t off = soff[slice];
+  const int64_t r = slice * kWave + lane;
+  const int w = r < n ? (int)((soff[slice + 1] - off) >> 6) : 0;  // padding rows past n: nothing
+  T acc = (T)0;
+  if (FMT == FMT_SELL16) {
+    gbl<const int16_t>* __restrict__ scol = G(reinterpret_cast<const int16_t*>(scol_));
+#pragma unroll 4
+    for (int e = 0; e < w; ++e) {
+      const int64_t q = off + (int64_t)e * kWave + lane;
+      const VT v = __builtin_nontemporal_load(&sval[q]);
+      const int64_t c = r + __builtin_nontemporal_load(&scol[q]);
+      const T prod = (T)v * x[c];
+      acc += prod;
+    }
+  } else {
+    gbl<const int32_t>* __restrict__ scol = G(reinterpret_cast<const int32_t*>(scol_));
+#pragma unroll 4
+    for (int e = 0; e < w; ++e) {
+      const int64_t q = off + (int64_t)e * kWave + lane;
+      const VT v = __builtin_nontemporal_load(&sval[q]);
+      const int32_t c = __builtin_nontemporal_load(&scol[q]);
+      const T prod = (T)v * x[c];
+      acc += prod;
+    }
+  }
+  return acc;
+}
+
+// Per slice: its width (longest row) and whether every column delta col - row of its rows
+// fits int16.  One wave per slice.
+__global__ __launch_bounds__(kRowBlock) void sell_analyze_kernel(const int32_t* __restrict__ row_ptr,
+                                                                 const int32_t* __restrict__ col, int64_t n,
+                                                                 int64_t nslices, int* width, int* fits16) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t slice = (int64_t)blockIdx.x * (kRowBlock / kWave) + threadIdx.x / kWave;
+  if (slice >= nslices) return;
+  const int64_t r = slice * kWave + lane;
+  int len = 0, ok = 1;
+  if (r < n) {
+    const int p0 = row_ptr[r], p1 = row_ptr[r + 1];
+    len = p1 - p0;
+    for (int p = p0; p < p1; ++p) {
+      const int64_t d = (int64_t)col[p] - r;
+      if (d < -32768 || d > 32767) ok = 0;
+    }
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    len = max(len, __shfl_xor(len, o, kWave));
+    ok = min(ok, __shfl_xor(ok, o, kWave));
+  }
+  if (lane == 0) {
+    width[slice] = len;
+    fits16[slice] = ok;
+  }
+}
+
+// Fill the packed arrays from CSR: one thread per (padded) row.
+__global__ __launch_bounds__(kRowBlock) void sell_fill_kernel(const int32_t* __restrict__ row_ptr,
+                                                              const int32_t* __restrict__ col,
+                                                              const double* __restrict__ val, int64_t n,
+                                                              int64_t nslices, const int64_t* __restrict__ soff,
+                                                              double* __restrict__ v64, float* __restrict__ v32,
+                                                              void* scol, int fmt) {
+  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
+  if (r >= nslices * kWave) return;
+  const int64_t slice = r / kWave;
+  const int lane = (int)(r % kWave);
+  const int64_t off = soff[slice];
+  const int w = (int)((soff[slice + 1] - off) >> 6);
+  const int p0 = r < n ? row_ptr[r] : 0, p1 = r < n ? row_ptr[r + 1] : 0;
+  for (int e = 0; e < w; ++e) {
+    const int64_t q = off + (int64_t)e * kWave + lane;
+    const int p = p0 + e;
+    const bool real = p < p1;
+    const double v = real ? val[p] : 0.0;
+    v64[q] = v;
+    v32[q] = (float)v;
+    if (fmt == FMT_SELL16) static_cast<int16_t*>(scol)[q] = real ? (int16_t)((int64_t)col[p] - r) : (int16_t)0;
+    else static_cast<int32_t*>(scol)[q] = real ? col[p] : (int32_t)(r < n ? r : 0);
+  }
+}
+
 // One step of the matrix-powers kernel (Sec. III): y = (A x - theta x) / sigma.
 // 4 waves x 64 rows per block; blocks are mapped XCD-contiguously so the x gathers of
 // neighbouring rows hit the same L2.  Values of type VT (float64, or the float32 copy of
 // the mixed-precision form), vectors of type T.
 struct MpkArgs {
-  const int32_t* row_ptr;
-  const int32_t* col;
-  const void* val;  // VT[nnz]
-  const void* x;    // T[n]
-  void* y;          // T[n]
+  const int32_t* row_ptr;  // CSR; packed: the slice offsets (int64)
+  const void* col;         // CSR int32; packed: int16 deltas or int32 columns
+  const void* val;         // VT[nnz] (packed: padded)
+  const void* x;           // T[n]
+  void* y;                 // T[n]
   int64_t n;
   double theta, sigma;
   const SmallState* st;
   int32_t panel;
   int32_t pad;
 };
-template <typename T, typename VT>
+template <typename T, typename VT, int FMT>
 struct MpkBody {
   typedef MpkArgs Args;
   static constexpr int kThreads = kRowBlock;
@@ -75,17 +176,22 @@ struct MpkBody {
   static __device__ void run(const MpkArgs& a, int bid, int nb) {
     gbl<const SmallState>* st = G(a.st);
     if (st->h.done || a.panel > st->h.stop_panel) return;
-    gbl<const int32_t>* __restrict__ row_ptr = G(a.row_ptr);
-    gbl<const int32_t>* __restrict__ col = G(a.col);
     gbl<const VT>* __restrict__ val = G(reinterpret_cast<const VT*>(a.val));
     gbl<const T>* __restrict__ x = G(reinterpret_cast<const T*>(a.x));
     gbl<T>* __restrict__ y = G(reinterpret_cast<T*>(a.y));
     const int64_t n = a.n;
-    __shared__ T prod[kRowBlock / kWave][kSegCap];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int64_t r0 = (int64_t)xcd_tile(bid, nb) * kRowBlock + wv * kWave;
     if (r0 >= n) return;
-    const T acc = csr_row_dot<T, VT>(row_ptr, col, val, x, n, r0, lane, prod[wv]);
+    T acc;
+    if (FMT == FMT_CSR) {
+      __shared__ T prod[kRowBlock / kWave][kSegCap];
+      acc = csr_row_dot<T, VT>(G(a.row_ptr), G(reinterpret_cast<const int32_t*>(a.col)), val, x, n, r0, lane,
+                               prod[wv]);
+    } else {
+      acc = sell_row_dot<T, VT, FMT>(G(reinterpret_cast<const int64_t*>(a.row_ptr)), val, a.col, x, n,
+                                     r0 / kWave, lane);
+    }
     const int64_t r = r0 + lane;
     if (r < n) {
       T v = acc;
@@ -114,8 +220,8 @@ __global__ __launch_bounds__(kRowBlock) void spmv_f64_kernel(
 // (explicit residual test), then initializes the cycle: beta, T = 1/beta for the
 // scaling pass, Givens rhs, cleared Hessenberg and stage-2 Gram.
 struct ResidArgs {
-  const int32_t* row_ptr;
-  const int32_t* col;
+  const int32_t* row_ptr;  // as in MpkArgs
+  const void* col;
   const double* val;
   const double* x;
   const double* b;
@@ -124,19 +230,17 @@ struct ResidArgs {
   const SmallState* st;
   double* part1;
 };
-template <typename T>
+template <typename T, int FMT>
 struct ResidBody {
   typedef ResidArgs Args;
   static constexpr int kThreads = kRowBlock;
   static constexpr int kMinWaves = 1;
   static __device__ void run(const ResidArgs& a, int bid, int nb);
 };
-template <typename T>
-__device__ void ResidBody<T>::run(const ResidArgs& a, int bid, int nb) {
+template <typename T, int FMT>
+__device__ void ResidBody<T, FMT>::run(const ResidArgs& a, int bid, int nb) {
   gbl<const SmallState>* __restrict__ st = G(a.st);
   if (st->h.done) return;
-  gbl<const int32_t>* __restrict__ row_ptr = G(a.row_ptr);
-  gbl<const int32_t>* __restrict__ col = G(a.col);
   gbl<const double>* __restrict__ val = G(a.val);
   gbl<const double>* __restrict__ x = G(a.x);
   gbl<const double>* __restrict__ b = G(a.b);
@@ -148,7 +252,12 @@ __device__ void ResidBody<T>::run(const ResidArgs& a, int bid, int nb) {
   const int64_t r0 = (int64_t)xcd_tile(bid, nb) * kRowBlock + wv * kWave;
   double rr = 0.0;
   if (r0 < n) {
-    const double acc = csr_row_dot<double, double>(row_ptr, col, val, x, n, r0, lane, prod[wv]);
+    const double acc =
+        FMT == FMT_CSR
+            ? csr_row_dot<double, double>(G(a.row_ptr), G(reinterpret_cast<const int32_t*>(a.col)), val, x, n, r0,
+                                          lane, prod[wv])
+            : sell_row_dot<double, double, FMT>(G(reinterpret_cast<const int64_t*>(a.row_ptr)), val, a.col, x,
+                                                n, r0 / kWave, lane);
     const int64_t r = r0 + lane;
     if (r < n) {
       double v = b[r] - acc;

@@ -27,6 +27,15 @@ struct tsg_csr_s {
   const double* val;
   double lo, hi;
   double* dev;  // 4 KiB: Gershgorin partials scratch of the final reduce
+  // SELL-64 plan (computed at create) and, once tsg_csr_pack ran, the packed arrays
+  int64_t nslices = 0, sell_total = 0;
+  int sell_fmt = 0;  // FMT_SELL16 or FMT_SELL32
+  std::vector<int64_t> soff_host;
+  const int64_t* soff = nullptr;
+  const double* v64 = nullptr;
+  const float* v32 = nullptr;
+  const void* scol = nullptr;
+  int packed = 0;
 };
 
 namespace {
@@ -271,9 +280,17 @@ void launch_gram_mt(const Phase& ph, const char* d, int nreq, hipStream_t s) {
 template <typename T>
 void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
   switch (ph.f) {
-    case F_RESID: launch_b<ResidBody<T>>(ph, d, nreq, s); break;
+    case F_RESID:
+      if (ph.t1 == FMT_SELL16) launch_b<ResidBody<T, FMT_SELL16>>(ph, d, nreq, s);
+      else if (ph.t1 == FMT_SELL32) launch_b<ResidBody<T, FMT_SELL32>>(ph, d, nreq, s);
+      else launch_b<ResidBody<T, FMT_CSR>>(ph, d, nreq, s);
+      break;
     case F_RTAIL: launch_b<RTailBody>(ph, d, nreq, s); break;
-    case F_MPK: launch_b<MpkBody<T, T>>(ph, d, nreq, s); break;
+    case F_MPK:
+      if (ph.t1 == FMT_SELL16) launch_b<MpkBody<T, T, FMT_SELL16>>(ph, d, nreq, s);
+      else if (ph.t1 == FMT_SELL32) launch_b<MpkBody<T, T, FMT_SELL32>>(ph, d, nreq, s);
+      else launch_b<MpkBody<T, T, FMT_CSR>>(ph, d, nreq, s);
+      break;
     case F_PREDUCE: launch_b<PReduceBody>(ph, d, nreq, s); break;
     case F_PTAIL: launch_b<PTailBody>(ph, d, nreq, s); break;
     case F_CYCLE_END: launch_b<CycleEndBody>(ph, d, nreq, s); break;
@@ -333,11 +350,13 @@ tsg_status exec_program(const Program& P, const char* d, hipStream_t s, Timer* t
 
 // One request of a program: its operator, vectors, basis and reduction buffers.
 struct ReqCtx {
-  const int32_t* row_ptr = nullptr;
-  const int32_t* col = nullptr;
+  int fmt = FMT_CSR;             // operator layout (OpFormat)
+  const int32_t* row_ptr = nullptr;  // CSR row pointers, or the packed slice offsets
+  const void* col = nullptr;     // CSR columns, or the packed column deltas / columns
   const double* val = nullptr;   // FP64 values (restart residual)
   const void* valT = nullptr;    // values of the basis type (MPK)
-  int64_t nnz = 0;
+  int64_t nnz = 0;               // stored entries (packed: with padding)
+  int64_t n_index = 0;           // row pointers or slice offsets (for the byte counts)
   const double* b = nullptr;
   double* x = nullptr;
   void* V = nullptr;
@@ -365,6 +384,12 @@ struct Builder {
   std::vector<ReqCtx*> R;
   int standalone = 0;
   int elem() const { return P.f32 ? 4 : 8; }
+  // bytes of the operator's index arrays read by one SpMV (CSR: row pointers and int32
+  // columns; packed: slice offsets and int16 deltas / int32 columns)
+  static double index_bytes(const ReqCtx& q) {
+    const double per = q.fmt == FMT_SELL16 ? 2.0 : 4.0;
+    return (double)q.n_index * (q.fmt == FMT_CSR ? 4.0 : 8.0) + (double)q.nnz * per;
+  }
 
   // One panel step: the streaming kernel and, when it reduces, the tail (after a
   // first-level reduction for requests with more than 64 blocks).
@@ -453,35 +478,42 @@ struct Builder {
     return TSG_OK;
   }
 
-  // restart residual r = b - A x into column 0, beta, convergence test, cycle set-up
+  // restart residual r = b - A x into column 0, beta, convergence test, cycle set-up.
+  // One launch per operator layout present in the batch.
   void resid() {
-    std::vector<ResidArgs> a;
-    std::vector<TailArgs> t;
-    std::vector<int> nb, one(R.size(), 1);
-    double bytes = 0.0;
-    for (ReqCtx* q : R) {
-      const int nbr = (int)cdiv(q->n, kRowBlock);
-      a.push_back(ResidArgs{q->row_ptr, q->col, q->val, q->x, q->b, q->V, q->n, q->c.st, q->c.part1});
-      t.push_back(TailArgs{q->c.st, q->c.part1, nbr, 0});
-      nb.push_back(nbr);
-      bytes += (double)(q->n + 1) * 4 + (double)q->nnz * 12 + 2.0 * q->n * 8 + (double)q->n * elem();
+    for (int fmt = FMT_CSR; fmt <= FMT_SELL32; ++fmt) {
+      std::vector<ResidArgs> a;
+      std::vector<int> nb;
+      double bytes = 0.0;
+      for (ReqCtx* q : R) {
+        const bool mine = q->fmt == fmt;
+        a.push_back(ResidArgs{q->row_ptr, q->col, q->val, q->x, q->b, q->V, q->n, q->c.st, q->c.part1});
+        nb.push_back(mine ? (int)cdiv(q->n, kRowBlock) : 0);
+        if (mine) bytes += index_bytes(*q) + (double)q->nnz * 8 + 2.0 * q->n * 8 + (double)q->n * elem();
+      }
+      P.add(F_RESID, fmt, 0, a, nb, TSG_KC_RESIDUAL, bytes);
     }
-    P.add(F_RESID, 0, 0, a, nb, TSG_KC_RESIDUAL, bytes);
+    std::vector<TailArgs> t;
+    std::vector<int> one(R.size(), 1);
+    for (ReqCtx* q : R) t.push_back(TailArgs{q->c.st, q->c.part1, (int)cdiv(q->n, kRowBlock), 0});
     P.add(F_RTAIL, 0, 0, t, one, -1, 0.0);
   }
   // w_i = (A w_{i-1} - theta_i w_{i-1}) / sigma_i into column col_out
   void mpk(int col_in, int col_out, int i, int panel) {
-    std::vector<MpkArgs> a;
-    std::vector<int> nb;
-    double bytes = 0.0;
-    for (ReqCtx* q : R) {
-      char* V = static_cast<char*>(q->V);
-      a.push_back(MpkArgs{q->row_ptr, q->col, q->valT, V + (size_t)col_in * q->ld * elem(),
-                          V + (size_t)col_out * q->ld * elem(), q->n, q->theta[i], q->sigma[i], q->c.st, panel, 0});
-      nb.push_back((int)cdiv(q->n, kRowBlock));
-      bytes += (double)(q->n + 1) * 4 + (double)q->nnz * (4 + elem()) + 2.0 * q->n * elem();
+    for (int fmt = FMT_CSR; fmt <= FMT_SELL32; ++fmt) {
+      std::vector<MpkArgs> a;
+      std::vector<int> nb;
+      double bytes = 0.0;
+      for (ReqCtx* q : R) {
+        const bool mine = q->fmt == fmt;
+        char* V = static_cast<char*>(q->V);
+        a.push_back(MpkArgs{q->row_ptr, q->col, q->valT, V + (size_t)col_in * q->ld * elem(),
+                            V + (size_t)col_out * q->ld * elem(), q->n, q->theta[i], q->sigma[i], q->c.st, panel, 0});
+        nb.push_back(mine ? (int)cdiv(q->n, kRowBlock) : 0);
+        if (mine) bytes += index_bytes(*q) + (double)q->nnz * elem() + 2.0 * q->n * elem();
+      }
+      P.add(F_MPK, fmt, 0, a, nb, TSG_KC_MPK, bytes);
     }
-    P.add(F_MPK, 0, 0, a, nb, TSG_KC_MPK, bytes);
   }
   void cycle_end(int two) {
     std::vector<TailArgs> t;
@@ -667,7 +699,75 @@ tsg_status tsg_csr_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const 
   }
   A->lo = lohi[0];
   A->hi = lohi[1];
+  // SELL-64 plan: slice widths and the column-delta range, offsets on the host
+  A->nslices = cdiv(n, kWave);
+  int* wf = nullptr;
+  e = hipMallocAsync(&wf, sizeof(int) * 2 * A->nslices, s);
+  std::vector<int> wh(2 * A->nslices);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(sell_analyze_kernel, dim3(cdiv(A->nslices, kRowBlock / kWave)), dim3(kRowBlock), 0, s,
+                       row_ptr, col, n, A->nslices, wf, wf + A->nslices);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(wh.data(), wf, sizeof(int) * 2 * A->nslices, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipFreeAsync(wf, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(A->dev);
+    delete A;
+    return fail(TSG_ERR_HIP, "operator analysis failed: %s", hipGetErrorString(e));
+  }
+  A->soff_host.resize(A->nslices + 1);
+  int fits = 1;
+  int64_t acc = 0;
+  for (int64_t i = 0; i < A->nslices; ++i) {
+    A->soff_host[i] = acc;
+    acc += (int64_t)kWave * wh[i];
+    fits &= wh[A->nslices + i];
+  }
+  A->soff_host[A->nslices] = acc;
+  A->sell_total = acc;
+  A->sell_fmt = fits ? FMT_SELL16 : FMT_SELL32;
   *out = A;
+  return TSG_OK;
+}
+
+size_t tsg_csr_pack_bytes(tsg_csr A) {
+  if (!A) return 0;
+  const size_t t = (size_t)A->sell_total;
+  return align_up((A->nslices + 1) * sizeof(int64_t)) + align_up(t * 8) + align_up(t * 4) +
+         align_up(t * (A->sell_fmt == FMT_SELL16 ? 2 : 4)) + kAlign;
+}
+
+tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream) {
+  if (!A) return fail(TSG_ERR_INVALID_ARG, "NULL operator");
+  hipStream_t s = (hipStream_t)stream;
+  if (!buf) {  // back to the CSR arrays (after the stream's pending solves)
+    HIP_TRY(hipStreamSynchronize(s));
+    A->packed = 0;
+    A->soff = nullptr;
+    A->v64 = nullptr;
+    A->v32 = nullptr;
+    A->scol = nullptr;
+    return TSG_OK;
+  }
+  if (reinterpret_cast<uintptr_t>(buf) % kAlign != 0) return fail(TSG_ERR_WORKSPACE, "buffer must be 256-byte aligned");
+  if (bytes < tsg_csr_pack_bytes(A)) return fail(TSG_ERR_WORKSPACE, "buffer %zu < required %zu", bytes, tsg_csr_pack_bytes(A));
+  Carve cv{(char*)buf};
+  int64_t* soff = cv.take<int64_t>(A->nslices + 1);
+  double* v64 = cv.take<double>((size_t)A->sell_total);
+  float* v32 = cv.take<float>((size_t)A->sell_total);
+  void* scol = A->sell_fmt == FMT_SELL16 ? (void*)cv.take<int16_t>((size_t)A->sell_total)
+                                         : (void*)cv.take<int32_t>((size_t)A->sell_total);
+  HIP_TRY(hipMemcpyAsync(soff, A->soff_host.data(), sizeof(int64_t) * (A->nslices + 1), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(sell_fill_kernel, dim3(cdiv(A->nslices * kWave, kRowBlock)), dim3(kRowBlock), 0, s, A->row_ptr,
+                     A->col, A->val, A->n, A->nslices, soff, v64, v32, scol, A->sell_fmt);
+  HIP_LAUNCH_CHECK();
+  A->soff = soff;
+  A->v64 = v64;
+  A->v32 = v32;
+  A->scol = scol;
+  A->packed = 1;
   return TSG_OK;
 }
 
@@ -763,17 +863,29 @@ void carve_request(char* base, const tsg_csr_s* A, const tsg_solve_params* p, Re
   q.c = carve_common(cv, A->n);
   q.ld = basis_ld(A->n);
   q.n = A->n;
-  q.nnz = A->nnz;
-  q.row_ptr = A->row_ptr;
-  q.col = A->col;
-  q.val = A->val;
   const bool f32 = p->precision == TSG_PREC_FP32_IR;
+  if (A->packed) {
+    q.fmt = A->sell_fmt;
+    q.nnz = A->sell_total;
+    q.n_index = A->nslices + 1;
+    q.row_ptr = reinterpret_cast<const int32_t*>(A->soff);
+    q.col = A->scol;
+    q.val = A->v64;
+  } else {
+    q.fmt = FMT_CSR;
+    q.nnz = A->nnz;
+    q.n_index = A->n + 1;
+    q.row_ptr = A->row_ptr;
+    q.col = A->col;
+    q.val = A->val;
+  }
   if (f32) {
     q.V = cv.take<float>((size_t)q.ld * (p->m + 1));
-    q.valT = cv.take<float>((size_t)std::max<int64_t>(A->nnz, 1));
+    float* v32 = cv.take<float>((size_t)std::max<int64_t>(A->nnz, 1));  // CSR form's FP32 copy
+    q.valT = A->packed ? (const void*)A->v32 : (const void*)v32;
   } else {
     q.V = cv.take<double>((size_t)q.ld * (p->m + 1));
-    q.valT = A->val;
+    q.valT = q.val;
   }
 }
 
@@ -802,7 +914,7 @@ tsg_status init_request(const tsg_csr_s* A, const tsg_solve_params* p, ReqCtx& q
   hipError_t e = hipMemcpyAsync(q.c.st, hs, offsetof(SmallState, Hh), hipMemcpyHostToDevice, s);
   delete hs;
   HIP_TRY(e);
-  if (f32 && A->nnz > 0) {
+  if (f32 && A->nnz > 0 && !A->packed) {
     hipLaunchKernelGGL(to_f32_kernel, dim3(cdiv(A->nnz, kRowBlock)), dim3(kRowBlock), 0, s, A->val,
                        (float*)q.valT, A->nnz);
   }

@@ -31,7 +31,8 @@ def test_header_declares_the_boundary():
     for s in ("tsg_csr_create", "tsg_csr_destroy", "tsg_spmv", "tsg_solve", "tsg_solve_workspace_bytes",
               "tsg_orthogonalize", "tsg_orthogonalize_workspace_bytes", "tsg_status_string",
               "tsg_last_error", "tsg_csr_gershgorin", "tsg_server_create", "tsg_server_destroy",
-              "tsg_server_submit", "tsg_server_step", "tsg_server_poll", "tsg_server_request_bytes"):
+              "tsg_server_submit", "tsg_server_step", "tsg_server_poll", "tsg_server_request_bytes",
+              "tsg_csr_pack", "tsg_csr_pack_bytes"):
         assert s in syms
 
 

@@ -219,6 +219,51 @@ def test_zero_rhs(tsg):
     assert info.converged and float(x.abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("kind,N,prec", [("laplace2d", 64, "fp64"), ("convdiff2d", 93, "fp64"),
+                                         ("convdiff2d", 93, "fp32_ir"), ("laplace3d", 17, "fp64")])
+def test_packed_operator_equals_csr(tsg, kind, N, prec):
+    """The packed SELL-64 operator and the CSR kernels give the same solve bit for bit
+    (same products, rounded the same way, summed in the same order)."""
+    _say("case packed vs csr", kind, N, prec)
+    pr = W.make_problem(kind, N, seed=4)
+    b = _dev(pr["b"])
+    kw = dict(m=60, s=5, tol=1e-10, precision=prec, basis="shifted")
+    Ac = tsg.CSRMatrix.from_host(pr["A"], pack=False)
+    Ap = tsg.CSRMatrix.from_host(pr["A"], pack=True)
+    xc, ic = tsg.solve(Ac, b, **kw)
+    xp, ip = tsg.solve(Ap, b, **kw)
+    assert torch.equal(xc, xp)
+    assert (ic.iters, ic.cycles) == (ip.iters, ip.cycles)
+    Ap.unpack()
+    xu, iu = tsg.solve(Ap, b, **kw)
+    assert torch.equal(xc, xu)
+
+
+def test_packed_operator_wide_columns(tsg):
+    """A matrix whose column deltas exceed int16 uses the int32 packed columns."""
+    _say("case packed int32 columns")
+    import scipy.sparse as sp
+    n = 70000
+    rng = np.random.default_rng(5)
+    rows = np.repeat(np.arange(n), 4)
+    cols = rng.integers(0, n, size=4 * n)  # far columns: deltas beyond int16
+    M = sp.csr_matrix((rng.uniform(0, 1, 4 * n), (rows, cols)), shape=(n, n)) + sp.eye(n, format="csr") * 8.0
+    M = M.tocsr()
+    M.sum_duplicates()
+    M.sort_indices()
+    A = W.CSR(n=n, row_ptr=M.indptr.astype(np.int32), col=M.indices.astype(np.int32), val=M.data.astype(np.float64))
+    b = rng.uniform(-1, 1, n)
+    Ac = tsg.CSRMatrix.from_host(A, pack=False)
+    Ap = tsg.CSRMatrix.from_host(A, pack=True)
+    x = _dev(rng.uniform(-1, 1, n))
+    kw = dict(m=30, s=5, tol=1e-12, basis="shifted")
+    xc, ic = tsg.solve(Ac, _dev(b), **kw)
+    xp, ip = tsg.solve(Ap, _dev(b), **kw)
+    assert torch.equal(xc, xp)
+    ref = G.sstep_gmres(A, b, m=30, s=5, tol=1e-12, basis="shifted")
+    assert ic.iters == ref["iters"]
+
+
 def test_determinism(tsg):
     _say("case determinism")
     pr = W.make_problem("convdiff2d", 64, seed=1)
