@@ -185,13 +185,12 @@ def main():
     st_ = lambda w: w if w <= 6 else (8 if w <= 8 else (10 if w <= 10 else (12 if w <= 12 else 16)))
     s_ = args.s
     nt2 = 1 if 2 * args.s <= 16 else 2
-    fs = min(v for v in (1, 2, 4, 5, 8, 10, 16) if v >= s_)
     names = {  # every per-request kernel runs as batched_kernel<Body>
         "mpk": f"MpkBody<{elem}, {elem}>",
         "gram": f"GramBody<{elem}, 1..4, {nt2}>",
         "gram_first": f"GramBody<{elem}, {(args.s + 16) // 16}, {(args.s + 16) // 16}>",
         "update": f"UpdateBody<{elem}, {st_(s_)}>",
-        "fused": f"FusedBody<{elem}, 4, {fs}>",
+        "fused": f"FusedBody<{elem}, 4>",
     }
     streaming = {c: v for c, v in classes.items() if c in names and v[0] > 0}
     dom = max(streaming, key=lambda c: streaming[c][0])

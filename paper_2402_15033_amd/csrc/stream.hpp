@@ -259,21 +259,22 @@ __device__ void UpdateBody<T, S>::run(const PanelArgs& a, int bid, int) {
 //     q = (W(r,:) - Q(r,:) P) T          (PF_HAS_P / PF_HAS_T; Q = V(:,0:k), W = V(:,wcol:+sw))
 // stored in place (PF_STORE), and the Gram of its output  G = [Q, q]^T q  (PF_GRAM_Q: Q rows;
 // the q rows always), in one pass over the rows.  Batches of the staged columns (Q when
-// it is needed, then W) go through LDS as in TileLoad; between the two barriers of a batch
-// every row's q is formed in the tile (the next two batches load meanwhile): `parts` consecutive lanes share a row, each summing
-// Q(r,c) P(c,:) over every parts-th column, the partial sums are combined by lane exchange
-// (xor shuffles), and each lane applies T for its own columns and writes q over W.  The
-// matrix cores then reduce the tile, and the waves store q from LDS in whole row segments.
-// Partials: (k + sw) x sw float64 per block (rows of Q zero unless PF_GRAM_Q).
-template <typename T, int MT, int S>
+// it is needed, then W) go through LDS as in TileLoad.  The update is itself a product:
+// q = [Q, W] B with B = [-P T; T] ((k+sw) x sw, formed once per block in LDS), so each
+// 16-row tile of the batch is multiplied by B on the matrix cores (rows are the M
+// dimension, the staged columns the K dimension) and q is written over W in the tile;
+// after a barrier the matrix cores reduce the Gram of the tile as in gram_mfma_kernel, and
+// the waves store q from LDS in whole row segments.  Partials: (k + sw) x sw float64 per
+// block (rows of Q zero unless PF_GRAM_Q).  Requires sw <= 16.
+template <typename T, int MT>
 struct FusedBody {
   typedef PanelArgs Args;
   static constexpr int kThreads = 512;
-  static constexpr int kMinWaves = S <= 10 ? 4 : 1;  // two 8-wave blocks per CU up to s = 10
+  static constexpr int kMinWaves = 4;  // two 8-wave blocks per CU
   static __device__ void run(const PanelArgs& a, int bid, int nb);
 };
-template <typename T, int MT, int S>
-__device__ void FusedBody<T, MT, S>::run(const PanelArgs& a, int bid, int) {
+template <typename T, int MT>
+__device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
   if (gated_off(a, a.st)) return;
   gbl<const SmallState>* st = G(a.st);
   typedef typename MfmaOp<T>::v4 v4;
@@ -294,22 +295,30 @@ __device__ void FusedBody<T, MT, S>::run(const PanelArgs& a, int bid, int) {
   gbl<T>* __restrict__ V = G(reinterpret_cast<T*>(a.V));
   const int64_t ld = a.ld;
   __shared__ T lt[2][mfma_tile<T>()];
-  __shared__ T lP[kMaxCols * S];
-  __shared__ T lT[S * S];
-  for (int idx = tid; idx < kMaxCols * S; idx += blockDim.x) {
-    const int c = idx / S, j = idx % S;
-    lP[idx] = (hasP && c < k && j < sw) ? (T)st->Pcur[c + j * kLd] : (T)0;
-  }
-  for (int idx = tid; idx < S * S; idx += blockDim.x) {
-    const int i = idx / S, j = idx % S;
-    lT[idx] = (i < sw && j < sw && i <= j) ? (T)st->Tcur[i + j * kMaxS] : (T)0;
+  __shared__ T lB[(kMaxCols + 4) * 16];  // B(c, j) at c * 16 + j, zero-padded to 16 columns
+  // B = [-P T; T]: rows c < kq from the projection, rows kq + i from T (identity if no T)
+  for (int idx = tid; idx < (kMaxCols + 4) * 16; idx += blockDim.x) {
+    const int c = idx / 16, j = idx % 16;
+    double v = 0.0;
+    if (j < sw && c < ncol) {
+      if (c < kq) {
+        if (hasP) {
+          if (hasT) {
+            for (int l = 0; l <= j; ++l) v -= st->Pcur[c + l * kLd] * st->Tcur[l + j * kMaxS];
+          } else {
+            v = -st->Pcur[c + j * kLd];
+          }
+        }
+      } else {
+        const int i = c - kq;
+        v = hasT ? (i <= j ? st->Tcur[i + j * kMaxS] : 0.0) : (i == j ? 1.0 : 0.0);
+      }
+    }
+    lB[idx] = (T)v;
   }
   TL tl;
   tl.init(wv, ncol, kq, a.wcol, ld);
   const int BR = tl.BR, LDT = tl.LDT;
-  const int parts = BR <= 64 ? 8 : (BR <= 128 ? 4 : (BR <= 256 ? 2 : 1));  // lanes per row
-  const int rows_pass = 512 / parts;
-  const int part = tid % parts;
 
   const int64_t rb = (int64_t)bid * a.rows_per_block;
   const int64_t re = min(a.n, rb + a.rows_per_block);
@@ -318,6 +327,7 @@ __device__ void FusedBody<T, MT, S>::run(const PanelArgs& a, int bid, int) {
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) acc[mt] = v4{0, 0, 0, 0};
   const int li = lane & 15, lk = lane >> 4;
+  const int ksteps_upd = (ncol + 3) / 4;
   tl.load(V, wv, lane, rb, re, v);
   if (rb + BR < re) tl.load(V, wv, lane, rb + BR, re, vn);
   int buf = 0;
@@ -326,43 +336,18 @@ __device__ void FusedBody<T, MT, S>::run(const PanelArgs& a, int bid, int) {
     T* L = lt[buf];
     tl.to_lds(L, wv, lane, v);
     __syncthreads();
-    // ---- q = (W - Q P) T for the rows of the batch, in the tile.  The compiler barrier
-    //      keeps P and T in LDS (held in registers across batches they would take
-    //      k s + s^2 of them)
-    asm volatile("" ::: "memory");
-    for (int rbase = 0; rbase < BR; rbase += rows_pass) {
-      const int rl = rbase + tid / parts;
-      const bool rok = rl < BR;
-      T y[S];
-#pragma unroll
-      for (int j = 0; j < S; ++j) y[j] = (T)0;
-      if (hasP) {
-        for (int c = part; c < k; c += parts) {
-          const T qv = rok ? L[c * LDT + rl] : (T)0;
-#pragma unroll
-          for (int j = 0; j < S; ++j) y[j] += qv * lP[c * S + j];
-        }
-        for (int o = 1; o < parts; o <<= 1) {
-#pragma unroll
-          for (int j = 0; j < S; ++j) y[j] += __shfl_xor(y[j], o, kWave);
-        }
+    // ---- q = [Q, W] B for 16-row tiles: lane holds A(row li, column kk + lk) and
+    //      B(kk + lk, li); the wave's rows are its own, so it overwrites their W in place
+    for (int m0 = wv * 16; m0 < BR; m0 += NW * 16) {
+      v4 d = v4{0, 0, 0, 0};
+      for (int ks = 0; ks < ksteps_upd; ++ks) {
+        const int c = ks * 4 + lk;
+        const T av = (c < ncol) ? L[c * LDT + m0 + li] : (T)0;
+        d = MfmaOp<T>::mac(av, lB[c * 16 + li], d);
       }
+      if (li < sw) {
 #pragma unroll
-      for (int j = 0; j < S; ++j) y[j] = (rok && j < sw) ? L[(kq + j) * LDT + rl] - y[j] : (T)0;
-      // every lane of the row now holds y; each forms q(r, j) = sum_{i <= j} y_i T(i, j) for
-      // its own columns j = part, part + parts, ... and writes it over W(r, j)
-      for (int j = part; j < sw; j += parts) {
-        T q = (T)0;
-        if (hasT) {
-#pragma unroll
-          for (int i = 0; i < S; ++i)
-            if (i <= j) q += y[i] * lT[i * S + j];
-        } else {
-#pragma unroll
-          for (int i = 0; i < S; ++i)
-            if (i == j) q = y[i];
-        }
-        if (rok) L[(kq + j) * LDT + rl] = q;
+        for (int r = 0; r < 4; ++r) L[(kq + li) * LDT + m0 + MfmaOp<T>::row(lk, r)] = d[r];
       }
     }
     __syncthreads();

@@ -205,8 +205,6 @@ struct Timer {
 
 // Round a panel width up to an instantiated template width.
 int s_template(int sw) { return sw <= 6 ? sw : (sw <= 8 ? 8 : (sw <= 10 ? 10 : (sw <= 12 ? 12 : 16))); }
-// Panel widths with a fused-kernel instantiation (a panel runs in the smallest one >= sw).
-int fused_s(int sw) { return sw <= 1 ? 1 : sw <= 2 ? 2 : sw <= 4 ? 4 : sw <= 5 ? 5 : sw <= 8 ? 8 : sw <= 10 ? 10 : 16; }
 constexpr int kMaxGramNz = kMaxNz;   // widest lean reduction (two 16-wide MFMA tiles)
 constexpr int kMaxMfmaBlocks = 512;  // two 8-wave blocks per CU
 static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks, "reduction partial buffer too small");
@@ -261,18 +259,6 @@ void launch_b(const Phase& ph, const char* d, int nreq, hipStream_t s) {
                      reinterpret_cast<const int*>(d + ph.boff), nreq);
 }
 template <typename T, int MT>
-void launch_fused_mt(const Phase& ph, const char* d, int nreq, hipStream_t s) {
-  switch (ph.t2) {
-    case 1: launch_b<FusedBody<T, MT, 1>>(ph, d, nreq, s); break;
-    case 2: launch_b<FusedBody<T, MT, 2>>(ph, d, nreq, s); break;
-    case 4: launch_b<FusedBody<T, MT, 4>>(ph, d, nreq, s); break;
-    case 5: launch_b<FusedBody<T, MT, 5>>(ph, d, nreq, s); break;
-    case 8: launch_b<FusedBody<T, MT, 8>>(ph, d, nreq, s); break;
-    case 10: launch_b<FusedBody<T, MT, 10>>(ph, d, nreq, s); break;
-    default: launch_b<FusedBody<T, MT, 16>>(ph, d, nreq, s); break;
-  }
-}
-template <typename T, int MT>
 void launch_gram_mt(const Phase& ph, const char* d, int nreq, hipStream_t s) {
   if (ph.t2 == 1) launch_b<GramBody<T, MT, 1>>(ph, d, nreq, s);
   else launch_b<GramBody<T, MT, 2>>(ph, d, nreq, s);
@@ -319,10 +305,10 @@ void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
       break;
     case F_FUSED:
       switch (ph.t1) {
-        case 1: launch_fused_mt<T, 1>(ph, d, nreq, s); break;
-        case 2: launch_fused_mt<T, 2>(ph, d, nreq, s); break;
-        case 3: launch_fused_mt<T, 3>(ph, d, nreq, s); break;
-        default: launch_fused_mt<T, 4>(ph, d, nreq, s); break;
+        case 1: launch_b<FusedBody<T, 1>>(ph, d, nreq, s); break;
+        case 2: launch_b<FusedBody<T, 2>>(ph, d, nreq, s); break;
+        case 3: launch_b<FusedBody<T, 3>>(ph, d, nreq, s); break;
+        default: launch_b<FusedBody<T, 4>>(ph, d, nreq, s); break;
       }
       break;
   }
@@ -454,7 +440,7 @@ struct Builder {
       P.add(F_GRAM, (st.k + st.sw + 15) / 16, nz <= 16 ? 1 : 2, a, nb, kc, fb ? 0.0 : bytes);
     } else {
       const int ncolA = (st.flags & PF_GRAM_Q) ? st.k + st.sw : st.sw;
-      P.add(F_FUSED, (ncolA + 15) / 16, fused_s(st.sw), a, nb, kc, fb ? 0.0 : bytes);
+      P.add(F_FUSED, (ncolA + 15) / 16, 0, a, nb, kc, fb ? 0.0 : bytes);
     }
     if (!reduces) return TSG_OK;
     // first level for requests with many blocks, then the tail
