@@ -161,10 +161,20 @@ def hessenberg_block(Hh: np.ndarray, P: np.ndarray, R: np.ndarray, B: np.ndarray
 
 def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
                 max_iters: int = 10**9, ortho: str = "two_stage",
-                basis: str = "monomial", shifts=None, record: bool = False):
-    """s-step GMRES(m) with one-stage or two-stage (s_hat = m) block orthogonalization."""
+                basis: str = "monomial", shifts=None, record: bool = False, s_hat: int | None = None):
+    """s-step GMRES(m) with one-stage or two-stage block orthogonalization.
+
+    Two-stage with s_hat = m (default): stage 2 is one CholQR of the m+1 columns at the end
+    of the cycle.  With s_hat < m (s | s_hat | m) the cycle's columns form big panels (the
+    first holds column 1 plus s_hat columns, the others s_hat columns, as in the
+    stand-alone scheme) and stage 2 runs when each big panel is complete (Sec. V, Fig. 5).
+    """
     if m % s != 0:
         raise ValueError("s must divide m")
+    if ortho == "two_stage" and s_hat is not None and s_hat < m:
+        if s_hat % s != 0 or m % s_hat != 0:
+            raise ValueError("need s | s_hat | m")
+        return _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record)
     op = A if isinstance(A, Operator) else Operator(A)
     theta, sigma = basis_params(op, s, basis, shifts)
     J = m // s
@@ -233,6 +243,115 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
             rec = {"Q": Qh[:, : k_used + 1], "H": Hh[: k_used + 1, :k_used], "y": y,
                    "panels": panels, "beta": beta, "breakdown": breakdown}
         return Qh[:, :k_used] @ y, k_used, abs(giv.g[k_used]), rec
+
+    out = _outer(op, b, x0, tol, max_iters, cycle, record)
+    out["theta"], out["sigma"] = theta, sigma
+    out["fallbacks"] = stats["fallbacks"]
+    return out
+
+
+def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record):
+    """Two-stage s-step GMRES(m) with big panels of s_hat < m columns.
+
+    Within a cycle the basis Y holds final (orthonormal) columns for the completed big
+    panels and pre-processed columns for the current one; the Hessenberg matrix H always
+    describes A Y(:, :c-1) = Y(:, :c) H for the current Y.  Stage 1 of each panel and its
+    Hessenberg block are as with s_hat = m.  When a big panel [b0, b1) is complete,
+    stage 2 is one BCGS-PIP of it against the final columns (the explicit Q of Fig. 5):
+      P2 = Y(:, :b0)^T Y(:, b0:b1),  R2 = Chol(Y_b^T Y_b - P2^T P2),
+      Y(:, b0:b1) <- (Y(:, b0:b1) - Y(:, :b0) P2) R2^{-1},
+    i.e. Y_old = Y_new M with M = I except M(:b0, b0:b1) = P2, M(b0:b1, b0:b1) = R2, so
+    H <- M(:b1, :b1) H M(:b1-1, :b1-1)^{-1} (still upper Hessenberg) and the least-squares
+    rhs beta e_1 becomes beta M(0, 0) e_1.  The next panel's matrix-powers kernel then starts
+    from the final column (reading of the paper's silence on the start vector).  The
+    residual is checked at the end of every big panel (least squares over the final
+    columns); the cycle stops there when it is below tol.
+    """
+    op = A if isinstance(A, Operator) else Operator(A)
+    theta, sigma = basis_params(op, s, basis, shifts)
+    J = m // s
+    bigs = blockortho.big_panel_bounds(m + 1, s, s_hat)
+    stats = {"fallbacks": 0}
+
+    def stage2(Y, H, done, b1, c_h):
+        """Stage 2 on columns [done, b1); transforms H(:b1, :c_h).  Returns (kept, M00)."""
+        Yb = Y[:, done:b1]
+        P2 = Y[:, :done].T @ Yb
+        Gb = Yb.T @ Yb
+        G = Gb - P2.T @ P2
+        kept = b1 - done
+        try:
+            R2 = chol_upper(G, ref_diag=np.diag(Gb), tol=PIVOT_TOL)
+        except CholeskyBreakdown as e:
+            kept = e.index
+            if kept == 0:
+                return 0, None
+            R2 = chol_upper(G[:kept, :kept], ref_diag=np.diag(Gb)[:kept], tol=PIVOT_TOL)
+            P2 = P2[:, :kept]
+        e1 = done + kept
+        Y[:, done:e1] = right_solve_upper(Y[:, done:e1] - Y[:, :done] @ P2, R2)
+        M = np.eye(e1)
+        M[:done, done:e1] = P2
+        M[done:e1, done:e1] = R2
+        c = min(c_h, e1 - 1)
+        H[:e1, :c] = right_solve_upper(M @ H[:e1, :c], M[:c, :c])
+        H[e1:, :c] = 0.0
+        return kept, M[0, 0]
+
+    def cycle(op, r, beta, tol_abs):
+        n = op.n
+        Y = np.zeros((n, m + 1), order="F")
+        H = np.zeros((m + 1, m))
+        Y[:, 0] = r / beta
+        g0 = beta
+        done = 0  # columns already final
+        bi = 0
+        k_used = m
+        breakdown = None
+        est = beta
+        for j in range(J):
+            k = j * s + 1
+            W, B = mpk(op, Y[:, k - 1], theta, sigma)
+            try:
+                Qn, P, R, fb = blockortho.bcgs_pip_explicit(Y[:, :k], W, PIVOT_TOL)
+                stats["fallbacks"] += int(fb)
+            except CholeskyBreakdown:
+                k_used = k - 1
+                breakdown = ("panel", j)
+                break
+            Y[:, k: k + s] = Qn
+            H[: k + s, k - 1: k - 1 + s] = hessenberg_block(H, P, R, B, k)
+            b0, b1 = bigs[bi]
+            if k + s == b1:
+                kept, m00 = stage2(Y, H, done, b1, b1 - 1)
+                if done == 0 and kept > 0:
+                    g0 = beta * m00
+                if kept < b1 - done:  # stage-2 breakdown: keep the leading columns
+                    k_used = done + kept - 1
+                    breakdown = ("stage2", done + kept)
+                    done = done + kept
+                    break
+                done = b1
+                bi += 1
+                _, est = givens_lsq(H[:b1, : b1 - 1], g0)
+                if est <= tol_abs:
+                    k_used = b1 - 1
+                    break
+        if breakdown is not None and breakdown[0] == "panel" and done < k_used + 1:
+            # the unfinished big panel still needs its stage 2 before the least squares
+            kept, m00 = stage2(Y, H, done, k_used + 1, k_used)
+            if done == 0 and kept > 0:
+                g0 = beta * m00
+            k_used = done + kept - 1
+        if k_used <= 0:
+            return np.zeros(n), 0, beta, {"breakdown": breakdown} if record else None
+        y, est = givens_lsq(H[: k_used + 1, :k_used], g0)
+        dx = Y[:, :k_used] @ y
+        rec = None
+        if record:
+            rec = {"Q": Y[:, : k_used + 1].copy(), "H": H[: k_used + 1, :k_used].copy(), "y": y,
+                   "beta": beta, "g0": g0, "breakdown": breakdown}
+        return dx, k_used, est, rec
 
     out = _outer(op, b, x0, tol, max_iters, cycle, record)
     out["theta"], out["sigma"] = theta, sigma

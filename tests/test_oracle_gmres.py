@@ -210,3 +210,46 @@ def test_monomial_s10_takes_the_explicit_second_pass():
     # the shifted basis keeps every panel inside the limit: no second pass
     out2 = G.sstep_gmres(pr["A"], pr["b"], m=60, s=10, tol=1e-10, basis="shifted")
     assert out2["fallbacks"] == 0
+
+
+# ------------------------------------------------------------------ two-stage with s_hat < m
+@pytest.mark.parametrize("s_hat", [5, 10, 20, 30])
+def test_shat_checkpoints_and_basis(lap64, s_hat):
+    """Big panels of s_hat columns: the residual is checked at every big-panel end, so the
+    iteration count is the standard count rounded up to the next check point (Table 2's
+    rule); the first cycle's final basis is orthonormal and satisfies the Arnoldi relation."""
+    pr = lap64
+    A, b = pr["A"], pr["b"]
+    std = G.gmres(A, b, m=60, tol=1e-10, ortho="cgs2")
+    r = G.sstep_gmres(A, b, m=60, s=5, tol=1e-10, s_hat=s_hat, record=True)
+    full, part = divmod(std["iters"], 60)
+    expect = full * 60 + (-(-part // s_hat) * s_hat if part else 0)
+    assert r["converged"] and r["relres"] <= 1e-10
+    assert r["iters"] == expect
+    rec = r["records"][0]
+    Q, H = rec["Q"], rec["H"]
+    assert D.orth_error(Q) <= 1e-13
+    op = S.Operator(A)
+    AQ = np.column_stack([S.spmv(op, Q[:, i]) for i in range(H.shape[1])])
+    assert np.linalg.norm(AQ - Q @ H) / (8 * np.linalg.norm(Q)) <= 1e-13
+    assert np.allclose(np.tril(H, -2), 0.0)
+
+
+def test_shat_equal_s_is_bcgs_pip2(lap64):
+    """With s_hat = s every panel gets stage 1 then stage 2, both BCGS-PIP against all
+    previous columns: that is BCGS-PIP2 (Fig. 4b), whose one-stage solve checks at the
+    same points -- same iteration count, same iterate up to rounding."""
+    pr = lap64
+    a = G.sstep_gmres(pr["A"], pr["b"], m=60, s=5, tol=1e-10, s_hat=5)
+    b = G.sstep_gmres(pr["A"], pr["b"], m=60, s=5, tol=1e-10, ortho="bcgs_pip2")
+    assert a["iters"] == b["iters"] and a["cycles"] == b["cycles"]
+    assert np.linalg.norm(a["x"] - b["x"]) / np.linalg.norm(b["x"]) <= 1e-10
+
+
+def test_shat_first_cycle_is_the_krylov_minimizer():
+    """A full first cycle (no early stop) gives the same x as standard GMRES(m)."""
+    pr = W.make_problem("convdiff2d", 24, seed=2)
+    a = G.sstep_gmres(pr["A"], pr["b"], m=30, s=5, tol=1e-14, s_hat=10, max_iters=30)
+    b = G.gmres(pr["A"], pr["b"], m=30, tol=1e-14, ortho="mgs", max_iters=30)
+    assert a["iters"] == 30 and b["iters"] == 30
+    assert np.linalg.norm(a["x"] - b["x"]) / np.linalg.norm(b["x"]) <= 1e-10
