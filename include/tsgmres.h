@@ -76,7 +76,10 @@ typedef enum { TSG_PREC_FP64 = 0, TSG_PREC_FP32_IR = 1 } tsg_prec;
 typedef struct {
   int32_t m;            /* restart length (Krylov vectors per cycle), 1 <= m <= 63      */
   int32_t s;            /* step size; s divides m; 1 <= s <= 16 (CGS2 ignores s)        */
-  int32_t s_hat;        /* second step size; 0 or m (s_hat < m is not built: UNSUPPORTED)*/
+  int32_t s_hat;        /* two-stage big-panel size: 0 or m (one stage 2 per cycle), or
+                           s | s_hat | m (stage 2 = BCGS-PIP of every completed big panel
+                           against the final columns, explicit Q; the residual is checked
+                           at every big-panel end)                                      */
   int32_t ortho;        /* tsg_ortho                                                    */
   int32_t basis;        /* tsg_basis                                                    */
   int32_t precision;    /* tsg_prec                                                     */
@@ -113,7 +116,8 @@ enum {
   TSG_KC_SCALE = 9,      /* first basis vector r / beta                                   */
   TSG_KC_FALLBACK = 10,  /* two-stage explicit second pass (its launches return at entry
                             unless a panel needs it; no bytes are attributed)            */
-  TSG_KC_COUNT = 11
+  TSG_KC_STAGE2 = 11,    /* two-stage with s_hat < m: big-panel stage 2 (tail, explicit Q) */
+  TSG_KC_COUNT = 12
 };
 
 typedef struct {

@@ -265,7 +265,8 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
     rhs beta e_1 becomes beta M(0, 0) e_1.  The next panel's matrix-powers kernel then starts
     from the final column (reading of the paper's silence on the start vector).  The
     residual is checked at the end of every big panel (least squares over the final
-    columns); the cycle stops there when it is below tol.
+    columns); the cycle stops there when it is below tol.  A stage-1 breakdown ends the
+    cycle with the columns of its completed big panels.
     """
     op = A if isinstance(A, Operator) else Operator(A)
     theta, sigma = basis_params(op, s, basis, shifts)
@@ -316,7 +317,10 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
                 Qn, P, R, fb = blockortho.bcgs_pip_explicit(Y[:, :k], W, PIVOT_TOL)
                 stats["fallbacks"] += int(fb)
             except CholeskyBreakdown:
-                k_used = k - 1
+                # the cycle keeps the columns of its completed big panels (their stage 2
+                # is done and their residual was checked); the unfinished big panel is
+                # dropped
+                k_used = done - 1
                 breakdown = ("panel", j)
                 break
             Y[:, k: k + s] = Qn
@@ -337,12 +341,6 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
                 if est <= tol_abs:
                     k_used = b1 - 1
                     break
-        if breakdown is not None and breakdown[0] == "panel" and done < k_used + 1:
-            # the unfinished big panel still needs its stage 2 before the least squares
-            kept, m00 = stage2(Y, H, done, k_used + 1, k_used)
-            if done == 0 and kept > 0:
-                g0 = beta * m00
-            k_used = done + kept - 1
         if k_used <= 0:
             return np.zeros(n), 0, beta, {"breakdown": breakdown} if record else None
         y, est = givens_lsq(H[: k_used + 1, :k_used], g0)

@@ -50,7 +50,7 @@ class _Info(C.Structure):
 
 
 KERNEL_CLASSES = ["mpk", "gram", "gram_first", "update", "fused", "tail", "cycle_end", "xupdate",
-                  "residual", "scale", "fallback"]
+                  "residual", "scale", "fallback", "stage2"]
 
 
 @dataclass
@@ -254,9 +254,9 @@ def spmv(A: CSRMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.
     return y
 
 
-def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph=True):
+def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph=True, s_hat=0):
     p = _Params()
-    p.m, p.s, p.s_hat = int(m), int(s), 0
+    p.m, p.s, p.s_hat = int(m), int(s), int(s_hat or 0)
     p.ortho = ORTHO[ortho] if isinstance(ortho, str) else int(ortho)
     p.basis = BASIS[basis] if isinstance(basis, str) else int(basis)
     p.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
@@ -272,25 +272,26 @@ def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph
 
 
 def solve_workspace_bytes(A: CSRMatrix, m=60, s=5, ortho="two_stage", basis="monomial",
-                          precision="fp64") -> int:
-    p, _ = _params(m, s, ortho, basis, precision, 1e-10, 1 << 40, None, False)
+                          precision="fp64", s_hat=0) -> int:
+    p, _ = _params(m, s, ortho, basis, precision, 1e-10, 1 << 40, None, False, s_hat=s_hat)
     return int(load_library().tsg_solve_workspace_bytes(A.n, A.nnz, C.byref(p)))
 
 
 def solve(A: CSRMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, m: int = 60, s: int = 5,
           tol: float = 1e-10, max_iters: int = 1 << 40, ortho: str = "two_stage",
           basis: str = "monomial", precision: str = "fp64", shifts=None, timing: bool = False,
-          graph: bool = True, workspace: torch.Tensor | None = None):
+          graph: bool = True, s_hat: int = 0, workspace: torch.Tensor | None = None):
     """Solve A x = b (x updated in place; zeros if None).  Returns (x, SolveInfo).
 
     graph=False launches every kernel directly instead of replaying one captured restart
-    cycle per cycle (same results, bit for bit)."""
+    cycle per cycle (same results, bit for bit).  s_hat (two-stage): 0 or m for one big
+    panel per cycle, else the big-panel size (s | s_hat | m)."""
     lib = load_library()
     _dev_tensor(b, torch.float64, "b")
     if x is None:
         x = torch.zeros_like(b)
     _dev_tensor(x, torch.float64, "x")
-    p, keep = _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph)
+    p, keep = _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph, s_hat)
     need = int(lib.tsg_solve_workspace_bytes(A.n, A.nnz, C.byref(p)))
     if need == 0:
         _check(-1)
@@ -365,9 +366,9 @@ class Server:
 
     def __init__(self, arena_bytes: int, *, m: int = 60, s: int = 5, tol: float = 1e-8,
                  max_iters: int = 1 << 40, ortho: str = "two_stage", basis: str = "shifted",
-                 precision: str = "fp32_ir", max_active: int = 256, device="cuda"):
+                 precision: str = "fp32_ir", max_active: int = 256, s_hat: int = 0, device="cuda"):
         lib = load_library()
-        self._p, _ = _params(m, s, ortho, basis, precision, tol, max_iters, None, False)
+        self._p, _ = _params(m, s, ortho, basis, precision, tol, max_iters, None, False, s_hat=s_hat)
         self.device = torch.device(device)
         self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
         base = (self._arena.data_ptr() + 255) // 256 * 256

@@ -321,6 +321,7 @@ __device__ void RTailBody::run(const TailArgs& a, int, int) {
       st->h.stop_panel = 1 << 30;
       st->h.k_used = st->m;
       st->h.refine = 0;
+      st->gscale = beta;
     }
   }
   __syncthreads();
@@ -597,6 +598,127 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
     st->h.cycles += 1;
     st->h.est = est / st->bnorm;
   }
+}
+
+// ------------------------------------------------------------------ big-panel stage 2
+// Two-stage with big panels (s_hat < m), at the end of big panel [b0, b1) of the cycle:
+// stage 2 = BCGS-PIP of the big panel against the final columns 0..b0-1 (Fig. 5), from
+// the stage-2 Gram block columns the panels' reductions accumulated in st->G2:
+//   P2 = G2(:b0, b0:b1),  R2 = Chol(G2(b0:b1, b0:b1) - P2^T P2),  T2 = R2^{-1},
+//   Bs(:b1, b0:b1) = [-P2 T2; T2]  (the apply launches then form Y(:, b0:b1) <- Y(:, :b1) Bs).
+// The basis change Y_old = Y_new M (M = I but M(:b0, b0:b1) = P2, M(b0:b1, b0:b1) = R2)
+// transforms the Hessenberg matrix, H <- M H M(:b1-1, :b1-1)^{-1}; the least-squares
+// problem over the final columns is refactored by Givens from scratch and the residual
+// checked (the cycle stops after this big panel when it is below tol).  A stage-2 pivot
+// failure at column f keeps the big panel's first f columns and ends the cycle.
+struct S2Args {
+  SmallState* st;
+  int32_t b0, b1, panel, pad;
+};
+struct Stage2Body {
+  typedef S2Args Args;
+  static constexpr int kThreads = 256;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const S2Args& a, int bid, int nb);
+};
+__device__ void Stage2Body::run(const S2Args& a, int, int) {
+  SmallState* st = a.st;
+  if (st->h.done || a.panel > st->h.stop_panel) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int b0 = a.b0, w = a.b1 - a.b0;
+  __shared__ double sG[kLd * kLd];   // w x w Gram, then reused for M H
+  __shared__ double sR[kLd * kLd];   // R2, then H
+  __shared__ double sM[kLd * kLd];   // T2, then M
+  __shared__ double sref[kLd];
+  __shared__ int s_kept;
+  // G = Gb - P2^T P2 (G2 holds the upper triangle)
+  for (int idx = tid; idx < w * w; idx += nt) {
+    const int i = idx % w, j = idx / w;
+    const int r = b0 + min(i, j), c = b0 + max(i, j);
+    double v = st->G2[r + c * kLd];
+    if (i == j) sref[i] = v;
+    for (int l = 0; l < b0; ++l) v -= st->G2[l + (b0 + i) * kLd] * st->G2[l + (b0 + j) * kLd];
+    sG[i + j * kLd] = v;
+  }
+  __syncthreads();
+  const int f = block_chol_upper(sG, kLd, sR, kLd, w, sref, st->pivot_tol);
+  if (tid == 0) s_kept = f < 0 ? w : f;
+  __syncthreads();
+  const int kept = s_kept;
+  if (kept == 0) {  // nothing of this big panel survives: keep the final columns before it
+    if (tid == 0) {
+      st->h.stop_panel = a.panel - 1;
+      st->h.k_used = b0 > 0 ? b0 - 1 : 0;
+      st->h.truncated += 1;
+    }
+    return;
+  }
+  block_tri_inv_upper(sR, kLd, sM, kLd, kept);  // T2
+  __syncthreads();
+  const int e1 = b0 + kept;
+  // Bs(:e1, b0:b1): rows < b0 = -P2 T2, rows b0.. = T2; columns beyond kept are zero
+  for (int idx = tid; idx < e1 * w; idx += nt) {
+    const int r = idx % e1, j = idx / e1;
+    double v = 0.0;
+    if (j < kept) {
+      if (r < b0) {
+        for (int l = 0; l <= j; ++l) v -= st->G2[r + (b0 + l) * kLd] * sM[l + j * kLd];
+      } else if (r - b0 <= j) {
+        v = sM[(r - b0) + j * kLd];
+      }
+    }
+    st->Bs[r + (b0 + j) * kLd] = v;
+  }
+  __syncthreads();
+  // M (e1 x e1) into sM; X = M H(:e1, :c) into sG; H(:e1, :c) = X M(:c, :c)^{-1}
+  const int c = e1 - 1;
+  for (int idx = tid; idx < e1 * e1; idx += nt) {
+    const int r = idx % e1, j = idx / e1;
+    double v = (r == j) ? 1.0 : 0.0;
+    if (j >= b0) {
+      if (r < b0) v = st->G2[r + j * kLd];                       // P2
+      else v = (r <= j) ? sR[(r - b0) + (j - b0) * kLd] : 0.0;   // R2
+    }
+    sM[r + j * kLd] = v;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < e1 * c; idx += nt) {
+    const int r = idx % e1, j = idx / e1;
+    double v = 0.0;
+    for (int l = r; l <= min(e1 - 1, j + 1); ++l) v += sM[r + l * kLd] * st->Hh[l + j * kLd];
+    sG[r + j * kLd] = v;
+  }
+  __syncthreads();
+  // right solve by the upper-triangular M(:c, :c), one row per thread
+  for (int r = tid; r < e1; r += nt) {
+    for (int j = 0; j < c; ++j) {
+      double v = sG[r + j * kLd];
+      for (int l = 0; l < j; ++l) v -= sR[r + l * kLd] * sM[l + j * kLd];
+      sR[r + j * kLd] = v / sM[j + j * kLd];
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < e1 * c; idx += nt) {
+    const int r = idx % e1, j = idx / e1;
+    st->Hh[r + j * kLd] = (r <= j + 1) ? sR[r + j * kLd] : 0.0;
+  }
+  if (tid == 0 && b0 == 0) st->gscale = st->beta * sM[0];
+  __syncthreads();
+  // least squares over the final columns 0..c-1, refactored from scratch
+  for (int i = tid; i <= kLd; i += nt) st->gg[i] = (i == 0) ? st->gscale : 0.0;
+  __syncthreads();
+  givens_append(st, st->Hh, 0, c);
+  if (tid == 0) {
+    if (kept < w) {
+      st->h.stop_panel = a.panel;
+      st->h.k_used = c;
+      st->h.truncated += 1;
+    } else if (c < st->m && fabs(st->gg[c]) <= st->tol * st->bnorm) {
+      st->h.stop_panel = a.panel;
+      st->h.k_used = c;
+    }
+  }
+  __syncthreads();
 }
 
 // ------------------------------------------------------------------ stand-alone ortho

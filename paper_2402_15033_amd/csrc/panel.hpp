@@ -23,6 +23,7 @@ enum PanelFlags : int {
   PF_STORE = 4,
   PF_GRAM_Q = 8,
   PF_GRAM_W = 16,
+  PF_BMAT = 32,  // fused kernel: q = Y(:, staged) Bs(staged, wcol:wcol+sw) (big-panel stage 2)
 };
 
 enum TailOp : int {

@@ -45,6 +45,9 @@ struct SmallState {
   double Ra[kMaxS * kMaxS];   // accumulated CholQR factor (BCGS2 + CholQR2)
   double P2[kLd * kMaxS];     // second-pass projection coefficients
   double refW[kMaxS];         // raw Gram diagonal of the panel whose PIP pass failed
+  // two-stage with big panels (s_hat < m)
+  double gscale;              // least-squares rhs: beta M(0,0) once the first big panel is final
+  double Bs[kLd * kLd];       // q(:, big panel) = Y(:, :b1) Bs(:b1, big panel): [-P2 T2; T2]
   // Givens state of the one-stage variants and of standard GMRES
   double gc[kLd], gs[kLd], gg[kLd + 1];
   double Rg[kLd * kLd];       // Givens-triangularized Hessenberg

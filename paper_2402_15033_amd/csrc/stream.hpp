@@ -288,7 +288,7 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
   const bool hasT = (flags & PF_HAS_T) && !st->identity_t;
   const bool store = flags & PF_STORE;
   const bool gramQ = flags & PF_GRAM_Q;
-  const int kq = (hasP || gramQ) ? k : 0;  // staged Q columns
+  const int kq = (hasP || gramQ || (flags & PF_BMAT)) ? k : 0;  // staged Q columns
   const int ncol = kq + sw;                // staged columns: Q then W
   const int a0 = gramQ ? 0 : kq;           // first staged column on the A side of the Gram
   const int ncolA = ncol - a0;
@@ -296,12 +296,16 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
   const int64_t ld = a.ld;
   __shared__ T lt[2][mfma_tile<T>()];
   __shared__ T lB[(kMaxCols + 4) * 16];  // B(c, j) at c * 16 + j, zero-padded to 16 columns
-  // B = [-P T; T]: rows c < kq from the projection, rows kq + i from T (identity if no T)
+  // B = [-P T; T]: rows c < kq from the projection, rows kq + i from T (identity if no T);
+  // PF_BMAT: B given in st->Bs, staged column c being basis column c (kq = wcol)
+  const bool bmat = flags & PF_BMAT;
   for (int idx = tid; idx < (kMaxCols + 4) * 16; idx += blockDim.x) {
     const int c = idx / 16, j = idx % 16;
     double v = 0.0;
     if (j < sw && c < ncol) {
-      if (c < kq) {
+      if (bmat) {
+        v = st->Bs[c + (a.wcol + j) * kLd];
+      } else if (c < kq) {
         if (hasP) {
           if (hasT) {
             for (int l = 0; l <= j; ++l) v -= st->Pcur[c + l * kLd] * st->Tcur[l + j * kMaxS];
@@ -316,6 +320,7 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
     }
     lB[idx] = (T)v;
   }
+  const bool gram = flags & (PF_GRAM_Q | PF_GRAM_W);
   TL tl;
   tl.init(wv, ncol, kq, a.wcol, ld);
   const int BR = tl.BR, LDT = tl.LDT;
@@ -352,7 +357,7 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
     }
     __syncthreads();
     // ---- Gram of the tile on the matrix cores; q back to HBM in whole row segments
-    for (int ks = wv; ks < BR / 4; ks += NW) {
+    for (int ks = wv; gram && ks < BR / 4; ks += NW) {
       const int row = ks * 4 + lk;
       const T bv = (li < sw) ? L[(kq + li) * LDT + row] : (T)0;
 #pragma unroll
@@ -383,6 +388,7 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
       }
     buf ^= 1;
   }
+  if (!gram) return;
   __syncthreads();
   T* red = &lt[0][0];
 #pragma unroll

@@ -211,7 +211,7 @@ static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks, "reduction partial buffer too 
 // Device bytes reserved for the launch image of one request's program.
 constexpr size_t kProgramBytesPerRequest = 512 * 1024;
 
-enum Family : int { F_RESID, F_RTAIL, F_UPDATE, F_MPK, F_GRAM, F_PREDUCE, F_PTAIL, F_FUSED, F_CYCLE_END, F_XUPD };
+enum Family : int { F_RESID, F_RTAIL, F_UPDATE, F_MPK, F_GRAM, F_PREDUCE, F_PTAIL, F_FUSED, F_CYCLE_END, F_XUPD, F_S2 };
 
 struct Phase {
   Family f;
@@ -280,6 +280,7 @@ void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
     case F_PREDUCE: launch_b<PReduceBody>(ph, d, nreq, s); break;
     case F_PTAIL: launch_b<PTailBody>(ph, d, nreq, s); break;
     case F_CYCLE_END: launch_b<CycleEndBody>(ph, d, nreq, s); break;
+    case F_S2: launch_b<Stage2Body>(ph, d, nreq, s); break;
     case F_XUPD: launch_b<XupdBody<T>>(ph, d, nreq, s); break;
     case F_UPDATE:
       switch (ph.t1) {
@@ -363,6 +364,33 @@ struct Step {
   int kclass = -1;
 };
 
+// A reduction over the k + sw columns against the nprev previous-panel columns and W.
+Step gram_step(int k, int wcol, int sw, int nprev, int tail, int panel, int kkeep, int gate = 1) {
+  Step st{};
+  st.kind = PK_GRAM;
+  st.nprev = nprev;
+  st.k = k;
+  st.wcol = wcol;
+  st.sw = sw;
+  st.tail = tail;
+  st.panel = panel;
+  st.kkeep = kkeep;
+  st.gate = gate;
+  return st;
+}
+Step upd_step(PanelKind kind, int k, int wcol, int sw, int flags, int tail, int panel, int kkeep) {
+  Step st{};
+  st.kind = kind;
+  st.k = k;
+  st.wcol = wcol;
+  st.sw = sw;
+  st.flags = flags;
+  st.tail = tail;
+  st.panel = panel;
+  st.kkeep = kkeep;
+  return st;
+}
+
 // Builds the phases of a batch of requests that share the basis type and every step
 // parameter; each request keeps its own sizes, buffers and block decomposition.
 struct Builder {
@@ -417,14 +445,14 @@ struct Builder {
         cols = ((st.flags & PF_HAS_P) ? st.k : 0) + 2.0 * st.sw;
       } else {
         const int rpl = P.f32 ? tile_rows_per_lane<float>() : tile_rows_per_lane<double>();
-        const int staged = gram ? st.k + st.sw : (loadQ ? st.k : 0) + st.sw;
+        const int staged = (gram || (st.flags & PF_BMAT)) ? st.k + st.sw : (loadQ ? st.k : 0) + st.sw;
         const int br = kWave * rpl * (kTileItems / staged);  // the MFMA kernels' batch height
         int64_t tiles = cdiv(q.n, br);
         int b0 = (int)std::min<int64_t>(tiles, kMaxMfmaBlocks);
         x.rows_per_block = cdiv(cdiv(q.n, b0), br) * br;
         nb[r] = (int)cdiv(q.n, x.rows_per_block);
         cols = gram ? st.k + st.sw : staged + ((st.flags & PF_STORE) ? st.sw : 0);
-        reduces = true;
+        reduces = gram || (st.flags & (PF_GRAM_Q | PF_GRAM_W)) != 0;
         if ((size_t)nb[r] * (size_t)((st.k + st.sw) * nz) > q.c.part1_n)
           return fail(TSG_ERR_WORKSPACE, "internal: reduction partials (%d blocks x %d) exceed the buffer", nb[r],
                       (st.k + st.sw) * nz);
@@ -440,7 +468,7 @@ struct Builder {
       P.add(F_GRAM, (st.k + st.sw + 15) / 16, nz <= 16 ? 1 : 2, a, nb, kc, fb ? 0.0 : bytes);
     } else {
       const int ncolA = (st.flags & PF_GRAM_Q) ? st.k + st.sw : st.sw;
-      P.add(F_FUSED, (ncolA + 15) / 16, 0, a, nb, kc, fb ? 0.0 : bytes);
+      P.add(F_FUSED, std::max(1, (ncolA + 15) / 16), 0, a, nb, kc, fb ? 0.0 : bytes);
     }
     if (!reduces) return TSG_OK;
     // first level for requests with many blocks, then the tail
@@ -501,6 +529,23 @@ struct Builder {
       P.add(F_MPK, fmt, 0, a, nb, TSG_KC_MPK, bytes);
     }
   }
+  // stage 2 of big panel [b0, b1) (s_hat < m), then Y(:, b0:b1) <- Y(:, :b1) Bs in
+  // 16-column chunks from the last to the first (a chunk reads only columns before its
+  // end, none of which a later-launched chunk has overwritten)
+  tsg_status big_stage2(int b0, int b1, int panel) {
+    std::vector<S2Args> t;
+    std::vector<int> one(R.size(), 1);
+    for (ReqCtx* q : R) t.push_back(S2Args{q->c.st, b0, b1, panel, 0});
+    P.add(F_S2, 0, 0, t, one, TSG_KC_STAGE2, 0.0);
+    const int nchunks = (b1 - b0 + 15) / 16;
+    for (int ch = nchunks - 1; ch >= 0; --ch) {
+      const int o0 = b0 + 16 * ch, sw = std::min(16, b1 - o0);
+      Step ap = upd_step(PK_FUSED, o0, o0, sw, PF_BMAT | PF_STORE, TAIL_NONE, panel, 0);
+      ap.kclass = TSG_KC_STAGE2;
+      TRY(step(ap));
+    }
+    return TSG_OK;
+  }
   void cycle_end(int two) {
     std::vector<TailArgs> t;
     std::vector<int> one(R.size(), 1);
@@ -519,33 +564,6 @@ struct Builder {
     P.add(F_XUPD, 0, 0, a, nb, TSG_KC_XUPDATE, bytes);
   }
 };
-
-// A reduction over the k + sw columns against the nprev previous-panel columns and W.
-Step gram_step(int k, int wcol, int sw, int nprev, int tail, int panel, int kkeep, int gate = 1) {
-  Step st{};
-  st.kind = PK_GRAM;
-  st.nprev = nprev;
-  st.k = k;
-  st.wcol = wcol;
-  st.sw = sw;
-  st.tail = tail;
-  st.panel = panel;
-  st.kkeep = kkeep;
-  st.gate = gate;
-  return st;
-}
-Step upd_step(PanelKind kind, int k, int wcol, int sw, int flags, int tail, int panel, int kkeep) {
-  Step st{};
-  st.kind = kind;
-  st.k = k;
-  st.wcol = wcol;
-  st.sw = sw;
-  st.flags = flags;
-  st.tail = tail;
-  st.panel = panel;
-  st.kkeep = kkeep;
-  return st;
-}
 
 // The kernel sequence of one panel (columns wcol .. wcol+sw-1 against the k before them).
 //   two_stage: stage-1 BCGS-PIP; the reduction also covers the previous panel's stage-2
@@ -596,10 +614,44 @@ tsg_status panel_sequence(Builder& B, int ortho, int k, int sw, int nprev, bool 
   return TSG_OK;
 }
 
+// The phases of a two-stage restart cycle with big panels of s_hat < m columns (the first
+// holds column 0 too): stage 1 per panel as with s_hat = m -- each reduction also carries
+// the previous panel's stage-2 Gram block column when that panel is in the same big
+// panel, and a panel that ends a big panel forms its own block column in its (fused)
+// update -- then at the end of each big panel its stage 2 (tail + explicit Q).  A stage-1
+// breakdown keeps the final columns of the completed big panels.
+tsg_status build_cycle_big_panels(Builder& B, int m, int sstep, int s_hat) {
+  const int J = m / sstep;
+  B.resid();
+  {
+    Step sc = upd_step(PK_UPDATE, 0, 0, 1, PF_HAS_T | PF_STORE, TAIL_NONE, -1, 0);
+    sc.kclass = TSG_KC_SCALE;
+    TRY(B.step(sc));
+  }
+  int b0 = 0, b1 = 1 + s_hat;
+  for (int j = 0; j < J; ++j) {
+    const int k = j * sstep + 1;
+    for (int i = 0; i < sstep; ++i) B.mpk(k - 1 + i, k + i, i, j);
+    const bool first_in_big = (k == b0) || (b0 == 0 && k == 1);
+    const int nprev = j == 0 ? 1 : (first_in_big ? 0 : sstep);
+    const bool ends_big = k + sstep == b1;
+    TRY(panel_sequence(B, TSG_ORTHO_TWO_STAGE, k, sstep, nprev, ends_big, j, b0 > 0 ? b0 - 1 : 0));
+    if (ends_big) {
+      TRY(B.big_stage2(b0, b1, j));
+      b0 = b1;
+      b1 = b0 + s_hat;
+    }
+  }
+  B.cycle_end(0);  // least squares from the Givens factorization of the final H
+  B.xupdate(m);
+  return TSG_OK;
+}
+
 // The phases of one restart cycle of s-step GMRES(m) with the given orthogonalization.
-tsg_status build_cycle(Builder& B, int m, int sstep, int ortho) {
+tsg_status build_cycle(Builder& B, int m, int sstep, int ortho, int s_hat) {
   const bool two = ortho == TSG_ORTHO_TWO_STAGE;
   const int J = m / sstep;
+  if (two && s_hat > 0 && s_hat < m) return build_cycle_big_panels(B, m, sstep, s_hat);
   B.resid();
   // qhat_1 = r / beta; two-stage: its G2(0,0) comes with the first panel's reduction when
   // column 0 and the panel fit one lean reduction, else from this pass
@@ -790,8 +842,12 @@ static tsg_status validate_params(int64_t n, const tsg_solve_params* p) {
     if (p->s < 1 || p->s > kMaxS) return fail(TSG_ERR_INVALID_ARG, "s=%d outside [1, 16]", p->s);
     if (p->m % p->s != 0) return fail(TSG_ERR_INVALID_ARG, "s=%d does not divide m=%d", p->s, p->m);
   }
-  if (p->s_hat != 0 && p->s_hat != p->m)
-    return fail(TSG_ERR_UNSUPPORTED, "s_hat=%d: only s_hat = m is built", p->s_hat);
+  if (p->s_hat != 0 && p->s_hat != p->m) {
+    if (p->ortho != TSG_ORTHO_TWO_STAGE)
+      return fail(TSG_ERR_INVALID_ARG, "s_hat=%d is a two-stage parameter", p->s_hat);
+    if (p->s_hat < p->s || p->s_hat > p->m || p->s_hat % p->s != 0 || p->m % p->s_hat != 0)
+      return fail(TSG_ERR_INVALID_ARG, "need s | s_hat | m (s=%d, s_hat=%d, m=%d)", p->s, p->s_hat, p->m);
+  }
   if (p->basis < 0 || p->basis > 2) return fail(TSG_ERR_INVALID_ARG, "bad basis %d", p->basis);
   if (p->basis == TSG_BASIS_NEWTON && !p->newton_shifts)
     return fail(TSG_ERR_INVALID_ARG, "newton basis needs newton_shifts");
@@ -956,7 +1012,7 @@ tsg_status run_solve(tsg_csr A, const tsg_solve_params* p, ReqCtx& q, char* dpro
   P.f32 = f32;
   P.nreq = 1;
   Builder B{P, {&q}, 0};
-  TRY(build_cycle(B, m, sstep, ortho));
+  TRY(build_cycle(B, m, sstep, ortho, p->s_hat));
   if (P.blob.size() > kProgramBytesPerRequest) return fail(TSG_ERR_UNSUPPORTED, "internal: launch image too large");
   HIP_TRY(hipMemcpyAsync(dprog, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, s));
 
@@ -1391,7 +1447,7 @@ tsg_status tsg_server_step(tsg_server S, int32_t* n_active, int32_t* n_queued) {
       S->prog.nreq = (int)S->active.size();
       Builder B{S->prog, {}, 0};
       for (auto* r : S->active) B.R.push_back(&r->q);
-      TRY(build_cycle(B, S->p.m, step_size(&S->p), S->p.ortho));
+      TRY(build_cycle(B, S->p.m, step_size(&S->p), S->p.ortho, S->p.s_hat));
       std::vector<SmallState*> sts;
       for (auto* r : S->active) sts.push_back(r->q.c.st);
       S->sts_off = S->prog.put(sts.data(), sizeof(SmallState*) * sts.size());

@@ -165,6 +165,33 @@ def test_solve_shifted_basis_s10(tsg):
     assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
 
 
+@pytest.mark.parametrize("s_hat", [5, 10, 20, 30])
+def test_solve_big_panels_match_oracle(tsg, s_hat):
+    """Two-stage with big panels s_hat < m: stage 2 of every completed big panel against the
+    final columns, residual checked at each big-panel end (Table 2's check points)."""
+    _say("case solve big panels", s_hat)
+    pr = W.make_problem("laplace2d", 64, seed=0)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=60, s=5, tol=1e-10, s_hat=s_hat)
+    ref = G.sstep_gmres(pr["A"], pr["b"], m=60, s=5, tol=1e-10, s_hat=s_hat)
+    xg = x.cpu().numpy()
+    _say(f"  iters gpu {info.iters} oracle {ref['iters']}")
+    assert info.converged and info.iters == ref["iters"] and info.cycles == ref["cycles"]
+    assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
+    relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], xg)) / np.linalg.norm(pr["b"])
+    assert relres <= 1e-10
+
+
+def test_solve_big_panels_convdiff_s10(tsg):
+    _say("case solve big panels convdiff")
+    pr = W.make_problem("convdiff2d", 93, seed=2)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=60, s=10, tol=1e-10, s_hat=20, basis="shifted")
+    ref = G.sstep_gmres(pr["A"], pr["b"], m=60, s=10, tol=1e-10, s_hat=20, basis="shifted")
+    assert info.converged and info.iters == ref["iters"]
+    assert np.linalg.norm(x.cpu().numpy() - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
+
+
 def test_solve_monomial_s10_explicit_second_pass(tsg):
     """Panels beyond PIP's stability limit take the explicit second pass on both sides.
     Which panels take it is decided by pivots that sit within rounding of the threshold
