@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--N", type=int, default=None,
                     help="grid side (default 2048 in 2D, 160 in 3D)")
     ap.add_argument("--basis", default="monomial", choices=["monomial", "shifted"])
+    ap.add_argument("--s-hat", type=int, default=0, help="two-stage big-panel size (0 = m)")
+    ap.add_argument("--shat-sweep", action="store_true",
+                    help="also time one solve for each s_hat in {s, 2s, 4s, 6s, m} (Table 2's knob)")
     ap.add_argument("--s", type=int, default=5)
     ap.add_argument("--m", type=int, default=60)
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -140,9 +143,9 @@ def main():
     b = torch.as_tensor(pr["b"], device=dev)
     x = torch.zeros_like(b)
     kw = dict(m=args.m, s=args.s, tol=args.tol, ortho=args.ortho, precision=args.precision,
-              basis=args.basis, graph=not args.eager)
+              basis=args.basis, graph=not args.eager, s_hat=args.s_hat)
     need = tsg.binding.solve_workspace_bytes(A, m=args.m, s=args.s, ortho=args.ortho,
-                                             precision=args.precision)
+                                             precision=args.precision, s_hat=args.s_hat)
     ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
     off = (-ws.data_ptr()) % 256
     ws = ws[off:]
@@ -226,11 +229,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{desc} (n={Ah.n}, nnz={Ah.nnz}) CSR, "
                                f"x_true~U(-1,1) seed 0, x0=0; s-step GMRES m={args.m} s={args.s} "
-                               f"{args.ortho} (s_hat=m), {args.basis} basis, tol={args.tol:g}, "
+                               f"{args.ortho} (s_hat={args.s_hat or args.m}), {args.basis} basis, tol={args.tol:g}, "
                                f"{args.precision}",
                    "problem": args.problem, "N": N,
                    "n": Ah.n, "nnz": Ah.nnz, "m": args.m, "s": args.s, "ortho": args.ortho,
-                   "basis": args.basis, "precision": args.precision, "tol": args.tol},
+                   "basis": args.basis, "precision": args.precision, "tol": args.tol,
+                   "s_hat": args.s_hat or args.m},
         "time_to_solution_s": round(elapsed / args.steps, 4),
         "iters": int(info.iters), "cycles": int(info.cycles),
         "relres_device": info.relres, "relres_host_check": relres_host,
@@ -257,6 +261,21 @@ def main():
                 modes[key] = round(time.perf_counter() - t, 4)
                 log(f"[bench] mode {key}: {modes[key]} s")
         out["launch_modes_s"] = modes
+
+    if args.shat_sweep and args.ortho == "two_stage":
+        sweep = {}
+        for sh in sorted({args.s, 2 * args.s, 4 * args.s, 6 * args.s, args.m}):
+            if sh > args.m or args.m % sh:
+                continue
+            x.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, si = tsg.solve(A, b, x, workspace=None, **dict(kw, s_hat=sh))
+            torch.cuda.synchronize()
+            sweep[sh] = {"time_to_solution_s": round(time.perf_counter() - t, 4), "iters": int(si.iters),
+                         "cycles": int(si.cycles), "relres": si.relres}
+            log(f"[bench] s_hat {sh}: {sweep[sh]}")
+        out["s_hat_sweep"] = sweep
 
     if args.compare:
         cmp = {}
