@@ -188,8 +188,12 @@ def main():
     st_ = lambda w: w if w <= 6 else (8 if w <= 8 else (10 if w <= 10 else (12 if w <= 12 else 16)))
     s_ = args.s
     nt2 = 1 if 2 * args.s <= 16 else 2
+    # the packed operator stores column - row in 16 bits when every delta of the matrix fits
+    rows = np.repeat(np.arange(Ah.n, dtype=np.int64), np.diff(Ah.row_ptr))
+    delta = Ah.col.astype(np.int64) - rows
+    fmt = 1 if Ah.nnz == 0 or (delta.min() >= -32768 and delta.max() <= 32767) else 2  # 16- or 32-bit
     names = {  # every per-request kernel runs as batched_kernel<Body>
-        "mpk": f"MpkBody<{elem}, {elem}>",
+        "mpk": f"MpkBody<{elem}, {elem}, {fmt}>",
         "gram": f"GramBody<{elem}, 1..4, {nt2}>",
         "gram_first": f"GramBody<{elem}, {(args.s + 16) // 16}, {(args.s + 16) // 16}>",
         "update": f"UpdateBody<{elem}, {st_(s_)}>",
