@@ -8,7 +8,9 @@
 * ``sstep_gmres``              -- s-step GMRES(m) (Sec. III, Fig. 1): each panel is
   s SpMVs of the matrix-powers kernel followed by a block orthogonalization;
   ortho = 'two_stage' (Sec. V, Fig. 5 with s_hat = m), 'bcgs_pip2' (Fig. 4b) or
-  'bcgs2_cholqr2' (Fig. 2b).
+  'bcgs2_cholqr2' (Fig. 2b).  basis = 'monomial', 'shifted', 'newton' (given real
+  shifts) or 'leja' (Newton basis from the Leja-ordered Ritz values of the first
+  cycle, ``oracle.ritz``).
 
 One restart cycle of every variant computes, in exact arithmetic, the same
 iterate: x + argmin_{z in K_k(A, r)} ||b - A(x + z)||, with k the number of
@@ -22,8 +24,10 @@ iteration count is the number of Krylov vectors generated.
 
 s-step Hessenberg recovery (the small-matrix algebra implied by Fig. 1 and
 Sec. VI; the paper's listing is not reproduced): with the basis
-w_i = (A w_{i-1} - theta_i w_{i-1}) / sigma_i, w_0 = qhat_k,
+w_i = (A w_{i-1} - theta_i w_{i-1} + tau_i w_{i-2}) / sigma_i, w_0 = qhat_k
+(tau_i != 0 only in the Newton basis, at the second step of a complex pair),
   A [w_0 .. w_{s-1}] = [w_0 .. w_s] B,   B(i,i) = theta_i, B(i+1,i) = sigma_i,
+  B(i-1,i) = -tau_i,
 and the panel factorization W = Qhat_{1:k} P + Qhat_{k+1:k+s} R gives
 [w_0, W] = Qhat_{1:k+s} S with S(:,1) = e_k, S(:,2:s+1) = [P; R].  Splitting the
 first k-1 rows off S(1:k+s-1,1:s) and using A Qhat_{1:k-1} = Qhat_{1:k} Hhat
@@ -47,8 +51,8 @@ import numpy as np
 
 from .dense import (PIVOT_TOL, CholeskyBreakdown, GivensState, chol_upper, givens_lsq,
                     right_solve_upper, solve_upper)
-from .sparse import Operator, basis_params, spmv
-from . import blockortho
+from .sparse import Operator, basis_params, gershgorin, spmv
+from . import blockortho, ritz
 
 
 def _outer(A, b, x0, tol, max_iters, cycle_fn, record):
@@ -131,18 +135,53 @@ def gmres(A, b, x0=None, m: int = 60, tol: float = 1e-10, max_iters: int = 10**9
     return _outer(A, b, x0, tol, max_iters, cycle, record)
 
 
-def mpk(op, w0: np.ndarray, theta: np.ndarray, sigma: np.ndarray):
-    """Matrix-powers kernel: s SpMVs in sequence (Sec. III).  Returns (W, B)."""
+def mpk(op, w0: np.ndarray, theta: np.ndarray, sigma: np.ndarray, tau=None):
+    """Matrix-powers kernel: s SpMVs in sequence (Sec. III).  Returns (W, B).
+
+    Step i: w_{i+1} = (A w_i - theta_i w_i + tau_i w_{i-1}) / sigma_i (tau = 0 except at
+    the second step of a complex pair of the Newton basis), so
+    A w_i = sigma_i w_{i+1} + theta_i w_i - tau_i w_{i-1}: B(i+1,i) = sigma_i,
+    B(i,i) = theta_i, B(i-1,i) = -tau_i.
+    """
     s = len(theta)
+    tau = np.zeros(s) if tau is None else np.asarray(tau, dtype=np.float64)
     W = np.zeros((op.n, s), order="F")
     B = np.zeros((s + 1, s))
-    w = w0
+    prev, w = None, w0
     for i in range(s):
-        w = (spmv(op, w) - theta[i] * w) / sigma[i]
+        nxt = spmv(op, w) - theta[i] * w
+        if tau[i] != 0.0:
+            nxt = nxt + tau[i] * prev
+            B[i - 1, i] = -tau[i]
+        prev, w = w, nxt / sigma[i]
         W[:, i] = w
         B[i, i] = theta[i]
         B[i + 1, i] = sigma[i]
     return W, B
+
+
+class _Basis:
+    """The s-step basis parameters of a solve.  basis = 'leja': the first cycle that keeps
+    at least s columns runs with the shifted basis; its Ritz values then give the Newton
+    basis of every later cycle (``ritz.leja_ritz_params``)."""
+
+    def __init__(self, op, s, basis, shifts):
+        self.s = s
+        self.lo, self.hi = gershgorin(op)
+        self.theta, self.sigma = basis_params(op, s, "shifted" if basis == "leja" else basis, shifts)
+        self.tau = np.zeros(s)
+        self.pending = basis == "leja"
+        self.switched_after = None
+
+    def cycle_done(self, H_square: np.ndarray, cycle_index: int):
+        if self.pending and H_square.shape[0] >= self.s:
+            self.theta, self.tau, self.sigma = ritz.leja_ritz_params(H_square, self.s, self.lo, self.hi)
+            self.pending = False
+            self.switched_after = cycle_index
+
+    def export(self, out):
+        out["theta"], out["sigma"], out["tau"] = self.theta, self.sigma, self.tau
+        out["basis_switched_after"] = self.switched_after
 
 
 def hessenberg_block(Hh: np.ndarray, P: np.ndarray, R: np.ndarray, B: np.ndarray, k: int):
@@ -176,10 +215,10 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
             raise ValueError("need s | s_hat | m")
         return _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record)
     op = A if isinstance(A, Operator) else Operator(A)
-    theta, sigma = basis_params(op, s, basis, shifts)
+    bp = _Basis(op, s, basis, shifts)
     J = m // s
     one_stage = None if ortho == "two_stage" else blockortho.ONE_STAGE[ortho]
-    stats = {"fallbacks": 0}  # stage-1 panels that needed the explicit second pass
+    stats = {"fallbacks": 0, "cycles": 0}  # fallbacks: panels that took the explicit second pass
 
     def cycle(op, r, beta, tol_abs):
         n = op.n
@@ -192,7 +231,7 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
         breakdown = None
         for j in range(J):
             k = j * s + 1
-            W, B = mpk(op, Qh[:, k - 1], theta, sigma)
+            W, B = mpk(op, Qh[:, k - 1], bp.theta, bp.sigma, bp.tau)
             try:
                 if one_stage is None:  # stage 1 (second pass only where PIP fails)
                     Qn, P, R, fb = blockortho.bcgs_pip_explicit(Qh[:, :k], W, PIVOT_TOL)
@@ -231,6 +270,8 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
                     return np.zeros(n), 0, beta, {"breakdown": breakdown} if record else None
                 R2 = chol_upper(G2[:kb, :kb], tol=PIVOT_TOL)
             H = right_solve_upper(R2 @ Hh[:kb, :k_used], R2[:k_used, :k_used])
+            stats["cycles"] += 1
+            bp.cycle_done(H[:k_used, :k_used], stats["cycles"])
             y, est = givens_lsq(H, beta * R2[0, 0])
             z = solve_upper(R2[:k_used, :k_used], y)
             dx = Qh[:, :k_used] @ z
@@ -239,13 +280,15 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
                        "z": z, "panels": panels, "beta": beta, "breakdown": breakdown}
             return dx, k_used, est, rec
         y = giv.solve(k_used)
+        stats["cycles"] += 1
+        bp.cycle_done(Hh[:k_used, :k_used], stats["cycles"])
         if record:
             rec = {"Q": Qh[:, : k_used + 1], "H": Hh[: k_used + 1, :k_used], "y": y,
                    "panels": panels, "beta": beta, "breakdown": breakdown}
         return Qh[:, :k_used] @ y, k_used, abs(giv.g[k_used]), rec
 
     out = _outer(op, b, x0, tol, max_iters, cycle, record)
-    out["theta"], out["sigma"] = theta, sigma
+    bp.export(out)
     out["fallbacks"] = stats["fallbacks"]
     return out
 
@@ -269,10 +312,10 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
     cycle with the columns of its completed big panels.
     """
     op = A if isinstance(A, Operator) else Operator(A)
-    theta, sigma = basis_params(op, s, basis, shifts)
+    bp = _Basis(op, s, basis, shifts)
     J = m // s
     bigs = blockortho.big_panel_bounds(m + 1, s, s_hat)
-    stats = {"fallbacks": 0}
+    stats = {"fallbacks": 0, "cycles": 0}
 
     def stage2(Y, H, done, b1, c_h):
         """Stage 2 on columns [done, b1); transforms H(:b1, :c_h).  Returns (kept, M00)."""
@@ -312,7 +355,7 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
         est = beta
         for j in range(J):
             k = j * s + 1
-            W, B = mpk(op, Y[:, k - 1], theta, sigma)
+            W, B = mpk(op, Y[:, k - 1], bp.theta, bp.sigma, bp.tau)
             try:
                 Qn, P, R, fb = blockortho.bcgs_pip_explicit(Y[:, :k], W, PIVOT_TOL)
                 stats["fallbacks"] += int(fb)
@@ -344,6 +387,8 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
         if k_used <= 0:
             return np.zeros(n), 0, beta, {"breakdown": breakdown} if record else None
         y, est = givens_lsq(H[: k_used + 1, :k_used], g0)
+        stats["cycles"] += 1
+        bp.cycle_done(H[:k_used, :k_used], stats["cycles"])
         dx = Y[:, :k_used] @ y
         rec = None
         if record:
@@ -352,7 +397,7 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
         return dx, k_used, est, rec
 
     out = _outer(op, b, x0, tol, max_iters, cycle, record)
-    out["theta"], out["sigma"] = theta, sigma
+    bp.export(out)
     out["fallbacks"] = stats["fallbacks"]
     return out
 
