@@ -79,7 +79,7 @@ def bcgs_pip(Q: np.ndarray, V: np.ndarray, tol: float = 0.0):
     return Qnew, P, R
 
 
-def bcgs_pip_explicit(Q: np.ndarray, V: np.ndarray, tol: float = 0.0):
+def bcgs_pip_explicit(Q: np.ndarray, V: np.ndarray, tol: float = 0.0, shifted: bool = False):
     """BCGS-PIP, with an explicit-Gram second pass where the Pythagorean Gram fails.
 
     The Pythagorean Gram G_V - P^T P loses all accuracy once [Q, V] is too ill-conditioned
@@ -90,11 +90,20 @@ def bcgs_pip_explicit(Q: np.ndarray, V: np.ndarray, tol: float = 0.0):
     so V = Q (P1 + P2) + Qnew R.  A pivot of the second pass fails when it is at most
     tol * (Y^T Y)_jj (Y itself too ill-conditioned) or at most tol^2 * (V^T V)_jj (the
     column is numerically in span(Q): the pivot is at the rounding level of V).
-    Returns (Qnew, P, R, used_second_pass).
+
+    shifted = True: where the second pass fails, shifted Cholesky QR (Fukaya et al. 2020,
+    the remedy the paper cites for CholQR's instability) takes over: with the second
+    pass's Gram G, Rs = Chol(G + mu I), mu = 10 tol trace(G) (a shift well above the Gram's
+    rounding level), Z = (Y - Q P2) Rs^{-1} is well conditioned, and one more BCGS-PIP pass
+    orthogonalizes it: P3 = Q^T Z, R3 = Chol(Z^T Z - P3^T P3) (pivot test tol * (Z^T Z)_jj),
+    Qnew = (Z - Q P3) R3^{-1}; V = Q (P1 + P2 + P3 Rs) + Qnew (R3 Rs).  A column whose final
+    pivot (R3 Rs)_jj^2 is at most tol^2 * (V^T V)_jj is numerically in span(Q) and still
+    breaks down.
+    Returns (Qnew, P, R, passes): passes = 0 (PIP), 1 (second pass), 2 (shifted pass too).
     """
     try:
         Qn, P, R = bcgs_pip(Q, V, tol)
-        return Qn, P, R, False
+        return Qn, P, R, 0
     except CholeskyBreakdown:
         pass
     P1 = Q.T @ V
@@ -102,10 +111,30 @@ def bcgs_pip_explicit(Q: np.ndarray, V: np.ndarray, tol: float = 0.0):
     P2 = Q.T @ Y
     GY = Y.T @ Y
     G = GY - P2.T @ P2
-    thr = np.maximum(tol * np.diag(GY), tol * tol * np.diag(V.T @ V))
-    R = chol_upper(G, ref_diag=thr, tol=1.0 if tol > 0.0 else 0.0)
-    Qnew = right_solve_upper(Y - Q @ P2, R)
-    return Qnew, P1 + P2, R, True
+    refV = np.diag(V.T @ V)
+    thr = np.maximum(tol * np.diag(GY), tol * tol * refV)
+    try:
+        R = chol_upper(G, ref_diag=thr, tol=1.0 if tol > 0.0 else 0.0)
+        Qnew = right_solve_upper(Y - Q @ P2, R)
+        return Qnew, P1 + P2, R, 1
+    except CholeskyBreakdown:
+        if not shifted or tol <= 0.0:
+            raise
+    s = V.shape[1]
+    mu = 10.0 * tol * float(np.trace(G))
+    Rs = chol_upper(G + mu * np.eye(s))
+    Z = right_solve_upper(Y - Q @ P2, Rs)
+    P3 = Q.T @ Z
+    GZ = Z.T @ Z
+    R3 = chol_upper(GZ - P3.T @ P3, ref_diag=np.diag(GZ), tol=tol)
+    R = R3 @ Rs
+    bad = np.nonzero(np.diag(R) ** 2 <= tol * tol * refV)[0]
+    if bad.size:
+        err = CholeskyBreakdown("column numerically in span(Q)")
+        err.index = int(bad[0])
+        raise err
+    Qnew = right_solve_upper(Z - Q @ P3, R3)
+    return Qnew, P1 + P2 + P3 @ Rs, R, 2
 
 
 def bcgs_pip2(Q: np.ndarray, V: np.ndarray, tol: float = 0.0):

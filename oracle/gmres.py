@@ -55,6 +55,13 @@ from .sparse import Operator, basis_params, gershgorin, spmv
 from . import blockortho, ritz
 
 
+# Two-stage stage 1 takes the shifted Cholesky QR pass (``blockortho.bcgs_pip_explicit``)
+# where its explicit second pass fails, by default for s >= SHIFTED_MIN_S (smaller steps
+# with a scaled basis stay far from that pass's limit, and a failure there means a
+# numerically dependent panel).
+SHIFTED_MIN_S = 8
+
+
 def _outer(A, b, x0, tol, max_iters, cycle_fn, record):
     op = A if isinstance(A, Operator) else Operator(A)
     b = np.asarray(b, dtype=np.float64)
@@ -200,7 +207,8 @@ def hessenberg_block(Hh: np.ndarray, P: np.ndarray, R: np.ndarray, B: np.ndarray
 
 def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
                 max_iters: int = 10**9, ortho: str = "two_stage",
-                basis: str = "monomial", shifts=None, record: bool = False, s_hat: int | None = None):
+                basis: str = "monomial", shifts=None, record: bool = False, s_hat: int | None = None,
+                shifted: bool | None = None):
     """s-step GMRES(m) with one-stage or two-stage block orthogonalization.
 
     Two-stage with s_hat = m (default): stage 2 is one CholQR of the m+1 columns at the end
@@ -213,12 +221,13 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
     if ortho == "two_stage" and s_hat is not None and s_hat < m:
         if s_hat % s != 0 or m % s_hat != 0:
             raise ValueError("need s | s_hat | m")
-        return _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record)
+        return _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record, shifted)
     op = A if isinstance(A, Operator) else Operator(A)
     bp = _Basis(op, s, basis, shifts)
     J = m // s
     one_stage = None if ortho == "two_stage" else blockortho.ONE_STAGE[ortho]
-    stats = {"fallbacks": 0, "cycles": 0}  # fallbacks: panels that took the explicit second pass
+    stats = {"fallbacks": 0, "shifted": 0, "cycles": 0}  # panels that took the second / shifted pass
+    use_shift = s >= SHIFTED_MIN_S if shifted is None else bool(shifted)
 
     def cycle(op, r, beta, tol_abs):
         n = op.n
@@ -234,8 +243,9 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
             W, B = mpk(op, Qh[:, k - 1], bp.theta, bp.sigma, bp.tau)
             try:
                 if one_stage is None:  # stage 1 (second pass only where PIP fails)
-                    Qn, P, R, fb = blockortho.bcgs_pip_explicit(Qh[:, :k], W, PIVOT_TOL)
-                    stats["fallbacks"] += int(fb)
+                    Qn, P, R, fb = blockortho.bcgs_pip_explicit(Qh[:, :k], W, PIVOT_TOL, use_shift)
+                    stats["fallbacks"] += int(fb >= 1)
+                    stats["shifted"] += int(fb == 2)
                 else:
                     Qn, P, R = one_stage(Qh[:, :k], W, PIVOT_TOL)
             except CholeskyBreakdown:
@@ -290,10 +300,11 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
     out = _outer(op, b, x0, tol, max_iters, cycle, record)
     bp.export(out)
     out["fallbacks"] = stats["fallbacks"]
+    out["shifted"] = stats["shifted"]
     return out
 
 
-def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record):
+def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record, shifted=None):
     """Two-stage s-step GMRES(m) with big panels of s_hat < m columns.
 
     Within a cycle the basis Y holds final (orthonormal) columns for the completed big
@@ -315,7 +326,8 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
     bp = _Basis(op, s, basis, shifts)
     J = m // s
     bigs = blockortho.big_panel_bounds(m + 1, s, s_hat)
-    stats = {"fallbacks": 0, "cycles": 0}
+    stats = {"fallbacks": 0, "shifted": 0, "cycles": 0}
+    use_shift = s >= SHIFTED_MIN_S if shifted is None else bool(shifted)
 
     def stage2(Y, H, done, b1, c_h):
         """Stage 2 on columns [done, b1); transforms H(:b1, :c_h).  Returns (kept, M00)."""
@@ -357,8 +369,9 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
             k = j * s + 1
             W, B = mpk(op, Y[:, k - 1], bp.theta, bp.sigma, bp.tau)
             try:
-                Qn, P, R, fb = blockortho.bcgs_pip_explicit(Y[:, :k], W, PIVOT_TOL)
-                stats["fallbacks"] += int(fb)
+                Qn, P, R, fb = blockortho.bcgs_pip_explicit(Y[:, :k], W, PIVOT_TOL, use_shift)
+                stats["fallbacks"] += int(fb >= 1)
+                stats["shifted"] += int(fb == 2)
             except CholeskyBreakdown:
                 # the cycle keeps the columns of its completed big panels (their stage 2
                 # is done and their residual was checked); the unfinished big panel is
@@ -399,6 +412,7 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
     out = _outer(op, b, x0, tol, max_iters, cycle, record)
     bp.export(out)
     out["fallbacks"] = stats["fallbacks"]
+    out["shifted"] = stats["shifted"]
     return out
 
 

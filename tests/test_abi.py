@@ -32,7 +32,7 @@ def test_header_declares_the_boundary():
               "tsg_orthogonalize", "tsg_orthogonalize_workspace_bytes", "tsg_status_string",
               "tsg_last_error", "tsg_csr_gershgorin", "tsg_server_create", "tsg_server_destroy",
               "tsg_server_submit", "tsg_server_step", "tsg_server_poll", "tsg_server_request_bytes",
-              "tsg_csr_pack", "tsg_csr_pack_bytes"):
+              "tsg_csr_pack", "tsg_csr_pack_bytes", "tsg_ritz_newton"):
         assert s in syms
 
 
@@ -70,6 +70,11 @@ def test_host_side_validation(lib):
     assert lib.tsg_orthogonalize(100, 65, None, 100, None, 65, 5, 0, 0, None, 0, None, None) == -1
     assert lib.tsg_orthogonalize_workspace_bytes(100, 65, 5) == 0
     assert lib.tsg_orthogonalize_workspace_bytes(100, 61, 5) > 0
+    # Ritz/Newton entry: argument checks happen before any device work
+    assert lib.tsg_ritz_newton(None, 10, 10, 5, 0.0, 1.0, None, None) == -1
+    assert lib.tsg_ritz_newton(C.c_void_p(256), 10, 64, 5, 0.0, 1.0, C.c_void_p(256), None) == -1  # k > 63
+    assert lib.tsg_ritz_newton(C.c_void_p(256), 10, 10, 11, 0.0, 1.0, C.c_void_p(256), None) == -1  # s > k
+    assert lib.tsg_ritz_newton(C.c_void_p(256), 9, 10, 5, 0.0, 1.0, C.c_void_p(256), None) == -1  # ldh < k
 
 
 def test_no_cpu_fallback(monkeypatch, tmp_path):

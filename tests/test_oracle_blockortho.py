@@ -209,3 +209,52 @@ def test_pip_explicit_second_pass_rejects_dependent_columns():
     with pytest.raises(D.CholeskyBreakdown) as e:
         BO.bcgs_pip_explicit(Q, V, 1e-12)
     assert e.value.index == 2
+
+
+def _ill_conditioned_panel(n, k, s, kappa, seed):
+    """Q (n x k orthonormal) and V = Q C + Z D with Z orthonormal, orthogonal to Q, and D
+    upper triangular with unit diagonal but D[s-1, s-1] = 1/kappa: the last column of
+    Y = V - Q Q^T V = Z D lies within 1/kappa of the span of the others, numerically full
+    rank but beyond CholQR's limit (its relative pivot ~kappa^-2 is below the threshold)."""
+    rng = np.random.default_rng(seed)
+    X, _ = np.linalg.qr(rng.standard_normal((n, k + s)))
+    Q, Z = X[:, :k], X[:, k:]
+    D = np.triu(rng.standard_normal((s, s)), 1) + np.eye(s)
+    D[s - 1, s - 1] = 1.0 / kappa
+    return Q, Q @ rng.standard_normal((k, s)) + Z @ D
+
+
+def test_shifted_pass_where_the_second_pass_fails():
+    """A relative pivot of 1e-18: the explicit second pass fails its pivot test;
+    the shifted Cholesky QR pass and one more BCGS-PIP pass still give the thin QR of
+    [Q, V]: orthogonal to O(eps kappa(Z)^2) with kappa(Z) ~ (mu / sigma_min^2)^(1/2),
+    V = Q P + Qnew R to rounding, R equal to the Householder factor's trailing block to
+    O(eps kappa(Y))."""
+    n, k, s = 4000, 9, 6
+    Q, V = _ill_conditioned_panel(n, k, s, 1e9, seed=21)
+    with pytest.raises(D.CholeskyBreakdown):
+        BO.bcgs_pip_explicit(Q, V, 1e-12)
+    Qn, P, R, passes = BO.bcgs_pip_explicit(Q, V, 1e-12, shifted=True)
+    assert passes == 2
+    Qf = np.hstack([Q, Qn])
+    assert D.orth_error(Qf) <= 1e-10
+    assert np.linalg.norm(V - Q @ P - Qn @ R) / np.linalg.norm(V) <= 1e-15
+    _, Rh = D.householder_qr(np.hstack([Q, V]))
+    assert np.linalg.norm(P - Rh[:k, k:]) / np.linalg.norm(Rh[:k, k:]) <= 1e-12
+    assert np.linalg.norm(R - Rh[k:, k:]) / np.linalg.norm(Rh[k:, k:]) <= 1e-6
+    # a panel the second pass handles never reaches the shifted pass
+    Q2, V2 = _nearly_dependent_panel(n, k, 5, 1e-7, seed=11)
+    assert BO.bcgs_pip_explicit(Q2, V2, 1e-12, shifted=True)[3] == 1
+
+
+def test_shifted_pass_still_rejects_dependent_columns():
+    n, k, s = 4000, 9, 5
+    Q, V = _nearly_dependent_panel(n, k, s, 0.0, seed=13)
+    with pytest.raises(D.CholeskyBreakdown) as e:
+        BO.bcgs_pip_explicit(Q, V, 1e-12, shifted=True)
+    assert e.value.index == 0
+    Q, V = _nearly_dependent_panel(n, k, s, 1e-3, seed=14)
+    V[:, 2] = Q @ np.arange(1.0, k + 1.0)
+    with pytest.raises(D.CholeskyBreakdown) as e:
+        BO.bcgs_pip_explicit(Q, V, 1e-12, shifted=True)
+    assert e.value.index == 2

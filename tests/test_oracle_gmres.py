@@ -253,3 +253,18 @@ def test_shat_first_cycle_is_the_krylov_minimizer():
     b = G.gmres(pr["A"], pr["b"], m=30, tol=1e-14, ortho="mgs", max_iters=30)
     assert a["iters"] == 30 and b["iters"] == 30
     assert np.linalg.norm(a["x"] - b["x"]) / np.linalg.norm(b["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("kind,s", [("laplace2d", 12), ("laplace2d", 15), ("convdiff2d", 15)])
+def test_shifted_pass_extends_the_monomial_basis(kind, s):
+    """Monomial panels at s >= 12 are beyond the explicit second pass (the first panel
+    breaks down and the solve makes no progress); with the shifted Cholesky QR pass the
+    same solve converges to the dense-solve accuracy."""
+    pr = W.make_problem(kind, 40, seed=0)
+    A, b = pr["A"], pr["b"]
+    plain = G.sstep_gmres(A, b, m=60, s=s, tol=1e-10, shifted=False, max_iters=6000)
+    assert not plain["converged"] and plain["iters"] == 0
+    out = G.sstep_gmres(A, b, m=60, s=s, tol=1e-10, max_iters=6000)  # default: shifted for s >= 8
+    assert out["converged"] and out["shifted"] > 0
+    x_lu, M = G.dense_solve(A, b)
+    assert np.linalg.norm(out["x"] - x_lu) / np.linalg.norm(x_lu) <= 2 * 1e-10 * np.linalg.cond(M)
