@@ -63,7 +63,7 @@ def main():
     ap.add_argument("--problem", default="laplace2d", choices=["laplace2d", "laplace3d", "convdiff2d"])
     ap.add_argument("--N", type=int, default=None,
                     help="grid side (default 2048 in 2D, 160 in 3D)")
-    ap.add_argument("--basis", default="monomial", choices=["monomial", "shifted"])
+    ap.add_argument("--basis", default="monomial", choices=["monomial", "shifted", "leja"])
     ap.add_argument("--s-hat", type=int, default=0, help="two-stage big-panel size (0 = m)")
     ap.add_argument("--shat-sweep", action="store_true",
                     help="also time one solve for each s_hat in {s, 2s, 4s, 6s, m} (Table 2's knob)")

@@ -59,12 +59,26 @@ typedef enum {
   TSG_ORTHO_CGS2 = 3
 } tsg_ortho;
 
-/* s-step basis w_i = (A w_{i-1} - theta_i w_{i-1}) / sigma_i (matrix-powers kernel,
- * Sec. III).  [lo, hi] is the Gershgorin interval computed at tsg_csr_create.
+/* s-step basis w_i = (A w_{i-1} - theta_i w_{i-1} + tau_i w_{i-2}) / sigma_i
+ * (matrix-powers kernel, Sec. III; tau = 0 except in LEJA).  [lo, hi] is the Gershgorin
+ * interval computed at tsg_csr_create.
  *   MONOMIAL  theta = 0, sigma = max(|lo|, |hi|)          (the paper's choice, Sec. VI)
  *   SHIFTED   theta = (lo+hi)/2, sigma = (hi-lo)/2
- *   NEWTON    theta_i = newton_shifts[i] (host), sigma = (hi-lo)/2              */
-typedef enum { TSG_BASIS_MONOMIAL = 0, TSG_BASIS_SHIFTED = 1, TSG_BASIS_NEWTON = 2 } tsg_basis;
+ *   NEWTON    theta_i = newton_shifts[i] (host), sigma = (hi-lo)/2
+ *   LEJA      Newton basis from Ritz values (the better-conditioned basis the paper names
+ *             for larger s, Sec. III and Sec. VI, after Bai, Hu and Reichel): cycles run
+ *             with SHIFTED until one keeps >= s columns; at its end the device computes
+ *             the eigenvalues of that cycle's Hessenberg matrix (Francis double-shift QR),
+ *             Leja-orders them (conjugates adjacent) and takes the first s in real form
+ *             (a pair a +- ib as theta = a, a and tau = b^2 / sigma on its second step),
+ *             sigma = the capacity estimate of the ordered Ritz values; every later cycle
+ *             uses them (tsg_solve_info.newton_from_cycle).  Not used by CGS2.          */
+typedef enum {
+  TSG_BASIS_MONOMIAL = 0,
+  TSG_BASIS_SHIFTED = 1,
+  TSG_BASIS_NEWTON = 2,
+  TSG_BASIS_LEJA = 3
+} tsg_basis;
 
 /* FP64: every step in float64.
  * FP32_IR: basis, SpMV and tall-skinny products in float32 with float32
@@ -138,6 +152,8 @@ typedef struct {
   int64_t timed_cycles;    /* restart cycles whose launches were timed                    */
   int64_t pip_fallbacks;   /* two-stage: stage-1 panels whose Pythagorean Gram failed the
                               pivot test and took the explicit second pass              */
+  int64_t newton_from_cycle; /* LEJA: cycles completed when the Newton basis took over
+                                (0: it never did)                                       */
 } tsg_solve_info;
 
 typedef struct tsg_csr_s* tsg_csr;
@@ -166,6 +182,17 @@ tsg_status tsg_csr_gershgorin(tsg_csr A, double* lo, double* hi);
  * products in CSR order, rounded as the CSR kernel rounds them: results are identical. */
 size_t tsg_csr_pack_bytes(tsg_csr A);
 tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream);
+
+/* Newton-basis parameters of TSG_BASIS_LEJA for a given k x k upper Hessenberg matrix
+ * H (device, column-major, leading dimension ldh >= k; entries below the subdiagonal are
+ * ignored), 1 <= s <= k <= 63: the same device routine the solver runs at a cycle end.
+ * out (device, 2k + 3s + 1 doubles, caller-owned): the Ritz values in Leja order (k real
+ * parts, then k imaginary parts), theta (s), tau (s), sigma (s), then a status word.
+ * [lo, hi] supplies the fallback scaling (hi - lo) / 2.  Synchronizes `stream`.
+ * Returns TSG_BREAKDOWN (status word 1) when the QR iteration did not converge within
+ * 30 k double-shift steps; INVALID_ARG for bad sizes or NULL pointers; HIP. */
+tsg_status tsg_ritz_newton(const double* H, int64_t ldh, int32_t k, int32_t s, double lo, double hi, double* out,
+                           void* stream);
 
 /* y = A x in float64 (the SpMV of the matrix-powers kernel with theta = 0, sigma = 1).
  * x and y must not overlap.  Asynchronous on `stream`. */

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libtsgmres.so"
 
 ORTHO = {"two_stage": 0, "bcgs_pip2": 1, "bcgs2_cholqr2": 2, "cgs2": 3}
-BASIS = {"monomial": 0, "shifted": 1, "newton": 2}
+BASIS = {"monomial": 0, "shifted": 1, "newton": 2, "leja": 3}
 PRECISION = {"fp64": 0, "fp32_ir": 1}
 FLAG_EAGER = 1
 STATUS = {0: "ok", 1: "not converged", 2: "breakdown", -1: "invalid argument",
@@ -46,7 +46,8 @@ class _Info(C.Structure):
                 ("bytes_ortho_reduce", C.c_double), ("bytes_ortho_update", C.c_double),
                 ("bytes_spmv", C.c_double), ("kc_ms", C.c_double * 16),
                 ("kc_launches", C.c_int64 * 16), ("kc_bytes", C.c_double * 16),
-                ("timed_cycles", C.c_int64), ("pip_fallbacks", C.c_int64)]
+                ("timed_cycles", C.c_int64), ("pip_fallbacks", C.c_int64),
+                ("newton_from_cycle", C.c_int64)]
 
 
 KERNEL_CLASSES = ["mpk", "gram", "gram_first", "update", "fused", "tail", "cycle_end", "xupdate",
@@ -79,6 +80,7 @@ class SolveInfo:
     kc_bytes: tuple = ()
     timed_cycles: int = 0
     pip_fallbacks: int = 0
+    newton_from_cycle: int = 0
 
     def kernel_classes(self) -> dict:
         """{class: (ms, launches, algorithmic bytes)} for the classes that ran (timing mode)."""
@@ -140,6 +142,8 @@ def load_library():
     lib.tsg_server_step.restype = C.c_int
     lib.tsg_server_poll.argtypes = [vp, C.POINTER(i64), C.POINTER(_Info), i32]
     lib.tsg_server_poll.restype = i32
+    lib.tsg_ritz_newton.argtypes = [vp, i64, i32, i32, C.c_double, C.c_double, vp, vp]
+    lib.tsg_ritz_newton.restype = C.c_int
     lib.tsg_status_string.argtypes = [C.c_int]
     lib.tsg_status_string.restype = C.c_char_p
     lib.tsg_last_error.argtypes = []
@@ -252,6 +256,27 @@ def spmv(A: CSRMatrix, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.
         y = torch.empty_like(x)
     _check(load_library().tsg_spmv(A.handle, x.data_ptr(), y.data_ptr(), _stream(x.device)))
     return y
+
+
+def ritz_newton(H: torch.Tensor, s: int, lo: float, hi: float):
+    """Newton-basis parameters of basis='leja' for the k x k upper Hessenberg H (float64
+    device tensor, column-major: H.T contiguous, or any (k, k) tensor with stride (1, ld)).
+    Returns dict(ritz=complex Leja-ordered Ritz values (host), theta, tau, sigma (device))."""
+    lib = load_library()
+    if H.dim() != 2 or H.shape[0] != H.shape[1] or H.dtype != torch.float64 or H.device.type != "cuda":
+        raise ValueError("H must be a square float64 device tensor")
+    if H.stride(0) != 1:
+        raise ValueError("H must be column-major (stride (1, ld))")
+    k = H.shape[0]
+    ld = H.stride(1) if k > 1 else 1
+    out = torch.empty(2 * k + 3 * int(s) + 1, dtype=torch.float64, device=H.device)
+    _check(lib.tsg_ritz_newton(H.data_ptr(), ld, k, int(s), float(lo), float(hi), out.data_ptr(),
+                               _stream(H.device)))
+    o = out.cpu()
+    ritz = torch.complex(o[:k], o[k:2 * k])
+    s = int(s)
+    return {"ritz": ritz, "theta": out[2 * k:2 * k + s], "tau": out[2 * k + s:2 * k + 2 * s],
+            "sigma": out[2 * k + 2 * s:2 * k + 3 * s]}
 
 
 def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph=True, s_hat=0):

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "panel.hpp"
+#include "ritz.hpp"
 
 namespace tsg {
 
@@ -152,7 +153,9 @@ __global__ __launch_bounds__(kRowBlock) void sell_fill_kernel(const int32_t* __r
   }
 }
 
-// One step of the matrix-powers kernel (Sec. III): y = (A x - theta x) / sigma.
+// One step of the matrix-powers kernel (Sec. III): y = (A x - theta x + tau xm) / sigma,
+// with the step's theta, sigma, tau read from the request's state (tau != 0 only where
+// the Newton basis closes a complex pair; xm is the basis vector before x).
 // 4 waves x 64 rows per block; blocks are mapped XCD-contiguously so the x gathers of
 // neighbouring rows hit the same L2.  Values of type VT (float64, or the float32 copy of
 // the mixed-precision form), vectors of type T.
@@ -162,11 +165,11 @@ struct MpkArgs {
   const void* val;         // VT[nnz] (packed: padded)
   const void* x;           // T[n]
   void* y;                 // T[n]
+  const void* xm;          // T[n], the vector before x (NULL at a panel's first step)
   int64_t n;
-  double theta, sigma;
   const SmallState* st;
+  int32_t step;            // index of the step in the panel (0 .. s-1)
   int32_t panel;
-  int32_t pad;
 };
 template <typename T, typename VT, int FMT>
 struct MpkBody {
@@ -193,10 +196,12 @@ struct MpkBody {
                                      r0 / kWave, lane);
     }
     const int64_t r = r0 + lane;
+    const double theta = st->theta[a.step], sigma = st->sigma[a.step], tau = st->tau[a.step];
     if (r < n) {
       T v = acc;
-      if (a.theta != 0.0) v -= (T)a.theta * x[r];
-      y[r] = v / (T)a.sigma;
+      if (theta != 0.0) v -= (T)theta * x[r];
+      if (tau != 0.0 && a.xm) v += (T)tau * G(reinterpret_cast<const T*>(a.xm))[r];
+      y[r] = v / (T)sigma;
     }
   }
 };
@@ -489,6 +494,7 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
   if (tid == 0) s_ku = st->h.k_used;
   __syncthreads();
   int ku = s_ku;
+  const int ritz = st->ritz_pending;
   double est = 0.0;
   if (two_stage && ku > 0) {
     int kb = ku + 1;
@@ -544,6 +550,16 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
       }
       for (int i = tid; i <= kLd; i += nt) sg[i] = 0.0;
       __syncthreads();
+      if (ritz) {  // for the Newton shifts: H(0:ku, 0:ku) = sM(0:ku, 0:ku) R2(0:ku, 0:ku)^{-1}
+        for (int r = tid; r < ku; r += nt) {
+          for (int j = 0; j < ku; ++j) {
+            double v = sM[r + j * kLd];
+            for (int l = 0; l < j; ++l) v -= st->Wk[r + l * kLd] * sR[l + j * kLd];
+            st->Wk[r + j * kLd] = v / sR[j + j * kLd];
+          }
+        }
+        __syncthreads();
+      }
       if (tid < kWave) {  // wave 0: Givens QR of sM and back substitution
         const int lane = tid;
         if (lane == 0) sg[0] = st->beta * sR[0];
@@ -598,6 +614,80 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
     st->h.cycles += 1;
     st->h.est = est / st->bnorm;
   }
+}
+
+// ------------------------------------------------------------------ Leja-Ritz basis
+// After a cycle end, while the request's Newton shifts are pending and the cycle kept at
+// least s columns: the Ritz values of its k x k Hessenberg matrix (two-stage with
+// s_hat = m: the one CycleEndBody formed in Wk; otherwise Hh, which holds H itself),
+// their Leja ordering and the real-form parameters of the first s, which every later
+// matrix-powers step reads.  One wave.  If the QR iteration does not converge the
+// current basis stays.
+struct RitzBody {
+  typedef TailArgs Args;
+  static constexpr int kThreads = kWave;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const TailArgs& a, int bid, int nb);
+};
+struct WaveLdsSync {
+  __device__ void operator()() const { wave_lds_sync(); }
+};
+__device__ void RitzBody::run(const TailArgs& a, int, int) {
+  SmallState* st = a.st;
+  if (!st->ritz_pending || st->h.done) return;
+  const int k = st->h.k_used, s = st->s, lane = threadIdx.x;
+  if (k < s) return;  // stays pending for the next cycle
+  __shared__ double sH[kLd * kLd];
+  __shared__ RitzScratch w;
+  __shared__ double prm[3 * kMaxS];
+  const double* src = a.two_stage ? st->Wk : st->Hh;
+  for (int idx = lane; idx < k * k; idx += kWave) {
+    const int i = idx % k, j = idx / k;
+    sH[i + j * kLd] = (i <= j + 1) ? src[i + j * kLd] : 0.0;
+  }
+  wave_lds_sync();
+  const int rc = ritz_newton(sH, k, s, st->glo, st->ghi, w, prm, prm + kMaxS, prm + 2 * kMaxS, lane, kWave,
+                             WaveLdsSync());
+  if (rc == 0) {
+    for (int i = lane; i < s; i += kWave) {
+      st->theta[i] = prm[i];
+      st->tau[i] = prm[kMaxS + i];
+      st->sigma[i] = prm[2 * kMaxS + i];
+    }
+  }
+  if (lane == 0) {
+    st->ritz_pending = 0;
+    if (rc == 0) st->h.newton_from = (int32_t)st->h.cycles;
+  }
+}
+
+// Stand-alone form for a given Hessenberg matrix (device, column-major, leading
+// dimension ldh): out = [Leja-ordered Ritz values: real parts (k), imaginary parts (k);
+// theta (s), tau (s), sigma (s); status (0 ok, 1 no convergence)].
+__global__ __launch_bounds__(kWave) void ritz_newton_kernel(const double* H, int64_t ldh, int k, int s, double lo,
+                                                           double hi, double* out) {
+  __shared__ double sH[kLd * kLd];
+  __shared__ RitzScratch w;
+  __shared__ double prm[3 * kMaxS];
+  const int lane = threadIdx.x;
+  for (int idx = lane; idx < k * k; idx += kWave) {
+    const int i = idx % k, j = idx / k;
+    sH[i + j * kLd] = (i <= j + 1) ? H[i + j * ldh] : 0.0;
+  }
+  wave_lds_sync();
+  const int rc = ritz_newton(sH, k, s, lo, hi, w, prm, prm + kMaxS, prm + 2 * kMaxS, lane, kWave, WaveLdsSync());
+  if (rc == 0) {
+    for (int i = lane; i < k; i += kWave) {
+      out[i] = w.zr[i];
+      out[k + i] = w.zi[i];
+    }
+    for (int i = lane; i < s; i += kWave) {
+      out[2 * k + i] = prm[i];
+      out[2 * k + s + i] = prm[kMaxS + i];
+      out[2 * k + 2 * s + i] = prm[2 * kMaxS + i];
+    }
+  }
+  if (lane == 0) out[2 * k + 3 * s] = rc == 0 ? 0.0 : 1.0;
 }
 
 // ------------------------------------------------------------------ big-panel stage 2

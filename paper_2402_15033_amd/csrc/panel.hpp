@@ -173,7 +173,7 @@ __device__ void tail_emit_panel(const PanelArgs& a, const double* P, const doubl
     __syncthreads();
     return;
   }
-  block_hessenberg_panel(st->Hh, P, R, st->theta, st->sigma, k, s, st->Wk);
+  block_hessenberg_panel(st->Hh, P, R, st->theta, st->sigma, st->tau, k, s, st->Wk);
   if (givens) {
     givens_append(st, st->Hh, k - 1, k - 1 + s);
     tail_check(st, k - 1 + s, a.panel);

@@ -79,15 +79,15 @@ __device__ void block_gemm(const double* A, int lda, const double* B, int ldb, d
 
 // Hessenberg block of one s-step panel (the small-matrix algebra of Fig. 1):
 //   [w_0, W] = Qb_{1:k+s} S,  S(:,1) = e_k,  S(:,2:s+1) = [P; R]
-//   A [w_0..w_{s-1}] = [w_0..w_s] B,  B(i,i) = theta_i, B(i+1,i) = sigma_i
+//   A [w_0..w_{s-1}] = [w_0..w_s] B,  B(i,i) = theta_i, B(i+1,i) = sigma_i, B(i-1,i) = -tau_i
 //   H(1:k+s, k:k+s-1) = (S B - [H(1:k,1:k-1) S(1:k-1,1:s); 0]) T^{-1},
 //   T = S(k:k+s-1, 1:s).
 // P (k x s, ld kLd) and R (s x s, ld kMaxS) are the panel factors, H (ld kLd) holds
 // columns 0..k-2 on entry.  M is a kLd x kMaxS scratch.  0-based: the new columns are
 // k-1 .. k+s-2 and rows 0 .. k+s-1.
 __device__ void block_hessenberg_panel(double* H, const double* P, const double* R,
-                                       const double* theta, const double* sigma, int k, int s,
-                                       double* M) {
+                                       const double* theta, const double* sigma, const double* tau, int k,
+                                       int s, double* M) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int rows = k + s;
   // LDS copies of the operands of the inner products (H(0:k, 0:k-1) is upper Hessenberg)
@@ -109,6 +109,7 @@ __device__ void block_hessenberg_panel(double* H, const double* P, const double*
   for (int idx = tid; idx < rows * s; idx += nt) {
     int i = idx % rows, c = idx / rows;
     double v = Sv(i, c) * theta[c] + Sv(i, c + 1) * sigma[c];
+    if (c >= 1 && tau[c] != 0.0) v -= Sv(i, c - 1) * tau[c];
     if (c >= 1 && i < k) {
       for (int l = (i > 0 ? i - 1 : 0); l < k - 1; ++l) v -= lH[i + l * kLd] * lP[l + (c - 1) * kLd];
     }

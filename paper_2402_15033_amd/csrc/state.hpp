@@ -20,7 +20,7 @@ struct StateHead {
   int32_t truncated;     // cycles truncated by a Cholesky breakdown
   int32_t refine;        // panel + 1 of the panel whose stage-1 PIP needs the explicit pass
   int32_t fallbacks;     // stage-1 panels that took the explicit second pass (all cycles)
-  int32_t pad;
+  int32_t newton_from;   // Leja-Ritz basis: cycles completed when it took over (0: not yet)
 };
 
 struct SmallState {
@@ -29,7 +29,11 @@ struct SmallState {
   int32_t m, s, ortho, prec;
   int64_t max_iters;
   double tol, bnorm, pivot_tol;
-  double theta[kMaxS], sigma[kMaxS];
+  // basis step i: w_{i+1} = ((A - theta_i I) w_i + tau_i w_{i-1}) / sigma_i
+  double theta[kMaxS], sigma[kMaxS], tau[kMaxS];
+  double glo, ghi;       // Gershgorin interval of the operator
+  int32_t ritz_pending;  // Leja-Ritz basis: the next cycle end computes the Newton shifts
+  int32_t pad3;
   // cycle scalars
   double beta, inv_beta;
   int32_t identity_t;    // the next update kernel uses T = I (no scaling)

@@ -211,7 +211,9 @@ static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks, "reduction partial buffer too 
 // Device bytes reserved for the launch image of one request's program.
 constexpr size_t kProgramBytesPerRequest = 512 * 1024;
 
-enum Family : int { F_RESID, F_RTAIL, F_UPDATE, F_MPK, F_GRAM, F_PREDUCE, F_PTAIL, F_FUSED, F_CYCLE_END, F_XUPD, F_S2 };
+enum Family : int {
+  F_RESID, F_RTAIL, F_UPDATE, F_MPK, F_GRAM, F_PREDUCE, F_PTAIL, F_FUSED, F_CYCLE_END, F_XUPD, F_S2, F_RITZ
+};
 
 struct Phase {
   Family f;
@@ -281,6 +283,7 @@ void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
     case F_PTAIL: launch_b<PTailBody>(ph, d, nreq, s); break;
     case F_CYCLE_END: launch_b<CycleEndBody>(ph, d, nreq, s); break;
     case F_S2: launch_b<Stage2Body>(ph, d, nreq, s); break;
+    case F_RITZ: launch_b<RitzBody>(ph, d, nreq, s); break;
     case F_XUPD: launch_b<XupdBody<T>>(ph, d, nreq, s); break;
     case F_UPDATE:
       switch (ph.t1) {
@@ -350,6 +353,7 @@ struct ReqCtx {
   int64_t ld = 0, n = 0;
   Common c{};
   double theta[kMaxS] = {0}, sigma[kMaxS] = {0};
+  bool leja = false;             // Newton shifts from the Ritz values of a cycle
 };
 
 enum PanelKind { PK_GRAM, PK_UPDATE, PK_FUSED };
@@ -512,7 +516,7 @@ struct Builder {
     for (ReqCtx* q : R) t.push_back(TailArgs{q->c.st, q->c.part1, (int)cdiv(q->n, kRowBlock), 0});
     P.add(F_RTAIL, 0, 0, t, one, -1, 0.0);
   }
-  // w_i = (A w_{i-1} - theta_i w_{i-1}) / sigma_i into column col_out
+  // w_{i+1} = (A w_i - theta_i w_i + tau_i w_{i-1}) / sigma_i into column col_out
   void mpk(int col_in, int col_out, int i, int panel) {
     for (int fmt = FMT_CSR; fmt <= FMT_SELL32; ++fmt) {
       std::vector<MpkArgs> a;
@@ -522,7 +526,8 @@ struct Builder {
         const bool mine = q->fmt == fmt;
         char* V = static_cast<char*>(q->V);
         a.push_back(MpkArgs{q->row_ptr, q->col, q->valT, V + (size_t)col_in * q->ld * elem(),
-                            V + (size_t)col_out * q->ld * elem(), q->n, q->theta[i], q->sigma[i], q->c.st, panel, 0});
+                            V + (size_t)col_out * q->ld * elem(),
+                            i > 0 ? V + (size_t)(col_in - 1) * q->ld * elem() : nullptr, q->n, q->c.st, i, panel});
         nb.push_back(mine ? (int)cdiv(q->n, kRowBlock) : 0);
         if (mine) bytes += index_bytes(*q) + (double)q->nnz * elem() + 2.0 * q->n * elem();
       }
@@ -549,8 +554,14 @@ struct Builder {
   void cycle_end(int two) {
     std::vector<TailArgs> t;
     std::vector<int> one(R.size(), 1);
-    for (ReqCtx* q : R) t.push_back(TailArgs{q->c.st, nullptr, 0, two});
+    bool leja = false;
+    for (ReqCtx* q : R) {
+      t.push_back(TailArgs{q->c.st, nullptr, 0, two});
+      leja = leja || q->leja;
+    }
     P.add(F_CYCLE_END, 0, 0, t, one, TSG_KC_CYCLE_END, 0.0);
+    // Newton shifts from this cycle's Ritz values (returns at entry unless pending)
+    if (leja) P.add(F_RITZ, 0, 0, t, one, TSG_KC_CYCLE_END, 0.0);
   }
   void xupdate(int m) {
     std::vector<XupdArgs> a;
@@ -833,6 +844,21 @@ tsg_status tsg_spmv(tsg_csr A, const double* x, double* y, void* stream) {
   return TSG_OK;
 }
 
+tsg_status tsg_ritz_newton(const double* H, int64_t ldh, int32_t k, int32_t s, double lo, double hi, double* out,
+                           void* stream) {
+  if (!H || !out) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  if (k < 1 || k > kMaxCols - 1 || s < 1 || s > kMaxS || s > k || ldh < k)
+    return fail(TSG_ERR_INVALID_ARG, "need 1 <= s <= k <= 63, s <= 16, ldh >= k (k=%d s=%d ldh=%lld)", k, s,
+                (long long)ldh);
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(ritz_newton_kernel, dim3(1), dim3(kWave), 0, st, H, ldh, k, s, lo, hi, out);
+  HIP_LAUNCH_CHECK();
+  double flag = 0.0;
+  HIP_TRY(hipMemcpyAsync(&flag, out + 2 * (int64_t)k + 3 * (int64_t)s, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return flag == 0.0 ? TSG_OK : fail(TSG_BREAKDOWN, "QR iteration for the Ritz values did not converge");
+}
+
 static tsg_status validate_params(int64_t n, const tsg_solve_params* p) {
   if (!p) return fail(TSG_ERR_INVALID_ARG, "params is NULL");
   if (p->m < 1 || p->m + 1 > kMaxCols) return fail(TSG_ERR_INVALID_ARG, "m=%d outside [1, 63]", p->m);
@@ -848,7 +874,7 @@ static tsg_status validate_params(int64_t n, const tsg_solve_params* p) {
     if (p->s_hat < p->s || p->s_hat > p->m || p->s_hat % p->s != 0 || p->m % p->s_hat != 0)
       return fail(TSG_ERR_INVALID_ARG, "need s | s_hat | m (s=%d, s_hat=%d, m=%d)", p->s, p->s_hat, p->m);
   }
-  if (p->basis < 0 || p->basis > 2) return fail(TSG_ERR_INVALID_ARG, "bad basis %d", p->basis);
+  if (p->basis < 0 || p->basis > 3) return fail(TSG_ERR_INVALID_ARG, "bad basis %d", p->basis);
   if (p->basis == TSG_BASIS_NEWTON && !p->newton_shifts)
     return fail(TSG_ERR_INVALID_ARG, "newton basis needs newton_shifts");
   if (p->precision < 0 || p->precision > 1) return fail(TSG_ERR_INVALID_ARG, "bad precision");
@@ -885,7 +911,7 @@ void basis_params(const tsg_csr_s* A, const tsg_solve_params* p, int sstep, doub
     } else if (p->basis == TSG_BASIS_MONOMIAL) {
       theta[i] = 0.0;
       sigma[i] = std::max(std::fabs(lo), std::fabs(hi));
-    } else if (p->basis == TSG_BASIS_SHIFTED) {
+    } else if (p->basis == TSG_BASIS_SHIFTED || p->basis == TSG_BASIS_LEJA) {
       theta[i] = 0.5 * (lo + hi);
       sigma[i] = 0.5 * (hi - lo);
     } else {
@@ -905,6 +931,7 @@ void carve_request(char* base, const tsg_csr_s* A, const tsg_solve_params* p, Re
   q.c = carve_common(cv, A->n);
   q.ld = basis_ld(A->n);
   q.n = A->n;
+  q.leja = p->basis == TSG_BASIS_LEJA && p->ortho != TSG_ORTHO_CGS2;
   const bool f32 = p->precision == TSG_PREC_FP32_IR;
   if (A->packed) {
     q.fmt = A->sell_fmt;
@@ -952,6 +979,9 @@ tsg_status init_request(const tsg_csr_s* A, const tsg_solve_params* p, ReqCtx& q
     hs->theta[i] = q.theta[i];
     hs->sigma[i] = q.sigma[i];
   }
+  hs->glo = A->lo;
+  hs->ghi = A->hi;
+  hs->ritz_pending = q.leja ? 1 : 0;
   // pageable source: the copy is staged before the call returns
   hipError_t e = hipMemcpyAsync(q.c.st, hs, offsetof(SmallState, Hh), hipMemcpyHostToDevice, s);
   delete hs;
@@ -976,6 +1006,7 @@ void fill_info(tsg_solve_info* info, const StateHead& h, tsg_status st) {
   info->status = st;
   info->truncated_cycles = h.truncated;
   info->pip_fallbacks = h.fallbacks;
+  info->newton_from_cycle = h.newton_from;
 }
 
 tsg_status head_status(const StateHead& h) {
