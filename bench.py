@@ -170,6 +170,8 @@ def main():
     # independent residual check of the final iterate (scipy on the host)
     xh = x.cpu().numpy()
     relres_host = float(np.linalg.norm(pr["b"] - Ah.to_scipy() @ xh) / np.linalg.norm(pr["b"]))
+    if not info.converged:
+        log(f"[bench] WARNING: the solve did not converge (status {info.status}, relres {relres_host:.3e})")
 
     def tot(f):
         return sum(getattr(i, f) for i in infos)
@@ -242,6 +244,9 @@ def main():
         "time_to_solution_s": round(elapsed / args.steps, 4),
         "iters": int(info.iters), "cycles": int(info.cycles),
         "relres_device": info.relres, "relres_host_check": relres_host,
+        "converged": bool(info.converged), "status": int(info.status),
+        "pip_fallbacks": int(info.pip_fallbacks), "shifted_passes": int(info.shifted_passes),
+        "newton_from_cycle": int(info.newton_from_cycle),
         "ortho_ms_per_cycle": round(ortho_ms_cycle, 3),
         "kernel_classes": per_class,
         "roofline": roofline,

@@ -66,7 +66,7 @@ typedef enum {
  *   SHIFTED   theta = (lo+hi)/2, sigma = (hi-lo)/2
  *   NEWTON    theta_i = newton_shifts[i] (host), sigma = (hi-lo)/2
  *   LEJA      Newton basis from Ritz values (the better-conditioned basis the paper names
- *             for larger s, Sec. III and Sec. VI, after Bai, Hu and Reichel): cycles run
+ *             for larger s, Sec. IV and Sec. VI, after Bai, Hu and Reichel): cycles run
  *             with SHIFTED until one keeps >= s columns; at its end the device computes
  *             the eigenvalues of that cycle's Hessenberg matrix (Francis double-shift QR),
  *             Leja-orders them (conjugates adjacent) and takes the first s in real form
@@ -154,6 +154,11 @@ typedef struct {
                               pivot test and took the explicit second pass              */
   int64_t newton_from_cycle; /* LEJA: cycles completed when the Newton basis took over
                                 (0: it never did)                                       */
+  int64_t shifted_passes;  /* two-stage with s >= 8 or FP32_IR: stage-1 panels whose
+                              explicit second pass failed too and took the shifted Cholesky
+                              QR pass (Fukaya et al.; Sec. II names it as CholQR's remedy):
+                              Rs = Chol(G + mu I), mu = 10 pivot_tol trace(G), then one
+                              more BCGS-PIP pass; elsewhere such a panel ends the cycle */
 } tsg_solve_info;
 
 typedef struct tsg_csr_s* tsg_csr;

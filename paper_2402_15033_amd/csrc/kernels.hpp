@@ -326,6 +326,7 @@ __device__ void RTailBody::run(const TailArgs& a, int, int) {
       st->h.stop_panel = 1 << 30;
       st->h.k_used = st->m;
       st->h.refine = 0;
+      st->h.refine2 = 0;
       st->gscale = beta;
     }
   }

@@ -32,6 +32,7 @@ enum TailOp : int {
   TAIL_SA_NORM,    // stand-alone: r00 = ||x0||, T = 1/r00
   TAIL_PIP,        // BCGS-PIP Cholesky; two-stage stage 1 (+ Hessenberg block)
   TAIL_PIP_FB,     // two-stage stage 1: explicit second pass after a failed PIP pivot
+  TAIL_PIP_FB2,    // two-stage stage 1: pass after the shifted Cholesky QR
   TAIL_G2COL,      // two-stage: block column of the stage-2 Gram
   TAIL_PIP2_A,     // BCGS-PIP2 first pass
   TAIL_PIP2_B,     // BCGS-PIP2 second pass (+ Hessenberg block, Givens)
@@ -57,12 +58,13 @@ struct PanelArgs {
   int32_t tail;
   int32_t nblocks;
   int32_t gate;      // 1: return at entry when the solve is done or panel > stop_panel;
-                     // 2: also unless this panel asked for the explicit second pass
+                     // 2: also unless this panel asked for the explicit second pass;
+                     // 3: also unless it asked for the pass after the shifted Cholesky QR
   int32_t standalone;// tails assemble an R factor (st->Hh) instead of Hessenberg/Givens
   int32_t kkeep;     // Krylov vectors kept if this panel breaks down (solver mode)
   int32_t panel;     // index of the panel within the cycle (-1: cycle set-up)
   int32_t nz;        // reduced Gram has nz columns: nz - sw previous-panel columns, then W
-  int32_t pad;
+  int32_t shifted;   // the cycle holds the gate-3 pass: a failed explicit pass shifts
   SmallState* st;
   double* part1;     // per-block partial Grams, nblocks x (k+sw)*sw
 };
@@ -72,7 +74,8 @@ __device__ __forceinline__ bool gated_off(const PanelArgs& a, const SmallState* 
   if (!a.gate) return false;
   gbl<const SmallState>* st = G(st_);
   if (st->h.done || a.panel > st->h.stop_panel) return true;
-  return a.gate == 2 && st->h.refine != a.panel + 1;
+  if (a.gate == 2) return st->h.refine != a.panel + 1;
+  return a.gate == 3 && st->h.refine2 != a.panel + 1;
 }
 
 // ----------------------------------------------------------------------------- tails
@@ -137,6 +140,32 @@ __device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, 
   }
   __syncthreads();
   return block_chol_upper(sG, kMaxS, R, kMaxS, s, sRef, 1.0);
+}
+
+// Shifted Cholesky QR (Fukaya et al. 2020) of the explicit pass's panel: with that pass's
+// Pythagorean Gram G, Rs = Chol(G + mu I), mu = 10 pivot_tol trace(G) -- well above the
+// Gram's rounding level, so G + mu I is positive definite and (Y - Q P2) Rs^{-1} is well
+// conditioned.  Returns the failing pivot or -1.
+__device__ int tail_shifted_chol(const PanelArgs& a, const double* sred, double* Rs) {
+  const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double sG[kMaxS * kMaxS];
+  __shared__ double s_mu;
+  for (int idx = tid; idx < s * s; idx += nt) {
+    int i = idx % s, j = idx / s;
+    double v = red(a, sred, k + i, j);
+    for (int c = 0; c < k; ++c) v -= red(a, sred, c, i) * red(a, sred, c, j);
+    sG[i + j * kMaxS] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int j = 0; j < s; ++j) tr += sG[j + j * kMaxS];
+    s_mu = 10.0 * a.st->pivot_tol * tr;
+  }
+  __syncthreads();
+  for (int j = tid; j < s; j += nt) sG[j + j * kMaxS] += s_mu;
+  __syncthreads();
+  return block_chol_upper(sG, kMaxS, Rs, kMaxS, s, nullptr, 0.0);
 }
 
 // Plain Cholesky of rows r0..r0+s-1 of sred (a q^T q Gram) into R (ld kMaxS).
@@ -240,6 +269,22 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
       // second pass on the panel Y = W - Q P1: P2 = Q^T Y, R = Chol(Y^T Y - P2^T P2);
       // V_panel = Q (P1 + P2) + Q_new R
       int f = tail_pip_chol(a, sred, st->Pcur, sR, true);
+      if (f >= 0 && a.shifted) {
+        // Y is beyond Cholesky QR: the update forms Z = (Y - Q P2) Rs^{-1} with the shifted
+        // factor, and the gated pass after it orthogonalizes Z (P1 accumulates P2)
+        if (tail_shifted_chol(a, sred, st->Rs) >= 0) { tail_breakdown(a, a.kkeep); break; }
+        for (int idx = tid; idx < k * s; idx += nt) {
+          int c = idx % k, j = idx / k;
+          st->P1[c + j * kLd] += st->Pcur[c + j * kLd];
+        }
+        tail_set_tinv(st, st->Rs, s);
+        if (tid == 0) {
+          st->h.refine2 = a.panel + 1;
+          st->h.shifted += 1;
+        }
+        __syncthreads();
+        break;
+      }
       if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
       tail_set_tinv(st, sR, s);
       for (int idx = tid; idx < k * s; idx += nt) {
@@ -248,6 +293,43 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
       }
       __syncthreads();
       tail_emit_panel(a, sP, sR, false);
+    } break;
+    case TAIL_PIP_FB2: {
+      // pass on Z = (Y - Q P2) Rs^{-1}: P3 = Q^T Z, R3 = Chol(Z^T Z - P3^T P3);
+      // V_panel = Q (P1 + P2 + P3 Rs) + Q_new (R3 Rs).  A final pivot (R3 Rs)_jj^2 at most
+      // pivot_tol^2 refW_j is a column numerically in span(Q): breakdown.
+      __shared__ int s_dep;
+      int f = tail_pip_chol(a, sred, st->Pcur, sR);
+      if (f < 0) {
+        for (int idx = tid; idx < s * s; idx += nt) {
+          int i = idx % s, j = idx / s;
+          double v = 0.0;
+          for (int l = i; l <= j; ++l) v += sR[i + l * kMaxS] * st->Rs[l + j * kMaxS];
+          sR2[i + j * kMaxS] = (i <= j) ? v : 0.0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          const double tol = st->pivot_tol;
+          int dep = -1;
+          for (int j = s - 1; j >= 0; --j) {
+            const double d = sR2[j + j * kMaxS];
+            if (!(d * d > tol * tol * st->refW[j])) dep = j;
+          }
+          s_dep = dep;
+        }
+        __syncthreads();
+        f = s_dep;
+      }
+      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      tail_set_tinv(st, sR, s);
+      for (int idx = tid; idx < k * s; idx += nt) {
+        int c = idx % k, j = idx / k;
+        double v = st->P1[c + j * kLd];
+        for (int l = 0; l <= j; ++l) v += st->Pcur[c + l * kLd] * st->Rs[l + j * kMaxS];
+        sP[c + j * kLd] = v;
+      }
+      __syncthreads();
+      tail_emit_panel(a, sP, sR2, false);
     } break;
     case TAIL_G2COL: {
       for (int idx = tid; idx < (k + s) * s; idx += nt) {

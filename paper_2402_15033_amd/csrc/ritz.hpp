@@ -1,6 +1,6 @@
 // Newton basis from Leja-ordered Ritz values (Bai, Hu and Reichel's Newton-basis GMRES,
 // which the paper names as the better-conditioned alternative to the monomial basis of
-// its experiments, Sec. III and Sec. VI).
+// its experiments, Sec. IV and Sec. VI).
 //
 // From the k x k Hessenberg matrix H of a restart cycle (A Q_k = Q_{k+1} H):
 //   1. its eigenvalues (the Ritz values) by Francis's implicit double-shift QR iteration;

@@ -21,6 +21,8 @@ struct StateHead {
   int32_t refine;        // panel + 1 of the panel whose stage-1 PIP needs the explicit pass
   int32_t fallbacks;     // stage-1 panels that took the explicit second pass (all cycles)
   int32_t newton_from;   // Leja-Ritz basis: cycles completed when it took over (0: not yet)
+  int32_t refine2;       // panel + 1 of the panel whose explicit pass needs the shifted pass
+  int32_t shifted;       // stage-1 panels that took the shifted Cholesky QR pass (all cycles)
 };
 
 struct SmallState {
@@ -49,6 +51,7 @@ struct SmallState {
   double Ra[kMaxS * kMaxS];   // accumulated CholQR factor (BCGS2 + CholQR2)
   double P2[kLd * kMaxS];     // second-pass projection coefficients
   double refW[kMaxS];         // raw Gram diagonal of the panel whose PIP pass failed
+  double Rs[kMaxS * kMaxS];   // shifted Cholesky factor of that panel's explicit pass
   // two-stage with big panels (s_hat < m)
   double gscale;              // least-squares rhs: beta M(0,0) once the first big panel is final
   double Bs[kLd * kLd];       // q(:, big panel) = Y(:, :b1) Bs(:b1, big panel): [-P2 T2; T2]

@@ -401,6 +401,7 @@ struct Builder {
   Program& P;
   std::vector<ReqCtx*> R;
   int standalone = 0;
+  int shifted = 0;  // two-stage stage 1 holds the gated pass after a shifted Cholesky QR
   int elem() const { return P.f32 ? 4 : 8; }
   // bytes of the operator's index arrays read by one SpMV (CSR: row pointers and int32
   // columns; packed: slice offsets and int16 deltas / int32 columns)
@@ -442,6 +443,7 @@ struct Builder {
       x.st = q.c.st;
       x.part1 = q.c.part1;
       x.nz = nz;
+      x.shifted = shifted;
       double cols;
       if (st.kind == PK_UPDATE) {
         nb[r] = (int)cdiv(q.n, 256);
@@ -587,18 +589,21 @@ tsg_status panel_sequence(Builder& B, int ortho, int k, int sw, int nprev, bool 
   switch (ortho) {
     case TSG_ORTHO_TWO_STAGE: {
       // stage-1 BCGS-PIP; in solver mode followed by the explicit second pass, whose
-      // launches return at entry unless this panel's PIP pivot failed (gate 2)
-      const int passes = B.standalone ? 1 : 2;
+      // launches return at entry unless this panel's PIP pivot failed (gate 2), and where
+      // enabled by the pass after a shifted Cholesky QR, which runs only when the explicit
+      // pass failed too (gate 3)
+      const int passes = B.standalone ? 1 : (B.shifted ? 3 : 2);
       for (int pass = 0; pass < passes; ++pass) {
-        const int gate = pass == 0 ? 1 : 2;
-        Step g = gram_step(k, c0, sw, pass == 0 ? nprev : 0, pass == 0 ? TAIL_PIP : TAIL_PIP_FB, j, kkeep, gate);
-        if (pass == 1) g.kclass = TSG_KC_FALLBACK;
+        const int gate = pass + 1;
+        const int tail = pass == 0 ? TAIL_PIP : (pass == 1 ? TAIL_PIP_FB : TAIL_PIP_FB2);
+        Step g = gram_step(k, c0, sw, pass == 0 ? nprev : 0, tail, j, kkeep, gate);
+        if (pass >= 1) g.kclass = TSG_KC_FALLBACK;
         TRY(B.step(g));
         Step u = fuse_update ? upd_step(PK_FUSED, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE | PF_GRAM_Q | PF_GRAM_W,
                                         TAIL_G2COL, j, kkeep)
                              : upd_step(PK_UPDATE, k, c0, sw, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, j, kkeep);
         u.gate = gate;
-        if (pass == 1) u.kclass = TSG_KC_FALLBACK;
+        if (pass >= 1) u.kclass = TSG_KC_FALLBACK;
         TRY(B.step(u));
       }
     } break;
@@ -924,6 +929,13 @@ void basis_params(const tsg_csr_s* A, const tsg_solve_params* p, int sstep, doub
 
 int step_size(const tsg_solve_params* p) { return p->ortho == TSG_ORTHO_CGS2 ? 1 : p->s; }
 
+// Two-stage stage 1 holds the shifted Cholesky QR remedy for s >= 8 and in the mixed
+// form: there a numerically full-rank panel can be beyond the explicit second pass;
+// smaller FP64 steps with a scaled basis stay far from that limit.
+bool shifted_pass(const tsg_solve_params* p) {
+  return p->ortho == TSG_ORTHO_TWO_STAGE && (p->s >= 8 || p->precision == TSG_PREC_FP32_IR);
+}
+
 // Carve one request's buffers from its workspace region: reduction buffers and state,
 // the basis, and (mixed form) the FP32 copy of the values.
 void carve_request(char* base, const tsg_csr_s* A, const tsg_solve_params* p, ReqCtx& q) {
@@ -1007,6 +1019,7 @@ void fill_info(tsg_solve_info* info, const StateHead& h, tsg_status st) {
   info->truncated_cycles = h.truncated;
   info->pip_fallbacks = h.fallbacks;
   info->newton_from_cycle = h.newton_from;
+  info->shifted_passes = h.shifted;
 }
 
 tsg_status head_status(const StateHead& h) {
@@ -1043,6 +1056,7 @@ tsg_status run_solve(tsg_csr A, const tsg_solve_params* p, ReqCtx& q, char* dpro
   P.f32 = f32;
   P.nreq = 1;
   Builder B{P, {&q}, 0};
+  B.shifted = shifted_pass(p);
   TRY(build_cycle(B, m, sstep, ortho, p->s_hat));
   if (P.blob.size() > kProgramBytesPerRequest) return fail(TSG_ERR_UNSUPPORTED, "internal: launch image too large");
   HIP_TRY(hipMemcpyAsync(dprog, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, s));
@@ -1477,6 +1491,7 @@ tsg_status tsg_server_step(tsg_server S, int32_t* n_active, int32_t* n_queued) {
       S->prog.f32 = S->p.precision == TSG_PREC_FP32_IR;
       S->prog.nreq = (int)S->active.size();
       Builder B{S->prog, {}, 0};
+      B.shifted = shifted_pass(&S->p);
       for (auto* r : S->active) B.R.push_back(&r->q);
       TRY(build_cycle(B, S->p.m, step_size(&S->p), S->p.ortho, S->p.s_hat));
       std::vector<SmallState*> sts;

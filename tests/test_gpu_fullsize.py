@@ -109,3 +109,24 @@ def test_mixed_precision_convdiff2048(tsg):
     _say(f"  iters {info.iters} cycles {info.cycles} fallbacks {info.pip_fallbacks} "
          f"truncated {info.truncated_cycles} relres {relres:.3e}")
     assert info.converged and relres <= 1e-10
+
+
+@pytest.mark.parametrize("basis", ["shifted", "leja"])
+def test_mixed_precision_convdiff2048_s10(tsg, basis):
+    """The mixed-precision form at s = 10 on convection-diffusion 2048^2: the FP32 Gram of
+    the first panels is beyond the explicit second pass (kappa^2 of the panel times the
+    FP32 rounding exceeds its pivot threshold), so without the shifted Cholesky QR pass the
+    first cycle breaks down and the solve makes no progress; with it the solve converges
+    to the FP64 residual gate."""
+    _say("case fullsize mixed convdiff s10", basis)
+    pr = W.make_problem("convdiff2d", 2048, seed=0)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    b = torch.as_tensor(pr["b"], device="cuda")
+    x, info = tsg.solve(A, b, m=60, s=10, tol=1e-10, basis=basis, precision="fp32_ir")
+    xg = x.cpu().numpy()
+    relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], xg)) / np.linalg.norm(pr["b"])
+    _say(f"  iters {info.iters} cycles {info.cycles} fallbacks {info.pip_fallbacks} shifted "
+         f"{info.shifted_passes} truncated {info.truncated_cycles} newton from {info.newton_from_cycle} "
+         f"relres {relres:.3e}")
+    assert info.converged and relres <= 1e-10
+    assert info.shifted_passes > 0

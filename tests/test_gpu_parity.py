@@ -359,3 +359,27 @@ def test_mixed_precision_refinement(tsg, kind, N, basis):
     else:
         assert err <= 1e-6
     _say(f"  mixed {kind}: iters {info.iters} (fp64 oracle {ref['iters']}), |x - x_fp64| = {err:.2e}")
+
+
+@pytest.mark.parametrize("kind,N,s", [("laplace2d", 40, 12), ("laplace2d", 64, 15), ("convdiff2d", 40, 15)])
+def test_solve_monomial_shifted_cholqr_pass(tsg, kind, N, s):
+    """Monomial panels at s >= 12 are beyond the explicit second pass; both sides take the
+    shifted Cholesky QR pass and converge.  Which panels take it is decided by pivots near
+    the threshold (as for the explicit pass), so the gates are the explicit residual and
+    ||x_gpu - x_oracle|| <= 2 tol kappa(A) ||x_oracle||."""
+    _say("case solve monomial shifted pass", kind, N, s)
+    pr = W.make_problem(kind, N, seed=0)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=60, s=s, tol=1e-10)
+    ref = G.sstep_gmres(pr["A"], pr["b"], m=60, s=s, tol=1e-10)
+    xg = x.cpu().numpy()
+    _say(f"  iters gpu {info.iters} oracle {ref['iters']}; shifted gpu {info.shifted_passes} oracle {ref['shifted']}")
+    relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], xg)) / np.linalg.norm(pr["b"])
+    assert info.converged and relres <= 1e-10
+    assert info.shifted_passes > 0 and ref["shifted"] > 0
+    if kind == "laplace2d":
+        lmin, lmax = W.laplace_extreme_eigs(N, 2)
+        kap = lmax / lmin
+    else:
+        kap = np.linalg.cond(G.dense_solve(pr["A"], pr["b"])[1])
+    assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 2 * 1e-10 * kap
