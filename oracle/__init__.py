@@ -20,10 +20,12 @@ Layout:
                    two-stage block orthogonalization of a tall-skinny block
   gmres.py      -- standard GMRES(m) with MGS or CGS2, and s-step GMRES(m)
                    with one-stage (BCGS2+CholQR2, BCGS-PIP2) or two-stage
-                   block orthogonalization
+                   block orthogonalization, optionally right-preconditioned
+  ritz.py       -- Newton basis from Leja-ordered Ritz values
+  precond.py    -- multicolor Gauss-Seidel preconditioner
 
 Every routine is pinned by tests under ``tests/`` (``-m "not gpu"``) against
 closed forms, library routines (LAPACK via numpy) and invariants the paper
 states; pins are listed in each routine's docstring.
 """
-from . import dense, sparse, blockortho, gmres  # noqa: F401
+from . import dense, sparse, blockortho, gmres, ritz, precond  # noqa: F401

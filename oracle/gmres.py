@@ -53,6 +53,7 @@ from .dense import (PIVOT_TOL, CholeskyBreakdown, GivensState, chol_upper, given
                     right_solve_upper, solve_upper)
 from .sparse import Operator, basis_params, gershgorin, spmv
 from . import blockortho, ritz
+from . import precond as precond_mod
 
 
 # Two-stage stage 1 takes the shifted Cholesky QR pass (``blockortho.bcgs_pip_explicit``)
@@ -99,8 +100,10 @@ def _outer(A, b, x0, tol, max_iters, cycle_fn, record):
 
 
 def gmres(A, b, x0=None, m: int = 60, tol: float = 1e-10, max_iters: int = 10**9,
-          ortho: str = "mgs", record: bool = False):
-    """Standard restarted GMRES(m) with MGS or CGS2 Arnoldi."""
+          ortho: str = "mgs", record: bool = False, precond=None):
+    """Standard restarted GMRES(m) with MGS or CGS2 Arnoldi; precond: an object with
+    apply(w) = M^{-1} w for right preconditioning (Arnoldi on A M^{-1}, x += M^{-1} Q y)."""
+    prec = precond.apply if precond is not None else None
 
     def cycle(op, r, beta, tol_abs):
         n = op.n
@@ -110,7 +113,7 @@ def gmres(A, b, x0=None, m: int = 60, tol: float = 1e-10, max_iters: int = 10**9
         giv = GivensState(beta, m)
         k_used = m
         for j in range(m):
-            w = spmv(op, Q[:, j])
+            w = spmv(op, Q[:, j] if prec is None else prec(Q[:, j]))
             h = np.zeros(j + 2)
             if ortho == "mgs":
                 for i in range(j + 1):
@@ -137,18 +140,20 @@ def gmres(A, b, x0=None, m: int = 60, tol: float = 1e-10, max_iters: int = 10**9
                 break
         y = giv.solve(k_used)
         rec = {"Q": Q[:, : k_used + 1], "H": H[: k_used + 1, :k_used]} if record else None
-        return Q[:, :k_used] @ y, k_used, giv.residual(), rec
+        dx = Q[:, :k_used] @ y
+        return (dx if prec is None else prec(dx)), k_used, giv.residual(), rec
 
     return _outer(A, b, x0, tol, max_iters, cycle, record)
 
 
-def mpk(op, w0: np.ndarray, theta: np.ndarray, sigma: np.ndarray, tau=None):
+def mpk(op, w0: np.ndarray, theta: np.ndarray, sigma: np.ndarray, tau=None, prec=None):
     """Matrix-powers kernel: s SpMVs in sequence (Sec. III).  Returns (W, B).
 
     Step i: w_{i+1} = (A w_i - theta_i w_i + tau_i w_{i-1}) / sigma_i (tau = 0 except at
     the second step of a complex pair of the Newton basis), so
     A w_i = sigma_i w_{i+1} + theta_i w_i - tau_i w_{i-1}: B(i+1,i) = sigma_i,
-    B(i,i) = theta_i, B(i-1,i) = -tau_i.
+    B(i,i) = theta_i, B(i-1,i) = -tau_i.  With a right preconditioner (prec(w) = M^{-1} w)
+    the product is A M^{-1} w_i.
     """
     s = len(theta)
     tau = np.zeros(s) if tau is None else np.asarray(tau, dtype=np.float64)
@@ -156,7 +161,7 @@ def mpk(op, w0: np.ndarray, theta: np.ndarray, sigma: np.ndarray, tau=None):
     B = np.zeros((s + 1, s))
     prev, w = None, w0
     for i in range(s):
-        nxt = spmv(op, w) - theta[i] * w
+        nxt = spmv(op, w if prec is None else prec(w)) - theta[i] * w
         if tau[i] != 0.0:
             nxt = nxt + tau[i] * prev
             B[i - 1, i] = -tau[i]
@@ -172,10 +177,11 @@ class _Basis:
     at least s columns runs with the shifted basis; its Ritz values then give the Newton
     basis of every later cycle (``ritz.leja_ritz_params``)."""
 
-    def __init__(self, op, s, basis, shifts):
+    def __init__(self, op, s, basis, shifts, prec=None):
         self.s = s
-        self.lo, self.hi = gershgorin(op)
-        self.theta, self.sigma = basis_params(op, s, "shifted" if basis == "leja" else basis, shifts)
+        self.lo, self.hi = gershgorin(op) if prec is None else precond_mod.PRECOND_INTERVAL
+        self.theta, self.sigma = basis_params(op, s, "shifted" if basis == "leja" else basis, shifts,
+                                              interval=(self.lo, self.hi))
         self.tau = np.zeros(s)
         self.pending = basis == "leja"
         self.switched_after = None
@@ -208,7 +214,7 @@ def hessenberg_block(Hh: np.ndarray, P: np.ndarray, R: np.ndarray, B: np.ndarray
 def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
                 max_iters: int = 10**9, ortho: str = "two_stage",
                 basis: str = "monomial", shifts=None, record: bool = False, s_hat: int | None = None,
-                shifted: bool | None = None):
+                shifted: bool | None = None, precond=None):
     """s-step GMRES(m) with one-stage or two-stage block orthogonalization.
 
     Two-stage with s_hat = m (default): stage 2 is one CholQR of the m+1 columns at the end
@@ -221,9 +227,11 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
     if ortho == "two_stage" and s_hat is not None and s_hat < m:
         if s_hat % s != 0 or m % s_hat != 0:
             raise ValueError("need s | s_hat | m")
-        return _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record, shifted)
+        return _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record, shifted,
+                                 precond)
     op = A if isinstance(A, Operator) else Operator(A)
-    bp = _Basis(op, s, basis, shifts)
+    prec = precond.apply if precond is not None else None
+    bp = _Basis(op, s, basis, shifts, prec)
     J = m // s
     one_stage = None if ortho == "two_stage" else blockortho.ONE_STAGE[ortho]
     stats = {"fallbacks": 0, "shifted": 0, "cycles": 0}  # panels that took the second / shifted pass
@@ -240,7 +248,7 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
         breakdown = None
         for j in range(J):
             k = j * s + 1
-            W, B = mpk(op, Qh[:, k - 1], bp.theta, bp.sigma, bp.tau)
+            W, B = mpk(op, Qh[:, k - 1], bp.theta, bp.sigma, bp.tau, prec)
             try:
                 if one_stage is None:  # stage 1 (second pass only where PIP fails)
                     Qn, P, R, fb = blockortho.bcgs_pip_explicit(Qh[:, :k], W, PIVOT_TOL, use_shift)
@@ -285,6 +293,8 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
             y, est = givens_lsq(H, beta * R2[0, 0])
             z = solve_upper(R2[:k_used, :k_used], y)
             dx = Qh[:, :k_used] @ z
+            if prec is not None:
+                dx = prec(dx)
             if record:
                 rec = {"Qhat": Qh[:, :kb], "Hhat": Hh[:kb, :k_used], "R2": R2, "H": H, "y": y,
                        "z": z, "panels": panels, "beta": beta, "breakdown": breakdown}
@@ -295,7 +305,8 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
         if record:
             rec = {"Q": Qh[:, : k_used + 1], "H": Hh[: k_used + 1, :k_used], "y": y,
                    "panels": panels, "beta": beta, "breakdown": breakdown}
-        return Qh[:, :k_used] @ y, k_used, abs(giv.g[k_used]), rec
+        dx = Qh[:, :k_used] @ y
+        return (dx if prec is None else prec(dx)), k_used, abs(giv.g[k_used]), rec
 
     out = _outer(op, b, x0, tol, max_iters, cycle, record)
     bp.export(out)
@@ -304,7 +315,8 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
     return out
 
 
-def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record, shifted=None):
+def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, record, shifted=None,
+                      precond=None):
     """Two-stage s-step GMRES(m) with big panels of s_hat < m columns.
 
     Within a cycle the basis Y holds final (orthonormal) columns for the completed big
@@ -323,7 +335,8 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
     cycle with the columns of its completed big panels.
     """
     op = A if isinstance(A, Operator) else Operator(A)
-    bp = _Basis(op, s, basis, shifts)
+    prec = precond.apply if precond is not None else None
+    bp = _Basis(op, s, basis, shifts, prec)
     J = m // s
     bigs = blockortho.big_panel_bounds(m + 1, s, s_hat)
     stats = {"fallbacks": 0, "shifted": 0, "cycles": 0}
@@ -367,7 +380,7 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
         est = beta
         for j in range(J):
             k = j * s + 1
-            W, B = mpk(op, Y[:, k - 1], bp.theta, bp.sigma, bp.tau)
+            W, B = mpk(op, Y[:, k - 1], bp.theta, bp.sigma, bp.tau, prec)
             try:
                 Qn, P, R, fb = blockortho.bcgs_pip_explicit(Y[:, :k], W, PIVOT_TOL, use_shift)
                 stats["fallbacks"] += int(fb >= 1)
@@ -403,6 +416,8 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
         stats["cycles"] += 1
         bp.cycle_done(H[:k_used, :k_used], stats["cycles"])
         dx = Y[:, :k_used] @ y
+        if prec is not None:
+            dx = prec(dx)
         rec = None
         if record:
             rec = {"Q": Y[:, : k_used + 1].copy(), "H": H[: k_used + 1, :k_used].copy(), "y": y,

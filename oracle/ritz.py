@@ -2,7 +2,7 @@
 
 The paper runs its experiments with the monomial basis and names Newton and
 Chebyshev bases (Bai, Hu and Reichel 1994) as the better-conditioned choice for
-larger s (Sec. III and Sec. VI).  This module states the Newton basis the way that
+larger s (Sec. IV and Sec. VI).  This module states the Newton basis the way that
 reference builds it, in plain FP64:
 
 * ``ritz_values``    -- eigenvalues of the square k x k Hessenberg matrix of one

@@ -57,14 +57,15 @@ def gershgorin(A):
     return float(np.min(diag - rad)), float(np.max(diag + rad))
 
 
-def basis_params(A, s: int, basis: str = "monomial", shifts=None):
+def basis_params(A, s: int, basis: str = "monomial", shifts=None, interval=None):
     """Per-step shift theta_i and scale sigma_i of the s-step basis.
 
     The basis is built as w_i = (A w_{i-1} - theta_i w_{i-1}) / sigma_i.
     monomial: theta = 0, sigma = max(|lo|, |hi|);  shifted: theta = (lo+hi)/2,
     sigma = (hi-lo)/2;  newton: theta = given shifts, sigma = (hi-lo)/2.
+    [lo, hi]: the Gershgorin interval of A, or the given interval (preconditioned operator).
     """
-    lo, hi = gershgorin(A)
+    lo, hi = gershgorin(A) if interval is None else interval
     if basis == "monomial":
         theta = np.zeros(s)
         sigma = np.full(s, max(abs(lo), abs(hi)))
