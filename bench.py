@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--N", type=int, default=None,
                     help="grid side (default 2048 in 2D, 160 in 3D)")
     ap.add_argument("--basis", default="monomial", choices=["monomial", "shifted", "leja"])
+    ap.add_argument("--precond", default="none", choices=["none", "mcgs"],
+                    help="right preconditioning: multicolor Gauss-Seidel (the workload of Fig. 13)")
     ap.add_argument("--s-hat", type=int, default=0, help="two-stage big-panel size (0 = m)")
     ap.add_argument("--shat-sweep", action="store_true",
                     help="also time one solve for each s_hat in {s, 2s, 4s, 6s, m} (Table 2's knob)")
@@ -140,12 +142,16 @@ def main():
         desc += f" (Pe={pr['meta']['pe']:.2f}, theta={pr['meta']['theta']:.3f})"
     Ah = pr["A"]
     A = tsg.CSRMatrix.from_host(Ah, device=dev)
+    precond = None if args.precond == "none" else args.precond
+    if precond:
+        A.precond_setup()
+        desc += f", multicolor Gauss-Seidel ({A.ncolors} colors)"
     b = torch.as_tensor(pr["b"], device=dev)
     x = torch.zeros_like(b)
     kw = dict(m=args.m, s=args.s, tol=args.tol, ortho=args.ortho, precision=args.precision,
-              basis=args.basis, graph=not args.eager, s_hat=args.s_hat)
+              basis=args.basis, graph=not args.eager, s_hat=args.s_hat, precond=precond)
     need = tsg.binding.solve_workspace_bytes(A, m=args.m, s=args.s, ortho=args.ortho,
-                                             precision=args.precision, s_hat=args.s_hat)
+                                             precision=args.precision, s_hat=args.s_hat, precond=precond)
     ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
     off = (-ws.data_ptr()) % 256
     ws = ws[off:]
@@ -240,6 +246,7 @@ def main():
                    "problem": args.problem, "N": N,
                    "n": Ah.n, "nnz": Ah.nnz, "m": args.m, "s": args.s, "ortho": args.ortho,
                    "basis": args.basis, "precision": args.precision, "tol": args.tol,
+                   "precond": args.precond,
                    "s_hat": args.s_hat or args.m},
         "time_to_solution_s": round(elapsed / args.steps, 4),
         "iters": int(info.iters), "cycles": int(info.cycles),
@@ -297,7 +304,8 @@ def main():
             torch.cuda.synchronize()
             t = time.perf_counter()
             _, ci = tsg.solve(A, b, x, workspace=None, timing=True, m=args.m, s=args.s, tol=args.tol,
-                              ortho=o, precision=args.precision, basis=args.basis, graph=not args.eager)
+                              ortho=o, precision=args.precision, basis=args.basis, graph=not args.eager,
+                              precond=precond)
             torch.cuda.synchronize()
             t = time.perf_counter() - t
             cmp[o] = {"time_to_solution_s": round(t, 4), "iters": int(ci.iters), "relres": ci.relres,
@@ -337,6 +345,7 @@ def main():
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle: {args.cpu_cycles} restart cycle(s) of the same solve")
         from oracle import gmres as G
+        from oracle import precond as PC
         from oracle import sparse as S
         try:
             from threadpoolctl import threadpool_info
@@ -347,7 +356,8 @@ def main():
         t = time.perf_counter()
         ref = G.sstep_gmres(op, pr["b"], m=args.m, s=args.s, tol=args.tol, ortho=args.ortho
                             if args.ortho != "cgs2" else "two_stage", basis=args.basis,
-                            max_iters=args.cpu_cycles * args.m)
+                            max_iters=args.cpu_cycles * args.m,
+                            precond=PC.MulticolorGS(Ah) if precond else None)
         t = time.perf_counter() - t
         t_cycle = t / max(ref["cycles"], 1)
         cpu_solves_per_s = 1.0 / (t_cycle * max(info.cycles, 1))

@@ -104,7 +104,18 @@ typedef struct {
                            (cycles 0, t, 2t, ...) with HIP events; timed cycles are
                            launched directly even in graph mode                         */
   int32_t flags;        /* TSG_FLAG_* bits, 0 by default                                */
+  int32_t precond;      /* tsg_precond: right preconditioning (FP64 only)               */
 } tsg_solve_params;
+
+/* Right preconditioning (the paper's last experiment, Sec. VI, Fig. 13, runs s-step GMRES
+ * with a local Gauss-Seidel preconditioner swept by colors on the GPU).  GMRES runs on
+ * A M^{-1}: every matrix-powers step applies z = M^{-1} w then A z, the cycle update is
+ * x += M^{-1} (Q y), and the residual stays the true one.
+ *   NONE  no preconditioner
+ *   MCGS  M = D + L_c, one forward multicolor Gauss-Seidel sweep from z = 0 (colors from
+ *         tsg_csr_precond); the basis interval [lo, hi] becomes [0, 2] (the eigenvalues
+ *         of A M^{-1} lie in |z - 1| < 1 for a convergent Gauss-Seidel splitting) */
+typedef enum { TSG_PRECOND_NONE = 0, TSG_PRECOND_MCGS = 1 } tsg_precond;
 
 /* tsg_solve_params.flags.  By default the launches of one restart cycle (they are the
  * same in every cycle) are captured once per solve into a HIP graph on a private
@@ -131,7 +142,8 @@ enum {
   TSG_KC_FALLBACK = 10,  /* two-stage explicit second pass (its launches return at entry
                             unless a panel needs it; no bytes are attributed)            */
   TSG_KC_STAGE2 = 11,    /* two-stage with s_hat < m: big-panel stage 2 (tail, explicit Q) */
-  TSG_KC_COUNT = 12
+  TSG_KC_PRECOND = 12,   /* multicolor Gauss-Seidel sweeps of right preconditioning       */
+  TSG_KC_COUNT = 13
 };
 
 typedef struct {
@@ -187,6 +199,29 @@ tsg_status tsg_csr_gershgorin(tsg_csr A, double* lo, double* hi);
  * products in CSR order, rounded as the CSR kernel rounds them: results are identical. */
 size_t tsg_csr_pack_bytes(tsg_csr A);
 tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream);
+
+/* Multicolor Gauss-Seidel set-up for TSG_PRECOND_MCGS: a distance-1 coloring of the
+ * pattern by Jones and Plassmann's parallel rounds (priority of row i = output i of the
+ * SplitMix64 generator seeded with 0, ties to the higher index; equal to the greedy
+ * coloring in decreasing priority), then the rows grouped by color (counting sort of the
+ * device-computed colors on the host).  The pattern must be structurally symmetric
+ * (a_ij stored iff a_ji stored) and every row must store its diagonal, which must be
+ * nonzero.  tsg_csr_precond_bytes: device bytes needed.  tsg_csr_precond fills buf
+ * (device, 256-byte aligned, caller-owned, must stay valid while the handle uses it) and
+ * synchronizes `stream`; from then on solves with precond = MCGS may use A.
+ * Errors: INVALID_ARG (NULL handle or buffer, too small); UNSUPPORTED when the rounds do
+ * not finish within n rounds; HIP. */
+size_t tsg_csr_precond_bytes(tsg_csr A);
+tsg_status tsg_csr_precond(tsg_csr A, void* buf, size_t bytes, void* stream);
+/* Number of colors of the preconditioner set-up (0 before tsg_csr_precond). */
+int32_t tsg_csr_ncolors(tsg_csr A);
+/* Copy the n row colors (int32) to colors (device, caller-owned); INVALID_ARG before
+ * tsg_csr_precond. */
+tsg_status tsg_csr_colors(tsg_csr A, int32_t* colors, void* stream);
+
+/* z = M^{-1} w for the handle's multicolor Gauss-Seidel preconditioner (device vectors of
+ * n doubles; z must not alias w).  The sweep of the solver's matrix-powers steps. */
+tsg_status tsg_precond_apply(tsg_csr A, const double* w, double* z, void* stream);
 
 /* Newton-basis parameters of TSG_BASIS_LEJA for a given k x k upper Hessenberg matrix
  * H (device, column-major, leading dimension ldh >= k; entries below the subdiagonal are

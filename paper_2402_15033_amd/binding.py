@@ -33,7 +33,7 @@ class _Params(C.Structure):
     _fields_ = [("m", C.c_int32), ("s", C.c_int32), ("s_hat", C.c_int32), ("ortho", C.c_int32),
                 ("basis", C.c_int32), ("precision", C.c_int32), ("tol", C.c_double),
                 ("max_iters", C.c_int64), ("newton_shifts", C.POINTER(C.c_double)),
-                ("timing", C.c_int32), ("flags", C.c_int32)]
+                ("timing", C.c_int32), ("flags", C.c_int32), ("precond", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -51,7 +51,8 @@ class _Info(C.Structure):
 
 
 KERNEL_CLASSES = ["mpk", "gram", "gram_first", "update", "fused", "tail", "cycle_end", "xupdate",
-                  "residual", "scale", "fallback", "stage2"]
+                  "residual", "scale", "fallback", "stage2", "precond"]
+PRECOND = {None: 0, "none": 0, "mcgs": 1}
 
 
 @dataclass
@@ -143,6 +144,16 @@ def load_library():
     lib.tsg_server_step.restype = C.c_int
     lib.tsg_server_poll.argtypes = [vp, C.POINTER(i64), C.POINTER(_Info), i32]
     lib.tsg_server_poll.restype = i32
+    lib.tsg_csr_precond_bytes.argtypes = [vp]
+    lib.tsg_csr_precond_bytes.restype = C.c_size_t
+    lib.tsg_csr_precond.argtypes = [vp, vp, C.c_size_t, vp]
+    lib.tsg_csr_precond.restype = C.c_int
+    lib.tsg_csr_ncolors.argtypes = [vp]
+    lib.tsg_csr_ncolors.restype = i32
+    lib.tsg_csr_colors.argtypes = [vp, vp, vp]
+    lib.tsg_csr_colors.restype = C.c_int
+    lib.tsg_precond_apply.argtypes = [vp, vp, vp, vp]
+    lib.tsg_precond_apply.restype = C.c_int
     lib.tsg_ritz_newton.argtypes = [vp, i64, i32, i32, C.c_double, C.c_double, vp, vp]
     lib.tsg_ritz_newton.restype = C.c_int
     lib.tsg_status_string.argtypes = [C.c_int]
@@ -206,6 +217,7 @@ class CSRMatrix:
                                   self.val.data_ptr(), _stream(self.device), C.byref(h)))
         self._h = h
         self._pack = None
+        self._precond = None
         if pack:
             self.pack()
 
@@ -223,6 +235,27 @@ class CSRMatrix:
         _check(load_library().tsg_csr_pack(self._h, None, 0, _stream(self.device)))
         self._pack = None
         return self
+
+    def precond_setup(self):
+        """Color the operator for the multicolor Gauss-Seidel preconditioner (precond='mcgs');
+        the device buffer is owned by this object."""
+        lib = load_library()
+        nbytes = int(lib.tsg_csr_precond_bytes(self._h))
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        p = (buf.data_ptr() + 255) // 256 * 256
+        _check(lib.tsg_csr_precond(self._h, p, nbytes, _stream(self.device)))
+        self._precond = buf
+        return self
+
+    @property
+    def ncolors(self) -> int:
+        return int(load_library().tsg_csr_ncolors(self._h))
+
+    def colors(self) -> torch.Tensor:
+        """The row colors of the preconditioner set-up (int32 device tensor)."""
+        c = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _check(load_library().tsg_csr_colors(self._h, c.data_ptr(), _stream(self.device)))
+        return c
 
     @classmethod
     def from_host(cls, A, device="cuda", pack: bool = True):
@@ -280,7 +313,16 @@ def ritz_newton(H: torch.Tensor, s: int, lo: float, hi: float):
             "sigma": out[2 * k + 2 * s:2 * k + 3 * s]}
 
 
-def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph=True, s_hat=0):
+def precond_apply(A: CSRMatrix, w: torch.Tensor, z: torch.Tensor | None = None) -> torch.Tensor:
+    """z = M^{-1} w for A's multicolor Gauss-Seidel preconditioner (A.precond_setup() first)."""
+    _dev_tensor(w, torch.float64, "w")
+    if z is None:
+        z = torch.empty_like(w)
+    _check(load_library().tsg_precond_apply(A.handle, w.data_ptr(), z.data_ptr(), _stream(w.device)))
+    return z
+
+
+def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph=True, s_hat=0, precond=None):
     p = _Params()
     p.m, p.s, p.s_hat = int(m), int(s), int(s_hat or 0)
     p.ortho = ORTHO[ortho] if isinstance(ortho, str) else int(ortho)
@@ -294,30 +336,32 @@ def _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph
         p.newton_shifts = C.cast(keep, C.POINTER(C.c_double))
     p.timing = int(timing)  # False/True -> 0/1; an int t > 1 times every t-th cycle
     p.flags = 0 if graph else FLAG_EAGER
+    p.precond = PRECOND[precond] if (precond is None or isinstance(precond, str)) else int(precond)
     return p, keep
 
 
 def solve_workspace_bytes(A: CSRMatrix, m=60, s=5, ortho="two_stage", basis="monomial",
-                          precision="fp64", s_hat=0) -> int:
-    p, _ = _params(m, s, ortho, basis, precision, 1e-10, 1 << 40, None, False, s_hat=s_hat)
+                          precision="fp64", s_hat=0, precond=None) -> int:
+    p, _ = _params(m, s, ortho, basis, precision, 1e-10, 1 << 40, None, False, s_hat=s_hat, precond=precond)
     return int(load_library().tsg_solve_workspace_bytes(A.n, A.nnz, C.byref(p)))
 
 
 def solve(A: CSRMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, m: int = 60, s: int = 5,
           tol: float = 1e-10, max_iters: int = 1 << 40, ortho: str = "two_stage",
           basis: str = "monomial", precision: str = "fp64", shifts=None, timing: bool = False,
-          graph: bool = True, s_hat: int = 0, workspace: torch.Tensor | None = None):
+          graph: bool = True, s_hat: int = 0, workspace: torch.Tensor | None = None, precond=None):
     """Solve A x = b (x updated in place; zeros if None).  Returns (x, SolveInfo).
 
     graph=False launches every kernel directly instead of replaying one captured restart
     cycle per cycle (same results, bit for bit).  s_hat (two-stage): 0 or m for one big
-    panel per cycle, else the big-panel size (s | s_hat | m)."""
+    panel per cycle, else the big-panel size (s | s_hat | m).  precond='mcgs': right
+    preconditioning by multicolor Gauss-Seidel (A.precond_setup() first; FP64)."""
     lib = load_library()
     _dev_tensor(b, torch.float64, "b")
     if x is None:
         x = torch.zeros_like(b)
     _dev_tensor(x, torch.float64, "x")
-    p, keep = _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph, s_hat)
+    p, keep = _params(m, s, ortho, basis, precision, tol, max_iters, shifts, timing, graph, s_hat, precond)
     need = int(lib.tsg_solve_workspace_bytes(A.n, A.nnz, C.byref(p)))
     if need == 0:
         _check(-1)

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "panel.hpp"
+#include "precond.hpp"
 #include "ritz.hpp"
 
 namespace tsg {
@@ -166,6 +167,8 @@ struct MpkArgs {
   const void* x;           // T[n]
   void* y;                 // T[n]
   const void* xm;          // T[n], the vector before x (NULL at a panel's first step)
+  const void* xs;          // T[n], the vector the shift applies to: x, or (right
+                           // preconditioning) the basis vector w with x = M^{-1} w
   int64_t n;
   const SmallState* st;
   int32_t step;            // index of the step in the panel (0 .. s-1)
@@ -199,7 +202,7 @@ struct MpkBody {
     const double theta = st->theta[a.step], sigma = st->sigma[a.step], tau = st->tau[a.step];
     if (r < n) {
       T v = acc;
-      if (theta != 0.0) v -= (T)theta * x[r];
+      if (theta != 0.0) v -= (T)theta * G(reinterpret_cast<const T*>(a.xs))[r];
       if (tau != 0.0 && a.xm) v += (T)tau * G(reinterpret_cast<const T*>(a.xm))[r];
       y[r] = v / (T)sigma;
     }
@@ -434,6 +437,7 @@ struct XupdArgs {
   const void* V;  // T basis
   int64_t ld, n;
   const SmallState* st;
+  double* t;      // non-NULL (right preconditioning): t = V coef instead of x += V coef
 };
 template <typename T>
 struct XupdBody {
@@ -450,7 +454,8 @@ struct XupdBody {
     if (r >= a.n) return;
     double acc = 0.0;
     for (int c = 0; c < ku; ++c) acc += (double)V[(int64_t)c * a.ld + r] * st->coef[c];
-    x[r] += acc;
+    if (a.t) G(a.t)[r] = acc;
+    else x[r] += acc;
   }
 };
 

@@ -36,6 +36,11 @@ struct tsg_csr_s {
   const float* v32 = nullptr;
   const void* scol = nullptr;
   int packed = 0;
+  // multicolor Gauss-Seidel (tsg_csr_precond): row colors and the rows in color order
+  int ncolors = 0;
+  const int32_t* colors = nullptr;
+  const int32_t* cperm = nullptr;
+  std::vector<int64_t> coff_host;  // color c holds cperm[coff[c] .. coff[c+1])
 };
 
 namespace {
@@ -212,7 +217,8 @@ static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks, "reduction partial buffer too 
 constexpr size_t kProgramBytesPerRequest = 512 * 1024;
 
 enum Family : int {
-  F_RESID, F_RTAIL, F_UPDATE, F_MPK, F_GRAM, F_PREDUCE, F_PTAIL, F_FUSED, F_CYCLE_END, F_XUPD, F_S2, F_RITZ
+  F_RESID, F_RTAIL, F_UPDATE, F_MPK, F_GRAM, F_PREDUCE, F_PTAIL, F_FUSED, F_CYCLE_END, F_XUPD, F_S2, F_RITZ,
+  F_GS0, F_GSC, F_AXPY
 };
 
 struct Phase {
@@ -284,6 +290,9 @@ void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
     case F_CYCLE_END: launch_b<CycleEndBody>(ph, d, nreq, s); break;
     case F_S2: launch_b<Stage2Body>(ph, d, nreq, s); break;
     case F_RITZ: launch_b<RitzBody>(ph, d, nreq, s); break;
+    case F_GS0: launch_b<GsFirstBody>(ph, d, nreq, s); break;
+    case F_GSC: launch_b<GsColorBody>(ph, d, nreq, s); break;
+    case F_AXPY: launch_b<AxpyBody>(ph, d, nreq, s); break;
     case F_XUPD: launch_b<XupdBody<T>>(ph, d, nreq, s); break;
     case F_UPDATE:
       switch (ph.t1) {
@@ -354,6 +363,11 @@ struct ReqCtx {
   Common c{};
   double theta[kMaxS] = {0}, sigma[kMaxS] = {0};
   bool leja = false;             // Newton shifts from the Ritz values of a cycle
+  // right preconditioning by multicolor Gauss-Seidel (NULL colors: none)
+  const tsg_csr_s* A = nullptr;
+  const int32_t* colors = nullptr;
+  double* zp = nullptr;          // M^{-1} w of the current step; M^{-1} t of the cycle update
+  double* tp = nullptr;          // V coef of the cycle update
 };
 
 enum PanelKind { PK_GRAM, PK_UPDATE, PK_FUSED };
@@ -518,8 +532,55 @@ struct Builder {
     for (ReqCtx* q : R) t.push_back(TailArgs{q->c.st, q->c.part1, (int)cdiv(q->n, kRowBlock), 0});
     P.add(F_RTAIL, 0, 0, t, one, -1, 0.0);
   }
+  // z = M^{-1} w (one multicolor Gauss-Seidel sweep) for the preconditioned requests:
+  // w(q), z(q) give each request's vectors; panel gates as the matrix-powers steps do
+  template <typename FW, typename FZ>
+  void gs(FW w_of, FZ z_of, int panel) {
+    bool any = false;
+    int maxc = 0;
+    for (ReqCtx* q : R)
+      if (q->colors) {
+        any = true;
+        maxc = std::max(maxc, q->A->ncolors);
+      }
+    if (!any) return;
+    {
+      std::vector<GsArgs> a;
+      std::vector<int> nb;
+      double bytes = 0.0;
+      for (ReqCtx* q : R) {
+        const bool on = q->colors != nullptr;
+        a.push_back(on ? GsArgs{q->A->row_ptr, q->A->col, q->A->val, q->colors, nullptr, w_of(q), z_of(q), q->n,
+                                q->c.st, panel, 0}
+                       : GsArgs{});
+        nb.push_back(on ? (int)cdiv(q->n, 256) : 0);
+        if (on) bytes += 4.0 * q->n + 16.0 * q->n;
+      }
+      P.add(F_GS0, 0, 0, a, nb, TSG_KC_PRECOND, bytes);
+    }
+    for (int c = 1; c < maxc; ++c) {
+      std::vector<GsArgs> a;
+      std::vector<int> nb;
+      double bytes = 0.0;
+      for (ReqCtx* q : R) {
+        const bool on = q->colors != nullptr && c < q->A->ncolors;
+        const int64_t r0 = on ? q->A->coff_host[c] : 0, cnt = on ? q->A->coff_host[c + 1] - r0 : 0;
+        a.push_back(on ? GsArgs{q->A->row_ptr, q->A->col, q->A->val, nullptr, q->A->cperm + r0, w_of(q), z_of(q),
+                                cnt, q->c.st, panel, 0}
+                       : GsArgs{});
+        nb.push_back(on ? (int)cdiv(cnt, 256) : 0);
+        // this color's rows: index, row pointers, their CSR entries, w, z gathers and z
+        if (on) bytes += (double)cnt * (4.0 + 8.0 + 8.0 + 8.0) + (double)q->A->nnz * 20.0 * cnt / q->n;
+      }
+      P.add(F_GSC, 0, 0, a, nb, TSG_KC_PRECOND, bytes);
+    }
+  }
   // w_{i+1} = (A w_i - theta_i w_i + tau_i w_{i-1}) / sigma_i into column col_out
+  // (preconditioned: A M^{-1} w_i, the sweep into zp first)
   void mpk(int col_in, int col_out, int i, int panel) {
+    auto colp = [&](ReqCtx* q, int c) { return static_cast<char*>(q->V) + (size_t)c * q->ld * elem(); };
+    gs([&](ReqCtx* q) { return reinterpret_cast<const double*>(colp(q, col_in)); }, [](ReqCtx* q) { return q->zp; },
+       panel);
     for (int fmt = FMT_CSR; fmt <= FMT_SELL32; ++fmt) {
       std::vector<MpkArgs> a;
       std::vector<int> nb;
@@ -527,9 +588,11 @@ struct Builder {
       for (ReqCtx* q : R) {
         const bool mine = q->fmt == fmt;
         char* V = static_cast<char*>(q->V);
-        a.push_back(MpkArgs{q->row_ptr, q->col, q->valT, V + (size_t)col_in * q->ld * elem(),
+        const void* win = V + (size_t)col_in * q->ld * elem();
+        a.push_back(MpkArgs{q->row_ptr, q->col, q->valT, q->colors ? (const void*)q->zp : win,
                             V + (size_t)col_out * q->ld * elem(),
-                            i > 0 ? V + (size_t)(col_in - 1) * q->ld * elem() : nullptr, q->n, q->c.st, i, panel});
+                            i > 0 ? V + (size_t)(col_in - 1) * q->ld * elem() : nullptr, win, q->n, q->c.st, i,
+                            panel});
         nb.push_back(mine ? (int)cdiv(q->n, kRowBlock) : 0);
         if (mine) bytes += index_bytes(*q) + (double)q->nnz * elem() + 2.0 * q->n * elem();
       }
@@ -565,16 +628,30 @@ struct Builder {
     // Newton shifts from this cycle's Ritz values (returns at entry unless pending)
     if (leja) P.add(F_RITZ, 0, 0, t, one, TSG_KC_CYCLE_END, 0.0);
   }
+  // x += Q coef; preconditioned: t = Q coef, z = M^{-1} t, x += z
   void xupdate(int m) {
     std::vector<XupdArgs> a;
     std::vector<int> nb;
     double bytes = 0.0;
+    bool any = false;
     for (ReqCtx* q : R) {
-      a.push_back(XupdArgs{q->x, q->V, q->ld, q->n, q->c.st});
+      a.push_back(XupdArgs{q->x, q->V, q->ld, q->n, q->c.st, q->colors ? q->tp : nullptr});
       nb.push_back((int)cdiv(q->n, kRowBlock));
       bytes += (double)m * q->n * elem() + 16.0 * q->n;
+      any = any || q->colors;
     }
     P.add(F_XUPD, 0, 0, a, nb, TSG_KC_XUPDATE, bytes);
+    if (!any) return;
+    gs([](ReqCtx* q) { return (const double*)q->tp; }, [](ReqCtx* q) { return q->zp; }, -1);
+    std::vector<AxpyArgs> x;
+    std::vector<int> xb;
+    double xbytes = 0.0;
+    for (ReqCtx* q : R) {
+      x.push_back(AxpyArgs{q->x, q->zp, q->n, q->c.st});
+      xb.push_back(q->colors ? (int)cdiv(q->n, 256) : 0);
+      if (q->colors) xbytes += 24.0 * q->n;
+    }
+    P.add(F_AXPY, 0, 0, x, xb, TSG_KC_XUPDATE, xbytes);
   }
 };
 
@@ -849,6 +926,84 @@ tsg_status tsg_spmv(tsg_csr A, const double* x, double* y, void* stream) {
   return TSG_OK;
 }
 
+size_t tsg_csr_precond_bytes(tsg_csr A) {
+  if (!A) return 0;
+  const size_t n = (size_t)A->n, nb = (size_t)cdiv(A->n, 256);
+  return 3 * align_up(4 * n) + align_up(4 * nb) + align_up(4) + kAlign;
+}
+
+tsg_status tsg_csr_precond(tsg_csr A, void* buf, size_t bytes, void* stream) {
+  if (!A || !buf) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(buf) % kAlign != 0) return fail(TSG_ERR_INVALID_ARG, "buffer not 256-byte aligned");
+  if (bytes < tsg_csr_precond_bytes(A)) return fail(TSG_ERR_INVALID_ARG, "buffer too small");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = A->n;
+  const int nb = (int)cdiv(n, 256);
+  Carve cv{static_cast<char*>(buf)};
+  int32_t* ca = cv.take<int32_t>((size_t)n);
+  int32_t* cb = cv.take<int32_t>((size_t)n);
+  int32_t* perm = cv.take<int32_t>((size_t)n);
+  int32_t* cnt = cv.take<int32_t>((size_t)nb);
+  int32_t* total = cv.take<int32_t>(1);
+  hipLaunchKernelGGL(jp_init_kernel, dim3(nb), dim3(256), 0, s, ca, n);
+  HIP_LAUNCH_CHECK();
+  int32_t *cold = ca, *cnew = cb;
+  int32_t left = 1;
+  for (int64_t round = 0; left > 0; ++round) {
+    if (round > n) return fail(TSG_ERR_UNSUPPORTED, "coloring did not finish in %lld rounds", (long long)n);
+    hipLaunchKernelGGL(jp_round_kernel, dim3(nb), dim3(256), 0, s, A->row_ptr, A->col, n, cold, cnew, cnt);
+    hipLaunchKernelGGL(jp_total_kernel, dim3(1), dim3(1024), 0, s, cnt, nb, total);
+    HIP_LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(&left, total, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::swap(cold, cnew);
+  }
+  // rows grouped by color, in index order within a color (counting sort on the host)
+  std::vector<int32_t> ch((size_t)n), ph((size_t)n);
+  HIP_TRY(hipMemcpyAsync(ch.data(), cold, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int ncol = 0;
+  for (int64_t i = 0; i < n; ++i) ncol = std::max(ncol, ch[i] + 1);
+  std::vector<int64_t> off((size_t)ncol + 1, 0);
+  for (int64_t i = 0; i < n; ++i) off[ch[i] + 1] += 1;
+  for (int c = 0; c < ncol; ++c) off[c + 1] += off[c];
+  std::vector<int64_t> pos(off.begin(), off.end() - 1);
+  for (int64_t i = 0; i < n; ++i) ph[pos[ch[i]]++] = (int32_t)i;
+  HIP_TRY(hipMemcpyAsync(perm, ph.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  A->colors = cold;
+  A->cperm = perm;
+  A->ncolors = ncol;
+  A->coff_host = off;
+  return TSG_OK;
+}
+
+int32_t tsg_csr_ncolors(tsg_csr A) { return A ? A->ncolors : 0; }
+
+tsg_status tsg_csr_colors(tsg_csr A, int32_t* colors, void* stream) {
+  if (!A || !colors) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  if (!A->colors) return fail(TSG_ERR_INVALID_ARG, "no preconditioner set-up (tsg_csr_precond)");
+  HIP_TRY(hipMemcpyAsync(colors, A->colors, sizeof(int32_t) * A->n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return TSG_OK;
+}
+
+tsg_status tsg_precond_apply(tsg_csr A, const double* w, double* z, void* stream) {
+  if (!A || !w || !z) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  if (!A->colors) return fail(TSG_ERR_INVALID_ARG, "no preconditioner set-up (tsg_csr_precond)");
+  if (w == z) return fail(TSG_ERR_INVALID_ARG, "z must not alias w");
+  hipStream_t s = (hipStream_t)stream;
+  GsArgs a{A->row_ptr, A->col, A->val, A->colors, nullptr, w, z, A->n, nullptr, -1, 0};
+  hipLaunchKernelGGL(gs_first_kernel, dim3(cdiv(A->n, 256)), dim3(256), 0, s, a);
+  for (int c = 1; c < A->ncolors; ++c) {
+    const int64_t r0 = A->coff_host[c], cntc = A->coff_host[c + 1] - r0;
+    if (cntc == 0) continue;
+    GsArgs g{A->row_ptr, A->col, A->val, nullptr, A->cperm + r0, w, z, cntc, nullptr, -1, 0};
+    hipLaunchKernelGGL(gs_color_kernel, dim3(cdiv(cntc, 256)), dim3(256), 0, s, g);
+  }
+  HIP_LAUNCH_CHECK();
+  return TSG_OK;
+}
+
 tsg_status tsg_ritz_newton(const double* H, int64_t ldh, int32_t k, int32_t s, double lo, double hi, double* out,
                            void* stream) {
   if (!H || !out) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
@@ -886,6 +1041,9 @@ static tsg_status validate_params(int64_t n, const tsg_solve_params* p) {
   if (!(p->tol >= 0.0)) return fail(TSG_ERR_INVALID_ARG, "bad tol");
   if (p->max_iters < 0) return fail(TSG_ERR_INVALID_ARG, "bad max_iters");
   if (p->timing < 0) return fail(TSG_ERR_INVALID_ARG, "bad timing %d", p->timing);
+  if (p->precond < 0 || p->precond > 1) return fail(TSG_ERR_INVALID_ARG, "bad precond %d", p->precond);
+  if (p->precond == TSG_PRECOND_MCGS && p->precision != TSG_PREC_FP64)
+    return fail(TSG_ERR_INVALID_ARG, "the multicolor Gauss-Seidel preconditioner runs in FP64 only");
   if (p->flags & ~TSG_FLAG_EAGER) return fail(TSG_ERR_INVALID_ARG, "unknown flags 0x%x", p->flags);
   return TSG_OK;
 }
@@ -896,7 +1054,8 @@ static size_t request_bytes(int64_t n, int64_t nnz, const tsg_solve_params* p) {
   size_t elem = p->precision == TSG_PREC_FP32_IR ? 4 : 8;
   size_t basis = align_up((size_t)basis_ld(n) * (p->m + 1) * elem);
   size_t v32 = p->precision == TSG_PREC_FP32_IR ? align_up((size_t)std::max<int64_t>(nnz, 1) * 4) : 0;
-  return cb + basis + v32;
+  size_t pre = p->precond == TSG_PRECOND_MCGS ? 2 * align_up((size_t)n * 8) : 0;
+  return cb + basis + v32 + pre;
 }
 
 size_t tsg_solve_workspace_bytes(int64_t n, int64_t nnz, const tsg_solve_params* p) {
@@ -907,8 +1066,20 @@ size_t tsg_solve_workspace_bytes(int64_t n, int64_t nnz, const tsg_solve_params*
 namespace {
 
 // Basis parameters from the Gershgorin interval (Sec. VI uses the monomial basis).
+// The basis interval: Gershgorin's of A, or [0, 2] for A M^{-1} (right preconditioning).
+void basis_interval(const tsg_csr_s* A, const tsg_solve_params* p, double* lo, double* hi) {
+  if (p->precond == TSG_PRECOND_MCGS) {
+    *lo = 0.0;
+    *hi = 2.0;
+  } else {
+    *lo = A->lo;
+    *hi = A->hi;
+  }
+}
+
 void basis_params(const tsg_csr_s* A, const tsg_solve_params* p, int sstep, double* theta, double* sigma) {
-  const double lo = A->lo, hi = A->hi;
+  double lo, hi;
+  basis_interval(A, p, &lo, &hi);
   for (int i = 0; i < sstep; ++i) {
     if (p->ortho == TSG_ORTHO_CGS2) {
       theta[i] = 0.0;
@@ -968,6 +1139,12 @@ void carve_request(char* base, const tsg_csr_s* A, const tsg_solve_params* p, Re
     q.V = cv.take<double>((size_t)q.ld * (p->m + 1));
     q.valT = q.val;
   }
+  if (p->precond == TSG_PRECOND_MCGS) {
+    q.A = A;
+    q.colors = A->colors;  // NULL until tsg_csr_precond: rejected by the entry points
+    q.zp = cv.take<double>((size_t)A->n);
+    q.tp = cv.take<double>((size_t)A->n);
+  }
 }
 
 
@@ -991,8 +1168,7 @@ tsg_status init_request(const tsg_csr_s* A, const tsg_solve_params* p, ReqCtx& q
     hs->theta[i] = q.theta[i];
     hs->sigma[i] = q.sigma[i];
   }
-  hs->glo = A->lo;
-  hs->ghi = A->hi;
+  basis_interval(A, p, &hs->glo, &hs->ghi);
   hs->ritz_pending = q.leja ? 1 : 0;
   // pageable source: the copy is staged before the call returns
   hipError_t e = hipMemcpyAsync(q.c.st, hs, offsetof(SmallState, Hh), hipMemcpyHostToDevice, s);
@@ -1174,6 +1350,8 @@ tsg_status tsg_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   size_t need = tsg_solve_workspace_bytes(A->n, A->nnz, p);
   if (need == 0) return fail(TSG_ERR_INVALID_ARG, "problem too large for the reduction buffers");
   if (ws_bytes < need) return fail(TSG_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, need);
+  if (p->precond == TSG_PRECOND_MCGS && !A->colors)
+    return fail(TSG_ERR_INVALID_ARG, "precond = MCGS needs tsg_csr_precond on the operator first");
   ReqCtx q;
   q.b = b;
   q.x = x;
@@ -1417,6 +1595,8 @@ tsg_status tsg_server_destroy(tsg_server S) {
 tsg_status tsg_server_submit(tsg_server S, tsg_csr A, const double* b, double* x, int64_t tag) {
   if (!S || !A || !b || !x) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
   TRY(validate_params(A->n, &S->p));
+  if (S->p.precond == TSG_PRECOND_MCGS && !A->colors)
+    return fail(TSG_ERR_INVALID_ARG, "precond = MCGS needs tsg_csr_precond on the operator first");
   const size_t bytes = align_up(request_bytes(A->n, A->nnz, &S->p));
   if (bytes > S->arena_bytes - S->image_bytes)
     return fail(TSG_ERR_INVALID_ARG, "request of %zu bytes can never fit the arena", bytes);
