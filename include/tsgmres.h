@@ -203,16 +203,16 @@ tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream);
 /* Multicolor Gauss-Seidel set-up for TSG_PRECOND_MCGS: a distance-1 coloring of the
  * pattern by Jones and Plassmann's parallel rounds (priority of row i = output i of the
  * SplitMix64 generator seeded with 0, ties to the higher index; equal to the greedy
- * coloring in decreasing priority), then the rows grouped by color (counting sort of the
- * device-computed colors on the host).  The pattern must be structurally symmetric
- * (a_ij stored iff a_ji stored) and every row must store its diagonal, which must be
- * nonzero.  tsg_csr_precond_bytes: device bytes needed.  tsg_csr_precond fills buf
- * (device, 256-byte aligned, caller-owned, must stay valid while the handle uses it) and
- * synchronizes `stream`; from then on solves with precond = MCGS may use A.
- * Errors: INVALID_ARG (NULL handle or buffer, too small); UNSUPPORTED when the rounds do
- * not finish within n rounds; HIP. */
-size_t tsg_csr_precond_bytes(tsg_csr A);
-tsg_status tsg_csr_precond(tsg_csr A, void* buf, size_t bytes, void* stream);
+ * coloring in decreasing priority), the rows grouped by color (counting sort of the
+ * device-computed colors on the host), and the sweep layout: each color's rows cut into
+ * slices of 64 with their off-diagonal entries stored entry by entry (about
+ * 12 (nnz - n) + 16 n bytes plus padding).  The handle allocates and owns this device
+ * memory (freed by tsg_csr_destroy); the call synchronizes `stream`; a second call does
+ * nothing.  The pattern must be structurally symmetric (a_ij stored iff a_ji stored) and
+ * every row must store a nonzero diagonal.  From then on solves with precond = MCGS may
+ * use A.  Errors: INVALID_ARG (NULL handle); UNSUPPORTED when the rounds do not finish
+ * within n rounds; HIP (allocation, launches). */
+tsg_status tsg_csr_precond(tsg_csr A, void* stream);
 /* Number of colors of the preconditioner set-up (0 before tsg_csr_precond). */
 int32_t tsg_csr_ncolors(tsg_csr A);
 /* Copy the n row colors (int32) to colors (device, caller-owned); INVALID_ARG before

@@ -11,9 +11,13 @@
 //             off-diagonal columns: the pattern must be structurally symmetric.
 //   sweep     z = M^{-1} w with M = D + L_c (the diagonal and the entries whose column has
 //             a lower color than the row): one forward sweep from z = 0 over the colors in
-//             increasing order.  The first launch writes z over all rows (color-0 rows
-//             w_i / a_ii, every other row 0), then one launch per color c >= 1 over that
-//             color's rows: z_i = (w_i - sum_{j != i} a_ij z_j) / a_ii.
+//             increasing order: z = 0, then one launch per color over that color's rows,
+//             z_i = (w_i - sum_{j != i} a_ij z_j) / a_ii (off-diagonal entries in CSR order).
+//   layout    built once by tsg_csr_precond: each color's rows (in index order) cut into
+//             slices of 64, one wave per slice; a slice stores its rows' off-diagonal
+//             values and columns entry by entry (entry e of lane l at off + 64 e + l, padded
+//             with value 0 and the row's own column), so the wave's loads of the operator
+//             are coalesced 64-wide runs; per lane the row index and the diagonal.
 #pragma once
 
 #include "common.hpp"
@@ -90,16 +94,79 @@ __global__ __launch_bounds__(1024) void jp_total_kernel(const int32_t* __restric
   if (threadIdx.x == 0) *total = s[0];
 }
 
+// ------------------------------------------------------------------ sweep layout (set-up)
+// Per slice s (64 positions p0 .. p0+63 of the color permutation, cut at color ends):
+// width[s] = the largest off-diagonal count of its rows.
+__global__ __launch_bounds__(256) void gs_analyze_kernel(const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const int32_t* __restrict__ perm,
+                                                        const int64_t* __restrict__ sstart,
+                                                        const int64_t* __restrict__ send, int64_t nslices,
+                                                        int32_t* __restrict__ width) {
+  const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (s >= nslices) return;
+  const int64_t p = sstart[s] + lane;
+  int cnt = 0;
+  if (p < send[s]) {
+    const int32_t i = perm[p];
+    for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) cnt += col[q] != i;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) cnt = max(cnt, __shfl_xor(cnt, o, kWave));
+  if (lane == 0) width[s] = cnt;
+}
+
+// Fill slice s: row index (-1 on padding lanes), diagonal, off-diagonal values and columns.
+__global__ __launch_bounds__(256) void gs_fill_kernel(const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ val,
+                                                     const int32_t* __restrict__ perm,
+                                                     const int64_t* __restrict__ sstart,
+                                                     const int64_t* __restrict__ send,
+                                                     const int64_t* __restrict__ eoff,
+                                                     const int32_t* __restrict__ width, int64_t nslices,
+                                                     int32_t* __restrict__ prow, double* __restrict__ diag,
+                                                     double* __restrict__ gval, int32_t* __restrict__ gcol) {
+  const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (s >= nslices) return;
+  const int64_t p = sstart[s] + lane, slot = s * kWave + lane, e0 = eoff[s];
+  const int wd = width[s];
+  int32_t i = -1;
+  double d = 0.0;
+  int e = 0;
+  if (p < send[s]) {
+    i = perm[p];
+    for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+      if (col[q] == i) {
+        d = val[q];
+      } else {
+        gval[e0 + (int64_t)kWave * e + lane] = val[q];
+        gcol[e0 + (int64_t)kWave * e + lane] = col[q];
+        ++e;
+      }
+    }
+  }
+  for (; e < wd; ++e) {  // padding: value 0 at the row's own column (row 0 on empty lanes)
+    gval[e0 + (int64_t)kWave * e + lane] = 0.0;
+    gcol[e0 + (int64_t)kWave * e + lane] = i >= 0 ? i : 0;
+  }
+  prow[slot] = i;
+  diag[slot] = d;
+}
+
 // ------------------------------------------------------------------ sweeps (per request)
 struct GsArgs {
-  const int32_t* row_ptr;  // CSR of A (FP64 values)
-  const int32_t* col;
-  const double* val;
-  const int32_t* colors;   // first sweep: the row colors
-  const int32_t* rows;     // color sweep: this color's rows (a slice of the color permutation)
+  const int32_t* prow;     // sweep layout: row index per slot (-1: padding)
+  const double* diag;      //   diagonal per slot
+  const double* gval;      //   off-diagonal values, entry-major per slice
+  const int32_t* gcol;     //   their columns
+  const int64_t* eoff;     //   first entry of each slice
+  const int32_t* width;    //   entries per lane of each slice
+  int64_t slice0;          // color sweep: this color's first slice
   const double* w;         // right-hand side of the sweep
   double* z;               // result
-  int64_t n;               // first sweep: rows; color sweep: rows of this color
+  int64_t n;               // zero pass: rows; color sweep: slices of this color
   const SmallState* st;
   int32_t panel;           // -1: gate on the solve's end only; else also on stop_panel
   int32_t pad;
@@ -110,67 +177,54 @@ __device__ __forceinline__ bool gs_gated(const GsArgs& a) {
   return st->h.done || a.panel > st->h.stop_panel;
 }
 
-// z_i = w_i / a_ii on color-0 rows, 0 elsewhere (every row, natural order).
-__device__ __forceinline__ void gs_first_row(const GsArgs& a, int64_t i) {
-  gbl<double>* z = G(a.z);
-  if (G(a.colors)[i] != 0) {
-    z[i] = 0.0;
-    return;
-  }
-  gbl<const int32_t>* rp = G(a.row_ptr);
-  gbl<const int32_t>* cl = G(a.col);
-  double d = 0.0;
-  for (int p = rp[i]; p < rp[i + 1]; ++p)
-    if (cl[p] == i) d = G(a.val)[p];
-  z[i] = G(a.w)[i] / d;
-}
-
-// One color c >= 1: z_i = (w_i - sum_{j != i} a_ij z_j) / a_ii for its rows (CSR order).
-__device__ __forceinline__ void gs_color_row(const GsArgs& a, int64_t t) {
+// One slice of a color: z_i = (w_i - sum_e a_ie z_col(e)) / a_ii (entries in CSR order).
+__device__ __forceinline__ void gs_slice(const GsArgs& a, int64_t s, int lane) {
 #pragma clang fp contract(off)
-  const int64_t i = G(a.rows)[t];
-  gbl<const int32_t>* rp = G(a.row_ptr);
-  gbl<const int32_t>* cl = G(a.col);
-  gbl<const double>* v = G(a.val);
-  gbl<double>* z = G(a.z);
-  double s = 0.0, d = 0.0;
-  for (int p = rp[i]; p < rp[i + 1]; ++p) {
-    const int32_t j = cl[p];
-    if (j == i) d = v[p];
-    else s += v[p] * z[j];
+  const int64_t slot = s * kWave + lane;
+  const int32_t i = G(a.prow)[slot];
+  if (i < 0) return;
+  gbl<const double>* __restrict__ v = G(a.gval) + G(a.eoff)[s] + lane;
+  gbl<const int32_t>* __restrict__ c = G(a.gcol) + G(a.eoff)[s] + lane;
+  gbl<const double>* __restrict__ z = G(a.z);
+  const int wd = G(a.width)[s];
+  double acc = 0.0;
+  for (int e = 0; e < wd; ++e) {
+    const double ve = __builtin_nontemporal_load(&v[(int64_t)kWave * e]);
+    const int32_t ce = __builtin_nontemporal_load(&c[(int64_t)kWave * e]);
+    acc += ve * z[ce];
   }
-  z[i] = (G(a.w)[i] - s) / d;
+  G(a.z)[i] = (G(a.w)[i] - acc) / G(a.diag)[slot];
 }
 
-struct GsFirstBody {
+struct GsZeroBody {  // z = 0 before the first color
   typedef GsArgs Args;
   static constexpr int kThreads = 256;
   static constexpr int kMinWaves = 1;
   static __device__ void run(const GsArgs& a, int bid, int) {
     if (gs_gated(a)) return;
     const int64_t i = (int64_t)bid * kThreads + threadIdx.x;
-    if (i < a.n) gs_first_row(a, i);
+    if (i < a.n) G(a.z)[i] = 0.0;
   }
 };
-struct GsColorBody {
+struct GsColorBody {  // one color: 4 slices per block, one per wave
   typedef GsArgs Args;
   static constexpr int kThreads = 256;
   static constexpr int kMinWaves = 1;
   static __device__ void run(const GsArgs& a, int bid, int) {
     if (gs_gated(a)) return;
-    const int64_t t = (int64_t)bid * kThreads + threadIdx.x;
-    if (t < a.n) gs_color_row(a, t);
+    const int64_t s = (int64_t)bid * (kThreads / kWave) + threadIdx.x / kWave;
+    if (s < a.n) gs_slice(a, a.slice0 + s, threadIdx.x & (kWave - 1));
   }
 };
 
 // Stand-alone sweep launches (no request state).
-__global__ __launch_bounds__(256) void gs_first_kernel(GsArgs a) {
+__global__ __launch_bounds__(256) void gs_zero_kernel(double* z, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < a.n) gs_first_row(a, i);
+  if (i < n) z[i] = 0.0;
 }
 __global__ __launch_bounds__(256) void gs_color_kernel(GsArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t < a.n) gs_color_row(a, t);
+  const int64_t s = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
+  if (s < a.n) gs_slice(a, a.slice0 + s, threadIdx.x & (kWave - 1));
 }
 
 // x += z (the preconditioned cycle update x += M^{-1} Q y).

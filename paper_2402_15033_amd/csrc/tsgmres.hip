@@ -36,11 +36,18 @@ struct tsg_csr_s {
   const float* v32 = nullptr;
   const void* scol = nullptr;
   int packed = 0;
-  // multicolor Gauss-Seidel (tsg_csr_precond): row colors and the rows in color order
+  // multicolor Gauss-Seidel (tsg_csr_precond): row colors and the sweep layout, in one
+  // device block owned by the handle
   int ncolors = 0;
+  void* gs_mem = nullptr;
   const int32_t* colors = nullptr;
-  const int32_t* cperm = nullptr;
-  std::vector<int64_t> coff_host;  // color c holds cperm[coff[c] .. coff[c+1])
+  const int32_t* gs_prow = nullptr;
+  const double* gs_diag = nullptr;
+  const double* gs_val = nullptr;
+  const int32_t* gs_col = nullptr;
+  const int64_t* gs_eoff = nullptr;
+  const int32_t* gs_width = nullptr;
+  std::vector<int64_t> gs_sloff;  // color c holds slices gs_sloff[c] .. gs_sloff[c+1]-1
 };
 
 namespace {
@@ -290,7 +297,7 @@ void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
     case F_CYCLE_END: launch_b<CycleEndBody>(ph, d, nreq, s); break;
     case F_S2: launch_b<Stage2Body>(ph, d, nreq, s); break;
     case F_RITZ: launch_b<RitzBody>(ph, d, nreq, s); break;
-    case F_GS0: launch_b<GsFirstBody>(ph, d, nreq, s); break;
+    case F_GS0: launch_b<GsZeroBody>(ph, d, nreq, s); break;
     case F_GSC: launch_b<GsColorBody>(ph, d, nreq, s); break;
     case F_AXPY: launch_b<AxpyBody>(ph, d, nreq, s); break;
     case F_XUPD: launch_b<XupdBody<T>>(ph, d, nreq, s); break;
@@ -411,6 +418,12 @@ Step upd_step(PanelKind kind, int k, int wcol, int sw, int flags, int tail, int 
 
 // Builds the phases of a batch of requests that share the basis type and every step
 // parameter; each request keeps its own sizes, buffers and block decomposition.
+// The sweep arguments of color c of A's multicolor Gauss-Seidel layout.
+GsArgs gs_color_args(const tsg_csr_s* A, int c, const double* w, double* z, const SmallState* st, int panel) {
+  const int64_t s0 = A->gs_sloff[c], ns = A->gs_sloff[c + 1] - s0;
+  return GsArgs{A->gs_prow, A->gs_diag, A->gs_val, A->gs_col, A->gs_eoff, A->gs_width, s0, w, z, ns, st, panel, 0};
+}
+
 struct Builder {
   Program& P;
   std::vector<ReqCtx*> R;
@@ -550,27 +563,33 @@ struct Builder {
       double bytes = 0.0;
       for (ReqCtx* q : R) {
         const bool on = q->colors != nullptr;
-        a.push_back(on ? GsArgs{q->A->row_ptr, q->A->col, q->A->val, q->colors, nullptr, w_of(q), z_of(q), q->n,
-                                q->c.st, panel, 0}
-                       : GsArgs{});
+        GsArgs g{};
+        if (on) {
+          g.z = z_of(q);
+          g.n = q->n;
+          g.st = q->c.st;
+          g.panel = panel;
+        }
+        a.push_back(g);
         nb.push_back(on ? (int)cdiv(q->n, 256) : 0);
-        if (on) bytes += 4.0 * q->n + 16.0 * q->n;
+        if (on) bytes += 8.0 * q->n;
       }
       P.add(F_GS0, 0, 0, a, nb, TSG_KC_PRECOND, bytes);
     }
-    for (int c = 1; c < maxc; ++c) {
+    for (int c = 0; c < maxc; ++c) {
       std::vector<GsArgs> a;
       std::vector<int> nb;
       double bytes = 0.0;
       for (ReqCtx* q : R) {
         const bool on = q->colors != nullptr && c < q->A->ncolors;
-        const int64_t r0 = on ? q->A->coff_host[c] : 0, cnt = on ? q->A->coff_host[c + 1] - r0 : 0;
-        a.push_back(on ? GsArgs{q->A->row_ptr, q->A->col, q->A->val, nullptr, q->A->cperm + r0, w_of(q), z_of(q),
-                                cnt, q->c.st, panel, 0}
-                       : GsArgs{});
-        nb.push_back(on ? (int)cdiv(cnt, 256) : 0);
-        // this color's rows: index, row pointers, their CSR entries, w, z gathers and z
-        if (on) bytes += (double)cnt * (4.0 + 8.0 + 8.0 + 8.0) + (double)q->A->nnz * 20.0 * cnt / q->n;
+        const GsArgs g = on ? gs_color_args(q->A, c, w_of(q), z_of(q), q->c.st, panel) : GsArgs{};
+        a.push_back(g);
+        nb.push_back(on ? (int)cdiv(g.n, 4) : 0);
+        if (on) {  // slot rows and diagonals, entries (value, column, z gather), w, z
+          const int64_t s0 = q->A->gs_sloff[c], s1 = q->A->gs_sloff[c + 1];
+          const double rows = (double)(s1 - s0) * kWave;
+          bytes += rows * (4.0 + 8.0 + 8.0 + 8.0) + 20.0 * (double)q->A->nnz * rows / (double)q->n;
+        }
       }
       P.add(F_GSC, 0, 0, a, nb, TSG_KC_PRECOND, bytes);
     }
@@ -905,6 +924,10 @@ tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream) {
 tsg_status tsg_csr_destroy(tsg_csr A) {
   if (!A) return TSG_OK;
   hipError_t e = hipFree(A->dev);
+  if (A->gs_mem) {
+    hipError_t e2 = hipFree(A->gs_mem);
+    if (e == hipSuccess) e = e2;
+  }
   delete A;
   if (e != hipSuccess) return fail(TSG_ERR_HIP, "hipFree: %s", hipGetErrorString(e));
   return TSG_OK;
@@ -926,55 +949,132 @@ tsg_status tsg_spmv(tsg_csr A, const double* x, double* y, void* stream) {
   return TSG_OK;
 }
 
-size_t tsg_csr_precond_bytes(tsg_csr A) {
-  if (!A) return 0;
-  const size_t n = (size_t)A->n, nb = (size_t)cdiv(A->n, 256);
-  return 3 * align_up(4 * n) + align_up(4 * nb) + align_up(4) + kAlign;
-}
-
-tsg_status tsg_csr_precond(tsg_csr A, void* buf, size_t bytes, void* stream) {
-  if (!A || !buf) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
-  if (reinterpret_cast<uintptr_t>(buf) % kAlign != 0) return fail(TSG_ERR_INVALID_ARG, "buffer not 256-byte aligned");
-  if (bytes < tsg_csr_precond_bytes(A)) return fail(TSG_ERR_INVALID_ARG, "buffer too small");
+tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
+  if (!A) return fail(TSG_ERR_INVALID_ARG, "NULL handle");
+  if (A->gs_mem) return TSG_OK;  // already set up
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = A->n;
   const int nb = (int)cdiv(n, 256);
-  Carve cv{static_cast<char*>(buf)};
+  // coloring scratch: two color arrays, per-block counts, the total
+  void* scratch = nullptr;
+  const size_t sbytes = 2 * align_up(4 * (size_t)n) + align_up(4 * (size_t)nb) + kAlign;
+  HIP_TRY(hipMalloc(&scratch, sbytes));
+  Carve cv{static_cast<char*>(scratch)};
   int32_t* ca = cv.take<int32_t>((size_t)n);
   int32_t* cb = cv.take<int32_t>((size_t)n);
-  int32_t* perm = cv.take<int32_t>((size_t)n);
   int32_t* cnt = cv.take<int32_t>((size_t)nb);
   int32_t* total = cv.take<int32_t>(1);
+  auto bail = [&](tsg_status st) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(scratch);
+    return st;
+  };
   hipLaunchKernelGGL(jp_init_kernel, dim3(nb), dim3(256), 0, s, ca, n);
-  HIP_LAUNCH_CHECK();
   int32_t *cold = ca, *cnew = cb;
   int32_t left = 1;
   for (int64_t round = 0; left > 0; ++round) {
-    if (round > n) return fail(TSG_ERR_UNSUPPORTED, "coloring did not finish in %lld rounds", (long long)n);
+    if (round > n) return bail(fail(TSG_ERR_UNSUPPORTED, "coloring did not finish in %lld rounds", (long long)n));
     hipLaunchKernelGGL(jp_round_kernel, dim3(nb), dim3(256), 0, s, A->row_ptr, A->col, n, cold, cnew, cnt);
     hipLaunchKernelGGL(jp_total_kernel, dim3(1), dim3(1024), 0, s, cnt, nb, total);
-    HIP_LAUNCH_CHECK();
-    HIP_TRY(hipMemcpyAsync(&left, total, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (hipGetLastError() != hipSuccess) return bail(fail(TSG_ERR_HIP, "coloring launch failed"));
+    if (hipMemcpyAsync(&left, total, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return bail(fail(TSG_ERR_HIP, "coloring round failed"));
     std::swap(cold, cnew);
   }
-  // rows grouped by color, in index order within a color (counting sort on the host)
+  // rows grouped by color (index order within a color), cut into slices of 64
   std::vector<int32_t> ch((size_t)n), ph((size_t)n);
-  HIP_TRY(hipMemcpyAsync(ch.data(), cold, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  if (hipMemcpyAsync(ch.data(), cold, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return bail(fail(TSG_ERR_HIP, "reading the colors failed"));
   int ncol = 0;
   for (int64_t i = 0; i < n; ++i) ncol = std::max(ncol, ch[i] + 1);
   std::vector<int64_t> off((size_t)ncol + 1, 0);
   for (int64_t i = 0; i < n; ++i) off[ch[i] + 1] += 1;
   for (int c = 0; c < ncol; ++c) off[c + 1] += off[c];
-  std::vector<int64_t> pos(off.begin(), off.end() - 1);
-  for (int64_t i = 0; i < n; ++i) ph[pos[ch[i]]++] = (int32_t)i;
-  HIP_TRY(hipMemcpyAsync(perm, ph.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  A->colors = cold;
-  A->cperm = perm;
+  {
+    std::vector<int64_t> pos(off.begin(), off.end() - 1);
+    for (int64_t i = 0; i < n; ++i) ph[pos[ch[i]]++] = (int32_t)i;
+  }
+  std::vector<int64_t> sl((size_t)ncol + 1, 0), ss, se;
+  for (int c = 0; c < ncol; ++c) {
+    for (int64_t p = off[c]; p < off[c + 1]; p += kWave) {
+      ss.push_back(p);
+      se.push_back(std::min<int64_t>(p + kWave, off[c + 1]));
+    }
+    sl[c + 1] = (int64_t)ss.size();
+  }
+  const int64_t ns = (int64_t)ss.size();
+  // plan arrays: perm, slice starts/ends, widths, entry offsets
+  void* plan = nullptr;
+  const size_t pbytes = align_up(4 * (size_t)n) + 3 * align_up(8 * (size_t)(ns + 1)) + align_up(4 * (size_t)ns) + kAlign;
+  if (hipMalloc(&plan, pbytes) != hipSuccess) return bail(fail(TSG_ERR_HIP, "hipMalloc of the sweep plan failed"));
+  Carve pc{static_cast<char*>(plan)};
+  int32_t* perm = pc.take<int32_t>((size_t)n);
+  int64_t* dss = pc.take<int64_t>((size_t)ns + 1);
+  int64_t* dse = pc.take<int64_t>((size_t)ns + 1);
+  int64_t* deo = pc.take<int64_t>((size_t)ns + 1);
+  int32_t* dwd = pc.take<int32_t>((size_t)ns);
+  std::vector<int32_t> wh((size_t)ns);
+  auto bail2 = [&](tsg_status st) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(plan);
+    return bail(st);
+  };
+  hipError_t e = hipMemcpyAsync(perm, ph.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dss, ss.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dse, se.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(gs_analyze_kernel, dim3(cdiv(ns * kWave, 256)), dim3(256), 0, s, A->row_ptr, A->col, perm,
+                       dss, dse, ns, dwd);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(wh.data(), dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bail2(fail(TSG_ERR_HIP, "sweep analysis failed: %s", hipGetErrorString(e)));
+  std::vector<int64_t> eo((size_t)ns + 1, 0);
+  for (int64_t k = 0; k < ns; ++k) eo[k + 1] = eo[k] + (int64_t)kWave * wh[k];
+  const int64_t nent = eo[ns];
+  // the layout the handle keeps: colors, slot rows and diagonals, entries, offsets, widths
+  void* mem = nullptr;
+  const size_t mbytes = align_up(4 * (size_t)n) + align_up(4 * (size_t)ns * kWave) + align_up(8 * (size_t)ns * kWave) +
+                        align_up(8 * (size_t)std::max<int64_t>(nent, 1)) + align_up(4 * (size_t)std::max<int64_t>(nent, 1)) +
+                        align_up(8 * (size_t)(ns + 1)) + align_up(4 * (size_t)ns) + kAlign;
+  if (hipMalloc(&mem, mbytes) != hipSuccess) return bail2(fail(TSG_ERR_HIP, "hipMalloc of the sweep layout failed"));
+  Carve mc{static_cast<char*>(mem)};
+  int32_t* colors = mc.take<int32_t>((size_t)n);
+  int32_t* prow = mc.take<int32_t>((size_t)ns * kWave);
+  double* diag = mc.take<double>((size_t)ns * kWave);
+  double* gval = mc.take<double>((size_t)std::max<int64_t>(nent, 1));
+  int32_t* gcol = mc.take<int32_t>((size_t)std::max<int64_t>(nent, 1));
+  int64_t* geo = mc.take<int64_t>((size_t)ns + 1);
+  int32_t* gwd = mc.take<int32_t>((size_t)ns);
+  e = hipMemcpyAsync(colors, cold, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(geo, eo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(deo, eo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(gwd, dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(gs_fill_kernel, dim3(cdiv(ns * kWave, 256)), dim3(256), 0, s, A->row_ptr, A->col, A->val, perm,
+                       dss, dse, deo, dwd, ns, prow, diag, gval, gcol);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    return bail2(fail(TSG_ERR_HIP, "sweep layout fill failed: %s", hipGetErrorString(e)));
+  }
+  (void)hipFree(plan);
+  (void)hipFree(scratch);
+  A->gs_mem = mem;
+  A->colors = colors;
+  A->gs_prow = prow;
+  A->gs_diag = diag;
+  A->gs_val = gval;
+  A->gs_col = gcol;
+  A->gs_eoff = geo;
+  A->gs_width = gwd;
+  A->gs_sloff = sl;
   A->ncolors = ncol;
-  A->coff_host = off;
   return TSG_OK;
 }
 
@@ -992,13 +1092,10 @@ tsg_status tsg_precond_apply(tsg_csr A, const double* w, double* z, void* stream
   if (!A->colors) return fail(TSG_ERR_INVALID_ARG, "no preconditioner set-up (tsg_csr_precond)");
   if (w == z) return fail(TSG_ERR_INVALID_ARG, "z must not alias w");
   hipStream_t s = (hipStream_t)stream;
-  GsArgs a{A->row_ptr, A->col, A->val, A->colors, nullptr, w, z, A->n, nullptr, -1, 0};
-  hipLaunchKernelGGL(gs_first_kernel, dim3(cdiv(A->n, 256)), dim3(256), 0, s, a);
-  for (int c = 1; c < A->ncolors; ++c) {
-    const int64_t r0 = A->coff_host[c], cntc = A->coff_host[c + 1] - r0;
-    if (cntc == 0) continue;
-    GsArgs g{A->row_ptr, A->col, A->val, nullptr, A->cperm + r0, w, z, cntc, nullptr, -1, 0};
-    hipLaunchKernelGGL(gs_color_kernel, dim3(cdiv(cntc, 256)), dim3(256), 0, s, g);
+  hipLaunchKernelGGL(gs_zero_kernel, dim3(cdiv(A->n, 256)), dim3(256), 0, s, z, A->n);
+  for (int c = 0; c < A->ncolors; ++c) {
+    const GsArgs g = gs_color_args(A, c, w, z, nullptr, -1);
+    if (g.n > 0) hipLaunchKernelGGL(gs_color_kernel, dim3(cdiv(g.n, 4)), dim3(256), 0, s, g);
   }
   HIP_LAUNCH_CHECK();
   return TSG_OK;
