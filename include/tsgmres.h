@@ -203,15 +203,17 @@ tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream);
 /* Multicolor Gauss-Seidel set-up for TSG_PRECOND_MCGS: a distance-1 coloring of the
  * pattern by Jones and Plassmann's parallel rounds (priority of row i = output i of the
  * SplitMix64 generator seeded with 0, ties to the higher index; equal to the greedy
- * coloring in decreasing priority), the rows grouped by color (counting sort of the
- * device-computed colors on the host), and the sweep layout: each color's rows cut into
- * slices of 64 with their off-diagonal entries stored entry by entry (about
- * 12 (nnz - n) + 16 n bytes plus padding).  The handle allocates and owns this device
- * memory (freed by tsg_csr_destroy); the call synchronizes `stream`; a second call does
- * nothing.  The pattern must be structurally symmetric (a_ij stored iff a_ji stored) and
- * every row must store a nonzero diagonal.  From then on solves with precond = MCGS may
- * use A.  Errors: INVALID_ARG (NULL handle); UNSUPPORTED when the rounds do not finish
- * within n rounds; HIP (allocation, launches). */
+ * coloring in decreasing priority), the color order P (rows grouped by color, index order
+ * within a color: counting sort of the device-computed colors on the host), the
+ * color-ordered system P A P^T (CSR with columns renamed and sorted, its own Gershgorin
+ * interval and packed copy) on which preconditioned solves run, and its sweep layout:
+ * each color's (contiguous) rows cut into slices of 64 with their off-diagonal entries
+ * stored entry by entry.  About 2 x (12 nnz + 24 n) bytes in all; the handle allocates
+ * and owns this device memory (freed by tsg_csr_destroy).  Synchronizes `stream`; a
+ * second call does nothing.  The pattern must be structurally symmetric (a_ij stored iff
+ * a_ji stored) and every row must store a nonzero diagonal.  From then on solves with
+ * precond = MCGS may use A.  Errors: INVALID_ARG (NULL handle); UNSUPPORTED when the
+ * rounds do not finish within n rounds; HIP (allocation, launches). */
 tsg_status tsg_csr_precond(tsg_csr A, void* stream);
 /* Number of colors of the preconditioner set-up (0 before tsg_csr_precond). */
 int32_t tsg_csr_ncolors(tsg_csr A);
@@ -220,7 +222,9 @@ int32_t tsg_csr_ncolors(tsg_csr A);
 tsg_status tsg_csr_colors(tsg_csr A, int32_t* colors, void* stream);
 
 /* z = M^{-1} w for the handle's multicolor Gauss-Seidel preconditioner (device vectors of
- * n doubles; z must not alias w).  The sweep of the solver's matrix-powers steps. */
+ * n doubles; z must not alias w): w is put in color order, swept as in the solver's
+ * matrix-powers steps, and z put back.  Uses two scratch vectors of the handle: calls on
+ * one handle must not overlap. */
 tsg_status tsg_precond_apply(tsg_csr A, const double* w, double* z, void* stream);
 
 /* Newton-basis parameters of TSG_BASIS_LEJA for a given k x k upper Hessenberg matrix
@@ -296,7 +300,7 @@ size_t tsg_server_request_bytes(int64_t n, int64_t nnz, const tsg_solve_params* 
  * each), their status heads, and every admitted request's buffers (the HBM budget).  The
  * server makes no device allocation; it owns one pinned host buffer of max_active x 64
  * bytes.  All device work goes to `stream`.  Errors: INVALID_ARG (bad params, max_active
- * outside [1, 4096]), UNSUPPORTED (timing or a Newton basis), WORKSPACE (arena misaligned
+ * outside [1, 4096]), UNSUPPORTED (timing, a Newton basis, or a preconditioner), WORKSPACE (arena misaligned
  * or smaller than the launch images plus 1 MiB). */
 tsg_status tsg_server_create(const tsg_solve_params* p, void* arena, size_t arena_bytes, int32_t max_active,
                              void* stream, tsg_server* out /* host */);

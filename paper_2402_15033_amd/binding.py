@@ -428,9 +428,11 @@ class Server:
 
     def __init__(self, arena_bytes: int, *, m: int = 60, s: int = 5, tol: float = 1e-8,
                  max_iters: int = 1 << 40, ortho: str = "two_stage", basis: str = "shifted",
-                 precision: str = "fp32_ir", max_active: int = 256, s_hat: int = 0, device="cuda"):
+                 precision: str = "fp32_ir", max_active: int = 256, s_hat: int = 0, device="cuda",
+                 precond=None):
         lib = load_library()
-        self._p, _ = _params(m, s, ortho, basis, precision, tol, max_iters, None, False, s_hat=s_hat)
+        self._p, _ = _params(m, s, ortho, basis, precision, tol, max_iters, None, False, s_hat=s_hat,
+                             precond=precond)
         self.device = torch.device(device)
         self._arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
         base = (self._arena.data_ptr() + 255) // 256 * 256

@@ -13,11 +13,12 @@
 //             a lower color than the row): one forward sweep from z = 0 over the colors in
 //             increasing order: z = 0, then one launch per color over that color's rows,
 //             z_i = (w_i - sum_{j != i} a_ij z_j) / a_ii (off-diagonal entries in CSR order).
-//   layout    built once by tsg_csr_precond: each color's rows (in index order) cut into
-//             slices of 64, one wave per slice; a slice stores its rows' off-diagonal
-//             values and columns entry by entry (entry e of lane l at off + 64 e + l, padded
-//             with value 0 and the row's own column), so the wave's loads of the operator
-//             are coalesced 64-wide runs; per lane the row index and the diagonal.
+//   layout    built once by tsg_csr_precond on the color-ordered system P A P^T (each
+//             color's rows contiguous): each color's rows cut into slices of 64, one wave
+//             per slice; a slice stores its rows' off-diagonal values and columns entry by
+//             entry (entry e of lane l at off + 64 e + l, padded with value 0 and the row's
+//             own column), so the wave's loads of the operator, of w and of z are coalesced
+//             64-wide runs; per lane the row index and the diagonal.
 #pragma once
 
 #include "common.hpp"
@@ -92,6 +93,60 @@ __global__ __launch_bounds__(1024) void jp_total_kernel(const int32_t* __restric
     __syncthreads();
   }
   if (threadIdx.x == 0) *total = s[0];
+}
+
+// ------------------------------------------------------------------ color-ordered system
+// The preconditioned solve runs on P A P^T with the rows (and columns) in color order, so
+// that each color's rows are contiguous: its sweep reads w and writes z in coalesced runs.
+// Row p of P A P^T is row perm[p] of A with its columns renamed by inv (= perm^{-1}) and
+// sorted.
+__global__ __launch_bounds__(256) void permute_csr_kernel(const int32_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col,
+                                                         const double* __restrict__ val,
+                                                         const int32_t* __restrict__ perm,
+                                                         const int32_t* __restrict__ inv, int64_t n,
+                                                         const int32_t* __restrict__ row_ptr_p,
+                                                         int32_t* __restrict__ col_p, double* __restrict__ val_p) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t i = perm[p];
+  const int q0 = row_ptr[i], len = row_ptr[i + 1] - q0, o = row_ptr_p[p];
+  for (int k = 0; k < len; ++k) {  // insertion by renamed column
+    const int32_t c = inv[col[q0 + k]];
+    const double v = val[q0 + k];
+    int m = k;
+    while (m > 0 && col_p[o + m - 1] > c) {
+      col_p[o + m] = col_p[o + m - 1];
+      val_p[o + m] = val_p[o + m - 1];
+      --m;
+    }
+    col_p[o + m] = c;
+    val_p[o + m] = v;
+  }
+}
+
+// dst[p] = src[perm[p]] (into color order) and dst[perm[p]] = src[p] (back).
+__global__ __launch_bounds__(256) void gather_f64_kernel(const double* __restrict__ src,
+                                                        const int32_t* __restrict__ perm, double* __restrict__ dst,
+                                                        int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dst[p] = src[perm[p]];
+}
+__global__ __launch_bounds__(256) void scatter_f64_kernel(const double* __restrict__ src,
+                                                         const int32_t* __restrict__ perm, double* __restrict__ dst,
+                                                         int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dst[perm[p]] = src[p];
+}
+__global__ __launch_bounds__(256) void gather_i32_kernel(const int32_t* __restrict__ src,
+                                                        const int32_t* __restrict__ perm, int32_t* __restrict__ dst,
+                                                        int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dst[p] = src[perm[p]];
+}
+__global__ __launch_bounds__(256) void iota_kernel(int32_t* __restrict__ a, int64_t n) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) a[p] = (int32_t)p;
 }
 
 // ------------------------------------------------------------------ sweep layout (set-up)

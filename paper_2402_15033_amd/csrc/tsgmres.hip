@@ -41,6 +41,13 @@ struct tsg_csr_s {
   int ncolors = 0;
   void* gs_mem = nullptr;
   const int32_t* colors = nullptr;
+  // the color-ordered system P A P^T the preconditioned solve runs on (its own handle with
+  // the sweep layout), the permutation and its scratch; memory owned by this handle
+  tsg_csr_s* pa = nullptr;
+  void* own_mem = nullptr;
+  void* pa_pack = nullptr;
+  const int32_t* perm = nullptr;  // position p in color order holds row perm[p]
+  double* gs_tmp = nullptr;       // 2 n doubles for tsg_precond_apply
   const int32_t* gs_prow = nullptr;
   const double* gs_diag = nullptr;
   const double* gs_val = nullptr;
@@ -138,6 +145,11 @@ __global__ void zero_f64_kernel(double* p, int64_t n) {
   do {                          \
     tsg_status s_ = (x);        \
     if (s_ != TSG_OK) return s_; \
+  } while (0)
+#define TRY_OR(x, cleanup)                \
+  do {                                    \
+    tsg_status s_ = (x);                  \
+    if (s_ != TSG_OK) return cleanup(s_); \
   } while (0)
 
 // ------------------------------------------------------------------ timing
@@ -375,6 +387,8 @@ struct ReqCtx {
   const int32_t* colors = nullptr;
   double* zp = nullptr;          // M^{-1} w of the current step; M^{-1} t of the cycle update
   double* tp = nullptr;          // V coef of the cycle update
+  double* bp = nullptr;          // b and x in color order (the solve runs on P A P^T)
+  double* xp = nullptr;
 };
 
 enum PanelKind { PK_GRAM, PK_UPDATE, PK_FUSED };
@@ -924,8 +938,10 @@ tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream) {
 tsg_status tsg_csr_destroy(tsg_csr A) {
   if (!A) return TSG_OK;
   hipError_t e = hipFree(A->dev);
-  if (A->gs_mem) {
-    hipError_t e2 = hipFree(A->gs_mem);
+  if (A->pa) (void)tsg_csr_destroy(A->pa);
+  for (void* m : {A->gs_mem, A->own_mem, A->pa_pack}) {
+    if (!m) continue;
+    hipError_t e2 = hipFree(m);
     if (e == hipSuccess) e = e2;
   }
   delete A;
@@ -949,13 +965,95 @@ tsg_status tsg_spmv(tsg_csr A, const double* x, double* y, void* stream) {
   return TSG_OK;
 }
 
+namespace {
+
+// The sweep layout of handle H whose rows in color order are perm[off[c] .. off[c+1]):
+// slices of 64 per color, widths, entry offsets, then the fill (device memory owned by H).
+tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, const int32_t* perm, hipStream_t s) {
+  const int ncol = (int)off.size() - 1;
+  std::vector<int64_t> sl((size_t)ncol + 1, 0), ss, se;
+  for (int c = 0; c < ncol; ++c) {
+    for (int64_t p = off[c]; p < off[c + 1]; p += kWave) {
+      ss.push_back(p);
+      se.push_back(std::min<int64_t>(p + kWave, off[c + 1]));
+    }
+    sl[c + 1] = (int64_t)ss.size();
+  }
+  const int64_t ns = (int64_t)ss.size();
+  void* plan = nullptr;
+  const size_t pbytes = 3 * align_up(8 * (size_t)(ns + 1)) + align_up(4 * (size_t)ns) + kAlign;
+  HIP_TRY(hipMalloc(&plan, pbytes));
+  Carve pc{static_cast<char*>(plan)};
+  int64_t* dss = pc.take<int64_t>((size_t)ns + 1);
+  int64_t* dse = pc.take<int64_t>((size_t)ns + 1);
+  int64_t* deo = pc.take<int64_t>((size_t)ns + 1);
+  int32_t* dwd = pc.take<int32_t>((size_t)ns);
+  std::vector<int32_t> wh((size_t)ns);
+  hipError_t e = hipMemcpyAsync(dss, ss.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dse, se.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(gs_analyze_kernel, dim3(cdiv(ns * kWave, 256)), dim3(256), 0, s, H->row_ptr, H->col, perm,
+                       dss, dse, ns, dwd);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(wh.data(), dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  std::vector<int64_t> eo((size_t)ns + 1, 0);
+  for (int64_t k = 0; k < ns; ++k) eo[k + 1] = eo[k] + (int64_t)kWave * wh[k];
+  const int64_t nent = eo[ns];
+  void* mem = nullptr;
+  const size_t mbytes = align_up(4 * (size_t)ns * kWave) + align_up(8 * (size_t)ns * kWave) +
+                        align_up(8 * (size_t)std::max<int64_t>(nent, 1)) +
+                        align_up(4 * (size_t)std::max<int64_t>(nent, 1)) + align_up(8 * (size_t)(ns + 1)) +
+                        align_up(4 * (size_t)ns) + kAlign;
+  if (e == hipSuccess) e = hipMalloc(&mem, mbytes);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(plan);
+    return fail(TSG_ERR_HIP, "sweep layout: %s", hipGetErrorString(e));
+  }
+  Carve mc{static_cast<char*>(mem)};
+  int32_t* prow = mc.take<int32_t>((size_t)ns * kWave);
+  double* diag = mc.take<double>((size_t)ns * kWave);
+  double* gval = mc.take<double>((size_t)std::max<int64_t>(nent, 1));
+  int32_t* gcol = mc.take<int32_t>((size_t)std::max<int64_t>(nent, 1));
+  int64_t* geo = mc.take<int64_t>((size_t)ns + 1);
+  int32_t* gwd = mc.take<int32_t>((size_t)ns);
+  e = hipMemcpyAsync(geo, eo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(deo, eo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(gwd, dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(gs_fill_kernel, dim3(cdiv(ns * kWave, 256)), dim3(256), 0, s, H->row_ptr, H->col, H->val, perm,
+                       dss, dse, deo, dwd, ns, prow, diag, gval, gcol);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(plan);
+  if (e != hipSuccess) {
+    (void)hipFree(mem);
+    return fail(TSG_ERR_HIP, "sweep layout fill: %s", hipGetErrorString(e));
+  }
+  H->gs_mem = mem;
+  H->gs_prow = prow;
+  H->gs_diag = diag;
+  H->gs_val = gval;
+  H->gs_col = gcol;
+  H->gs_eoff = geo;
+  H->gs_width = gwd;
+  H->gs_sloff = sl;
+  H->ncolors = ncol;
+  return TSG_OK;
+}
+
+}  // namespace
+
 tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
   if (!A) return fail(TSG_ERR_INVALID_ARG, "NULL handle");
-  if (A->gs_mem) return TSG_OK;  // already set up
+  if (A->pa) return TSG_OK;  // already set up
   hipStream_t s = (hipStream_t)stream;
-  const int64_t n = A->n;
+  const int64_t n = A->n, nnz = A->nnz;
   const int nb = (int)cdiv(n, 256);
-  // coloring scratch: two color arrays, per-block counts, the total
+  // ---- coloring: Jones-Plassmann rounds (scratch: two color arrays, counts, total)
   void* scratch = nullptr;
   const size_t sbytes = 2 * align_up(4 * (size_t)n) + align_up(4 * (size_t)nb) + kAlign;
   HIP_TRY(hipMalloc(&scratch, sbytes));
@@ -964,9 +1062,15 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
   int32_t* cb = cv.take<int32_t>((size_t)n);
   int32_t* cnt = cv.take<int32_t>((size_t)nb);
   int32_t* total = cv.take<int32_t>(1);
+  void* own = nullptr;
+  tsg_csr pa = nullptr;
+  void* pack = nullptr;
   auto bail = [&](tsg_status st) {
     (void)hipStreamSynchronize(s);
     (void)hipFree(scratch);
+    if (pa) (void)tsg_csr_destroy(pa);
+    if (pack) (void)hipFree(pack);
+    if (own) (void)hipFree(own);
     return st;
   };
   hipLaunchKernelGGL(jp_init_kernel, dim3(nb), dim3(256), 0, s, ca, n);
@@ -982,9 +1086,11 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
       return bail(fail(TSG_ERR_HIP, "coloring round failed"));
     std::swap(cold, cnew);
   }
-  // rows grouped by color (index order within a color), cut into slices of 64
-  std::vector<int32_t> ch((size_t)n), ph((size_t)n);
+  // ---- color order (index order within a color: counting sort on the host), its
+  // inverse, and the row pointers of P A P^T
+  std::vector<int32_t> ch((size_t)n), ph((size_t)n), ih((size_t)n), rp((size_t)n + 1), rpp((size_t)n + 1);
   if (hipMemcpyAsync(ch.data(), cold, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(rp.data(), A->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return bail(fail(TSG_ERR_HIP, "reading the colors failed"));
   int ncol = 0;
@@ -996,84 +1102,54 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
     std::vector<int64_t> pos(off.begin(), off.end() - 1);
     for (int64_t i = 0; i < n; ++i) ph[pos[ch[i]]++] = (int32_t)i;
   }
-  std::vector<int64_t> sl((size_t)ncol + 1, 0), ss, se;
-  for (int c = 0; c < ncol; ++c) {
-    for (int64_t p = off[c]; p < off[c + 1]; p += kWave) {
-      ss.push_back(p);
-      se.push_back(std::min<int64_t>(p + kWave, off[c + 1]));
-    }
-    sl[c + 1] = (int64_t)ss.size();
+  rpp[0] = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    ih[ph[p]] = (int32_t)p;
+    rpp[p + 1] = rpp[p] + (rp[ph[p] + 1] - rp[ph[p]]);
   }
-  const int64_t ns = (int64_t)ss.size();
-  // plan arrays: perm, slice starts/ends, widths, entry offsets
-  void* plan = nullptr;
-  const size_t pbytes = align_up(4 * (size_t)n) + 3 * align_up(8 * (size_t)(ns + 1)) + align_up(4 * (size_t)ns) + kAlign;
-  if (hipMalloc(&plan, pbytes) != hipSuccess) return bail(fail(TSG_ERR_HIP, "hipMalloc of the sweep plan failed"));
-  Carve pc{static_cast<char*>(plan)};
-  int32_t* perm = pc.take<int32_t>((size_t)n);
-  int64_t* dss = pc.take<int64_t>((size_t)ns + 1);
-  int64_t* dse = pc.take<int64_t>((size_t)ns + 1);
-  int64_t* deo = pc.take<int64_t>((size_t)ns + 1);
-  int32_t* dwd = pc.take<int32_t>((size_t)ns);
-  std::vector<int32_t> wh((size_t)ns);
-  auto bail2 = [&](tsg_status st) {
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(plan);
-    return bail(st);
-  };
-  hipError_t e = hipMemcpyAsync(perm, ph.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(dss, ss.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(dse, se.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
+  // ---- owned block: colors (index order), perm, inv, P A P^T (CSR), colors in color
+  // order, identity, two scratch vectors
+  const size_t obytes = 6 * align_up(4 * (size_t)n + 4) + align_up(4 * (size_t)std::max<int64_t>(nnz, 1)) +
+                        align_up(8 * (size_t)std::max<int64_t>(nnz, 1)) + align_up(16 * (size_t)n) + kAlign;
+  if (hipMalloc(&own, obytes) != hipSuccess) return bail(fail(TSG_ERR_HIP, "hipMalloc of the preconditioner failed"));
+  Carve oc{static_cast<char*>(own)};
+  int32_t* colors = oc.take<int32_t>((size_t)n);
+  int32_t* perm = oc.take<int32_t>((size_t)n);
+  int32_t* inv = oc.take<int32_t>((size_t)n);
+  int32_t* row_ptr_p = oc.take<int32_t>((size_t)n + 1);
+  int32_t* colors_p = oc.take<int32_t>((size_t)n);
+  int32_t* iota = oc.take<int32_t>((size_t)n);
+  int32_t* col_p = oc.take<int32_t>((size_t)std::max<int64_t>(nnz, 1));
+  double* val_p = oc.take<double>((size_t)std::max<int64_t>(nnz, 1));
+  double* tmp = oc.take<double>(2 * (size_t)n);
+  hipError_t e = hipMemcpyAsync(colors, cold, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(perm, ph.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(inv, ih.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(row_ptr_p, rpp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(gs_analyze_kernel, dim3(cdiv(ns * kWave, 256)), dim3(256), 0, s, A->row_ptr, A->col, perm,
-                       dss, dse, ns, dwd);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) e = hipMemcpyAsync(wh.data(), dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return bail2(fail(TSG_ERR_HIP, "sweep analysis failed: %s", hipGetErrorString(e)));
-  std::vector<int64_t> eo((size_t)ns + 1, 0);
-  for (int64_t k = 0; k < ns; ++k) eo[k + 1] = eo[k] + (int64_t)kWave * wh[k];
-  const int64_t nent = eo[ns];
-  // the layout the handle keeps: colors, slot rows and diagonals, entries, offsets, widths
-  void* mem = nullptr;
-  const size_t mbytes = align_up(4 * (size_t)n) + align_up(4 * (size_t)ns * kWave) + align_up(8 * (size_t)ns * kWave) +
-                        align_up(8 * (size_t)std::max<int64_t>(nent, 1)) + align_up(4 * (size_t)std::max<int64_t>(nent, 1)) +
-                        align_up(8 * (size_t)(ns + 1)) + align_up(4 * (size_t)ns) + kAlign;
-  if (hipMalloc(&mem, mbytes) != hipSuccess) return bail2(fail(TSG_ERR_HIP, "hipMalloc of the sweep layout failed"));
-  Carve mc{static_cast<char*>(mem)};
-  int32_t* colors = mc.take<int32_t>((size_t)n);
-  int32_t* prow = mc.take<int32_t>((size_t)ns * kWave);
-  double* diag = mc.take<double>((size_t)ns * kWave);
-  double* gval = mc.take<double>((size_t)std::max<int64_t>(nent, 1));
-  int32_t* gcol = mc.take<int32_t>((size_t)std::max<int64_t>(nent, 1));
-  int64_t* geo = mc.take<int64_t>((size_t)ns + 1);
-  int32_t* gwd = mc.take<int32_t>((size_t)ns);
-  e = hipMemcpyAsync(colors, cold, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(geo, eo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(deo, eo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(gwd, dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(gs_fill_kernel, dim3(cdiv(ns * kWave, 256)), dim3(256), 0, s, A->row_ptr, A->col, A->val, perm,
-                       dss, dse, deo, dwd, ns, prow, diag, gval, gcol);
+    hipLaunchKernelGGL(permute_csr_kernel, dim3(nb), dim3(256), 0, s, A->row_ptr, A->col, A->val, perm, inv, n,
+                       row_ptr_p, col_p, val_p);
+    hipLaunchKernelGGL(gather_i32_kernel, dim3(nb), dim3(256), 0, s, colors, perm, colors_p, n);
+    hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(256), 0, s, iota, n);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) {
-    (void)hipFree(mem);
-    return bail2(fail(TSG_ERR_HIP, "sweep layout fill failed: %s", hipGetErrorString(e)));
-  }
-  (void)hipFree(plan);
+  if (e != hipSuccess) return bail(fail(TSG_ERR_HIP, "building P A P^T: %s", hipGetErrorString(e)));
+  // ---- its own handle (Gershgorin interval, packed copy for the SpMV) and sweep layout
+  TRY_OR(tsg_csr_create(n, nnz, row_ptr_p, col_p, val_p, stream, &pa), bail);
+  const size_t pk = tsg_csr_pack_bytes(pa);
+  if (hipMalloc(&pack, pk) != hipSuccess) return bail(fail(TSG_ERR_HIP, "hipMalloc of the packed copy failed"));
+  TRY_OR(tsg_csr_pack(pa, pack, pk, stream), bail);
+  TRY_OR(build_sweep_layout(pa, off, iota, s), bail);
+  HIP_TRY(hipStreamSynchronize(s));
   (void)hipFree(scratch);
-  A->gs_mem = mem;
+  pa->colors = colors_p;
+  A->pa = pa;
+  A->pa_pack = pack;
+  A->own_mem = own;
   A->colors = colors;
-  A->gs_prow = prow;
-  A->gs_diag = diag;
-  A->gs_val = gval;
-  A->gs_col = gcol;
-  A->gs_eoff = geo;
-  A->gs_width = gwd;
-  A->gs_sloff = sl;
+  A->perm = perm;
+  A->gs_tmp = tmp;
   A->ncolors = ncol;
   return TSG_OK;
 }
@@ -1089,14 +1165,18 @@ tsg_status tsg_csr_colors(tsg_csr A, int32_t* colors, void* stream) {
 
 tsg_status tsg_precond_apply(tsg_csr A, const double* w, double* z, void* stream) {
   if (!A || !w || !z) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
-  if (!A->colors) return fail(TSG_ERR_INVALID_ARG, "no preconditioner set-up (tsg_csr_precond)");
+  if (!A->pa) return fail(TSG_ERR_INVALID_ARG, "no preconditioner set-up (tsg_csr_precond)");
   if (w == z) return fail(TSG_ERR_INVALID_ARG, "z must not alias w");
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(gs_zero_kernel, dim3(cdiv(A->n, 256)), dim3(256), 0, s, z, A->n);
-  for (int c = 0; c < A->ncolors; ++c) {
-    const GsArgs g = gs_color_args(A, c, w, z, nullptr, -1);
+  const int64_t n = A->n;
+  double *wp = A->gs_tmp, *zp = A->gs_tmp + n;
+  hipLaunchKernelGGL(gather_f64_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, w, A->perm, wp, n);
+  hipLaunchKernelGGL(gs_zero_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, zp, n);
+  for (int c = 0; c < A->pa->ncolors; ++c) {
+    const GsArgs g = gs_color_args(A->pa, c, wp, zp, nullptr, -1);
     if (g.n > 0) hipLaunchKernelGGL(gs_color_kernel, dim3(cdiv(g.n, 4)), dim3(256), 0, s, g);
   }
+  hipLaunchKernelGGL(scatter_f64_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, zp, A->perm, z, n);
   HIP_LAUNCH_CHECK();
   return TSG_OK;
 }
@@ -1151,7 +1231,7 @@ static size_t request_bytes(int64_t n, int64_t nnz, const tsg_solve_params* p) {
   size_t elem = p->precision == TSG_PREC_FP32_IR ? 4 : 8;
   size_t basis = align_up((size_t)basis_ld(n) * (p->m + 1) * elem);
   size_t v32 = p->precision == TSG_PREC_FP32_IR ? align_up((size_t)std::max<int64_t>(nnz, 1) * 4) : 0;
-  size_t pre = p->precond == TSG_PRECOND_MCGS ? 2 * align_up((size_t)n * 8) : 0;
+  size_t pre = p->precond == TSG_PRECOND_MCGS ? 4 * align_up((size_t)n * 8) : 0;
   return cb + basis + v32 + pre;
 }
 
@@ -1241,6 +1321,8 @@ void carve_request(char* base, const tsg_csr_s* A, const tsg_solve_params* p, Re
     q.colors = A->colors;  // NULL until tsg_csr_precond: rejected by the entry points
     q.zp = cv.take<double>((size_t)A->n);
     q.tp = cv.take<double>((size_t)A->n);
+    q.bp = cv.take<double>((size_t)A->n);
+    q.xp = cv.take<double>((size_t)A->n);
   }
 }
 
@@ -1447,14 +1529,30 @@ tsg_status tsg_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   size_t need = tsg_solve_workspace_bytes(A->n, A->nnz, p);
   if (need == 0) return fail(TSG_ERR_INVALID_ARG, "problem too large for the reduction buffers");
   if (ws_bytes < need) return fail(TSG_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, need);
-  if (p->precond == TSG_PRECOND_MCGS && !A->colors)
-    return fail(TSG_ERR_INVALID_ARG, "precond = MCGS needs tsg_csr_precond on the operator first");
   ReqCtx q;
-  q.b = b;
-  q.x = x;
-  carve_request((char*)workspace, A, p, q);
   char* dprog = (char*)workspace + request_bytes(A->n, A->nnz, p);
-  return run_solve(A, p, q, dprog, (hipStream_t)stream, info);
+  if (p->precond != TSG_PRECOND_MCGS) {
+    q.b = b;
+    q.x = x;
+    carve_request((char*)workspace, A, p, q);
+    return run_solve(A, p, q, dprog, (hipStream_t)stream, info);
+  }
+  // right preconditioning: the solve runs on the color-ordered system P A P^T with P b and
+  // P x; x = P^T x_p afterwards (norms and the residual are permutation-invariant)
+  if (!A->pa) return fail(TSG_ERR_INVALID_ARG, "precond = MCGS needs tsg_csr_precond on the operator first");
+  hipStream_t s = (hipStream_t)stream;
+  carve_request((char*)workspace, A->pa, p, q);
+  const int nb = (int)cdiv(A->n, 256);
+  hipLaunchKernelGGL(gather_f64_kernel, dim3(nb), dim3(256), 0, s, b, A->perm, q.bp, A->n);
+  hipLaunchKernelGGL(gather_f64_kernel, dim3(nb), dim3(256), 0, s, (const double*)x, A->perm, q.xp, A->n);
+  HIP_LAUNCH_CHECK();
+  q.b = q.bp;
+  q.x = q.xp;
+  const tsg_status st = run_solve(A->pa, p, q, dprog, s, info);
+  hipLaunchKernelGGL(scatter_f64_kernel, dim3(nb), dim3(256), 0, s, (const double*)q.xp, A->perm, x, A->n);
+  HIP_LAUNCH_CHECK();
+  HIP_TRY(hipStreamSynchronize(s));
+  return st;
 }
 
 size_t tsg_orthogonalize_workspace_bytes(int64_t n, int32_t k, int32_t s) {
@@ -1650,6 +1748,7 @@ tsg_status tsg_server_create(const tsg_solve_params* p, void* arena, size_t aren
   TRY(validate_params(1 << 30, p));
   if (max_active < 1 || max_active > 4096) return fail(TSG_ERR_INVALID_ARG, "max_active=%d outside [1, 4096]", max_active);
   if (p->timing != 0) return fail(TSG_ERR_UNSUPPORTED, "per-kernel timing is not available in the server");
+  if (p->precond != TSG_PRECOND_NONE) return fail(TSG_ERR_UNSUPPORTED, "the server runs unpreconditioned solves");
   if (reinterpret_cast<uintptr_t>(arena) % kAlign != 0) return fail(TSG_ERR_WORKSPACE, "arena must be 256-byte aligned");
   const size_t image = align_up((size_t)max_active * kProgramBytesPerRequest);
   const size_t heads = align_up((size_t)max_active * sizeof(StateHead));
@@ -1692,8 +1791,6 @@ tsg_status tsg_server_destroy(tsg_server S) {
 tsg_status tsg_server_submit(tsg_server S, tsg_csr A, const double* b, double* x, int64_t tag) {
   if (!S || !A || !b || !x) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
   TRY(validate_params(A->n, &S->p));
-  if (S->p.precond == TSG_PRECOND_MCGS && !A->colors)
-    return fail(TSG_ERR_INVALID_ARG, "precond = MCGS needs tsg_csr_precond on the operator first");
   const size_t bytes = align_up(request_bytes(A->n, A->nnz, &S->p));
   if (bytes > S->arena_bytes - S->image_bytes)
     return fail(TSG_ERR_INVALID_ARG, "request of %zu bytes can never fit the arena", bytes);

@@ -2,8 +2,8 @@
 
 * Coloring (Jones-Plassmann rounds on the device) equal, row by row, to the oracle's
   greedy coloring in decreasing SplitMix64 priority (integer result: bit-exact).
-* One sweep z = M^{-1} w against the oracle's sweep (1e-14 relative; both sum each row
-  in CSR order without fused multiply-adds).
+* One sweep z = M^{-1} w against the oracle's sweep (1e-13 relative: the GPU sweeps the
+  color-ordered system, whose rows hold their entries in renamed-column order).
 * Preconditioned solves of every variant against the oracle: iteration and cycle
   counts equal, x within 1e-10; two-stage with s_hat < m and the Leja basis; graph
   replay against direct launches; the explicit FP64 residual gate.
@@ -47,7 +47,7 @@ def test_coloring_and_sweep_match_oracle(tsg, kind, N):
     w = np.random.default_rng(N).uniform(-1, 1, pr["A"].n)
     z = tsg.precond_apply(A, torch.as_tensor(w, device="cuda")).cpu().numpy()
     zr = PC.mcgs_apply(pr["A"], ref, w)
-    assert np.max(np.abs(z - zr)) <= 1e-14 * np.max(np.abs(zr))
+    assert np.max(np.abs(z - zr)) <= 1e-13 * np.max(np.abs(zr))
 
 
 PRECOND_CASES = [("two_stage", "laplace2d", 64, 5, 0, "monomial"), ("bcgs_pip2", "laplace2d", 64, 5, 0, "monomial"),
@@ -90,3 +90,8 @@ def test_precond_requires_setup(tsg):
     A = tsg.CSRMatrix.from_host(pr["A"])
     with pytest.raises(tsg.TSGError):
         tsg.solve(A, torch.as_tensor(pr["b"], device="cuda"), m=30, s=5, precond="mcgs")
+
+
+def test_server_rejects_precond(tsg):
+    with pytest.raises(tsg.TSGError):
+        tsg.Server(64 << 20, m=30, s=5, precision="fp64", precond="mcgs")
