@@ -495,8 +495,7 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
   __shared__ double sR[kLd * kLd];
   __shared__ double sM[kLd * kLd];
   __shared__ double sc[kLd], ss[kLd], sg[kLd + 1], sz[kLd];
-  __shared__ int s_ku, s_kb, s_fail;
-  __shared__ double s_piv;
+  __shared__ int s_ku;
   if (tid == 0) s_ku = st->h.k_used;
   __syncthreads();
   int ku = s_ku;
@@ -504,37 +503,49 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
   double est = 0.0;
   if (two_stage && ku > 0) {
     int kb = ku + 1;
-    for (int i = tid; i < kb * kb; i += nt) {
-      const int r = i % kb, c = i / kb;
-      const double g = st->G2[r + c * kLd];
-      sG[r + c * kLd] = g;
-      sR[r + c * kLd] = (r <= c) ? g : 0.0;
-    }
-    __syncthreads();
-    // right-looking Cholesky of the upper triangle; a pivot d_j <= tol * G_jj truncates
-    int fail = -1;
-    for (int j = 0; j < kb; ++j) {
-      if (tid == 0) {
-        const double d = sR[j + j * kLd];
-        s_fail = !(d > st->pivot_tol * sG[j + j * kLd]);
-        s_piv = s_fail ? 0.0 : sqrt(d);
-        if (!s_fail) sR[j + j * kLd] = s_piv;
+    // (loops over matrices run on a 64-row x (nt/64)-column thread grid: no integer division)
+    for (int c = tid / kWave; c < kb; c += nt / kWave)
+      for (int r = tid % kWave; r < kb; r += kWave) {
+        const double g = st->G2[r + c * kLd];
+        sG[r + c * kLd] = g;
+        sR[r + c * kLd] = (r <= c) ? g : 0.0;
       }
-      __syncthreads();
-      if (s_fail) {
+    __syncthreads();
+    // right-looking Cholesky of the upper triangle; a pivot d_j <= tol * G_jj truncates.
+    // One barrier per step: every thread takes the pivot itself, the trailing update uses
+    // row j divided on the fly, and row j is scaled in place during the next step (which
+    // reads neither it nor its diagonal).
+    const double ptol = st->pivot_tol;
+    int fail = -1;
+    int jp = -1;
+    double rp = 0.0;
+    for (int j = 0; j < kb; ++j) {
+      const double d = sR[j + j * kLd];
+      const bool bad = !(d > ptol * sG[j + j * kLd]);
+      if (jp >= 0) {  // finish row j - 1
+        for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] /= rp;
+        if (tid == 0) sR[jp + jp * kLd] = rp;
+      }
+      jp = -1;
+      if (bad) {
         fail = j;
         break;
       }
-      const double rjj = s_piv;
-      for (int c = j + 1 + tid; c < kb; c += nt) sR[j + c * kLd] /= rjj;
-      __syncthreads();
-      const int t = kb - j - 1;
-      for (int idx = tid; idx < t * t; idx += nt) {
-        const int i = j + 1 + idx / t, c = j + 1 + idx % t;
-        if (i <= c) sR[i + c * kLd] -= sR[j + i * kLd] * sR[j + c * kLd];
+      const double rjj = sqrt(d);
+      // trailing update on a 16 x 16 thread grid (no integer division in the loop)
+      for (int c = j + 1 + tid / 16; c < kb; c += nt / 16) {
+        const double rjc = sR[j + c * kLd] / rjj;
+        for (int i = j + 1 + tid % 16; i <= c; i += 16) sR[i + c * kLd] -= (sR[j + i * kLd] / rjj) * rjc;
       }
+      jp = j;
+      rp = rjj;
       __syncthreads();
     }
+    if (jp >= 0) {  // the last row when no pivot failed
+      for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] /= rp;
+      if (tid == 0) sR[jp + jp * kLd] = rp;
+    }
+    __syncthreads();
     if (fail >= 0) {  // keep the leading `fail` columns (rows 0..fail-1 of R are final)
       kb = fail;
       if (tid == 0) st->h.truncated += 1;
@@ -542,18 +553,16 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
     ku = kb - 1;
     if (ku > 0) {
       // stage Hhat in LDS (sG is free now), then sM = R2(0:kb,0:kb) Hhat(0:kb,0:ku)
-      for (int idx = tid; idx < kb * ku; idx += nt) {
-        const int i = idx % kb, j = idx / kb;
-        sG[i + j * kLd] = st->Hh[i + j * kLd];
-      }
+      for (int j = tid / kWave; j < ku; j += nt / kWave)
+        for (int i = tid % kWave; i < kb; i += kWave) sG[i + j * kLd] = st->Hh[i + j * kLd];
       __syncthreads();
-      for (int idx = tid; idx < kb * ku; idx += nt) {
-        const int i = idx % kb, j = idx / kb;
-        double v = 0.0;
-        const int lmax = min(kb - 1, j + 1);
-        for (int l = i; l <= lmax; ++l) v += sR[i + l * kLd] * sG[l + j * kLd];
-        sM[i + j * kLd] = v;
-      }
+      for (int j = tid / kWave; j < ku; j += nt / kWave)
+        for (int i = tid % kWave; i < kb; i += kWave) {
+          double v = 0.0;
+          const int lmax = min(kb - 1, j + 1);
+          for (int l = i; l <= lmax; ++l) v += sR[i + l * kLd] * sG[l + j * kLd];
+          sM[i + j * kLd] = v;
+        }
       for (int i = tid; i <= kLd; i += nt) sg[i] = 0.0;
       __syncthreads();
       if (ritz) {  // for the Newton shifts: H(0:ku, 0:ku) = sM(0:ku, 0:ku) R2(0:ku, 0:ku)^{-1}
