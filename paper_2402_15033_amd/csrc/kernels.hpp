@@ -465,9 +465,8 @@ struct XupdBody {
 __device__ void wave_back_subst(const double* U, double* g, double* z, int k) {
   const int lane = threadIdx.x;
   for (int i = k - 1; i >= 0; --i) {
-    if (lane == 0) z[i] = g[i] / U[i + i * kLd];
-    wave_lds_sync();
-    const double zi = z[i];
+    const double zi = g[i] / U[i + i * kLd];  // every lane (g[i] is final)
+    if (lane == 0) z[i] = zi;
     if (lane < i) g[lane] -= U[lane + i * kLd] * zi;
     wave_lds_sync();
   }
@@ -494,7 +493,7 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
   __shared__ double sG[kLd * kLd];
   __shared__ double sR[kLd * kLd];
   __shared__ double sM[kLd * kLd];
-  __shared__ double sc[kLd], ss[kLd], sg[kLd + 1], sz[kLd];
+  __shared__ double sg[kLd + 1], sz[kLd];
   __shared__ int s_ku;
   if (tid == 0) s_ku = st->h.k_used;
   __syncthreads();
@@ -515,15 +514,16 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
     // One barrier per step: every thread takes the pivot itself, the trailing update uses
     // row j divided on the fly, and row j is scaled in place during the next step (which
     // reads neither it nor its diagonal).
+    // (one reciprocal per step: row j is multiplied by 1 / r_jj)
     const double ptol = st->pivot_tol;
     int fail = -1;
     int jp = -1;
-    double rp = 0.0;
+    double rp = 0.0, rpi = 0.0;
     for (int j = 0; j < kb; ++j) {
       const double d = sR[j + j * kLd];
       const bool bad = !(d > ptol * sG[j + j * kLd]);
       if (jp >= 0) {  // finish row j - 1
-        for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] /= rp;
+        for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] *= rpi;
         if (tid == 0) sR[jp + jp * kLd] = rp;
       }
       jp = -1;
@@ -531,18 +531,35 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
         fail = j;
         break;
       }
-      const double rjj = sqrt(d);
-      // trailing update on a 16 x 16 thread grid (no integer division in the loop)
-      for (int c = j + 1 + tid / 16; c < kb; c += nt / 16) {
-        const double rjc = sR[j + c * kLd] / rjj;
-        for (int i = j + 1 + tid % 16; i <= c; i += 16) sR[i + c * kLd] -= (sR[j + i * kLd] / rjj) * rjc;
+      const double rjj = sqrt(d), rinv = 1.0 / rjj;
+      // trailing update on a 16 x 16 thread grid (256 threads, kb <= 64: at most 4 x 4
+      // entries per thread): all loads of a column's entries before its stores, so the LDS
+      // accesses overlap instead of waiting on each other
+      {
+        const int r0 = j + 1 + tid % 16, c0 = j + 1 + tid / 16;
+        double ri[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) ri[m] = (r0 + 16 * m < kb) ? sR[j + (r0 + 16 * m) * kLd] * rinv : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = c0 + 16 * q;
+          if (c >= kb) break;
+          const double rjc = sR[j + c * kLd] * rinv;
+          double v[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) v[m] = (r0 + 16 * m <= c) ? sR[r0 + 16 * m + c * kLd] : 0.0;
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            if (r0 + 16 * m <= c) sR[r0 + 16 * m + c * kLd] = v[m] - ri[m] * rjc;
+        }
       }
       jp = j;
       rp = rjj;
+      rpi = rinv;
       __syncthreads();
     }
     if (jp >= 0) {  // the last row when no pivot failed
-      for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] /= rp;
+      for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] *= rpi;
       if (tid == 0) sR[jp + jp * kLd] = rp;
     }
     __syncthreads();
@@ -560,6 +577,7 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
         for (int i = tid % kWave; i < kb; i += kWave) {
           double v = 0.0;
           const int lmax = min(kb - 1, j + 1);
+#pragma unroll 8
           for (int l = i; l <= lmax; ++l) v += sR[i + l * kLd] * sG[l + j * kLd];
           sM[i + j * kLd] = v;
         }
@@ -579,28 +597,34 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
         const int lane = tid;
         if (lane == 0) sg[0] = st->beta * sR[0];
         wave_lds_sync();
+        // every lane forms rotation i itself (the same values from LDS), then rotates its
+        // own column pair; lane 0 the diagonal and the right-hand side
         for (int i = 0; i < ku; ++i) {
+          const double a = sM[i + i * kLd], b = sM[(i + 1) + i * kLd];
+          const double rho = hypot(a, b);
+          double c = 1.0, s = 0.0;
+          if (rho != 0.0) {
+            const double ri = 1.0 / rho;
+            c = a * ri;
+            s = b * ri;
+          }
+          const int t = lane;
+          const bool mine = t > i && t < ku;
+          double x = 0.0, y = 0.0, gi = 0.0;
+          if (mine) {
+            x = sM[i + t * kLd];
+            y = sM[(i + 1) + t * kLd];
+          }
+          if (lane == 0) gi = sg[i];
+          wave_lds_sync();
+          if (mine) {
+            sM[i + t * kLd] = c * x + s * y;
+            sM[(i + 1) + t * kLd] = -s * x + c * y;
+          }
           if (lane == 0) {
-            const double a = sM[i + i * kLd], b = sM[(i + 1) + i * kLd];
-            const double rho = hypot(a, b);
-            double c = 1.0, s = 0.0;
-            if (rho != 0.0) {
-              c = a / rho;
-              s = b / rho;
-            }
-            sc[i] = c;
-            ss[i] = s;
             sM[i + i * kLd] = rho;
-            const double gi = sg[i];
             sg[i] = c * gi;
             sg[i + 1] = -s * gi;
-          }
-          wave_lds_sync();
-          const int t = lane;
-          if (t > i && t < ku) {
-            const double a = sM[i + t * kLd], b = sM[(i + 1) + t * kLd];
-            sM[i + t * kLd] = sc[i] * a + ss[i] * b;
-            sM[(i + 1) + t * kLd] = -ss[i] * a + sc[i] * b;
           }
           wave_lds_sync();
         }
