@@ -130,8 +130,17 @@ __device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, 
   }
   for (int idx = tid; idx < s * s; idx += nt) {
     int i = idx % s, j = idx / s;
-    double v = red(a, sred, k + i, j);
-    for (int c = 0; c < k; ++c) v -= red(a, sred, c, i) * red(a, sred, c, j);
+    // P^T P entry in four interleaved partial sums (independent LDS loads and FMAs)
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    int c = 0;
+    for (; c + 3 < k; c += 4) {
+      p0 += red(a, sred, c, i) * red(a, sred, c, j);
+      p1 += red(a, sred, c + 1, i) * red(a, sred, c + 1, j);
+      p2 += red(a, sred, c + 2, i) * red(a, sred, c + 2, j);
+      p3 += red(a, sred, c + 3, i) * red(a, sred, c + 3, j);
+    }
+    for (; c < k; ++c) p0 += red(a, sred, c, i) * red(a, sred, c, j);
+    const double v = red(a, sred, k + i, j) - ((p0 + p1) + (p2 + p3));
     sG[i + j * kMaxS] = v;
     if (i == j) {
       const double d = red(a, sred, k + i, j);
@@ -139,7 +148,7 @@ __device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, 
     }
   }
   __syncthreads();
-  return block_chol_upper(sG, kMaxS, R, kMaxS, s, sRef, 1.0);
+  return small_chol_upper(sG, kMaxS, R, kMaxS, s, sRef, 1.0);
 }
 
 // Shifted Cholesky QR (Fukaya et al. 2020) of the explicit pass's panel: with that pass's
@@ -182,8 +191,14 @@ __device__ int tail_chol_rows(const PanelArgs& a, const double* sred, int r0, do
 
 // Write T = R^{-1} (s x s) for the next update kernel.
 __device__ void tail_set_tinv(SmallState* st, const double* R, int s) {
-  block_tri_inv_upper(R, kMaxS, st->Tcur, kMaxS, s);
-  if (threadIdx.x == 0) st->identity_t = 0;
+  // in LDS (R copied first), then one store of T
+  __shared__ double lR[kMaxS * kMaxS], lX[kMaxS * kMaxS];
+  const int tid = threadIdx.x;
+  if (tid < s * s) lR[tid % s + (tid / s) * kMaxS] = R[tid % s + (tid / s) * kMaxS];
+  __syncthreads();
+  block_tri_inv_upper(lR, kMaxS, lX, kMaxS, s);
+  if (tid < s * s) st->Tcur[tid % s + (tid / s) * kMaxS] = lX[tid % s + (tid / s) * kMaxS];
+  if (tid == 0) st->identity_t = 0;
   __syncthreads();
 }
 

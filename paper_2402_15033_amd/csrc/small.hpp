@@ -48,6 +48,46 @@ __device__ int block_chol_upper(const double* G, int ldg, double* R, int ldr, in
   return -1;
 }
 
+// block_chol_upper's factorization for k <= 16 by wave 0 alone (lane c owns column c; the
+// same operations in the same order, one wave-level sync per step instead of three block
+// barriers).  Called by every thread of the block; ends with a barrier.
+__device__ int small_chol_upper(const double* G, int ldg, double* R, int ldr, int k, const double* ref_diag,
+                                double tol) {
+  __shared__ int s_fail;
+  const int tid = threadIdx.x;
+  if (tid < kWave) {
+    const int c = tid;
+    int fail = -1;
+    if (c < k)
+      for (int i = c + 1; i < k; ++i) R[i + c * ldr] = 0.0;
+    for (int j = 0; j < k; ++j) {
+      double d = G[j + j * ldg];
+      for (int i = 0; i < j; ++i) {
+        const double r = R[i + j * ldr];
+        d -= r * r;
+      }
+      const double ref = ref_diag ? ref_diag[j] : G[j + j * ldg];
+      if (!(d > tol * ref)) {
+        fail = j;
+        break;
+      }
+      const double rjj = sqrt(d);
+      if (c > j && c < k) {
+        double v = G[j + c * ldg];
+        for (int i = 0; i < j; ++i) v -= R[i + j * ldr] * R[i + c * ldr];
+        R[j + c * ldr] = v / rjj;
+      }
+      if (c == j) R[j + j * ldr] = rjj;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+    if (tid == 0) s_fail = fail;
+  }
+  __syncthreads();
+  return s_fail;
+}
+
 // X = R^{-1} for upper-triangular k x k R (one thread per column of X).
 __device__ void block_tri_inv_upper(const double* R, int ldr, double* X, int ldx, int k) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -88,48 +128,60 @@ __device__ void block_gemm(const double* A, int lda, const double* B, int ldb, d
 __device__ void block_hessenberg_panel(double* H, const double* P, const double* R,
                                        const double* theta, const double* sigma, const double* tau, int k,
                                        int s, double* M) {
+  (void)M;  // the products and the solve run in LDS
   const int tid = threadIdx.x, nt = blockDim.x;
   const int rows = k + s;
-  // LDS copies of the operands of the inner products (H(0:k, 0:k-1) is upper Hessenberg)
+  // LDS copies of the operands (H(0:k, 0:k-1) is upper Hessenberg), of R, of T and of
+  // the basis parameters; loops over matrices on 64-row thread grids (no integer division)
   __shared__ double lH[kLd * kLd];
   __shared__ double lP[kLd * kMaxS];
-  for (int idx = tid; idx < k * (k - 1); idx += nt) {
-    const int i = idx % k, l = idx / k;
-    lH[i + l * kLd] = H[i + l * kLd];
+  __shared__ double lM[kLd * kMaxS];
+  __shared__ double lR[kMaxS * kMaxS], lT[kMaxS * kMaxS], lB[3 * kMaxS];
+  const int rg = tid % kWave, cg = tid / kWave, ncg = nt / kWave;
+  for (int l = cg; l < k - 1; l += ncg)
+    for (int i = rg; i < k; i += kWave) lH[i + l * kLd] = H[i + l * kLd];
+  for (int c = cg; c < s; c += ncg)
+    for (int i = rg; i < k; i += kWave) lP[i + c * kLd] = P[i + c * kLd];
+  if (tid < s * s) {
+    const int a = tid % s, c = tid / s;
+    lR[a + c * kMaxS] = R[a + c * kMaxS];
+    // T = S(k-1 .. k+s-2, 0 .. s-1): T(0,0) = 1, T(a,0) = 0, T(0,c) = P(k-1,c-1), T(a,c) = R(a-1,c-1)
+    lT[a + c * kMaxS] = c == 0 ? (a == 0 ? 1.0 : 0.0) : (a == 0 ? P[(k - 1) + (c - 1) * kLd] : R[(a - 1) + (c - 1) * kMaxS]);
   }
-  for (int idx = tid; idx < k * s; idx += nt) {
-    const int i = idx % k, c = idx / k;
-    lP[i + c * kLd] = P[i + c * kLd];
+  if (tid < s) {
+    lB[tid] = theta[tid];
+    lB[kMaxS + tid] = sigma[tid];
+    lB[2 * kMaxS + tid] = tau[tid];
   }
   __syncthreads();
   auto Sv = [&](int i, int l) -> double {  // S(i, l), 0-based, l in [0, s]
     if (l == 0) return (i == k - 1) ? 1.0 : 0.0;
-    return (i < k) ? lP[i + (l - 1) * kLd] : R[(i - k) + (l - 1) * kMaxS];
+    return (i < k) ? lP[i + (l - 1) * kLd] : lR[(i - k) + (l - 1) * kMaxS];
   };
-  for (int idx = tid; idx < rows * s; idx += nt) {
-    int i = idx % rows, c = idx / rows;
-    double v = Sv(i, c) * theta[c] + Sv(i, c + 1) * sigma[c];
-    if (c >= 1 && tau[c] != 0.0) v -= Sv(i, c - 1) * tau[c];
-    if (c >= 1 && i < k) {
-      for (int l = (i > 0 ? i - 1 : 0); l < k - 1; ++l) v -= lH[i + l * kLd] * lP[l + (c - 1) * kLd];
+  for (int c = cg; c < s; c += ncg)
+    for (int i = rg; i < rows; i += kWave) {
+      double v = Sv(i, c) * lB[c] + Sv(i, c + 1) * lB[kMaxS + c];
+      if (c >= 1 && lB[2 * kMaxS + c] != 0.0) v -= Sv(i, c - 1) * lB[2 * kMaxS + c];
+      if (c >= 1 && i < k) {
+#pragma unroll 4
+        for (int l = (i > 0 ? i - 1 : 0); l < k - 1; ++l) v -= lH[i + l * kLd] * lP[l + (c - 1) * kLd];
+      }
+      lM[i + c * kLd] = v;
     }
-    M[i + c * kLd] = v;
+  __syncthreads();
+  // right solve with T (upper triangular), one thread per row (rows <= 64):
+  // X(i,c) = (M(i,c) - sum_{a<c} X(i,a) T(a,c)) / T(c,c), written over M
+  if (tid < rows) {
+    for (int c = 0; c < s; ++c) {
+      double v = lM[tid + c * kLd];
+      for (int a = 0; a < c; ++a) v -= lM[tid + a * kLd] * lT[a + c * kMaxS];
+      lM[tid + c * kLd] = v / lT[c + c * kMaxS];
+    }
   }
   __syncthreads();
-  // right solve with T (upper triangular): X(:,c) = (M(:,c) - sum_{a<c} X(:,a) T(a,c)) / T(c,c)
-  auto Tv = [&](int a, int c) -> double {
-    if (c == 0) return (a == 0) ? 1.0 : 0.0;
-    if (a == 0) return P[(k - 1) + (c - 1) * kLd];
-    return R[(a - 1) + (c - 1) * kMaxS];
-  };
-  for (int c = 0; c < s; ++c) {
-    for (int i = tid; i < rows; i += nt) {
-      double v = M[i + c * kLd];
-      for (int a = 0; a < c; ++a) v -= H[i + (k - 1 + a) * kLd] * Tv(a, c);
-      H[i + (k - 1 + c) * kLd] = v / Tv(c, c);
-    }
-    __syncthreads();
-  }
+  for (int c = cg; c < s; c += ncg)
+    for (int i = rg; i < rows; i += kWave) H[i + (k - 1 + c) * kLd] = lM[i + c * kLd];
+  __syncthreads();
 }
 
 // Append Hessenberg columns c0..c1-1 (0-based) to the incremental Givens QR held in

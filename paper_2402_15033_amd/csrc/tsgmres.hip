@@ -518,13 +518,15 @@ struct Builder {
       P.add(F_FUSED, std::max(1, (ncolA + 15) / 16), 0, a, nb, kc, fb ? 0.0 : bytes);
     }
     if (!reduces) return TSG_OK;
-    // first level for requests with many blocks, then the tail
+    // first level for requests with many blocks, then the tail.  The gated passes (which
+    // almost always return at entry) skip the first level: their tail sums every block's
+    // partial itself, one launch less per panel when they are off
     std::vector<RedArgs> ra(nr);
     std::vector<int> rb(nr, 0), one(nr, 1);
     std::vector<PanelArgs> at(a);
     for (size_t r = 0; r < nr; ++r) {
       ra[r] = RedArgs{a[r], R[r]->c.part2, 0, 0};
-      if (nb[r] > 2 * kReduceGroups) {
+      if (nb[r] > 2 * kReduceGroups && st.gate < 2) {
         const int chunk = (int)cdiv(nb[r], kReduceGroups);
         rb[r] = (int)cdiv(nb[r], chunk);
         ra[r].chunk = chunk;
