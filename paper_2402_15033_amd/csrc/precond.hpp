@@ -11,14 +11,16 @@
 //             off-diagonal columns: the pattern must be structurally symmetric.
 //   sweep     z = M^{-1} w with M = D + L_c (the diagonal and the entries whose column has
 //             a lower color than the row): one forward sweep from z = 0 over the colors in
-//             increasing order: z = 0, then one launch per color over that color's rows,
-//             z_i = (w_i - sum_{j != i} a_ij z_j) / a_ii (off-diagonal entries in CSR order).
+//             increasing order, one launch per color over that color's rows,
+//             z_i = (w_i - sum_{j: color(j) < color(i)} a_ij z_j) / a_ii (the entries of higher
+//             colors would meet z_j = 0, so they are left out of the layout and z needs no
+//             zeroing).
 //   layout    built once by tsg_csr_precond on the color-ordered system P A P^T (each
 //             color's rows contiguous): each color's rows cut into slices of 64, one wave
-//             per slice; a slice stores its rows' off-diagonal values and columns entry by
-//             entry (entry e of lane l at off + 64 e + l, padded with value 0 and the row's
-//             own column), so the wave's loads of the operator, of w and of z are coalesced
-//             64-wide runs; per lane the row index and the diagonal.
+//             per slice; a slice stores its rows' lower-color values and columns entry by
+//             entry (entry e of lane l at off + 64 e + l, padded with value 0 at position 0,
+//             a color-0 row whose z is already set), so the wave's loads of the operator, of
+//             w and of z are coalesced 64-wide runs; per lane the row index and the diagonal.
 #pragma once
 
 #include "common.hpp"
@@ -151,12 +153,15 @@ __global__ __launch_bounds__(256) void iota_kernel(int32_t* __restrict__ a, int6
 
 // ------------------------------------------------------------------ sweep layout (set-up)
 // Per slice s (64 positions p0 .. p0+63 of the color permutation, cut at color ends):
-// width[s] = the largest off-diagonal count of its rows.
+// width[s] = the largest count of its rows' entries in lower colors.  On the color-ordered
+// system those are exactly the columns below the first position of the row's color, clo[s]:
+// the sweep needs only them (the entries of higher colors meet z = 0), so it needs no zeroing.
 __global__ __launch_bounds__(256) void gs_analyze_kernel(const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col,
                                                         const int32_t* __restrict__ perm,
                                                         const int64_t* __restrict__ sstart,
-                                                        const int64_t* __restrict__ send, int64_t nslices,
+                                                        const int64_t* __restrict__ send,
+                                                        const int64_t* __restrict__ clo, int64_t nslices,
                                                         int32_t* __restrict__ width) {
   const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
@@ -165,19 +170,20 @@ __global__ __launch_bounds__(256) void gs_analyze_kernel(const int32_t* __restri
   int cnt = 0;
   if (p < send[s]) {
     const int32_t i = perm[p];
-    for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) cnt += col[q] != i;
+    for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) cnt += col[q] < clo[s];
   }
   for (int o = kWave / 2; o > 0; o >>= 1) cnt = max(cnt, __shfl_xor(cnt, o, kWave));
   if (lane == 0) width[s] = cnt;
 }
 
-// Fill slice s: row index (-1 on padding lanes), diagonal, off-diagonal values and columns.
+// Fill slice s: row index (-1 on padding lanes), diagonal, lower-color values and columns.
 __global__ __launch_bounds__(256) void gs_fill_kernel(const int32_t* __restrict__ row_ptr,
                                                      const int32_t* __restrict__ col,
                                                      const double* __restrict__ val,
                                                      const int32_t* __restrict__ perm,
                                                      const int64_t* __restrict__ sstart,
                                                      const int64_t* __restrict__ send,
+                                                     const int64_t* __restrict__ clo,
                                                      const int64_t* __restrict__ eoff,
                                                      const int32_t* __restrict__ width, int64_t nslices,
                                                      int32_t* __restrict__ prow, double* __restrict__ diag,
@@ -195,16 +201,16 @@ __global__ __launch_bounds__(256) void gs_fill_kernel(const int32_t* __restrict_
     for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
       if (col[q] == i) {
         d = val[q];
-      } else {
+      } else if (col[q] < clo[s]) {
         gval[e0 + (int64_t)kWave * e + lane] = val[q];
         gcol[e0 + (int64_t)kWave * e + lane] = col[q];
         ++e;
       }
     }
   }
-  for (; e < wd; ++e) {  // padding: value 0 at the row's own column (row 0 on empty lanes)
+  for (; e < wd; ++e) {  // padding: value 0 at position 0 (color 0, swept first: finite)
     gval[e0 + (int64_t)kWave * e + lane] = 0.0;
-    gcol[e0 + (int64_t)kWave * e + lane] = i >= 0 ? i : 0;
+    gcol[e0 + (int64_t)kWave * e + lane] = 0;
   }
   prow[slot] = i;
   diag[slot] = d;
@@ -221,7 +227,7 @@ struct GsArgs {
   int64_t slice0;          // color sweep: this color's first slice
   const double* w;         // right-hand side of the sweep
   double* z;               // result
-  int64_t n;               // zero pass: rows; color sweep: slices of this color
+  int64_t n;               // slices of this color
   const SmallState* st;
   int32_t panel;           // -1: gate on the solve's end only; else also on stop_panel
   int32_t pad;
@@ -251,16 +257,6 @@ __device__ __forceinline__ void gs_slice(const GsArgs& a, int64_t s, int lane) {
   G(a.z)[i] = (G(a.w)[i] - acc) / G(a.diag)[slot];
 }
 
-struct GsZeroBody {  // z = 0 before the first color
-  typedef GsArgs Args;
-  static constexpr int kThreads = 256;
-  static constexpr int kMinWaves = 1;
-  static __device__ void run(const GsArgs& a, int bid, int) {
-    if (gs_gated(a)) return;
-    const int64_t i = (int64_t)bid * kThreads + threadIdx.x;
-    if (i < a.n) G(a.z)[i] = 0.0;
-  }
-};
 struct GsColorBody {  // one color: 4 slices per block, one per wave
   typedef GsArgs Args;
   static constexpr int kThreads = 256;
@@ -273,10 +269,6 @@ struct GsColorBody {  // one color: 4 slices per block, one per wave
 };
 
 // Stand-alone sweep launches (no request state).
-__global__ __launch_bounds__(256) void gs_zero_kernel(double* z, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) z[i] = 0.0;
-}
 __global__ __launch_bounds__(256) void gs_color_kernel(GsArgs a) {
   const int64_t s = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
   if (s < a.n) gs_slice(a, a.slice0 + s, threadIdx.x & (kWave - 1));

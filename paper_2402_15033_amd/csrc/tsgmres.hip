@@ -237,7 +237,7 @@ constexpr size_t kProgramBytesPerRequest = 512 * 1024;
 
 enum Family : int {
   F_RESID, F_RTAIL, F_UPDATE, F_MPK, F_GRAM, F_PREDUCE, F_PTAIL, F_FUSED, F_CYCLE_END, F_XUPD, F_S2, F_RITZ,
-  F_GS0, F_GSC, F_AXPY
+  F_GSC, F_AXPY
 };
 
 struct Phase {
@@ -309,7 +309,6 @@ void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
     case F_CYCLE_END: launch_b<CycleEndBody>(ph, d, nreq, s); break;
     case F_S2: launch_b<Stage2Body>(ph, d, nreq, s); break;
     case F_RITZ: launch_b<RitzBody>(ph, d, nreq, s); break;
-    case F_GS0: launch_b<GsZeroBody>(ph, d, nreq, s); break;
     case F_GSC: launch_b<GsColorBody>(ph, d, nreq, s); break;
     case F_AXPY: launch_b<AxpyBody>(ph, d, nreq, s); break;
     case F_XUPD: launch_b<XupdBody<T>>(ph, d, nreq, s); break;
@@ -573,25 +572,6 @@ struct Builder {
         maxc = std::max(maxc, q->A->ncolors);
       }
     if (!any) return;
-    {
-      std::vector<GsArgs> a;
-      std::vector<int> nb;
-      double bytes = 0.0;
-      for (ReqCtx* q : R) {
-        const bool on = q->colors != nullptr;
-        GsArgs g{};
-        if (on) {
-          g.z = z_of(q);
-          g.n = q->n;
-          g.st = q->c.st;
-          g.panel = panel;
-        }
-        a.push_back(g);
-        nb.push_back(on ? (int)cdiv(q->n, 256) : 0);
-        if (on) bytes += 8.0 * q->n;
-      }
-      P.add(F_GS0, 0, 0, a, nb, TSG_KC_PRECOND, bytes);
-    }
     for (int c = 0; c < maxc; ++c) {
       std::vector<GsArgs> a;
       std::vector<int> nb;
@@ -601,10 +581,11 @@ struct Builder {
         const GsArgs g = on ? gs_color_args(q->A, c, w_of(q), z_of(q), q->c.st, panel) : GsArgs{};
         a.push_back(g);
         nb.push_back(on ? (int)cdiv(g.n, 4) : 0);
-        if (on) {  // slot rows and diagonals, entries (value, column, z gather), w, z
+        if (on) {  // slot rows and diagonals, w, z, and the lower-color entries (value,
+                   // column, z gather): about half of the off-diagonals over the colors
           const int64_t s0 = q->A->gs_sloff[c], s1 = q->A->gs_sloff[c + 1];
           const double rows = (double)(s1 - s0) * kWave;
-          bytes += rows * (4.0 + 8.0 + 8.0 + 8.0) + 20.0 * (double)q->A->nnz * rows / (double)q->n;
+          bytes += rows * (4.0 + 8.0 + 8.0 + 8.0) + 10.0 * (double)(q->A->nnz - q->n) * rows / (double)q->n;
         }
       }
       P.add(F_GSC, 0, 0, a, nb, TSG_KC_PRECOND, bytes);
@@ -973,29 +954,32 @@ namespace {
 // slices of 64 per color, widths, entry offsets, then the fill (device memory owned by H).
 tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, const int32_t* perm, hipStream_t s) {
   const int ncol = (int)off.size() - 1;
-  std::vector<int64_t> sl((size_t)ncol + 1, 0), ss, se;
+  std::vector<int64_t> sl((size_t)ncol + 1, 0), ss, se, sc;
   for (int c = 0; c < ncol; ++c) {
     for (int64_t p = off[c]; p < off[c + 1]; p += kWave) {
       ss.push_back(p);
       se.push_back(std::min<int64_t>(p + kWave, off[c + 1]));
+      sc.push_back(off[c]);  // columns below the color's first position are lower colors
     }
     sl[c + 1] = (int64_t)ss.size();
   }
   const int64_t ns = (int64_t)ss.size();
   void* plan = nullptr;
-  const size_t pbytes = 3 * align_up(8 * (size_t)(ns + 1)) + align_up(4 * (size_t)ns) + kAlign;
+  const size_t pbytes = 4 * align_up(8 * (size_t)(ns + 1)) + align_up(4 * (size_t)ns) + kAlign;
   HIP_TRY(hipMalloc(&plan, pbytes));
   Carve pc{static_cast<char*>(plan)};
   int64_t* dss = pc.take<int64_t>((size_t)ns + 1);
   int64_t* dse = pc.take<int64_t>((size_t)ns + 1);
+  int64_t* dsc = pc.take<int64_t>((size_t)ns + 1);
   int64_t* deo = pc.take<int64_t>((size_t)ns + 1);
   int32_t* dwd = pc.take<int32_t>((size_t)ns);
   std::vector<int32_t> wh((size_t)ns);
   hipError_t e = hipMemcpyAsync(dss, ss.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(dse, se.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dsc, sc.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(gs_analyze_kernel, dim3(cdiv(ns * kWave, 256)), dim3(256), 0, s, H->row_ptr, H->col, perm,
-                       dss, dse, ns, dwd);
+                       dss, dse, dsc, ns, dwd);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(wh.data(), dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s);
@@ -1026,7 +1010,7 @@ tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, con
   if (e == hipSuccess) e = hipMemcpyAsync(gwd, dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(gs_fill_kernel, dim3(cdiv(ns * kWave, 256)), dim3(256), 0, s, H->row_ptr, H->col, H->val, perm,
-                       dss, dse, deo, dwd, ns, prow, diag, gval, gcol);
+                       dss, dse, dsc, deo, dwd, ns, prow, diag, gval, gcol);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1173,7 +1157,6 @@ tsg_status tsg_precond_apply(tsg_csr A, const double* w, double* z, void* stream
   const int64_t n = A->n;
   double *wp = A->gs_tmp, *zp = A->gs_tmp + n;
   hipLaunchKernelGGL(gather_f64_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, w, A->perm, wp, n);
-  hipLaunchKernelGGL(gs_zero_kernel, dim3(cdiv(n, 256)), dim3(256), 0, s, zp, n);
   for (int c = 0; c < A->pa->ncolors; ++c) {
     const GsArgs g = gs_color_args(A->pa, c, wp, zp, nullptr, -1);
     if (g.n > 0) hipLaunchKernelGGL(gs_color_kernel, dim3(cdiv(g.n, 4)), dim3(256), 0, s, g);
