@@ -136,6 +136,28 @@ def test_fp64_requests_and_zero_rhs(tsg):
     srv.close()
 
 
+@pytest.mark.parametrize("kw", [dict(precision="fp64", basis="leja", s=10, tol=1e-10),
+                                dict(precision="fp32_ir", basis="leja", s=10, tol=1e-8)])
+def test_leja_basis_requests_equal_alone(tsg, kw):
+    """Every request finds its own Newton shifts (Ritz values of its first cycle) inside the
+    batched launches, and takes the shifted Cholesky QR pass where its panels need it."""
+    _say("case server leja", kw)
+    reqs = _requests(tsg, SPECS)
+    alone = _alone(tsg, reqs, **kw)
+    srv = tsg.Server(1 << 30, **dict(KW, **kw))
+    for i, (pr, A, b) in enumerate(reqs):
+        srv.submit(i, A, b)
+    got = _drain(srv, len(reqs))
+    for i in range(len(reqs)):
+        xa, ia = alone[i]
+        xm, im = got[i]
+        assert torch.equal(xa, xm), i
+        assert (ia.iters, ia.newton_from_cycle, ia.shifted_passes) == (im.iters, im.newton_from_cycle,
+                                                                       im.shifted_passes)
+        assert im.converged
+    srv.close()
+
+
 def test_request_larger_than_arena_is_rejected(tsg):
     _say("case server reject")
     reqs = _requests(tsg, [("laplace2d", 128)])
