@@ -383,3 +383,38 @@ def test_solve_monomial_shifted_cholqr_pass(tsg, kind, N, s):
     else:
         kap = np.linalg.cond(G.dense_solve(pr["A"], pr["b"])[1])
     assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 2 * 1e-10 * kap
+
+
+@pytest.mark.parametrize("m,s,basis,ortho,kind,N", [
+    (63, 9, "shifted", "two_stage", "laplace2d", 40),   # m + 1 = 64 columns, s >= 8
+    (63, 9, "shifted", "bcgs_pip2", "laplace2d", 40),
+    (48, 16, "leja", "two_stage", "convdiff2d", 40),    # the largest step
+    (63, 3, "shifted", "two_stage", "convdiff2d", 33),  # ragged n = 1089
+])
+def test_solve_largest_parameters_match_oracle(tsg, m, s, basis, ortho, kind, N):
+    _say("case solve largest parameters", m, s, basis, ortho, kind, N)
+    pr = W.make_problem(kind, N, seed=3)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=m, s=s, tol=1e-10, basis=basis, ortho=ortho)
+    ref = G.sstep_gmres(pr["A"], pr["b"], m=m, s=s, tol=1e-10, basis=basis, ortho=ortho)
+    xg = x.cpu().numpy()
+    _say(f"  iters gpu {info.iters} oracle {ref['iters']}")
+    assert info.converged and info.iters == ref["iters"] and info.cycles == ref["cycles"]
+    assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
+
+
+@pytest.mark.parametrize("ortho", ["two_stage", "bcgs_pip2", "bcgs2_cholqr2", "cgs2"])
+def test_solve_restart_length_one(tsg, ortho):
+    """GMRES(1): one Krylov vector per cycle (the degenerate restart length), stopped by
+    max_iters before convergence: 50 cycles equal the oracle's iterate."""
+    _say("case solve m = 1", ortho)
+    pr = W.make_problem("convdiff2d", 10, seed=3)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    x, info = tsg.solve(A, _dev(pr["b"]), m=1, s=1, tol=1e-10, max_iters=50, ortho=ortho)
+    if ortho == "cgs2":
+        ref = G.gmres(pr["A"], pr["b"], m=1, tol=1e-10, max_iters=50, ortho="cgs2")
+    else:
+        ref = G.sstep_gmres(pr["A"], pr["b"], m=1, s=1, tol=1e-10, max_iters=50, ortho=ortho)
+    assert info.status == 1 and info.iters == ref["iters"] == 50 and info.cycles == 50
+    xg = x.cpu().numpy()
+    assert np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"]) <= 1e-10
