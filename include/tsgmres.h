@@ -248,9 +248,10 @@ size_t tsg_solve_workspace_bytes(int64_t n, int64_t nnz, const tsg_solve_params*
 /* Solve A x = b by restarted s-step GMRES(m) (Sec. III, Fig. 1) with the block
  * orthogonalization p->ortho.  b[n] (device, float64) is read; x[n] (device, float64)
  * holds x0 on entry and the result on exit.  Every step of a restart cycle runs in
- * the library's HIP kernels on `stream`; the host only reads back a 64-byte status
+ * the library's HIP kernels on `stream`; the host only reads back a 72-byte status
  * block once per cycle (the host synchronizes `stream` once per cycle).  Returns after
- * the solve has finished on the device.
+ * the solve has finished on the device.  precond = MCGS: the solve runs on the operator's
+ * color-ordered system (b and x permuted in and out on `stream`).
  * Status: OK (converged), NOT_CONVERGED, BREAKDOWN, or a negative error (then x is
  * untouched).  `info` (host) is filled for every non-negative status. */
 tsg_status tsg_solve(tsg_csr A, const double* b, double* x, const tsg_solve_params* p,
@@ -298,7 +299,7 @@ size_t tsg_server_request_bytes(int64_t n, int64_t nnz, const tsg_solve_params* 
 /* Create a server.  arena (device, 256-byte aligned, arena_bytes) is caller-owned and must
  * outlive the server: it holds the launch image of up to max_active requests (512 KiB
  * each), their status heads, and every admitted request's buffers (the HBM budget).  The
- * server makes no device allocation; it owns one pinned host buffer of max_active x 64
+ * server makes no device allocation; it owns one pinned host buffer of max_active x 72
  * bytes.  All device work goes to `stream`.  Errors: INVALID_ARG (bad params, max_active
  * outside [1, 4096]), UNSUPPORTED (timing, a Newton basis, or a preconditioner), WORKSPACE (arena misaligned
  * or smaller than the launch images plus 1 MiB). */

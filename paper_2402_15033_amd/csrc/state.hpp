@@ -24,6 +24,7 @@ struct StateHead {
   int32_t refine2;       // panel + 1 of the panel whose explicit pass needs the shifted pass
   int32_t shifted;       // stage-1 panels that took the shifted Cholesky QR pass (all cycles)
 };
+static_assert(sizeof(StateHead) == 72, "the host reads a 72-byte status head per cycle");
 
 struct SmallState {
   StateHead h;

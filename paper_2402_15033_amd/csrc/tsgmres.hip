@@ -2,7 +2,7 @@
 // orthogonalization, arXiv:2402.15033) for AMD MI355X (gfx950).
 //
 // The host only enqueues kernels on the caller's stream and, once per restart cycle,
-// reads back the 64-byte StateHead; every numerical decision (convergence, breakdown,
+// reads back the 72-byte StateHead; every numerical decision (convergence, breakdown,
 // truncation) is taken on the device by the tails of the reduction kernels.
 #include <hip/hip_runtime.h>
 
@@ -1534,6 +1534,7 @@ tsg_status tsg_solve(tsg_csr A, const double* b, double* x, const tsg_solve_para
   q.b = q.bp;
   q.x = q.xp;
   const tsg_status st = run_solve(A->pa, p, q, dprog, s, info);
+  if (st < 0) return st;  // errors leave x untouched
   hipLaunchKernelGGL(scatter_f64_kernel, dim3(nb), dim3(256), 0, s, (const double*)q.xp, A->perm, x, A->n);
   HIP_LAUNCH_CHECK();
   HIP_TRY(hipStreamSynchronize(s));
