@@ -64,37 +64,62 @@ __device__ __forceinline__ T csr_row_dot(gbl<const int32_t>* __restrict__ row_pt
 // int32 columns (FMT_SELL32).
 enum OpFormat : int { FMT_CSR = 0, FMT_SELL16 = 1, FMT_SELL32 = 2 };
 
+// acc += sum over entries e0 .. e0 + K - 1 of one slice: all K value and column loads, then
+// all K x gathers are issued before the first product (two dependent memory round trips
+// per group); products rounded, then summed in entry order.
+template <int K, typename T, typename VT, int FMT>
+__device__ __forceinline__ T sell_group(gbl<const VT>* __restrict__ sval, const void* scol_,
+                                        gbl<const T>* __restrict__ x, int64_t q0, int64_t rb, T acc) {
+#pragma clang fp contract(off)
+  VT v[K];
+  int64_t c[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const int64_t q = q0 + (int64_t)u * kWave;
+    v[u] = __builtin_nontemporal_load(&sval[q]);
+    if (FMT == FMT_SELL16)
+      c[u] = __builtin_nontemporal_load(&G(reinterpret_cast<const int16_t*>(scol_))[q]);
+    else
+      c[u] = __builtin_nontemporal_load(&G(reinterpret_cast<const int32_t*>(scol_))[q]);
+  }
+  T xv[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) xv[u] = x[FMT == FMT_SELL16 ? rb + c[u] : c[u]];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    const T prod = (T)v[u] * xv[u];
+    acc += prod;
+  }
+  return acc;
+}
+
 // acc(r) = sum_e val * x[col] for row r = 64 slice + lane of a packed operator; the
 // products are rounded before they are summed, in the rows' CSR order (as csr_row_dot).
+// The slice index is uniform over the wave, so its width w is too: every lane runs all w
+// entries (rows past n are all padding -- value 0, delta 0 -- and gather x[n - 1], an
+// index in range).  Entries go in groups of 8, the last w mod 8 as one group of that size,
+// so a slice of width <= 8 costs two dependent memory round trips.
 template <typename T, typename VT, int FMT>
 __device__ __forceinline__ T sell_row_dot(gbl<const int64_t>* __restrict__ soff, gbl<const VT>* __restrict__ sval,
                                           const void* scol_, gbl<const T>* __restrict__ x, int64_t n, int64_t slice,
                                           int lane) {
-#pragma clang fp contract(off)
   const int64_t off = soff[slice];
+  const int w = (int)((soff[slice + 1] - off) >> 6);
   const int64_t r = slice * kWave + lane;
-  const int w = r < n ? (int)((soff[slice + 1] - off) >> 6) : 0;  // padding rows past n: nothing
+  const int64_t rb = r < n ? r : n - 1;
   T acc = (T)0;
-  if (FMT == FMT_SELL16) {
-    gbl<const int16_t>* __restrict__ scol = G(reinterpret_cast<const int16_t*>(scol_));
-#pragma unroll 4
-    for (int e = 0; e < w; ++e) {
-      const int64_t q = off + (int64_t)e * kWave + lane;
-      const VT v = __builtin_nontemporal_load(&sval[q]);
-      const int64_t c = r + __builtin_nontemporal_load(&scol[q]);
-      const T prod = (T)v * x[c];
-      acc += prod;
-    }
-  } else {
-    gbl<const int32_t>* __restrict__ scol = G(reinterpret_cast<const int32_t*>(scol_));
-#pragma unroll 4
-    for (int e = 0; e < w; ++e) {
-      const int64_t q = off + (int64_t)e * kWave + lane;
-      const VT v = __builtin_nontemporal_load(&sval[q]);
-      const int32_t c = __builtin_nontemporal_load(&scol[q]);
-      const T prod = (T)v * x[c];
-      acc += prod;
-    }
+  int e0 = 0;
+  for (; e0 + 8 <= w; e0 += 8) acc = sell_group<8, T, VT, FMT>(sval, scol_, x, off + (int64_t)e0 * kWave + lane, rb, acc);
+  const int64_t q0 = off + (int64_t)e0 * kWave + lane;
+  switch (w - e0) {
+    case 1: acc = sell_group<1, T, VT, FMT>(sval, scol_, x, q0, rb, acc); break;
+    case 2: acc = sell_group<2, T, VT, FMT>(sval, scol_, x, q0, rb, acc); break;
+    case 3: acc = sell_group<3, T, VT, FMT>(sval, scol_, x, q0, rb, acc); break;
+    case 4: acc = sell_group<4, T, VT, FMT>(sval, scol_, x, q0, rb, acc); break;
+    case 5: acc = sell_group<5, T, VT, FMT>(sval, scol_, x, q0, rb, acc); break;
+    case 6: acc = sell_group<6, T, VT, FMT>(sval, scol_, x, q0, rb, acc); break;
+    case 7: acc = sell_group<7, T, VT, FMT>(sval, scol_, x, q0, rb, acc); break;
+    default: break;
   }
   return acc;
 }
@@ -186,9 +211,16 @@ struct MpkBody {
     gbl<const T>* __restrict__ x = G(reinterpret_cast<const T*>(a.x));
     gbl<T>* __restrict__ y = G(reinterpret_cast<T*>(a.y));
     const int64_t n = a.n;
-    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t r0 = (int64_t)xcd_tile(bid, nb) * kRowBlock + wv * kWave;
     if (r0 >= n) return;
+    const double theta = st->theta[a.step], sigma = st->sigma[a.step], tau = st->tau[a.step];
+    const int64_t r = r0 + lane, rc = r < n ? r : n - 1;
+    // the shift and pair terms are loaded before the row's products
+    T xsv = (T)0, xmv = (T)0;
+    if (theta != 0.0) xsv = G(reinterpret_cast<const T*>(a.xs))[rc];
+    if (tau != 0.0 && a.xm) xmv = G(reinterpret_cast<const T*>(a.xm))[rc];
     T acc;
     if (FMT == FMT_CSR) {
       __shared__ T prod[kRowBlock / kWave][kSegCap];
@@ -198,12 +230,10 @@ struct MpkBody {
       acc = sell_row_dot<T, VT, FMT>(G(reinterpret_cast<const int64_t*>(a.row_ptr)), val, a.col, x, n,
                                      r0 / kWave, lane);
     }
-    const int64_t r = r0 + lane;
-    const double theta = st->theta[a.step], sigma = st->sigma[a.step], tau = st->tau[a.step];
     if (r < n) {
       T v = acc;
-      if (theta != 0.0) v -= (T)theta * G(reinterpret_cast<const T*>(a.xs))[r];
-      if (tau != 0.0 && a.xm) v += (T)tau * G(reinterpret_cast<const T*>(a.xm))[r];
+      if (theta != 0.0) v -= (T)theta * xsv;
+      if (tau != 0.0 && a.xm) v += (T)tau * xmv;
       y[r] = v / (T)sigma;
     }
   }
@@ -256,7 +286,8 @@ __device__ void ResidBody<T, FMT>::run(const ResidArgs& a, int bid, int nb) {
   const int64_t n = a.n;
   gbl<double>* part1 = G(a.part1);
   __shared__ double prod[kRowBlock / kWave][kSegCap];
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t r0 = (int64_t)xcd_tile(bid, nb) * kRowBlock + wv * kWave;
   double rr = 0.0;
   if (r0 < n) {
