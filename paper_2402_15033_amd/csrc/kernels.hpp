@@ -66,7 +66,9 @@ enum OpFormat : int { FMT_CSR = 0, FMT_SELL16 = 1, FMT_SELL32 = 2 };
 
 // acc += sum over entries e0 .. e0 + K - 1 of one slice: all K value and column loads, then
 // all K x gathers are issued before the first product (two dependent memory round trips
-// per group); products rounded, then summed in entry order.
+// per group); products rounded, then summed in entry order.  Plain loads: with the
+// non-temporal hint on the value and column streams the step ran at 5.3 TB/s instead
+// of 5.8 (2048^2 Laplacian, FP64).
 template <int K, typename T, typename VT, int FMT>
 __device__ __forceinline__ T sell_group(gbl<const VT>* __restrict__ sval, const void* scol_,
                                         gbl<const T>* __restrict__ x, int64_t q0, int64_t rb, T acc) {
@@ -76,11 +78,11 @@ __device__ __forceinline__ T sell_group(gbl<const VT>* __restrict__ sval, const 
 #pragma unroll
   for (int u = 0; u < K; ++u) {
     const int64_t q = q0 + (int64_t)u * kWave;
-    v[u] = __builtin_nontemporal_load(&sval[q]);
+    v[u] = sval[q];
     if (FMT == FMT_SELL16)
-      c[u] = __builtin_nontemporal_load(&G(reinterpret_cast<const int16_t*>(scol_))[q]);
+      c[u] = G(reinterpret_cast<const int16_t*>(scol_))[q];
     else
-      c[u] = __builtin_nontemporal_load(&G(reinterpret_cast<const int32_t*>(scol_))[q]);
+      c[u] = G(reinterpret_cast<const int32_t*>(scol_))[q];
   }
   T xv[K];
 #pragma unroll

@@ -238,7 +238,29 @@ __device__ __forceinline__ bool gs_gated(const GsArgs& a) {
   return st->h.done || a.panel > st->h.stop_panel;
 }
 
-// One slice of a color: z_i = (w_i - sum_e a_ie z_col(e)) / a_ii (entries in CSR order).
+// acc += sum over entries e0 .. e0 + K - 1 of a sweep slice: the K value
+// and column loads, then the K z gathers, are issued before the first product (two
+// dependent memory round trips per group); products rounded, then summed in entry order.
+template <int K>
+__device__ __forceinline__ double gs_group(gbl<const double>* __restrict__ v, gbl<const int32_t>* __restrict__ c,
+                                           gbl<const double>* __restrict__ z, int e0, double acc) {
+#pragma clang fp contract(off)
+  double ve[K], zg[K];
+  int32_t ce[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) {
+    ve[u] = __builtin_nontemporal_load(&v[(int64_t)kWave * (e0 + u)]);
+    ce[u] = __builtin_nontemporal_load(&c[(int64_t)kWave * (e0 + u)]);
+  }
+#pragma unroll
+  for (int u = 0; u < K; ++u) zg[u] = z[ce[u]];
+#pragma unroll
+  for (int u = 0; u < K; ++u) acc += ve[u] * zg[u];
+  return acc;
+}
+
+// One slice of a color: z_i = (w_i - sum_e a_ie z_col(e)) / a_ii (entries in CSR order),
+// the entries in groups of 4, the last width mod 4 as one group of that size.
 __device__ __forceinline__ void gs_slice(const GsArgs& a, int64_t s, int lane) {
 #pragma clang fp contract(off)
   const int64_t slot = s * kWave + lane;
@@ -249,10 +271,13 @@ __device__ __forceinline__ void gs_slice(const GsArgs& a, int64_t s, int lane) {
   gbl<const double>* __restrict__ z = G(a.z);
   const int wd = G(a.width)[s];
   double acc = 0.0;
-  for (int e = 0; e < wd; ++e) {
-    const double ve = __builtin_nontemporal_load(&v[(int64_t)kWave * e]);
-    const int32_t ce = __builtin_nontemporal_load(&c[(int64_t)kWave * e]);
-    acc += ve * z[ce];
+  int e0 = 0;
+  for (; e0 + 4 <= wd; e0 += 4) acc = gs_group<4>(v, c, z, e0, acc);
+  switch (wd - e0) {
+    case 1: acc = gs_group<1>(v, c, z, e0, acc); break;
+    case 2: acc = gs_group<2>(v, c, z, e0, acc); break;
+    case 3: acc = gs_group<3>(v, c, z, e0, acc); break;
+    default: break;
   }
   G(a.z)[i] = (G(a.w)[i] - acc) / G(a.diag)[slot];
 }
