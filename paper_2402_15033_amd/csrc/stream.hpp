@@ -69,34 +69,35 @@ struct TileLoad {
       ldsof[sl] = c * LDT + chunk * kWave * R;
     }
   }
+  // Every lane issues all SL loads, with no branch, so that the compiler can count them and
+  // wait only for the batch it needs (a load under a branch made it wait for every load in
+  // flight, the prefetched batches included).  Rows past re are clamped to the last row
+  // pair that starts before re (in bounds, their values unused) and zeroed by to_lds, and
+  // so are the items t >= items (whose column t % ncol exists).
   __device__ void load(gbl<const T>* __restrict__ V, int wv, int lane, int64_t r0, int64_t re,
                        T (&dst)[SL][R]) const {
+    const int64_t rmax = (re - 1) & ~(int64_t)(R - 1);
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
-      const int t = wv + NW * sl;
-      const int64_t row = r0 + rowoff[sl] + (int64_t)R * lane;
-      if (t < items && row + R <= re) {
-        if constexpr (R == 2) {
-          typedef float f2 __attribute__((ext_vector_type(2)));
-          const f2 x = *reinterpret_cast<gbl<const f2>*>(V + colbase[sl] + row);
-          dst[sl][0] = x.x;
-          dst[sl][1] = x.y;
-        } else {
-          dst[sl][0] = V[colbase[sl] + row];
-        }
+      const int64_t row = min(r0 + rowoff[sl] + (int64_t)R * lane, rmax);
+      if constexpr (R == 2) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const f2 x = *reinterpret_cast<gbl<const f2>*>(V + colbase[sl] + row);
+        dst[sl][0] = x.x;
+        dst[sl][1] = x.y;
       } else {
-#pragma unroll
-        for (int e = 0; e < R; ++e) dst[sl][e] = (t < items && row + e < re) ? V[colbase[sl] + row + e] : (T)0;
+        dst[sl][0] = V[colbase[sl] + row];
       }
     }
   }
-  __device__ void to_lds(T* L, int wv, int lane, const T (&src)[SL][R]) const {
+  __device__ void to_lds(T* L, int wv, int lane, int64_t r0, int64_t re, const T (&src)[SL][R]) const {
 #pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
       const int t = wv + NW * sl;
       if (t < items) {
+        const int64_t row = r0 + rowoff[sl] + (int64_t)R * lane;
 #pragma unroll
-        for (int e = 0; e < R; ++e) L[ldsof[sl] + R * lane + e] = src[sl][e];
+        for (int e = 0; e < R; ++e) L[ldsof[sl] + R * lane + e] = row + e < re ? src[sl][e] : (T)0;
       }
     }
   }
@@ -143,14 +144,14 @@ __device__ void GramBody<T, MT, NT>::run(const PanelArgs& a, int bid, int) {
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4{0, 0, 0, 0};
   const int li = lane & 15, lk = lane >> 4;
   const int ksteps = BR / 4;  // K-steps of 4 rows per batch, dealt to the waves round-robin
-  // prefetch depth 2: batches r0+BR and r0+2BR are in flight while r0 is consumed
-  tl.load(V, wv, lane, rb, re, v);
-  if (rb + BR < re) tl.load(V, wv, lane, rb + BR, re, vn);
+  // prefetch depth 2: batches r0+BR and r0+2BR are in flight while r0 is consumed.  The
+  // three register buffers take turns (loop unrolled by 3), so no register copy waits for
+  // a batch still in flight.
   int buf = 0;
-  for (int64_t r0 = rb; r0 < re; r0 += BR) {
-    if (r0 + 2 * BR < re) tl.load(V, wv, lane, r0 + 2 * BR, re, vnn);
+  auto batch = [&](const T (&cur)[SL][R], T (&fut)[SL][R], int64_t r0) {
+    tl.load(V, wv, lane, r0 + 2 * BR, re, fut);
     T* L = lt[buf];
-    tl.to_lds(L, wv, lane, v);
+    tl.to_lds(L, wv, lane, r0, re, cur);
     __syncthreads();
     for (int ks = wv; ks < ksteps; ks += NW) {
       const int row = ks * 4 + lk;
@@ -168,14 +169,16 @@ __device__ void GramBody<T, MT, NT>::run(const PanelArgs& a, int bid, int) {
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = MfmaOp<T>::mac(av, bv[nt], acc[mt][nt]);
       }
     }
-#pragma unroll
-    for (int sl = 0; sl < SL; ++sl)
-#pragma unroll
-      for (int e = 0; e < R; ++e) {
-        v[sl][e] = vn[sl][e];
-        vn[sl][e] = vnn[sl][e];
-      }
     buf ^= 1;
+  };
+  tl.load(V, wv, lane, rb, re, v);
+  tl.load(V, wv, lane, rb + BR, re, vn);
+  for (int64_t r0 = rb; r0 < re; r0 += 3 * BR) {
+    batch(v, vnn, r0);
+    if (r0 + BR >= re) break;
+    batch(vn, v, r0 + BR);
+    if (r0 + 2 * BR >= re) break;
+    batch(vnn, vn, r0 + 2 * BR);
   }
   // sum the 8 waves' partial tiles in wave order, one 16-wide Z tile at a time:
   // red[w][c][z], c < 64, z < 16 (8 x 64 x 16 values fit in the two LDS buffers)
@@ -333,13 +336,12 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
   for (int mt = 0; mt < MT; ++mt) acc[mt] = v4{0, 0, 0, 0};
   const int li = lane & 15, lk = lane >> 4;
   const int ksteps_upd = (ncol + 3) / 4;
-  tl.load(V, wv, lane, rb, re, v);
-  if (rb + BR < re) tl.load(V, wv, lane, rb + BR, re, vn);
+  // prefetch depth 2 with three register buffers taking turns (as in GramBody)
   int buf = 0;
-  for (int64_t r0 = rb; r0 < re; r0 += BR) {
-    if (r0 + 2 * BR < re) tl.load(V, wv, lane, r0 + 2 * BR, re, vnn);
+  auto batch = [&](const T (&cur)[SL][R], T (&fut)[SL][R], int64_t r0) {
+    tl.load(V, wv, lane, r0 + 2 * BR, re, fut);
     T* L = lt[buf];
-    tl.to_lds(L, wv, lane, v);
+    tl.to_lds(L, wv, lane, r0, re, cur);
     __syncthreads();
     // ---- q = [Q, W] B for 16-row tiles: lane holds A(row li, column kk + lk) and
     //      B(kk + lk, li); the wave's rows are its own, so it overwrites their W in place
@@ -379,14 +381,16 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
         }
       }
     }
-#pragma unroll
-    for (int sl = 0; sl < SL; ++sl)
-#pragma unroll
-      for (int e = 0; e < R; ++e) {
-        v[sl][e] = vn[sl][e];
-        vn[sl][e] = vnn[sl][e];
-      }
     buf ^= 1;
+  };
+  tl.load(V, wv, lane, rb, re, v);
+  tl.load(V, wv, lane, rb + BR, re, vn);
+  for (int64_t r0 = rb; r0 < re; r0 += 3 * BR) {
+    batch(v, vnn, r0);
+    if (r0 + BR >= re) break;
+    batch(vn, v, r0 + BR);
+    if (r0 + 2 * BR >= re) break;
+    batch(vnn, vn, r0 + 2 * BR);
   }
   if (!gram) return;
   __syncthreads();
