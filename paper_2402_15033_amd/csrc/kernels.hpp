@@ -472,6 +472,19 @@ struct XupdArgs {
   const SmallState* st;
   double* t;      // non-NULL (right preconditioning): t = V coef instead of x += V coef
 };
+// acc += sum over columns c0 .. c0 + K - 1 of V(r, c) coef(c), in column order; the K loads
+// are issued before the first product.
+template <int K, typename T>
+__device__ __forceinline__ double xupd_group(gbl<const T>* __restrict__ V, int64_t ld, int64_t r, int c0,
+                                            gbl<const double>* coef, double acc) {
+  T q[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) q[u] = V[(int64_t)(c0 + u) * ld + r];
+#pragma unroll
+  for (int u = 0; u < K; ++u) acc += (double)q[u] * coef[c0 + u];
+  return acc;
+}
+
 template <typename T>
 struct XupdBody {
   typedef XupdArgs Args;
@@ -485,8 +498,26 @@ struct XupdBody {
     const int ku = st->h.k_used;
     const int64_t r = (int64_t)bid * kRowBlock + threadIdx.x;
     if (r >= a.n) return;
+    // columns in groups of 16, then one of 8, then one of the remaining size, each group's
+    // loads issued before its first product; the sum runs in column order
+    gbl<const double>* coef = st->coef;
     double acc = 0.0;
-    for (int c = 0; c < ku; ++c) acc += (double)V[(int64_t)c * a.ld + r] * st->coef[c];
+    int c = 0;
+    for (; c + 16 <= ku; c += 16) acc = xupd_group<16>(V, a.ld, r, c, coef, acc);
+    if (c + 8 <= ku) {
+      acc = xupd_group<8>(V, a.ld, r, c, coef, acc);
+      c += 8;
+    }
+    switch (ku - c) {
+      case 1: acc = xupd_group<1>(V, a.ld, r, c, coef, acc); break;
+      case 2: acc = xupd_group<2>(V, a.ld, r, c, coef, acc); break;
+      case 3: acc = xupd_group<3>(V, a.ld, r, c, coef, acc); break;
+      case 4: acc = xupd_group<4>(V, a.ld, r, c, coef, acc); break;
+      case 5: acc = xupd_group<5>(V, a.ld, r, c, coef, acc); break;
+      case 6: acc = xupd_group<6>(V, a.ld, r, c, coef, acc); break;
+      case 7: acc = xupd_group<7>(V, a.ld, r, c, coef, acc); break;
+      default: break;
+    }
     if (a.t) G(a.t)[r] = acc;
     else x[r] += acc;
   }

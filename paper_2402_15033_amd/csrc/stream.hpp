@@ -207,6 +207,20 @@ __device__ void GramBody<T, MT, NT>::run(const PanelArgs& a, int bid, int) {
   }
 }
 
+// y(j) -= sum over columns c0 .. c0 + K - 1 of Q(r, c) P(c, j), in column order; the K
+// loads of the row's Q entries are issued before the first product.
+template <int K, typename T, int S>
+__device__ __forceinline__ void upd_group(gbl<T>* __restrict__ V, int64_t ld, int64_t r, int c0,
+                                          gbl<const double>* P, T (&y)[S]) {
+  T q[K];
+#pragma unroll
+  for (int u = 0; u < K; ++u) q[u] = V[(int64_t)(c0 + u) * ld + r];
+#pragma unroll
+  for (int u = 0; u < K; ++u)
+#pragma unroll
+    for (int j = 0; j < S; ++j) y[j] -= q[u] * (T)P[c0 + u + j * kLd];
+}
+
 // W <- (W - Q P) T in place (PF_HAS_P / PF_HAS_T), one row per thread: every lane reads
 // its row of the k + sw columns (each wave access is a coalesced 64-row segment of one
 // column), P and T are uniform (scalar loads).  No LDS, no barrier, high occupancy.
@@ -233,12 +247,24 @@ __device__ void UpdateBody<T, S>::run(const PanelArgs& a, int bid, int) {
 #pragma unroll
   for (int j = 0; j < S; ++j) y[j] = (j < sw) ? W[(int64_t)j * ld] : (T)0;
   if (hasP) {
+    // columns in groups of 16, then one of 8, then one of the remaining size: each group
+    // issues all its loads before its first update (few dependent round trips per row)
     gbl<const double>* P = st->Pcur;
-#pragma unroll 8
-    for (int c = 0; c < k; ++c) {
-      const T qc = V[(int64_t)c * ld + r];
-#pragma unroll
-      for (int j = 0; j < S; ++j) y[j] -= qc * (T)P[c + j * kLd];
+    int c = 0;
+    for (; c + 16 <= k; c += 16) upd_group<16, T, S>(V, ld, r, c, P, y);
+    if (c + 8 <= k) {
+      upd_group<8, T, S>(V, ld, r, c, P, y);
+      c += 8;
+    }
+    switch (k - c) {
+      case 1: upd_group<1, T, S>(V, ld, r, c, P, y); break;
+      case 2: upd_group<2, T, S>(V, ld, r, c, P, y); break;
+      case 3: upd_group<3, T, S>(V, ld, r, c, P, y); break;
+      case 4: upd_group<4, T, S>(V, ld, r, c, P, y); break;
+      case 5: upd_group<5, T, S>(V, ld, r, c, P, y); break;
+      case 6: upd_group<6, T, S>(V, ld, r, c, P, y); break;
+      case 7: upd_group<7, T, S>(V, ld, r, c, P, y); break;
+      default: break;
     }
   }
   if (hasT) {
