@@ -145,8 +145,8 @@ __device__ void GramBody<T, MT, NT>::run(const PanelArgs& a, int bid, int) {
   const int li = lane & 15, lk = lane >> 4;
   const int ksteps = BR / 4;  // K-steps of 4 rows per batch, dealt to the waves round-robin
   // prefetch depth 2: batches r0+BR and r0+2BR are in flight while r0 is consumed.  The
-  // three register buffers take turns (loop unrolled by 3), so no register copy waits for
-  // a batch still in flight.
+  // three register buffers take turns (loop unrolled by 6: the compiler drains the loads
+  // in flight at the loop head), so no register copy waits for a batch still in flight.
   int buf = 0;
   auto batch = [&](const T (&cur)[SL][R], T (&fut)[SL][R], int64_t r0) {
     tl.load(V, wv, lane, r0 + 2 * BR, re, fut);
@@ -173,12 +173,18 @@ __device__ void GramBody<T, MT, NT>::run(const PanelArgs& a, int bid, int) {
   };
   tl.load(V, wv, lane, rb, re, v);
   tl.load(V, wv, lane, rb + BR, re, vn);
-  for (int64_t r0 = rb; r0 < re; r0 += 3 * BR) {
+  for (int64_t r0 = rb; r0 < re; r0 += 6 * BR) {
     batch(v, vnn, r0);
     if (r0 + BR >= re) break;
     batch(vn, v, r0 + BR);
     if (r0 + 2 * BR >= re) break;
     batch(vnn, vn, r0 + 2 * BR);
+    if (r0 + 3 * BR >= re) break;
+    batch(v, vnn, r0 + 3 * BR);
+    if (r0 + 4 * BR >= re) break;
+    batch(vn, v, r0 + 4 * BR);
+    if (r0 + 5 * BR >= re) break;
+    batch(vnn, vn, r0 + 5 * BR);
   }
   // sum the 8 waves' partial tiles in wave order, one 16-wide Z tile at a time:
   // red[w][c][z], c < 64, z < 16 (8 x 64 x 16 values fit in the two LDS buffers)
