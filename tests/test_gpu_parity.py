@@ -291,6 +291,27 @@ def test_packed_operator_wide_columns(tsg):
     assert ic.iters == ref["iters"]
 
 
+@pytest.mark.parametrize("n,far,prec", [(2909, False, "fp64"), (2909, False, "fp32_ir"), (33309, True, "fp64")])
+def test_packed_operator_variable_widths(tsg, n, far, prec):
+    """Slices of every width 1 .. 20 (the packed SpMV's groups of 8 and every remainder,
+    a ragged last slice): packed and CSR solves equal bit for bit; 16-bit deltas for the
+    banded operator, 32-bit columns for the one with far columns."""
+    _say("case packed variable widths", n, far, prec)
+    A = W.variable_width(n, seed=7, far=far)
+    b = W.uniform_vector(n, seed=8)
+    kw = dict(m=30, s=5, tol=1e-12, precision=prec, basis="shifted")
+    Ac = tsg.CSRMatrix.from_host(A, pack=False)
+    Ap = tsg.CSRMatrix.from_host(A, pack=True)
+    xc, ic = tsg.solve(Ac, _dev(b), **kw)
+    xp, ip = tsg.solve(Ap, _dev(b), **kw)
+    assert ic.converged and torch.equal(xc, xp)
+    assert (ic.iters, ic.cycles) == (ip.iters, ip.cycles)
+    if prec == "fp64" and n < 10000:
+        ref = G.sstep_gmres(A, b, m=30, s=5, tol=1e-12, basis="shifted")
+        assert ic.iters == ref["iters"]
+        assert np.linalg.norm(xc.cpu().numpy() - ref["x"]) <= 1e-10 * np.linalg.norm(ref["x"])
+
+
 def test_determinism(tsg):
     _say("case determinism")
     pr = W.make_problem("convdiff2d", 64, seed=1)

@@ -50,6 +50,26 @@ def test_coloring_and_sweep_match_oracle(tsg, kind, N):
     assert np.max(np.abs(z - zr)) <= 1e-13 * np.max(np.abs(zr))
 
 
+def test_coloring_sweep_and_solve_variable_widths(tsg):
+    """Rows of 1 .. 32 nonzeros (symmetrized random pattern): the sweep's groups of 4 and
+    every remainder; coloring bit-exact, one sweep and a preconditioned solve against the
+    oracle."""
+    _say("case precond variable widths")
+    A0 = W.variable_width(2909, seed=9, symmetric=True)
+    A = tsg.CSRMatrix.from_host(A0).precond_setup()
+    ref = PC.coloring(A0)
+    assert np.array_equal(A.colors().cpu().numpy(), ref)
+    w = np.random.default_rng(10).uniform(-1, 1, A0.n)
+    z = tsg.precond_apply(A, torch.as_tensor(w, device="cuda")).cpu().numpy()
+    zr = PC.mcgs_apply(A0, ref, w)
+    assert np.max(np.abs(z - zr)) <= 1e-13 * np.max(np.abs(zr))
+    b = W.uniform_vector(A0.n, seed=11)
+    x, info = tsg.solve(A, torch.as_tensor(b, device="cuda"), m=30, s=5, tol=1e-12, precond="mcgs")
+    out = G.sstep_gmres(A0, b, m=30, s=5, tol=1e-12, precond=PC.MulticolorGS(A0))
+    assert info.converged and info.iters == out["iters"]
+    assert np.linalg.norm(x.cpu().numpy() - out["x"]) <= 1e-10 * np.linalg.norm(out["x"])
+
+
 PRECOND_CASES = [("two_stage", "laplace2d", 64, 5, 0, "monomial"), ("bcgs_pip2", "laplace2d", 64, 5, 0, "monomial"),
                  ("bcgs2_cholqr2", "convdiff2d", 45, 5, 0, "monomial"), ("cgs2", "convdiff2d", 45, 5, 0, "monomial"),
                  ("two_stage", "convdiff2d", 93, 5, 20, "monomial"), ("two_stage", "laplace2d", 64, 10, 0, "leja")]

@@ -11,6 +11,7 @@ from .generators import (  # noqa: F401
     laplace3d,
     convdiff2d,
     convdiff_params,
+    variable_width,
     uniform_vector,
     rhs_from_solution,
     gaussian_block,

@@ -14,6 +14,14 @@ lexicographic unknown ordering with x fastest):
   three-point row is  [-1 - h*max(c,0),  2 + h*|c|,  -1 + h*min(c,0)].
   (Not in the paper; a nonsymmetric stand-in for its SuiteSparse inputs.)
 
+* ``variable_width(n, seed, far, symmetric)`` -- random diagonally dominant operator
+  whose rows hold 1 .. 20 nonzeros: rows 64 j .. 64 j + 63 have at most 1 + (j mod 20)
+  (reached by the first of them), so consecutive 64-row slices of a packed layout take
+  every width from 1 to 20.  Off-diagonal columns lie within 60 of the row
+  (``far=False``) or anywhere (``far=True``); ``symmetric=True`` symmetrizes the pattern
+  (row lengths then vary further).  Off-diagonal values U(-1, 1); the diagonal is the
+  row's absolute off-diagonal sum plus 1.  (A test operator, not a paper workload.)
+
 Dense test blocks for the block orthogonalization experiments (Sec. VI):
 
 * ``gaussian_block``  -- i.i.d. N(0,1) entries (well conditioned).
@@ -105,6 +113,35 @@ def convdiff2d(N: int, pe: float, theta: float) -> CSR:
     north = -1.0 + h * min(by, 0.0)
     diag = 4.0 + h * (abs(bx) + abs(by))
     return _stencil_2d(N, west, east, south, north, diag)
+
+
+def variable_width(n: int, seed: int, far: bool = False, symmetric: bool = False) -> CSR:
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(n):
+        w = 1 + (i // 64) % 20
+        L = w if i % 64 == 0 else int(rng.integers(1, w + 1))
+        if L > 1:
+            if far:
+                pool = rng.choice(n - 1, size=L - 1, replace=False)
+                c = np.where(pool >= i, pool + 1, pool)  # skip the diagonal
+            else:
+                lo, hi = max(0, i - 60), min(n - 1, i + 60)
+                pool = np.array([j for j in range(lo, hi + 1) if j != i])
+                c = rng.choice(pool, size=min(L - 1, pool.size), replace=False)
+            rows.append(np.full(c.size, i))
+            cols.append(c)
+    r = np.concatenate(rows) if rows else np.zeros(0, dtype=np.int64)
+    c = np.concatenate(cols) if cols else np.zeros(0, dtype=np.int64)
+    off = sp.csr_matrix((rng.uniform(-1.0, 1.0, r.size), (r, c)), shape=(n, n))
+    if symmetric:
+        off = off + off.T
+    off = off.tocsr()
+    off.sum_duplicates()
+    M = (off + sp.diags(np.asarray(abs(off).sum(axis=1)).ravel() + 1.0)).tocsr()
+    M.sort_indices()
+    return CSR(n=n, row_ptr=M.indptr.astype(np.int32), col=M.indices.astype(np.int32),
+               val=M.data.astype(np.float64))
 
 
 def convdiff_params(seed: int, pe_lo: float = 10.0, pe_hi: float = 100.0):
