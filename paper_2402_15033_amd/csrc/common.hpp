@@ -56,6 +56,23 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return x * per + (x < rem ? x : rem) + j;
 }
 
+// sum_{b < count} p[b * stride] in the order b = 0, 1, ...; the loads go in groups of 8
+// issued before their adds (one memory round trip per group instead of one per term).
+__device__ __forceinline__ double sum_strided(const double* p_, size_t stride, int count) {
+  gbl<const double>* __restrict__ p = G(p_);
+  double acc = 0.0;
+  int b = 0;
+  for (; b + 8 <= count; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(b + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; b < count; ++b) acc += p[(size_t)b * stride];
+  return acc;
+}
+
 // Deterministic cross-block reduction, run by ONE block of a separate "tail" kernel
 // (the kernel boundary makes the partials of the streaming kernel visible; no
 // device-scope fence is executed -- on gfx950 such a fence writes back the L2 of
@@ -69,11 +86,7 @@ __device__ void block_sum_partials(const double* __restrict__ part1, int E, int 
                                    double* out, double* scratch) {
   const int tid = threadIdx.x, nt = blockDim.x;
   if (E >= nt || nblocks == 1) {
-    for (int e = tid; e < E; e += nt) {
-      double acc = 0.0;
-      for (int b = 0; b < nblocks; ++b) acc += part1[(size_t)b * E + e];
-      out[e] = acc;
-    }
+    for (int e = tid; e < E; e += nt) out[e] = sum_strided(part1 + e, E, nblocks);
     __syncthreads();
     return;
   }
@@ -82,10 +95,7 @@ __device__ void block_sum_partials(const double* __restrict__ part1, int E, int 
   if (tid < G * E) {
     const int e = tid % E, g = tid / E;
     const int b0 = g * chunk, b1 = min(nblocks, b0 + chunk);
-    double acc = 0.0;
-#pragma unroll 8
-    for (int b = b0; b < b1; ++b) acc += part1[(size_t)b * E + e];
-    scratch[g * E + e] = acc;
+    scratch[g * E + e] = sum_strided(part1 + (size_t)b0 * E + e, E, b1 - b0);
   }
   __syncthreads();
   for (int e = tid; e < E; e += nt) {

@@ -515,11 +515,8 @@ struct PReduceBody {
     if (gated_off(a, st)) return;
     const int E = (a.k + a.sw) * a.nz;
     const int b0 = bid * ra.chunk, b1 = min(a.nblocks, b0 + ra.chunk);
-    for (int e = threadIdx.x; e < E; e += blockDim.x) {
-      double acc = 0.0;
-      for (int b = b0; b < b1; ++b) acc += a.part1[(size_t)b * E + e];
-      ra.part2[(size_t)bid * E + e] = acc;
-    }
+    for (int e = threadIdx.x; e < E; e += blockDim.x)
+      ra.part2[(size_t)bid * E + e] = b1 > b0 ? sum_strided(a.part1 + (size_t)b0 * E + e, E, b1 - b0) : 0.0;
   }
 };
 
