@@ -203,12 +203,12 @@ tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream);
 /* Multicolor Gauss-Seidel set-up for TSG_PRECOND_MCGS: a distance-1 coloring of the
  * pattern by Jones and Plassmann's parallel rounds (priority of row i = output i of the
  * SplitMix64 generator seeded with 0, ties to the higher index; equal to the greedy
- * coloring in decreasing priority), the color order P (rows grouped by color, index order
- * within a color: counting sort of the device-computed colors on the host), the
- * color-ordered system P A P^T (CSR with columns renamed and sorted, its own Gershgorin
- * interval and packed copy) on which preconditioned solves run, and its sweep layout:
- * each color's (contiguous) rows cut into slices of 64 with their off-diagonal entries
- * stored entry by entry.  About 2 x (12 nnz + 24 n) bytes in all; the handle allocates
+ * coloring in decreasing priority), the order P (blocks of 8192 consecutive rows; within
+ * a block the rows grouped by color, index order within a color: counting sort of the
+ * device-computed colors on the host), the reordered system P A P^T (CSR with columns
+ * renamed and sorted, its own Gershgorin interval and packed copy) on which
+ * preconditioned solves run, and its sweep layout: each color's rows (one run per block)
+ * cut into slices of 64 with their lower-color entries stored entry by entry.  About 2 x (12 nnz + 24 n) bytes in all; the handle allocates
  * and owns this device memory (freed by tsg_csr_destroy).  Synchronizes `stream`; a
  * second call does nothing.  The pattern must be structurally symmetric (a_ij stored iff
  * a_ji stored) and every row must store a nonzero diagonal.  From then on solves with
@@ -222,7 +222,7 @@ int32_t tsg_csr_ncolors(tsg_csr A);
 tsg_status tsg_csr_colors(tsg_csr A, int32_t* colors, void* stream);
 
 /* z = M^{-1} w for the handle's multicolor Gauss-Seidel preconditioner (device vectors of
- * n doubles; z must not alias w): w is put in color order, swept as in the solver's
+ * n doubles; z must not alias w): w is put in the order of P A P^T, swept as in the solver's
  * matrix-powers steps, and z put back.  Uses two scratch vectors of the handle: calls on
  * one handle must not overlap. */
 tsg_status tsg_precond_apply(tsg_csr A, const double* w, double* z, void* stream);
@@ -251,7 +251,7 @@ size_t tsg_solve_workspace_bytes(int64_t n, int64_t nnz, const tsg_solve_params*
  * the library's HIP kernels on `stream`; the host only reads back a 72-byte status
  * block once per cycle (the host synchronizes `stream` once per cycle).  Returns after
  * the solve has finished on the device.  precond = MCGS: the solve runs on the operator's
- * color-ordered system (b and x permuted in and out on `stream`).
+ * reordered system P A P^T (b and x permuted in and out on `stream`).
  * Status: OK (converged), NOT_CONVERGED, BREAKDOWN, or a negative error (then x is
  * untouched).  `info` (host) is filled for every non-negative status. */
 tsg_status tsg_solve(tsg_csr A, const double* b, double* x, const tsg_solve_params* p,

@@ -15,11 +15,11 @@
 //             z_i = (w_i - sum_{j: color(j) < color(i)} a_ij z_j) / a_ii (the entries of higher
 //             colors would meet z_j = 0, so they are left out of the layout and z needs no
 //             zeroing).
-//   layout    built once by tsg_csr_precond on the color-ordered system P A P^T (each
-//             color's rows contiguous): each color's rows cut into slices of 64, one wave
+//   layout    built once by tsg_csr_precond on the reordered system P A P^T (rows by
+//             block of 8192, then by color): each color's rows cut into slices of 64, one wave
 //             per slice; a slice stores its rows' lower-color values and columns entry by
-//             entry (entry e of lane l at off + 64 e + l, padded with value 0 at position 0,
-//             a color-0 row whose z is already set), so the wave's loads of the operator, of
+//             entry (entry e of lane l at off + 64 e + l, padded with value 0 at a color-0 row,
+//             whose z is already set), so the wave's loads of the operator, of
 //             w and of z are coalesced 64-wide runs; per lane the row index and the diagonal.
 #pragma once
 
@@ -97,11 +97,11 @@ __global__ __launch_bounds__(1024) void jp_total_kernel(const int32_t* __restric
   if (threadIdx.x == 0) *total = s[0];
 }
 
-// ------------------------------------------------------------------ color-ordered system
-// The preconditioned solve runs on P A P^T with the rows (and columns) in color order, so
-// that each color's rows are contiguous: its sweep reads w and writes z in coalesced runs.
-// Row p of P A P^T is row perm[p] of A with its columns renamed by inv (= perm^{-1}) and
-// sorted.
+// ------------------------------------------------------------------ reordered system
+// The preconditioned solve runs on P A P^T with the rows (and columns) ordered by block of
+// consecutive rows, then by color, so that a color's rows form one run per block: its
+// sweep reads w and writes z in coalesced runs and the gathers stay near.  Row p of
+// P A P^T is row perm[p] of A with its columns renamed by inv (= perm^{-1}) and sorted.
 __global__ __launch_bounds__(256) void permute_csr_kernel(const int32_t* __restrict__ row_ptr,
                                                          const int32_t* __restrict__ col,
                                                          const double* __restrict__ val,
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void permute_csr_kernel(const int32_t* __restr
   }
 }
 
-// dst[p] = src[perm[p]] (into color order) and dst[perm[p]] = src[p] (back).
+// dst[p] = src[perm[p]] (into the order of P A P^T) and dst[perm[p]] = src[p] (back).
 __global__ __launch_bounds__(256) void gather_f64_kernel(const double* __restrict__ src,
                                                         const int32_t* __restrict__ perm, double* __restrict__ dst,
                                                         int64_t n) {
@@ -146,22 +146,19 @@ __global__ __launch_bounds__(256) void gather_i32_kernel(const int32_t* __restri
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < n) dst[p] = src[perm[p]];
 }
-__global__ __launch_bounds__(256) void iota_kernel(int32_t* __restrict__ a, int64_t n) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n) a[p] = (int32_t)p;
-}
 
 // ------------------------------------------------------------------ sweep layout (set-up)
-// Per slice s (64 positions p0 .. p0+63 of the color permutation, cut at color ends):
-// width[s] = the largest count of its rows' entries in lower colors.  On the color-ordered
-// system those are exactly the columns below the first position of the row's color, clo[s]:
-// the sweep needs only them (the entries of higher colors meet z = 0), so it needs no zeroing.
+// Per slice s (64 consecutive entries p0 .. p0+63 of the list of one color's rows, perm):
+// width[s] = the largest count of its rows' entries whose column has a lower color than
+// the slice's, sclr[s] (colors: per row of the system swept).  The sweep needs only those
+// (the entries of higher colors meet z = 0), so it needs no zeroing pass.
 __global__ __launch_bounds__(256) void gs_analyze_kernel(const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ col,
                                                         const int32_t* __restrict__ perm,
                                                         const int64_t* __restrict__ sstart,
                                                         const int64_t* __restrict__ send,
-                                                        const int64_t* __restrict__ clo, int64_t nslices,
+                                                        const int64_t* __restrict__ sclr,
+                                                        const int32_t* __restrict__ colors, int64_t nslices,
                                                         int32_t* __restrict__ width) {
   const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
@@ -170,7 +167,7 @@ __global__ __launch_bounds__(256) void gs_analyze_kernel(const int32_t* __restri
   int cnt = 0;
   if (p < send[s]) {
     const int32_t i = perm[p];
-    for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) cnt += col[q] < clo[s];
+    for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) cnt += colors[col[q]] < sclr[s];
   }
   for (int o = kWave / 2; o > 0; o >>= 1) cnt = max(cnt, __shfl_xor(cnt, o, kWave));
   if (lane == 0) width[s] = cnt;
@@ -183,11 +180,13 @@ __global__ __launch_bounds__(256) void gs_fill_kernel(const int32_t* __restrict_
                                                      const int32_t* __restrict__ perm,
                                                      const int64_t* __restrict__ sstart,
                                                      const int64_t* __restrict__ send,
-                                                     const int64_t* __restrict__ clo,
+                                                     const int64_t* __restrict__ sclr,
+                                                     const int32_t* __restrict__ colors,
                                                      const int64_t* __restrict__ eoff,
                                                      const int32_t* __restrict__ width, int64_t nslices,
-                                                     int32_t* __restrict__ prow, double* __restrict__ diag,
-                                                     double* __restrict__ gval, int32_t* __restrict__ gcol) {
+                                                     int32_t padcol, int32_t* __restrict__ prow,
+                                                     double* __restrict__ diag, double* __restrict__ gval,
+                                                     int32_t* __restrict__ gcol) {
   const int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (s >= nslices) return;
@@ -201,16 +200,16 @@ __global__ __launch_bounds__(256) void gs_fill_kernel(const int32_t* __restrict_
     for (int q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
       if (col[q] == i) {
         d = val[q];
-      } else if (col[q] < clo[s]) {
+      } else if (colors[col[q]] < sclr[s]) {
         gval[e0 + (int64_t)kWave * e + lane] = val[q];
         gcol[e0 + (int64_t)kWave * e + lane] = col[q];
         ++e;
       }
     }
   }
-  for (; e < wd; ++e) {  // padding: value 0 at position 0 (color 0, swept first: finite)
+  for (; e < wd; ++e) {  // padding: value 0 at a row of color 0 (swept first: z finite)
     gval[e0 + (int64_t)kWave * e + lane] = 0.0;
-    gcol[e0 + (int64_t)kWave * e + lane] = 0;
+    gcol[e0 + (int64_t)kWave * e + lane] = padcol;
   }
   prow[slot] = i;
   diag[slot] = d;

@@ -41,12 +41,13 @@ struct tsg_csr_s {
   int ncolors = 0;
   void* gs_mem = nullptr;
   const int32_t* colors = nullptr;
-  // the color-ordered system P A P^T the preconditioned solve runs on (its own handle with
-  // the sweep layout), the permutation and its scratch; memory owned by this handle
+  // the reordered system P A P^T the preconditioned solve runs on (rows by block, then by
+  // color: its own handle with the sweep layout), the permutation and its scratch; memory
+  // owned by this handle
   tsg_csr_s* pa = nullptr;
   void* own_mem = nullptr;
   void* pa_pack = nullptr;
-  const int32_t* perm = nullptr;  // position p in color order holds row perm[p]
+  const int32_t* perm = nullptr;  // position p of P A P^T holds row perm[p] of A
   double* gs_tmp = nullptr;       // 2 n doubles for tsg_precond_apply
   const int32_t* gs_prow = nullptr;
   const double* gs_diag = nullptr;
@@ -231,6 +232,7 @@ struct Timer {
 int s_template(int sw) { return sw <= 6 ? sw : (sw <= 8 ? 8 : (sw <= 10 ? 10 : (sw <= 12 ? 12 : 16))); }
 constexpr int kMaxGramNz = kMaxNz;   // widest lean reduction (two 16-wide MFMA tiles)
 constexpr int kMaxMfmaBlocks = 512;  // two 8-wave blocks per CU
+constexpr int64_t kGsBlock = 8192;   // rows per block of the preconditioned system's order
 static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks, "reduction partial buffer too small");
 // Device bytes reserved for the launch image of one request's program.
 constexpr size_t kProgramBytesPerRequest = 512 * 1024;
@@ -386,7 +388,7 @@ struct ReqCtx {
   const int32_t* colors = nullptr;
   double* zp = nullptr;          // M^{-1} w of the current step; M^{-1} t of the cycle update
   double* tp = nullptr;          // V coef of the cycle update
-  double* bp = nullptr;          // b and x in color order (the solve runs on P A P^T)
+  double* bp = nullptr;          // P b and P x (the solve runs on P A P^T)
   double* xp = nullptr;
 };
 
@@ -950,16 +952,19 @@ tsg_status tsg_spmv(tsg_csr A, const double* x, double* y, void* stream) {
 
 namespace {
 
-// The sweep layout of handle H whose rows in color order are perm[off[c] .. off[c+1]):
-// slices of 64 per color, widths, entry offsets, then the fill (device memory owned by H).
-tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, const int32_t* perm, hipStream_t s) {
+// The sweep layout of handle H: the rows of color c are perm[off[c] .. off[c+1]) (rows of
+// H, in increasing order); colors: the color of every row of H (device); padcol: a row of
+// color 0.  Slices of 64 per color, widths, entry offsets, then the fill (device memory
+// owned by H).
+tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, const int32_t* perm,
+                              const int32_t* colors, int32_t padcol, hipStream_t s) {
   const int ncol = (int)off.size() - 1;
   std::vector<int64_t> sl((size_t)ncol + 1, 0), ss, se, sc;
   for (int c = 0; c < ncol; ++c) {
     for (int64_t p = off[c]; p < off[c + 1]; p += kWave) {
       ss.push_back(p);
       se.push_back(std::min<int64_t>(p + kWave, off[c + 1]));
-      sc.push_back(off[c]);  // columns below the color's first position are lower colors
+      sc.push_back(c);
     }
     sl[c + 1] = (int64_t)ss.size();
   }
@@ -979,7 +984,7 @@ tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, con
   if (e == hipSuccess) e = hipMemcpyAsync(dsc, sc.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(gs_analyze_kernel, dim3(cdiv(ns * kWave, 256)), dim3(256), 0, s, H->row_ptr, H->col, perm,
-                       dss, dse, dsc, ns, dwd);
+                       dss, dse, dsc, colors, ns, dwd);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(wh.data(), dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s);
@@ -1010,7 +1015,7 @@ tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, con
   if (e == hipSuccess) e = hipMemcpyAsync(gwd, dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(gs_fill_kernel, dim3(cdiv(ns * kWave, 256)), dim3(256), 0, s, H->row_ptr, H->col, H->val, perm,
-                       dss, dse, dsc, deo, dwd, ns, prow, diag, gval, gcol);
+                       dss, dse, dsc, colors, deo, dwd, ns, padcol, prow, diag, gval, gcol);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1072,8 +1077,13 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
       return bail(fail(TSG_ERR_HIP, "coloring round failed"));
     std::swap(cold, cnew);
   }
-  // ---- color order (index order within a color: counting sort on the host), its
-  // inverse, and the row pointers of P A P^T
+  // ---- the order of P A P^T: blocks of kGsBlock consecutive rows, within a block the
+  // rows by color, within a color in index order (counting sort on the host).  A color's
+  // rows are then one segment per block: the SpMV's and the sweep's gathers stay within a
+  // block and its neighbours (L2-resident, and column distances small enough for the
+  // packed operator's 16-bit deltas on banded operators), while the rows of one color
+  // still do not couple.  Also its inverse, the row pointers of P A P^T, and per color
+  // the list of its rows' positions (the sweep's row lists).
   std::vector<int32_t> ch((size_t)n), ph((size_t)n), ih((size_t)n), rp((size_t)n + 1), rpp((size_t)n + 1);
   if (hipMemcpyAsync(ch.data(), cold, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(rp.data(), A->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -1081,20 +1091,34 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
     return bail(fail(TSG_ERR_HIP, "reading the colors failed"));
   int ncol = 0;
   for (int64_t i = 0; i < n; ++i) ncol = std::max(ncol, ch[i] + 1);
-  std::vector<int64_t> off((size_t)ncol + 1, 0);
-  for (int64_t i = 0; i < n; ++i) off[ch[i] + 1] += 1;
-  for (int c = 0; c < ncol; ++c) off[c + 1] += off[c];
+  const int64_t nblk = cdiv(n, kGsBlock);
+  std::vector<int64_t> koff((size_t)(nblk * ncol) + 1, 0);
+  for (int64_t i = 0; i < n; ++i) koff[(i / kGsBlock) * ncol + ch[i] + 1] += 1;
+  for (int64_t k = 0; k < nblk * ncol; ++k) koff[k + 1] += koff[k];
   {
-    std::vector<int64_t> pos(off.begin(), off.end() - 1);
-    for (int64_t i = 0; i < n; ++i) ph[pos[ch[i]]++] = (int32_t)i;
+    std::vector<int64_t> pos(koff.begin(), koff.end() - 1);
+    for (int64_t i = 0; i < n; ++i) ph[pos[(i / kGsBlock) * ncol + ch[i]]++] = (int32_t)i;
   }
   rpp[0] = 0;
   for (int64_t p = 0; p < n; ++p) {
     ih[ph[p]] = (int32_t)p;
     rpp[p + 1] = rpp[p] + (rp[ph[p] + 1] - rp[ph[p]]);
   }
-  // ---- owned block: colors (index order), perm, inv, P A P^T (CSR), colors in color
-  // order, identity, two scratch vectors
+  std::vector<int64_t> off((size_t)ncol + 1, 0);
+  for (int64_t i = 0; i < n; ++i) off[ch[i] + 1] += 1;
+  for (int c = 0; c < ncol; ++c) off[c + 1] += off[c];
+  std::vector<int32_t> rows_by_color((size_t)n);
+  int32_t padcol = -1;
+  {
+    std::vector<int64_t> pos(off.begin(), off.end() - 1);
+    for (int64_t p = 0; p < n; ++p) {
+      const int c = ch[ph[p]];
+      rows_by_color[pos[c]++] = (int32_t)p;
+      if (c == 0 && padcol < 0) padcol = (int32_t)p;
+    }
+  }
+  // ---- owned block: colors (index order), perm, inv, P A P^T (CSR), colors of its rows,
+  // the sweep's row lists, two scratch vectors
   const size_t obytes = 6 * align_up(4 * (size_t)n + 4) + align_up(4 * (size_t)std::max<int64_t>(nnz, 1)) +
                         align_up(8 * (size_t)std::max<int64_t>(nnz, 1)) + align_up(16 * (size_t)n) + kAlign;
   if (hipMalloc(&own, obytes) != hipSuccess) return bail(fail(TSG_ERR_HIP, "hipMalloc of the preconditioner failed"));
@@ -1104,7 +1128,7 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
   int32_t* inv = oc.take<int32_t>((size_t)n);
   int32_t* row_ptr_p = oc.take<int32_t>((size_t)n + 1);
   int32_t* colors_p = oc.take<int32_t>((size_t)n);
-  int32_t* iota = oc.take<int32_t>((size_t)n);
+  int32_t* rlist = oc.take<int32_t>((size_t)n);
   int32_t* col_p = oc.take<int32_t>((size_t)std::max<int64_t>(nnz, 1));
   double* val_p = oc.take<double>((size_t)std::max<int64_t>(nnz, 1));
   double* tmp = oc.take<double>(2 * (size_t)n);
@@ -1112,11 +1136,11 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
   if (e == hipSuccess) e = hipMemcpyAsync(perm, ph.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(inv, ih.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(row_ptr_p, rpp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(rlist, rows_by_color.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(permute_csr_kernel, dim3(nb), dim3(256), 0, s, A->row_ptr, A->col, A->val, perm, inv, n,
                        row_ptr_p, col_p, val_p);
     hipLaunchKernelGGL(gather_i32_kernel, dim3(nb), dim3(256), 0, s, colors, perm, colors_p, n);
-    hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(256), 0, s, iota, n);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1126,7 +1150,7 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
   const size_t pk = tsg_csr_pack_bytes(pa);
   if (hipMalloc(&pack, pk) != hipSuccess) return bail(fail(TSG_ERR_HIP, "hipMalloc of the packed copy failed"));
   TRY_OR(tsg_csr_pack(pa, pack, pk, stream), bail);
-  TRY_OR(build_sweep_layout(pa, off, iota, s), bail);
+  TRY_OR(build_sweep_layout(pa, off, rlist, colors_p, padcol, s), bail);
   HIP_TRY(hipStreamSynchronize(s));
   (void)hipFree(scratch);
   pa->colors = colors_p;
