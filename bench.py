@@ -101,8 +101,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on exactly one GPU (the whole problem fits one MI355X); "
-              "multi-GPU runs are not part of it", file=sys.stderr)
+        print("bench.py: the solver runs on exactly one GPU (the whole problem fits one MI355X); "
+              "multi-GPU runs are not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -204,7 +204,7 @@ def main():
         "mpk": f"MpkBody<{elem}, {elem}, {fmt}>",
         "gram": f"GramBody<{elem}, 1..4, {nt2}>",
         "gram_first": f"GramBody<{elem}, {(args.s + 16) // 16}, {(args.s + 16) // 16}>",
-        "update": f"UpdateBody<{elem}, {st_(s_)}>",
+        "update": f"UpdateBody<{elem}, {st_(s_)}, false>",
         "fused": f"FusedBody<{elem}, 4>",
     }
     streaming = {c: v for c, v in classes.items() if c in names and v[0] > 0}

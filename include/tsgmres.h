@@ -38,7 +38,7 @@ typedef enum {
   TSG_ERR_INVALID_ARG = -1, /* bad sizes / NULL pointers / unsupported combination    */
   TSG_ERR_HIP = -2,         /* a HIP runtime call failed (message in tsg_last_error)  */
   TSG_ERR_WORKSPACE = -3,   /* workspace too small or misaligned (256-byte alignment) */
-  TSG_ERR_UNSUPPORTED = -4  /* valid request outside what this build implements       */
+  TSG_ERR_UNSUPPORTED = -4  /* valid request outside what the library implements     */
 } tsg_status;
 
 /* Block orthogonalization scheme used inside a restart cycle.
