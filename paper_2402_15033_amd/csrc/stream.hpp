@@ -227,11 +227,22 @@ __device__ __forceinline__ void upd_group(gbl<T>* __restrict__ V, int64_t ld, in
     for (int j = 0; j < S; ++j) y[j] -= q[u] * (T)P[c0 + u + j * kLd];
 }
 
-// Row r of W <- (W - Q P) T in place (PF_HAS_P / PF_HAS_T): every lane reads its row of the
-// k + sw columns (each wave access is a coalesced 64-row segment of one column), P and T
-// are uniform (scalar loads).  No LDS, no barrier, high occupancy.
+// W <- (W - Q P) T in place (PF_HAS_P / PF_HAS_T), one row per thread: every lane reads
+// its row of the k + sw columns (each wave access is a coalesced 64-row segment of one
+// column), P and T are uniform (scalar loads).  No LDS, no barrier, high occupancy.
 template <typename T, int S>
-__device__ __forceinline__ void update_row(const PanelArgs& a, gbl<const SmallState>* st, const int64_t r) {
+struct UpdateBody {
+  typedef PanelArgs Args;
+  static constexpr int kThreads = 256;
+  static constexpr int kMinWaves = 1;
+  static __device__ void run(const PanelArgs& a, int bid, int nb);
+};
+template <typename T, int S>
+__device__ void UpdateBody<T, S>::run(const PanelArgs& a, int bid, int) {
+  if (gated_off(a, a.st)) return;
+  gbl<const SmallState>* st = G(a.st);
+  const int64_t r = (int64_t)bid * blockDim.x + threadIdx.x;
+  if (r >= a.n) return;
   const int k = a.k, sw = a.sw;
   const bool hasP = a.flags & PF_HAS_P;
   const bool hasT = (a.flags & PF_HAS_T) && !st->identity_t;
@@ -277,29 +288,7 @@ __device__ __forceinline__ void update_row(const PanelArgs& a, gbl<const SmallSt
     if (j < sw) W[(int64_t)j * ld] = y[j];
 }
 
-// kRange = false: one row per thread, blocks of blockDim.x rows.  kRange = true: each block
-// takes rows_per_block rows, blockDim.x at a time -- used for the gated second pass, which
-// almost always returns at entry, so that fewer blocks are dispatched then.
-template <typename T, int S, bool kRange>
-struct UpdateBody {
-  typedef PanelArgs Args;
-  static constexpr int kThreads = 256;
-  static constexpr int kMinWaves = 1;
-  static __device__ void run(const PanelArgs& a, int bid, int nb);
-};
-template <typename T, int S, bool kRange>
-__device__ void UpdateBody<T, S, kRange>::run(const PanelArgs& a, int bid, int) {
-  if (gated_off(a, a.st)) return;
-  gbl<const SmallState>* st = G(a.st);
-  if constexpr (kRange) {
-    const int64_t rend = min(a.n, (int64_t)(bid + 1) * a.rows_per_block);
-    for (int64_t r = (int64_t)bid * a.rows_per_block + threadIdx.x; r < rend; r += blockDim.x)
-      update_row<T, S>(a, st, r);
-  } else {
-    const int64_t r = (int64_t)bid * blockDim.x + threadIdx.x;
-    if (r < a.n) update_row<T, S>(a, st, r);
-  }
-}
+
 
 // The fused panel step on the matrix cores: per row, the update
 //     q = (W(r,:) - Q(r,:) P) T          (PF_HAS_P / PF_HAS_T; Q = V(:,0:k), W = V(:,wcol:+sw))
