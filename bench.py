@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="mean arrivals per second")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-seed", type=int, default=0)
+    ap.add_argument("--serve-sides", default="128,256,512,1024,2048",
+                    help="grid sides the served requests draw from (uniformly)")
     ap.add_argument("--compare", action="store_true",
                     help="also time one solve of each other orthogonalization scheme")
     args = ap.parse_args()
@@ -381,7 +383,8 @@ def serve_bench(args, tsg, W, np, torch, dev):
     R = args.serve_requests
     gaps = rng.exponential(1.0 / args.serve_rate, size=R)
     arrival = np.cumsum(gaps) - gaps[0]
-    sides = rng.choice([128, 256, 512, 1024, 2048], size=R)
+    side_set = [int(v) for v in args.serve_sides.split(",")]
+    sides = rng.choice(side_set, size=R)
     kinds = np.where(rng.random(R) < 0.5, "laplace2d", "convdiff2d")
     log(f"[serve] building {R} requests")
     reqs = []
@@ -434,10 +437,10 @@ def serve_bench(args, tsg, W, np, torch, dev):
         per.setdefault(key, []).append(float(lat[i]))
     out = {
         "metric": "served solves/s and p50/p99 latency (Poisson mix of 2D Laplace / convection-diffusion "
-                  "128^2..2048^2, FP32+FP64 refinement, tol 1e-8)",
+                  f"{min(side_set)}^2..{max(side_set)}^2, FP32+FP64 refinement, tol 1e-8)",
         "value": round(R / makespan, 4), "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "Poisson arrivals, grid side uniform in {128,256,512,1024,2048}, half 2D Laplace "
+        "config": {"workload": f"Poisson arrivals, grid side uniform in {{{args.serve_sides}}}, half 2D Laplace "
                                "and half upwind convection-diffusion (Pe~U[1,100]), b~U(-1,1), m=60, s=5, "
                                "two-stage, shifted basis, FP32 basis + FP64 refinement, tol 1e-8",
                    "requests": R, "arrival_rate_per_s": args.serve_rate, "hbm_budget_gb": args.serve_budget_gb,
