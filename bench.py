@@ -206,7 +206,7 @@ def main():
         "mpk": f"MpkBody<{elem}, {elem}, {fmt}>",
         "gram": f"GramBody<{elem}, 1..4, {nt2}>",
         "gram_first": f"GramBody<{elem}, {(args.s + 16) // 16}, {(args.s + 16) // 16}>",
-        "update": f"UpdateBody<{elem}, {st_(s_)}>",
+        "update": f"UpdateBody<{elem}, {st_(s_)}, 128>",
         "fused": f"FusedBody<{elem}, 4>",
     }
     streaming = {c: v for c, v in classes.items() if c in names and v[0] > 0}

@@ -230,15 +230,18 @@ __device__ __forceinline__ void upd_group(gbl<T>* __restrict__ V, int64_t ld, in
 // W <- (W - Q P) T in place (PF_HAS_P / PF_HAS_T), one row per thread: every lane reads
 // its row of the k + sw columns (each wave access is a coalesced 64-row segment of one
 // column), P and T are uniform (scalar loads).  No LDS, no barrier, high occupancy.
-template <typename T, int S>
+// Blocks of kBlock rows: 128 (measured faster than 256 or more), 256 for the gated second
+// pass, which almost always returns at entry (half the blocks to dispatch then; 1024-row
+// blocks were no faster there).
+template <typename T, int S, int kBlock>
 struct UpdateBody {
   typedef PanelArgs Args;
-  static constexpr int kThreads = 256;
+  static constexpr int kThreads = kBlock;
   static constexpr int kMinWaves = 1;
   static __device__ void run(const PanelArgs& a, int bid, int nb);
 };
-template <typename T, int S>
-__device__ void UpdateBody<T, S>::run(const PanelArgs& a, int bid, int) {
+template <typename T, int S, int kBlock>
+__device__ void UpdateBody<T, S, kBlock>::run(const PanelArgs& a, int bid, int) {
   if (gated_off(a, a.st)) return;
   gbl<const SmallState>* st = G(a.st);
   const int64_t r = (int64_t)bid * blockDim.x + threadIdx.x;

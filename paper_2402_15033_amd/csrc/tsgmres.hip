@@ -287,6 +287,21 @@ void launch_b(const Phase& ph, const char* d, int nreq, hipStream_t s) {
                      reinterpret_cast<const typename Body::Args*>(d + ph.aoff),
                      reinterpret_cast<const int*>(d + ph.boff), nreq);
 }
+template <typename T, int B>
+void launch_update(const Phase& ph, const char* d, int nreq, hipStream_t s) {
+  switch (ph.t1) {
+    case 1: launch_b<UpdateBody<T, 1, B>>(ph, d, nreq, s); break;
+    case 2: launch_b<UpdateBody<T, 2, B>>(ph, d, nreq, s); break;
+    case 3: launch_b<UpdateBody<T, 3, B>>(ph, d, nreq, s); break;
+    case 4: launch_b<UpdateBody<T, 4, B>>(ph, d, nreq, s); break;
+    case 5: launch_b<UpdateBody<T, 5, B>>(ph, d, nreq, s); break;
+    case 6: launch_b<UpdateBody<T, 6, B>>(ph, d, nreq, s); break;
+    case 8: launch_b<UpdateBody<T, 8, B>>(ph, d, nreq, s); break;
+    case 10: launch_b<UpdateBody<T, 10, B>>(ph, d, nreq, s); break;
+    case 12: launch_b<UpdateBody<T, 12, B>>(ph, d, nreq, s); break;
+    default: launch_b<UpdateBody<T, 16, B>>(ph, d, nreq, s); break;
+  }
+}
 template <typename T, int MT>
 void launch_gram_mt(const Phase& ph, const char* d, int nreq, hipStream_t s) {
   if (ph.t2 == 1) launch_b<GramBody<T, MT, 1>>(ph, d, nreq, s);
@@ -315,18 +330,8 @@ void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
     case F_AXPY: launch_b<AxpyBody>(ph, d, nreq, s); break;
     case F_XUPD: launch_b<XupdBody<T>>(ph, d, nreq, s); break;
     case F_UPDATE:
-      switch (ph.t1) {
-        case 1: launch_b<UpdateBody<T, 1>>(ph, d, nreq, s); break;
-        case 2: launch_b<UpdateBody<T, 2>>(ph, d, nreq, s); break;
-        case 3: launch_b<UpdateBody<T, 3>>(ph, d, nreq, s); break;
-        case 4: launch_b<UpdateBody<T, 4>>(ph, d, nreq, s); break;
-        case 5: launch_b<UpdateBody<T, 5>>(ph, d, nreq, s); break;
-        case 6: launch_b<UpdateBody<T, 6>>(ph, d, nreq, s); break;
-        case 8: launch_b<UpdateBody<T, 8>>(ph, d, nreq, s); break;
-        case 10: launch_b<UpdateBody<T, 10>>(ph, d, nreq, s); break;
-        case 12: launch_b<UpdateBody<T, 12>>(ph, d, nreq, s); break;
-        default: launch_b<UpdateBody<T, 16>>(ph, d, nreq, s); break;
-      }
+      if (ph.t2) launch_update<T, 256>(ph, d, nreq, s);
+      else launch_update<T, 128>(ph, d, nreq, s);
       break;
     case F_GRAM:
       switch (ph.t1) {
@@ -488,8 +493,8 @@ struct Builder {
       x.shifted = shifted;
       double cols;
       if (st.kind == PK_UPDATE) {
-        nb[r] = (int)cdiv(q.n, 256);
-        x.rows_per_block = 256;
+        x.rows_per_block = st.gate >= 2 ? 256 : 128;  // the kernel's block (see UpdateBody)
+        nb[r] = (int)cdiv(q.n, x.rows_per_block);
         cols = ((st.flags & PF_HAS_P) ? st.k : 0) + 2.0 * st.sw;
       } else {
         const int rpl = P.f32 ? tile_rows_per_lane<float>() : tile_rows_per_lane<double>();
@@ -511,7 +516,7 @@ struct Builder {
     if (kc < 0) kc = st.kind == PK_UPDATE ? TSG_KC_UPDATE : (gram ? (st.nprev > 0 ? TSG_KC_GRAM : TSG_KC_GRAM_FIRST) : TSG_KC_FUSED);
     const bool fb = kc == TSG_KC_FALLBACK;
     if (st.kind == PK_UPDATE) {
-      P.add(F_UPDATE, s_template(st.sw), 0, a, nb, kc, fb ? 0.0 : bytes);
+      P.add(F_UPDATE, s_template(st.sw), st.gate >= 2 ? 1 : 0, a, nb, kc, fb ? 0.0 : bytes);
     } else if (gram) {
       P.add(F_GRAM, (st.k + st.sw + 15) / 16, nz <= 16 ? 1 : 2, a, nb, kc, fb ? 0.0 : bytes);
     } else {
