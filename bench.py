@@ -79,9 +79,9 @@ def main():
     ap.add_argument("--no-ortho-bench", action="store_true")
     ap.add_argument("--ortho-reps", type=int, default=20)
     ap.add_argument("--cpu-cycles", type=int, default=1)
-    ap.add_argument("--time-stride", type=int, default=8,
+    ap.add_argument("--time-stride", type=int, default=16,
                     help="HIP-event timing of every launch in every n-th restart cycle of the timed "
-                         "solves (1 = every cycle; events between launches slow a cycle by ~7%%)")
+                         "solves (1 = every cycle; events between launches slow a cycle by ~12%%)")
     ap.add_argument("--eager", action="store_true",
                     help="launch every kernel directly instead of replaying one captured cycle")
     ap.add_argument("--modes", action="store_true",
