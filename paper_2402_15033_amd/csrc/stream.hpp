@@ -371,7 +371,8 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
   for (int mt = 0; mt < MT; ++mt) acc[mt] = v4{0, 0, 0, 0};
   const int li = lane & 15, lk = lane >> 4;
   const int ksteps_upd = (ncol + 3) / 4;
-  // prefetch depth 2 with three register buffers taking turns (as in GramBody)
+  // prefetch depth 2 with three register buffers taking turns, loop unrolled by 6 (as in
+  // GramBody)
   int buf = 0;
   auto batch = [&](const T (&cur)[SL][R], T (&fut)[SL][R], int64_t r0) {
     tl.load(V, wv, lane, r0 + 2 * BR, re, fut);
@@ -420,12 +421,18 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
   };
   tl.load(V, wv, lane, rb, re, v);
   tl.load(V, wv, lane, rb + BR, re, vn);
-  for (int64_t r0 = rb; r0 < re; r0 += 3 * BR) {
+  for (int64_t r0 = rb; r0 < re; r0 += 6 * BR) {
     batch(v, vnn, r0);
     if (r0 + BR >= re) break;
     batch(vn, v, r0 + BR);
     if (r0 + 2 * BR >= re) break;
     batch(vnn, vn, r0 + 2 * BR);
+    if (r0 + 3 * BR >= re) break;
+    batch(v, vnn, r0 + 3 * BR);
+    if (r0 + 4 * BR >= re) break;
+    batch(vn, v, r0 + 4 * BR);
+    if (r0 + 5 * BR >= re) break;
+    batch(vnn, vn, r0 + 5 * BR);
   }
   if (!gram) return;
   __syncthreads();
