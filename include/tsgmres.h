@@ -278,6 +278,23 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
                              int32_t s, int32_t s_hat, int32_t algo, void* workspace,
                              size_t ws_bytes, void* stream, double* orth_err /* host, opt */);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): tsg_orthogonalize without a workspace
+ * argument.  Same arguments, layout, results (bit for bit) and status codes as
+ * tsg_orthogonalize; the workspace is instead a file-scope device array of
+ * tsg_orthogonalize_noalloc_max_bytes() = 12 MiB that every GPU the library runs on holds
+ * until the process ends (its address on the current device is looked up once, on the first
+ * call there).  The call makes no device allocation.  Limits: n <= 268,435,456 rows (and the
+ * limits of tsg_orthogonalize); larger n returns INVALID_ARG with a message, before any device
+ * work.  Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * host threads, or other streams before this call has returned) race and give wrong results;
+ * the call synchronizes `stream` before returning, so calls made one after another from one
+ * thread are safe.  X, R and `stream` must belong to the current device. */
+size_t tsg_orthogonalize_noalloc_max_bytes(void);
+tsg_status tsg_orthogonalize_noalloc(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr,
+                                     int32_t s, int32_t s_hat, int32_t algo, void* stream,
+                                     double* orth_err /* host, opt */);
+
 /* ---------------------------------------------------------------- solve server
  * Continuous batching of many solves (different operators and sizes) that share one
  * tsg_solve_params (m, s, ortho, basis monomial or shifted, precision, tol, max_iters;

@@ -132,6 +132,10 @@ def load_library():
     lib.tsg_orthogonalize_workspace_bytes.restype = C.c_size_t
     lib.tsg_orthogonalize.argtypes = [i64, i32, vp, i64, vp, i32, i32, i32, i32, vp, C.c_size_t, vp, f64p]
     lib.tsg_orthogonalize.restype = C.c_int
+    lib.tsg_orthogonalize_noalloc.argtypes = [i64, i32, vp, i64, vp, i32, i32, i32, i32, vp, f64p]
+    lib.tsg_orthogonalize_noalloc.restype = C.c_int
+    lib.tsg_orthogonalize_noalloc_max_bytes.argtypes = []
+    lib.tsg_orthogonalize_noalloc_max_bytes.restype = C.c_size_t
     lib.tsg_server_request_bytes.argtypes = [i64, i64, C.POINTER(_Params)]
     lib.tsg_server_request_bytes.restype = C.c_size_t
     lib.tsg_server_create.argtypes = [C.POINTER(_Params), vp, C.c_size_t, i32, vp, C.POINTER(vp)]
@@ -371,15 +375,8 @@ def solve(A: CSRMatrix, b: torch.Tensor, x: torch.Tensor | None = None, *, m: in
     return x, out
 
 
-def orthogonalize(X: torch.Tensor, s: int = 5, algo: str = "two_stage", *, ldx: int | None = None,
-                  orth_err: bool = False, workspace: torch.Tensor | None = None):
-    """Orthonormalize the n x k block in place.
-
-    X is a float64 device tensor viewed as column-major: either a (k, ldx) contiguous tensor
-    whose row c is column c of the block, or an (n, k) tensor with stride (1, ldx) (e.g. the
-    transpose of a contiguous (k, n) tensor).  Returns (X, R[, ||I - Q^T Q||_F]).
-    """
-    lib = load_library()
+def _block_view(X: torch.Tensor, ldx):
+    """(n, k, ld) of a float64 device tensor viewed as a column-major block."""
     if X.dim() != 2 or X.dtype != torch.float64 or X.device.type != "cuda":
         raise ValueError("X must be a 2-D float64 device tensor")
     if X.stride(0) == 1:  # (n, k) column-major view
@@ -392,17 +389,37 @@ def orthogonalize(X: torch.Tensor, s: int = 5, algo: str = "two_stage", *, ldx: 
         n = min(n, X.shape[1])
     else:
         raise ValueError("X must be column-major")
+    return n, k, ld
+
+
+def orthogonalize(X: torch.Tensor, s: int = 5, algo: str = "two_stage", *, ldx: int | None = None,
+                  orth_err: bool = False, workspace: torch.Tensor | None = None, noalloc: bool = False):
+    """Orthonormalize the n x k block in place.
+
+    X is a float64 device tensor viewed as column-major: either a (k, ldx) contiguous tensor
+    whose row c is column c of the block, or an (n, k) tensor with stride (1, ldx) (e.g. the
+    transpose of a contiguous (k, n) tensor).  Returns (X, R[, ||I - Q^T Q||_F]).
+    noalloc=True calls tsg_orthogonalize_noalloc (the library's own static scratch, no
+    workspace).
+    """
+    lib = load_library()
+    n, k, ld = _block_view(X, ldx)
     R = torch.zeros((k, k), dtype=torch.float64, device=X.device)  # column-major: R_t[j, i] = R[i, j]
-    need = int(lib.tsg_orthogonalize_workspace_bytes(n, k, s))
-    if need == 0:
-        _check(-1)
-    ws, wp = _workspace(need, X.device, workspace)
+    a = ORTHO[algo] if isinstance(algo, str) else int(algo)
     err = C.c_double(0.0)
-    st = lib.tsg_orthogonalize(n, k, X.data_ptr(), ld, R.data_ptr(), k, int(s), 0,
-                               ORTHO[algo] if isinstance(algo, str) else int(algo), wp, need,
-                               _stream(X.device), C.byref(err) if orth_err else None)
-    _check(st)
-    del ws
+    if noalloc:
+        st = lib.tsg_orthogonalize_noalloc(n, k, X.data_ptr(), ld, R.data_ptr(), k, int(s), 0, a,
+                                           _stream(X.device), C.byref(err) if orth_err else None)
+        _check(st)
+    else:
+        need = int(lib.tsg_orthogonalize_workspace_bytes(n, k, s))
+        if need == 0:
+            _check(-1)
+        ws, wp = _workspace(need, X.device, workspace)
+        st = lib.tsg_orthogonalize(n, k, X.data_ptr(), ld, R.data_ptr(), k, int(s), 0, a, wp, need,
+                                   _stream(X.device), C.byref(err) if orth_err else None)
+        _check(st)
+        del ws
     Rt = R.t()  # R was written column-major
     if orth_err:
         return X, Rt, err.value

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1577,10 +1578,12 @@ size_t tsg_orthogonalize_workspace_bytes(int64_t n, int32_t k, int32_t s) {
   return cb + kProgramBytesPerRequest + kAlign;
 }
 
-tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr,
-                             int32_t s, int32_t s_hat, int32_t algo, void* workspace, size_t ws_bytes,
-                             void* stream, double* orth_err) {
-  if (!X || !R || !workspace) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+namespace {
+
+// Argument checks shared by the stand-alone orthogonalization entry points (host only).
+tsg_status orthogonalize_check(int64_t n, int32_t k, const double* X, int64_t ldx, const double* R, int32_t ldr,
+                               int32_t s, int32_t s_hat, int32_t algo) {
+  if (!X || !R) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
   if (n < 1 || k < 1 || k > kMaxCols || k > n)
     return fail(TSG_ERR_INVALID_ARG, "need 1 <= k <= min(n, 64): n=%lld k=%d", (long long)n, k);
   if (ldx < n || ldr < k) return fail(TSG_ERR_INVALID_ARG, "leading dimension too small");
@@ -1589,13 +1592,16 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
     return fail(TSG_ERR_INVALID_ARG, "bad algo %d", algo);
   if (algo == TSG_ORTHO_TWO_STAGE && s_hat != 0 && s_hat != k - 1)
     return fail(TSG_ERR_UNSUPPORTED, "s_hat=%d: only one big panel (s_hat = k-1) is built", s_hat);
-  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
-    return fail(TSG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
-  size_t need = tsg_orthogonalize_workspace_bytes(n, k, s);
-  if (need == 0) return fail(TSG_ERR_INVALID_ARG, "problem too large for the reduction buffers");
-  if (ws_bytes < need) return fail(TSG_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, need);
-  hipStream_t st = (hipStream_t)stream;
-  Carve cv{(char*)workspace};
+  return TSG_OK;
+}
+
+// The stand-alone orthogonalization on a checked workspace `ws` of at least
+// tsg_orthogonalize_workspace_bytes(n, k, s) bytes (256-byte aligned): every buffer of the
+// call (small state, reduction partials, launch image) is carved from it, and everything
+// read before it is written is initialized here.
+tsg_status orthogonalize_ws(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr, int32_t s,
+                            int32_t algo, char* ws, hipStream_t st, double* orth_err) {
+  Carve cv{ws};
   Common c = carve_common(cv, n);
   char* dprog = cv.take<char>(kProgramBytesPerRequest);
   const bool two = algo == TSG_ORTHO_TWO_STAGE;
@@ -1672,6 +1678,74 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   HIP_TRY(hipStreamSynchronize(st));
   if (h.status == 2) return fail(TSG_BREAKDOWN, "a Gram matrix was not positive definite");
   return TSG_OK;
+}
+
+}  // namespace
+
+tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr,
+                             int32_t s, int32_t s_hat, int32_t algo, void* workspace, size_t ws_bytes,
+                             void* stream, double* orth_err) {
+  if (!workspace) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  TRY(orthogonalize_check(n, k, X, ldx, R, ldr, s, s_hat, algo));
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(TSG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  size_t need = tsg_orthogonalize_workspace_bytes(n, k, s);
+  if (need == 0) return fail(TSG_ERR_INVALID_ARG, "problem too large for the reduction buffers");
+  if (ws_bytes < need) return fail(TSG_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, need);
+  return orthogonalize_ws(n, k, X, ldx, R, ldr, s, algo, (char*)workspace, (hipStream_t)stream, orth_err);
+}
+
+// ------------------------------------------------------------------ no-allocation entry
+// tsg_orthogonalize_noalloc runs tsg_orthogonalize with its workspace in `scratch`, a
+// file-scope device array of kNoAllocScratchBytes that every GPU the library runs on holds
+// for the life of the process.  In host code the array's name only stands in for the
+// symbol: its device address on the current device comes from hipGetSymbolAddress, taken
+// once per device (with that device current) on the first call there, and only that
+// address is ever passed to kernels or copies.
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = size_t(12) << 20;
+// the workspace of tsg_orthogonalize is the same ~9.3 MB for every n up to this many rows
+// (the reduction partials outgrow their fixed size beyond it)
+constexpr int64_t kNoAllocMaxRows = (int64_t)kMaxReduceBlocks * kMaxCols * kMaxNz * kRowBlock;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+tsg_status scratch_address(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TSG_ERR_UNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TSG_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return TSG_OK;
+}
+
+}  // namespace
+
+size_t tsg_orthogonalize_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+tsg_status tsg_orthogonalize_noalloc(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr,
+                                     int32_t s, int32_t s_hat, int32_t algo, void* stream, double* orth_err) {
+  TRY(orthogonalize_check(n, k, X, ldx, R, ldr, s, s_hat, algo));
+  const size_t need = tsg_orthogonalize_workspace_bytes(n, k, s);
+  if (n > kNoAllocMaxRows || need == 0 || need > kNoAllocScratchBytes)
+    return fail(TSG_ERR_INVALID_ARG,
+                "n=%lld k=%d s=%d needs %zu scratch bytes; the no-allocation entry point holds %zu "
+                "(n <= %lld rows)",
+                (long long)n, k, s, need, kNoAllocScratchBytes, (long long)kNoAllocMaxRows);
+  void* ws = nullptr;
+  TRY(scratch_address(&ws));
+  return orthogonalize_ws(n, k, X, ldx, R, ldr, s, algo, static_cast<char*>(ws), (hipStream_t)stream, orth_err);
 }
 
 // =================================================================== solve server

@@ -98,3 +98,16 @@ def test_no_cpu_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         binding.load_library()
+
+
+def test_noalloc_entry_rejects_oversized_blocks_on_the_host(lib):
+    """tsg_orthogonalize_noalloc checks sizes against its fixed scratch before any device
+    work (the pointers below are never dereferenced)."""
+    assert lib.tsg_orthogonalize_noalloc_max_bytes() == 12 << 20
+    assert lib.tsg_orthogonalize_workspace_bytes(1 << 28, 64, 16) <= lib.tsg_orthogonalize_noalloc_max_bytes()
+    fake = C.c_void_p(256)
+    n = (1 << 28) + 1
+    assert lib.tsg_orthogonalize_noalloc(n, 61, fake, n, fake, 61, 5, 0, 0, None, None) == -1
+    assert b"no-allocation" in lib.tsg_last_error()
+    assert lib.tsg_orthogonalize_noalloc(100, 65, fake, 100, fake, 65, 5, 0, 0, None, None) == -1
+    assert lib.tsg_orthogonalize_noalloc(100, 61, None, 100, fake, 61, 5, 0, 0, None, None) == -1
