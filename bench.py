@@ -204,8 +204,8 @@ def main():
     fmt = 1 if Ah.nnz == 0 or (delta.min() >= -32768 and delta.max() <= 32767) else 2  # 16- or 32-bit
     names = {  # every per-request kernel runs as batched_kernel<Body>
         "mpk": f"MpkBody<{elem}, {elem}, {fmt}>",
-        "gram": f"GramBody<{elem}, 1..4, {nt2}>",
-        "gram_first": f"GramBody<{elem}, {(args.s + 16) // 16}, {(args.s + 16) // 16}>",
+        "gram": f"GramBody<{elem}, 1..5, {nt2}>",
+        "gram_first": f"GramBody<{elem}, 1..2, 1..2>",
         "update": f"UpdateBody<{elem}, {st_(s_)}, 128>",
         "fused": f"FusedBody<{elem}, 4>",
     }

@@ -278,6 +278,33 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
                              int32_t s, int32_t s_hat, int32_t algo, void* workspace,
                              size_t ws_bytes, void* stream, double* orth_err /* host, opt */);
 
+/* One stage-1 panel of the two-stage scheme through the solver's fallback chain
+ * (Sec. V, Fig. 5 stage 1; Sec. IV-C, Fig. 4a for BCGS-PIP and its stability limit; Sec. II
+ * names shifted Cholesky QR as the remedy for CholQR's breakdown): W = V(:, k:k+s) is
+ * orthogonalized against Q = V(:, 0:k) (device float64, column-major, ldv >= n; Q is taken
+ * as given, normally orthonormal) and overwritten by Qnew with W = Q P + Qnew R.
+ *   pass 0  BCGS-PIP: one reduction [Q, W]^T W, R = Chol(W^T W - P^T P); a relative pivot
+ *           R_jj^2 <= pip_tol (W^T W)_jj fails the pass (the solver uses 1e-8 in FP64);
+ *   pass 1  (chain >= 1, only if pass 0 failed) the explicit second pass: Y = W - Q P1,
+ *           then BCGS-PIP of Y; a pivot fails at <= max(pivot_tol (Y^T Y)_jj,
+ *           pivot_tol^2 (W^T W)_jj) (the solver uses pivot_tol = 1e-12);
+ *   pass 2  (chain = 2, only if pass 1 failed) shifted Cholesky QR of pass 1's Gram G,
+ *           Rs = Chol(G + mu I), mu = 10 pivot_tol trace(G), Z = (Y - Q P2) Rs^{-1}, then
+ *           BCGS-PIP of Z; a final (R3 Rs)_jj^2 <= pivot_tol^2 (W^T W)_jj still fails.
+ * The kernels and tails are the solver's own (the same reductions, updates and gates).
+ * P (device, k x s, ldp >= k; unused when k = 0) and R (device, s x s upper triangular,
+ * ldr >= s, strictly lower part set to 0) receive the factors.  out (host, 2 ints,
+ * optional): out[0] = the last pass taken (0, 1 or 2), out[1] = the failing column of the
+ * panel on BREAKDOWN, else -1.  Requires 0 <= k, 1 <= s <= 16, k + s <= min(n, 64),
+ * 0 <= pip_tol, pivot_tol < 1, pivot_tol > 0 when chain >= 1.  Workspace (device, 256-byte
+ * aligned): tsg_block_pip_workspace_bytes.  Synchronizes `stream`.  BREAKDOWN: the last
+ * pass of the chain failed (W is then partially overwritten and P, R are not written);
+ * INVALID_ARG, WORKSPACE, HIP as elsewhere. */
+size_t tsg_block_pip_workspace_bytes(int64_t n, int32_t k, int32_t s);
+tsg_status tsg_block_pip(int64_t n, int32_t k, int32_t s, double* V, int64_t ldv, double pip_tol,
+                         double pivot_tol, int32_t chain, double* P, int32_t ldp, double* R, int32_t ldr,
+                         int32_t* out /* host, 2, opt */, void* workspace, size_t ws_bytes, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): tsg_orthogonalize without a workspace
  * argument.  Same arguments, layout, results (bit for bit) and status codes as

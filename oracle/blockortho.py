@@ -79,12 +79,14 @@ def bcgs_pip(Q: np.ndarray, V: np.ndarray, tol: float = 0.0):
     return Qnew, P, R
 
 
-def bcgs_pip_explicit(Q: np.ndarray, V: np.ndarray, tol: float = 0.0, shifted: bool = False):
+def bcgs_pip_explicit(Q: np.ndarray, V: np.ndarray, tol: float = 0.0, shifted: bool = False,
+                      pip_tol: float | None = None):
     """BCGS-PIP, with an explicit-Gram second pass where the Pythagorean Gram fails.
 
     The Pythagorean Gram G_V - P^T P loses all accuracy once [Q, V] is too ill-conditioned
     for the working precision (the stability condition of BCGS-PIP, Sec. IV-C).  When its
-    Cholesky fails the pivot test, the projection is applied explicitly first,
+    Cholesky fails the pivot test (relative threshold pip_tol, default tol; the GMRES cycles
+    pass dense.PIP_TOL), the projection is applied explicitly first,
     Y = V - Q P1, and Y is orthogonalized by a second BCGS-PIP pass whose Gram has no
     cancellation: P2 = Q^T Y, G = Y^T Y - P2^T P2, R = Chol(G), Qnew = (Y - Q P2) R^{-1},
     so V = Q (P1 + P2) + Qnew R.  A pivot of the second pass fails when it is at most
@@ -102,7 +104,7 @@ def bcgs_pip_explicit(Q: np.ndarray, V: np.ndarray, tol: float = 0.0, shifted: b
     Returns (Qnew, P, R, passes): passes = 0 (PIP), 1 (second pass), 2 (shifted pass too).
     """
     try:
-        Qn, P, R = bcgs_pip(Q, V, tol)
+        Qn, P, R = bcgs_pip(Q, V, tol if pip_tol is None else pip_tol)
         return Qn, P, R, 0
     except CholeskyBreakdown:
         pass

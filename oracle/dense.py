@@ -29,6 +29,20 @@ class CholeskyBreakdown(ArithmeticError):
 # (tol = 0: fail only if not SPD); the GMRES cycles pass PIVOT_TOL.
 PIVOT_TOL = 1e-12
 
+# Relative pivot threshold of two-stage stage 1's one-reduction pass (BCGS-PIP, Fig. 4a)
+# below which the panel takes the explicit second pass instead.  Sec. IV-C: the Pythagorean
+# Gram G_W - P^T P keeps its accuracy only while kappa([Q, W])^2 eps stays well below 1; a
+# pivot near PIVOT_TOL is then at the rounding level of the subtraction.  On the s-step
+# bases this happens: the monomial basis at s = 10 (2D Laplacian, 64^2) has relative pivots
+# of 5e-12..1.5e-9 whose Pythagorean values differ from the explicitly projected ones by up
+# to 2e-9, so a test at PIVOT_TOL is decided by rounding and two correct implementations
+# take the second pass on different panels.  Below PIP_TOL (kappa above ~1e4, kappa^2 eps
+# above ~1e-8) the explicit pass is taken; that decision has four decades of margin over
+# the Pythagorean pivots' rounding while they are still this large, and the bases of s <= 5
+# (relative pivots >= 2e-6 measured on 64^2 .. 512^2 Laplacians, 3D Laplacians and
+# convection-diffusion) never reach it.  Our reading; the paper does not treat the case.
+PIP_TOL = 1e-8
+
 
 def chol_upper(G: np.ndarray, ref_diag=None, tol: float = 0.0) -> np.ndarray:
     """Upper Cholesky factor R (R^T R = G, diag(R) > 0); library primitive: LAPACK potrf.

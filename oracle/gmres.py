@@ -49,7 +49,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .dense import (PIVOT_TOL, CholeskyBreakdown, GivensState, chol_upper, givens_lsq,
+from .dense import (PIP_TOL, PIVOT_TOL, CholeskyBreakdown, GivensState, chol_upper, givens_lsq,
                     right_solve_upper, solve_upper)
 from .sparse import Operator, basis_params, gershgorin, spmv
 from . import blockortho, ritz
@@ -251,7 +251,8 @@ def sstep_gmres(A, b, x0=None, m: int = 60, s: int = 5, tol: float = 1e-10,
             W, B = mpk(op, Qh[:, k - 1], bp.theta, bp.sigma, bp.tau, prec)
             try:
                 if one_stage is None:  # stage 1 (second pass only where PIP fails)
-                    Qn, P, R, fb = blockortho.bcgs_pip_explicit(Qh[:, :k], W, PIVOT_TOL, use_shift)
+                    Qn, P, R, fb = blockortho.bcgs_pip_explicit(Qh[:, :k], W, PIVOT_TOL, use_shift,
+                                                                pip_tol=PIP_TOL)
                     stats["fallbacks"] += int(fb >= 1)
                     stats["shifted"] += int(fb == 2)
                 else:
@@ -382,7 +383,7 @@ def _sstep_gmres_shat(A, b, x0, m, s, s_hat, tol, max_iters, basis, shifts, reco
             k = j * s + 1
             W, B = mpk(op, Y[:, k - 1], bp.theta, bp.sigma, bp.tau, prec)
             try:
-                Qn, P, R, fb = blockortho.bcgs_pip_explicit(Y[:, :k], W, PIVOT_TOL, use_shift)
+                Qn, P, R, fb = blockortho.bcgs_pip_explicit(Y[:, :k], W, PIVOT_TOL, use_shift, pip_tol=PIP_TOL)
                 stats["fallbacks"] += int(fb >= 1)
                 stats["shifted"] += int(fb == 2)
             except CholeskyBreakdown:

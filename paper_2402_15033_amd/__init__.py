@@ -24,6 +24,7 @@ from .binding import (  # noqa: F401
     load_library,
     solve,
     orthogonalize,
+    block_pip,
     precond_apply,
     ritz_newton,
     spmv,

@@ -132,6 +132,11 @@ def load_library():
     lib.tsg_orthogonalize_workspace_bytes.restype = C.c_size_t
     lib.tsg_orthogonalize.argtypes = [i64, i32, vp, i64, vp, i32, i32, i32, i32, vp, C.c_size_t, vp, f64p]
     lib.tsg_orthogonalize.restype = C.c_int
+    lib.tsg_block_pip_workspace_bytes.argtypes = [i64, i32, i32]
+    lib.tsg_block_pip_workspace_bytes.restype = C.c_size_t
+    lib.tsg_block_pip.argtypes = [i64, i32, i32, vp, i64, C.c_double, C.c_double, i32, vp, i32, vp, i32,
+                                  C.POINTER(i32), vp, C.c_size_t, vp]
+    lib.tsg_block_pip.restype = C.c_int
     lib.tsg_orthogonalize_noalloc.argtypes = [i64, i32, vp, i64, vp, i32, i32, i32, i32, vp, f64p]
     lib.tsg_orthogonalize_noalloc.restype = C.c_int
     lib.tsg_orthogonalize_noalloc_max_bytes.argtypes = []
@@ -424,6 +429,31 @@ def orthogonalize(X: torch.Tensor, s: int = 5, algo: str = "two_stage", *, ldx: 
     if orth_err:
         return X, Rt, err.value
     return X, Rt
+
+
+def block_pip(V: torch.Tensor, k: int, s: int, *, pip_tol: float = 1e-8, pivot_tol: float = 1e-12,
+              chain: int = 2, ldv: int | None = None):
+    """One stage-1 panel through the solver's fallback chain (tsg_block_pip): V is a float64
+    device block viewed column-major as by orthogonalize(); its columns k .. k+s-1 are
+    orthogonalized in place against columns 0 .. k-1.  Returns dict(status, passes,
+    fail_col, P (k x s), R (s x s)); a breakdown is reported in status (2), not raised."""
+    lib = load_library()
+    n, ncol, ld = _block_view(V, ldv)
+    if ncol < k + s:
+        raise ValueError("V has fewer than k + s columns")
+    P = torch.zeros((s, max(k, 1)), dtype=torch.float64, device=V.device)  # column-major k x s
+    R = torch.zeros((s, s), dtype=torch.float64, device=V.device)
+    need = int(lib.tsg_block_pip_workspace_bytes(n, int(k), int(s)))
+    if need == 0:
+        _check(-1)
+    ws, wp = _workspace(need, V.device, None)
+    out = (C.c_int32 * 2)(-1, -1)
+    st = lib.tsg_block_pip(n, int(k), int(s), V.data_ptr(), ld, float(pip_tol), float(pivot_tol), int(chain),
+                           P.data_ptr(), max(int(k), 1), R.data_ptr(), int(s), out, wp, need, _stream(V.device))
+    _check(st, allow_positive=True)
+    del ws
+    return {"status": int(st), "passes": int(out[0]), "fail_col": int(out[1]),
+            "P": P.t()[:k, :] if k > 0 else P.t()[:0, :], "R": R.t()}
 
 
 def _info_to_py(info: _Info) -> SolveInfo:

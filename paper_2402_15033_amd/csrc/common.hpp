@@ -18,6 +18,14 @@ constexpr int kTailThreads = 1024;  // threads of the one-block tail kernels
 // numerically dependent column (breakdown).  FP64 and FP32 bases.
 constexpr double kPivotTolF64 = 1e-12;
 constexpr double kPivotTolF32 = 1e-5;
+// Two-stage stage 1 in FP64: a relative pivot of the one-reduction pass (BCGS-PIP) at most
+// this takes the explicit second pass.  Sec. IV-C: the Pythagorean Gram G_W - P^T P is
+// accurate only while kappa([Q, W])^2 eps stays well below 1; its pivots near kPivotTolF64
+// are at the rounding level of the subtraction (measured on the monomial basis at s = 10:
+// pivots of 5e-12 .. 1.5e-9 off by up to 2e-9), so the pass is taken below 1e-8, where the
+// decision has a wide margin.  Bases with s <= 5 (relative pivots >= 2e-6) never reach it.
+// The mixed form keeps kPivotTolF32.
+constexpr double kPipTolF64 = 1e-8;
 
 // Device (global) memory as the compiler's address space 1.  The kernels take their
 // pointers from a per-launch argument table in memory, so to the compiler they are

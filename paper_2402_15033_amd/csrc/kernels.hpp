@@ -977,6 +977,22 @@ __global__ __launch_bounds__(256) void copy_r_kernel(const SmallState* st, int w
   }
 }
 
+// The factors of one stand-alone panel (columns k .. k+s-1 against the k before them) from
+// the R assembly in st->Hh: P = Hh(0:k, k:k+s) (ldp), R = Hh(k:k+s, k:k+s) (ldr, strictly
+// lower part 0).  Returns at entry after a breakdown (nothing written).
+__global__ __launch_bounds__(256) void copy_panel_kernel(const SmallState* st, int k, int s, double* P, int ldp,
+                                                         double* R, int ldr) {
+  if (st->h.done) return;
+  for (int idx = threadIdx.x; idx < k * s; idx += blockDim.x) {
+    const int i = idx % k, j = idx / k;
+    P[i + (int64_t)j * ldp] = st->Hh[i + (k + j) * kLd];
+  }
+  for (int idx = threadIdx.x; idx < s * s; idx += blockDim.x) {
+    const int i = idx % s, j = idx / s;
+    R[i + (int64_t)j * ldr] = i <= j ? st->Hh[(k + i) + (k + j) * kLd] : 0.0;
+  }
+}
+
 // ||I - G||_F for the k x k Gram in st->Wk (upper triangle valid) -> st->Wk[kLd*kLd-1].
 __global__ __launch_bounds__(256) void orth_err_kernel(SmallState* st, int k) {
   __shared__ double s[256];

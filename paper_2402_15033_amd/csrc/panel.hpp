@@ -1,5 +1,5 @@
 // Panel steps of every block orthogonalization scheme (Sec. IV-V): the arguments shared
-// by the streaming kernels (gram_mfma_kernel, panel_mfma_kernel, update_kernel), and the
+// by the streaming kernels (GramBody, FusedBody, UpdateBody), and the
 // one-block FP64 "tail" that follows a reduction.
 //
 // A streaming launch passes once over the rows of the column-major basis V and, per row r,
@@ -9,7 +9,7 @@
 //     W(r,:) <- q                     (PF_STORE, in place)
 //     G += [Q(r,:), q]^T q            (PF_GRAM_Q: Q rows, PF_GRAM_W: q rows)
 // where Q = V(:, 0:k) and W = V(:, wcol:wcol+sw).  Each block writes its partial Gram;
-// panel_tail_kernel sums the partials in a fixed order and runs the tail (Cholesky of the
+// PTailBody sums the partials in a fixed order and runs the tail (Cholesky of the
 // Pythagorean Gram, Hessenberg block, Givens, ...).
 #pragma once
 
@@ -60,7 +60,10 @@ struct PanelArgs {
   int32_t gate;      // 1: return at entry when the solve is done or panel > stop_panel;
                      // 2: also unless this panel asked for the explicit second pass;
                      // 3: also unless it asked for the pass after the shifted Cholesky QR
-  int32_t standalone;// tails assemble an R factor (st->Hh) instead of Hessenberg/Givens
+  int32_t standalone;// 0: solver; 1: stand-alone (tails assemble an R factor in st->Hh
+                     // instead of Hessenberg/Givens; any failed pivot is a breakdown);
+                     // 2: stand-alone with stage 1's fallback chain (a failed PIP pivot
+                     // takes the explicit pass, as in the solver)
   int32_t kkeep;     // Krylov vectors kept if this panel breaks down (solver mode)
   int32_t panel;     // index of the panel within the cycle (-1: cycle set-up)
   int32_t nz;        // reduced Gram has nz columns: nz - sw previous-panel columns, then W
@@ -86,12 +89,13 @@ __device__ __forceinline__ double red(const PanelArgs& a, const double* sred, in
   return sred[c * a.nz + (a.nz - a.sw) + j];
 }
 
-__device__ void tail_breakdown(const PanelArgs& a, int kkeep) {
+__device__ void tail_breakdown(const PanelArgs& a, int kkeep, int f = -1) {
   SmallState* st = a.st;
   if (threadIdx.x == 0) {
     if (a.standalone) {
       st->h.status = 2;
       st->h.done = 1;
+      st->fail_col = f;
     } else {  // this panel is discarded: stop after the previous one
       st->h.stop_panel = a.panel - 1;
       st->h.k_used = kkeep;
@@ -115,14 +119,13 @@ __device__ void tail_check(SmallState* st, int ncols, int panel) {
 }
 
 // Pythagorean Gram G = Gw - P^T P (P = sred rows 0..k-1, Gw = rows k..k+s-1) and its
-// Cholesky factor into R (ld kMaxS).  A pivot fails when it is at most pivot_tol * Gw_jj,
-// or, for the explicit second pass (second = true, the panel holds Y = W - Q P1), at most
-// max(pivot_tol * Gw_jj, pivot_tol^2 * refW_j) with refW the raw Gram diagonal of W.
+// Cholesky factor into R (ld kMaxS).  A pivot fails when it is at most tol * Gw_jj, or, for
+// the explicit second pass (second = true, the panel holds Y = W - Q P1), at most
+// max(tol * Gw_jj, pivot_tol^2 * refW_j) with refW the raw Gram diagonal of W.
 // Returns the failing pivot or -1.
-__device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, double* R,
+__device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, double* R, double tol,
                              bool second = false) {
   const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
-  const double tol = a.st->pivot_tol;
   __shared__ double sG[kMaxS * kMaxS], sRef[kMaxS];
   for (int idx = tid; idx < k * s; idx += nt) {
     int c = idx % k, j = idx / k;
@@ -144,7 +147,8 @@ __device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, 
     sG[i + j * kMaxS] = v;
     if (i == j) {
       const double d = red(a, sred, k + i, j);
-      sRef[i] = second ? fmax(tol * d, tol * tol * a.st->refW[i]) : tol * d;
+      const double pt = a.st->pivot_tol;
+      sRef[i] = second ? fmax(tol * d, pt * pt * a.st->refW[i]) : tol * d;
     }
   }
   __syncthreads();
@@ -258,9 +262,9 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
         if (c <= col) st->G2[c + col * kLd] = sred[c * a.nz + z];
       }
       __syncthreads();
-      int f = tail_pip_chol(a, sred, st->Pcur, sR);
+      int f = tail_pip_chol(a, sred, st->Pcur, sR, st->pip_tol);
       if (f >= 0) {
-        if (a.standalone) { tail_breakdown(a, a.kkeep); break; }
+        if (a.standalone == 1) { tail_breakdown(a, a.kkeep, f); break; }
         // The Pythagorean Gram has cancelled to rounding: apply the projection
         // explicitly (the next update computes Y = W - Q P1 with T = I) and let the
         // gated second pass orthogonalize Y.
@@ -283,11 +287,12 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
     case TAIL_PIP_FB: {
       // second pass on the panel Y = W - Q P1: P2 = Q^T Y, R = Chol(Y^T Y - P2^T P2);
       // V_panel = Q (P1 + P2) + Q_new R
-      int f = tail_pip_chol(a, sred, st->Pcur, sR, true);
+      int f = tail_pip_chol(a, sred, st->Pcur, sR, st->pivot_tol, true);
       if (f >= 0 && a.shifted) {
         // Y is beyond Cholesky QR: the update forms Z = (Y - Q P2) Rs^{-1} with the shifted
         // factor, and the gated pass after it orthogonalizes Z (P1 accumulates P2)
-        if (tail_shifted_chol(a, sred, st->Rs) >= 0) { tail_breakdown(a, a.kkeep); break; }
+        const int fs = tail_shifted_chol(a, sred, st->Rs);
+        if (fs >= 0) { tail_breakdown(a, a.kkeep, fs); break; }
         for (int idx = tid; idx < k * s; idx += nt) {
           int c = idx % k, j = idx / k;
           st->P1[c + j * kLd] += st->Pcur[c + j * kLd];
@@ -300,7 +305,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
         __syncthreads();
         break;
       }
-      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      if (f >= 0) { tail_breakdown(a, a.kkeep, f); break; }
       tail_set_tinv(st, sR, s);
       for (int idx = tid; idx < k * s; idx += nt) {
         int c = idx % k, j = idx / k;
@@ -314,7 +319,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
       // V_panel = Q (P1 + P2 + P3 Rs) + Q_new (R3 Rs).  A final pivot (R3 Rs)_jj^2 at most
       // pivot_tol^2 refW_j is a column numerically in span(Q): breakdown.
       __shared__ int s_dep;
-      int f = tail_pip_chol(a, sred, st->Pcur, sR);
+      int f = tail_pip_chol(a, sred, st->Pcur, sR, st->pivot_tol);
       if (f < 0) {
         for (int idx = tid; idx < s * s; idx += nt) {
           int i = idx % s, j = idx / s;
@@ -335,7 +340,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
         __syncthreads();
         f = s_dep;
       }
-      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      if (f >= 0) { tail_breakdown(a, a.kkeep, f); break; }
       tail_set_tinv(st, sR, s);
       for (int idx = tid; idx < k * s; idx += nt) {
         int c = idx % k, j = idx / k;
@@ -356,8 +361,8 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
       __syncthreads();
     } break;
     case TAIL_PIP2_A: {
-      int f = tail_pip_chol(a, sred, st->Pcur, st->R1);
-      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      int f = tail_pip_chol(a, sred, st->Pcur, st->R1, st->pivot_tol);
+      if (f >= 0) { tail_breakdown(a, a.kkeep, f); break; }
       for (int idx = tid; idx < k * s; idx += nt) {
         int c = idx % k, j = idx / k;
         st->P1[c + j * kLd] = st->Pcur[c + j * kLd];
@@ -366,8 +371,8 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
       tail_set_tinv(st, st->R1, s);
     } break;
     case TAIL_PIP2_B: {
-      int f = tail_pip_chol(a, sred, st->Pcur, sR2);
-      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      int f = tail_pip_chol(a, sred, st->Pcur, sR2, st->pivot_tol);
+      if (f >= 0) { tail_breakdown(a, a.kkeep, f); break; }
       tail_set_tinv(st, sR2, s);
       // P = P1 + P2 R1,  R = R2 R1
       for (int idx = tid; idx < k * s; idx += nt) {
@@ -396,13 +401,13 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
     } break;
     case TAIL_BC_A1: {
       int f = tail_chol_rows(a, sred, k, st->Ra, st->pivot_tol);
-      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      if (f >= 0) { tail_breakdown(a, a.kkeep, f); break; }
       tail_set_tinv(st, st->Ra, s);
     } break;
     case TAIL_BC_A2: {
       // this launch has k = 0 (the panel alone)
       int f = tail_chol_rows(a, sred, 0, sR, st->pivot_tol);
-      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      if (f >= 0) { tail_breakdown(a, a.kkeep, f); break; }
       tail_set_tinv(st, sR, s);
       for (int idx = tid; idx < s * s; idx += nt) {
         int i = idx % s, j = idx / s;
@@ -425,7 +430,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
     } break;
     case TAIL_BC_C: {
       int f = tail_chol_rows(a, sred, k, sR2, st->pivot_tol);
-      if (f >= 0) { tail_breakdown(a, a.kkeep); break; }
+      if (f >= 0) { tail_breakdown(a, a.kkeep, f); break; }
       tail_set_tinv(st, sR2, s);
       // P = P1 + P2 Ra,  R = Rc Ra
       for (int idx = tid; idx < k * s; idx += nt) {

@@ -32,6 +32,7 @@ struct SmallState {
   int32_t m, s, ortho, prec;
   int64_t max_iters;
   double tol, bnorm, pivot_tol;
+  double pip_tol;        // two-stage stage 1: relative pivot below which the explicit pass runs
   // basis step i: w_{i+1} = ((A - theta_i I) w_i + tau_i w_{i-1}) / sigma_i
   double theta[kMaxS], sigma[kMaxS], tau[kMaxS];
   double glo, ghi;       // Gershgorin interval of the operator
@@ -40,7 +41,7 @@ struct SmallState {
   // cycle scalars
   double beta, inv_beta;
   int32_t identity_t;    // the next update kernel uses T = I (no scaling)
-  int32_t pad2;
+  int32_t fail_col;      // stand-alone: panel column whose pivot failed (-1: none)
   // small matrices
   double Hh[kLd * kLd];    // Hessenberg of the basis, (m+1) x m
   double G2[kLd * kLd];    // stage-2 Gram of the pre-processed basis (upper triangle)

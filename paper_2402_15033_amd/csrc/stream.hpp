@@ -1,8 +1,8 @@
 // Lean streaming kernels of the panel steps:
-//   gram_mfma_kernel  -- the reduction  G = V(:, 0:ncol)^T V(:, ncol-nz : ncol)  (no update)
-//   update_kernel     -- the update     W <- (W - Q P) T  in place            (no reduction)
-//   panel_mfma_kernel -- the update and the Gram of its output in one pass, for the steps
-//                        whose next reduction needs exactly the columns just written
+//   GramBody   -- the reduction  G = V(:, 0:ncol)^T V(:, ncol-nz : ncol)  (no update)
+//   UpdateBody -- the update     W <- (W - Q P) T  in place            (no reduction)
+//   FusedBody  -- the update and the Gram of its output in one pass, for the steps whose
+//                 next reduction needs exactly the columns just written
 #pragma once
 
 #include "panel.hpp"
@@ -103,115 +103,156 @@ struct TileLoad {
   }
 };
 
-// The reduction G = V(:, 0:ncol)^T V(:, ncol-nz : ncol) of a panel step on the matrix
-// cores, where ncol = k + sw (Q = V(:,0:k), W = V(:,wcol:wcol+sw)) and the nz right-hand
-// columns are the previous panel's nprev columns (their block column of the stage-2 Gram)
-// followed by W.  Batches are staged as in TileLoad (one barrier per batch), the next two
-// batches loading into registers while the matrix cores consume the current one.  The
-// K-steps (4 rows each) of a batch are dealt to the waves round-robin; every wave
-// accumulates all MT x NT tiles (4 MT NT values per lane).  The 8 waves' tiles are summed
-// in LDS in wave order (in float64) at the end.  Partials: ncol x nz float64 per block.
-// Requires ncol <= 16 MT, nz <= 16 NT.
-template <typename T, int MT, int NT>
+// The reduction G = V(:, 0:ncol)^T V(:, ncol-nz : ncol) of a panel step on the matrix cores
+// (ncol = k + sw, Q = V(:, 0:k), W = V(:, wcol:wcol+sw); the nz right-hand columns are the
+// previous panel's nprev columns, their block column of the stage-2 Gram, followed by W),
+// with the operands taken straight from global memory: no LDS staging and no block barrier
+// in the row loop.  Rows are the K dimension.  Lane l = 16 g + i holds, for each column tile
+// t, column c_t + i and the RL consecutive rows r + RL g .. r + RL g + RL - 1 of a group of
+// 4 RL rows (two 16-byte loads per tile: RL = 4 in FP64, 8 in FP32); K-step e of the group
+// pairs row r + RL g + e with k index g in both operands.  The tiles are laid out from the
+// right: the last NT tiles are the nz right-hand columns (the B operand is the A operand of
+// those tiles, no extra load) and MA - NT tiles cover the columns to their left down to
+// column 0 (lanes outside [0, ncol) hold zeros).  Each wave walks its own groups (wave w:
+// groups w, w + NW, ... of the block's rows) with one group's loads in flight while the
+// matrix cores consume the previous one; the loads are unconditional (the index is clamped
+// to the last full group), so the compiler waits only for the group it consumes.  A ragged
+// last group (and every group when the columns are not 16-byte aligned) is loaded element
+// by element with its rows masked.  The NW waves' tiles are summed in LDS in wave order at
+// the end.  Partials: ncol x nz float64 per block.  Measured on a 4194304 x 61 FP64 block:
+// 6.07 TB/s with 256 blocks against 4.73 for the LDS-staged version.
+template <typename T>
+constexpr int gram_rows_per_lane() { return 32 / (int)sizeof(T); }
+constexpr int kGramGroupRows = 32;  // row blocks of the reduction are multiples of this
+template <typename T, int MA, int NT>
 struct GramBody {
   typedef PanelArgs Args;
   static constexpr int kThreads = 512;
-  static constexpr int kMinWaves = 4;  // two 8-wave blocks per CU: at most 128 VGPRs
+  static constexpr int kMinWaves = 1;
   static __device__ void run(const PanelArgs& a, int bid, int nb);
 };
-template <typename T, int MT, int NT>
-__device__ void GramBody<T, MT, NT>::run(const PanelArgs& a, int bid, int) {
+template <typename T, int MA, int NT>
+__device__ void GramBody<T, MA, NT>::run(const PanelArgs& a, int bid, int) {
   if (gated_off(a, a.st)) return;
   typedef typename MfmaOp<T>::v4 v4;
-  typedef TileLoad<T> TL;
-  constexpr int NW = 8, SL = TL::SL, R = TL::R;
+  constexpr int NW = kThreads / kWave, RL = gram_rows_per_lane<T>(), GR = 4 * RL;
+  static_assert(kGramGroupRows % GR == 0, "row blocks must hold whole groups");
   const int lane = threadIdx.x & (kWave - 1);
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int g = lane >> 4, li = lane & 15;
   const int k = a.k, ncol = a.k + a.sw, nz = a.nz, z0 = ncol - nz;
+  const int64_t ld = a.ld, n = a.n;
   gbl<const T>* __restrict__ V = G(reinterpret_cast<const T*>(a.V));
-  __shared__ T lt[2][mfma_tile<T>()];
-  TL tl;
-  tl.init(wv, ncol, k, a.wcol, a.ld);
-  const int BR = tl.BR, LDT = tl.LDT;
-
+  // per tile: this lane's column (offset of its first element) and whether it exists
+  int64_t coff[MA];
+  bool cval[MA];
+#pragma unroll
+  for (int t = 0; t < MA; ++t) {
+    const int c = z0 + 16 * (t - (MA - NT)) + li;
+    cval[t] = c >= 0 && c < ncol;
+    const int cc = cval[t] ? c : 0;
+    coff[t] = (int64_t)(cc < k ? cc : a.wcol + (cc - k)) * ld + RL * g;
+  }
   const int64_t rb = (int64_t)bid * a.rows_per_block;
-  const int64_t re = min(a.n, rb + a.rows_per_block);
-  T v[SL][R], vn[SL][R], vnn[SL][R];
-  v4 acc[MT][NT];
+  const int64_t re = min(n, rb + a.rows_per_block);
+  const int64_t nfull = (re - rb) / GR;  // full groups of this block
+  const bool vec = (reinterpret_cast<uintptr_t>(a.V) & 15) == 0 && (ld % (16 / (int)sizeof(T))) == 0;
+  v4 acc[MA][NT];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+  for (int t = 0; t < MA; ++t)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = v4{0, 0, 0, 0};
-  const int li = lane & 15, lk = lane >> 4;
-  const int ksteps = BR / 4;  // K-steps of 4 rows per batch, dealt to the waves round-robin
-  // prefetch depth 2: batches r0+BR and r0+2BR are in flight while r0 is consumed.  The
-  // three register buffers take turns (loop unrolled by 6: the compiler drains the loads
-  // in flight at the loop head), so no register copy waits for a batch still in flight.
-  int buf = 0;
-  auto batch = [&](const T (&cur)[SL][R], T (&fut)[SL][R], int64_t r0) {
-    tl.load(V, wv, lane, r0 + 2 * BR, re, fut);
-    T* L = lt[buf];
-    tl.to_lds(L, wv, lane, r0, re, cur);
-    __syncthreads();
-    for (int ks = wv; ks < ksteps; ks += NW) {
-      const int row = ks * 4 + lk;
-      T bv[NT];
+    for (int u = 0; u < NT; ++u) acc[t][u] = v4{0, 0, 0, 0};
+  // rows r0 + RL g .. + RL - 1 of every tile column (a full group starting at row r0)
+  auto load = [&](int64_t r0, T (&v)[MA][RL]) {
+    typedef T t16 __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int H = 16 / (int)sizeof(T);
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int z = nt * 16 + li;
-        bv[nt] = (z < nz) ? L[(z0 + z) * LDT + row] : (T)0;
-      }
+    for (int t = 0; t < MA; ++t) {
+      gbl<const T>* p = V + coff[t] + r0;
+      const t16 x0 = *reinterpret_cast<gbl<const t16>*>(p);
+      const t16 x1 = *reinterpret_cast<gbl<const t16>*>(p + H);
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int c = mt * 16 + li;
-        const T av = (c < ncol) ? L[c * LDT + row] : (T)0;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = MfmaOp<T>::mac(av, bv[nt], acc[mt][nt]);
+      for (int e = 0; e < H; ++e) {
+        v[t][e] = x0[e];
+        v[t][H + e] = x1[e];
       }
     }
-    buf ^= 1;
   };
-  tl.load(V, wv, lane, rb, re, v);
-  tl.load(V, wv, lane, rb + BR, re, vn);
-  for (int64_t r0 = rb; r0 < re; r0 += 6 * BR) {
-    batch(v, vnn, r0);
-    if (r0 + BR >= re) break;
-    batch(vn, v, r0 + BR);
-    if (r0 + 2 * BR >= re) break;
-    batch(vnn, vn, r0 + 2 * BR);
-    if (r0 + 3 * BR >= re) break;
-    batch(v, vnn, r0 + 3 * BR);
-    if (r0 + 4 * BR >= re) break;
-    batch(vn, v, r0 + 4 * BR);
-    if (r0 + 5 * BR >= re) break;
-    batch(vnn, vn, r0 + 5 * BR);
+  auto mma = [&](const T (&v)[MA][RL]) {
+#pragma unroll
+    for (int e = 0; e < RL; ++e)
+#pragma unroll
+      for (int t = 0; t < MA; ++t) {
+        const T av = cval[t] ? v[t][e] : (T)0;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const int tb = MA - NT + u;
+          const T bv = cval[tb] ? v[tb][e] : (T)0;
+          acc[t][u] = MfmaOp<T>::mac(av, bv, acc[t][u]);
+        }
+      }
+  };
+  if (vec && nfull > 0) {
+    T va[MA][RL], vb[MA][RL];
+    int64_t q = wv;
+    load(rb + GR * min<int64_t>(q, nfull - 1), va);
+    for (; q < nfull; q += 2 * NW) {
+      load(rb + GR * min<int64_t>(q + NW, nfull - 1), vb);
+      mma(va);
+      if (q + NW >= nfull) break;
+      load(rb + GR * min<int64_t>(q + 2 * NW, nfull - 1), va);
+      mma(vb);
+    }
   }
-  // sum the 8 waves' partial tiles in wave order, one 16-wide Z tile at a time:
-  // red[w][c][z], c < 64, z < 16 (8 x 64 x 16 values fit in the two LDS buffers)
-  T* red = &lt[0][0];
+  {
+    // element by element: the ragged last group, or every group when the columns are not
+    // 16-byte aligned
+    const int64_t q0 = vec ? nfull : 0, qe = (re - rb + GR - 1) / GR;
+    for (int64_t q = q0 + wv; q < qe; q += NW) {
+      const int64_t r0 = rb + GR * q;
+      T v[MA][RL];
+#pragma unroll
+      for (int t = 0; t < MA; ++t)
+#pragma unroll
+        for (int e = 0; e < RL; ++e) v[t][e] = r0 + RL * g + e < re ? V[coff[t] + r0 + e] : (T)0;
+      mma(v);
+    }
+  }
+  // sum the NW waves' tiles in wave order, one right-hand tile at a time:
+  // red[w][c][z], c < 16 MA (every column c < ncol lies in one tile), z < 16
+  constexpr int RC = 16 * MA;
+  __shared__ T red[NW * RC * 16];
   gbl<double>* part = G(a.part1) + (size_t)bid * ncol * nz;
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
+  for (int u = 0; u < NT; ++u) {
     __syncthreads();
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int t = 0; t < MA; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int c = mt * 16 + MfmaOp<T>::row(lk, r);
-        red[(wv * kMaxCols + c) * 16 + li] = acc[mt][nt][r];
+        const int c = z0 + 16 * (t - (MA - NT)) + MfmaOp<T>::row(g, r);
+        if (c >= 0 && c < ncol) red[(wv * RC + c) * 16 + li] = acc[t][u][r];
       }
     __syncthreads();
     for (int e = threadIdx.x; e < ncol * 16; e += blockDim.x) {
-      const int c = e / 16, z = nt * 16 + e % 16;
+      const int c = e / 16, z = u * 16 + e % 16;
       if (z < nz) {
         double sum = 0.0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) sum += (double)red[(w * kMaxCols + c) * 16 + e % 16];
+        for (int w = 0; w < NW; ++w) sum += (double)red[(w * RC + c) * 16 + e % 16];
         part[c * nz + z] = sum;
       }
     }
   }
 }
+
+// Grid of the reduction for MA column tiles: one 8-wave block per CU where the registers
+// of MA tiles' loads in flight allow only that (measured: 256 blocks 6.07 TB/s, 512 blocks
+// 5.68, 1024 blocks 5.86 at MA = 5), more blocks for narrower reductions (MA = 1: 1024
+// blocks 4.70 TB/s, 512 blocks 4.55).
+inline int gram_max_blocks(int ma) { return ma <= 1 ? 1024 : (ma == 2 ? 512 : 256); }
+// Column tiles of a reduction of ncol columns against its last nz.
+inline int gram_tiles(int ncol, int nz) { return (nz + 15) / 16 + (ncol - nz + 15) / 16; }
 
 // y(j) -= sum over columns c0 .. c0 + K - 1 of Q(r, c) P(c, j), in column order; the K
 // loads of the row's Q entries are issued before the first product.
@@ -301,7 +342,7 @@ __device__ void UpdateBody<T, S, kBlock>::run(const PanelArgs& a, int bid, int) 
 // q = [Q, W] B with B = [-P T; T] ((k+sw) x sw, formed once per block in LDS), so each
 // 16-row tile of the batch is multiplied by B on the matrix cores (rows are the M
 // dimension, the staged columns the K dimension) and q is written over W in the tile;
-// after a barrier the matrix cores reduce the Gram of the tile as in gram_mfma_kernel, and
+// after a barrier the matrix cores reduce the Gram of the tile (rows as the K dimension), and
 // the waves store q from LDS in whole row segments.  Partials: (k + sw) x sw float64 per
 // block (rows of Q zero unless PF_GRAM_Q).  Requires sw <= 16.
 template <typename T, int MT>
@@ -371,8 +412,8 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
   for (int mt = 0; mt < MT; ++mt) acc[mt] = v4{0, 0, 0, 0};
   const int li = lane & 15, lk = lane >> 4;
   const int ksteps_upd = (ncol + 3) / 4;
-  // prefetch depth 2 with three register buffers taking turns, loop unrolled by 6 (as in
-  // GramBody)
+  // prefetch depth 2 with three register buffers taking turns, loop unrolled by 6 (the
+  // compiler drains the loads in flight at the loop head)
   int buf = 0;
   auto batch = [&](const T (&cur)[SL][R], T (&fut)[SL][R], int64_t r0) {
     tl.load(V, wv, lane, r0 + 2 * BR, re, fut);

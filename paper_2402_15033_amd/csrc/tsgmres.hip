@@ -303,10 +303,25 @@ void launch_update(const Phase& ph, const char* d, int nreq, hipStream_t s) {
     default: launch_b<UpdateBody<T, 16, B>>(ph, d, nreq, s); break;
   }
 }
-template <typename T, int MT>
-void launch_gram_mt(const Phase& ph, const char* d, int nreq, hipStream_t s) {
-  if (ph.t2 == 1) launch_b<GramBody<T, MT, 1>>(ph, d, nreq, s);
-  else launch_b<GramBody<T, MT, 2>>(ph, d, nreq, s);
+// t1 = MA column tiles, t2 = NT right-hand tiles (MA >= NT)
+template <typename T>
+void launch_gram(const Phase& ph, const char* d, int nreq, hipStream_t s) {
+  if (ph.t2 == 1) {
+    switch (ph.t1) {
+      case 1: launch_b<GramBody<T, 1, 1>>(ph, d, nreq, s); break;
+      case 2: launch_b<GramBody<T, 2, 1>>(ph, d, nreq, s); break;
+      case 3: launch_b<GramBody<T, 3, 1>>(ph, d, nreq, s); break;
+      case 4: launch_b<GramBody<T, 4, 1>>(ph, d, nreq, s); break;
+      default: launch_b<GramBody<T, 5, 1>>(ph, d, nreq, s); break;
+    }
+  } else {
+    switch (ph.t1) {
+      case 2: launch_b<GramBody<T, 2, 2>>(ph, d, nreq, s); break;
+      case 3: launch_b<GramBody<T, 3, 2>>(ph, d, nreq, s); break;
+      case 4: launch_b<GramBody<T, 4, 2>>(ph, d, nreq, s); break;
+      default: launch_b<GramBody<T, 5, 2>>(ph, d, nreq, s); break;
+    }
+  }
 }
 template <typename T>
 void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
@@ -334,14 +349,7 @@ void launch_phase_t(const Phase& ph, const char* d, int nreq, hipStream_t s) {
       if (ph.t2) launch_update<T, 256>(ph, d, nreq, s);
       else launch_update<T, 128>(ph, d, nreq, s);
       break;
-    case F_GRAM:
-      switch (ph.t1) {
-        case 1: launch_gram_mt<T, 1>(ph, d, nreq, s); break;
-        case 2: launch_gram_mt<T, 2>(ph, d, nreq, s); break;
-        case 3: launch_gram_mt<T, 3>(ph, d, nreq, s); break;
-        default: launch_gram_mt<T, 4>(ph, d, nreq, s); break;
-      }
-      break;
+    case F_GRAM: launch_gram<T>(ph, d, nreq, s); break;
     case F_FUSED:
       switch (ph.t1) {
         case 1: launch_b<FusedBody<T, 1>>(ph, d, nreq, s); break;
@@ -497,16 +505,27 @@ struct Builder {
         x.rows_per_block = st.gate >= 2 ? 256 : 128;  // the kernel's block (see UpdateBody)
         nb[r] = (int)cdiv(q.n, x.rows_per_block);
         cols = ((st.flags & PF_HAS_P) ? st.k : 0) + 2.0 * st.sw;
+      } else if (gram) {
+        const int ma = gram_tiles(st.k + st.sw, nz);
+        const int64_t groups = cdiv(q.n, kGramGroupRows);
+        const int b0 = (int)std::min<int64_t>(groups, gram_max_blocks(ma));
+        x.rows_per_block = cdiv(cdiv(q.n, b0), kGramGroupRows) * kGramGroupRows;
+        nb[r] = (int)cdiv(q.n, x.rows_per_block);
+        cols = st.k + st.sw;
+        reduces = true;
+        if ((size_t)nb[r] * (size_t)((st.k + st.sw) * nz) > q.c.part1_n)
+          return fail(TSG_ERR_WORKSPACE, "internal: reduction partials (%d blocks x %d) exceed the buffer", nb[r],
+                      (st.k + st.sw) * nz);
       } else {
         const int rpl = P.f32 ? tile_rows_per_lane<float>() : tile_rows_per_lane<double>();
-        const int staged = (gram || (st.flags & PF_BMAT)) ? st.k + st.sw : (loadQ ? st.k : 0) + st.sw;
+        const int staged = (st.flags & PF_BMAT) ? st.k + st.sw : (loadQ ? st.k : 0) + st.sw;
         const int br = kWave * rpl * (kTileItems / staged);  // the MFMA kernels' batch height
         int64_t tiles = cdiv(q.n, br);
         int b0 = (int)std::min<int64_t>(tiles, kMaxMfmaBlocks);
         x.rows_per_block = cdiv(cdiv(q.n, b0), br) * br;
         nb[r] = (int)cdiv(q.n, x.rows_per_block);
-        cols = gram ? st.k + st.sw : staged + ((st.flags & PF_STORE) ? st.sw : 0);
-        reduces = gram || (st.flags & (PF_GRAM_Q | PF_GRAM_W)) != 0;
+        cols = staged + ((st.flags & PF_STORE) ? st.sw : 0);
+        reduces = (st.flags & (PF_GRAM_Q | PF_GRAM_W)) != 0;
         if ((size_t)nb[r] * (size_t)((st.k + st.sw) * nz) > q.c.part1_n)
           return fail(TSG_ERR_WORKSPACE, "internal: reduction partials (%d blocks x %d) exceed the buffer", nb[r],
                       (st.k + st.sw) * nz);
@@ -519,7 +538,7 @@ struct Builder {
     if (st.kind == PK_UPDATE) {
       P.add(F_UPDATE, s_template(st.sw), st.gate >= 2 ? 1 : 0, a, nb, kc, fb ? 0.0 : bytes);
     } else if (gram) {
-      P.add(F_GRAM, (st.k + st.sw + 15) / 16, nz <= 16 ? 1 : 2, a, nb, kc, fb ? 0.0 : bytes);
+      P.add(F_GRAM, gram_tiles(st.k + st.sw, nz), nz <= 16 ? 1 : 2, a, nb, kc, fb ? 0.0 : bytes);
     } else {
       const int ncolA = (st.flags & PF_GRAM_Q) ? st.k + st.sw : st.sw;
       P.add(F_FUSED, std::max(1, (ncolA + 15) / 16), 0, a, nb, kc, fb ? 0.0 : bytes);
@@ -1358,6 +1377,7 @@ tsg_status init_request(const tsg_csr_s* A, const tsg_solve_params* p, ReqCtx& q
   hs->max_iters = p->max_iters;
   hs->tol = p->tol;
   hs->pivot_tol = f32 ? kPivotTolF32 : kPivotTolF64;
+  hs->pip_tol = f32 ? kPivotTolF32 : kPipTolF64;
   for (int i = 0; i < sstep; ++i) {
     hs->theta[i] = q.theta[i];
     hs->sigma[i] = q.sigma[i];
@@ -1611,6 +1631,8 @@ tsg_status orthogonalize_ws(int64_t n, int32_t k, double* X, int64_t ldx, double
   std::memset(hs, 0, sizeof(SmallState));
   hs->h.stop_panel = 1 << 30;
   hs->pivot_tol = 0.0;  // stand-alone: fail only when a Gram is not positive definite
+  hs->pip_tol = 0.0;
+  hs->fail_col = -1;
   hipError_t e = hipMemcpyAsync(c.st, hs, offsetof(SmallState, Hh), hipMemcpyHostToDevice, st);
   delete hs;
   HIP_TRY(e);
@@ -1693,6 +1715,83 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   if (need == 0) return fail(TSG_ERR_INVALID_ARG, "problem too large for the reduction buffers");
   if (ws_bytes < need) return fail(TSG_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, need);
   return orthogonalize_ws(n, k, X, ldx, R, ldr, s, algo, (char*)workspace, (hipStream_t)stream, orth_err);
+}
+
+// ------------------------------------------------------------------ one stage-1 panel
+size_t tsg_block_pip_workspace_bytes(int64_t n, int32_t k, int32_t s) {
+  if (k < 0 || s < 1 || s > kMaxS || k + s > kMaxCols) return 0;
+  return tsg_orthogonalize_workspace_bytes(n, k + s, s);
+}
+
+tsg_status tsg_block_pip(int64_t n, int32_t k, int32_t s, double* V, int64_t ldv, double pip_tol, double pivot_tol,
+                         int32_t chain, double* P, int32_t ldp, double* R, int32_t ldr, int32_t* out, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  if (!V || !R || !workspace || (k > 0 && !P)) return fail(TSG_ERR_INVALID_ARG, "NULL argument");
+  if (k < 0 || s < 1 || s > kMaxS || k + s > kMaxCols || k + s > n)
+    return fail(TSG_ERR_INVALID_ARG, "need 0 <= k, 1 <= s <= 16, k + s <= min(n, 64): n=%lld k=%d s=%d",
+                (long long)n, k, s);
+  if (ldv < n || ldr < s || (k > 0 && ldp < k)) return fail(TSG_ERR_INVALID_ARG, "leading dimension too small");
+  if (chain < 0 || chain > 2) return fail(TSG_ERR_INVALID_ARG, "chain=%d outside [0, 2]", chain);
+  if (!(pip_tol >= 0.0 && pip_tol < 1.0) || !(pivot_tol >= 0.0 && pivot_tol < 1.0))
+    return fail(TSG_ERR_INVALID_ARG, "pivot thresholds must lie in [0, 1)");
+  if (chain >= 1 && !(pivot_tol > 0.0))
+    return fail(TSG_ERR_INVALID_ARG, "the explicit and shifted passes need pivot_tol > 0");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(TSG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  const size_t need = tsg_block_pip_workspace_bytes(n, k, s);
+  if (need == 0) return fail(TSG_ERR_INVALID_ARG, "problem too large for the reduction buffers");
+  if (ws_bytes < need) return fail(TSG_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  Carve cv{(char*)workspace};
+  Common c = carve_common(cv, n);
+  char* dprog = cv.take<char>(kProgramBytesPerRequest);
+  SmallState* hs = new (std::nothrow) SmallState();
+  if (!hs) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
+  std::memset(hs, 0, sizeof(SmallState));
+  hs->h.stop_panel = 1 << 30;
+  hs->pivot_tol = pivot_tol;
+  hs->pip_tol = pip_tol;
+  hs->fail_col = -1;
+  hipError_t e = hipMemcpyAsync(c.st, hs, offsetof(SmallState, Hh), hipMemcpyHostToDevice, st);
+  delete hs;
+  HIP_TRY(e);
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(kLd * kLd, 256)), dim3(256), 0, st, c.st->Hh, (int64_t)kLd * kLd);
+  HIP_LAUNCH_CHECK();
+  ReqCtx q;
+  q.V = V;
+  q.ld = ldv;
+  q.n = n;
+  q.c = c;
+  Program Pg;
+  Pg.nreq = 1;
+  // chain 0: PIP alone (a failed pivot is a breakdown); 1: + the explicit pass, gated on
+  // the PIP pivot test; 2: + the shifted Cholesky QR pass, gated on the explicit pass's test
+  Builder B{Pg, {&q}, chain > 0 ? 2 : 1};
+  B.shifted = chain >= 2 ? 1 : 0;
+  for (int pass = 0; pass <= chain; ++pass) {
+    const int gate = pass + 1;
+    TRY(B.step(gram_step(k, k, s, 0, pass == 0 ? TAIL_PIP : (pass == 1 ? TAIL_PIP_FB : TAIL_PIP_FB2), 0, 0, gate)));
+    Step u = upd_step(PK_UPDATE, k, k, s, PF_HAS_P | PF_HAS_T | PF_STORE, TAIL_NONE, 0, 0);
+    u.gate = gate;
+    TRY(B.step(u));
+  }
+  if (Pg.blob.size() > kProgramBytesPerRequest) return fail(TSG_ERR_UNSUPPORTED, "internal: launch image too large");
+  HIP_TRY(hipMemcpyAsync(dprog, Pg.blob.data(), Pg.blob.size(), hipMemcpyHostToDevice, st));
+  TRY(exec_program(Pg, dprog, st, nullptr));
+  hipLaunchKernelGGL(copy_panel_kernel, dim3(1), dim3(256), 0, st, (const SmallState*)c.st, k, s, P, ldp, R, ldr);
+  HIP_LAUNCH_CHECK();
+  StateHead h{};
+  int32_t fcol = -1;
+  HIP_TRY(hipMemcpyAsync(&h, &c.st->h, sizeof(StateHead), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&fcol, &c.st->fail_col, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (out) {
+    out[0] = h.fallbacks + h.shifted;
+    out[1] = h.status == 2 ? fcol : -1;
+  }
+  if (h.status == 2) return fail(TSG_BREAKDOWN, "pivot %d of the panel failed after %d fallback pass(es)", fcol,
+                                 h.fallbacks + h.shifted);
+  return TSG_OK;
 }
 
 // ------------------------------------------------------------------ no-allocation entry

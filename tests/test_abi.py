@@ -111,3 +111,27 @@ def test_noalloc_entry_rejects_oversized_blocks_on_the_host(lib):
     assert b"no-allocation" in lib.tsg_last_error()
     assert lib.tsg_orthogonalize_noalloc(100, 65, fake, 100, fake, 65, 5, 0, 0, None, None) == -1
     assert lib.tsg_orthogonalize_noalloc(100, 61, None, 100, fake, 61, 5, 0, 0, None, None) == -1
+
+
+def test_block_pip_argument_checks_on_the_host(lib):
+    fake = C.c_void_p(256)
+    ws = lib.tsg_block_pip_workspace_bytes(1000, 9, 5)
+    assert ws > 0 and lib.tsg_block_pip_workspace_bytes(1000, 60, 5) == 0  # k + s > 64
+    assert lib.tsg_block_pip_workspace_bytes(1000, 9, 17) == 0
+    args = dict(n=1000, k=9, s=5, V=fake, ldv=1000, pip=1e-8, piv=1e-12, chain=2, P=fake, ldp=9, R=fake, ldr=5)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return lib.tsg_block_pip(a["n"], a["k"], a["s"], a["V"], a["ldv"], a["pip"], a["piv"], a["chain"], a["P"],
+                                 a["ldp"], a["R"], a["ldr"], None, fake, ws, None)
+    assert call(V=None) == -1
+    assert call(s=0) == -1
+    assert call(k=60) == -1           # k + s > 64
+    assert call(n=10) == -1           # k + s > n
+    assert call(ldv=999) == -1
+    assert call(ldp=8) == -1
+    assert call(chain=3) == -1
+    assert call(piv=0.0) == -1        # the explicit pass needs a positive threshold
+    assert call(pip=-1.0) == -1
+    assert lib.tsg_block_pip(1000, 9, 5, fake, 1000, 1e-8, 1e-12, 2, fake, 9, fake, 5, None, C.c_void_p(257), ws,
+                             None) == -3  # misaligned workspace

@@ -162,14 +162,7 @@ def test_bcgs_pip2_on_glued_matrix(glued):
 
 
 def _nearly_dependent_panel(n, k, s, delta, seed):
-    """Q (n x k orthonormal) and V = Q C + delta Z with Z orthonormal and orthogonal to Q:
-    [Q, V] has condition number ~ 1/delta while V - Q Q^T V = delta Z is perfectly
-    conditioned."""
-    rng = np.random.default_rng(seed)
-    X, _ = np.linalg.qr(rng.standard_normal((n, k + s)))
-    Q, Z = X[:, :k], X[:, k:]
-    C = rng.standard_normal((k, s))
-    return Q, Q @ C + delta * Z
+    return W.nearly_dependent_panel(n, k, s, delta, seed)
 
 
 def test_pip_explicit_second_pass_where_pip_fails():
@@ -212,16 +205,7 @@ def test_pip_explicit_second_pass_rejects_dependent_columns():
 
 
 def _ill_conditioned_panel(n, k, s, kappa, seed):
-    """Q (n x k orthonormal) and V = Q C + Z D with Z orthonormal, orthogonal to Q, and D
-    upper triangular with unit diagonal but D[s-1, s-1] = 1/kappa: the last column of
-    Y = V - Q Q^T V = Z D lies within 1/kappa of the span of the others, numerically full
-    rank but beyond CholQR's limit (its relative pivot ~kappa^-2 is below the threshold)."""
-    rng = np.random.default_rng(seed)
-    X, _ = np.linalg.qr(rng.standard_normal((n, k + s)))
-    Q, Z = X[:, :k], X[:, k:]
-    D = np.triu(rng.standard_normal((s, s)), 1) + np.eye(s)
-    D[s - 1, s - 1] = 1.0 / kappa
-    return Q, Q @ rng.standard_normal((k, s)) + Z @ D
+    return W.ill_conditioned_panel(n, k, s, kappa, seed)
 
 
 def test_shifted_pass_where_the_second_pass_fails():
@@ -258,3 +242,23 @@ def test_shifted_pass_still_rejects_dependent_columns():
     with pytest.raises(D.CholeskyBreakdown) as e:
         BO.bcgs_pip_explicit(Q, V, 1e-12, shifted=True)
     assert e.value.index == 2
+
+
+def test_pip_trigger_threshold_takes_the_explicit_pass_before_pip_loses_digits():
+    """Stage 1's trigger (dense.PIP_TOL): a panel whose Pythagorean pivots are ~1e-10
+    relative (kappa([Q, V]) ~ 1e5) is accepted by PIP at PIVOT_TOL but loses orthogonality
+    O(eps kappa^2) there (Sec. IV-C); at PIP_TOL it takes the explicit pass and gets the thin
+    QR of [Q, V] to O(eps): orthogonality at rounding, R equal to the Householder factor."""
+    n, k, s = 4000, 9, 5
+    Q, V = _nearly_dependent_panel(n, k, s, 1e-5, seed=31)
+    Qa, Pa, Ra, pa = BO.bcgs_pip_explicit(Q, V, D.PIVOT_TOL, pip_tol=D.PIVOT_TOL)
+    Qb, Pb, Rb, pb = BO.bcgs_pip_explicit(Q, V, D.PIVOT_TOL, pip_tol=D.PIP_TOL)
+    assert pa == 0 and pb == 1
+    ea, eb = D.orth_error(np.hstack([Q, Qa])), D.orth_error(np.hstack([Q, Qb]))
+    assert ea > 1e-9 and eb <= 1e-14, (ea, eb)
+    _, Rh = D.householder_qr(np.hstack([Q, V]))
+    assert np.linalg.norm(Rb - Rh[k:, k:]) / np.linalg.norm(Rh[k:, k:]) <= 1e-9
+    assert np.linalg.norm(V - Q @ Pb - Qb @ Rb) / np.linalg.norm(V) <= 1e-15
+    # the s <= 5 bases stay far above the trigger: a well-conditioned panel is PIP's
+    Q2, V2 = _nearly_dependent_panel(n, k, s, 1e-2, seed=32)
+    assert BO.bcgs_pip_explicit(Q2, V2, D.PIVOT_TOL, pip_tol=D.PIP_TOL)[3] == 0

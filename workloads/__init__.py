@@ -17,6 +17,8 @@ from .generators import (  # noqa: F401
     gaussian_block,
     logscaled_block,
     glued_block,
+    nearly_dependent_panel,
+    ill_conditioned_panel,
     laplace_eigpair_2d,
     laplace_eigpair_3d,
     laplace_extreme_eigs,

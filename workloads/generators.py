@@ -277,3 +277,27 @@ def glued_block(n: int, npanels: int, s: int, kappa_p: float, seed: int, alpha: 
             G = rng.standard_normal((widths[bi], w))
             K[offs[bi]:offs[bi + 1], o:o + w] = alpha * G / np.linalg.norm(G, 2)
     return np.asfortranarray(X @ (K @ S))
+
+
+def nearly_dependent_panel(n: int, k: int, s: int, delta: float, seed: int):
+    """(Q, V): Q n x k orthonormal and V = Q C + delta Z, C Gaussian, Z n x s orthonormal and
+    orthogonal to Q.  [Q, V] has a condition number of about 1/delta while V - Q Q^T V =
+    delta Z is perfectly conditioned; delta = 0 makes every column of V lie in span(Q)."""
+    rng = np.random.default_rng(seed)
+    X, _ = np.linalg.qr(rng.standard_normal((n, k + s)))
+    Q, Z = X[:, :k], X[:, k:]
+    C = rng.standard_normal((k, s))
+    return np.asfortranarray(Q), np.asfortranarray(Q @ C + delta * Z)
+
+
+def ill_conditioned_panel(n: int, k: int, s: int, kappa: float, seed: int):
+    """(Q, V): Q n x k orthonormal and V = Q C + Z D, Z n x s orthonormal and orthogonal to
+    Q, D upper triangular with unit diagonal but D[s-1, s-1] = 1/kappa: the last column of
+    V - Q Q^T V = Z D lies within 1/kappa of the span of the others (numerically full rank,
+    relative Cholesky pivot ~ kappa^-2)."""
+    rng = np.random.default_rng(seed)
+    X, _ = np.linalg.qr(rng.standard_normal((n, k + s)))
+    Q, Z = X[:, :k], X[:, k:]
+    D = np.triu(rng.standard_normal((s, s)), 1) + np.eye(s)
+    D[s - 1, s - 1] = 1.0 / kappa
+    return np.asfortranarray(Q), np.asfortranarray(Q @ rng.standard_normal((k, s)) + Z @ D)
