@@ -55,6 +55,42 @@ def measured_traffic(kernel: str):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+# kernel classes that make up the orthogonalization (every class the library times except
+# the SpMV, the residual, the first-vector scaling, the x update and the preconditioner)
+ORTHO_CLASSES = ("gram", "gram_first", "update", "fused", "tail", "cycle_end", "fallback", "stage2")
+
+METHOD_PASSES_DOC = {
+    "two_stage": "sum_j (2 k_j + 3 s) + (m + 1) column passes per cycle (stage 1 per panel; the stage-2 "
+                 "Gram read, its explicit Q folded into the x update), k_j = (j - 1) s + 1",
+    "bcgs_pip2": "sum_j 2 (2 k_j + 3 s) column passes per cycle",
+    "bcgs2_cholqr2": "sum_j (4 k_j + 15 s) column passes per cycle",
+    "cgs2": "sum_{k=1..m} (4 k + 9) column passes per cycle",
+}
+
+
+def method_column_passes(ortho: str, m: int, s: int) -> int:
+    """Column passes (reads + writes of one n-vector) of one restart cycle of the method's
+    orthogonalization, the byte model of the measurement plan."""
+    if ortho == "cgs2":
+        return sum(4 * k + 9 for k in range(1, m + 1))
+    ks = [j * s + 1 for j in range(m // s)]
+    if ortho == "two_stage":
+        return sum(2 * k + 3 * s for k in ks) + (m + 1)
+    if ortho == "bcgs_pip2":
+        return sum(2 * (2 * k + 3 * s) for k in ks)
+    return sum(4 * k + 15 * s for k in ks)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,7 +114,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ortho-bench", action="store_true")
     ap.add_argument("--ortho-reps", type=int, default=20)
-    ap.add_argument("--cpu-cycles", type=int, default=1)
+    ap.add_argument("--cpu-budget-s", type=float, default=30.0,
+                    help="host seconds for the CPU oracle legs (all cores, then one thread)")
     ap.add_argument("--time-stride", type=int, default=16,
                     help="HIP-event timing of every launch in every n-th restart cycle of the timed "
                          "solves (1 = every cycle; events between launches slow a cycle by ~12%%)")
@@ -213,20 +250,46 @@ def main():
     dom = max(streaming, key=lambda c: streaming[c][0])
     ms, cnt, by = streaming[dom]
     kname = names[dom]
-    achieved = by / (ms * 1e-3) / 1e9
+    w = 8.0 if args.precision == "fp64" else 4.0
+    per_launch_us = ms / cnt * 1e3
+    format_bytes = by / cnt  # the library's own count for the launched layout
+    # the survey's per-launch byte model: a CSR SpMV step reads w + 4 bytes per stored entry,
+    # the row pointers and x once, and writes y; the panel kernels' algorithmic bytes are
+    # the w n (columns read + written) the library counts
+    if dom == "mpk":
+        model_bytes = (w + 4.0) * Ah.nnz + 4.0 * (Ah.n + 1) + 2.0 * w * Ah.n
+        model = "CSR SpMV step: (w + 4) nnz + 4 (n + 1) + 2 w n bytes (w = element bytes)"
+    else:
+        model_bytes = format_bytes
+        model = "w n (columns read + columns written)"
+    achieved = model_bytes / (per_launch_us * 1e-6) / 1e9
     traffic = measured_traffic(kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": traffic, "kernel": kname,
-                "avg_launch_us": round(ms / cnt * 1e3, 2), "launches": int(cnt),
-                "algorithmic_bytes_per_launch": round(by / cnt),
+                "byte_model": model, "algorithmic_bytes_per_launch": round(model_bytes),
+                "avg_launch_us": round(per_launch_us, 2), "launches": int(cnt),
+                "time_source": (f"HIP events around every launch of every {args.time_stride}th restart cycle "
+                                "of the timed solves (launched directly), on the solve's stream; they include "
+                                "the launch gap"),
+                "format_bytes_per_launch": round(format_bytes),
+                "frac_format": round(format_bytes / (per_launch_us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4),
+                "frac_counter": (round(traffic / (per_launch_us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)
+                                 if traffic else None),
                 "timed_cycles": int(tcyc), "time_stride": args.time_stride}
     per_class = {}
     for c, (cms, ccnt, cby) in classes.items():
         per_class[c] = {"kernel": names.get(c), "ms_per_cycle": round(cms / tcyc, 4),
                         "launches_per_cycle": round(ccnt / tcyc, 2),
                         "GBps": round(cby / (cms * 1e-3) / 1e9, 1) if cms > 0 and cby > 0 else None}
-    ortho_ms_cycle = (tot("ms_ortho_reduce") + tot("ms_ortho_update") + tot("ms_small")) / tcyc
+    ortho_ms_cycle = sum(classes[c][0] for c in ORTHO_CLASSES if c in classes) / tcyc
+    passes = method_column_passes(args.ortho, args.m, args.s)
+    ortho_gb = passes * Ah.n * w / 1e9
+    ortho = {"ms_per_cycle": round(ortho_ms_cycle, 3), "classes": [c for c in ORTHO_CLASSES if c in classes],
+             "column_passes_per_cycle": passes, "method_GB_per_cycle": round(ortho_gb, 3),
+             "GBps": round(ortho_gb / (ortho_ms_cycle * 1e-3), 1),
+             "frac": round(ortho_gb / (ortho_ms_cycle * 1e-3) / HBM_PEAK_GBPS, 4),
+             "byte_model": METHOD_PASSES_DOC.get(args.ortho)}
 
     out = {
         "metric": METRIC,
@@ -257,6 +320,7 @@ def main():
         "pip_fallbacks": int(info.pip_fallbacks), "shifted_passes": int(info.shifted_passes),
         "newton_from_cycle": int(info.newton_from_cycle),
         "ortho_ms_per_cycle": round(ortho_ms_cycle, 3),
+        "ortho": ortho,
         "kernel_classes": per_class,
         "roofline": roofline,
     }
@@ -310,66 +374,124 @@ def main():
                               precond=precond)
             torch.cuda.synchronize()
             t = time.perf_counter() - t
+            kc = ci.kernel_classes()
+            oms = sum(kc[c][0] for c in ORTHO_CLASSES if c in kc) / max(ci.timed_cycles, 1)
             cmp[o] = {"time_to_solution_s": round(t, 4), "iters": int(ci.iters), "relres": ci.relres,
-                      "ortho_ms_per_cycle": round((ci.ms_ortho_reduce + ci.ms_ortho_update + ci.ms_small)
-                                                  / max(ci.timed_cycles, 1), 3)}
+                      "ortho_ms_per_cycle": round(oms, 3),
+                      "ortho_frac": round(method_column_passes(o, args.m, args.s) * Ah.n * w / (oms * 1e-3)
+                                          / 1e9 / HBM_PEAK_GBPS, 4)}
             log(f"[bench] compare {o}: {cmp[o]}")
         out["compare"] = cmp
 
+    if args.precision == "fp32_ir":
+        # the mixed form's error per solve against the plain FP64 solve of the same system
+        xr = torch.zeros_like(b)
+        _, i64 = tsg.solve(A, b, xr, **dict(kw, precision="fp64"))
+        torch.cuda.synchronize()
+        x64 = xr.cpu().numpy()
+        xt = pr.get("x_true")
+        out["vs_fp64"] = {"rel_diff_x": float(np.linalg.norm(xh - x64) / np.linalg.norm(x64)),
+                          "fp64_iters": int(i64.iters), "fp64_relres": i64.relres,
+                          "rel_err_mixed_vs_x_true": (float(np.linalg.norm(xh - xt) / np.linalg.norm(xt))
+                                                      if xt is not None else None),
+                          "rel_err_fp64_vs_x_true": (float(np.linalg.norm(x64 - xt) / np.linalg.norm(xt))
+                                                     if xt is not None else None)}
+        log(f"[bench] mixed vs FP64: {out['vs_fp64']}")
+
     if not args.no_ortho_bench:
         n, k, s = Ah.n, 61, args.s
-        log("[bench] isolated block orthogonalization 4194304 x 61")
+        log(f"[bench] isolated block orthogonalization {n} x {k}")
         X0 = torch.as_tensor(W.gaussian_block(n, k, seed=7).T.copy(), device=dev)
-        Xw = torch.empty_like(X0)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        times = []
-        oerr = None
-        for r in range(args.ortho_reps + 2):
-            Xw.copy_(X0)
-            e0.record()
-            _, R = tsg.orthogonalize(Xw, s=s, algo="two_stage")
-            e1.record()
-            torch.cuda.synchronize()
-            if r >= 2:
-                times.append(e0.elapsed_time(e1))
-        _, _, oerr = tsg.orthogonalize(Xw.copy_(X0), s=s, algo="two_stage", orth_err=True)
-        med = float(np.median(times))
-        panels = [(c0, min(s, k - c0)) for c0 in range(1, k, s)]
-        passes = 3 + sum(2 * (c0 + sw) + sw for c0, sw in panels) + 2 * k
-        moved = passes * n * 8
-        method_bytes = 1047 * n * 8  # stage-2 Gram pass counted as a separate read
-        out["ortho_bench"] = {"shape": [n, k], "s": s, "algo": "two_stage", "median_ms": round(med, 3),
-                              "column_passes": passes, "GBps": round(moved / med / 1e6, 1),
-                              "GBps_method_equiv": round(method_bytes / med / 1e6, 1),
+        res = {}
+        for pad in (64, 0):
+            # columns n + 64 elements apart (the solver's basis layout: column starts that are
+            # multiples of 64 Ki elements put the columns on the same HBM channels), and the
+            # unpadded layout for reference
+            buf = torch.empty((k, n + pad), dtype=torch.float64, device=dev)
+            Xw = buf[:, :n]
+            times = []
+            for r in range(args.ortho_reps + 2):
+                Xw.copy_(X0)
+                e0.record()
+                tsg.orthogonalize(Xw, s=s, algo="two_stage")
+                e1.record()
+                torch.cuda.synchronize()
+                if r >= 2:
+                    times.append(e0.elapsed_time(e1))
+            res[pad] = float(np.median(times))
+            if pad == 64:
+                _, _, oerr = tsg.orthogonalize(Xw.copy_(X0), s=s, algo="two_stage", orth_err=True)
+            del buf, Xw
+        med = res[64]
+        passes = 1047 if (args.s == 5 and k == 61) else None
+        method_bytes = sum(2 * c0 + 3 * min(s, k - c0) for c0 in range(1, k, s)) * n * 8 + 3 * k * n * 8
+        out["ortho_bench"] = {"shape": [n, k], "ld": n + 64, "s": s, "algo": "two_stage", "median_ms": round(med, 3),
+                              "median_ms_ld_n": round(res[0], 3),
+                              "method_column_passes": passes if passes else round(method_bytes / (n * 8)),
+                              "method_GB": round(method_bytes / 1e9, 3),
+                              "GBps": round(method_bytes / med / 1e6, 1),
+                              "frac": round(method_bytes / med / 1e6 / HBM_PEAK_GBPS, 4),
+                              "byte_model": "stage 1 sum_j (2 k_j + 3 s) + stage 2 3 k column passes (Gram read, "
+                                            "explicit Q read and written)",
                               "orth_err": oerr, "reps": args.ortho_reps}
-        del X0, Xw
+        del X0
 
     if not args.no_cpu_baseline:
-        log(f"[bench] CPU oracle: {args.cpu_cycles} restart cycle(s) of the same solve")
-        from oracle import gmres as G
-        from oracle import precond as PC
-        from oracle import sparse as S
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-        except Exception:
-            cores = os.cpu_count()
-        op = S.Operator(Ah)
-        t = time.perf_counter()
-        ref = G.sstep_gmres(op, pr["b"], m=args.m, s=args.s, tol=args.tol, ortho=args.ortho
-                            if args.ortho != "cgs2" else "two_stage", basis=args.basis,
-                            max_iters=args.cpu_cycles * args.m,
-                            precond=PC.MulticolorGS(Ah) if precond else None)
-        t = time.perf_counter() - t
-        t_cycle = t / max(ref["cycles"], 1)
-        cpu_solves_per_s = 1.0 / (t_cycle * max(info.cycles, 1))
-        out["cpu_baseline"] = {"value": cpu_solves_per_s, "unit": "solves/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": f"{ref['cycles']} restart cycle(s) of the same {desc} solve "
-                                         f"({t:.1f} s, {t_cycle:.2f} s/cycle), scaled by the "
-                                         f"{info.cycles} cycles the GPU solve needed; numpy BLAS on "
-                                         f"{cores} threads, scipy SpMV single-threaded"}
+        out["cpu_baseline"] = cpu_baseline(args, Ah, pr, info, desc, precond)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(args, Ah, pr, info, desc, precond):
+    """The FP64 oracle on the host cores, on a bounded sample of the same solve: restart
+    cycles timed with all the cores numpy's BLAS uses and with one thread; the solve's time
+    is extrapolated with the GPU's cycle count.  Each leg runs one cycle, then as many more
+    as fit its budget (10 at most)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import gmres as G
+    from oracle import precond as PC
+    from oracle import sparse as S
+
+    op = S.Operator(Ah)
+    prec = PC.MulticolorGS(Ah) if precond else None
+    ortho = args.ortho if args.ortho != "cgs2" else "two_stage"
+
+    def run(cycles):
+        t = time.perf_counter()
+        ref = G.sstep_gmres(op, pr["b"], m=args.m, s=args.s, tol=args.tol, ortho=ortho, basis=args.basis,
+                            max_iters=cycles * args.m, precond=prec)
+        return time.perf_counter() - t, ref["cycles"]
+
+    def leg(budget):
+        t1, c1 = run(1)
+        more = int(min(9, max(0, budget / max(t1, 1e-9) - 1)))
+        if more == 0:
+            return t1 / max(c1, 1), c1
+        t2, c2 = run(more)
+        return t2 / max(c2, 1), c2
+
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    log(f"[bench] CPU oracle, {threads} threads")
+    t_all, c_all = leg(args.cpu_budget_s / 2)
+    log(f"[bench] CPU oracle, 1 thread")
+    with threadpool_limits(limits=1):
+        t_one, c_one = leg(args.cpu_budget_s / 2)
+    cyc = max(info.cycles, 1)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except Exception:
+        avail = os.cpu_count()
+    return {"value": 1.0 / (t_all * cyc), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": (f"restart cycles of the same {desc} solve, timed and scaled by the {cyc} cycles the GPU "
+                       f"solve needed: all-core leg {c_all} cycle(s) at {t_all:.2f} s/cycle (numpy BLAS on "
+                       f"{threads} threads, scipy SpMV single-threaded), single-thread leg {c_one} cycle(s) "
+                       f"at {t_one:.2f} s/cycle"),
+            "single_thread": {"value": 1.0 / (t_one * cyc), "s_per_cycle": round(t_one, 3), "cycles_timed": c_one},
+            "all_cores": {"value": 1.0 / (t_all * cyc), "s_per_cycle": round(t_all, 3), "cycles_timed": c_all,
+                          "threads": threads},
+            "cpu_model": cpu_model(), "host_cpus_available": avail}
 
 
 def serve_bench(args, tsg, W, np, torch, dev):

@@ -123,7 +123,11 @@ typedef enum { TSG_PRECOND_NONE = 0, TSG_PRECOND_MCGS = 1 } tsg_precond;
  * captured as timing nodes here, so cycles timed by params.timing are enqueued
  * directly).
  *   EAGER  launch every kernel of every cycle directly on `stream` instead (same
- *          kernels and arguments, bitwise-identical results). */
+ *          kernels and arguments, bitwise-identical results).
+ * Two-stage cycles run first without stage 1's fallback passes (the launches that only
+ * check whether a panel needs them); a cycle whose PIP pivot test fails there ends at once,
+ * before it has touched x or the counters, and is run again with the full sequence, which
+ * runs from then on (tsg_solve_info.redone_cycles).  The results are the same bit for bit. */
 enum { TSG_FLAG_EAGER = 1 };
 
 /* Kernel classes reported by tsg_solve_info (timing mode).  Each class is one kernel
@@ -171,6 +175,10 @@ typedef struct {
                               QR pass (Fukaya et al.; Sec. II names it as CholQR's remedy):
                               Rs = Chol(G + mu I), mu = 10 pivot_tol trace(G), then one
                               more BCGS-PIP pass; elsewhere such a panel ends the cycle */
+  int64_t redone_cycles;   /* two-stage: restart cycles run first without stage 1's fallback
+                              passes (the launches that check for them), met a panel that needs
+                              them, and were run again in full; the full cycle runs from then on
+                              (the results are the same bit for bit either way)             */
 } tsg_solve_info;
 
 typedef struct tsg_csr_s* tsg_csr;
@@ -248,7 +256,7 @@ size_t tsg_solve_workspace_bytes(int64_t n, int64_t nnz, const tsg_solve_params*
 /* Solve A x = b by restarted s-step GMRES(m) (Sec. III, Fig. 1) with the block
  * orthogonalization p->ortho.  b[n] (device, float64) is read; x[n] (device, float64)
  * holds x0 on entry and the result on exit.  Every step of a restart cycle runs in
- * the library's HIP kernels on `stream`; the host only reads back a 72-byte status
+ * the library's HIP kernels on `stream`; the host only reads back an 80-byte status
  * block once per cycle (the host synchronizes `stream` once per cycle).  Returns after
  * the solve has finished on the device.  precond = MCGS: the solve runs on the operator's
  * reordered system P A P^T (b and x permuted in and out on `stream`).

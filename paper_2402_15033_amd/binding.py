@@ -47,7 +47,8 @@ class _Info(C.Structure):
                 ("bytes_spmv", C.c_double), ("kc_ms", C.c_double * 16),
                 ("kc_launches", C.c_int64 * 16), ("kc_bytes", C.c_double * 16),
                 ("timed_cycles", C.c_int64), ("pip_fallbacks", C.c_int64),
-                ("newton_from_cycle", C.c_int64), ("shifted_passes", C.c_int64)]
+                ("newton_from_cycle", C.c_int64), ("shifted_passes", C.c_int64),
+                ("redone_cycles", C.c_int64)]
 
 
 KERNEL_CLASSES = ["mpk", "gram", "gram_first", "update", "fused", "tail", "cycle_end", "xupdate",
@@ -83,6 +84,7 @@ class SolveInfo:
     pip_fallbacks: int = 0
     newton_from_cycle: int = 0
     shifted_passes: int = 0
+    redone_cycles: int = 0
 
     def kernel_classes(self) -> dict:
         """{class: (ms, launches, algorithmic bytes)} for the classes that ran (timing mode)."""

@@ -363,6 +363,7 @@ __device__ void RTailBody::run(const TailArgs& a, int, int) {
       st->h.k_used = st->m;
       st->h.refine = 0;
       st->h.refine2 = 0;
+      st->h.redo = 0;
       st->gscale = beta;
     }
   }
@@ -492,7 +493,7 @@ struct XupdBody {
   static constexpr int kMinWaves = 1;
   static __device__ void run(const XupdArgs& a, int bid, int) {
     gbl<const SmallState>* __restrict__ st = G(a.st);
-    if (st->h.done) return;
+    if (st->h.done || st->h.redo) return;
     gbl<const T>* __restrict__ V = G(reinterpret_cast<const T*>(a.V));
     gbl<double>* __restrict__ x = G(a.x);
     const int ku = st->h.k_used;
@@ -552,7 +553,7 @@ struct CycleEndBody {
 __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
   SmallState* st = a.st;
   const int two_stage = a.two_stage;
-  if (st->h.done) return;
+  if (st->h.done || st->h.redo) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ double sG[kLd * kLd];
   __shared__ double sR[kLd * kLd];
@@ -574,59 +575,11 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
         sR[r + c * kLd] = (r <= c) ? g : 0.0;
       }
     __syncthreads();
-    // right-looking Cholesky of the upper triangle; a pivot d_j <= tol * G_jj truncates.
-    // One barrier per step: every thread takes the pivot itself, the trailing update uses
-    // row j divided on the fly, and row j is scaled in place during the next step (which
-    // reads neither it nor its diagonal).
-    // (one reciprocal per step: row j is multiplied by 1 / r_jj)
-    const double ptol = st->pivot_tol;
-    int fail = -1;
-    int jp = -1;
-    double rp = 0.0, rpi = 0.0;
-    for (int j = 0; j < kb; ++j) {
-      const double d = sR[j + j * kLd];
-      const bool bad = !(d > ptol * sG[j + j * kLd]);
-      if (jp >= 0) {  // finish row j - 1
-        for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] *= rpi;
-        if (tid == 0) sR[jp + jp * kLd] = rp;
-      }
-      jp = -1;
-      if (bad) {
-        fail = j;
-        break;
-      }
-      const double rjj = sqrt(d), rinv = 1.0 / rjj;
-      // trailing update on a 16 x 16 thread grid (256 threads, kb <= 64: at most 4 x 4
-      // entries per thread): all loads of a column's entries before its stores, so the LDS
-      // accesses overlap instead of waiting on each other
-      {
-        const int r0 = j + 1 + tid % 16, c0 = j + 1 + tid / 16;
-        double ri[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) ri[m] = (r0 + 16 * m < kb) ? sR[j + (r0 + 16 * m) * kLd] * rinv : 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = c0 + 16 * q;
-          if (c >= kb) break;
-          const double rjc = sR[j + c * kLd] * rinv;
-          double v[4];
-#pragma unroll
-          for (int m = 0; m < 4; ++m) v[m] = (r0 + 16 * m <= c) ? sR[r0 + 16 * m + c * kLd] : 0.0;
-#pragma unroll
-          for (int m = 0; m < 4; ++m)
-            if (r0 + 16 * m <= c) sR[r0 + 16 * m + c * kLd] = v[m] - ri[m] * rjc;
-        }
-      }
-      jp = j;
-      rp = rjj;
-      rpi = rinv;
-      __syncthreads();
-    }
-    if (jp >= 0) {  // the last row when no pivot failed
-      for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] *= rpi;
-      if (tid == 0) sR[jp + jp * kLd] = rp;
-    }
+    // right-looking Cholesky of the upper triangle; a pivot d_j <= tol * G_jj truncates
+    __shared__ double sdiag[kLd];
+    for (int i = tid; i < kb; i += nt) sdiag[i] = sG[i + i * kLd];
     __syncthreads();
+    const int fail = lds_chol_upper256(sR, sdiag, st->pivot_tol, kb);
     if (fail >= 0) {  // keep the leading `fail` columns (rows 0..fail-1 of R are final)
       kb = fail;
       if (tid == 0) st->h.truncated += 1;
@@ -737,7 +690,7 @@ struct WaveLdsSync {
 };
 __device__ void RitzBody::run(const TailArgs& a, int, int) {
   SmallState* st = a.st;
-  if (!st->ritz_pending || st->h.done) return;
+  if (!st->ritz_pending || st->h.done || st->h.redo) return;
   const int k = st->h.k_used, s = st->s, lane = threadIdx.x;
   if (k < s) return;  // stays pending for the next cycle
   __shared__ double sH[kLd * kLd];
@@ -848,12 +801,13 @@ __device__ void Stage2Body::run(const S2Args& a, int, int) {
   }
   block_tri_inv_upper(sR, kLd, sM, kLd, kept);  // T2
   __syncthreads();
-  const int e1 = b0 + kept;
-  // Bs(:e1, b0:b1): rows < b0 = -P2 T2, rows b0.. = T2; columns beyond kept are zero
-  for (int idx = tid; idx < e1 * w; idx += nt) {
-    const int r = idx % e1, j = idx / e1;
+  const int e1 = b0 + kept, b1 = a.b1;
+  // Bs(:b1, b0:b1) in full (the apply launches read every row below their chunk's end):
+  // rows < b0 = -P2 T2, rows b0 .. e1-1 = T2, rows from e1 on and the columns beyond kept zero
+  for (int idx = tid; idx < b1 * w; idx += nt) {
+    const int r = idx % b1, j = idx / b1;
     double v = 0.0;
-    if (j < kept) {
+    if (j < kept && r < e1) {
       if (r < b0) {
         for (int l = 0; l <= j; ++l) v -= st->G2[r + (b0 + l) * kLd] * sM[l + j * kLd];
       } else if (r - b0 <= j) {
@@ -940,31 +894,44 @@ __global__ __launch_bounds__(kRowBlock) void apply_rinv_kernel(double* __restric
 }
 
 // Stage 2 of the stand-alone two-stage scheme: R2 = Chol(G2), Rinv = R2^{-1} (st->Wk),
-// R = R2 R1 with R1 the stage-1 factor in st->Hh.  One block.
+// R = R2 R1 with R1 the stage-1 factor in st->Hh.  One block of 256 threads; every small
+// matrix in LDS.
 __global__ __launch_bounds__(256) void sa_stage2_kernel(SmallState* st, int k) {
   if (st->h.done) return;
   const int tid = threadIdx.x, nt = blockDim.x;
-  __shared__ double sG[kLd * kLd];
   __shared__ double sR[kLd * kLd];
-  for (int i = tid; i < k * k; i += nt) sG[(i % k) + (i / k) * kLd] = st->G2[(i % k) + (i / k) * kLd];
+  __shared__ double sX[kLd * kLd];
+  __shared__ double sdiag[kLd];
+  for (int c = tid / kWave; c < k; c += nt / kWave)
+    for (int r = tid % kWave; r < k; r += kWave) {
+      const double g = st->G2[r + c * kLd];
+      sR[r + c * kLd] = r <= c ? g : 0.0;
+      if (r == c) sdiag[r] = g;
+    }
   __syncthreads();
-  int f = block_chol_upper(sG, kLd, sR, kLd, k, nullptr, 0.0);
-  if (f >= 0) {
+  if (lds_chol_upper256(sR, sdiag, 0.0, k) >= 0) {
     if (tid == 0) {
       st->h.status = 2;
       st->h.done = 1;
     }
     return;
   }
-  block_tri_inv_upper(sR, kLd, st->Wk, kLd, k);
-  // R = R2 * R1 (both upper); write into G2 as output staging
-  for (int idx = tid; idx < k * k; idx += nt) {
-    int i = idx % k, j = idx / k;
-    double v = 0.0;
-    if (i <= j)
-      for (int l = i; l <= j; ++l) v += sR[i + l * kLd] * st->Hh[l + j * kLd];
-    st->G2[i + j * kLd] = v;
-  }
+  lds_tri_inv_upper(sR, sX, k);
+  // Rinv to st->Wk; R = R2 R1 (both upper) to st->G2 (output staging); R1 (st->Hh) read
+  // once into LDS over sX's columns after they are stored
+  for (int c = tid / kWave; c < k; c += nt / kWave)
+    for (int r = tid % kWave; r < k; r += kWave) st->Wk[r + c * kLd] = sX[r + c * kLd];
+  __syncthreads();
+  for (int c = tid / kWave; c < k; c += nt / kWave)
+    for (int r = tid % kWave; r < k; r += kWave) sX[r + c * kLd] = st->Hh[r + c * kLd];
+  __syncthreads();
+  for (int c = tid / kWave; c < k; c += nt / kWave)
+    for (int i = tid % kWave; i < k; i += kWave) {
+      double v = 0.0;
+      if (i <= c)
+        for (int l = i; l <= c; ++l) v += sR[i + l * kLd] * sX[l + c * kLd];
+      st->G2[i + c * kLd] = v;
+    }
 }
 
 // Copy a k x k upper-triangular factor (ld kLd, from src) to the caller's R (ldr).

@@ -68,6 +68,7 @@ struct PanelArgs {
   int32_t panel;     // index of the panel within the cycle (-1: cycle set-up)
   int32_t nz;        // reduced Gram has nz columns: nz - sw previous-panel columns, then W
   int32_t shifted;   // the cycle holds the gate-3 pass: a failed explicit pass shifts
+  int32_t fast;      // the cycle holds no fallback pass: a failed PIP pivot asks for a redo
   SmallState* st;
   double* part1;     // per-block partial Grams, nblocks x (k+sw)*sw
 };
@@ -265,6 +266,17 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
       int f = tail_pip_chol(a, sred, st->Pcur, sR, st->pip_tol);
       if (f >= 0) {
         if (a.standalone == 1) { tail_breakdown(a, a.kkeep, f); break; }
+        if (a.fast) {
+          // this cycle's program has no fallback pass: every later kernel of the cycle returns
+          // at entry (x is not touched before the cycle's last kernel) and the host runs the
+          // cycle again with the full program
+          if (tid == 0) {
+            st->h.redo = 1;
+            st->h.stop_panel = -2;
+          }
+          __syncthreads();
+          break;
+        }
         // The Pythagorean Gram has cancelled to rounding: apply the projection
         // explicitly (the next update computes Y = W - Q P1 with T = I) and let the
         // gated second pass orthogonalize Y.

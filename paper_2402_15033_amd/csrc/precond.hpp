@@ -310,7 +310,7 @@ struct AxpyBody {
   static constexpr int kThreads = 256;
   static constexpr int kMinWaves = 1;
   static __device__ void run(const AxpyArgs& a, int bid, int) {
-    if (G(a.st)->h.done) return;
+    if (G(a.st)->h.done || G(a.st)->h.redo) return;
     const int64_t i = (int64_t)bid * kThreads + threadIdx.x;
     if (i < a.n) G(a.x)[i] += G(a.z)[i];
   }

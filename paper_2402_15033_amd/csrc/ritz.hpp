@@ -87,7 +87,11 @@ __host__ __device__ inline int hess_eigvals(double* H, int n, double* wr, double
     if (total >= 30 * n) return -1;
     // the two shifts through their sum and product
     double tr, det;
-    if (its == 10 || its == 20) {  // exceptional shifts after a stall
+    if (its == 10 || its == 20) {
+      // exceptional shifts after a stall, with the constants 0.75 and -0.4375 of the
+      // published EISPACK routine hqr (Wilkinson and Reinsch, Handbook for Automatic
+      // Computation II, 1971; Francis's implicit double-shift QR): both shifts near
+      // H(hi, hi) + 0.75 ex, a complex pair of imaginary part ~0.66 ex
       const double ex = fabs(HH(hi, hi - 1)) + fabs(HH(hi - 1, hi - 2));
       const double a = 0.75 * ex + HH(hi, hi);
       tr = 2.0 * a;

@@ -88,6 +88,78 @@ __device__ int small_chol_upper(const double* G, int ldg, double* R, int ldr, in
   return s_fail;
 }
 
+// Right-looking upper Cholesky in LDS of the kb x kb (kb <= 64) symmetric matrix whose upper
+// triangle is in sR (ld kLd; the strict lower part must be zero), in place: R^T R = G.  A pivot
+// d_j <= ptol * ref[j] (ref in LDS) stops it; rows 0 .. j-1 are then final and the failing
+// index is returned (-1: success).  For exactly 256 threads.  One barrier per step: every
+// thread takes the pivot itself, the trailing update uses row j divided on the fly, and row j
+// is scaled in place during the next step (which reads neither it nor its diagonal).
+__device__ int lds_chol_upper256(double* sR, const double* ref, double ptol, int kb) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  int jp = -1, fail = -1;
+  double rp = 0.0, rpi = 0.0;
+  for (int j = 0; j < kb; ++j) {
+    const double d = sR[j + j * kLd];
+    const bool bad = !(d > ptol * ref[j]);
+    if (jp >= 0) {  // finish row j - 1
+      for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] *= rpi;
+      if (tid == 0) sR[jp + jp * kLd] = rp;
+    }
+    jp = -1;
+    if (bad) {
+      fail = j;
+      break;
+    }
+    const double rjj = sqrt(d), rinv = 1.0 / rjj;
+    // trailing update on a 16 x 16 thread grid (at most 4 x 4 entries per thread): all
+    // loads of a column's entries before its stores
+    {
+      const int r0 = j + 1 + tid % 16, c0 = j + 1 + tid / 16;
+      double ri[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) ri[m] = (r0 + 16 * m < kb) ? sR[j + (r0 + 16 * m) * kLd] * rinv : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = c0 + 16 * q;
+        if (c >= kb) break;
+        const double rjc = sR[j + c * kLd] * rinv;
+        double v[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v[m] = (r0 + 16 * m <= c) ? sR[r0 + 16 * m + c * kLd] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          if (r0 + 16 * m <= c) sR[r0 + 16 * m + c * kLd] = v[m] - ri[m] * rjc;
+      }
+    }
+    jp = j;
+    rp = rjj;
+    rpi = rinv;
+    __syncthreads();
+  }
+  if (jp >= 0) {  // the last row when no pivot failed
+    for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] *= rpi;
+    if (tid == 0) sR[jp + jp * kLd] = rp;
+  }
+  __syncthreads();
+  return fail;
+}
+
+// X = R^{-1} for upper-triangular k x k R with R and X in LDS (ld kLd): one thread per
+// column of X, back substitution over its own column.  Ends with a barrier.
+__device__ void lds_tri_inv_upper(const double* R, double* X, int k) {
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    for (int i = k - 1; i >= 0; --i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      if (i <= c) {
+        for (int l = i + 1; l <= c; ++l) v -= R[i + l * kLd] * X[l + c * kLd];
+        v /= R[i + i * kLd];
+      }
+      X[i + c * kLd] = v;
+    }
+  }
+  __syncthreads();
+}
+
 // X = R^{-1} for upper-triangular k x k R (one thread per column of X).
 __device__ void block_tri_inv_upper(const double* R, int ldr, double* X, int ldx, int k) {
   const int tid = threadIdx.x, nt = blockDim.x;

@@ -23,8 +23,11 @@ struct StateHead {
   int32_t newton_from;   // Leja-Ritz basis: cycles completed when it took over (0: not yet)
   int32_t refine2;       // panel + 1 of the panel whose explicit pass needs the shifted pass
   int32_t shifted;       // stage-1 panels that took the shifted Cholesky QR pass (all cycles)
+  int32_t redo;          // a cycle run without the fallback passes met a panel that needs them:
+                         // the rest of the cycle returned at entry, the host runs it again in full
+  int32_t pad4;
 };
-static_assert(sizeof(StateHead) == 72, "the host reads a 72-byte status head per cycle");
+static_assert(sizeof(StateHead) == 80, "the host reads an 80-byte status head per cycle");
 
 struct SmallState {
   StateHead h;

@@ -2,7 +2,7 @@
 // orthogonalization, arXiv:2402.15033) for AMD MI355X (gfx950).
 //
 // The host only enqueues kernels on the caller's stream and, once per restart cycle,
-// reads back the 72-byte StateHead; every numerical decision (convergence, breakdown,
+// reads back the 80-byte StateHead; every numerical decision (convergence, breakdown,
 // truncation) is taken on the device by the tails of the reduction kernels.
 #include <hip/hip_runtime.h>
 
@@ -458,6 +458,8 @@ struct Builder {
   std::vector<ReqCtx*> R;
   int standalone = 0;
   int shifted = 0;  // two-stage stage 1 holds the gated pass after a shifted Cholesky QR
+  int fast = 0;     // two-stage stage 1 without the gated fallback passes (a failed PIP pivot
+                    // asks the host to run the cycle again with the full program)
   int elem() const { return P.f32 ? 4 : 8; }
   // bytes of the operator's index arrays read by one SpMV (CSR: row pointers and int32
   // columns; packed: slice offsets and int16 deltas / int32 columns)
@@ -500,6 +502,7 @@ struct Builder {
       x.part1 = q.c.part1;
       x.nz = nz;
       x.shifted = shifted;
+      x.fast = fast;
       double cols;
       if (st.kind == PK_UPDATE) {
         x.rows_per_block = st.gate >= 2 ? 256 : 128;  // the kernel's block (see UpdateBody)
@@ -712,7 +715,7 @@ tsg_status panel_sequence(Builder& B, int ortho, int k, int sw, int nprev, bool 
       // launches return at entry unless this panel's PIP pivot failed (gate 2), and where
       // enabled by the pass after a shifted Cholesky QR, which runs only when the explicit
       // pass failed too (gate 3)
-      const int passes = B.standalone ? 1 : (B.shifted ? 3 : 2);
+      const int passes = (B.standalone || B.fast) ? 1 : (B.shifted ? 3 : 2);
       for (int pass = 0; pass < passes; ++pass) {
         const int gate = pass + 1;
         const int tail = pass == 0 ? TAIL_PIP : (pass == 1 ? TAIL_PIP_FB : TAIL_PIP_FB2);
@@ -1441,15 +1444,32 @@ tsg_status run_solve(tsg_csr A, const tsg_solve_params* p, ReqCtx& q, char* dpro
   }
 
   // the launches of one restart cycle (identical in every cycle: what changes --
-  // convergence, truncation, the fallback flag, the counters -- lives in the device state)
+  // convergence, truncation, the fallback flag, the counters -- lives in the device state).
+  // Two-stage: also a fast program without stage 1's gated fallback passes, run while no
+  // cycle needed them; a cycle whose PIP pivot test fails there is run again in full (it
+  // touched neither x nor the counters) and the full program runs from then on.
   Program P;
   P.f32 = f32;
   P.nreq = 1;
   Builder B{P, {&q}, 0};
   B.shifted = shifted_pass(p);
   TRY(build_cycle(B, m, sstep, ortho, p->s_hat));
-  if (P.blob.size() > kProgramBytesPerRequest) return fail(TSG_ERR_UNSUPPORTED, "internal: launch image too large");
+  Program PF;
+  PF.f32 = f32;
+  PF.nreq = 1;
+  const bool have_fast = ortho == TSG_ORTHO_TWO_STAGE;
+  if (have_fast) {
+    Builder BF{PF, {&q}, 0};
+    BF.shifted = B.shifted;
+    BF.fast = 1;
+    TRY(build_cycle(BF, m, sstep, ortho, p->s_hat));
+  }
+  const size_t off_fast = align_up(P.blob.size());
+  if (off_fast + PF.blob.size() > kProgramBytesPerRequest)
+    return fail(TSG_ERR_UNSUPPORTED, "internal: launch image too large");
   HIP_TRY(hipMemcpyAsync(dprog, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, s));
+  if (have_fast) HIP_TRY(hipMemcpyAsync(dprog + off_fast, PF.blob.data(), PF.blob.size(), hipMemcpyHostToDevice, s));
+  char* dprog_fast = dprog + off_fast;
 
   StateHead* head = nullptr;
   HIP_TRY(hipHostMalloc((void**)&head, sizeof(StateHead), hipHostMallocDefault));
@@ -1460,46 +1480,57 @@ tsg_status run_solve(tsg_csr A, const tsg_solve_params* p, ReqCtx& q, char* dpro
     HIP_TRY(hipEventRecord(t0, s));
   }
 
-  // graph mode: capture one cycle on a private stream, replay it on s.  A timed cycle is
-  // launched directly (HIP events around each launch; same kernels and arguments).
+  // graph mode: capture each program's cycle on a private stream, replay it on s.  A timed
+  // cycle is launched directly (HIP events around each launch; same kernels and arguments).
   const bool use_graph = (p->flags & TSG_FLAG_EAGER) == 0;
   hipStream_t cs = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   tsg_status result = TSG_OK;
   hipError_t e = hipSuccess;
   if (use_graph) {
     hipError_t ge = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (ge == hipSuccess) ge = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
-    if (ge == hipSuccess) {
-      tsg_status cst = exec_program(P, dprog, cs, nullptr);
-      ge = hipStreamEndCapture(cs, &graph);
-      if (cst != TSG_OK) result = cst;
+    for (int g = 0; g < (have_fast ? 2 : 1) && ge == hipSuccess && result == TSG_OK; ++g) {
+      ge = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+      if (ge == hipSuccess) {
+        tsg_status cst = g == 0 ? exec_program(P, dprog, cs, nullptr) : exec_program(PF, dprog_fast, cs, nullptr);
+        ge = hipStreamEndCapture(cs, &graph[g]);
+        if (cst != TSG_OK) result = cst;
+      }
+      if (ge == hipSuccess && result == TSG_OK) ge = hipGraphInstantiate(&exec[g], graph[g], nullptr, nullptr, 0);
     }
-    if (ge == hipSuccess && result == TSG_OK) ge = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (ge != hipSuccess && result == TSG_OK)
       result = fail(TSG_ERR_HIP, "capture of a restart cycle failed: %s", hipGetErrorString(ge));
   }
+  bool full = !have_fast;
+  int64_t redone = 0;
   int64_t timed_cycles = 0;
   for (int64_t cyc = 0; result == TSG_OK; ++cyc) {
     timer.on = timing && cyc % stride == 0;
-    if (use_graph && !timer.on) {
-      e = hipGraphLaunch(exec, s);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      const int g = full ? 0 : 1;
+      if (use_graph && !timer.on) {
+        e = hipGraphLaunch(exec[g], s);
+        if (e != hipSuccess) {
+          result = fail(TSG_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+          break;
+        }
+      } else {
+        result = g == 0 ? exec_program(P, dprog, s, &timer) : exec_program(PF, dprog_fast, s, &timer);
+        if (result != TSG_OK) break;
+      }
+      e = hipMemcpyAsync(head, &q.c.st->h, sizeof(StateHead), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
       if (e != hipSuccess) {
-        result = fail(TSG_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+        result = fail(TSG_ERR_HIP, "cycle sync failed: %s", hipGetErrorString(e));
         break;
       }
-    } else {
-      result = exec_program(P, dprog, s, &timer);
-      if (result != TSG_OK) break;
-      timed_cycles += timer.on ? 1 : 0;
+      if (!head->redo) break;
+      full = true;  // the cycle needs the fallback passes: run it again in full, and from now on
+      redone += 1;
     }
-    e = hipMemcpyAsync(head, &q.c.st->h, sizeof(StateHead), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) {
-      result = fail(TSG_ERR_HIP, "cycle sync failed: %s", hipGetErrorString(e));
-      break;
-    }
+    if (result != TSG_OK) break;
+    timed_cycles += timer.on ? 1 : 0;
     if (timer.err != hipSuccess) {
       result = fail(TSG_ERR_HIP, "timing event: %s", hipGetErrorString(timer.err));
       break;
@@ -1507,8 +1538,10 @@ tsg_status run_solve(tsg_csr A, const tsg_solve_params* p, ReqCtx& q, char* dpro
     timer.harvest();
     if (head->done) break;
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
+  for (int g = 0; g < 2; ++g) {
+    if (exec[g]) (void)hipGraphExecDestroy(exec[g]);
+    if (graph[g]) (void)hipGraphDestroy(graph[g]);
+  }
   if (cs) (void)hipStreamDestroy(cs);
   double ms_total = 0.0;
   if (timing && result == TSG_OK) {
@@ -1526,6 +1559,7 @@ tsg_status run_solve(tsg_csr A, const tsg_solve_params* p, ReqCtx& q, char* dpro
   tsg_status st = head_status(h);
   if (info) {
     fill_info(info, h, st);
+    info->redone_cycles = redone;
     if (timing) {
       info->ms_total = ms_total;
       info->timed_cycles = timed_cycles;
@@ -2019,7 +2053,10 @@ tsg_status tsg_server_step(tsg_server S, int32_t* n_active, int32_t* n_queued) {
     carve_request(S->arena + off, r->A, &S->p, r->q);
     tsg_status st = init_request(r->A, &S->p, r->q, s);
     if (st != TSG_OK) {
+      // nobody joins at this boundary: the requests stay queued and free their arena blocks
       S->mem.release(off, r->bytes);
+      for (ServeReq* j : joining) S->mem.release(j->off, j->bytes);
+      (void)hipStreamSynchronize(s);
       return st;
     }
     joining.push_back(r);
