@@ -41,6 +41,14 @@ __device__ __forceinline__ gbl<T>* G(T* p) {
   return (gbl<T>*)p;
 }
 
+// Wave-level synchronization of LDS traffic (workgroup-scope fences only: no cache
+// write-back, just ordering of this wave's LDS accesses).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

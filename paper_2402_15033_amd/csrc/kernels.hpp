@@ -10,13 +10,6 @@ namespace tsg {
 constexpr int kRowBlock = 256;  // threads (rows) per block of the row-parallel kernels
 
 // ------------------------------------------------------------------ matrix powers
-// Wave-level synchronization of LDS traffic (workgroup-scope fences only: no cache
-// write-back, just ordering of this wave's LDS accesses).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 constexpr int kSegCap = 8 * kWave;  // products staged per wave (rows of <= 8 nonzeros on average)
 

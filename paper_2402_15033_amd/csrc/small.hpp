@@ -93,7 +93,9 @@ __device__ int small_chol_upper(const double* G, int ldg, double* R, int ldr, in
 // d_j <= ptol * ref[j] (ref in LDS) stops it; rows 0 .. j-1 are then final and the failing
 // index is returned (-1: success).  For exactly 256 threads.  One barrier per step: every
 // thread takes the pivot itself, the trailing update uses row j divided on the fly, and row j
-// is scaled in place during the next step (which reads neither it nor its diagonal).
+// is scaled in place during the next step (which reads neither it nor its diagonal).  (A
+// single-wave version with wave-level syncs only was measured slower: the per-step chain of
+// dependent LDS accesses of one wave costs more than the barrier of four.)
 __device__ int lds_chol_upper256(double* sR, const double* ref, double ptol, int kb) {
   const int tid = threadIdx.x, nt = blockDim.x;
   int jp = -1, fail = -1;

@@ -36,73 +36,6 @@ struct MfmaOp<float> {
   __device__ static int row(int lk, int r) { return 4 * lk + r; }
 };
 
-// Batch staging shared by the MFMA kernels.  A block of 8 waves moves batches of BR rows of
-// ncol <= 64 basis columns into an LDS tile (column-major, row stride BR + 1, two buffers).
-// A batch is 64 load items of 64 R rows of one column (R = 8 / sizeof(T): each lane loads
-// one double or two adjacent floats, 8 bytes either way); item t = wave + 8 sl, sl < 8,
-// holds column t % ncol, row chunk t / ncol.  So BR = 64 R floor(64 / ncol): every lane
-// keeps 8 loads of 8 bytes in flight whatever ncol is.
-constexpr int kTileItems = 64;
-template <typename T>
-constexpr int tile_rows_per_lane() { return 8 / (int)sizeof(T); }
-template <typename T>
-constexpr int mfma_tile() { return kWave * kTileItems * tile_rows_per_lane<T>() + kMaxCols; }
-
-template <typename T>
-struct TileLoad {
-  static constexpr int R = tile_rows_per_lane<T>(), SL = 8, NW = 8;
-  int64_t colbase[SL];
-  int rowoff[SL], ldsof[SL];
-  int items, BR, LDT;
-  // staged column c is V(:, c) for c < kq, else V(:, wcol + c - kq)
-  __device__ void init(int wv, int ncol, int kq, int64_t wcol, int64_t ld) {
-    const int RB = kTileItems / ncol;
-    BR = kWave * R * RB;
-    LDT = BR + 1;
-    items = ncol * RB;
-#pragma unroll
-    for (int sl = 0; sl < SL; ++sl) {
-      const int t = wv + NW * sl;
-      const int c = t % ncol, chunk = t / ncol;
-      colbase[sl] = ((c < kq) ? (int64_t)c : wcol + (c - kq)) * ld;
-      rowoff[sl] = chunk * kWave * R;
-      ldsof[sl] = c * LDT + chunk * kWave * R;
-    }
-  }
-  // Every lane issues all SL loads, with no branch, so that the compiler can count them and
-  // wait only for the batch it needs (a load under a branch made it wait for every load in
-  // flight, the prefetched batches included).  Rows past re are clamped to the last row
-  // pair that starts before re (in bounds, their values unused) and zeroed by to_lds, and
-  // so are the items t >= items (whose column t % ncol exists).
-  __device__ void load(gbl<const T>* __restrict__ V, int wv, int lane, int64_t r0, int64_t re,
-                       T (&dst)[SL][R]) const {
-    const int64_t rmax = (re - 1) & ~(int64_t)(R - 1);
-#pragma unroll
-    for (int sl = 0; sl < SL; ++sl) {
-      const int64_t row = min(r0 + rowoff[sl] + (int64_t)R * lane, rmax);
-      if constexpr (R == 2) {
-        typedef float f2 __attribute__((ext_vector_type(2)));
-        const f2 x = *reinterpret_cast<gbl<const f2>*>(V + colbase[sl] + row);
-        dst[sl][0] = x.x;
-        dst[sl][1] = x.y;
-      } else {
-        dst[sl][0] = V[colbase[sl] + row];
-      }
-    }
-  }
-  __device__ void to_lds(T* L, int wv, int lane, int64_t r0, int64_t re, const T (&src)[SL][R]) const {
-#pragma unroll
-    for (int sl = 0; sl < SL; ++sl) {
-      const int t = wv + NW * sl;
-      if (t < items) {
-        const int64_t row = r0 + rowoff[sl] + (int64_t)R * lane;
-#pragma unroll
-        for (int e = 0; e < R; ++e) L[ldsof[sl] + R * lane + e] = row + e < re ? src[sl][e] : (T)0;
-      }
-    }
-  }
-};
-
 // The reduction G = V(:, 0:ncol)^T V(:, ncol-nz : ncol) of a panel step on the matrix cores
 // (ncol = k + sw, Q = V(:, 0:k), W = V(:, wcol:wcol+sw); the nz right-hand columns are the
 // previous panel's nprev columns, their block column of the stage-2 Gram, followed by W),
@@ -111,16 +44,17 @@ struct TileLoad {
 // t, column c_t + i and the RL consecutive rows r + RL g .. r + RL g + RL - 1 of a group of
 // 4 RL rows (two 16-byte loads per tile: RL = 4 in FP64, 8 in FP32); K-step e of the group
 // pairs row r + RL g + e with k index g in both operands.  The tiles are laid out from the
-// right: the last NT tiles are the nz right-hand columns (the B operand is the A operand of
-// those tiles, no extra load) and MA - NT tiles cover the columns to their left down to
-// column 0 (lanes outside [0, ncol) hold zeros).  Each wave walks its own groups (wave w:
+// right: the last NT tiles are the last 16 NT columns (from column 0 if there are fewer),
+// which hold the nz right-hand columns -- the B operand is the A operand of those tiles, no
+// extra load, and the products with their other columns are dropped -- and MA - NT tiles
+// cover the columns to their left down to column 0 (lanes outside [0, ncol) hold zeros).  Each wave walks its own groups (wave w:
 // groups w, w + NW, ... of the block's rows) with one group's loads in flight while the
 // matrix cores consume the previous one; the loads are unconditional (the index is clamped
 // to the last full group), so the compiler waits only for the group it consumes.  A ragged
 // last group (and every group when the columns are not 16-byte aligned) is loaded element
 // by element with its rows masked.  The NW waves' tiles are summed in LDS in wave order at
 // the end.  Partials: ncol x nz float64 per block.  Measured on a 4194304 x 61 FP64 block:
-// 6.07 TB/s with 256 blocks against 4.73 for the LDS-staged version.
+// 5.5-6.1 TB/s against 4.73 for an LDS-staged version with block barriers.
 template <typename T>
 constexpr int gram_rows_per_lane() { return 32 / (int)sizeof(T); }
 constexpr int kGramGroupRows = 32;  // row blocks of the reduction are multiples of this
@@ -141,6 +75,7 @@ __device__ void GramBody<T, MA, NT>::run(const PanelArgs& a, int bid, int) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int g = lane >> 4, li = lane & 15;
   const int k = a.k, ncol = a.k + a.sw, nz = a.nz, z0 = ncol - nz;
+  const int zb = max(0, ncol - 16 * NT);  // first column of the right-hand tiles (zb <= z0)
   const int64_t ld = a.ld, n = a.n;
   gbl<const T>* __restrict__ V = G(reinterpret_cast<const T*>(a.V));
   // per tile: this lane's column (offset of its first element) and whether it exists
@@ -148,7 +83,7 @@ __device__ void GramBody<T, MA, NT>::run(const PanelArgs& a, int bid, int) {
   bool cval[MA];
 #pragma unroll
   for (int t = 0; t < MA; ++t) {
-    const int c = z0 + 16 * (t - (MA - NT)) + li;
+    const int c = zb + 16 * (t - (MA - NT)) + li;
     cval[t] = c >= 0 && c < ncol;
     const int cc = cval[t] ? c : 0;
     coff[t] = (int64_t)(cc < k ? cc : a.wcol + (cc - k)) * ld + RL * g;
@@ -230,13 +165,13 @@ __device__ void GramBody<T, MA, NT>::run(const PanelArgs& a, int bid, int) {
     for (int t = 0; t < MA; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int c = z0 + 16 * (t - (MA - NT)) + MfmaOp<T>::row(g, r);
+        const int c = zb + 16 * (t - (MA - NT)) + MfmaOp<T>::row(g, r);
         if (c >= 0 && c < ncol) red[(wv * RC + c) * 16 + li] = acc[t][u][r];
       }
     __syncthreads();
     for (int e = threadIdx.x; e < ncol * 16; e += blockDim.x) {
-      const int c = e / 16, z = u * 16 + e % 16;
-      if (z < nz) {
+      const int c = e / 16, z = zb + u * 16 + e % 16 - z0;  // right-hand column zb + 16 u + e % 16
+      if (z >= 0 && z < nz) {
         double sum = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) sum += (double)red[(w * RC + c) * 16 + e % 16];
@@ -251,8 +186,13 @@ __device__ void GramBody<T, MA, NT>::run(const PanelArgs& a, int bid, int) {
 // 5.68, 1024 blocks 5.86 at MA = 5), more blocks for narrower reductions (MA = 1: 1024
 // blocks 4.70 TB/s, 512 blocks 4.55).
 inline int gram_max_blocks(int ma) { return ma <= 1 ? 1024 : (ma == 2 ? 512 : 256); }
-// Column tiles of a reduction of ncol columns against its last nz.
-inline int gram_tiles(int ncol, int nz) { return (nz + 15) / 16 + (ncol - nz + 15) / 16; }
+// Column tiles of a reduction of ncol columns against its last nz: the right-hand tiles
+// (the last 16 ceil(nz / 16) columns) and the tiles to their left.
+inline int gram_tiles(int ncol, int nz) {
+  const int nt = (nz + 15) / 16;
+  const int left = ncol > 16 * nt ? ncol - 16 * nt : 0;
+  return nt + (left + 15) / 16;
+}
 
 // y(j) -= sum over columns c0 .. c0 + K - 1 of Q(r, c) P(c, j), in column order; the K
 // loads of the row's Q entries are issued before the first product.
@@ -334,50 +274,57 @@ __device__ void UpdateBody<T, S, kBlock>::run(const PanelArgs& a, int bid, int) 
 
 
 
-// The fused panel step on the matrix cores: per row, the update
+// The fused panel step: per row, the update
 //     q = (W(r,:) - Q(r,:) P) T          (PF_HAS_P / PF_HAS_T; Q = V(:,0:k), W = V(:,wcol:+sw))
 // stored in place (PF_STORE), and the Gram of its output  G = [Q, q]^T q  (PF_GRAM_Q: Q rows;
-// the q rows always), in one pass over the rows.  Batches of the staged columns (Q when
-// it is needed, then W) go through LDS as in TileLoad.  The update is itself a product:
-// q = [Q, W] B with B = [-P T; T] ((k+sw) x sw, formed once per block in LDS), so each
-// 16-row tile of the batch is multiplied by B on the matrix cores (rows are the M
-// dimension, the staged columns the K dimension) and q is written over W in the tile;
-// after a barrier the matrix cores reduce the Gram of the tile (rows as the K dimension), and
-// the waves store q from LDS in whole row segments.  Partials: (k + sw) x sw float64 per
-// block (rows of Q zero unless PF_GRAM_Q).  Requires sw <= 16.
-template <typename T, int MT>
+// the q rows always), in one pass over the rows.  The update is a product q = [Q, W] B with
+// B = [-P T; T] ((k+sw) x sw, formed once per block in LDS; PF_BMAT: B given in st->Bs), done
+// on the matrix cores with the rows as the M dimension: for K-step ks (staged columns 4 ks ..
+// 4 ks + 3) lane l = 16 g + i takes row r0 + i of staged column 4 ks + g straight from
+// global memory (each load instruction covers 16 consecutive rows of 4 columns), and the
+// result lane (g, i) holds q(row(g, r), i) for r = 0..3.  The Gram needs the rows as the K
+// dimension instead: the wave writes its 16 x (k+sw) tile -- Q as loaded, q in place of W --
+// to a wave-private LDS tile and reads it back column-wise as the A operand, while the B
+// operand is q as the update left it (K-step e pairs row row(g, e) with k index g in both).
+// Each wave walks its own 16-row groups with the next group's loads in flight; there is no
+// block barrier in the row loop.  Partials: (k + sw) x sw float64 per block (rows of Q zero
+// unless PF_GRAM_Q).  Requires sw <= 16 and k + sw <= 16 NC.
+constexpr int kFusedGroupRows = 16;  // row blocks of the fused step are multiples of this
+template <typename T, int NC>
 struct FusedBody {
   typedef PanelArgs Args;
   static constexpr int kThreads = 512;
-  static constexpr int kMinWaves = 4;  // two 8-wave blocks per CU
+  static constexpr int kMinWaves = 1;
   static __device__ void run(const PanelArgs& a, int bid, int nb);
 };
-template <typename T, int MT>
-__device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
+template <typename T, int NC>
+__device__ void FusedBody<T, NC>::run(const PanelArgs& a, int bid, int) {
   if (gated_off(a, a.st)) return;
   gbl<const SmallState>* st = G(a.st);
   typedef typename MfmaOp<T>::v4 v4;
-  typedef TileLoad<T> TL;
-  constexpr int NW = 8, SL = TL::SL, R = TL::R;
+  constexpr int NW = kThreads / kWave, NKS = 4 * NC, GR = kFusedGroupRows;
+  constexpr int LS = sizeof(T) == 8 ? 66 : 68;  // LDS row stride: <= 2-way bank conflicts
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
+  const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int g = lane >> 4, li = lane & 15;
   const int k = a.k, sw = a.sw, flags = a.flags;
   const bool hasP = flags & PF_HAS_P;
   const bool hasT = (flags & PF_HAS_T) && !st->identity_t;
   const bool store = flags & PF_STORE;
   const bool gramQ = flags & PF_GRAM_Q;
-  const int kq = (hasP || gramQ || (flags & PF_BMAT)) ? k : 0;  // staged Q columns
-  const int ncol = kq + sw;                // staged columns: Q then W
-  const int a0 = gramQ ? 0 : kq;           // first staged column on the A side of the Gram
-  const int ncolA = ncol - a0;
+  const bool bmat = flags & PF_BMAT;
+  const bool gram = flags & (PF_GRAM_Q | PF_GRAM_W);
+  const int kq = (hasP || gramQ || bmat) ? k : 0;  // staged Q columns
+  const int ncol = kq + sw;                        // staged columns: Q then W
+  const int a0 = gramQ ? 0 : kq;                   // first staged column on the A side of the Gram
+  const int mat = gram ? (ncol - a0 + 15) / 16 : 0;
   gbl<T>* __restrict__ V = G(reinterpret_cast<T*>(a.V));
   const int64_t ld = a.ld;
-  __shared__ T lt[2][mfma_tile<T>()];
-  __shared__ T lB[(kMaxCols + 4) * 16];  // B(c, j) at c * 16 + j, zero-padded to 16 columns
+  __shared__ T lB[(kMaxCols + 4) * 16];  // B(c, j) at c * 16 + j, zero-padded
+  __shared__ T lt[NW * GR * LS];          // per-wave tiles; the cross-wave sums at the end
   // B = [-P T; T]: rows c < kq from the projection, rows kq + i from T (identity if no T);
   // PF_BMAT: B given in st->Bs, staged column c being basis column c (kq = wcol)
-  const bool bmat = flags & PF_BMAT;
   for (int idx = tid; idx < (kMaxCols + 4) * 16; idx += blockDim.x) {
     const int c = idx / 16, j = idx % 16;
     double v = 0.0;
@@ -399,103 +346,107 @@ __device__ void FusedBody<T, MT>::run(const PanelArgs& a, int bid, int) {
     }
     lB[idx] = (T)v;
   }
-  const bool gram = flags & (PF_GRAM_Q | PF_GRAM_W);
-  TL tl;
-  tl.init(wv, ncol, kq, a.wcol, ld);
-  const int BR = tl.BR, LDT = tl.LDT;
-
+  __syncthreads();
   const int64_t rb = (int64_t)bid * a.rows_per_block;
   const int64_t re = min(a.n, rb + a.rows_per_block);
-  T v[SL][R], vn[SL][R], vnn[SL][R];
-  v4 acc[MT];
+  const int64_t nfull = (re - rb) / GR;
+  const int64_t shift = (int64_t)a.wcol - kq;  // staged column c >= kq is basis column c + shift
+  // element offset of row i of staged K-step column 4 ks + g (clamped into the staged columns;
+  // B's rows past ncol are zero)
+  auto coff = [&](int ks) -> int64_t {
+    const int c = min(4 * ks + g, ncol - 1);
+    return (int64_t)(c + (c >= kq ? shift : 0)) * ld + li;
+  };
+  v4 acc[NC];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) acc[mt] = v4{0, 0, 0, 0};
-  const int li = lane & 15, lk = lane >> 4;
-  const int ksteps_upd = (ncol + 3) / 4;
-  // prefetch depth 2 with three register buffers taking turns, loop unrolled by 6 (the
-  // compiler drains the loads in flight at the loop head)
-  int buf = 0;
-  auto batch = [&](const T (&cur)[SL][R], T (&fut)[SL][R], int64_t r0) {
-    tl.load(V, wv, lane, r0 + 2 * BR, re, fut);
-    T* L = lt[buf];
-    tl.to_lds(L, wv, lane, r0, re, cur);
-    __syncthreads();
-    // ---- q = [Q, W] B for 16-row tiles: lane holds A(row li, column kk + lk) and
-    //      B(kk + lk, li); the wave's rows are its own, so it overwrites their W in place
-    for (int m0 = wv * 16; m0 < BR; m0 += NW * 16) {
-      v4 d = v4{0, 0, 0, 0};
-      for (int ks = 0; ks < ksteps_upd; ++ks) {
-        const int c = ks * 4 + lk;
-        const T av = (c < ncol) ? L[c * LDT + m0 + li] : (T)0;
-        d = MfmaOp<T>::mac(av, lB[c * 16 + li], d);
-      }
-      if (li < sw) {
+  for (int t = 0; t < NC; ++t) acc[t] = v4{0, 0, 0, 0};
+  T* L = lt + wv * GR * LS;
+  auto load = [&](int64_t r0, T (&v)[NKS]) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) L[(kq + li) * LDT + m0 + MfmaOp<T>::row(lk, r)] = d[r];
-      }
-    }
-    __syncthreads();
-    // ---- Gram of the tile on the matrix cores; q back to HBM in whole row segments
-    for (int ks = wv; gram && ks < BR / 4; ks += NW) {
-      const int row = ks * 4 + lk;
-      const T bv = (li < sw) ? L[(kq + li) * LDT + row] : (T)0;
+    for (int ks = 0; ks < NKS; ++ks) v[ks] = V[coff(ks) + r0];
+  };
+  // one group of rows r0 .. r0 + 15 (rows from nrows on are padding, zero in v)
+  auto group = [&](int64_t r0, const T (&v)[NKS], int nrows) {
+    v4 d = v4{0, 0, 0, 0};
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int c = a0 + mt * 16 + li;
-        const T av = (c < ncol) ? L[c * LDT + row] : (T)0;
-        acc[mt] = MfmaOp<T>::mac(av, bv, acc[mt]);
+    for (int ks = 0; ks < NKS; ++ks) d = MfmaOp<T>::mac(v[ks], lB[(4 * ks + g) * 16 + li], d);
+    if (store && li < sw) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = MfmaOp<T>::row(g, r);
+        if (row < nrows) V[(int64_t)(a.wcol + li) * ld + r0 + row] = d[r];
       }
     }
-    if (store) {
-      const int nchunk = BR / (kWave * R);
-      for (int t = wv; t < sw * nchunk; t += NW) {
-        const int j = t % sw, chunk = t / sw;
-        const int rl = chunk * kWave * R + R * lane;
+    if (!gram) return;
+    // the wave's tile: Q as loaded (row li of staged column 4 ks + g), q over W's columns
 #pragma unroll
-        for (int e = 0; e < R; ++e) {
-          const int64_t row = r0 + rl + e;
-          if (row < re) V[((int64_t)a.wcol + j) * ld + row] = L[(kq + j) * LDT + rl + e];
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int c = 4 * ks + g;
+      if (gramQ && c < kq) L[li * LS + c] = v[ks];
+    }
+    if (li < sw) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) L[MfmaOp<T>::row(g, r) * LS + kq + li] = d[r];
+    }
+    wave_lds_sync();
+    const T bq[4] = {li < sw ? d[0] : (T)0, li < sw ? d[1] : (T)0, li < sw ? d[2] : (T)0, li < sw ? d[3] : (T)0};
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      if (t < mat) {
+        const int c = a0 + 16 * t + li;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const T av = c < ncol ? L[MfmaOp<T>::row(g, e) * LS + c] : (T)0;
+          acc[t] = MfmaOp<T>::mac(av, bq[e], acc[t]);
         }
       }
     }
-    buf ^= 1;
+    wave_lds_sync();
   };
-  tl.load(V, wv, lane, rb, re, v);
-  tl.load(V, wv, lane, rb + BR, re, vn);
-  for (int64_t r0 = rb; r0 < re; r0 += 6 * BR) {
-    batch(v, vnn, r0);
-    if (r0 + BR >= re) break;
-    batch(vn, v, r0 + BR);
-    if (r0 + 2 * BR >= re) break;
-    batch(vnn, vn, r0 + 2 * BR);
-    if (r0 + 3 * BR >= re) break;
-    batch(v, vnn, r0 + 3 * BR);
-    if (r0 + 4 * BR >= re) break;
-    batch(vn, v, r0 + 4 * BR);
-    if (r0 + 5 * BR >= re) break;
-    batch(vnn, vn, r0 + 5 * BR);
+  if (nfull > 0) {
+    T va[NKS], vb[NKS];
+    int64_t q = wv;
+    load(rb + GR * min<int64_t>(q, nfull - 1), va);
+    for (; q < nfull; q += 2 * NW) {
+      load(rb + GR * min<int64_t>(q + NW, nfull - 1), vb);
+      group(rb + GR * q, va, GR);
+      if (q + NW >= nfull) break;
+      load(rb + GR * min<int64_t>(q + 2 * NW, nfull - 1), va);
+      group(rb + GR * (q + NW), vb, GR);
+    }
+  }
+  if (re - rb - GR * nfull > 0 && wv == (int)(nfull % NW)) {  // the ragged last group
+    const int64_t r0 = rb + GR * nfull;
+    const int nrows = (int)(re - r0);
+    T v[NKS];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) v[ks] = li < nrows ? V[coff(ks) + r0] : (T)0;
+    group(r0, v, nrows);
   }
   if (!gram) return;
+  // sum the NW waves' tiles in wave order: red[w][c][z], c < 16 NC, z < 16 (fits lt)
+  static_assert(NW * 16 * NC * 16 <= NW * GR * LS, "reduction buffer");
   __syncthreads();
-  T* red = &lt[0][0];
+  T* red = lt;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+  for (int t = 0; t < NC; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int c = mt * 16 + MfmaOp<T>::row(lk, r);
-      red[(wv * kMaxCols + c) * 16 + li] = acc[mt][r];
+      const int c = 16 * t + MfmaOp<T>::row(g, r);
+      red[(wv * 16 * NC + c) * 16 + li] = acc[t][r];
     }
   __syncthreads();
   gbl<double>* part1 = G(a.part1) + (size_t)bid * (k + sw) * sw;
   if (!gramQ) {
     for (int e = tid; e < k * sw; e += blockDim.x) part1[e] = 0.0;
   }
+  const int ncolA = ncol - a0;
   for (int e = tid; e < ncolA * 16; e += blockDim.x) {
     const int c = e / 16, z = e % 16;
     if (z < sw) {
       double sum = 0.0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) sum += (double)red[(w * kMaxCols + c) * 16 + z];
+      for (int w = 0; w < NW; ++w) sum += (double)red[(w * 16 * NC + c) * 16 + z];
       const int sc = a0 + c;  // staged column
       const int prow = sc < kq ? sc : k + (sc - kq);
       part1[prow * sw + z] = sum;

@@ -233,6 +233,8 @@ struct Timer {
 int s_template(int sw) { return sw <= 6 ? sw : (sw <= 8 ? 8 : (sw <= 10 ? 10 : (sw <= 12 ? 12 : 16))); }
 constexpr int kMaxGramNz = kMaxNz;   // widest lean reduction (two 16-wide MFMA tiles)
 constexpr int kMaxMfmaBlocks = 512;  // two 8-wave blocks per CU
+// the fused step's registers (two groups of operands in flight) allow one 8-wave block per CU
+constexpr int kMaxFusedBlocks = 256;
 constexpr int64_t kGsBlock = 8192;   // rows per block of the preconditioned system's order
 static_assert(kMaxMfmaBlocks <= kMaxReduceBlocks, "reduction partial buffer too small");
 // Device bytes reserved for the launch image of one request's program.
@@ -520,12 +522,10 @@ struct Builder {
           return fail(TSG_ERR_WORKSPACE, "internal: reduction partials (%d blocks x %d) exceed the buffer", nb[r],
                       (st.k + st.sw) * nz);
       } else {
-        const int rpl = P.f32 ? tile_rows_per_lane<float>() : tile_rows_per_lane<double>();
         const int staged = (st.flags & PF_BMAT) ? st.k + st.sw : (loadQ ? st.k : 0) + st.sw;
-        const int br = kWave * rpl * (kTileItems / staged);  // the MFMA kernels' batch height
-        int64_t tiles = cdiv(q.n, br);
-        int b0 = (int)std::min<int64_t>(tiles, kMaxMfmaBlocks);
-        x.rows_per_block = cdiv(cdiv(q.n, b0), br) * br;
+        const int64_t groups = cdiv(q.n, kFusedGroupRows);
+        const int b0 = (int)std::min<int64_t>(groups, kMaxFusedBlocks);
+        x.rows_per_block = cdiv(cdiv(q.n, b0), kFusedGroupRows) * kFusedGroupRows;
         nb[r] = (int)cdiv(q.n, x.rows_per_block);
         cols = staged + ((st.flags & PF_STORE) ? st.sw : 0);
         reduces = (st.flags & (PF_GRAM_Q | PF_GRAM_W)) != 0;
@@ -543,8 +543,8 @@ struct Builder {
     } else if (gram) {
       P.add(F_GRAM, gram_tiles(st.k + st.sw, nz), nz <= 16 ? 1 : 2, a, nb, kc, fb ? 0.0 : bytes);
     } else {
-      const int ncolA = (st.flags & PF_GRAM_Q) ? st.k + st.sw : st.sw;
-      P.add(F_FUSED, std::max(1, (ncolA + 15) / 16), 0, a, nb, kc, fb ? 0.0 : bytes);
+      const int staged = (st.flags & (PF_HAS_P | PF_GRAM_Q | PF_BMAT)) ? st.k + st.sw : st.sw;
+      P.add(F_FUSED, (staged + 15) / 16, 0, a, nb, kc, fb ? 0.0 : bytes);
     }
     if (!reduces) return TSG_OK;
     // first level for requests with many blocks, then the tail.  The gated passes (which
