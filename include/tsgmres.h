@@ -274,8 +274,11 @@ size_t tsg_orthogonalize_workspace_bytes(int64_t n, int32_t k, int32_t s);
  * R upper triangular with positive diagonal (the contract of Fig. 1's caption).
  * Column 1 is normalized alone; then panels of s columns (the last may be short).
  * algo: TWO_STAGE (stage 1 = BCGS-PIP per panel, stage 2 = one CholQR over all k
- * columns, then Q = Qhat R2^{-1}), BCGS_PIP2 or BCGS2_CHOLQR2.  s_hat must be 0 or
- * k-1.  R (device, k x k, column-major, leading dimension ldr >= k) receives R; its
+ * columns, then Q = Qhat R2^{-1}), BCGS_PIP2 or BCGS2_CHOLQR2.  s_hat (TWO_STAGE): 0 or
+ * >= k-1 for one big panel; else a multiple of s: big panels of s_hat columns (the first
+ * also holds column 1, the last may be short), each orthogonalized by stage 2 = BCGS-PIP
+ * against the final columns before it, its Q made explicit before the next big panel's
+ * stage 1 (Sec. V, Fig. 5; stage 1 projects every panel against all earlier columns).  R (device, k x k, column-major, leading dimension ldr >= k) receives R; its
  * strictly lower part is set to 0.  Requires 1 <= k <= 64, 1 <= s <= 16, k <= n.
  * Synchronizes `stream` before returning (the breakdown status is read back).  If
  * orth_err (host) is non-NULL, ||I - Q^T Q||_F is also computed on the device (one

@@ -400,14 +400,16 @@ def _block_view(X: torch.Tensor, ldx):
 
 
 def orthogonalize(X: torch.Tensor, s: int = 5, algo: str = "two_stage", *, ldx: int | None = None,
-                  orth_err: bool = False, workspace: torch.Tensor | None = None, noalloc: bool = False):
+                  orth_err: bool = False, workspace: torch.Tensor | None = None, noalloc: bool = False,
+                  s_hat: int = 0):
     """Orthonormalize the n x k block in place.
 
     X is a float64 device tensor viewed as column-major: either a (k, ldx) contiguous tensor
     whose row c is column c of the block, or an (n, k) tensor with stride (1, ldx) (e.g. the
     transpose of a contiguous (k, n) tensor).  Returns (X, R[, ||I - Q^T Q||_F]).
     noalloc=True calls tsg_orthogonalize_noalloc (the library's own static scratch, no
-    workspace).
+    workspace).  s_hat (two-stage): 0 for one big panel, else the big-panel size (a multiple
+    of s), each big panel's Q made final by its stage 2.
     """
     lib = load_library()
     n, k, ld = _block_view(X, ldx)
@@ -415,7 +417,7 @@ def orthogonalize(X: torch.Tensor, s: int = 5, algo: str = "two_stage", *, ldx: 
     a = ORTHO[algo] if isinstance(algo, str) else int(algo)
     err = C.c_double(0.0)
     if noalloc:
-        st = lib.tsg_orthogonalize_noalloc(n, k, X.data_ptr(), ld, R.data_ptr(), k, int(s), 0, a,
+        st = lib.tsg_orthogonalize_noalloc(n, k, X.data_ptr(), ld, R.data_ptr(), k, int(s), int(s_hat), a,
                                            _stream(X.device), C.byref(err) if orth_err else None)
         _check(st)
     else:
@@ -423,7 +425,7 @@ def orthogonalize(X: torch.Tensor, s: int = 5, algo: str = "two_stage", *, ldx: 
         if need == 0:
             _check(-1)
         ws, wp = _workspace(need, X.device, workspace)
-        st = lib.tsg_orthogonalize(n, k, X.data_ptr(), ld, R.data_ptr(), k, int(s), 0, a, wp, need,
+        st = lib.tsg_orthogonalize(n, k, X.data_ptr(), ld, R.data_ptr(), k, int(s), int(s_hat), a, wp, need,
                                    _stream(X.device), C.byref(err) if orth_err else None)
         _check(st)
         del ws

@@ -752,7 +752,8 @@ __global__ __launch_bounds__(kWave) void ritz_newton_kernel(const double* H, int
 // failure at column f keeps the big panel's first f columns and ends the cycle.
 struct S2Args {
   SmallState* st;
-  int32_t b0, b1, panel, pad;
+  int32_t b0, b1, panel;
+  int32_t standalone;  // stand-alone orthogonalization: R-factor update instead of H and Givens
 };
 struct Stage2Body {
   typedef S2Args Args;
@@ -783,6 +784,14 @@ __device__ void Stage2Body::run(const S2Args& a, int, int) {
   const int f = block_chol_upper(sG, kLd, sR, kLd, w, sref, st->pivot_tol);
   if (tid == 0) s_kept = f < 0 ? w : f;
   __syncthreads();
+  if (a.standalone && f >= 0) {  // stand-alone: the big panel's Gram is not positive definite
+    if (tid == 0) {
+      st->h.status = 2;
+      st->h.done = 1;
+      st->fail_col = b0 + f;
+    }
+    return;
+  }
   const int kept = s_kept;
   if (kept == 0) {  // nothing of this big panel survives: keep the final columns before it
     if (tid == 0) {
@@ -810,6 +819,31 @@ __device__ void Stage2Body::run(const S2Args& a, int, int) {
     st->Bs[r + (b0 + j) * kLd] = v;
   }
   __syncthreads();
+  if (a.standalone) {
+    // the R factor X = Y Rh of the columns so far: Y(:, b0:b1) = Q(:, :b0) P2 + Q(:, b0:b1) R2,
+    // so Rh(:b0, b0:b1) += P2 Rh(b0:b1, b0:b1) and Rh(b0:b1, b0:b1) = R2 Rh(b0:b1, b0:b1)
+    // (the big panel's rows have no entries left of column b0); Rb in LDS first (sG is free)
+    for (int idx = tid; idx < w * w; idx += nt) {
+      const int i = idx % w, j = idx / w;
+      sG[i + j * kLd] = i <= j ? st->Hh[(b0 + i) + (b0 + j) * kLd] : 0.0;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < b1 * w; idx += nt) {
+      const int r = idx % b1, j = idx / b1;
+      double v;
+      if (r < b0) {
+        v = st->Hh[r + (b0 + j) * kLd];
+        for (int l = 0; l <= j; ++l) v += st->G2[r + (b0 + l) * kLd] * sG[l + j * kLd];
+      } else {
+        const int i = r - b0;
+        v = 0.0;
+        for (int l = i; l <= j; ++l) v += sR[i + l * kLd] * sG[l + j * kLd];
+      }
+      st->Hh[r + (b0 + j) * kLd] = v;
+    }
+    __syncthreads();
+    return;
+  }
   // M (e1 x e1) into sM; X = M H(:e1, :c) into sG; H(:e1, :c) = X M(:c, :c)^{-1}
   const int c = e1 - 1;
   for (int idx = tid; idx < e1 * e1; idx += nt) {

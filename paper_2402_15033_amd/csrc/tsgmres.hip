@@ -651,7 +651,7 @@ struct Builder {
   tsg_status big_stage2(int b0, int b1, int panel) {
     std::vector<S2Args> t;
     std::vector<int> one(R.size(), 1);
-    for (ReqCtx* q : R) t.push_back(S2Args{q->c.st, b0, b1, panel, 0});
+    for (ReqCtx* q : R) t.push_back(S2Args{q->c.st, b0, b1, panel, standalone ? 1 : 0});
     P.add(F_S2, 0, 0, t, one, TSG_KC_STAGE2, 0.0);
     const int nchunks = (b1 - b0 + 15) / 16;
     for (int ch = nchunks - 1; ch >= 0; --ch) {
@@ -1644,8 +1644,11 @@ tsg_status orthogonalize_check(int64_t n, int32_t k, const double* X, int64_t ld
   if (s < 1 || s > kMaxS) return fail(TSG_ERR_INVALID_ARG, "s=%d outside [1, 16]", s);
   if (algo != TSG_ORTHO_TWO_STAGE && algo != TSG_ORTHO_BCGS_PIP2 && algo != TSG_ORTHO_BCGS2_CHOLQR2)
     return fail(TSG_ERR_INVALID_ARG, "bad algo %d", algo);
-  if (algo == TSG_ORTHO_TWO_STAGE && s_hat != 0 && s_hat != k - 1)
-    return fail(TSG_ERR_UNSUPPORTED, "s_hat=%d: only one big panel (s_hat = k-1) is built", s_hat);
+  if (s_hat != 0 && s_hat < k - 1) {
+    if (algo != TSG_ORTHO_TWO_STAGE) return fail(TSG_ERR_INVALID_ARG, "s_hat=%d is a two-stage parameter", s_hat);
+    if (s_hat < s || s_hat % s != 0)
+      return fail(TSG_ERR_INVALID_ARG, "s_hat=%d must be a multiple of s=%d (or 0, or >= k-1)", s_hat, s);
+  }
   return TSG_OK;
 }
 
@@ -1654,7 +1657,7 @@ tsg_status orthogonalize_check(int64_t n, int32_t k, const double* X, int64_t ld
 // call (small state, reduction partials, launch image) is carved from it, and everything
 // read before it is written is initialized here.
 tsg_status orthogonalize_ws(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr, int32_t s,
-                            int32_t algo, char* ws, hipStream_t st, double* orth_err) {
+                            int32_t s_hat, int32_t algo, char* ws, hipStream_t st, double* orth_err) {
   Carve cv{ws};
   Common c = carve_common(cv, n);
   char* dprog = cv.take<char>(kProgramBytesPerRequest);
@@ -1691,13 +1694,29 @@ tsg_status orthogonalize_ws(int64_t n, int32_t k, double* X, int64_t ldx, double
   TRY(B.step(upd_step(g00 ? PK_FUSED : PK_UPDATE, 0, 0, 1, PF_HAS_T | PF_STORE | (g00 ? PF_GRAM_W : 0),
                       g00 ? TAIL_NORM0 : TAIL_NONE, -1, 0)));
   const bool lean2 = 2 * s <= kMaxGramNz;
-  for (int c0 = 1; c0 < k; c0 += s) {
+  // big panels of the two-stage scheme (Sec. V, Fig. 5): the first holds column 0 and s_hat
+  // columns, every later one s_hat columns (the last may be short); s_hat = 0 or >= k - 1:
+  // one big panel, whose stage 2 is the CholQR of all k columns below
+  const bool big = two && s_hat > 0 && s_hat < k - 1;
+  int b0 = 0, b1 = big ? 1 + s_hat : k;
+  int panel = 0;
+  for (int c0 = 1; c0 < k; c0 += s, ++panel) {
     const int sw = std::min(s, k - c0);
     const bool last = c0 + sw >= k;
-    // previous columns reduced along: column 0 for the first panel, else the previous panel
-    // (panels before the last have width s)
-    const int nprev = !two ? 0 : (c0 == 1 ? (g00 ? 0 : 1) : (lean2 ? s : 0));
-    TRY(panel_sequence(B, algo, c0, sw, nprev, last || !lean2, 0, 0));
+    const bool ends_big = big && c0 + sw == b1;
+    // previous columns reduced along: column 0 for the first panel, none for the first panel
+    // of a later big panel (the panel before formed its own block column), else the previous
+    // panel (panels before the last have width s)
+    const int nprev = !two ? 0 : (c0 == 1 ? (g00 ? 0 : 1) : ((big && c0 == b0) || !lean2 ? 0 : s));
+    // the panel index gates each stage 1 sequence on its own fallback flag
+    TRY(panel_sequence(B, algo, c0, sw, nprev, last || ends_big || !lean2, big ? panel : 0, 0));
+    if (ends_big) {
+      // stage 2 of the big panel: BCGS-PIP against the final columns before it, the R factor
+      // updated, and Y(:, b0:b1) <- Y(:, :b1) Bs in 16-column chunks (explicit Q)
+      TRY(B.big_stage2(b0, b1, big ? panel : 0));
+      b0 = b1;
+      b1 = std::min(b0 + s_hat, k);
+    }
   }
   const size_t n_main = P.phases.size();
   if (orth_err) {  // the Gram of the result, 16 columns at a time, into st->Wk
@@ -1709,7 +1728,9 @@ tsg_status orthogonalize_ws(int64_t n, int32_t k, double* X, int64_t ldx, double
   if (P.blob.size() > kProgramBytesPerRequest) return fail(TSG_ERR_UNSUPPORTED, "internal: launch image too large");
   HIP_TRY(hipMemcpyAsync(dprog, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, st));
   TRY(exec_program(P, dprog, st, nullptr, 0, n_main));
-  if (two) {
+  if (big) {  // every big panel's Q is final: the R factor is the assembly in st->Hh
+    hipLaunchKernelGGL(copy_r_kernel, dim3(1), dim3(256), 0, st, c.st, 0, k, R, ldr);
+  } else if (two) {
     // stage 2: one CholQR over all k columns, then Q = Qhat R2^{-1}
     hipLaunchKernelGGL(sa_stage2_kernel, dim3(1), dim3(256), 0, st, c.st, k);
     HIP_LAUNCH_CHECK();
@@ -1748,7 +1769,7 @@ tsg_status tsg_orthogonalize(int64_t n, int32_t k, double* X, int64_t ldx, doubl
   size_t need = tsg_orthogonalize_workspace_bytes(n, k, s);
   if (need == 0) return fail(TSG_ERR_INVALID_ARG, "problem too large for the reduction buffers");
   if (ws_bytes < need) return fail(TSG_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, need);
-  return orthogonalize_ws(n, k, X, ldx, R, ldr, s, algo, (char*)workspace, (hipStream_t)stream, orth_err);
+  return orthogonalize_ws(n, k, X, ldx, R, ldr, s, s_hat, algo, (char*)workspace, (hipStream_t)stream, orth_err);
 }
 
 // ------------------------------------------------------------------ one stage-1 panel
@@ -1878,7 +1899,7 @@ tsg_status tsg_orthogonalize_noalloc(int64_t n, int32_t k, double* X, int64_t ld
                 (long long)n, k, s, need, kNoAllocScratchBytes, (long long)kNoAllocMaxRows);
   void* ws = nullptr;
   TRY(scratch_address(&ws));
-  return orthogonalize_ws(n, k, X, ldx, R, ldr, s, algo, static_cast<char*>(ws), (hipStream_t)stream, orth_err);
+  return orthogonalize_ws(n, k, X, ldx, R, ldr, s, s_hat, algo, static_cast<char*>(ws), (hipStream_t)stream, orth_err);
 }
 
 // =================================================================== solve server

@@ -71,6 +71,38 @@ def test_full_solve_gates(tsg, lap2048):
     assert info.iters == 60 * info.cycles
 
 
+@pytest.mark.parametrize("kind,N,basis", [("laplace3d", 160, "monomial"), ("convdiff2d", 2048, "shifted")])
+def test_fullsize_configs_two_cycles_and_gates(tsg, kind, N, basis):
+    """The other full-size configurations, FP64, m = 60, s = 5, two-stage: 3D Laplace 160^3
+    (n = 4,096,000, the stand-in for Table 4's Laplace3D) and 2D convection-diffusion 2048^2.
+    The first two restart cycles against the oracle's (the same cycles, so the iterates agree
+    to rounding), then the full solve: explicit FP64 relative residual <= 1e-10 recomputed by
+    the oracle's SpMV, and for the Laplacian the error against x_true within 2 tol kappa_2
+    (kappa_2 = 1.0505e4 in closed form)."""
+    _say("case fullsize", kind, N, basis)
+    pr = W.make_problem(kind, N, seed=0)
+    op = S.Operator(pr["A"])
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    b = torch.as_tensor(pr["b"], device="cuda")
+    x, info = tsg.solve(A, b, m=60, s=5, tol=1e-10, basis=basis, max_iters=120)
+    assert info.status == 1 and info.iters == 120 and info.cycles == 2
+    ref = G.sstep_gmres(op, pr["b"], m=60, s=5, tol=1e-10, basis=basis, max_iters=120)
+    err2 = np.linalg.norm(x.cpu().numpy() - ref["x"]) / np.linalg.norm(ref["x"])
+    _say(f"  |x_gpu - x_oracle| / |x_oracle| after 2 cycles = {err2:.3e}")
+    assert err2 <= 1e-10
+    x, info = tsg.solve(A, b, m=60, s=5, tol=1e-10, basis=basis)
+    xg = x.cpu().numpy()
+    relres = np.linalg.norm(pr["b"] - S.spmv(op, xg)) / np.linalg.norm(pr["b"])
+    xt = pr["x_true"]
+    err = np.linalg.norm(xg - xt) / np.linalg.norm(xt)
+    _say(f"  iters {info.iters} cycles {info.cycles} relres {relres:.3e} error vs x_true {err:.3e}")
+    assert info.converged and relres <= 1e-10
+    if kind == "laplace3d":
+        lmin, lmax = W.laplace_extreme_eigs(N, 3)
+        assert abs(lmax / lmin - 1.0505e4) <= 1e-3 * 1.0505e4
+        assert err <= 2 * 1e-10 * lmax / lmin
+
+
 def test_ortho_bench_block(tsg):
     _say("case fullsize ortho")
     n, k = 4194304, 61
@@ -109,6 +141,13 @@ def test_mixed_precision_convdiff2048(tsg):
     _say(f"  iters {info.iters} cycles {info.cycles} fallbacks {info.pip_fallbacks} "
          f"truncated {info.truncated_cycles} relres {relres:.3e}")
     assert info.converged and relres <= 1e-10
+    # the error of the mixed form per solve, against the plain FP64 solve and x_true
+    x64, i64 = tsg.solve(A, b, m=60, s=5, tol=1e-10, basis="shifted")
+    x64 = x64.cpu().numpy()
+    xt = pr["x_true"]
+    _say(f"  |x_mixed - x_fp64| / |x_fp64| = {np.linalg.norm(xg - x64) / np.linalg.norm(x64):.3e}; "
+         f"error vs x_true: mixed {np.linalg.norm(xg - xt) / np.linalg.norm(xt):.3e}, "
+         f"fp64 {np.linalg.norm(x64 - xt) / np.linalg.norm(xt):.3e} ({i64.iters} iterations)")
 
 
 @pytest.mark.parametrize("basis", ["shifted", "leja"])
