@@ -40,6 +40,17 @@ template <typename T>
 __device__ __forceinline__ gbl<T>* G(T* p) {
   return (gbl<T>*)p;
 }
+// The same wave-uniform pointer as a generic one that the compiler knows to point to device
+// memory: a round trip through address space 1, kept from folding away by an empty asm on
+// the scalar registers holding it.  Code that takes plain pointers derived from it (struct
+// members, helper arguments) then compiles its accesses to global loads and stores instead
+// of flat ones.
+template <typename T>
+__device__ __forceinline__ T* Gp(T* p) {
+  gbl<T>* q = (gbl<T>*)p;
+  __asm__ volatile("" : "+s"(q));
+  return (T*)q;
+}
 
 // Wave-level synchronization of LDS traffic (workgroup-scope fences only: no cache
 // write-back, just ordering of this wave's LDS accesses).
@@ -47,6 +58,14 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Lane `src`'s value (src uniform) in every lane of the wave.
+__device__ __forceinline__ double wave_bcast(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -72,12 +91,20 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return x * per + (x < rem ? x : rem) + j;
 }
 
-// sum_{b < count} p[b * stride] in the order b = 0, 1, ...; the loads go in groups of 8
-// issued before their adds (one memory round trip per group instead of one per term).
+// sum_{b < count} p[b * stride] in the order b = 0, 1, ...; the loads go in groups of 32,
+// then of 8, issued before their adds (one memory round trip per group instead of one per
+// term: a tail summing 32 first-level partials waits for one).
 __device__ __forceinline__ double sum_strided(const double* p_, size_t stride, int count) {
   gbl<const double>* __restrict__ p = G(p_);
   double acc = 0.0;
   int b = 0;
+  for (; b + 32 <= count; b += 32) {
+    double v[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) v[u] = p[(size_t)(b + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) acc += v[u];
+  }
   for (; b + 8 <= count; b += 8) {
     double v[8];
 #pragma unroll

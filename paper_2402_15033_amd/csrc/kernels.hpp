@@ -324,7 +324,7 @@ struct RTailBody {
   static __device__ void run(const TailArgs& a, int bid, int nb);
 };
 __device__ void RTailBody::run(const TailArgs& a, int, int) {
-  SmallState* st = a.st;
+  SmallState* st = Gp(a.st);  // (global, not flat, accesses)
   const double* part1 = a.part1;
   const int nblocks = a.nblocks;
   if (st->h.done) return;
@@ -544,13 +544,14 @@ struct CycleEndBody {
   static __device__ void run(const TailArgs& a, int bid, int nb);
 };
 __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
-  SmallState* st = a.st;
+  SmallState* st = Gp(a.st);  // (global, not flat, accesses)
   const int two_stage = a.two_stage;
   if (st->h.done || st->h.redo) return;
+  constexpr int LL = kLdsLd;
   const int tid = threadIdx.x, nt = blockDim.x;
-  __shared__ double sG[kLd * kLd];
-  __shared__ double sR[kLd * kLd];
-  __shared__ double sM[kLd * kLd];
+  __shared__ double sG[kLd * LL];
+  __shared__ double sR[kLd * LL];
+  __shared__ double sM[kLd * LL];
   __shared__ double sg[kLd + 1], sz[kLd];
   __shared__ int s_ku;
   if (tid == 0) s_ku = st->h.k_used;
@@ -560,57 +561,97 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
   double est = 0.0;
   if (two_stage && ku > 0) {
     int kb = ku + 1;
-    // (loops over matrices run on a 64-row x (nt/64)-column thread grid: no integer division)
-    for (int c = tid / kWave; c < kb; c += nt / kWave)
-      for (int r = tid % kWave; r < kb; r += kWave) {
-        const double g = st->G2[r + c * kLd];
-        sG[r + c * kLd] = g;
-        sR[r + c * kLd] = (r <= c) ? g : 0.0;
-      }
-    __syncthreads();
-    // right-looking Cholesky of the upper triangle; a pivot d_j <= tol * G_jj truncates
+    // every global read up front, all in flight at once (one memory round trip instead of
+    // one per loop trip): the upper triangle of G2 (kb x kb) into sR, Hhat (kb x ku) into sG
     __shared__ double sdiag[kLd];
-    for (int i = tid; i < kb; i += nt) sdiag[i] = sG[i + i * kLd];
+    {
+      static_assert(kThreads == 256, "16 entries per thread");
+      constexpr int PER = kLd * kLd / kThreads;
+      double g[PER], h[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + kThreads * u, r = idx % kLd, c = idx / kLd;
+        g[u] = (r <= c && c < kb) ? st->G2[r + c * kLd] : 0.0;
+        h[u] = (r < kb && c < ku) ? st->Hh[r + c * kLd] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int idx = tid + kThreads * u, r = idx % kLd, c = idx / kLd;
+        sR[r + c * LL] = g[u];
+        sG[r + c * LL] = h[u];
+        if (r == c) sdiag[r] = g[u];
+      }
+    }
     __syncthreads();
-    const int fail = lds_chol_upper256(sR, sdiag, st->pivot_tol, kb);
+    // Cholesky of the upper triangle; a pivot d_j <= tol * G_jj truncates
+    const int fail = lds_chol_upper_blk<LL>(sR, sdiag, st->pivot_tol, kb);
     if (fail >= 0) {  // keep the leading `fail` columns (rows 0..fail-1 of R are final)
       kb = fail;
       if (tid == 0) st->h.truncated += 1;
     }
     ku = kb - 1;
     if (ku > 0) {
-      // stage Hhat in LDS (sG is free now), then sM = R2(0:kb,0:kb) Hhat(0:kb,0:ku)
-      for (int j = tid / kWave; j < ku; j += nt / kWave)
-        for (int i = tid % kWave; i < kb; i += kWave) sG[i + j * kLd] = st->Hh[i + j * kLd];
-      __syncthreads();
-      for (int j = tid / kWave; j < ku; j += nt / kWave)
-        for (int i = tid % kWave; i < kb; i += kWave) {
-          double v = 0.0;
-          const int lmax = min(kb - 1, j + 1);
-#pragma unroll 8
-          for (int l = i; l <= lmax; ++l) v += sR[i + l * kLd] * sG[l + j * kLd];
-          sM[i + j * kLd] = v;
+      // sM = R2(0:kb,0:kb) Hhat(0:kb,0:ku): entries (ti + 16 m, tj + 16 q) per thread, the
+      // sum over l in increasing order (terms outside l in [i, min(kb - 1, j + 1)] are exact
+      // zeros)
+      {
+        const int ti = tid % 16, tj = tid / 16;
+        double acc[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[m][q] = 0.0;
+        for (int l = 0; l < kb; ++l) {
+          double ra[4], hb[4];
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int i = ti + 16 * m;
+            ra[m] = (i <= l) ? sR[i + l * LL] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = tj + 16 * q;
+            hb[q] = (j < ku && l <= j + 1) ? sG[l + j * LL] : 0.0;
+          }
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[m][q] += ra[m] * hb[q];
         }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = ti + 16 * m, j = tj + 16 * q;
+            if (i < kb && j < ku) sM[i + j * LL] = acc[m][q];
+          }
+      }
       for (int i = tid; i <= kLd; i += nt) sg[i] = 0.0;
       __syncthreads();
       if (ritz) {  // for the Newton shifts: H(0:ku, 0:ku) = sM(0:ku, 0:ku) R2(0:ku, 0:ku)^{-1}
         for (int r = tid; r < ku; r += nt) {
           for (int j = 0; j < ku; ++j) {
-            double v = sM[r + j * kLd];
-            for (int l = 0; l < j; ++l) v -= st->Wk[r + l * kLd] * sR[l + j * kLd];
-            st->Wk[r + j * kLd] = v / sR[j + j * kLd];
+            double v = sM[r + j * LL];
+            for (int l = 0; l < j; ++l) v -= st->Wk[r + l * kLd] * sR[l + j * LL];
+            st->Wk[r + j * kLd] = v / sR[j + j * LL];
           }
         }
         __syncthreads();
       }
-      if (tid < kWave) {  // wave 0: Givens QR of sM and back substitution
+      if (tid < kWave) {
+        // wave 0: Givens QR of sM and back substitution.  Lane t keeps its column's running
+        // top entry (row i after the rotations so far) in a register and reads row i + 1,
+        // which no rotation has touched yet, from LDS; rotation i is formed by every lane
+        // from lane i's entries; the rotated row i (final) goes to LDS
         const int lane = tid;
-        if (lane == 0) sg[0] = st->beta * sR[0];
-        wave_lds_sync();
-        // every lane forms rotation i itself (the same values from LDS), then rotates its
-        // own column pair; lane 0 the diagonal and the right-hand side
+        const bool col = lane < ku;
+        double x = col ? sM[lane * LL] : 0.0;
+        double y = col ? sM[1 + lane * LL] : 0.0;
+        double gi = st->beta * sR[0];  // the running right-hand side entry (every lane)
+        double gl = 0.0, dl = 1.0;     // lane l: its final right-hand side and R(l, l)
         for (int i = 0; i < ku; ++i) {
-          const double a = sM[i + i * kLd], b = sM[(i + 1) + i * kLd];
+          const double yn = (col && i + 2 <= ku) ? sM[(i + 2) + lane * LL] : 0.0;
+          const double a = wave_bcast(x, i), b = wave_bcast(y, i);
           const double rho = hypot(a, b);
           double c = 1.0, s = 0.0;
           if (rho != 0.0) {
@@ -618,29 +659,28 @@ __device__ void CycleEndBody::run(const TailArgs& a, int, int) {
             c = a * ri;
             s = b * ri;
           }
-          const int t = lane;
-          const bool mine = t > i && t < ku;
-          double x = 0.0, y = 0.0, gi = 0.0;
-          if (mine) {
-            x = sM[i + t * kLd];
-            y = sM[(i + 1) + t * kLd];
+          if (lane > i && col) {
+            sM[i + lane * LL] = c * x + s * y;
+            x = -s * x + c * y;
           }
-          if (lane == 0) gi = sg[i];
-          wave_lds_sync();
-          if (mine) {
-            sM[i + t * kLd] = c * x + s * y;
-            sM[(i + 1) + t * kLd] = -s * x + c * y;
+          if (lane == i) {
+            sM[i + i * LL] = rho;
+            gl = c * gi;
+            dl = rho;
           }
-          if (lane == 0) {
-            sM[i + i * kLd] = rho;
-            sg[i] = c * gi;
-            sg[i + 1] = -s * gi;
-          }
-          wave_lds_sync();
+          gi = -s * gi;
+          y = yn;
         }
-        est = fabs(sg[ku]);
-        wave_back_subst(sM, sg, sz, ku);
-        for (int i = lane; i < ku; i += kWave) st->coef[i] = sz[i];
+        est = fabs(gi);
+        // z = R^{-1} g: z_i = g_i / R(i, i), then g_l -= R(l, i) z_i for l < i
+        wave_lds_sync();
+        double z = 0.0;
+        for (int i = ku - 1; i >= 0; --i) {
+          const double zi = wave_bcast(gl, i) / wave_bcast(dl, i);
+          if (lane == i) z = zi;
+          if (lane < i) gl -= sM[lane + i * LL] * zi;
+        }
+        if (col) st->coef[lane] = z;
       }
     }
   } else if (!two_stage && ku > 0) {
@@ -682,7 +722,7 @@ struct WaveLdsSync {
   __device__ void operator()() const { wave_lds_sync(); }
 };
 __device__ void RitzBody::run(const TailArgs& a, int, int) {
-  SmallState* st = a.st;
+  SmallState* st = Gp(a.st);  // (global, not flat, accesses)
   if (!st->ritz_pending || st->h.done || st->h.redo) return;
   const int k = st->h.k_used, s = st->s, lane = threadIdx.x;
   if (k < s) return;  // stays pending for the next cycle
@@ -762,7 +802,7 @@ struct Stage2Body {
   static __device__ void run(const S2Args& a, int bid, int nb);
 };
 __device__ void Stage2Body::run(const S2Args& a, int, int) {
-  SmallState* st = a.st;
+  SmallState* st = Gp(a.st);  // (global, not flat, accesses)
   if (st->h.done || a.panel > st->h.stop_panel) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int b0 = a.b0, w = a.b1 - a.b0;
@@ -896,69 +936,47 @@ __device__ void Stage2Body::run(const S2Args& a, int, int) {
 }
 
 // ------------------------------------------------------------------ stand-alone ortho
-// Q = Qhat R2^{-1} in place, one row per thread (K = max columns held in registers).
-template <int K>
-__global__ __launch_bounds__(kRowBlock) void apply_rinv_kernel(double* __restrict__ V, int64_t ld,
-                                                               int64_t n, int k,
-                                                               const double* __restrict__ Rinv) {
-  const int64_t r = (int64_t)blockIdx.x * kRowBlock + threadIdx.x;
-  if (r >= n) return;
-  double q[K];
-#pragma unroll
-  for (int c = 0; c < K; ++c) q[c] = (c < k) ? V[(int64_t)c * ld + r] : 0.0;
-#pragma unroll
-  for (int j = K - 1; j >= 0; --j) {
-    if (j < k) {
-      double v = 0.0;
-#pragma unroll
-      for (int i = 0; i <= j; ++i) v += q[i] * Rinv[i + j * kLd];
-      q[j] = v;
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < K; ++c)
-    if (c < k) V[(int64_t)c * ld + r] = q[c];
-}
-
 // Stage 2 of the stand-alone two-stage scheme: R2 = Chol(G2), Rinv = R2^{-1} (st->Wk),
-// R = R2 R1 with R1 the stage-1 factor in st->Hh.  One block of 256 threads; every small
-// matrix in LDS.
+// R = R2 R1 with R1 the stage-1 factor in st->Hh (into st->G2).  One block of 256 threads;
+// every small matrix in LDS, each step parallel over a 16 x 16 thread grid.
 __global__ __launch_bounds__(256) void sa_stage2_kernel(SmallState* st, int k) {
   if (st->h.done) return;
+  constexpr int LL = kLdsLd;
   const int tid = threadIdx.x, nt = blockDim.x;
-  __shared__ double sR[kLd * kLd];
-  __shared__ double sX[kLd * kLd];
+  __shared__ double sR[kLd * LL];
+  __shared__ double sX[kLd * LL];
+  __shared__ double sR1[kLd * LL];
   __shared__ double sdiag[kLd];
-  for (int c = tid / kWave; c < k; c += nt / kWave)
-    for (int r = tid % kWave; r < k; r += kWave) {
-      const double g = st->G2[r + c * kLd];
-      sR[r + c * kLd] = r <= c ? g : 0.0;
-      if (r == c) sdiag[r] = g;
+  {  // every global read up front, all in flight at once
+    constexpr int PER = kLd * kLd / 256;
+    double g[PER], h[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + 256 * u, r = idx % kLd, c = idx / kLd;
+      const bool in = r <= c && c < k;
+      g[u] = in ? st->G2[r + c * kLd] : 0.0;
+      h[u] = in ? st->Hh[r + c * kLd] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int idx = tid + 256 * u, r = idx % kLd, c = idx / kLd;
+      sR[r + c * LL] = g[u];
+      sR1[r + c * LL] = h[u];
+      if (r == c) sdiag[r] = g[u];
+    }
+  }
   __syncthreads();
-  if (lds_chol_upper256(sR, sdiag, 0.0, k) >= 0) {
+  if (lds_chol_upper_blk<LL>(sR, sdiag, 0.0, k) >= 0) {
     if (tid == 0) {
       st->h.status = 2;
       st->h.done = 1;
     }
     return;
   }
-  lds_tri_inv_upper(sR, sX, k);
-  // Rinv to st->Wk; R = R2 R1 (both upper) to st->G2 (output staging); R1 (st->Hh) read
-  // once into LDS over sX's columns after they are stored
+  lds_tri_inv_upper_blk<LL>(sR, sX, k);
   for (int c = tid / kWave; c < k; c += nt / kWave)
-    for (int r = tid % kWave; r < k; r += kWave) st->Wk[r + c * kLd] = sX[r + c * kLd];
-  __syncthreads();
-  for (int c = tid / kWave; c < k; c += nt / kWave)
-    for (int r = tid % kWave; r < k; r += kWave) sX[r + c * kLd] = st->Hh[r + c * kLd];
-  __syncthreads();
-  for (int c = tid / kWave; c < k; c += nt / kWave)
-    for (int i = tid % kWave; i < k; i += kWave) {
-      double v = 0.0;
-      if (i <= c)
-        for (int l = i; l <= c; ++l) v += sR[i + l * kLd] * sX[l + c * kLd];
-      st->G2[i + c * kLd] = v;
-    }
+    for (int r = tid % kWave; r < k; r += kWave) st->Wk[r + c * kLd] = sX[r + c * LL];
+  lds_trmm_upper256<LL>(sR, sR1, G(st->G2), k);
 }
 
 // Copy a k x k upper-triangular factor (ld kLd, from src) to the caller's R (ldr).

@@ -209,7 +209,8 @@ __device__ void tail_set_tinv(SmallState* st, const double* R, int s) {
 
 // The panel's final factors (P, R): V_panel = Q P + Q_new R.  Solver mode: Hessenberg
 // block, and (one-stage) Givens + convergence check.  Stand-alone: R factor assembly.
-__device__ void tail_emit_panel(const PanelArgs& a, const double* P, const double* R, bool givens) {
+__device__ void tail_emit_panel(const PanelArgs& a, const double* P, const double* R, bool givens,
+                                const double* lH) {
   SmallState* st = a.st;
   const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
   const int c0 = a.wcol;
@@ -222,14 +223,14 @@ __device__ void tail_emit_panel(const PanelArgs& a, const double* P, const doubl
     __syncthreads();
     return;
   }
-  block_hessenberg_panel(st->Hh, P, R, st->theta, st->sigma, st->tau, k, s, st->Wk);
+  block_hessenberg_panel(lH, st->Hh, P, R, st->theta, st->sigma, st->tau, k, s);
   if (givens) {
     givens_append(st, st->Hh, k - 1, k - 1 + s);
     tail_check(st, k - 1 + s, a.panel);
   }
 }
 
-__device__ void panel_tail(const PanelArgs& a, const double* sred) {
+__device__ void panel_tail(const PanelArgs& a, const double* sred, const double* lH) {
   SmallState* st = a.st;
   const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
   __shared__ double sR[kMaxS * kMaxS], sR2[kMaxS * kMaxS], sP[kLd * kMaxS];
@@ -294,7 +295,12 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
         break;
       }
       tail_set_tinv(st, sR, s);
-      tail_emit_panel(a, st->Pcur, sR, false);
+      for (int idx = tid; idx < k * s; idx += nt) {  // P from the reduction, in LDS
+        int c = idx % k, j = idx / k;
+        sP[c + j * kLd] = red(a, sred, c, j);
+      }
+      __syncthreads();
+      tail_emit_panel(a, sP, sR, false, lH);
     } break;
     case TAIL_PIP_FB: {
       // second pass on the panel Y = W - Q P1: P2 = Q^T Y, R = Chol(Y^T Y - P2^T P2);
@@ -324,7 +330,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
         sP[c + j * kLd] = st->P1[c + j * kLd] + st->Pcur[c + j * kLd];
       }
       __syncthreads();
-      tail_emit_panel(a, sP, sR, false);
+      tail_emit_panel(a, sP, sR, false, lH);
     } break;
     case TAIL_PIP_FB2: {
       // pass on Z = (Y - Q P2) Rs^{-1}: P3 = Q^T Z, R3 = Chol(Z^T Z - P3^T P3);
@@ -361,7 +367,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
         sP[c + j * kLd] = v;
       }
       __syncthreads();
-      tail_emit_panel(a, sP, sR2, false);
+      tail_emit_panel(a, sP, sR2, false, lH);
     } break;
     case TAIL_G2COL: {
       for (int idx = tid; idx < (k + s) * s; idx += nt) {
@@ -400,7 +406,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
         sR[i + j * kMaxS] = (i <= j) ? v : 0.0;
       }
       __syncthreads();
-      tail_emit_panel(a, sP, sR, true);
+      tail_emit_panel(a, sP, sR, true, lH);
     } break;
     case TAIL_BC_P1: {
       for (int idx = tid; idx < k * s; idx += nt) {
@@ -458,7 +464,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred) {
         sR[i + j * kMaxS] = (i <= j) ? v : 0.0;
       }
       __syncthreads();
-      tail_emit_panel(a, sP, sR, true);
+      tail_emit_panel(a, sP, sR, true, lH);
     } break;
     case TAIL_CGS_H1: {
       for (int c = tid; c < k; c += nt) {
@@ -528,7 +534,7 @@ struct PReduceBody {
   static constexpr int kMinWaves = 1;
   static __device__ void run(const RedArgs& ra, int bid, int) {
     const PanelArgs& a = ra.a;
-    const SmallState* st = a.st;
+    const SmallState* st = Gp(a.st);
     if (gated_off(a, st)) return;
     const int E = (a.k + a.sw) * a.nz;
     const int b0 = bid * ra.chunk, b1 = min(a.nblocks, b0 + ra.chunk);
@@ -545,14 +551,21 @@ struct PTailBody {
   static constexpr int kMinWaves = 1;
   static __device__ void run(const PanelArgs& a, int bid, int nb);
 };
-__device__ void PTailBody::run(const PanelArgs& a, int, int) {
+__device__ void PTailBody::run(const PanelArgs& a_, int, int) {
+  PanelArgs a = a_;
+  a.st = Gp(a_.st);  // (device memory: global, not flat, accesses in every helper)
   SmallState* st = a.st;
   if (gated_off(a, st)) return;
   __shared__ double sred[kMaxCols * kMaxNz];
   __shared__ double scratch[kTailThreads];
+  __shared__ double lH[kLd * kLd];
+  // a solver tail may append a Hessenberg block: H's loads go out with the reduction's
+  HessPrefetch pf;
+  if (!a.standalone) hessenberg_prefetch(st->Hh, a.k, pf);
   const int E = (a.k + a.sw) * a.nz;
   block_sum_partials(a.part1, E, a.nblocks, sred, scratch);
-  panel_tail(a, sred);
+  if (!a.standalone) hessenberg_store(pf, lH);  // read after the tail's first barrier
+  panel_tail(a, sred, lH);
 }
 
 }  // namespace tsg

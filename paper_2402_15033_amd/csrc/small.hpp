@@ -88,78 +88,294 @@ __device__ int small_chol_upper(const double* G, int ldg, double* R, int ldr, in
   return s_fail;
 }
 
-// Right-looking upper Cholesky in LDS of the kb x kb (kb <= 64) symmetric matrix whose upper
-// triangle is in sR (ld kLd; the strict lower part must be zero), in place: R^T R = G.  A pivot
-// d_j <= ptol * ref[j] (ref in LDS) stops it; rows 0 .. j-1 are then final and the failing
-// index is returned (-1: success).  For exactly 256 threads.  One barrier per step: every
-// thread takes the pivot itself, the trailing update uses row j divided on the fly, and row j
-// is scaled in place during the next step (which reads neither it nor its diagonal).  (A
-// single-wave version with wave-level syncs only was measured slower: the per-step chain of
-// dependent LDS accesses of one wave costs more than the barrier of four.)
-__device__ int lds_chol_upper256(double* sR, const double* ref, double ptol, int kb) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  int jp = -1, fail = -1;
-  double rp = 0.0, rpi = 0.0;
-  for (int j = 0; j < kb; ++j) {
-    const double d = sR[j + j * kLd];
-    const bool bad = !(d > ptol * ref[j]);
-    if (jp >= 0) {  // finish row j - 1
-      for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] *= rpi;
-      if (tid == 0) sR[jp + jp * kLd] = rp;
-    }
-    jp = -1;
-    if (bad) {
-      fail = j;
-      break;
-    }
-    const double rjj = sqrt(d), rinv = 1.0 / rjj;
-    // trailing update on a 16 x 16 thread grid (at most 4 x 4 entries per thread): all
-    // loads of a column's entries before its stores
-    {
-      const int r0 = j + 1 + tid % 16, c0 = j + 1 + tid / 16;
-      double ri[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) ri[m] = (r0 + 16 * m < kb) ? sR[j + (r0 + 16 * m) * kLd] * rinv : 0.0;
+// LDS leading dimension of the blocked small-matrix routines below: odd, so that the entries
+// of one row in 16 different columns (the panel reads) fall in 16 different bank pairs.
+constexpr int kLdsLd = kLd + 1;
+
+// Blocked right-looking upper Cholesky in LDS of the kb x kb (kb <= 64) symmetric matrix whose
+// upper triangle is in sR (ld LD; the strict lower part must be zero), in place: R^T R = G.
+// Four columns per step: every thread factors the 4 x 4 diagonal block itself (the pivots
+// d_j = the Schur complement diagonal, in the same order as the unblocked algorithm), solves
+// the block's rows for the columns it needs, and takes the rank-4 update off the trailing
+// entries it owns (a 16 x 16 thread grid, entries (ti + 16 m, tc + 16 q)).  A pivot
+// d_j <= ptol * ref[j] (ref in LDS) stops it: rows 0 .. j-1 are then final and the failing
+// index is returned (-1: success).  One barrier per step: the rows of a finished block are
+// read by every thread during the step and written by their owners at the start of the next.
+// For exactly 256 threads; ends with a barrier.
+// (Forced inline: as a called function its LDS pointers would be generic ones, every access a
+// flat memory operation with a wait on both counters.)
+template <int LD>
+__device__ __forceinline__ int lds_chol_upper_blk(double* sR, const double* ref, double ptol, int kb) {
+  constexpr int B = 4;
+  const int tid = threadIdx.x, ti = tid % 16, tc = tid / 16;
+  double pend[4] = {0.0, 0.0, 0.0, 0.0};
+  int prow = -1, fail = -1;
+  for (int j0 = 0; j0 < kb; j0 += B) {
+    if (prow >= 0) {  // the previous block's rows this thread owns
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int c = c0 + 16 * q;
-        if (c >= kb) break;
-        const double rjc = sR[j + c * kLd] * rinv;
-        double v[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) v[m] = (r0 + 16 * m <= c) ? sR[r0 + 16 * m + c * kLd] : 0.0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-          if (r0 + 16 * m <= c) sR[r0 + 16 * m + c * kLd] = v[m] - ri[m] * rjc;
+        const int c = tc + 16 * q;
+        if (c >= prow && c < kb) sR[prow + c * LD] = pend[q];
       }
     }
-    jp = j;
-    rp = rjj;
-    rpi = rinv;
+    prow = -1;
+    const int bw = min(B, kb - j0);
+    double D[B][B];
+#pragma unroll
+    for (int p = 0; p < B; ++p)
+#pragma unroll
+      for (int q = 0; q < B; ++q) D[p][q] = (p <= q && q < bw) ? sR[(j0 + p) + (j0 + q) * LD] : 0.0;
+    // the block's rows, in place in D: R(p, p) and R(p, q > p); nok = rows that passed
+    double rinv[B];
+    int nok = bw;
+#pragma unroll
+    for (int p = 0; p < B; ++p) {
+      rinv[p] = 0.0;
+      if (p < nok) {
+        double d = D[p][p];
+#pragma unroll
+        for (int r = 0; r < p; ++r) d -= D[r][p] * D[r][p];
+        if (!(d > ptol * ref[j0 + p])) {
+          nok = p;
+        } else {
+          const double rd = sqrt(d), ri = 1.0 / rd;
+          D[p][p] = rd;
+          rinv[p] = ri;
+#pragma unroll
+          for (int q = p + 1; q < B; ++q) {
+            double v = D[p][q];
+#pragma unroll
+            for (int r = 0; r < p; ++r) v -= D[r][p] * D[r][q];
+            D[p][q] = v * ri;
+          }
+        }
+      }
+    }
+    // the block's rows in the thread's columns c and rows i beyond the block:
+    // R(j0 + p, c) = (S(j0 + p, c) - sum_{r < p} R(j0 + r, j0 + p) R(j0 + r, c)) / R(p, p)
+    double X[4][B], Y[4][B];
+    auto solve = [&](int c, double (&x)[B]) {
+      double sv[B];
+#pragma unroll
+      for (int p = 0; p < B; ++p) sv[p] = (p < bw) ? sR[(j0 + p) + c * LD] : 0.0;
+#pragma unroll
+      for (int p = 0; p < B; ++p) {
+        double v = sv[p];
+#pragma unroll
+        for (int r = 0; r < p; ++r) v -= D[r][p] * x[r];
+        x[p] = p < nok ? v * rinv[p] : 0.0;
+      }
+    };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tc + 16 * q;
+      if (c >= j0 + bw && c < kb) solve(c, X[q]);
+      const int i = ti + 16 * q;
+      if (i >= j0 + bw && i < kb) solve(i, Y[q]);
+    }
+    if (nok == bw) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = tc + 16 * q;
+        if (c < j0 + bw || c >= kb) continue;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int i = ti + 16 * m;
+          if (i < j0 + bw || i > c) continue;
+          double v = sR[i + c * LD];
+#pragma unroll
+          for (int p = 0; p < B; ++p) v -= Y[m][p] * X[q][p];
+          sR[i + c * LD] = v;
+        }
+      }
+    }
+    // this thread's entries in the block's final rows (at most one of its rows lies in it)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = ti + 16 * m;
+      if (i >= j0 && i < j0 + nok) {
+        prow = i;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = tc + 16 * q;
+          double v = 0.0;  // (columns left of row i are never written)
+#pragma unroll
+          for (int p = 0; p < B; ++p)
+            if (p == i - j0) {
+#pragma unroll
+              for (int u = 0; u < B; ++u)
+                if (c - j0 == u) v = D[p][u];
+              if (c >= j0 + bw) v = X[q][p];
+            }
+          pend[q] = v;
+        }
+      }
+    }
     __syncthreads();
+    if (nok < bw) {
+      fail = j0 + nok;
+      break;
+    }
   }
-  if (jp >= 0) {  // the last row when no pivot failed
-    for (int c = jp + 1 + tid; c < kb; c += nt) sR[jp + c * kLd] *= rpi;
-    if (tid == 0) sR[jp + jp * kLd] = rp;
+  if (prow >= 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tc + 16 * q;
+      if (c >= prow && c < kb) sR[prow + c * LD] = pend[q];
+    }
   }
   __syncthreads();
   return fail;
 }
 
-// X = R^{-1} for upper-triangular k x k R with R and X in LDS (ld kLd): one thread per
-// column of X, back substitution over its own column.  Ends with a barrier.
-__device__ void lds_tri_inv_upper(const double* R, double* X, int k) {
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    for (int i = k - 1; i >= 0; --i) {
-      double v = (i == c) ? 1.0 : 0.0;
-      if (i <= c) {
-        for (int l = i + 1; l <= c; ++l) v -= R[i + l * kLd] * X[l + c * kLd];
-        v /= R[i + i * kLd];
+// X = R^{-1} for the k x k (k <= 64) upper-triangular R in LDS (ld LD) into X (LDS, ld LD,
+// strict lower part zero), right-looking over blocks of four rows from the last: with S = I
+// at the start, the block's rows are X(J, c) = R_JJ^{-1} S(J, c) (c in the block or beyond),
+// and the finished rows take S(i, c) -= R(i, J) X(J, c) off every row i above the block.
+// Every thread inverts the 4 x 4 diagonal block itself; entries are owned on a 16 x 16 thread
+// grid (ti + 16 m, tc + 16 q); one barrier per block, the block's rows written by their owners
+// at the start of the next step.  For exactly 256 threads; ends with a barrier.
+template <int LD>
+__device__ __forceinline__ void lds_tri_inv_upper_blk(const double* R, double* X, int k) {
+  constexpr int B = 4;
+  const int tid = threadIdx.x, ti = tid % 16, tc = tid / 16;
+  for (int idx = tid; idx < kLd * LD; idx += 256) {
+    const int i = idx % LD, c = idx / LD;
+    X[idx] = (i == c && i < k) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double pend[4] = {0.0, 0.0, 0.0, 0.0};
+  int prow = -1;
+  const int nblk = (k + B - 1) / B;
+  for (int J = nblk - 1; J >= 0; --J) {
+    if (prow >= 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = tc + 16 * q;
+        if (c >= prow && c < k) X[prow + c * LD] = pend[q];
       }
-      X[i + c * kLd] = v;
+    }
+    prow = -1;
+    const int j0 = J * B, bw = min(B, k - j0);
+    // Ti = R_JJ^{-1} (upper), column by column: Ti(p, q) = (delta_pq - sum_{p<r<=q} R(p,r) Ti(r,q)) / R(p,p)
+    double Rb[B][B], Ti[B][B];
+#pragma unroll
+    for (int p = 0; p < B; ++p)
+#pragma unroll
+      for (int q = 0; q < B; ++q) Rb[p][q] = (p <= q && q < bw) ? R[(j0 + p) + (j0 + q) * LD] : 0.0;
+    double dinv[B];
+#pragma unroll
+    for (int p = 0; p < B; ++p) dinv[p] = p < bw ? 1.0 / Rb[p][p] : 0.0;
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+#pragma unroll
+      for (int p = B - 1; p >= 0; --p) {
+        double v = (p == q) ? 1.0 : 0.0;
+#pragma unroll
+        for (int r = p + 1; r < B; ++r)
+          if (r <= q) v -= Rb[p][r] * Ti[r][q];
+        Ti[p][q] = (p <= q && q < bw) ? v * dinv[p] : 0.0;
+      }
+    // X(J, c) for the thread's columns c >= j0 (in the block or beyond)
+    double Xc[4][B];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tc + 16 * q;
+#pragma unroll
+      for (int p = 0; p < B; ++p) Xc[q][p] = 0.0;
+      if (c >= j0 && c < k) {
+        double sv[B];
+#pragma unroll
+        for (int p = 0; p < B; ++p) sv[p] = (p < bw) ? X[(j0 + p) + c * LD] : 0.0;
+#pragma unroll
+        for (int p = 0; p < B; ++p) {
+          double v = 0.0;
+#pragma unroll
+          for (int r = 0; r < B; ++r) v += Ti[p][r] * sv[r];
+          Xc[q][p] = v;
+        }
+      }
+    }
+    // rows i above the block: S(i, c) -= sum_p R(i, j0 + p) X(j0 + p, c)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = ti + 16 * m;
+      if (i >= j0) continue;
+      double ri[B];
+#pragma unroll
+      for (int p = 0; p < B; ++p) ri[p] = (p < bw) ? R[i + (j0 + p) * LD] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = tc + 16 * q;
+        if (c < j0 || c >= k) continue;
+        double v = X[i + c * LD];
+#pragma unroll
+        for (int p = 0; p < B; ++p) v -= ri[p] * Xc[q][p];
+        X[i + c * LD] = v;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = ti + 16 * m;
+      if (i >= j0 && i < j0 + bw) {
+        prow = i;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double v = 0.0;
+#pragma unroll
+          for (int p = 0; p < B; ++p)
+            if (p == i - j0) v = Xc[q][p];
+          pend[q] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (prow >= 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tc + 16 * q;
+      if (c >= prow && c < k) X[prow + c * LD] = pend[q];
     }
   }
   __syncthreads();
+}
+
+// C = A B for upper-triangular k x k (k <= 64) A and B in LDS (ld LD), into C (any memory,
+// ld kLd; strict lower part not written): C(i, c) = sum_{i <= l <= c} A(i, l) B(l, c) in the order
+// l = 0, 1, ...  For exactly 256 threads on a 16 x 16 grid (at most 4 x 4 entries each).
+template <int LD, typename CPtr>
+__device__ __forceinline__ void lds_trmm_upper256(const double* A, const double* B, CPtr C, int k) {
+  const int tid = threadIdx.x, ti = tid % 16, tc = tid / 16;
+  double acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[m][q] = 0.0;
+  for (int l = 0; l < k; ++l) {
+    double a[4], b[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = ti + 16 * m;
+      a[m] = (i <= l) ? A[i + l * LD] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tc + 16 * q;
+      b[q] = (l <= c && c < k) ? B[l + c * LD] : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[m][q] += a[m] * b[q];
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ti + 16 * m, c = tc + 16 * q;
+      if (i < k && c < k) C[i + c * kLd] = acc[m][q];
+    }
 }
 
 // X = R^{-1} for upper-triangular k x k R (one thread per column of X).
@@ -191,29 +407,44 @@ __device__ void block_gemm(const double* A, int lda, const double* B, int ldb, d
   __syncthreads();
 }
 
+// H(0:k, 0:k-1) (global, ld kLd) into registers, every load in flight at once: the first half
+// of a copy to LDS that a tail issues before its reduction, so that both wait for memory
+// together.  For exactly kTailThreads threads; hessenberg_store completes it.
+struct HessPrefetch {
+  static constexpr int kPer = kLd * kLd / kTailThreads;
+  double v[kPer];
+};
+__device__ __forceinline__ void hessenberg_prefetch(const double* H, int k, HessPrefetch& pf) {
+#pragma unroll
+  for (int u = 0; u < HessPrefetch::kPer; ++u) {
+    const int idx = threadIdx.x + kTailThreads * u, i = idx % kLd, l = idx / kLd;
+    pf.v[u] = (i < k && l < k - 1) ? H[i + l * kLd] : 0.0;
+  }
+}
+__device__ __forceinline__ void hessenberg_store(const HessPrefetch& pf, double* lH) {
+#pragma unroll
+  for (int u = 0; u < HessPrefetch::kPer; ++u) lH[threadIdx.x + kTailThreads * u] = pf.v[u];
+}
+
 // Hessenberg block of one s-step panel (the small-matrix algebra of Fig. 1):
 //   [w_0, W] = Qb_{1:k+s} S,  S(:,1) = e_k,  S(:,2:s+1) = [P; R]
 //   A [w_0..w_{s-1}] = [w_0..w_s] B,  B(i,i) = theta_i, B(i+1,i) = sigma_i, B(i-1,i) = -tau_i
 //   H(1:k+s, k:k+s-1) = (S B - [H(1:k,1:k-1) S(1:k-1,1:s); 0]) T^{-1},
 //   T = S(k:k+s-1, 1:s).
-// P (k x s, ld kLd) and R (s x s, ld kMaxS) are the panel factors, H (ld kLd) holds
-// columns 0..k-2 on entry.  M is a kLd x kMaxS scratch.  0-based: the new columns are
-// k-1 .. k+s-2 and rows 0 .. k+s-1.
-__device__ void block_hessenberg_panel(double* H, const double* P, const double* R,
+// P (k x s, ld kLd, LDS) and R (s x s, ld kMaxS, LDS) are the panel factors; lH (LDS, ld
+// kLd) holds H(0:k, 0:k-1) on entry (hessenberg_prefetch), H (global, ld kLd) receives the
+// new columns.  0-based: the new columns are k-1 .. k+s-2 and rows 0 .. k+s-1.
+__device__ void block_hessenberg_panel(const double* lH, double* H, const double* P, const double* R,
                                        const double* theta, const double* sigma, const double* tau, int k,
-                                       int s, double* M) {
-  (void)M;  // the products and the solve run in LDS
+                                       int s) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int rows = k + s;
-  // LDS copies of the operands (H(0:k, 0:k-1) is upper Hessenberg), of R, of T and of
-  // the basis parameters; loops over matrices on 64-row thread grids (no integer division)
-  __shared__ double lH[kLd * kLd];
+  // LDS copies of P, R, T and the basis parameters; loops over matrices on 64-row thread
+  // grids (no integer division)
   __shared__ double lP[kLd * kMaxS];
   __shared__ double lM[kLd * kMaxS];
   __shared__ double lR[kMaxS * kMaxS], lT[kMaxS * kMaxS], lB[3 * kMaxS];
   const int rg = tid % kWave, cg = tid / kWave, ncg = nt / kWave;
-  for (int l = cg; l < k - 1; l += ncg)
-    for (int i = rg; i < k; i += kWave) lH[i + l * kLd] = H[i + l * kLd];
   for (int c = cg; c < s; c += ncg)
     for (int i = rg; i < k; i += kWave) lP[i + c * kLd] = P[i + c * kLd];
   if (tid < s * s) {

@@ -5,6 +5,8 @@
 //                 next reduction needs exactly the columns just written
 #pragma once
 
+#include <type_traits>
+
 #include "panel.hpp"
 
 namespace tsg {
@@ -452,6 +454,123 @@ __device__ void FusedBody<T, NC>::run(const PanelArgs& a, int bid, int) {
       part1[prow * sw + z] = sum;
     }
   }
+}
+
+// Q = Qhat R^{-1} in place (the explicit Q of a CholQR whose upper-triangular inverse Rinv,
+// k x k with k <= 16 NCT, ld kLd, is known), on the matrix cores with the rows as the N
+// dimension: per group of 16 rows, D = Rinv^T (output columns x input columns) times
+// X^T (input columns x rows).  For K-step ks lane l = 16 g + i takes row r0 + i of input
+// column 4 ks + g straight from global memory (each load covers 16 consecutive rows of 4
+// columns) and holds, in accumulator register r of tile t, output column 16 t + g + 4 r of
+// row r0 + i (each store covers 16 consecutive rows of 4 columns).  Rinv is upper triangular,
+// so tile t takes the K-steps ks <= 4 t + 3 only (40 products per group for k = 61 instead of
+// 64); the A operand values (Rinv^T, zero outside the triangle) sit in LDS in lane order
+// (conflict-free 8-byte reads).  Each wave walks its groups (wave w of the block: groups w,
+// w + NW, ... of the block's rows); the next group's input column of a K-step is loaded as
+// soon as the current group's last product with it is issued, so one group's loads are in
+// flight while the matrix cores work.  Every K-step runs (no runtime branch in the row loop):
+// lanes past column k - 1 read column k - 1, whose products meet zero Rinv entries.  Addresses
+// are a uniform part (K-step, group) plus the lane's byte offset, 32-bit when Off32 (3 ld + 15
+// elements fit: the host checks) -- the uniform part then stays in scalar registers.  The
+// ragged last group of rows is loaded and stored element-wise with its rows masked.  A row is read and written by one wave only, so the
+// update in place needs no barrier.  Returns at entry when st->h.done is set (a breakdown
+// before it: no inverse was formed).
+constexpr int kRinvThreads = 256;
+constexpr int kRinvGroupRows = 16;
+template <int NCT, bool Off32>
+__global__ __launch_bounds__(kRinvThreads) void apply_rinv_kernel(double* __restrict__ V_, int64_t ld, int64_t n,
+                                                                  int k, const double* __restrict__ Rinv,
+                                                                  int64_t rows_per_block, const SmallState* st) {
+  if (st->h.done) return;
+  typedef MfmaOp<double>::v4 v4;
+  typedef typename std::conditional<Off32, uint32_t, int64_t>::type off_t;
+  constexpr int NW = kRinvThreads / kWave, NKS = 4 * NCT, GR = kRinvGroupRows;
+  __shared__ double sA[NCT * NKS * kWave];  // (t, ks, lane) -> Rinv(4 ks + g, 16 t + i)
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+  const int g = lane >> 4, li = lane & 15;
+  for (int e = tid; e < NCT * NKS * kWave; e += kRinvThreads) {
+    const int l = e % kWave, ks = (e / kWave) % NKS, t = e / (kWave * NKS);
+    const int row = 4 * ks + (l >> 4), col = 16 * t + (l & 15);
+    sA[e] = (row <= col && col < k) ? Rinv[row + col * kLd] : 0.0;
+  }
+  __syncthreads();
+  gbl<char>* const base = G(reinterpret_cast<char*>(V_));
+  // K-step ks reads column cb + min(g, k - 1 - cb), cb = min(4 ks, k - 1) uniform
+  const off_t ldb = (off_t)(ld * 8), li8 = (off_t)(li * 8);
+  const off_t offl = (off_t)g * ldb + li8;
+  auto at = [=](int64_t uni, off_t lo) { return (gbl<double>*)(base + uni * 8 + lo); };
+  auto xat = [=](int ks, int64_t r0) {
+    const int cb = min(4 * ks, k - 1);
+    const off_t lo = (off_t)min(g, k - 1 - cb) * ldb + li8;
+    return (gbl<double>*)(base + ((int64_t)cb * ld + r0) * 8 + lo);
+  };
+  const int64_t rb = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t re = min(n, rb + rows_per_block);
+  const int64_t nfull = (re - rb) / GR;
+  if (wv < nfull) {
+    double x[NKS];
+    int64_t q = wv;
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) x[ks] = *xat(ks, rb + GR * q);
+    for (; q < nfull; q += NW) {
+      // an opaque zero in the LDS index: the operand values are read from LDS per group
+      // rather than hoisted into 80 registers across the loop
+      int z;
+      __asm__ volatile("s_mov_b32 %0, 0" : "=s"(z));
+      const int64_t r0 = rb + GR * q;
+      const int64_t rn = rb + GR * min<int64_t>(q + NW, nfull - 1);
+      v4 acc[NCT];
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) acc[t] = v4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+#pragma unroll
+        for (int t = 0; t < NCT; ++t)
+          if (ks <= 4 * t + 3) acc[t] = MfmaOp<double>::mac(sA[(t * NKS + ks) * kWave + lane + z], x[ks], acc[t]);
+        x[ks] = *xat(ks, rn);
+      }
+#pragma unroll
+      for (int t = 0; t < NCT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (16 * t + g + 4 * r < k) *at((int64_t)(16 * t + 4 * r) * ld + r0, offl) = acc[t][r];
+    }
+  }
+  if (re - rb - GR * nfull > 0 && wv == (int)(nfull % NW)) {  // the ragged last group
+    gbl<double>* __restrict__ V = G(V_);
+    const int64_t r0 = rb + GR * nfull;
+    const bool ok = r0 + li < re;
+    v4 acc[NCT];
+#pragma unroll
+    for (int t = 0; t < NCT; ++t) acc[t] = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int col = min(4 * ks + g, k - 1);
+      const double xv = ok ? V[(int64_t)col * ld + r0 + li] : 0.0;
+#pragma unroll
+      for (int t = 0; t < NCT; ++t)
+        if (ks <= 4 * t + 3) acc[t] = MfmaOp<double>::mac(sA[(t * NKS + ks) * kWave + lane], xv, acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NCT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = 16 * t + g + 4 * r;
+        if (ok && col < k) V[(int64_t)col * ld + r0 + li] = acc[t][r];
+      }
+  }
+}
+// Whether apply_rinv_kernel's lane byte offsets (3 ld + 15 elements at most) fit 32 bits.
+inline bool rinv_off32(int64_t ld) { return (3 * ld + 16) * 8 < ((int64_t)1 << 32); }
+// Rows per block of apply_rinv_kernel: at most kRinvMaxBlocks blocks, whole waves of groups.
+constexpr int kRinvMaxBlocks = 1024;
+inline int64_t rinv_rows_per_block(int64_t n) {
+  const int64_t unit = (int64_t)kRinvGroupRows * (kRinvThreads / kWave);
+  const int64_t units = (n + unit - 1) / unit;
+  const int64_t per = (units + kRinvMaxBlocks - 1) / kRinvMaxBlocks;
+  return per * unit;
 }
 
 // ----------------------------------------------------------------------------- launcher

@@ -1634,6 +1634,28 @@ size_t tsg_orthogonalize_workspace_bytes(int64_t n, int32_t k, int32_t s) {
 
 namespace {
 
+// Q = Qhat Rinv in place, Rinv = the upper-triangular inverse in sm->Wk (ld kLd).
+tsg_status launch_apply_rinv(double* X, int64_t ldx, int64_t n, int k, const SmallState* sm, hipStream_t st) {
+  const double* Rinv = sm->Wk;
+  const int64_t rpb = rinv_rows_per_block(n);
+  const dim3 grid((unsigned)cdiv(n, rpb)), block(kRinvThreads);
+  const bool o32 = rinv_off32(ldx);
+#define TSG_RINV(NCT)                                                                                 \
+  do {                                                                                                \
+    if (o32) hipLaunchKernelGGL((apply_rinv_kernel<NCT, true>), grid, block, 0, st, X, ldx, n, k, Rinv, rpb, sm); \
+    else hipLaunchKernelGGL((apply_rinv_kernel<NCT, false>), grid, block, 0, st, X, ldx, n, k, Rinv, rpb, sm);    \
+  } while (0)
+  switch ((k + 15) / 16) {
+    case 1: TSG_RINV(1); break;
+    case 2: TSG_RINV(2); break;
+    case 3: TSG_RINV(3); break;
+    default: TSG_RINV(4); break;
+  }
+#undef TSG_RINV
+  HIP_LAUNCH_CHECK();
+  return TSG_OK;
+}
+
 // Argument checks shared by the stand-alone orthogonalization entry points (host only).
 tsg_status orthogonalize_check(int64_t n, int32_t k, const double* X, int64_t ldx, const double* R, int32_t ldr,
                                int32_t s, int32_t s_hat, int32_t algo) {
@@ -1734,11 +1756,8 @@ tsg_status orthogonalize_ws(int64_t n, int32_t k, double* X, int64_t ldx, double
     // stage 2: one CholQR over all k columns, then Q = Qhat R2^{-1}
     hipLaunchKernelGGL(sa_stage2_kernel, dim3(1), dim3(256), 0, st, c.st, k);
     HIP_LAUNCH_CHECK();
-    const int nb = (int)cdiv(n, kRowBlock);
-    // rows are independent; the kernel returns early when the solve is done (breakdown)
-    hipLaunchKernelGGL((apply_rinv_kernel<kMaxCols>), dim3(nb), dim3(kRowBlock), 0, st, X, ldx, n, k,
-                       (const double*)c.st->Wk);
-    HIP_LAUNCH_CHECK();
+    // returns at entry after a breakdown (the caller gets TSG_BREAKDOWN)
+    TRY(launch_apply_rinv(X, ldx, n, k, c.st, st));
     hipLaunchKernelGGL(copy_r_kernel, dim3(1), dim3(256), 0, st, c.st, 1, k, R, ldr);
   } else {
     hipLaunchKernelGGL(copy_r_kernel, dim3(1), dim3(256), 0, st, c.st, 0, k, R, ldr);
