@@ -522,6 +522,8 @@ def serve_bench(args, tsg, W, np, torch, dev):
                 lap_cache[N] = A
         b = torch.as_tensor(pr["b"], device=dev)
         reqs.append({"kind": kind, "N": N, "A": A, "b": b, "n": pr["A"].n})
+        if (i + 1) % 100 == 0:
+            log(f"[serve] built {i + 1}/{R}")
     torch.cuda.synchronize()
     srv = tsg.Server(int(args.serve_budget_gb * 2**30), m=args.m, s=args.s, tol=1e-8, basis="shifted",
                      precision="fp32_ir", max_active=256, device=dev)

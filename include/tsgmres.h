@@ -186,8 +186,9 @@ typedef struct tsg_csr_s* tsg_csr;
 /* Create a handle for the n x n CSR matrix (Sec. VII: the operator).  The handle
  * BORROWS row_ptr[n+1], col[nnz], val[nnz] (device): they must stay valid and
  * unchanged until tsg_csr_destroy.  Computes the Gershgorin interval and the plan of the
- * packed layout on the device (small kernels, synchronizes `stream`).  The handle owns one
- * 4 KiB device block and (n/64 + 1) x 8 bytes of host memory.
+ * packed layout on the device (small kernels, synchronizes `stream`; their temporaries are
+ * stream-ordered allocations freed before it returns).  The handle owns one 4 KiB device
+ * block and about n/8 bytes of host memory.
  * Errors: INVALID_ARG for n < 1, nnz < 0, nnz >= 2^31, NULL pointers; HIP. */
 tsg_status tsg_csr_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
                           const double* val, void* stream, tsg_csr* out /* host */);
@@ -215,14 +216,22 @@ tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream);
  * a block the rows grouped by color, index order within a color: counting sort of the
  * device-computed colors on the host), the reordered system P A P^T (CSR with columns
  * renamed and sorted, its own Gershgorin interval and packed copy) on which
- * preconditioned solves run, and its sweep layout: each color's rows (one run per block)
- * cut into slices of 64 with their lower-color entries stored entry by entry.  About 2 x (12 nnz + 24 n) bytes in all; the handle allocates
- * and owns this device memory (freed by tsg_csr_destroy).  Synchronizes `stream`; a
- * second call does nothing.  The pattern must be structurally symmetric (a_ij stored iff
- * a_ji stored) and every row must store a nonzero diagonal.  From then on solves with
- * precond = MCGS may use A.  Errors: INVALID_ARG (NULL handle); UNSUPPORTED when the
- * rounds do not finish within n rounds; HIP (allocation, launches). */
-tsg_status tsg_csr_precond(tsg_csr A, void* stream);
+ * preconditioned solves run, and its sweep layout: the rows of one color within one block
+ * cut into slices of 64 with their lower-color entries stored entry by entry.
+ * tsg_csr_precond_bytes: device bytes of the buffer, an upper bound from n, nnz and the
+ * longest row of every block of 8192 rows (known since tsg_csr_create): about
+ * 12 nnz + (60 + 28 W) n bytes for rows of at most W entries; 0 for a NULL handle.
+ * tsg_csr_precond: everything the set-up builds or uses lives in buf (device, 256-byte
+ * aligned, caller-owned, at least tsg_csr_precond_bytes(A) bytes; it must stay valid and
+ * untouched until tsg_csr_destroy): the library allocates no device memory (the internal
+ * handle of P A P^T takes its 4 KiB block from buf too).  Synchronizes `stream`; a second
+ * call does nothing.  The pattern must be structurally symmetric (a_ij stored iff a_ji
+ * stored) and every row must store a nonzero diagonal.  From then on solves with
+ * precond = MCGS may use A.  Errors: INVALID_ARG (NULL handle or buffer); WORKSPACE
+ * (misaligned or too small); UNSUPPORTED when the rounds do not finish within n rounds;
+ * HIP (launches, copies). */
+size_t tsg_csr_precond_bytes(tsg_csr A);
+tsg_status tsg_csr_precond(tsg_csr A, void* buf, size_t bytes, void* stream);
 /* Number of colors of the preconditioner set-up (0 before tsg_csr_precond). */
 int32_t tsg_csr_ncolors(tsg_csr A);
 /* Copy the n row colors (int32) to colors (device, caller-owned); INVALID_ARG before

@@ -23,6 +23,7 @@ from .binding import (  # noqa: F401
     library_path,
     load_library,
     solve,
+    solve_workspace_bytes,
     orthogonalize,
     block_pip,
     precond_apply,

@@ -155,7 +155,9 @@ def load_library():
     lib.tsg_server_step.restype = C.c_int
     lib.tsg_server_poll.argtypes = [vp, C.POINTER(i64), C.POINTER(_Info), i32]
     lib.tsg_server_poll.restype = i32
-    lib.tsg_csr_precond.argtypes = [vp, vp]
+    lib.tsg_csr_precond_bytes.argtypes = [vp]
+    lib.tsg_csr_precond_bytes.restype = C.c_size_t
+    lib.tsg_csr_precond.argtypes = [vp, vp, C.c_size_t, vp]
     lib.tsg_csr_precond.restype = C.c_int
     lib.tsg_csr_ncolors.argtypes = [vp]
     lib.tsg_csr_ncolors.restype = i32
@@ -226,6 +228,7 @@ class CSRMatrix:
                                   self.val.data_ptr(), _stream(self.device), C.byref(h)))
         self._h = h
         self._pack = None
+        self._precond = None
         if pack:
             self.pack()
 
@@ -246,8 +249,16 @@ class CSRMatrix:
 
     def precond_setup(self):
         """Color the operator and build the sweep layout of the multicolor Gauss-Seidel
-        preconditioner (precond='mcgs'); the library's handle owns that device memory."""
-        _check(load_library().tsg_csr_precond(self._h, _stream(self.device)))
+        preconditioner (precond='mcgs') in a device buffer this object owns (the size the
+        library asks for); a second call does nothing."""
+        if getattr(self, "_precond", None) is not None:
+            return self
+        lib = load_library()
+        nbytes = int(lib.tsg_csr_precond_bytes(self._h))
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        p = (buf.data_ptr() + 255) // 256 * 256
+        _check(lib.tsg_csr_precond(self._h, p, nbytes, _stream(self.device)))
+        self._precond = buf
         return self
 
     @property

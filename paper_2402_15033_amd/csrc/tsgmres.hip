@@ -28,6 +28,8 @@ struct tsg_csr_s {
   const double* val;
   double lo, hi;
   double* dev;  // 4 KiB: Gershgorin partials scratch of the final reduce
+  bool dev_owned = true;  // false for the reordered system of a preconditioner set-up
+  std::vector<int32_t> blk_maxw;  // largest row length of each block of kGsBlock rows
   // SELL-64 plan (computed at create) and, once tsg_csr_pack ran, the packed arrays
   int64_t nslices = 0, sell_total = 0;
   int sell_fmt = 0;  // FMT_SELL16 or FMT_SELL32
@@ -37,17 +39,13 @@ struct tsg_csr_s {
   const float* v32 = nullptr;
   const void* scol = nullptr;
   int packed = 0;
-  // multicolor Gauss-Seidel (tsg_csr_precond): row colors and the sweep layout, in one
-  // device block owned by the handle
+  // multicolor Gauss-Seidel (tsg_csr_precond): row colors and the sweep layout
   int ncolors = 0;
-  void* gs_mem = nullptr;
   const int32_t* colors = nullptr;
   // the reordered system P A P^T the preconditioned solve runs on (rows by block, then by
-  // color: its own handle with the sweep layout), the permutation and its scratch; memory
-  // owned by this handle
+  // color: its own handle with the sweep layout), the permutation and its scratch; all in
+  // the caller's buffer of tsg_csr_precond
   tsg_csr_s* pa = nullptr;
-  void* own_mem = nullptr;
-  void* pa_pack = nullptr;
   const int32_t* perm = nullptr;  // position p of P A P^T holds row perm[p] of A
   double* gs_tmp = nullptr;       // 2 n doubles for tsg_precond_apply
   const int32_t* gs_prow = nullptr;
@@ -837,6 +835,91 @@ const char* tsg_status_string(tsg_status st) {
 
 const char* tsg_last_error(void) { return g_err.c_str(); }
 
+namespace {
+
+// Device bytes of the temporaries of create_impl (Gershgorin partials, slice analysis).
+size_t create_tmp_bytes(int64_t n) {
+  return align_up(sizeof(double) * 2 * (size_t)cdiv(n, kRowBlock)) + align_up(sizeof(int) * 2 * (size_t)cdiv(n, kWave));
+}
+
+// tsg_csr_create's work.  dev4k / tmp: the handle's 4 KiB block and the temporaries
+// (create_tmp_bytes), both device memory of the caller (then nothing is allocated and the
+// handle does not free dev4k), or NULL (allocated here: the block kept, the temporaries
+// stream-ordered and freed before returning).
+tsg_status create_impl(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, const double* val,
+                       hipStream_t s, void* dev4k, void* tmp, tsg_csr* out) {
+  *out = nullptr;
+  tsg_csr A = new (std::nothrow) tsg_csr_s();
+  if (!A) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
+  A->n = n;
+  A->nnz = nnz;
+  A->row_ptr = row_ptr;
+  A->col = col;
+  A->val = val;
+  const int nb = (int)cdiv(n, kRowBlock);
+  A->nslices = cdiv(n, kWave);
+  double* part = nullptr;
+  int* wf = nullptr;
+  hipError_t e = hipSuccess;
+  if (dev4k) {
+    A->dev = static_cast<double*>(dev4k);
+    A->dev_owned = false;
+    Carve tc{static_cast<char*>(tmp)};
+    part = tc.take<double>(2 * (size_t)nb);
+    wf = tc.take<int>(2 * (size_t)A->nslices);
+  } else {
+    e = hipMalloc(&A->dev, 4096);
+    if (e == hipSuccess) e = hipMallocAsync(&part, sizeof(double) * 2 * nb, s);
+    if (e == hipSuccess) e = hipMallocAsync(&wf, sizeof(int) * 2 * A->nslices, s);
+  }
+  auto bail = [&](const char* what) {
+    (void)hipStreamSynchronize(s);
+    if (!dev4k) {
+      if (part) (void)hipFree(part);
+      if (wf) (void)hipFree(wf);
+      if (A->dev) (void)hipFree(A->dev);
+    }
+    delete A;
+    return fail(TSG_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  };
+  if (e != hipSuccess) return bail("allocation failed");
+  // Gershgorin interval, then the SELL-64 plan: slice widths and the column-delta range,
+  // offsets on the host
+  hipLaunchKernelGGL(gershgorin_kernel, dim3(nb), dim3(kRowBlock), 0, s, row_ptr, col, val, n, part);
+  hipLaunchKernelGGL(minmax_final_kernel, dim3(1), dim3(kRowBlock), 0, s, part, nb, A->dev);
+  hipLaunchKernelGGL(sell_analyze_kernel, dim3(cdiv(A->nslices, kRowBlock / kWave)), dim3(kRowBlock), 0, s, row_ptr,
+                     col, n, A->nslices, wf, wf + A->nslices);
+  double lohi[2] = {0, 0};
+  std::vector<int> wh(2 * A->nslices);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(lohi, A->dev, sizeof(lohi), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(wh.data(), wf, sizeof(int) * 2 * A->nslices, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && !dev4k) e = hipFreeAsync(part, s);
+  if (e == hipSuccess && !dev4k) e = hipFreeAsync(wf, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bail("operator analysis failed");
+  A->lo = lohi[0];
+  A->hi = lohi[1];
+  A->soff_host.resize(A->nslices + 1);
+  A->blk_maxw.assign((size_t)cdiv(n, kGsBlock), 0);
+  int fits = 1;
+  int64_t acc = 0;
+  for (int64_t i = 0; i < A->nslices; ++i) {
+    A->soff_host[i] = acc;
+    acc += (int64_t)kWave * wh[i];
+    fits &= wh[A->nslices + i];
+    int32_t& bm = A->blk_maxw[(size_t)(i * kWave / kGsBlock)];
+    bm = std::max(bm, (int32_t)wh[i]);
+  }
+  A->soff_host[A->nslices] = acc;
+  A->sell_total = acc;
+  A->sell_fmt = fits ? FMT_SELL16 : FMT_SELL32;
+  *out = A;
+  return TSG_OK;
+}
+
+}  // namespace
+
 tsg_status tsg_csr_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col,
                           const double* val, void* stream, tsg_csr* out) {
   if (!out) return fail(TSG_ERR_INVALID_ARG, "out is NULL");
@@ -845,68 +928,7 @@ tsg_status tsg_csr_create(int64_t n, int64_t nnz, const int32_t* row_ptr, const 
     return fail(TSG_ERR_INVALID_ARG, "bad sizes n=%lld nnz=%lld", (long long)n, (long long)nnz);
   if (!row_ptr || (nnz > 0 && (!col || !val)))
     return fail(TSG_ERR_INVALID_ARG, "NULL CSR array");
-  hipStream_t s = (hipStream_t)stream;
-  tsg_csr A = new (std::nothrow) tsg_csr_s();
-  if (!A) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
-  A->n = n;
-  A->nnz = nnz;
-  A->row_ptr = row_ptr;
-  A->col = col;
-  A->val = val;
-  int nb = (int)cdiv(n, kRowBlock);
-  double* part = nullptr;
-  hipError_t e = hipMalloc(&A->dev, 4096);
-  if (e == hipSuccess) e = hipMallocAsync(&part, sizeof(double) * 2 * nb, s);
-  if (e != hipSuccess) {
-    if (A->dev) (void)hipFree(A->dev);
-    delete A;
-    return fail(TSG_ERR_HIP, "allocation failed: %s", hipGetErrorString(e));
-  }
-  hipLaunchKernelGGL(gershgorin_kernel, dim3(nb), dim3(kRowBlock), 0, s, row_ptr, col, val, n, part);
-  hipLaunchKernelGGL(minmax_final_kernel, dim3(1), dim3(kRowBlock), 0, s, part, nb, A->dev);
-  double lohi[2] = {0, 0};
-  e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemcpyAsync(lohi, A->dev, sizeof(lohi), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipFreeAsync(part, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) {
-    (void)hipFree(A->dev);
-    delete A;
-    return fail(TSG_ERR_HIP, "Gershgorin pass failed: %s", hipGetErrorString(e));
-  }
-  A->lo = lohi[0];
-  A->hi = lohi[1];
-  // SELL-64 plan: slice widths and the column-delta range, offsets on the host
-  A->nslices = cdiv(n, kWave);
-  int* wf = nullptr;
-  e = hipMallocAsync(&wf, sizeof(int) * 2 * A->nslices, s);
-  std::vector<int> wh(2 * A->nslices);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(sell_analyze_kernel, dim3(cdiv(A->nslices, kRowBlock / kWave)), dim3(kRowBlock), 0, s,
-                       row_ptr, col, n, A->nslices, wf, wf + A->nslices);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) e = hipMemcpyAsync(wh.data(), wf, sizeof(int) * 2 * A->nslices, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipFreeAsync(wf, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) {
-    (void)hipFree(A->dev);
-    delete A;
-    return fail(TSG_ERR_HIP, "operator analysis failed: %s", hipGetErrorString(e));
-  }
-  A->soff_host.resize(A->nslices + 1);
-  int fits = 1;
-  int64_t acc = 0;
-  for (int64_t i = 0; i < A->nslices; ++i) {
-    A->soff_host[i] = acc;
-    acc += (int64_t)kWave * wh[i];
-    fits &= wh[A->nslices + i];
-  }
-  A->soff_host[A->nslices] = acc;
-  A->sell_total = acc;
-  A->sell_fmt = fits ? FMT_SELL16 : FMT_SELL32;
-  *out = A;
-  return TSG_OK;
+  return create_impl(n, nnz, row_ptr, col, val, (hipStream_t)stream, nullptr, nullptr, out);
 }
 
 size_t tsg_csr_pack_bytes(tsg_csr A) {
@@ -950,13 +972,8 @@ tsg_status tsg_csr_pack(tsg_csr A, void* buf, size_t bytes, void* stream) {
 
 tsg_status tsg_csr_destroy(tsg_csr A) {
   if (!A) return TSG_OK;
-  hipError_t e = hipFree(A->dev);
-  if (A->pa) (void)tsg_csr_destroy(A->pa);
-  for (void* m : {A->gs_mem, A->own_mem, A->pa_pack}) {
-    if (!m) continue;
-    hipError_t e2 = hipFree(m);
-    if (e == hipSuccess) e = e2;
-  }
+  hipError_t e = A->dev_owned ? hipFree(A->dev) : hipSuccess;
+  if (A->pa) (void)tsg_csr_destroy(A->pa);  // (its memory is the caller's buffer)
   delete A;
   if (e != hipSuccess) return fail(TSG_ERR_HIP, "hipFree: %s", hipGetErrorString(e));
   return TSG_OK;
@@ -980,32 +997,81 @@ tsg_status tsg_spmv(tsg_csr A, const double* x, double* y, void* stream) {
 
 namespace {
 
-// The sweep layout of handle H: the rows of color c are perm[off[c] .. off[c+1]) (rows of
-// H, in increasing order); colors: the color of every row of H (device); padcol: a row of
-// color 0.  Slices of 64 per color, widths, entry offsets, then the fill (device memory
-// owned by H).
-tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, const int32_t* perm,
-                              const int32_t* colors, int32_t padcol, hipStream_t s) {
-  const int ncol = (int)off.size() - 1;
+// The regions of tsg_csr_precond's buffer, in bytes: coloring scratch, the reordered system
+// and its vectors, its handle block and temporaries, its packed copy, the sweep layout and
+// its plan.  The last three depend on the coloring; their sizes are upper bounds from the
+// row lengths: with W_b the longest row of block b (kGsBlock rows) and W the longest of all,
+//   * packed copy: every 64-row slice at most W wide, 32-bit column offsets;
+//   * sweep: the rows of one color within one block form one run, cut into slices of 64,
+//     so block b holds at most ceil(rows_b / 64) + C slices (C <= W colors: greedy colors
+//     stay below a row's neighbour count plus one), each at most W_b - 1 entries wide (a
+//     row's lower-color entries are off-diagonal ones).
+struct PrecondLayout {
+  size_t color = 0, own = 0, pa_dev = 0, pa_tmp = 0, pack = 0, plan = 0, sweep = 0;
+  int64_t max_slices = 0, max_entries = 0;
+  size_t total() const { return color + own + pa_dev + pa_tmp + pack + plan + sweep + kAlign; }
+};
+size_t sweep_plan_bytes(int64_t ns) { return 4 * align_up(8 * (size_t)(ns + 1)) + align_up(4 * (size_t)std::max<int64_t>(ns, 1)); }
+size_t sweep_bytes(int64_t ns, int64_t ne) {
+  const size_t slots = (size_t)std::max<int64_t>(ns, 1) * kWave, e = (size_t)std::max<int64_t>(ne, 1);
+  return align_up(4 * slots) + align_up(8 * slots) + align_up(8 * e) + align_up(4 * e) +
+         align_up(8 * (size_t)(ns + 1)) + align_up(4 * (size_t)std::max<int64_t>(ns, 1));
+}
+PrecondLayout precond_layout(const tsg_csr_s* A) {
+  const int64_t n = A->n, nnz = std::max<int64_t>(A->nnz, 1), nb = cdiv(n, 256);
+  PrecondLayout L;
+  L.color = 2 * align_up(4 * (size_t)n) + align_up(4 * (size_t)nb) + align_up(4);
+  L.own = 6 * align_up(4 * (size_t)n + 4) + align_up(4 * (size_t)nnz) + align_up(8 * (size_t)nnz) +
+          align_up(16 * (size_t)n);
+  L.pa_dev = 4096;
+  L.pa_tmp = create_tmp_bytes(n);
+  int32_t W = 1;
+  for (int32_t w : A->blk_maxw) W = std::max(W, w);
+  const int64_t nsl = cdiv(n, kWave);
+  const size_t T = (size_t)kWave * nsl * W;
+  L.pack = align_up(8 * (size_t)(nsl + 1)) + align_up(8 * T) + align_up(4 * T) + align_up(4 * T) + kAlign;
+  for (size_t b = 0; b < A->blk_maxw.size(); ++b) {
+    const int64_t rows = std::min<int64_t>(kGsBlock, n - (int64_t)b * kGsBlock);
+    const int64_t sl = cdiv(rows, kWave) + W;
+    L.max_slices += sl;
+    L.max_entries += sl * kWave * std::max<int64_t>(A->blk_maxw[b] - 1, 0);
+  }
+  L.plan = sweep_plan_bytes(L.max_slices);
+  L.sweep = sweep_bytes(L.max_slices, L.max_entries);
+  return L;
+}
+
+// The sweep layout of handle H: the rows of color c in block b are perm[run(b, c)] (rows of
+// H, in increasing order; run(b, c) = [koff[b ncol + c], koff[b ncol + c + 1]) in the
+// color-major list perm); colors: the color of every row of H (device); padcol: a row of
+// color 0.  Slices of 64 per run, ordered by color then block; widths, entry offsets, then
+// the fill, into plan / mem (caller device memory of at least sweep_plan_bytes(max_ns) /
+// sweep_bytes(max_ns, max_ne) bytes; the counts are checked against those bounds).
+tsg_status build_sweep_layout(tsg_csr_s* H, int ncol, int64_t nblk, const std::vector<int64_t>& run_len,
+                              const int32_t* perm, const int32_t* colors, int32_t padcol, void* plan, void* mem,
+                              int64_t max_ns, int64_t max_ne, hipStream_t s) {
   std::vector<int64_t> sl((size_t)ncol + 1, 0), ss, se, sc;
+  int64_t p = 0;
   for (int c = 0; c < ncol; ++c) {
-    for (int64_t p = off[c]; p < off[c + 1]; p += kWave) {
-      ss.push_back(p);
-      se.push_back(std::min<int64_t>(p + kWave, off[c + 1]));
-      sc.push_back(c);
+    for (int64_t b = 0; b < nblk; ++b) {
+      const int64_t len = run_len[(size_t)(b * ncol + c)];
+      for (int64_t q = 0; q < len; q += kWave) {
+        ss.push_back(p + q);
+        se.push_back(p + std::min<int64_t>(q + kWave, len));
+        sc.push_back(c);
+      }
+      p += len;
     }
     sl[c + 1] = (int64_t)ss.size();
   }
   const int64_t ns = (int64_t)ss.size();
-  void* plan = nullptr;
-  const size_t pbytes = 4 * align_up(8 * (size_t)(ns + 1)) + align_up(4 * (size_t)ns) + kAlign;
-  HIP_TRY(hipMalloc(&plan, pbytes));
+  if (ns > max_ns) return fail(TSG_ERR_UNSUPPORTED, "internal: %lld sweep slices above the bound %lld", (long long)ns, (long long)max_ns);
   Carve pc{static_cast<char*>(plan)};
   int64_t* dss = pc.take<int64_t>((size_t)ns + 1);
   int64_t* dse = pc.take<int64_t>((size_t)ns + 1);
   int64_t* dsc = pc.take<int64_t>((size_t)ns + 1);
   int64_t* deo = pc.take<int64_t>((size_t)ns + 1);
-  int32_t* dwd = pc.take<int32_t>((size_t)ns);
+  int32_t* dwd = pc.take<int32_t>((size_t)std::max<int64_t>(ns, 1));
   std::vector<int32_t> wh((size_t)ns);
   hipError_t e = hipMemcpyAsync(dss, ss.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(dse, se.data(), sizeof(int64_t) * ns, hipMemcpyHostToDevice, s);
@@ -1017,27 +1083,19 @@ tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, con
   }
   if (e == hipSuccess) e = hipMemcpyAsync(wh.data(), dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(TSG_ERR_HIP, "sweep layout: %s", hipGetErrorString(e));
   std::vector<int64_t> eo((size_t)ns + 1, 0);
   for (int64_t k = 0; k < ns; ++k) eo[k + 1] = eo[k] + (int64_t)kWave * wh[k];
   const int64_t nent = eo[ns];
-  void* mem = nullptr;
-  const size_t mbytes = align_up(4 * (size_t)ns * kWave) + align_up(8 * (size_t)ns * kWave) +
-                        align_up(8 * (size_t)std::max<int64_t>(nent, 1)) +
-                        align_up(4 * (size_t)std::max<int64_t>(nent, 1)) + align_up(8 * (size_t)(ns + 1)) +
-                        align_up(4 * (size_t)ns) + kAlign;
-  if (e == hipSuccess) e = hipMalloc(&mem, mbytes);
-  if (e != hipSuccess) {
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(plan);
-    return fail(TSG_ERR_HIP, "sweep layout: %s", hipGetErrorString(e));
-  }
+  if (nent > max_ne) return fail(TSG_ERR_UNSUPPORTED, "internal: %lld sweep entries above the bound %lld", (long long)nent, (long long)max_ne);
+  // carved with the bounds' sizes (the same regions whatever the coloring)
   Carve mc{static_cast<char*>(mem)};
-  int32_t* prow = mc.take<int32_t>((size_t)ns * kWave);
-  double* diag = mc.take<double>((size_t)ns * kWave);
-  double* gval = mc.take<double>((size_t)std::max<int64_t>(nent, 1));
-  int32_t* gcol = mc.take<int32_t>((size_t)std::max<int64_t>(nent, 1));
-  int64_t* geo = mc.take<int64_t>((size_t)ns + 1);
-  int32_t* gwd = mc.take<int32_t>((size_t)ns);
+  int32_t* prow = mc.take<int32_t>((size_t)std::max<int64_t>(max_ns, 1) * kWave);
+  double* diag = mc.take<double>((size_t)std::max<int64_t>(max_ns, 1) * kWave);
+  double* gval = mc.take<double>((size_t)std::max<int64_t>(max_ne, 1));
+  int32_t* gcol = mc.take<int32_t>((size_t)std::max<int64_t>(max_ne, 1));
+  int64_t* geo = mc.take<int64_t>((size_t)max_ns + 1);
+  int32_t* gwd = mc.take<int32_t>((size_t)std::max<int64_t>(max_ns, 1));
   e = hipMemcpyAsync(geo, eo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(deo, eo.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(gwd, dwd, sizeof(int32_t) * ns, hipMemcpyDeviceToDevice, s);
@@ -1047,12 +1105,7 @@ tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, con
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(plan);
-  if (e != hipSuccess) {
-    (void)hipFree(mem);
-    return fail(TSG_ERR_HIP, "sweep layout fill: %s", hipGetErrorString(e));
-  }
-  H->gs_mem = mem;
+  if (e != hipSuccess) return fail(TSG_ERR_HIP, "sweep layout fill: %s", hipGetErrorString(e));
   H->gs_prow = prow;
   H->gs_diag = diag;
   H->gs_val = gval;
@@ -1066,30 +1119,36 @@ tsg_status build_sweep_layout(tsg_csr_s* H, const std::vector<int64_t>& off, con
 
 }  // namespace
 
-tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
+size_t tsg_csr_precond_bytes(tsg_csr A) { return A ? precond_layout(A).total() : 0; }
+
+tsg_status tsg_csr_precond(tsg_csr A, void* buf, size_t bytes, void* stream) {
   if (!A) return fail(TSG_ERR_INVALID_ARG, "NULL handle");
   if (A->pa) return TSG_OK;  // already set up
+  if (!buf) return fail(TSG_ERR_INVALID_ARG, "NULL buffer");
+  if (reinterpret_cast<uintptr_t>(buf) % kAlign != 0) return fail(TSG_ERR_WORKSPACE, "buffer must be 256-byte aligned");
+  const PrecondLayout L = precond_layout(A);
+  if (bytes < L.total()) return fail(TSG_ERR_WORKSPACE, "buffer %zu < required %zu", bytes, L.total());
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = A->n, nnz = A->nnz;
   const int nb = (int)cdiv(n, 256);
-  // ---- coloring: Jones-Plassmann rounds (scratch: two color arrays, counts, total)
-  void* scratch = nullptr;
-  const size_t sbytes = 2 * align_up(4 * (size_t)n) + align_up(4 * (size_t)nb) + kAlign;
-  HIP_TRY(hipMalloc(&scratch, sbytes));
-  Carve cv{static_cast<char*>(scratch)};
+  Carve bc{static_cast<char*>(buf)};
+  char* r_color = bc.take<char>(L.color);
+  char* r_own = bc.take<char>(L.own);
+  char* r_padev = bc.take<char>(L.pa_dev);
+  char* r_patmp = bc.take<char>(L.pa_tmp);
+  char* r_pack = bc.take<char>(L.pack);
+  char* r_plan = bc.take<char>(L.plan);
+  char* r_sweep = bc.take<char>(L.sweep);
+  // ---- coloring: Jones-Plassmann rounds (two color arrays, counts, total)
+  Carve cv{r_color};
   int32_t* ca = cv.take<int32_t>((size_t)n);
   int32_t* cb = cv.take<int32_t>((size_t)n);
   int32_t* cnt = cv.take<int32_t>((size_t)nb);
   int32_t* total = cv.take<int32_t>(1);
-  void* own = nullptr;
   tsg_csr pa = nullptr;
-  void* pack = nullptr;
   auto bail = [&](tsg_status st) {
     (void)hipStreamSynchronize(s);
-    (void)hipFree(scratch);
     if (pa) (void)tsg_csr_destroy(pa);
-    if (pack) (void)hipFree(pack);
-    if (own) (void)hipFree(own);
     return st;
   };
   hipLaunchKernelGGL(jp_init_kernel, dim3(nb), dim3(256), 0, s, ca, n);
@@ -1107,11 +1166,11 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
   }
   // ---- the order of P A P^T: blocks of kGsBlock consecutive rows, within a block the
   // rows by color, within a color in index order (counting sort on the host).  A color's
-  // rows are then one segment per block: the SpMV's and the sweep's gathers stay within a
+  // rows are then one run per block: the SpMV's and the sweep's gathers stay within a
   // block and its neighbours (L2-resident, and column distances small enough for the
   // packed operator's 16-bit deltas on banded operators), while the rows of one color
-  // still do not couple.  Also its inverse, the row pointers of P A P^T, and per color
-  // the list of its rows' positions (the sweep's row lists).
+  // still do not couple.  Also its inverse, the row pointers of P A P^T, and the sweep's
+  // row list (color-major: per color its runs in block order).
   std::vector<int32_t> ch((size_t)n), ph((size_t)n), ih((size_t)n), rp((size_t)n + 1), rpp((size_t)n + 1);
   if (hipMemcpyAsync(ch.data(), cold, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(rp.data(), A->row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -1122,35 +1181,34 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
   const int64_t nblk = cdiv(n, kGsBlock);
   std::vector<int64_t> koff((size_t)(nblk * ncol) + 1, 0);
   for (int64_t i = 0; i < n; ++i) koff[(i / kGsBlock) * ncol + ch[i] + 1] += 1;
+  std::vector<int64_t> run_len((size_t)(nblk * ncol));
+  for (int64_t k = 0; k < nblk * ncol; ++k) run_len[k] = koff[k + 1];
   for (int64_t k = 0; k < nblk * ncol; ++k) koff[k + 1] += koff[k];
   {
     std::vector<int64_t> pos(koff.begin(), koff.end() - 1);
     for (int64_t i = 0; i < n; ++i) ph[pos[(i / kGsBlock) * ncol + ch[i]]++] = (int32_t)i;
   }
   rpp[0] = 0;
-  for (int64_t p = 0; p < n; ++p) {
-    ih[ph[p]] = (int32_t)p;
-    rpp[p + 1] = rpp[p] + (rp[ph[p] + 1] - rp[ph[p]]);
+  for (int64_t q = 0; q < n; ++q) {
+    ih[ph[q]] = (int32_t)q;
+    rpp[q + 1] = rpp[q] + (rp[ph[q] + 1] - rp[ph[q]]);
   }
-  std::vector<int64_t> off((size_t)ncol + 1, 0);
-  for (int64_t i = 0; i < n; ++i) off[ch[i] + 1] += 1;
-  for (int c = 0; c < ncol; ++c) off[c + 1] += off[c];
   std::vector<int32_t> rows_by_color((size_t)n);
   int32_t padcol = -1;
   {
+    std::vector<int64_t> off((size_t)ncol + 1, 0);
+    for (int64_t i = 0; i < n; ++i) off[ch[i] + 1] += 1;
+    for (int c = 0; c < ncol; ++c) off[c + 1] += off[c];
     std::vector<int64_t> pos(off.begin(), off.end() - 1);
-    for (int64_t p = 0; p < n; ++p) {
-      const int c = ch[ph[p]];
-      rows_by_color[pos[c]++] = (int32_t)p;
-      if (c == 0 && padcol < 0) padcol = (int32_t)p;
+    for (int64_t q = 0; q < n; ++q) {
+      const int c = ch[ph[q]];
+      rows_by_color[pos[c]++] = (int32_t)q;
+      if (c == 0 && padcol < 0) padcol = (int32_t)q;
     }
   }
-  // ---- owned block: colors (index order), perm, inv, P A P^T (CSR), colors of its rows,
-  // the sweep's row lists, two scratch vectors
-  const size_t obytes = 6 * align_up(4 * (size_t)n + 4) + align_up(4 * (size_t)std::max<int64_t>(nnz, 1)) +
-                        align_up(8 * (size_t)std::max<int64_t>(nnz, 1)) + align_up(16 * (size_t)n) + kAlign;
-  if (hipMalloc(&own, obytes) != hipSuccess) return bail(fail(TSG_ERR_HIP, "hipMalloc of the preconditioner failed"));
-  Carve oc{static_cast<char*>(own)};
+  // ---- colors (index order), perm, inv, P A P^T (CSR), colors of its rows, the sweep's
+  // row list, two scratch vectors
+  Carve oc{r_own};
   int32_t* colors = oc.take<int32_t>((size_t)n);
   int32_t* perm = oc.take<int32_t>((size_t)n);
   int32_t* inv = oc.take<int32_t>((size_t)n);
@@ -1173,18 +1231,18 @@ tsg_status tsg_csr_precond(tsg_csr A, void* stream) {
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return bail(fail(TSG_ERR_HIP, "building P A P^T: %s", hipGetErrorString(e)));
-  // ---- its own handle (Gershgorin interval, packed copy for the SpMV) and sweep layout
-  TRY_OR(tsg_csr_create(n, nnz, row_ptr_p, col_p, val_p, stream, &pa), bail);
+  // ---- its own handle (Gershgorin interval, packed copy for the SpMV) and sweep layout,
+  // all in the buffer
+  TRY_OR(create_impl(n, nnz, row_ptr_p, col_p, val_p, s, r_padev, r_patmp, &pa), bail);
   const size_t pk = tsg_csr_pack_bytes(pa);
-  if (hipMalloc(&pack, pk) != hipSuccess) return bail(fail(TSG_ERR_HIP, "hipMalloc of the packed copy failed"));
-  TRY_OR(tsg_csr_pack(pa, pack, pk, stream), bail);
-  TRY_OR(build_sweep_layout(pa, off, rlist, colors_p, padcol, s), bail);
+  if (pk > L.pack) return bail(fail(TSG_ERR_UNSUPPORTED, "internal: packed copy %zu above the bound %zu", pk, L.pack));
+  TRY_OR(tsg_csr_pack(pa, r_pack, pk, stream), bail);
+  TRY_OR(build_sweep_layout(pa, ncol, nblk, run_len, rlist, colors_p, padcol, r_plan, r_sweep, L.max_slices,
+                            L.max_entries, s),
+         bail);
   HIP_TRY(hipStreamSynchronize(s));
-  (void)hipFree(scratch);
   pa->colors = colors_p;
   A->pa = pa;
-  A->pa_pack = pack;
-  A->own_mem = own;
   A->colors = colors;
   A->perm = perm;
   A->gs_tmp = tmp;

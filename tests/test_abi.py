@@ -32,7 +32,7 @@ def test_header_declares_the_boundary():
               "tsg_orthogonalize", "tsg_orthogonalize_workspace_bytes", "tsg_status_string",
               "tsg_last_error", "tsg_csr_gershgorin", "tsg_server_create", "tsg_server_destroy",
               "tsg_server_submit", "tsg_server_step", "tsg_server_poll", "tsg_server_request_bytes",
-              "tsg_csr_pack", "tsg_csr_pack_bytes", "tsg_ritz_newton", "tsg_csr_precond",
+              "tsg_csr_pack", "tsg_csr_pack_bytes", "tsg_ritz_newton", "tsg_csr_precond", "tsg_csr_precond_bytes",
               "tsg_csr_ncolors", "tsg_csr_colors", "tsg_precond_apply"):
         assert s in syms
 
@@ -72,7 +72,8 @@ def test_host_side_validation(lib):
     assert lib.tsg_orthogonalize_workspace_bytes(100, 65, 5) == 0
     assert lib.tsg_orthogonalize_workspace_bytes(100, 61, 5) > 0
     # preconditioner entries reject NULL handles before any device work
-    assert lib.tsg_csr_precond(None, None) == -1
+    assert lib.tsg_csr_precond(None, None, 0, None) == -1
+    assert lib.tsg_csr_precond_bytes(None) == 0
     assert lib.tsg_precond_apply(None, None, None, None) == -1
     assert lib.tsg_csr_ncolors(None) == 0
     # precond = MCGS is FP64 only; an unknown precond value is rejected

@@ -118,3 +118,38 @@ def test_precond_requires_setup(tsg):
 def test_server_rejects_precond(tsg):
     with pytest.raises(tsg.TSGError):
         tsg.Server(64 << 20, m=30, s=5, precision="fp64", precond="mcgs")
+
+
+def test_precond_and_solve_use_caller_memory_only(tsg):
+    """tsg_csr_precond builds everything in the caller's buffer (coloring scratch, P A P^T,
+    its handle block and packed copy, the sweep layout) and a preconditioned solve runs in the
+    caller's workspace: after a warm-up on another operator (every kernel loaded), the set-up
+    and an eager solve leave the device's free memory unchanged -- the library's only device
+    allocation is the handle's 4 KiB block, made by tsg_csr_create before."""
+    lib = tsg.load_library()
+    _say("case precond caller memory")
+    pr0 = W.make_problem("convdiff2d", 40, seed=1)
+    A0 = tsg.CSRMatrix.from_host(pr0["A"]).precond_setup()
+    tsg.solve(A0, torch.as_tensor(pr0["b"], device="cuda"), m=30, s=5, tol=1e-8, precond="mcgs", graph=False)
+    pr = W.make_problem("convdiff2d", 96, seed=4)
+    A = tsg.CSRMatrix.from_host(pr["A"])
+    nbytes = int(lib.tsg_csr_precond_bytes(A.handle))
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ptr = (buf.data_ptr() + 255) // 256 * 256
+    b = torch.as_tensor(pr["b"], device="cuda")
+    x = torch.zeros_like(b)
+    need = tsg.solve_workspace_bytes(A, m=60, s=5, precond="mcgs")
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    assert ws.data_ptr() % 256 == 0
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    assert lib.tsg_csr_precond(A.handle, ptr, nbytes, torch.cuda.current_stream().cuda_stream) == 0
+    A._precond = buf  # the buffer lives as long as the handle
+    x, info = tsg.solve(A, b, x=x, m=60, s=5, tol=1e-10, precond="mcgs", graph=False, workspace=ws)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    _say(f"  buffer {nbytes} bytes ({nbytes / (8 * A.n):.1f} doubles per row); free memory change {free0 - free1}")
+    assert info.converged
+    assert free1 == free0, (free0, free1)
+    relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], x.cpu().numpy())) / np.linalg.norm(pr["b"])
+    assert relres <= 1e-10

@@ -3,13 +3,14 @@
 A request computes bit for bit what tsg_solve computes for it, whatever else shares the
 batched launches: checked with requests of different sizes and operators submitted
 together, arriving while others run, and admitted one by one through an arena too small
-to hold them all.  tsg_solve itself is checked against the oracle in test_gpu_parity.py.
+to hold them all; and served results against the oracle directly.
 """
 import numpy as np
 import pytest
 import torch
 
 import workloads as W
+from oracle import gmres as G
 from oracle import sparse as S
 
 pytestmark = pytest.mark.gpu
@@ -165,3 +166,62 @@ def test_request_larger_than_arena_is_rejected(tsg):
     with pytest.raises(tsg.TSGError):
         srv.submit(0, *reqs[0][1:])
     srv.close()
+
+
+def test_served_results_match_oracle(tsg):
+    """Served requests against the oracle, not against tsg_solve: a batch of operators and
+    sizes submitted together plus one arriving while they run.  FP64 requests (monomial and
+    shifted bases): the oracle's iteration count and x within 1e-10 wherever the oracle's
+    cycles took no fallback pass and no truncation (else x within 2 tol kappa_2(A)).  Mixed-form requests
+    (FP32 basis, FP64 refinement, tol 1e-8): the explicit residual at most tol, and x within
+    2 tol kappa_2(A) of the oracle's FP64 x (kappa_2 in closed form for the Laplacian, from
+    the SVD of the assembled operator for convection-diffusion)."""
+    _say("case server vs oracle")
+    specs = SPECS[:4]
+    reqs = _requests(tsg, specs)
+    for kw in (dict(precision="fp64", basis="monomial", tol=1e-10),
+               dict(precision="fp64", basis="shifted", tol=1e-10),
+               dict(precision="fp32_ir", basis="shifted", tol=1e-8)):
+        srv = tsg.Server(1 << 30, **dict(KW, **kw))
+        for i, (pr, A, b) in enumerate(reqs[:3]):
+            srv.submit(i, A, b)
+        got = {}
+        for step in range(4):
+            srv.step()
+            for tag, x, info in srv.poll():
+                got[tag] = (x, info)
+        srv.submit(3, reqs[3][1], reqs[3][2])
+        got.update(_drain(srv, len(reqs) - len(got)))
+        srv.close()
+        for i, (pr, A, b) in enumerate(reqs):
+            x, info = got[i]
+            xg = x.cpu().numpy()
+            relres = np.linalg.norm(pr["b"] - S.spmv(pr["A"], xg)) / np.linalg.norm(pr["b"])
+            assert info.converged and relres <= kw["tol"], (i, kw, relres)
+            kind, N = specs[i]
+            if kw["precision"] == "fp64":
+                ref = G.sstep_gmres(pr["A"], pr["b"], m=60, s=5, tol=1e-10, basis=kw["basis"], record=True)
+                err = np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"])
+                clean = ref["fallbacks"] == 0 and all(r["Qhat"].shape[1] == 61 for r in ref["records"])
+                _say(f"  {kw['basis']} {specs[i]}: iters served {info.iters} oracle {ref['iters']}, "
+                     f"|x - x_oracle| {err:.1e}{'' if clean else ' (oracle took fallback passes or truncated)'}")
+                if clean:
+                    assert info.iters == ref["iters"] and info.cycles == ref["cycles"]
+                    assert err <= 1e-10
+                else:
+                    # the monomial basis of the strongly convective 24^2 operator: the oracle's
+                    # pass and truncation decisions sit at rounding level (both sides converge);
+                    # two solutions with relative residuals <= tol differ by <= 2 tol kappa
+                    kap = np.linalg.cond(G.dense_solve(pr["A"], pr["b"])[1])
+                    assert err <= 2 * 1e-10 * kap
+            else:
+                ref = G.sstep_gmres(pr["A"], pr["b"], m=60, s=5, tol=1e-12, basis="shifted")
+                if kind == "laplace2d":
+                    lmin, lmax = W.laplace_extreme_eigs(N, 2)
+                    kap = lmax / lmin
+                else:
+                    kap = np.linalg.cond(G.dense_solve(pr["A"], pr["b"])[1])
+                err = np.linalg.norm(xg - ref["x"]) / np.linalg.norm(ref["x"])
+                _say(f"  mixed {specs[i]}: iters {info.iters}, |x - x_fp64| {err:.1e}, bound {2 * 1e-8 * kap:.1e}")
+                assert err <= 2 * 1e-8 * kap
+
