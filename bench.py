@@ -91,6 +91,149 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def _counter_rows(d: str):
+    """(kernel name, dispatch id, counter value) of a rocprofv3 --pmc csv run in directory d."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {d}")
+    out = []
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            out.append((r["Kernel_Name"], int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    return out
+
+
+def _kernel_key(name: str) -> str:
+    """The name the bench uses for a kernel: a batched body's own name (MpkBody<double, double,
+    1>), else the kernel's signature without its return type."""
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    pre = "tsg::batched_kernel<tsg::"
+    if name.startswith(pre):
+        body = name[len(pre):name.index(">(")].strip()
+        return body[:-1].strip() if body.endswith(">") and body.count("<") < body.count(">") else body
+    return name
+
+
+def write_traffic(fetch_dir: str, write_dir: str):
+    """HBM bytes per launch of every kernel of the --pmc-probe run, from its FETCH_SIZE and
+    WRITE_SIZE counter runs (KiB per dispatch, paired by dispatch id: both runs launch the
+    same sequence), each scaled by what the counter reads for the probe's 1 GiB device copies
+    (the calibration copies of known size: the copy dispatches that write at least half a
+    GiB).  Dispatches that did no work (gated launches that return at entry: below 1% of the
+    kernel's largest) are dropped.  Writes profiles/kernel_traffic.json with the hash of the
+    kernel sources it was taken on, and prints the table as markdown."""
+    runs = []
+    for d in (fetch_dir, write_dir):
+        per = {}
+        for name, disp, v in _counter_rows(d):
+            per[disp] = (_kernel_key(name), per.get(disp, (None, 0.0))[1] + v)
+        runs.append(per)
+    fetch, write = runs
+    agg = {}
+    for disp, (name, fv) in fetch.items():
+        if disp in write and write[disp][0] == name:
+            agg.setdefault(name, []).append((fv, write[disp][1]))
+    copy = [k for k in agg if "copyBuffer" in k]
+    if not copy:
+        raise SystemExit("no calibration copy in the counter runs")
+    cal_kb = (1 << 30) / 1024.0
+    cp = agg[copy[0]]
+    wmax = max(w for _, w in cp)
+    big = [(f, w) for f, w in cp if w >= 0.5 * wmax]
+    ff = cal_kb / (sum(f for f, _ in big) / len(big))
+    wf = cal_kb / (sum(w for _, w in big) / len(big))
+    kernels = {}
+    for name, v in agg.items():
+        if name in copy:
+            continue
+        top = max(f for f, _ in v)
+        keep = [(f, w) for f, w in v if f >= 0.01 * top] if top > 0 else v
+        fkb = sum(f for f, _ in keep) / len(keep)
+        wkb = sum(w for _, w in keep) / len(keep)
+        kernels[name] = {"dispatches": len(keep), "fetch_kb": round(fkb, 1), "write_kb": round(wkb, 1),
+                         "hbm_bytes_per_launch": int(round(1024 * (fkb * ff + wkb * wf)))}
+    rec = {"source_hash": kernel_source_hash(),
+           "commands": ["rocprofv3 --pmc FETCH_SIZE -d " + fetch_dir + " -o run --output-format csv -- python3 bench.py --pmc-probe",
+                        "rocprofv3 --pmc WRITE_SIZE -d " + write_dir + " -o run --output-format csv -- python3 bench.py --pmc-probe"],
+           "copy_calibration": {"bytes": 1 << 30, "copies": len(big),
+                                "fetch_kb": round(sum(f for f, _ in big) / len(big), 1),
+                                "write_kb": round(sum(w for _, w in big) / len(big), 1),
+                                "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
+           "kernels": dict(sorted(kernels.items(), key=lambda kv: -kv[1]["hbm_bytes_per_launch"] * kv[1]["dispatches"]))}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print("| kernel | dispatches | FETCH_SIZE KB | WRITE_SIZE KB | HBM bytes / launch |")
+    print("|---|---:|---:|---:|---:|")
+    for name, k in rec["kernels"].items():
+        print(f"| `{name.split('(')[0]}` | {k['dispatches']} | {k['fetch_kb']} | {k['write_kb']} | {k['hbm_bytes_per_launch']:,} |")
+
+def np_mean(v):
+    return sum(v) / len(v)
+
+
+def ortho_bench(args, tsg, W, np, torch, dev, n):
+    """The isolated two-stage block orthogonalization of a Gaussian n x 61 block (s = args.s,
+    one big panel), median over args.ortho_reps calls, at ld = n + 64 and ld = n."""
+    k, s = 61, args.s
+    log(f"[bench] isolated block orthogonalization {n} x {k}")
+    X0 = torch.as_tensor(W.gaussian_block(n, k, seed=7).T.copy(), device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for pad in (64, 0):
+        # columns n + 64 elements apart (the solver's basis layout: column starts that are
+        # multiples of 64 Ki elements put the columns on the same HBM channels), and the
+        # unpadded layout for reference
+        buf = torch.empty((k, n + pad), dtype=torch.float64, device=dev)
+        Xw = buf[:, :n]
+        times = []
+        for r in range(args.ortho_reps + 2):
+            Xw.copy_(X0)
+            e0.record()
+            tsg.orthogonalize(Xw, s=s, algo="two_stage")
+            e1.record()
+            torch.cuda.synchronize()
+            if r >= 2:
+                times.append(e0.elapsed_time(e1))
+        res[pad] = float(np.median(times))
+        if pad == 64:
+            _, _, oerr = tsg.orthogonalize(Xw.copy_(X0), s=s, algo="two_stage", orth_err=True)
+        del buf, Xw
+    med = res[64]
+    # context: torch's own kernels on the same padded block, a read-only reduction over the
+    # rows of every column and an in-place scaling (every column read and written once)
+    buf = torch.empty((k, n + 64), dtype=torch.float64, device=dev)
+    Xw = buf[:, :n]
+    Xw.copy_(X0)
+    ctx = {}
+    for name, fn, passes_ in (("torch_column_sums", lambda: Xw.sum(dim=1), k),
+                              ("torch_inplace_scale", lambda: Xw.mul_(1.0), 2 * k)):
+        ts = []
+        for r in range(7):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if r >= 2:
+                ts.append(e0.elapsed_time(e1))
+        ctx[name + "_GBps"] = round(passes_ * n * 8 / float(np.median(ts)) / 1e6, 1)
+    del buf, Xw
+    passes = 1047 if (args.s == 5 and k == 61) else None
+    method_bytes = sum(2 * c0 + 3 * min(s, k - c0) for c0 in range(1, k, s)) * n * 8 + 3 * k * n * 8
+    return {"shape": [n, k], "ld": n + 64, "s": s, "algo": "two_stage", "median_ms": round(med, 3),
+            "median_ms_ld_n": round(res[0], 3),
+            "method_column_passes": passes if passes else round(method_bytes / (n * 8)),
+            "method_GB": round(method_bytes / 1e9, 3),
+            "GBps": round(method_bytes / med / 1e6, 1),
+            "frac": round(method_bytes / med / 1e6 / HBM_PEAK_GBPS, 4),
+            "byte_model": "stage 1 sum_j (2 k_j + 3 s) + stage 2 3 k column passes (Gram read, "
+                          "explicit Q read and written)",
+            "orth_err": oerr, "reps": args.ortho_reps, "context": ctx}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +256,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_ir"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ortho-bench", action="store_true")
+    ap.add_argument("--ortho-only", action="store_true",
+                    help="only the isolated block orthogonalization (n = N^2 rows, 61 columns)")
     ap.add_argument("--ortho-reps", type=int, default=20)
     ap.add_argument("--cpu-budget-s", type=float, default=30.0,
                     help="host seconds for the CPU oracle legs (all cores, then one thread)")
@@ -123,6 +268,9 @@ def main():
                     help="launch every kernel directly instead of replaying one captured cycle")
     ap.add_argument("--modes", action="store_true",
                     help="also time one solve in each launch mode (graph/eager x events on/off)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/kernel_traffic.json (and print its table) from the two rocprofv3 "
+                         "counter runs of --pmc-probe: FETCH_SIZE in FETCH_DIR, WRITE_SIZE in WRITE_DIR")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for hardware-counter passes: three 1 GiB device copies (the "
                          "calibration kernel) and the first two restart cycles of the solve")
@@ -138,6 +286,9 @@ def main():
     ap.add_argument("--compare", action="store_true",
                     help="also time one solve of each other orthogonalization scheme")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(*args.traffic_from)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: the solver runs on exactly one GPU (the whole problem fits one MI355X); "
@@ -173,6 +324,10 @@ def main():
         print(json.dumps({"pmc_probe": True, "copy_bytes": 1 << 30, "iters": int(info.iters)}), flush=True)
         return
     N = args.N or (160 if args.problem == "laplace3d" else 2048)
+    if args.ortho_only:
+        ob = ortho_bench(args, tsg, W, np, torch, dev, N * N)
+        print(json.dumps({"ortho_bench": ob}), flush=True)
+        return
     desc = {"laplace2d": f"2D Laplace 5-point {N}x{N}", "laplace3d": f"3D Laplace 7-point {N}^3",
             "convdiff2d": f"2D convection-diffusion upwind {N}x{N}"}[args.problem]
     log(f"[bench] building {desc}")
@@ -399,43 +554,7 @@ def main():
         log(f"[bench] mixed vs FP64: {out['vs_fp64']}")
 
     if not args.no_ortho_bench:
-        n, k, s = Ah.n, 61, args.s
-        log(f"[bench] isolated block orthogonalization {n} x {k}")
-        X0 = torch.as_tensor(W.gaussian_block(n, k, seed=7).T.copy(), device=dev)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        res = {}
-        for pad in (64, 0):
-            # columns n + 64 elements apart (the solver's basis layout: column starts that are
-            # multiples of 64 Ki elements put the columns on the same HBM channels), and the
-            # unpadded layout for reference
-            buf = torch.empty((k, n + pad), dtype=torch.float64, device=dev)
-            Xw = buf[:, :n]
-            times = []
-            for r in range(args.ortho_reps + 2):
-                Xw.copy_(X0)
-                e0.record()
-                tsg.orthogonalize(Xw, s=s, algo="two_stage")
-                e1.record()
-                torch.cuda.synchronize()
-                if r >= 2:
-                    times.append(e0.elapsed_time(e1))
-            res[pad] = float(np.median(times))
-            if pad == 64:
-                _, _, oerr = tsg.orthogonalize(Xw.copy_(X0), s=s, algo="two_stage", orth_err=True)
-            del buf, Xw
-        med = res[64]
-        passes = 1047 if (args.s == 5 and k == 61) else None
-        method_bytes = sum(2 * c0 + 3 * min(s, k - c0) for c0 in range(1, k, s)) * n * 8 + 3 * k * n * 8
-        out["ortho_bench"] = {"shape": [n, k], "ld": n + 64, "s": s, "algo": "two_stage", "median_ms": round(med, 3),
-                              "median_ms_ld_n": round(res[0], 3),
-                              "method_column_passes": passes if passes else round(method_bytes / (n * 8)),
-                              "method_GB": round(method_bytes / 1e9, 3),
-                              "GBps": round(method_bytes / med / 1e6, 1),
-                              "frac": round(method_bytes / med / 1e6 / HBM_PEAK_GBPS, 4),
-                              "byte_model": "stage 1 sum_j (2 k_j + 3 s) + stage 2 3 k column passes (Gram read, "
-                                            "explicit Q read and written)",
-                              "orth_err": oerr, "reps": args.ortho_reps}
-        del X0
+        out["ortho_bench"] = ortho_bench(args, tsg, W, np, torch, dev, Ah.n)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, Ah, pr, info, desc, precond)
