@@ -45,9 +45,14 @@ __device__ __forceinline__ gbl<T>* G(T* p) {
 // the scalar registers holding it.  Code that takes plain pointers derived from it (struct
 // members, helper arguments) then compiles its accesses to global loads and stores instead
 // of flat ones.
+// (The pointer is wave-uniform by contract; reading it from the first active lane makes that
+// explicit where the compiler holds it in vector registers.)
 template <typename T>
 __device__ __forceinline__ T* Gp(T* p) {
-  gbl<T>* q = (gbl<T>*)p;
+  const uint64_t u = (uint64_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  gbl<T>* q = (gbl<T>*)(((uint64_t)hi << 32) | lo);
   __asm__ volatile("" : "+s"(q));
   return (T*)q;
 }
@@ -58,6 +63,21 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// A wave-uniform value (say, a kernel's argument block) read from the first active lane, one
+// 32-bit word at a time: scalar registers instead of vector ones wherever the compiler had
+// loaded it with vector loads.
+template <typename T>
+__device__ __forceinline__ T wave_uniform(const T& v) {
+  static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+  uint32_t w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)w[i]);
+  T r;
+  __builtin_memcpy(&r, w, sizeof(T));
+  return r;
 }
 
 // Lane `src`'s value (src uniform) in every lane of the wave.
@@ -145,6 +165,86 @@ __device__ void block_sum_partials(const double* __restrict__ part1, int E, int 
     double acc = 0.0;
     for (int g = 0; g < G; ++g) acc += scratch[g * E + e];
     out[e] = acc;
+  }
+  __syncthreads();
+}
+
+// block_sum_partials for the tail kernels, inline: the same thread groups, block ranges and
+// summation order, the loads in unconditional groups of 16 (rows clamped to the range, so a
+// branch never waits on a load) to bound the registers held in flight.
+__device__ __forceinline__ double strided_sum16(gbl<const double>* p, int E, int e, int b0, int b1) {
+  double acc = 0.0;
+  for (int b = b0; b < b1; b += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = p[(size_t)min(b + u, b1 - 1) * E + e];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (b + u < b1) acc += v[u];
+  }
+  return acc;
+}
+__device__ __forceinline__ void tail_sum_partials(const double* part1, int E, int nblocks, double* out,
+                                                  double* scratch) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  gbl<const double>* p = G(part1);
+  if (E >= nt || nblocks == 1) {
+    for (int e = tid; e < E; e += nt) out[e] = strided_sum16(p, E, e, 0, nblocks);
+    __syncthreads();
+    return;
+  }
+  const int ng = min(nt / E, nblocks), chunk = (nblocks + ng - 1) / ng;
+  if (tid < ng * E) {
+    const int e = tid % E, g = tid / E;
+    const int b0 = g * chunk, b1 = min(nblocks, b0 + chunk);
+    scratch[g * E + e] = strided_sum16(p, E, e, b0, b1);
+  }
+  __syncthreads();
+  for (int e = tid; e < E; e += nt) {
+    double acc = 0.0;
+    for (int g = 0; g < ng; ++g) acc += scratch[g * E + e];
+    out[e] = acc;
+  }
+  __syncthreads();
+}
+
+// The same sum in two halves when every thread's share is at most 16 partials (E < blockDim.x
+// and a block range of at most 16): partials_load issues all of this thread's loads at once,
+// so that the caller can wait for other memory together with them, and partials_sum adds
+// them in the same order.  partials_load returns false (nothing loaded) in other cases.
+struct PartialLoads {
+  double v[16];
+};
+__device__ __forceinline__ bool partials_load(const double* part1, int E, int nblocks, PartialLoads& pl) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (E >= nt || nblocks <= 1 || E <= 0) return false;
+  const int ng = min(nt / E, nblocks), chunk = (nblocks + ng - 1) / ng;
+  if (chunk > 16) return false;
+  const int e = tid % E, g = tid / E;
+  const int b0 = min(g * chunk, nblocks - 1);
+  // unconditional loads, rows clamped to the last block (in bounds for every thread);
+  // partials_sum adds only this thread's own rows
+  gbl<const double>* __restrict__ p = G(part1);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) pl.v[u] = p[(size_t)min(b0 + u, nblocks - 1) * E + e];
+  return true;
+}
+__device__ __forceinline__ void partials_sum(const PartialLoads& pl, int E, int nblocks, double* out,
+                                             double* scratch) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int ng = min(nt / E, nblocks), chunk = (nblocks + ng - 1) / ng;
+  const int e = tid % E, g = tid / E;
+  const int b0 = g * chunk, b1 = min(nblocks, b0 + chunk);
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u)
+    if (b0 + u < b1) acc += pl.v[u];
+  if (tid < ng * E) scratch[g * E + e] = acc;
+  __syncthreads();
+  for (int x = tid; x < E; x += nt) {
+    double t = 0.0;
+    for (int q = 0; q < ng; ++q) t += scratch[q * E + x];
+    out[x] = t;
   }
   __syncthreads();
 }

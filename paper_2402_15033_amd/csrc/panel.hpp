@@ -81,6 +81,20 @@ __device__ __forceinline__ bool gated_off(const PanelArgs& a, const SmallState* 
   if (a.gate == 2) return st->h.refine != a.panel + 1;
   return a.gate == 3 && st->h.refine2 != a.panel + 1;
 }
+// gated_off in two halves: the flags' loads (issued early), then the decision.
+struct GateFlags {
+  int32_t done, stop_panel, refine, refine2;
+};
+__device__ __forceinline__ GateFlags gate_flags(const SmallState* st_) {
+  gbl<const SmallState>* st = G(st_);
+  return GateFlags{st->h.done, st->h.stop_panel, st->h.refine, st->h.refine2};
+}
+__device__ __forceinline__ bool gated_off(const PanelArgs& a, const GateFlags& f) {
+  if (!a.gate) return false;
+  if (f.done || a.panel > f.stop_panel) return true;
+  if (a.gate == 2) return f.refine != a.panel + 1;
+  return a.gate == 3 && f.refine2 != a.panel + 1;
+}
 
 // ----------------------------------------------------------------------------- tails
 // Called by every thread of the tail block with the reduced Gram sred ((k+sw) x nz, entry
@@ -90,7 +104,7 @@ __device__ __forceinline__ double red(const PanelArgs& a, const double* sred, in
   return sred[c * a.nz + (a.nz - a.sw) + j];
 }
 
-__device__ void tail_breakdown(const PanelArgs& a, int kkeep, int f = -1) {
+__device__ __forceinline__ void tail_breakdown(const PanelArgs& a, int kkeep, int f = -1) {
   SmallState* st = a.st;
   if (threadIdx.x == 0) {
     if (a.standalone) {
@@ -124,7 +138,7 @@ __device__ void tail_check(SmallState* st, int ncols, int panel) {
 // the explicit second pass (second = true, the panel holds Y = W - Q P1), at most
 // max(tol * Gw_jj, pivot_tol^2 * refW_j) with refW the raw Gram diagonal of W.
 // Returns the failing pivot or -1.
-__device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, double* R, double tol,
+__device__ __forceinline__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, double* R, double tol,
                              bool second = false) {
   const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
   __shared__ double sG[kMaxS * kMaxS], sRef[kMaxS];
@@ -160,7 +174,7 @@ __device__ int tail_pip_chol(const PanelArgs& a, const double* sred, double* P, 
 // Pythagorean Gram G, Rs = Chol(G + mu I), mu = 10 pivot_tol trace(G) -- well above the
 // Gram's rounding level, so G + mu I is positive definite and (Y - Q P2) Rs^{-1} is well
 // conditioned.  Returns the failing pivot or -1.
-__device__ int tail_shifted_chol(const PanelArgs& a, const double* sred, double* Rs) {
+__device__ __forceinline__ int tail_shifted_chol(const PanelArgs& a, const double* sred, double* Rs) {
   const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
   __shared__ double sG[kMaxS * kMaxS];
   __shared__ double s_mu;
@@ -183,7 +197,7 @@ __device__ int tail_shifted_chol(const PanelArgs& a, const double* sred, double*
 }
 
 // Plain Cholesky of rows r0..r0+s-1 of sred (a q^T q Gram) into R (ld kMaxS).
-__device__ int tail_chol_rows(const PanelArgs& a, const double* sred, int r0, double* R, double tol) {
+__device__ __forceinline__ int tail_chol_rows(const PanelArgs& a, const double* sred, int r0, double* R, double tol) {
   const int s = a.sw, tid = threadIdx.x, nt = blockDim.x;
   __shared__ double sG[kMaxS * kMaxS];
   for (int idx = tid; idx < s * s; idx += nt) {
@@ -209,7 +223,7 @@ __device__ void tail_set_tinv(SmallState* st, const double* R, int s) {
 
 // The panel's final factors (P, R): V_panel = Q P + Q_new R.  Solver mode: Hessenberg
 // block, and (one-stage) Givens + convergence check.  Stand-alone: R factor assembly.
-__device__ void tail_emit_panel(const PanelArgs& a, const double* P, const double* R, bool givens,
+__device__ __forceinline__ void tail_emit_panel(const PanelArgs& a, const double* P, const double* R, bool givens,
                                 const double* lH) {
   SmallState* st = a.st;
   const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
@@ -230,7 +244,167 @@ __device__ void tail_emit_panel(const PanelArgs& a, const double* P, const doubl
   }
 }
 
-__device__ void panel_tail(const PanelArgs& a, const double* sred, const double* lH) {
+// Stage-1 PIP tail of a panel of compile-time width S (the solver's and the stand-alone
+// orthogonalization's common step size), the same operations in the same order per entry as
+// tail_pip_chol, tail_set_tinv and block_hessenberg_panel, spread over the waves of the tail:
+//   wave 0        G(i,j) = Gw(i,j) - P^T P (four interleaved partial sums), the row-oriented
+//                 Cholesky (d_j = G_jj - sum_{i<j} R_ij^2, R_jc = (G_jc - sum_{i<j} R_ij R_ic)
+//                 / R_jj) and X = R^{-1} by columns, in registers: lane c holds column c of
+//                 G, R and X, and row j of R reaches every lane by wave broadcasts as soon as
+//                 step j has formed it (the running sums of the later steps take their terms
+//                 then); R to LDS, T = X to st->Tcur;
+//   waves 1..S-1  solver: column c = wave of M = S B - [H S; 0] for the rows i < k (lane i),
+//                 which need P, H and the basis parameters only;
+//   the others    P to st->Pcur for the next update.
+// Straight-line code (S fixed): no branch waits on a load.  tail_pip_regs ends with a barrier
+// and returns the failing pivot or -1; on success tail_pip_regs_emit forms the rows
+// k .. k+S-1 of M, solves with T = S(k-1 .. k+S-2, 0 .. S-1) and stores the new Hessenberg
+// columns (solver), or writes P and R into the R factor (stand-alone).
+template <int S>
+__device__ __forceinline__ int tail_pip_regs(const PanelArgs& a, const double* sred, const double* lH,
+                                             const double* lB, double* sR, double* lM) {
+  static_assert(S >= 1 && S * S <= kWave && S <= kTailThreads / kWave - 1, "one wave per Hessenberg column");
+  SmallState* st = a.st;
+  const int k = a.k, nz = a.nz, tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const double* pw = sred + (nz - S);  // P(r, j) = pw[r * nz + j], Gw(i, j) = pw[(k + i) * nz + j]
+  __shared__ int s_fail;
+  if (wave == 0) {
+    double gv = 0.0;
+    if (lane < S * S) {
+      const int i = lane % S, j = lane / S;
+      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+      int c = 0;
+      for (; c + 3 < k; c += 4) {
+        p0 += pw[c * nz + i] * pw[c * nz + j];
+        p1 += pw[(c + 1) * nz + i] * pw[(c + 1) * nz + j];
+        p2 += pw[(c + 2) * nz + i] * pw[(c + 2) * nz + j];
+        p3 += pw[(c + 3) * nz + i] * pw[(c + 3) * nz + j];
+      }
+      for (; c < k; ++c) p0 += pw[c * nz + i] * pw[c * nz + j];
+      gv = pw[(k + i) * nz + j] - ((p0 + p1) + (p2 + p3));
+    }
+    // v[j]: G(j, lane) - sum_{i < step} R(i, j) R(i, lane); d[j]: the running pivot of row j.
+    // Every step runs (a failed pivot only records its index; nothing is used then).
+    double v[S], d[S], r[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      v[j] = __shfl(gv, (j + lane * S) & (kWave - 1), kWave);
+      d[j] = wave_bcast(gv, j + j * S);
+      r[j] = 0.0;
+    }
+    const double tol = st->pip_tol;
+    int fail = -1;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const double ref = tol * pw[(k + j) * nz + j];
+      if (!(d[j] > 1.0 * ref) && fail < 0) fail = j;
+      const double rjj = sqrt(d[j]);
+      const double rjc = v[j] / rjj;  // R(j, lane) for lanes past j
+      r[j] = lane == j ? rjj : (lane > j ? rjc : 0.0);
+#pragma unroll
+      for (int jp = j + 1; jp < S; ++jp) {
+        const double rj = wave_bcast(rjc, jp);  // R(j, jp)
+        d[jp] -= rj * rj;
+        v[jp] -= rj * rjc;
+      }
+    }
+    if (lane < S) {
+#pragma unroll
+      for (int i = 0; i < S; ++i) sR[i + lane * kMaxS] = r[i];
+    }
+    if (fail < 0) {
+      // column `lane` of X: X(i,c) = ([i == c] - sum_{l=i+1..c} R(i,l) X(l,c)) / R(i,i); the
+      // terms l > c are R(i,l) * 0 and leave the sum as it is
+      double x[S];
+#pragma unroll
+      for (int i = S - 1; i >= 0; --i) {
+        double w = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+        for (int l = i + 1; l < S; ++l) w -= wave_bcast(r[i], l) * x[l];
+        x[i] = w / wave_bcast(r[i], i);
+      }
+      if (lane < S) {
+#pragma unroll
+        for (int i = 0; i < S; ++i) st->Tcur[i + lane * kMaxS] = x[i];
+      }
+      if (lane == 0) st->identity_t = 0;
+    }
+    if (lane == 0) s_fail = fail;
+  } else if (wave < S) {
+    if (!a.standalone && lane < k) {
+      const int c = wave, i = lane;
+      // S(i, l) for i < k: l = 0 -> [i == k-1]; l >= 1 -> P(i, l-1)
+      const double sc = pw[i * nz + c - 1], sc1 = c + 1 <= S ? pw[i * nz + c] : 0.0;
+      const double scm = c - 1 == 0 ? (i == k - 1 ? 1.0 : 0.0) : pw[i * nz + c - 2];
+      double w = sc * lB[c] + sc1 * lB[kMaxS + c];
+      if (lB[2 * kMaxS + c] != 0.0) w -= scm * lB[2 * kMaxS + c];
+      const double* pc = pw + (c - 1);
+#pragma unroll 4
+      for (int l = (i > 0 ? i - 1 : 0); l < k - 1; ++l) w -= lH[i + l * kLd] * pc[l * nz];
+      lM[i + c * kLd] = w;
+    }
+  } else {
+    for (int idx = tid - S * kWave; idx < k * S; idx += blockDim.x - S * kWave) {
+      const int c = idx % k, j = idx / k;
+      st->Pcur[c + j * kLd] = pw[c * nz + j];
+    }
+  }
+  __syncthreads();
+  return s_fail;
+}
+
+template <int S>
+__device__ __forceinline__ void tail_pip_regs_emit(const PanelArgs& a, const double* sred, const double* sR,
+                                                   const double* lB, const double* lM) {
+  SmallState* st = a.st;
+  const int k = a.k, nz = a.nz, tid = threadIdx.x;
+  const double* pw = sred + (nz - S);
+  if (a.standalone) {
+    const int c0 = a.wcol;
+    for (int idx = tid; idx < (k + S) * S; idx += blockDim.x) {
+      const int i = idx % (k + S), j = idx / (k + S);
+      const double v = (i < k) ? pw[i * nz + j] : ((i - k) <= j ? sR[(i - k) + j * kMaxS] : 0.0);
+      st->Hh[(i < k ? i : c0 + i - k) + (c0 + j) * kLd] = v;
+    }
+    return;
+  }
+  const int i = tid - kWave;  // wave 1, lane i: row i
+  if (i < 0 || i >= k + S) return;
+  double m[S];
+  if (i < k) {
+    // column 0: S(i,0) theta_0 + S(i,1) sigma_0
+    m[0] = (i == k - 1 ? 1.0 : 0.0) * lB[0] + pw[i * nz] * lB[kMaxS];
+#pragma unroll
+    for (int c = 1; c < S; ++c) m[c] = lM[i + c * kLd];
+  } else {
+    // S(i, l) for i >= k: l = 0 -> 0; l >= 1 -> R(i-k, l-1)
+    double Srow[S + 1];
+    Srow[0] = 0.0;
+#pragma unroll
+    for (int l = 1; l <= S; ++l) Srow[l] = sR[(i - k) + (l - 1) * kMaxS];
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+      double w = Srow[c] * lB[c] + Srow[c + 1] * lB[kMaxS + c];
+      if (c >= 1 && lB[2 * kMaxS + c] != 0.0) w -= Srow[c - 1] * lB[2 * kMaxS + c];
+      m[c] = w;
+    }
+  }
+  // T(0,0) = 1, T(q,0) = 0, T(0,c) = P(k-1,c-1), T(q,c) = R(q-1,c-1)
+  double x[S];
+  x[0] = m[0] / 1.0;
+#pragma unroll
+  for (int c = 1; c < S; ++c) {
+    double w = m[c];
+    w -= x[0] * pw[(k - 1) * nz + c - 1];
+#pragma unroll
+    for (int q = 1; q < c; ++q) w -= x[q] * sR[(q - 1) + (c - 1) * kMaxS];
+    x[c] = w / sR[(c - 1) + (c - 1) * kMaxS];
+  }
+#pragma unroll
+  for (int c = 0; c < S; ++c) st->Hh[i + (k - 1 + c) * kLd] = x[c];
+}
+
+__device__ __forceinline__ void panel_tail(const PanelArgs& a, const double* sred, const double* lH, const double* lB) {
   SmallState* st = a.st;
   const int k = a.k, s = a.sw, tid = threadIdx.x, nt = blockDim.x;
   __shared__ double sR[kMaxS * kMaxS], sR2[kMaxS * kMaxS], sP[kLd * kMaxS];
@@ -256,15 +430,17 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred, const double*
     case TAIL_PIP: {
       // the previous panel's block column of the stage-2 Gram (nz - s leading columns of
       // the reduction: [Qhat(:, 0:k)]^T Qhat(:, k-np:k)), written before this panel's
-      // Cholesky so that it survives a breakdown of this panel
+      // Cholesky so that it survives a breakdown of this panel (read by later kernels only)
       const int np = a.nz - s;
       for (int idx = tid; idx < k * np; idx += nt) {
         int c = idx % k, z = idx / k;
         int col = k - np + z;
         if (c <= col) st->G2[c + col * kLd] = sred[c * a.nz + z];
       }
-      __syncthreads();
-      int f = tail_pip_chol(a, sred, st->Pcur, sR, st->pip_tol);
+      // (panels of the common width 5 take the register form)
+      const bool regs = s == 5;
+      const int f = regs ? tail_pip_regs<5>(a, sred, lH, lB, sR, sP)
+                         : tail_pip_chol(a, sred, st->Pcur, sR, st->pip_tol);
       if (f >= 0) {
         if (a.standalone == 1) { tail_breakdown(a, a.kkeep, f); break; }
         if (a.fast) {
@@ -283,7 +459,7 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred, const double*
         // gated second pass orthogonalize Y.
         for (int idx = tid; idx < k * s; idx += nt) {
           int c = idx % k, j = idx / k;
-          st->P1[c + j * kLd] = st->Pcur[c + j * kLd];
+          st->P1[c + j * kLd] = red(a, sred, c, j);
         }
         for (int j = tid; j < s; j += nt) st->refW[j] = red(a, sred, k + j, j);
         if (tid == 0) {
@@ -292,6 +468,10 @@ __device__ void panel_tail(const PanelArgs& a, const double* sred, const double*
           st->h.fallbacks += 1;
         }
         __syncthreads();
+        break;
+      }
+      if (regs) {
+        tail_pip_regs_emit<5>(a, sred, sR, lB, sP);
         break;
       }
       tail_set_tinv(st, sR, s);
@@ -549,23 +729,43 @@ struct PTailBody {
   typedef PanelArgs Args;
   static constexpr int kThreads = kTailThreads;
   static constexpr int kMinWaves = 1;
-  static __device__ void run(const PanelArgs& a, int bid, int nb);
+  static __device__ __forceinline__ void run(const PanelArgs& a, int bid, int nb);
 };
-__device__ void PTailBody::run(const PanelArgs& a_, int, int) {
-  PanelArgs a = a_;
-  a.st = Gp(a_.st);  // (device memory: global, not flat, accesses in every helper)
+// (Forced inline, like the tail it runs: as a called function its argument block and LDS
+// arrays would be reached through generic pointers, the block kept in scratch memory.)
+__device__ __forceinline__ void PTailBody::run(const PanelArgs& a_, int, int) {
+  PanelArgs a = wave_uniform(a_);  // (scalar registers: the partials' loads need the vector ones)
+  a.st = Gp(a.st);  // (device memory: global, not flat, accesses in every helper)
   SmallState* st = a.st;
-  if (gated_off(a, st)) return;
   __shared__ double sred[kMaxCols * kMaxNz];
   __shared__ double scratch[kTailThreads];
   __shared__ double lH[kLd * kLd];
-  // a solver tail may append a Hessenberg block: H's loads go out with the reduction's
+  __shared__ double lB[3 * kMaxS];
+  // Every load this tail needs goes out before the gate check, which then waits for memory
+  // together with them: the gate's flags, for a solver tail H and the basis parameters of its
+  // Hessenberg block, and the partial Grams (allocated whether or not this panel runs).
+  const GateFlags gf = gate_flags(st);
   HessPrefetch pf;
-  if (!a.standalone) hessenberg_prefetch(st->Hh, a.k, pf);
+  double bp = 0.0;
+  if (!a.standalone) {
+    hessenberg_prefetch(st->Hh, a.k, pf);
+    if (threadIdx.x < 3 * kMaxS) bp = G(&st->theta[0])[threadIdx.x];  // theta, sigma, tau
+  }
   const int E = (a.k + a.sw) * a.nz;
-  block_sum_partials(a.part1, E, a.nblocks, sred, scratch);
-  if (!a.standalone) hessenberg_store(pf, lH);  // read after the tail's first barrier
-  panel_tail(a, sred, lH);
+  PartialLoads pl;
+  const bool pre = partials_load(a.part1, E, a.nblocks, pl);
+  // (keeps the loads above the gate check: the compiler would otherwise sink them past it, to
+  // the only path that uses them)
+  __asm__ volatile("" ::: "memory");
+  if (gated_off(a, gf)) return;
+  if (!a.standalone) {
+    hessenberg_store(pf, lH);
+    if (threadIdx.x < 3 * kMaxS) lB[threadIdx.x] = bp;
+  }
+  // (each ends with a barrier, after which lH and lB are complete as well)
+  if (pre) partials_sum(pl, E, a.nblocks, sred, scratch);
+  else tail_sum_partials(a.part1, E, a.nblocks, sred, scratch);
+  panel_tail(a, sred, lH, lB);
 }
 
 }  // namespace tsg
