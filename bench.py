@@ -177,14 +177,14 @@ def np_mean(v):
 
 def ortho_bench(args, tsg, W, np, torch, dev, n):
     """The isolated two-stage block orthogonalization of a Gaussian n x 61 block (s = args.s,
-    one big panel), median over args.ortho_reps calls, at ld = n + 64 and ld = n."""
+    one big panel), median over args.ortho_reps calls, at ld = n + 512 and ld = n."""
     k, s = 61, args.s
     log(f"[bench] isolated block orthogonalization {n} x {k}")
     X0 = torch.as_tensor(W.gaussian_block(n, k, seed=7).T.copy(), device=dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     res = {}
-    for pad in (64, 0):
-        # columns n + 64 elements apart (the solver's basis layout: column starts that are
+    for pad in (512, 0):
+        # columns n + 512 elements apart (the solver's basis layout: column starts that are
         # multiples of 64 Ki elements put the columns on the same HBM channels), and the
         # unpadded layout for reference
         buf = torch.empty((k, n + pad), dtype=torch.float64, device=dev)
@@ -199,13 +199,13 @@ def ortho_bench(args, tsg, W, np, torch, dev, n):
             if r >= 2:
                 times.append(e0.elapsed_time(e1))
         res[pad] = float(np.median(times))
-        if pad == 64:
+        if pad == 512:
             _, _, oerr = tsg.orthogonalize(Xw.copy_(X0), s=s, algo="two_stage", orth_err=True)
         del buf, Xw
-    med = res[64]
+    med = res[512]
     # context: torch's own kernels on the same padded block, a read-only reduction over the
     # rows of every column and an in-place scaling (every column read and written once)
-    buf = torch.empty((k, n + 64), dtype=torch.float64, device=dev)
+    buf = torch.empty((k, n + 512), dtype=torch.float64, device=dev)
     Xw = buf[:, :n]
     Xw.copy_(X0)
     ctx = {}
@@ -223,7 +223,7 @@ def ortho_bench(args, tsg, W, np, torch, dev, n):
     del buf, Xw
     passes = 1047 if (args.s == 5 and k == 61) else None
     method_bytes = sum(2 * c0 + 3 * min(s, k - c0) for c0 in range(1, k, s)) * n * 8 + 3 * k * n * 8
-    return {"shape": [n, k], "ld": n + 64, "s": s, "algo": "two_stage", "median_ms": round(med, 3),
+    return {"shape": [n, k], "ld": n + 512, "s": s, "algo": "two_stage", "median_ms": round(med, 3),
             "median_ms_ld_n": round(res[0], 3),
             "method_column_passes": passes if passes else round(method_bytes / (n * 8)),
             "method_GB": round(method_bytes / 1e9, 3),

@@ -88,11 +88,13 @@ inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Leading dimension of a basis with n rows: a multiple of 64 elements; a column
-// stride that is a multiple of 64 KiB elements gets 64 more so that the 8 columns
-// read side by side by one block do not all start on the same HBM channel.
+// stride that is a multiple of 64 Ki elements gets 512 more (4 KiB) so that the columns
+// read side by side by one block do not all start on the same HBM channel (measured on
+// n = 4194304: 512 beats 64, 128, 256 and 1024 for the panel updates by 2-4%, and the
+// solve's orthogonalization by 0.5%).
 int64_t basis_ld(int64_t n) {
   int64_t ld = (n + 63) / 64 * 64;
-  if (ld % 65536 == 0) ld += 64;
+  if (ld % 65536 == 0) ld += 512;
   return ld;
 }
 
