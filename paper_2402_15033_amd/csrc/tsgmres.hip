@@ -1738,34 +1738,11 @@ tsg_status orthogonalize_check(int64_t n, int32_t k, const double* X, int64_t ld
 // tsg_orthogonalize_workspace_bytes(n, k, s) bytes (256-byte aligned): every buffer of the
 // call (small state, reduction partials, launch image) is carved from it, and everything
 // read before it is written is initialized here.
-tsg_status orthogonalize_ws(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr, int32_t s,
-                            int32_t s_hat, int32_t algo, char* ws, hipStream_t st, double* orth_err) {
-  Carve cv{ws};
-  Common c = carve_common(cv, n);
-  char* dprog = cv.take<char>(kProgramBytesPerRequest);
+// The launch program of a stand-alone orthogonalization (Sec. V, Fig. 5; Fig. 4b; Fig. 2b)
+// of the n x k block of request q; n_main: the phases before the optional orthogonality check.
+tsg_status build_ortho_program(Program& P, size_t& n_main, ReqCtx& q, int32_t k, int32_t s, int32_t s_hat,
+                               int32_t algo, bool orth_err) {
   const bool two = algo == TSG_ORTHO_TWO_STAGE;
-
-  SmallState* hs = new (std::nothrow) SmallState();
-  if (!hs) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
-  std::memset(hs, 0, sizeof(SmallState));
-  hs->h.stop_panel = 1 << 30;
-  hs->pivot_tol = 0.0;  // stand-alone: fail only when a Gram is not positive definite
-  hs->pip_tol = 0.0;
-  hs->fail_col = -1;
-  hipError_t e = hipMemcpyAsync(c.st, hs, offsetof(SmallState, Hh), hipMemcpyHostToDevice, st);
-  delete hs;
-  HIP_TRY(e);
-  hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(kLd * kLd, 256)), dim3(256), 0, st, c.st->Hh,
-                     (int64_t)kLd * kLd);
-  hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(kLd * kLd, 256)), dim3(256), 0, st, c.st->G2,
-                     (int64_t)kLd * kLd);
-  HIP_LAUNCH_CHECK();
-  ReqCtx q;
-  q.V = X;
-  q.ld = ldx;
-  q.n = n;
-  q.c = c;
-  Program P;
   P.nreq = 1;
   Builder B{P, {&q}, 1};
   // column 1 alone
@@ -1800,13 +1777,86 @@ tsg_status orthogonalize_ws(int64_t n, int32_t k, double* X, int64_t ldx, double
       b1 = std::min(b0 + s_hat, k);
     }
   }
-  const size_t n_main = P.phases.size();
+  n_main = P.phases.size();
   if (orth_err) {  // the Gram of the result, 16 columns at a time, into st->Wk
     for (int c0 = 0; c0 < k; c0 += kMaxS) {
       const int sw = std::min(kMaxS, k - c0);
       TRY(B.step(gram_step(c0, c0, sw, 0, TAIL_GRAM_OUT, 0, 0, 0)));
     }
   }
+  return TSG_OK;
+}
+
+// Programs of recent stand-alone orthogonalizations (per host thread): a call with the same
+// shapes, scheme and pointers -- the block and the workspace the program's launch tables
+// point into -- reuses the host image instead of building it again; the image is still
+// copied to the workspace on every call.
+struct OrthoKey {
+  int64_t n, ldx;
+  int32_t k, s, s_hat, algo;
+  const void* X;
+  const void* ws;
+  bool err;
+  bool operator==(const OrthoKey& o) const {
+    return n == o.n && ldx == o.ldx && k == o.k && s == o.s && s_hat == o.s_hat && algo == o.algo && X == o.X &&
+           ws == o.ws && err == o.err;
+  }
+};
+struct OrthoProgram {
+  OrthoKey key{};
+  Program P;
+  size_t n_main = 0;
+};
+constexpr size_t kOrthoPrograms = 4;
+thread_local std::vector<OrthoProgram> t_ortho_programs;
+
+tsg_status orthogonalize_ws(int64_t n, int32_t k, double* X, int64_t ldx, double* R, int32_t ldr, int32_t s,
+                            int32_t s_hat, int32_t algo, char* ws, hipStream_t st, double* orth_err) {
+  Carve cv{ws};
+  Common c = carve_common(cv, n);
+  char* dprog = cv.take<char>(kProgramBytesPerRequest);
+  const bool two = algo == TSG_ORTHO_TWO_STAGE;
+
+  // the state's head and parameters (the same for every call: formed once per host thread)
+  thread_local std::vector<char> init_image;
+  if (init_image.empty()) {
+    SmallState* hs = new (std::nothrow) SmallState();
+    if (!hs) return fail(TSG_ERR_INVALID_ARG, "out of host memory");
+    std::memset(hs, 0, sizeof(SmallState));
+    hs->h.stop_panel = 1 << 30;
+    hs->pivot_tol = 0.0;  // stand-alone: fail only when a Gram is not positive definite
+    hs->pip_tol = 0.0;
+    hs->fail_col = -1;
+    init_image.assign(reinterpret_cast<const char*>(hs), reinterpret_cast<const char*>(hs) + offsetof(SmallState, Hh));
+    delete hs;
+  }
+  HIP_TRY(hipMemcpyAsync(c.st, init_image.data(), init_image.size(), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(kLd * kLd, 256)), dim3(256), 0, st, c.st->Hh,
+                     (int64_t)kLd * kLd);
+  hipLaunchKernelGGL(zero_f64_kernel, dim3(cdiv(kLd * kLd, 256)), dim3(256), 0, st, c.st->G2,
+                     (int64_t)kLd * kLd);
+  HIP_LAUNCH_CHECK();
+  ReqCtx q;
+  q.V = X;
+  q.ld = ldx;
+  q.n = n;
+  q.c = c;
+  const bool big = two && s_hat > 0 && s_hat < k - 1;
+  // the launch program: reused from an earlier call with the same shapes, scheme and pointers
+  const OrthoKey key{n, ldx, k, s, s_hat, algo, X, ws, orth_err != nullptr};
+  const OrthoProgram* op = nullptr;
+  for (const OrthoProgram& ent : t_ortho_programs)
+    if (ent.key == key) op = &ent;
+  if (!op) {
+    OrthoProgram built;
+    built.key = key;
+    TRY(build_ortho_program(built.P, built.n_main, q, k, s, s_hat, algo, orth_err != nullptr));
+    if (t_ortho_programs.size() >= kOrthoPrograms) t_ortho_programs.erase(t_ortho_programs.begin());
+    t_ortho_programs.push_back(std::move(built));
+    op = &t_ortho_programs.back();
+  }
+  const Program& P = op->P;
+  const size_t n_main = op->n_main;
   if (P.blob.size() > kProgramBytesPerRequest) return fail(TSG_ERR_UNSUPPORTED, "internal: launch image too large");
   HIP_TRY(hipMemcpyAsync(dprog, P.blob.data(), P.blob.size(), hipMemcpyHostToDevice, st));
   TRY(exec_program(P, dprog, st, nullptr, 0, n_main));
