@@ -229,7 +229,10 @@ struct MpkBody {
       T v = acc;
       if (theta != 0.0) v -= (T)theta * xsv;
       if (tau != 0.0 && a.xm) v += (T)tau * xmv;
-      y[r] = v / (T)sigma;
+      // (non-temporal, like every basis column a streaming kernel writes: the next step's
+      // gathers of it and the Gram's reads ran faster than after plain stores -- SpMV steps
+      // 43.2 -> 41.1 us, Grams 193 -> 184 us per launch on the 2048^2 Laplace solve)
+      __builtin_nontemporal_store(v / (T)sigma, &y[r]);
     }
   }
 };
@@ -295,7 +298,7 @@ __device__ void ResidBody<T, FMT>::run(const ResidArgs& a, int bid, int nb) {
     const int64_t r = r0 + lane;
     if (r < n) {
       double v = b[r] - acc;
-      r_out[r] = (T)v;
+      __builtin_nontemporal_store((T)v, &r_out[r]);
       rr = v * v;
     }
   }
@@ -513,7 +516,7 @@ struct XupdBody {
       default: break;
     }
     if (a.t) G(a.t)[r] = acc;
-    else x[r] += acc;
+    else __builtin_nontemporal_store(x[r] + acc, &x[r]);
   }
 };
 
