@@ -476,7 +476,7 @@ __device__ __forceinline__ double xupd_group(gbl<const T>* __restrict__ V, int64
                                             gbl<const double>* coef, double acc) {
   T q[K];
 #pragma unroll
-  for (int u = 0; u < K; ++u) q[u] = V[(int64_t)(c0 + u) * ld + r];
+  for (int u = 0; u < K; ++u) q[u] = __builtin_nontemporal_load(&V[(int64_t)(c0 + u) * ld + r]);
 #pragma unroll
   for (int u = 0; u < K; ++u) acc += (double)q[u] * coef[c0 + u];
   return acc;

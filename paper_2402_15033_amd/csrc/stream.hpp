@@ -40,25 +40,33 @@ struct MfmaOp<float> {
 
 // The reduction G = V(:, 0:ncol)^T V(:, ncol-nz : ncol) of a panel step on the matrix cores
 // (ncol = k + sw, Q = V(:, 0:k), W = V(:, wcol:wcol+sw); the nz right-hand columns are the
-// previous panel's nprev columns, their block column of the stage-2 Gram, followed by W),
-// with the operands taken straight from global memory: no LDS staging and no block barrier
-// in the row loop.  Rows are the K dimension.  Lane l = 16 g + i holds, for each column tile
-// t, column c_t + i and the RL consecutive rows r + RL g .. r + RL g + RL - 1 of a group of
-// 4 RL rows (two 16-byte loads per tile: RL = 4 in FP64, 8 in FP32); K-step e of the group
-// pairs row r + RL g + e with k index g in both operands.  The tiles are laid out from the
-// right: the last NT tiles are the last 16 NT columns (from column 0 if there are fewer),
-// which hold the nz right-hand columns -- the B operand is the A operand of those tiles, no
-// extra load, and the products with their other columns are dropped -- and MA - NT tiles
-// cover the columns to their left down to column 0 (lanes outside [0, ncol) hold zeros).  Each wave walks its own groups (wave w:
-// groups w, w + NW, ... of the block's rows) with one group's loads in flight while the
-// matrix cores consume the previous one; the loads are unconditional (the index is clamped
-// to the last full group), so the compiler waits only for the group it consumes.  A ragged
-// last group (and every group when the columns are not 16-byte aligned) is loaded element
-// by element with its rows masked.  The NW waves' tiles are summed in LDS in wave order at
-// the end.  Partials: ncol x nz float64 per block.  Measured on a 4194304 x 61 FP64 block:
-// 5.5-6.1 TB/s against 4.73 for an LDS-staged version with block barriers.
+// previous panel's nprev columns, their block column of the stage-2 Gram, followed by W).
+// Rows are the K dimension.  In the operand layout lane l = 16 g + i holds, for each column
+// tile t, column c_t + i and the RL consecutive rows r + RL g .. r + RL g + RL - 1 of a
+// group of 4 RL rows (RL = 4 in FP64, 8 in FP32); K-step e of the group pairs row
+// r + RL g + e with k index g in both operands.  The tiles are laid out from the right: the
+// last NT tiles are the last 16 NT columns (from column 0 if there are fewer), which hold
+// the nz right-hand columns -- the B operand is the A operand of those tiles, and the
+// products with their other columns are dropped -- and MA - NT tiles cover the columns to
+// their left down to column 0 (lanes outside [0, ncol) hold zeros).  Each wave walks its own
+// groups (wave w: groups w, w + NW, ... of the block's rows); the loads of a group cover
+// whole 128-byte lines and reach the operand layout through the wave's own LDS tile (no
+// block barrier in the row loop), with the next group's loads in flight; they are
+// unconditional (the index is clamped to the last full group).  A ragged last group (and
+// every group when the columns are not 16-byte aligned) is read element by element in the
+// operand layout with its rows masked.  The NW waves' tiles are summed in LDS in wave order
+// at the end.  Partials: ncol x nz float64 per block.  Measured on the reductions of an
+// m = 60, s = 5 cycle (4194304 rows, FP64): 6.6-7.0 TB/s for every panel but the first
+// (1.98 ms in all), against 5.8-6.1 TB/s (2.28 ms) when each lane read its operand rows
+// straight from global memory (two 16-byte loads per tile, each covering half of every
+// line), and 4.73 TB/s for an LDS-staged version with block barriers.
 template <typename T>
 constexpr int gram_rows_per_lane() { return 32 / (int)sizeof(T); }
+template <bool NTL>
+struct LoadPolicy {
+  static constexpr bool nt = NTL;
+};
+constexpr int64_t kGramKeepBytes = 256ll << 20;
 constexpr int kGramGroupRows = 32;  // row blocks of the reduction are multiples of this
 template <typename T, int MA, int NT>
 struct GramBody {
@@ -99,21 +107,45 @@ __device__ void GramBody<T, MA, NT>::run(const PanelArgs& a, int bid, int) {
   for (int t = 0; t < MA; ++t)
 #pragma unroll
     for (int u = 0; u < NT; ++u) acc[t][u] = v4{0, 0, 0, 0};
-  // rows r0 + RL g .. + RL - 1 of every tile column (a full group starting at row r0)
-  auto load = [&](int64_t r0, T (&v)[MA][RL]) {
-    typedef T t16 __attribute__((ext_vector_type(16 / sizeof(T))));
-    constexpr int H = 16 / (int)sizeof(T);
+  // The row loop's loads: per tile two 16-byte loads per lane, load h covering the tile's
+  // columns 8 h .. 8 h + 7 with 8 lanes per column, so that every load reads whole 128-byte
+  // lines (one line per column: rows r0 .. r0 + GR - 1), with the non-temporal hint.  The
+  // wave turns them into the operand layout above through its own LDS tile (column-major,
+  // column stride CS = GR + H elements: both the 16-byte writes and the 16-byte operand reads
+  // are free of bank conflicts).  Measured on streams of 64 columns: loads covering whole
+  // lines run at 7.1 TB/s with the hint and 6.3 without, loads covering half lines (the
+  // operand layout read straight from global memory) at 4.8 and 3.9.
+  constexpr int H = 16 / (int)sizeof(T), CS = GR + H, TW = 16 * MA * CS;
+  typedef T t16 __attribute__((ext_vector_type(H)));
+  int64_t loff[MA][2];
 #pragma unroll
-    for (int t = 0; t < MA; ++t) {
-      gbl<const T>* p = V + coff[t] + r0;
-      const t16 x0 = *reinterpret_cast<gbl<const t16>*>(p);
-      const t16 x1 = *reinterpret_cast<gbl<const t16>*>(p + H);
+  for (int t = 0; t < MA; ++t)
 #pragma unroll
-      for (int e = 0; e < H; ++e) {
-        v[t][e] = x0[e];
-        v[t][H + e] = x1[e];
-      }
+    for (int h = 0; h < 2; ++h) {
+      const int c = zb + 16 * (t - (MA - NT)) + 8 * h + (lane >> 3);
+      const int cc = c >= 0 && c < ncol ? c : 0;
+      loff[t][h] = (int64_t)(cc < k ? cc : a.wcol + (cc - k)) * ld + (lane & 7) * H;
     }
+  __shared__ __align__(16) T lt[NW * TW];
+  T* const Lw = lt + wv * TW;
+  // The last kGramKeepBytes of the reduction's reads (the last groups of every block) take
+  // plain loads, the others the non-temporal hint: the lines read last stay in the
+  // last-level cache (256 MB on MI355X) for the panel update, which reads the same columns
+  // next.  Measured on the 2048^2 solve (per-launch means): all reads non-temporal, Grams
+  // 163 us, updates 187 us; the last 128 / 256 / 512 MB plain, 164 / 166 / 171 and 175 /
+  // 167 / 166 us (the matrix-powers steps, whose matrix the kept columns displace from the
+  // cache, 38.0 / 38.6 / 39.7 / 40.4 us): 256 MB.
+  const double kf = min(1.0, (double)kGramKeepBytes / ((double)ncol * (double)n * sizeof(T)));
+  const int64_t qs = nfull - (int64_t)(kf * (double)nfull);  // groups from qs on: plain loads
+  auto gload = [&](auto pol, int64_t q, t16 (&x)[MA][2]) {
+    const int64_t r0 = rb + GR * q;
+#pragma unroll
+    for (int t = 0; t < MA; ++t)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        gbl<const t16>* p = reinterpret_cast<gbl<const t16>*>(V + loff[t][h] + r0);
+        x[t][h] = decltype(pol)::nt ? __builtin_nontemporal_load(p) : *p;
+      }
   };
   auto mma = [&](const T (&v)[MA][RL]) {
 #pragma unroll
@@ -129,17 +161,41 @@ __device__ void GramBody<T, MA, NT>::run(const PanelArgs& a, int bid, int) {
         }
       }
   };
-  if (vec && nfull > 0) {
-    T va[MA][RL], vb[MA][RL];
-    int64_t q = wv;
-    load(rb + GR * min<int64_t>(q, nfull - 1), va);
-    for (; q < nfull; q += 2 * NW) {
-      load(rb + GR * min<int64_t>(q + NW, nfull - 1), vb);
-      mma(va);
-      if (q + NW >= nfull) break;
-      load(rb + GR * min<int64_t>(q + 2 * NW, nfull - 1), va);
-      mma(vb);
+  // Wave wv's groups q = wv, wv + NW, ... below qe, starting at q: the group's loads are
+  // written to the wave's LDS tile, the next group's loads are issued, and the tile is read
+  // back in the operand layout and multiplied while they are in flight.  (LDS accesses of
+  // one wave execute in order: only the compiler must keep them in order.)  Measured
+  // against two register buffers (the next two groups' loads in flight): 1.98 against 2.00
+  // ms for the reductions of an m = 60, s = 5 cycle on 4194304 rows; two groups per step
+  // with two LDS tiles 2.01 ms; twice the grid, with or without a 128-register cap, 2.00.
+  auto rowloop = [&](auto pol, int64_t q, int64_t qe) {
+    if (q >= qe) return;
+    t16 x[MA][2];
+    T v[MA][RL];
+    gload(pol, q, x);
+    for (; q < qe; q += NW) {
+#pragma unroll
+      for (int t = 0; t < MA; ++t)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) *reinterpret_cast<t16*>(Lw + (16 * t + 8 * h + (lane >> 3)) * CS + (lane & 7) * H) = x[t][h];
+      __asm__ volatile("" ::: "memory");
+      gload(pol, min<int64_t>(q + NW, qe - 1), x);
+#pragma unroll
+      for (int t = 0; t < MA; ++t)
+#pragma unroll
+        for (int p = 0; p < RL / H; ++p) {
+          const t16 y = *reinterpret_cast<const t16*>(Lw + (16 * t + li) * CS + RL * g + H * p);
+#pragma unroll
+          for (int e = 0; e < H; ++e) v[t][H * p + e] = y[e];
+        }
+      __asm__ volatile("" ::: "memory");
+      mma(v);
     }
+  };
+  if (vec && nfull > 0) {
+    const int64_t q2 = qs <= wv ? wv : wv + (qs - wv + NW - 1) / NW * NW;  // first own group >= qs
+    rowloop(LoadPolicy<true>{}, wv, min<int64_t>(qs, nfull));
+    rowloop(LoadPolicy<false>{}, q2, nfull);
   }
   {
     // element by element: the ragged last group, or every group when the columns are not
@@ -158,7 +214,8 @@ __device__ void GramBody<T, MA, NT>::run(const PanelArgs& a, int bid, int) {
   // sum the NW waves' tiles in wave order, one right-hand tile at a time:
   // red[w][c][z], c < 16 MA (every column c < ncol lies in one tile), z < 16
   constexpr int RC = 16 * MA;
-  __shared__ T red[NW * RC * 16];
+  static_assert(NW * RC * 16 <= NW * TW, "reduction buffer");
+  T* const red = lt;  // the waves' tiles are free once every wave has left its row loop
   gbl<double>* part = G(a.part1) + (size_t)bid * ncol * nz;
 #pragma unroll
   for (int u = 0; u < NT; ++u) {
@@ -203,7 +260,7 @@ __device__ __forceinline__ void upd_group(gbl<T>* __restrict__ V, int64_t ld, in
                                           gbl<const double>* P, T (&y)[S]) {
   T q[K];
 #pragma unroll
-  for (int u = 0; u < K; ++u) q[u] = V[(int64_t)(c0 + u) * ld + r];
+  for (int u = 0; u < K; ++u) q[u] = __builtin_nontemporal_load(&V[(int64_t)(c0 + u) * ld + r]);
 #pragma unroll
   for (int u = 0; u < K; ++u)
 #pragma unroll
@@ -237,7 +294,7 @@ __device__ void UpdateBody<T, S, kBlock>::run(const PanelArgs& a, int bid, int) 
   gbl<T>* W = V + (int64_t)a.wcol * ld + r;
   T y[S];
 #pragma unroll
-  for (int j = 0; j < S; ++j) y[j] = (j < sw) ? W[(int64_t)j * ld] : (T)0;
+  for (int j = 0; j < S; ++j) y[j] = (j < sw) ? __builtin_nontemporal_load(&W[(int64_t)j * ld]) : (T)0;
   if (hasP) {
     // columns in groups of 16, then one of 8, then one of the remaining size: each group
     // issues all its loads before its first update (few dependent round trips per row)
@@ -367,7 +424,7 @@ __device__ void FusedBody<T, NC>::run(const PanelArgs& a, int bid, int) {
   T* L = lt + wv * GR * LS;
   auto load = [&](int64_t r0, T (&v)[NKS]) {
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) v[ks] = V[coff(ks) + r0];
+    for (int ks = 0; ks < NKS; ++ks) v[ks] = __builtin_nontemporal_load(&V[coff(ks) + r0]);
   };
   // one group of rows r0 .. r0 + 15 (rows from nrows on are padding, zero in v)
   auto group = [&](int64_t r0, const T (&v)[NKS], int nrows) {
@@ -424,7 +481,7 @@ __device__ void FusedBody<T, NC>::run(const PanelArgs& a, int bid, int) {
     const int nrows = (int)(re - r0);
     T v[NKS];
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) v[ks] = li < nrows ? V[coff(ks) + r0] : (T)0;
+    for (int ks = 0; ks < NKS; ++ks) v[ks] = li < nrows ? __builtin_nontemporal_load(&V[coff(ks) + r0]) : (T)0;
     group(r0, v, nrows);
   }
   if (!gram) return;
@@ -515,7 +572,7 @@ __global__ __launch_bounds__(kRinvThreads) void apply_rinv_kernel(double* __rest
     double x[NKS];
     int64_t q = wv;
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) x[ks] = *xat(ks, rb + GR * q);
+    for (int ks = 0; ks < NKS; ++ks) x[ks] = __builtin_nontemporal_load(xat(ks, rb + GR * q));
     for (; q < nfull; q += NW) {
       // an opaque zero in the LDS index: the operand values are read from LDS per group
       // rather than hoisted into 80 registers across the loop
@@ -531,7 +588,7 @@ __global__ __launch_bounds__(kRinvThreads) void apply_rinv_kernel(double* __rest
 #pragma unroll
         for (int t = 0; t < NCT; ++t)
           if (ks <= 4 * t + 3) acc[t] = MfmaOp<double>::mac(sA[(t * NKS + ks) * kWave + lane + z], x[ks], acc[t]);
-        x[ks] = *xat(ks, rn);
+        x[ks] = __builtin_nontemporal_load(xat(ks, rn));
       }
 #pragma unroll
       for (int t = 0; t < NCT; ++t)
@@ -550,7 +607,7 @@ __global__ __launch_bounds__(kRinvThreads) void apply_rinv_kernel(double* __rest
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
       const int col = min(4 * ks + g, k - 1);
-      const double xv = ok ? V[(int64_t)col * ld + r0 + li] : 0.0;
+      const double xv = ok ? __builtin_nontemporal_load(&V[(int64_t)col * ld + r0 + li]) : 0.0;
 #pragma unroll
       for (int t = 0; t < NCT; ++t)
         if (ks <= 4 * t + 3) acc[t] = MfmaOp<double>::mac(sA[(t * NKS + ks) * kWave + lane], xv, acc[t]);
