@@ -111,10 +111,13 @@ __device__ void GramBody<T, MA, NT>::run(const PanelArgs& a, int bid, int) {
   // columns 8 h .. 8 h + 7 with 8 lanes per column, so that every load reads whole 128-byte
   // lines (one line per column: rows r0 .. r0 + GR - 1), with the non-temporal hint.  The
   // wave turns them into the operand layout above through its own LDS tile (column-major,
-  // column stride CS = GR + H elements: both the 16-byte writes and the 16-byte operand reads
-  // are free of bank conflicts).  Measured on streams of 64 columns: loads covering whole
-  // lines run at 7.1 TB/s with the hint and 6.3 without, loads covering half lines (the
-  // operand layout read straight from global memory) at 4.8 and 3.9.
+  // column stride CS = GR + H elements, which spreads the 16 columns of an operand read over
+  // the banks).  SQ_LDS_BANK_CONFLICT reports a quarter of the LDS cycles as conflict cycles
+  // here; an XOR swizzle of the 16-byte pieces (stride GR, no bank shared within any 16-lane
+  // quarter of a write or read) gave the same count and the same time, so the count is taken
+  // to be the cost of the 16-byte accesses themselves.  Measured on streams of 64 columns:
+  // loads covering whole lines run at 7.1 TB/s with the hint and 6.3 without, loads covering
+  // half lines (the operand layout read straight from global memory) at 4.8 and 3.9.
   constexpr int H = 16 / (int)sizeof(T), CS = GR + H, TW = 16 * MA * CS;
   typedef T t16 __attribute__((ext_vector_type(H)));
   int64_t loff[MA][2];
